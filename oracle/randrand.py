@@ -1,0 +1,246 @@
+"""C-RandRAND preconditioner construction in float64 (oracle).
+
+Follows, in order, Algorithm RandRAND_PCG steps 1-4 of the paper (Section 6.2)
+with the explicit-basis representation of Section 4.1:
+
+1. sketch            Y_mu = A Omega + mu Omega                      (eq. Rdef, q = 0)
+2. orthogonalise     Y_mu = Q R by Cholesky QR (Algorithm chol_qr) or by the
+                     sketched/preconditioned Cholesky QR (Algorithm prec_chol_qr)
+3. core              G = R^{-T} (Omega^T A_mu Omega) R^{-1}         (eq. g_randrand_explicit)
+                     in the spd-safe form G = (R_Omega R^{-1})^T (R_Omega R^{-1}),
+                     R_Omega^T R_Omega = Omega^T A_mu Omega          (remark after Alg. RandRAND_PCG)
+4. refined projector T = 2I - Q^T Q                                   (eq. accurate_proj)
+5. tau               OPT: tau = sqrt(mu ||E|| / lam)  (eq. optimal_rho with F = 1/mu,
+                          inserted in eq. c_randrand_tau)
+                     RHO: tau = rho ||E|| / lam        (eq. c_randrand_tau)
+                     NYS: tau = ||Pi A_mu^{-1} Pi||^{-1} = 1/lambda_max(G) (eq. nys_tau)
+                     with ||E|| and lam = lambda_max(Pi A_mu Pi A_mu^{-1} Pi) from power
+                     iterations (Section 3.2).
+6. apply             P = I - Pi + tau Pi~,  Pi = Q T Q^T,  Pi~ = Q T G T Q^T
+                     = I + Q K Q^T with K = tau T G T - T   (eq. g_randrand_explicit,
+                     refined with eq. accurate_proj).
+
+Several shifts (Section 5.1): joint basis Q_joint = qr([Omega, A Omega]) and, per
+mu, a QR of the 2l x l reduced matrix Q_joint^T A Omega + mu Q_joint^T Omega.
+
+Readings where the paper is silent are listed in the design notes; the main ones:
+q = 0; power iterations N_pow = 10 from counter-generated Gaussian starts
+(streams seed+2 for ||E||, seed+3 for lam); estimate = ||op(v)|| for unit v;
+Cholesky failure ladder alpha in {1e-14, ..., 1e-1} * max_i W_ii (Appendix C);
+Algorithm prec_chol_qr returns R = R_chol R_sk (the product order that makes
+Y = Q R hold).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import Callable, List, Optional
+
+import numpy as np
+import scipy.linalg as sla
+
+from . import rng as _rng
+
+OPT, RHO, NYS = 0, 1, 2
+SKETCHED_CHOLQR, CHOLQR = 0, 1
+
+
+class NotSPD(Exception):
+    pass
+
+
+def chol_upper_ladder(W: np.ndarray):
+    """Upper Cholesky factor R (R^T R = W); on failure add alpha I (Appendix C ladder).
+
+    Returns (R, alpha_used).
+    """
+    W = 0.5 * (W + W.T)
+    try:
+        return sla.cholesky(W, lower=False), 0.0
+    except np.linalg.LinAlgError:
+        pass
+    wn = float(np.max(np.abs(np.diag(W))))
+    for e in range(-14, 0):
+        alpha = (10.0 ** e) * wn
+        try:
+            return sla.cholesky(W + alpha * np.eye(W.shape[0]), lower=False), alpha
+        except np.linalg.LinAlgError:
+            continue
+    raise NotSPD("Cholesky ladder exhausted")
+
+
+def householder_r(S: np.ndarray) -> np.ndarray:
+    """R factor of a Householder QR (LAPACK geqrf via numpy), diagonal made positive."""
+    R = np.linalg.qr(S, mode="r")
+    sgn = np.sign(np.diag(R))
+    sgn[sgn == 0] = 1.0
+    return sgn[:, None] * R
+
+
+def householder_qr(S: np.ndarray):
+    Q, R = np.linalg.qr(S, mode="reduced")
+    sgn = np.sign(np.diag(R))
+    sgn[sgn == 0] = 1.0
+    return Q * sgn[None, :], sgn[:, None] * R
+
+
+def tri_inv_upper(R: np.ndarray) -> np.ndarray:
+    return sla.solve_triangular(R, np.eye(R.shape[0]), lower=False)
+
+
+def cholqr(Y: np.ndarray):
+    """Algorithm chol_qr: G = Y^T Y, R = chol(G), Q = Y R^{-1}."""
+    R, _ = chol_upper_ladder(Y.T @ Y)
+    Q = Y @ tri_inv_upper(R)
+    return Q, R
+
+
+def sketched_cholqr(Y: np.ndarray, Theta: np.ndarray):
+    """Algorithm prec_chol_qr with the explicit Q of Section 4.1.
+
+    S = Theta Y; R_sk = qr(S); W = Y R_sk^{-1}; G = W^T W; R_chol = chol(G);
+    Q = W R_chol^{-1}; R = R_chol R_sk.
+    """
+    S = Theta @ Y
+    R_sk = householder_r(S)
+    W = Y @ tri_inv_upper(R_sk)
+    R_c, _ = chol_upper_ladder(W.T @ W)
+    Q = W @ tri_inv_upper(R_c)
+    return Q, R_c @ R_sk
+
+
+def power_norm(op: Callable[[np.ndarray], np.ndarray], v0: np.ndarray, iters: int) -> float:
+    """Power iteration: v <- op(v)/||op(v)||; returns ||op(v)|| for the last unit v."""
+    v = v0 / np.linalg.norm(v0)
+    lam = 0.0
+    for _ in range(iters):
+        w = op(v)
+        lam = float(np.linalg.norm(w))
+        if lam == 0.0:
+            return 0.0
+        v = w / lam
+    return lam
+
+
+@dataclass
+class Precond:
+    """C-RandRAND preconditioner P = I + Qb (Kc) Qb^T for one shift mu.
+
+    For a single shift Qb = Q (n x l) and Kc = K_tau (l x l).  For the joint
+    basis Qb = Q_joint (n x 2l) and Kc = Q_red K_tau Q_red^T (2l x 2l).
+    """
+    mu: float
+    Q: Optional[np.ndarray]
+    R: Optional[np.ndarray]
+    G: Optional[np.ndarray]
+    T: Optional[np.ndarray]
+    K: Optional[np.ndarray]
+    tau: float
+    normE: float
+    lam: float
+    Qb: Optional[np.ndarray] = None
+    Kc: Optional[np.ndarray] = None
+    extras: dict = field(default_factory=dict)
+
+    def apply(self, r: np.ndarray) -> np.ndarray:
+        if self.Qb is None:
+            return r.copy()
+        return r + self.Qb @ (self.Kc @ (self.Qb.T @ r))
+
+    @property
+    def l(self) -> int:
+        return 0 if self.Q is None else self.Q.shape[1]
+
+    def dense(self) -> np.ndarray:
+        n = self.Qb.shape[0]
+        return np.eye(n) + self.Qb @ self.Kc @ self.Qb.T
+
+
+def _core(Omega, Y_mu, R):
+    """G = (R_Omega R^{-1})^T (R_Omega R^{-1}) with R_Omega = chol(Omega^T A_mu Omega)."""
+    C = Omega.T @ Y_mu
+    R_om, _ = chol_upper_ladder(0.5 * (C + C.T))
+    H = R_om @ tri_inv_upper(R)
+    return H.T @ H
+
+
+def _tau(rule, mu, rho, Amu, Q, T, G, seed, n, power_iters):
+    """tau and the two power-iteration estimates (||E||, lam) for one shift."""
+    def Pi(u):
+        return Q @ (T @ (Q.T @ u))
+
+    def Pi_tilde(u):
+        return Q @ (T @ (G @ (T @ (Q.T @ u))))
+
+    def E(u):
+        v = u - Pi(u)
+        w = Amu(v)
+        return w - Pi(w)
+
+    def M(u):
+        return Pi(Amu(Pi_tilde(u)))
+
+    normE = lam = float("nan")
+    if rule == NYS:
+        # tau = ||Pi A_mu^{-1} Pi||^{-1}; Pi A_mu^{-1} Pi has the nonzero spectrum of G
+        tau = 1.0 / float(np.max(np.linalg.eigvalsh(0.5 * (G + G.T))))
+        return tau, normE, lam
+    normE = power_norm(E, _rng.gaussian_vector(seed + 2, n), power_iters)
+    lam = power_norm(M, _rng.gaussian_vector(seed + 3, n), power_iters)
+    if rule == OPT and mu > 0:
+        tau = float(np.sqrt(mu * normE / lam))
+    else:
+        tau = rho * normE / lam
+    return tau, normE, lam
+
+
+def build(op, mus: List[float], l: int, sketch: str = "gaussian", seed: int = 0,
+          orth: int = SKETCHED_CHOLQR, tau_rule: int = OPT, rho: float = 1.0,
+          power_iters: int = 10, Omega: Optional[np.ndarray] = None) -> List[Precond]:
+    """Build one C-RandRAND preconditioner per shift (Algorithm RandRAND_PCG steps 1-4)."""
+    n = op.n
+    if l == 0:
+        return [Precond(mu, None, None, None, None, None, 1.0, float("nan"), float("nan"))
+                for mu in mus]
+    if Omega is None:
+        Omega = _rng.omega(sketch, seed, n, l)
+    out = []
+    if len(mus) == 1:
+        mu = mus[0]
+        Amu = op.shifted(mu)
+        Y = op.matmat(Omega) + mu * Omega
+        if orth == SKETCHED_CHOLQR:
+            Q, R = sketched_cholqr(Y, _rng.theta(seed, n, l))
+        else:
+            Q, R = cholqr(Y)
+        G = _core(Omega, Y, R)
+        T = 2.0 * np.eye(l) - Q.T @ Q
+        tau, normE, lam = _tau(tau_rule, mu, rho, Amu, Q, T, G, seed, n, power_iters)
+        K = tau * (T @ G @ T) - T
+        out.append(Precond(mu, Q, R, G, T, K, tau, normE, lam, Qb=Q, Kc=K))
+        return out
+    # several shifts sharing one joint basis (Section 5.1)
+    AO = op.matmat(Omega)
+    Z = np.concatenate([Omega, AO], axis=1)
+    if orth == SKETCHED_CHOLQR:
+        Qj, _ = sketched_cholqr(Z, _rng.theta(seed, n, 2 * l))
+    else:
+        Qj, _ = cholqr(Z)
+    Zj = Qj.T @ AO
+    Oj = Qj.T @ Omega
+    OAO = Omega.T @ AO
+    OO = Omega.T @ Omega
+    QjtQj = Qj.T @ Qj
+    for mu in mus:
+        Amu = op.shifted(mu)
+        Qred, R = householder_qr(Zj + mu * Oj)
+        Q = Qj @ Qred
+        C = OAO + mu * OO
+        R_om, _ = chol_upper_ladder(0.5 * (C + C.T))
+        H = R_om @ tri_inv_upper(R)
+        G = H.T @ H
+        T = 2.0 * np.eye(l) - Qred.T @ QjtQj @ Qred
+        tau, normE, lam = _tau(tau_rule, mu, rho, Amu, Q, T, G, seed, n, power_iters)
+        K = tau * (T @ G @ T) - T
+        out.append(Precond(mu, Q, R, G, T, K, tau, normE, lam, Qb=Qj,
+                           Kc=Qred @ K @ Qred.T, extras={"Qred": Qred}))
+    return out

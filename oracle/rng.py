@@ -1,0 +1,116 @@
+"""Counter-based random numbers for the method's random test matrices.
+
+The paper draws Omega = X^T from an oblivious subspace embedding (Section 1.1,
+eq. testmatrix; Section 2: Gaussian with iid entries, SRHT = S H D with zero
+padding to a power of two) and a second-level sketch Theta (Algorithm
+prec_chol_qr).  It fixes no generator, so both implementations use one
+published counter-based generator, implemented independently on each side:
+
+* SplitMix64 (Steele, Lea and Flood, "Fast splittable pseudorandom number
+  generators", OOPSLA 2014): state increments by the odd constant
+  GAMMA = 0x9E3779B97F4A7C15 and every state is passed through the 64-bit
+  finaliser z ^= z>>30; z *= 0xBF58476D1CE4E5B9; z ^= z>>27;
+  z *= 0x94D049BB133111EB; z ^= z>>31.  Word k of the stream with seed s is
+  therefore mix(s + (k+1)*GAMMA) mod 2^64, which makes every element
+  independently addressable.
+* Box-Muller: z = sqrt(-2 ln u1) cos(2 pi u2) with u1 in (0,1], u2 in [0,1)
+  taken from the top 53 bits of two consecutive words.
+
+Element e of a Gaussian stream uses words 2e and 2e+1.  Matrices are indexed
+column-major (e = row + col * nrows).  The Gaussian scale 1/sqrt(l) of the
+paper is dropped: Pi, Omega (A_mu Omega)^+, Q, G and tau are invariant under
+Omega -> c Omega.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+MASK = (1 << 64) - 1
+GAMMA = 0x9E3779B97F4A7C15
+M1 = 0xBF58476D1CE4E5B9
+M2 = 0x94D049BB133111EB
+
+
+def splitmix64_words(seed: int, k: np.ndarray) -> np.ndarray:
+    """Words k (uint64 array of indices) of the SplitMix64 stream started at `seed`."""
+    k = np.asarray(k, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        z = np.uint64(seed & MASK) + (k + np.uint64(1)) * np.uint64(GAMMA)
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(M1)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(M2)
+        z = z ^ (z >> np.uint64(31))
+    return z
+
+
+def gaussian(seed: int, e: np.ndarray) -> np.ndarray:
+    """Standard normal values for element indices e (float64), Box-Muller cosine branch."""
+    e = np.asarray(e, dtype=np.uint64)
+    w1 = splitmix64_words(seed, np.uint64(2) * e)
+    w2 = splitmix64_words(seed, np.uint64(2) * e + np.uint64(1))
+    u1 = ((w1 >> np.uint64(11)).astype(np.float64) + 1.0) * 2.0 ** -53
+    u2 = (w2 >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
+    return np.sqrt(-2.0 * np.log(u1)) * np.cos(2.0 * np.pi * u2)
+
+
+def gaussian_matrix(seed: int, rows: int, cols: int) -> np.ndarray:
+    """rows x cols Gaussian matrix, element (i, c) from counter i + c*rows."""
+    e = np.arange(rows * cols, dtype=np.uint64)
+    return gaussian(seed, e).reshape(cols, rows).T.copy()
+
+
+def gaussian_vector(seed: int, n: int) -> np.ndarray:
+    return gaussian(seed, np.arange(n, dtype=np.uint64))
+
+
+def srht_descriptor(seed: int, n: int, l: int):
+    """SRHT parts (Section 2): padded size s = 2^ceil(log2 n), signs D, sampled rows.
+
+    D_i = +1 if the top bit of word i is 0 else -1 (i < n).
+    The l sampled Hadamard rows are distinct, drawn by a partial Fisher-Yates
+    shuffle of [0, s): step c swaps position c with c + floor(hi32(w) * (s-c) / 2^32)
+    where w is word n + c.
+    """
+    s = 1
+    while s < n:
+        s *= 2
+    if l > s:
+        raise ValueError("l exceeds padded size")
+    wsign = splitmix64_words(seed, np.arange(n, dtype=np.uint64))
+    D = np.where((wsign >> np.uint64(63)) == 0, 1.0, -1.0)
+    perm = np.arange(s, dtype=np.int64)
+    wsamp = splitmix64_words(seed, np.arange(n, n + l, dtype=np.uint64))
+    for c in range(l):
+        span = s - c
+        j = c + int(((int(wsamp[c]) >> 32) * span) >> 32)
+        perm[c], perm[j] = perm[j], perm[c]
+    return s, D, perm[:l].copy()
+
+
+def srht_omega(seed: int, n: int, l: int) -> np.ndarray:
+    """Omega = (S H D)^T restricted to the first n rows (zero padding), scale dropped.
+
+    Omega[i, c] = D_i * H[s_c, i] with Sylvester ordering H[a, b] = (-1)^popcount(a & b).
+    """
+    s, D, rows = srht_descriptor(seed, n, l)
+    i = np.arange(n, dtype=np.int64)[:, None]
+    bits = np.bitwise_and(i, rows[None, :])
+    par = np.zeros_like(bits)
+    b = bits.copy()
+    while np.any(b):
+        par ^= (b & 1)
+        b >>= 1
+    H = 1.0 - 2.0 * par
+    return D[:, None] * H
+
+
+def omega(kind: str, seed: int, n: int, l: int) -> np.ndarray:
+    if kind == "gaussian":
+        return gaussian_matrix(seed, n, l)
+    if kind == "srht":
+        return srht_omega(seed, n, l)
+    raise ValueError(kind)
+
+
+def theta(seed: int, n: int, l: int) -> np.ndarray:
+    """Second-level Gaussian sketch Theta (2l x n), stream seed+1, column-major counters."""
+    return gaussian_matrix(seed + 1, 2 * l, n)

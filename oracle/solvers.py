@@ -1,0 +1,107 @@
+"""Krylov solvers and the direct reference solve (oracle, float64).
+
+* pcg         C-RandRAND PCG with restarts (Algorithm RandRAND_PCG steps 5-11,
+              Section 6.2).  Hestenes-Stiefel recurrences in this order per
+              iteration: w = A_mu p; alpha = rho / p^T w; x += alpha p;
+              r -= alpha w; (stop test on ||r||); z = P r; rho' = r^T z;
+              beta = rho'/rho; p = z + beta p.
+              Restart after every drop of the residual norm by eta = 1e-2
+              (Section 7, experimental setup): the true residual b - A_mu x is
+              recomputed, z = P r and p = z.  The relative residual
+              ||b - A_mu x|| / ||b|| is the stop test, with the recurrence
+              residual inside a restart cycle and the true residual at each
+              restart and at the end.
+* cg          the same loop with P = I (plain CG, Section 1).
+* direct      x* = (A + mu I)^{-1} b by a dense Cholesky solve (LAPACK).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import Callable, List, Optional
+
+import numpy as np
+import scipy.linalg as sla
+
+OK, NOCONV, BREAKDOWN = 0, 5, 4
+
+
+@dataclass
+class SolveResult:
+    x: np.ndarray
+    iters: int
+    restarts: int
+    relres: float
+    status: int
+    history: List[float] = field(default_factory=list)
+
+
+def pcg(Amu: Callable, P: Callable, b: np.ndarray, tol: float, x0: Optional[np.ndarray] = None,
+        eta: float = 1e-2, maxit: int = 5000, Amu_true: Optional[Callable] = None) -> SolveResult:
+    """C-RandRAND PCG with restarts.
+
+    Amu       working operator used inside the iteration.
+    Amu_true  operator used for the residual at each restart (outer iterative
+              refinement); defaults to Amu.
+    """
+    Atrue = Amu_true or Amu
+    x = np.zeros_like(b) if x0 is None else np.array(x0, dtype=np.float64)
+    nb = float(np.linalg.norm(b))
+    if nb == 0.0:
+        return SolveResult(np.zeros_like(b), 0, 0, 0.0, OK)
+    its = 0
+    cycles = 0
+    hist: List[float] = []
+    while True:
+        r = b - Atrue(x)
+        rn = float(np.linalg.norm(r))
+        hist.append(rn / nb)
+        if rn <= tol * nb:
+            return SolveResult(x, its, max(cycles - 1, 0), rn / nb, OK, hist)
+        if its >= maxit:
+            return SolveResult(x, its, max(cycles - 1, 0), rn / nb, NOCONV, hist)
+        cycles += 1
+        target = max(eta * rn, tol * nb)
+        z = P(r)
+        p = z.copy()
+        rho = float(r @ z)
+        if not rho > 0:
+            return SolveResult(x, its, cycles - 1, rn / nb, BREAKDOWN, hist)
+        while its < maxit:
+            w = Amu(p)
+            pw = float(p @ w)
+            if not pw > 0:
+                return SolveResult(x, its, cycles - 1, rn / nb, BREAKDOWN, hist)
+            alpha = rho / pw
+            x = x + alpha * p
+            r = r - alpha * w
+            its += 1
+            rn = float(np.linalg.norm(r))
+            if rn <= target:
+                break
+            z = P(r)
+            rho_new = float(r @ z)
+            if not rho_new > 0:
+                return SolveResult(x, its, cycles - 1, rn / nb, BREAKDOWN, hist)
+            beta = rho_new / rho
+            p = z + beta * p
+            rho = rho_new
+
+
+def cg(Amu: Callable, b: np.ndarray, tol: float, **kw) -> SolveResult:
+    """Plain unpreconditioned CG: the same loop and stop rule with P = I."""
+    return pcg(Amu, lambda r: r.copy(), b, tol, **kw)
+
+
+def direct(A_dense: np.ndarray, mu: float, b: np.ndarray) -> np.ndarray:
+    """x* = (A + mu I)^{-1} b by Cholesky (LAPACK potrf/potrs)."""
+    n = A_dense.shape[0]
+    c = sla.cho_factor(A_dense + mu * np.eye(n), lower=False)
+    return sla.cho_solve(c, b)
+
+
+def relres(Amu_true: Callable, x: np.ndarray, b: np.ndarray) -> float:
+    """||b - A_mu x|| / ||b|| with the float64 operator (per column for 2-D input)."""
+    r = b - Amu_true(x)
+    if b.ndim == 1:
+        return float(np.linalg.norm(r) / np.linalg.norm(b))
+    return np.linalg.norm(r, axis=0) / np.linalg.norm(b, axis=0)
