@@ -1,0 +1,298 @@
+/*
+ * randrand.h — C ABI of the RandRAND (randomized range deflation) solver library
+ * for MI355X (gfx950).
+ *
+ * Problem (paper, Section 1, eq. initsys): solve (A + mu I) x = b with A
+ * symmetric positive semidefinite and mu >= 0, A reached through matvecs (a
+ * stored dense matrix) or through its entries (a Gaussian RBF or Matern-3/2
+ * kernel formed on the fly).  The preconditioner is C-RandRAND (Section 3.2,
+ * eq. c_randrand_def) in its explicit-basis form (Section 4.1,
+ * eq. g_randrand_explicit):
+ *
+ *     P = I - Pi + tau Pi A_mu^{-1} Pi = I + Q (tau T G T - T) Q^T,
+ *     A_mu Omega = Q R,  G = R^{-T} (Omega^T A_mu Omega) R^{-1},  T = 2I - Q^T Q,
+ *
+ * used inside PCG with restarts (Algorithm RandRAND_PCG, Section 6.2).
+ *
+ * Conventions for every entry point:
+ *  - All functions are extern "C", never throw, never abort, and return rr_status.
+ *  - Matrices are column-major.  "device" pointers are HIP device memory on the
+ *    current device; "host" pointers are ordinary host memory.
+ *  - The caller owns every buffer it passes in.  Operator memory (A, pts) is
+ *    borrowed by a preconditioner handle and must outlive it.  A handle owns the
+ *    memory it allocates (Omega, Y, Q, the l x l factors, workspaces) and
+ *    releases it in rr_precond_destroy.
+ *  - Device work is enqueued on the caller's hipStream_t (passed as void*;
+ *    NULL = the default stream).  rr_build_precond, rr_solve and
+ *    rr_solve_batch return only after their work has completed.
+ *  - On failure the function returns a non-zero rr_status; rr_last_error()
+ *    returns a thread-local message describing it.  RR_EINVAL is returned
+ *    before any device work is done.
+ */
+#ifndef RANDRAND_H
+#define RANDRAND_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    RR_OK = 0,
+    RR_EINVAL = 1,      /* invalid argument (checked before any device work)        */
+    RR_ENOMEM = 2,      /* device allocation failed or the memory budget is exceeded */
+    RR_ENOTSPD = 3,     /* Cholesky failed after the whole shift ladder             */
+    RR_EBREAKDOWN = 4,  /* PCG breakdown: p^T A_mu p <= 0 or r^T z <= 0            */
+    RR_ENOCONV = 5,     /* maxit reached; x holds the last iterate, info is filled   */
+    RR_EDEVICE = 6,     /* HIP runtime error or no usable GPU                        */
+    RR_EBUSY = 7        /* resource in use                                           */
+} rr_status;
+
+/* Operator kinds (Section 1: A symmetric psd, reached by matvecs or entries). */
+typedef enum { RR_OP_DENSE = 0, RR_OP_RBF = 1, RR_OP_MATERN32 = 2 } rr_op_kind;
+
+/*
+ * The operator A (not including the shift mu).
+ *  DENSE:     A   device, float64, n x n column-major, leading dimension lda >= n,
+ *                 symmetric (only its symmetry is assumed, not checked).
+ *  RBF:       pts device, float32, structure-of-arrays d x n (pts[k*n + i] is
+ *                 coordinate k of point i); A_ij = scale * exp(-kconst ||x_i - x_j||^2).
+ *  MATERN32:  same layout; A_ij = scale * (1 + kconst r) exp(-kconst r), r = ||x_i - x_j||.
+ *  kconst is 1/(2 sigma^2) (RBF) or sqrt(3)/ell (Matern-3/2); scale is 1 for a
+ *  plain Gram matrix and 1/n for the kernel ridge normalisation (Section 7.2.2,
+ *  eq. kernel).  Unused fields are ignored.
+ */
+typedef struct {
+    int32_t kind;
+    int64_t n;
+    const double* A;
+    int64_t lda;
+    const float* pts;
+    int32_t d;
+    double kconst;
+    double scale;
+} rr_operator;
+
+/* Test matrix Omega (Section 1.1 eq. testmatrix with q = 0; Section 2). */
+typedef enum { RR_SK_GAUSSIAN = 0, RR_SK_SRHT = 1 } rr_sketch;
+/* Orthogonalisation of A_mu Omega: Algorithm prec_chol_qr (sketched, default) or chol_qr. */
+typedef enum { RR_ORTH_SKETCHED_CHOLQR = 0, RR_ORTH_CHOLQR = 1 } rr_orth;
+/*
+ * Working precision.
+ *  FP64:  everything float64.
+ *  FP32:  matvec in float32 (float32 copy of a dense A, or float32 kernel
+ *         entries) with float64 accumulation; float32 MFMA sketch; Q, Gram,
+ *         Cholesky, dots and vectors float64.
+ *  MIXED: as FP32 but a dense sketch runs bf16 x bf16 -> float32 on MFMA, and the
+ *         residual at every restart is taken with the float64 operator
+ *         (outer float64 iterative refinement).
+ */
+typedef enum { RR_PREC_FP64 = 0, RR_PREC_FP32 = 1, RR_PREC_MIXED = 2 } rr_precision;
+/*
+ * tau rule (Section 3.2).
+ *  OPT: tau = sqrt(mu ||E|| / lam)  (eq. optimal_rho with F = 1/mu in eq. c_randrand_tau);
+ *       falls back to RHO when mu == 0.
+ *  RHO: tau = rho ||E|| / lam        (eq. c_randrand_tau).
+ *  NYS: tau = 1 / lambda_max(G) = ||Pi A_mu^{-1} Pi||^{-1} (eq. nys_tau).
+ * ||E|| = ||(I-Pi) A_mu (I-Pi)|| and lam = lambda_max(Pi A_mu Pi A_mu^{-1} Pi) are
+ * power-iteration estimates (power_iters steps each).
+ */
+typedef enum { RR_TAU_OPT = 0, RR_TAU_RHO = 1, RR_TAU_NYS = 2 } rr_tau_rule;
+
+typedef struct {
+    int64_t l;            /* columns of Omega (sketch size); 0 = plain CG (P = I)       */
+    int32_t sketch;       /* rr_sketch                                                   */
+    uint64_t seed;        /* Omega: stream seed; Theta: seed+1; power starts: seed+2/+3  */
+    int32_t orth;         /* rr_orth                                                     */
+    int32_t prec;         /* rr_precision                                                */
+    int32_t tau_rule;     /* rr_tau_rule                                                 */
+    double rho;           /* RHO rule factor (default 1.0)                               */
+    int32_t power_iters;  /* power iterations per estimate (default 10)                  */
+} rr_build_opts;
+
+typedef struct {
+    double tol;           /* stop when ||b - A_mu x|| <= tol ||b||  (default 1e-6)        */
+    double restart_eta;   /* restart after each residual drop by this factor (1e-2)      */
+    int32_t maxit;        /* maximum PCG iterations (default 5000)                       */
+    int32_t check_every;  /* iterations per device launch batch between host checks (8)  */
+    int32_t fp64_ir;      /* 1: residual at restarts with the float64 operator; -1: by
+                             precision (on for MIXED); 0: off                            */
+    double* relres_history;  /* optional host array: relative residual per iteration     */
+    int32_t history_cap;     /* its length                                               */
+    int32_t use_graph;    /* 1: replay each batch of iterations as a captured hipGraph   */
+    int32_t certify;      /* 1: after convergence, one float64-operator residual fills
+                             info.relres_fp64 (not counted in ms_solve); 0: skip        */
+} rr_solve_opts;
+
+typedef struct {
+    int32_t iters;        /* PCG iterations                                               */
+    int32_t restarts;     /* restarts after the first cycle                               */
+    double relres_work;   /* final relative residual with the working operator            */
+    double relres_fp64;   /* final relative residual with the float64 operator            */
+    double tau, normE, lamhat;  /* preconditioner scale and its two estimates             */
+    double orth_err;      /* ||Q^T Q - I||_max of the stored basis                        */
+    double ms_build;      /* wall time of rr_build_precond                                */
+    double ms_solve;      /* wall time of the solve                                       */
+    int32_t status;       /* rr_status of this solve / column                             */
+} rr_solve_info;
+
+/* Optional device allocator (e.g. backed by PyTorch's caching allocator). */
+typedef struct {
+    void* ctx;
+    void* (*alloc)(void* ctx, size_t bytes, void* stream);
+    void (*free)(void* ctx, void* ptr, void* stream);
+} rr_allocator;
+
+typedef struct rr_precond rr_precond;   /* opaque; immutable after build */
+
+/* Fill option structs with defaults (l = 0 means plain CG). */
+void rr_build_opts_default(rr_build_opts* o);
+void rr_solve_opts_default(rr_solve_opts* o);
+
+/*
+ * Build C-RandRAND preconditioners for the shifts mus[0..n_mu-1] (host array)
+ * — Algorithm RandRAND_PCG steps 1-4 (Section 6.2):
+ *   Omega (Section 2) -> Y = A Omega + mu Omega -> Q R = Y (Algorithm prec_chol_qr or
+ *   chol_qr) -> G (remark after Algorithm RandRAND_PCG) -> T (eq. accurate_proj) -> tau.
+ * With n_mu > 1 all shifts share the joint basis orth([Omega, A Omega]) and each
+ * gets a 2l x l reduced QR (Section 5.1).
+ * A: operator (device memory borrowed).  alloc: NULL = hipMalloc.  out: new handle.
+ * Errors: RR_EINVAL (null pointers, n < 1, l < 0, l > n, n_mu < 1, a negative or
+ * non-finite mu, d < 1 for kernels, unknown enum values), RR_ENOMEM, RR_ENOTSPD,
+ * RR_EDEVICE.  On error *out is NULL.
+ */
+rr_status rr_build_precond(const rr_operator* A, const double* mus, int32_t n_mu,
+                           const rr_build_opts* opts, const rr_allocator* alloc,
+                           void* hip_stream, rr_precond** out);
+
+/*
+ * Solve (A + mus[mu_index] I) x = b by C-RandRAND PCG with restarts
+ * (Algorithm RandRAND_PCG steps 5-11).  b, x: device float64 vectors of length n;
+ * x holds x0 on entry and the solution on exit.  info may be NULL.
+ * A handle built with l = 0 runs plain CG with identical kernels.
+ * Errors: RR_EINVAL (also for NaN/Inf in b), RR_EBREAKDOWN, RR_ENOCONV (x holds the
+ * last iterate), RR_EDEVICE.
+ */
+rr_status rr_solve(const rr_precond* P, int32_t mu_index, const double* b, double* x,
+                   const rr_solve_opts* opts, rr_solve_info* info, void* hip_stream);
+
+/*
+ * Solve nrhs independent systems (A + mus[mu_index_per_col[j]] I) X_j = B_j at once:
+ * one PCG recurrence per column (own alpha, beta, stopping), fused launches,
+ * the kernel matvec of all columns as one MFMA product (Section 5.1 joint basis
+ * when the handle holds several shifts; multi-RHS block of Section 7.2.2).
+ * mu_index_per_col: host int array [nrhs].  B, X: device float64 n x nrhs with
+ * leading dimensions ldb, ldx >= n; X holds X0 on entry.  infos: host [nrhs] or NULL.
+ * Returns RR_OK if every column converged, else the first failing column's status.
+ */
+rr_status rr_solve_batch(const rr_precond* P, const int32_t* mu_index_per_col,
+                         const double* B, int64_t ldb, int32_t nrhs, double* X, int64_t ldx,
+                         const rr_solve_opts* opts, rr_solve_info* infos, void* hip_stream);
+
+/* ---------------------------------------------------------------- serving --- */
+
+/* One solve request.  All pointers are HOST memory owned by the caller and must
+ * stay valid until deliver() is called for the request: pts (d x n float32 SoA),
+ * B (n x nrhs float64), X (n x nrhs float64, written before deliver). */
+typedef struct {
+    int32_t kind;         /* RR_OP_RBF or RR_OP_MATERN32                              */
+    int64_t n;
+    int32_t d;
+    const float* pts;
+    double kconst, scale, mu;
+    int64_t l;            /* sketch size for this request (0 = plain CG)               */
+    int32_t nrhs;
+    const double* B;
+    double* X;
+    uint64_t id;
+    uint64_t seed;
+    double t_arrival;     /* seconds on the clock passed to next()                     */
+} rr_request;
+
+/* next(): return 1 and fill *out if a request has arrived by `now` (seconds since
+ * rr_serve started), 0 if none is due yet, -1 when the stream has ended. */
+typedef int32_t (*rr_next_fn)(void* user, double now, rr_request* out);
+/* deliver(): called once per request after X has been written on the host. */
+typedef void (*rr_deliver_fn)(void* user, const rr_request* req, const rr_solve_info* info,
+                              double t_done);
+
+typedef struct {
+    size_t hbm_budget;    /* device bytes the server may hold for requests               */
+    int32_t max_slots;    /* requests resident at once                                  */
+    int32_t graph_iters;  /* PCG iterations per replayed batch                          */
+    rr_build_opts build;  /* l and seed are taken per request                           */
+    rr_solve_opts solve;
+} rr_serve_config;
+
+typedef struct {
+    double p50_ms, p99_ms, mean_ms;  /* arrival -> delivered latency                     */
+    double solves_per_s;             /* delivered requests / wall time                   */
+    int64_t served, rejected;
+    size_t hbm_peak;
+    int32_t max_active;
+} rr_serve_stats;
+
+/*
+ * Continuous-batching server: a persistent loop polls next(), admits requests while
+ * slots and the HBM budget allow (a request larger than the whole budget is
+ * rejected with status RR_ENOMEM in its deliver()), builds each request's
+ * preconditioner on the device, advances all resident requests' PCG iterations in
+ * batches on separate streams so their work overlaps, and delivers each result
+ * as soon as it converges.  Per-request arithmetic does not depend on what else
+ * is resident.  Returns when next() has returned -1 and every admitted request is
+ * delivered.  Errors: RR_EINVAL, RR_EDEVICE.
+ */
+rr_status rr_serve(const rr_serve_config* cfg, rr_next_fn next, rr_deliver_fn deliver,
+                   void* user, rr_serve_stats* stats);
+
+/* ------------------------------------------------------------ inspection --- */
+
+/*
+ * Copy a handle's state to host memory for checking (any pointer may be NULL):
+ * Q (n x l, the per-shift basis Q_mu), R (l x l), G (l x l), T (l x l),
+ * scalars[4] = {tau, ||E|| estimate, lam estimate, mu}.
+ */
+rr_status rr_precond_export(const rr_precond* P, int32_t mu_index, double* Q_host,
+                            double* R_host, double* G_host, double* T_host,
+                            double* scalars_host);
+
+/* Write Omega (n x l, float64, host) as the handle drew it. */
+rr_status rr_precond_export_omega(const rr_precond* P, double* Omega_host);
+
+/* Number of rows n, columns l and shifts of a handle (any pointer may be NULL). */
+rr_status rr_precond_shape(const rr_precond* P, int64_t* n, int64_t* l, int32_t* n_mu);
+
+/*
+ * Form a kernel operator densely: A_out (device, n x n, leading dimension lda)
+ * = scale * K evaluated in float64 (dtype 0), float32 (1) or bf16 (2, from float64).
+ */
+rr_status rr_kernel_to_dense(const rr_operator* kernel_op, void* A_out, int32_t dtype,
+                             int64_t lda, void* hip_stream);
+
+/*
+ * y = (A + mu I) u with the operator in the given precision (rr_precision; FP32 uses
+ * float32 entries with float64 accumulation).  u, y: device float64 [n].
+ */
+rr_status rr_apply_operator(const rr_operator* A, double mu, int32_t prec, const double* u,
+                            double* y, void* hip_stream);
+
+/*
+ * Fill out (device, rows x cols, float64, column-major) with the method's random
+ * test matrix: kind 0 = Gaussian stream `seed` (element i + c*rows),
+ * kind 1 = SRHT columns (D, sampled Hadamard rows) for n = rows, l = cols.
+ */
+rr_status rr_random_matrix(int32_t kind, uint64_t seed, int64_t rows, int64_t cols,
+                           double* out, void* hip_stream);
+
+void rr_precond_destroy(rr_precond* P);
+const char* rr_status_string(rr_status s);
+const char* rr_last_error(void);
+/* Library version string. */
+const char* rr_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RANDRAND_H */

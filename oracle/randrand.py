@@ -186,6 +186,10 @@ def _tau(rule, mu, rho, Amu, Q, T, G, seed, n, power_iters):
         return tau, normE, lam
     normE = power_norm(E, _rng.gaussian_vector(seed + 2, n), power_iters)
     lam = power_norm(M, _rng.gaussian_vector(seed + 3, n), power_iters)
+    if normE == 0.0:
+        # range(Q) is the whole space (E = 0): eq. c_randrand_tau would give tau = 0
+        # and a singular P; use eq. nys_tau instead
+        return 1.0 / float(np.max(np.linalg.eigvalsh(0.5 * (G + G.T)))), normE, lam
     if rule == OPT and mu > 0:
         tau = float(np.sqrt(mu * normE / lam))
     else:

@@ -1,0 +1,337 @@
+"""ctypes binding of ``librandrand.so`` (the C ABI in include/randrand.h).
+
+Argument marshalling only: every step of the method runs inside the library's
+HIP kernels.  PyTorch supplies device memory (CUDA/HIP tensors) and the HIP
+stream (``torch.cuda.current_stream()``).
+
+Layout: the C ABI is column-major.  An n x m matrix crosses the boundary as the
+memory of a contiguous torch tensor of shape (m, n) (its transpose in row-major
+terms); the helpers below do that conversion.  A symmetric dense A can be
+passed as is.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librandrand.so")
+
+RR_OK, RR_EINVAL, RR_ENOMEM, RR_ENOTSPD, RR_EBREAKDOWN, RR_ENOCONV, RR_EDEVICE, RR_EBUSY = range(8)
+OP_DENSE, OP_RBF, OP_MATERN32 = 0, 1, 2
+SK_GAUSSIAN, SK_SRHT = 0, 1
+ORTH_SKETCHED_CHOLQR, ORTH_CHOLQR = 0, 1
+PREC_FP64, PREC_FP32, PREC_MIXED = 0, 1, 2
+TAU_OPT, TAU_RHO, TAU_NYS = 0, 1, 2
+
+_SKETCH = {"gaussian": SK_GAUSSIAN, "srht": SK_SRHT}
+_PREC = {"fp64": PREC_FP64, "fp32": PREC_FP32, "mixed": PREC_MIXED}
+_TAU = {"opt": TAU_OPT, "rho": TAU_RHO, "nys": TAU_NYS}
+_ORTH = {"sketched": ORTH_SKETCHED_CHOLQR, "cholqr": ORTH_CHOLQR}
+
+
+class rr_operator(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("n", C.c_int64), ("A", C.c_void_p), ("lda", C.c_int64),
+                ("pts", C.c_void_p), ("d", C.c_int32), ("kconst", C.c_double),
+                ("scale", C.c_double)]
+
+
+class rr_build_opts(C.Structure):
+    _fields_ = [("l", C.c_int64), ("sketch", C.c_int32), ("seed", C.c_uint64),
+                ("orth", C.c_int32), ("prec", C.c_int32), ("tau_rule", C.c_int32),
+                ("rho", C.c_double), ("power_iters", C.c_int32)]
+
+
+class rr_solve_opts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("restart_eta", C.c_double), ("maxit", C.c_int32),
+                ("check_every", C.c_int32), ("fp64_ir", C.c_int32),
+                ("relres_history", C.POINTER(C.c_double)), ("history_cap", C.c_int32),
+                ("use_graph", C.c_int32), ("certify", C.c_int32)]
+
+
+class rr_solve_info(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("restarts", C.c_int32), ("relres_work", C.c_double),
+                ("relres_fp64", C.c_double), ("tau", C.c_double), ("normE", C.c_double),
+                ("lamhat", C.c_double), ("orth_err", C.c_double), ("ms_build", C.c_double),
+                ("ms_solve", C.c_double), ("status", C.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class rr_allocator(C.Structure):
+    _fields_ = [("ctx", C.c_void_p),
+                ("alloc", C.CFUNCTYPE(C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p)),
+                ("free", C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p))]
+
+
+class rr_request(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("n", C.c_int64), ("d", C.c_int32), ("pts", C.c_void_p),
+                ("kconst", C.c_double), ("scale", C.c_double), ("mu", C.c_double),
+                ("l", C.c_int64), ("nrhs", C.c_int32), ("B", C.c_void_p), ("X", C.c_void_p),
+                ("id", C.c_uint64), ("seed", C.c_uint64), ("t_arrival", C.c_double)]
+
+
+NEXT_FN = C.CFUNCTYPE(C.c_int32, C.c_void_p, C.c_double, C.POINTER(rr_request))
+DELIVER_FN = C.CFUNCTYPE(None, C.c_void_p, C.POINTER(rr_request), C.POINTER(rr_solve_info),
+                         C.c_double)
+
+
+class rr_serve_config(C.Structure):
+    _fields_ = [("hbm_budget", C.c_size_t), ("max_slots", C.c_int32), ("graph_iters", C.c_int32),
+                ("build", rr_build_opts), ("solve", rr_solve_opts)]
+
+
+class rr_serve_stats(C.Structure):
+    _fields_ = [("p50_ms", C.c_double), ("p99_ms", C.c_double), ("mean_ms", C.c_double),
+                ("solves_per_s", C.c_double), ("served", C.c_int64), ("rejected", C.c_int64),
+                ("hbm_peak", C.c_size_t), ("max_active", C.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib():
+    """Load the library; raise loudly if it was not built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                              "(hipcc for gfx950); there is no fallback path")
+        L = C.CDLL(LIB_PATH)
+        P = C.c_void_p
+        L.rr_build_opts_default.argtypes = [C.POINTER(rr_build_opts)]
+        L.rr_solve_opts_default.argtypes = [C.POINTER(rr_solve_opts)]
+        L.rr_build_precond.argtypes = [C.POINTER(rr_operator), C.POINTER(C.c_double), C.c_int32,
+                                       C.POINTER(rr_build_opts), C.POINTER(rr_allocator), P,
+                                       C.POINTER(P)]
+        L.rr_solve.argtypes = [P, C.c_int32, P, P, C.POINTER(rr_solve_opts),
+                               C.POINTER(rr_solve_info), P]
+        L.rr_solve_batch.argtypes = [P, C.POINTER(C.c_int32), P, C.c_int64, C.c_int32, P, C.c_int64,
+                                     C.POINTER(rr_solve_opts), C.POINTER(rr_solve_info), P]
+        L.rr_serve.argtypes = [C.POINTER(rr_serve_config), NEXT_FN, DELIVER_FN, P,
+                               C.POINTER(rr_serve_stats)]
+        L.rr_precond_export.argtypes = [P, C.c_int32, P, P, P, P, P]
+        L.rr_precond_export_omega.argtypes = [P, P]
+        L.rr_precond_shape.argtypes = [P, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
+                                       C.POINTER(C.c_int32)]
+        L.rr_kernel_to_dense.argtypes = [C.POINTER(rr_operator), P, C.c_int32, C.c_int64, P]
+        L.rr_apply_operator.argtypes = [C.POINTER(rr_operator), C.c_double, C.c_int32, P, P, P]
+        L.rr_random_matrix.argtypes = [C.c_int32, C.c_uint64, C.c_int64, C.c_int64, P, P]
+        L.rr_precond_destroy.argtypes = [P]
+        L.rr_precond_destroy.restype = None
+        L.rr_status_string.argtypes = [C.c_int32]
+        L.rr_status_string.restype = C.c_char_p
+        L.rr_last_error.restype = C.c_char_p
+        L.rr_version.restype = C.c_char_p
+        for name in ("rr_build_precond", "rr_solve", "rr_solve_batch", "rr_serve",
+                     "rr_precond_export", "rr_precond_export_omega", "rr_precond_shape",
+                     "rr_kernel_to_dense", "rr_apply_operator", "rr_random_matrix"):
+            getattr(L, name).restype = C.c_int32
+        _lib = L
+    return _lib
+
+
+class RRError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        msg = lib().rr_last_error().decode()
+        super().__init__(f"{where}: {lib().rr_status_string(status).decode()} ({msg})")
+
+
+def _check(st: int, where: str, ok=(RR_OK,)):
+    if st not in ok:
+        raise RRError(st, where)
+    return st
+
+
+def _stream(stream=None):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t) -> C.c_void_p:
+    return C.c_void_p(t.data_ptr())
+
+
+# ------------------------------------------------------------------ operators
+@dataclass
+class Operator:
+    struct: rr_operator
+    keep: tuple = ()
+
+    @property
+    def n(self) -> int:
+        return int(self.struct.n)
+
+
+def dense_operator(A) -> Operator:
+    """A: CUDA float64 tensor (n, n), symmetric and contiguous (same bytes in both orders)."""
+    import torch
+    assert A.is_cuda and A.dtype == torch.float64 and A.is_contiguous() and A.shape[0] == A.shape[1]
+    s = rr_operator(kind=OP_DENSE, n=A.shape[0], A=A.data_ptr(), lda=A.shape[0], pts=None, d=0,
+                    kconst=0.0, scale=1.0)
+    return Operator(s, (A,))
+
+
+def kernel_operator(kind: int, pts, kconst: float, scale: float) -> Operator:
+    """pts: CUDA float32 tensor (d, n) contiguous (structure of arrays)."""
+    import torch
+    assert pts.is_cuda and pts.dtype == torch.float32 and pts.is_contiguous() and pts.dim() == 2
+    s = rr_operator(kind=kind, n=pts.shape[1], A=None, lda=0, pts=pts.data_ptr(), d=pts.shape[0],
+                    kconst=float(kconst), scale=float(scale))
+    return Operator(s, (pts,))
+
+
+def build_opts(l=0, sketch="gaussian", seed=0, orth="sketched", prec="fp64", tau_rule="opt",
+               rho=1.0, power_iters=10) -> rr_build_opts:
+    o = rr_build_opts()
+    lib().rr_build_opts_default(C.byref(o))
+    o.l = int(l)
+    o.sketch = _SKETCH[sketch] if isinstance(sketch, str) else int(sketch)
+    o.seed = int(seed)
+    o.orth = _ORTH[orth] if isinstance(orth, str) else int(orth)
+    o.prec = _PREC[prec] if isinstance(prec, str) else int(prec)
+    o.tau_rule = _TAU[tau_rule] if isinstance(tau_rule, str) else int(tau_rule)
+    o.rho = float(rho)
+    o.power_iters = int(power_iters)
+    return o
+
+
+def solve_opts(tol=1e-6, restart_eta=1e-2, maxit=5000, check_every=8, fp64_ir=-1,
+               use_graph=False, certify=True, history=None) -> rr_solve_opts:
+    o = rr_solve_opts()
+    lib().rr_solve_opts_default(C.byref(o))
+    o.tol = float(tol)
+    o.restart_eta = float(restart_eta)
+    o.maxit = int(maxit)
+    o.check_every = int(check_every)
+    o.fp64_ir = int(fp64_ir)
+    o.use_graph = 1 if use_graph else 0
+    o.certify = 1 if certify else 0
+    if history is not None:
+        o.relres_history = history.ctypes.data_as(C.POINTER(C.c_double))
+        o.history_cap = len(history)
+    return o
+
+
+class Precond:
+    """Owning wrapper of an rr_precond handle."""
+
+    def __init__(self, handle: C.c_void_p, op: Operator, mus):
+        self.h = handle
+        self.op = op
+        self.mus = list(mus)
+
+    def __del__(self):
+        try:
+            if self.h:
+                lib().rr_precond_destroy(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+    @property
+    def shape(self):
+        n, l, m = C.c_int64(), C.c_int64(), C.c_int32()
+        _check(lib().rr_precond_shape(self.h, C.byref(n), C.byref(l), C.byref(m)), "rr_precond_shape")
+        return n.value, l.value, m.value
+
+    def solve(self, b, x0=None, mu_index=0, stream=None, ok=(RR_OK,), **kw):
+        """b: CUDA float64 (n,).  Returns (x, info dict)."""
+        import torch
+        x = torch.zeros_like(b) if x0 is None else x0.clone()
+        hist = kw.pop("history", None)
+        o = solve_opts(history=hist, **kw)
+        info = rr_solve_info()
+        st = lib().rr_solve(self.h, int(mu_index), _ptr(b), _ptr(x), C.byref(o), C.byref(info),
+                            _stream(stream))
+        _check(st, "rr_solve", ok)
+        d = info.as_dict()
+        d["rc"] = st
+        return x, d
+
+    def solve_batch(self, B, mu_index_per_col: Sequence[int], X0=None, stream=None, ok=(RR_OK,),
+                    **kw):
+        """B: CUDA float64 (n, m).  Returns (X (n, m), list of info dicts)."""
+        import torch
+        n, m = B.shape
+        Bc = B.t().contiguous()                 # column-major n x m
+        Xc = torch.zeros_like(Bc) if X0 is None else X0.t().contiguous()
+        idx = (C.c_int32 * m)(*[int(i) for i in mu_index_per_col])
+        infos = (rr_solve_info * m)()
+        o = solve_opts(**kw)
+        st = lib().rr_solve_batch(self.h, idx, _ptr(Bc), n, m, _ptr(Xc), n, C.byref(o), infos,
+                                  _stream(stream))
+        _check(st, "rr_solve_batch", ok)
+        return Xc.t(), [i.as_dict() for i in infos], st
+
+    def export(self, mu_index=0, with_q=True):
+        n, l, _ = self.shape
+        Q = np.zeros((l, n)) if (with_q and l) else None
+        R = np.zeros((l, l)); G = np.zeros((l, l)); T = np.zeros((l, l))
+        sc = np.zeros(4)
+        p = lambda a: None if a is None else a.ctypes.data_as(C.c_void_p)
+        _check(lib().rr_precond_export(self.h, int(mu_index), p(Q), p(R) if l else None,
+                                       p(G) if l else None, p(T) if l else None, p(sc)),
+               "rr_precond_export")
+        out = {"tau": sc[0], "normE": sc[1], "lam": sc[2], "mu": sc[3]}
+        if l:
+            out.update(R=R.T.copy(), G=G.T.copy(), T=T.T.copy())
+            if Q is not None:
+                out["Q"] = Q.T.copy()
+        return out
+
+    def omega(self):
+        n, l, _ = self.shape
+        O = np.zeros((l, n))
+        _check(lib().rr_precond_export_omega(self.h, O.ctypes.data_as(C.c_void_p)), "export_omega")
+        return O.T.copy()
+
+
+def build_precond(op: Operator, mus, l=0, stream=None, **kw) -> Precond:
+    mus = [float(m) for m in (mus if isinstance(mus, (list, tuple)) else [mus])]
+    arr = (C.c_double * len(mus))(*mus)
+    o = build_opts(l=l, **kw)
+    h = C.c_void_p()
+    st = lib().rr_build_precond(C.byref(op.struct), arr, len(mus), C.byref(o), None,
+                                _stream(stream), C.byref(h))
+    _check(st, "rr_build_precond")
+    return Precond(h, op, mus)
+
+
+def kernel_to_dense(op: Operator, dtype: str = "fp64", stream=None):
+    import torch
+    n = op.n
+    tdt = {"fp64": torch.float64, "fp32": torch.float32, "bf16": torch.bfloat16}[dtype]
+    code = {"fp64": 0, "fp32": 1, "bf16": 2}[dtype]
+    A = torch.empty((n, n), dtype=tdt, device="cuda")
+    _check(lib().rr_kernel_to_dense(C.byref(op.struct), _ptr(A), code, n, _stream(stream)),
+           "rr_kernel_to_dense")
+    return A   # symmetric: row-major bytes == column-major bytes
+
+
+def apply_operator(op: Operator, mu: float, prec: str, u, stream=None):
+    import torch
+    y = torch.empty_like(u)
+    _check(lib().rr_apply_operator(C.byref(op.struct), float(mu), _PREC[prec], _ptr(u), _ptr(y),
+                                   _stream(stream)), "rr_apply_operator")
+    return y
+
+
+def random_matrix(kind: str, seed: int, rows: int, cols: int, stream=None):
+    """Returns a CUDA float64 tensor (rows, cols) with the library's test matrix."""
+    import torch
+    out = torch.empty((cols, rows), dtype=torch.float64, device="cuda")
+    _check(lib().rr_random_matrix({"gaussian": 0, "srht": 1}[kind], int(seed), int(rows), int(cols),
+                                  _ptr(out), _stream(stream)), "rr_random_matrix")
+    return out.t()

@@ -1,0 +1,316 @@
+// C-ABI plumbing: error strings, defaults, allocation, operator dispatch,
+// inspection/export entry points.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "ctx.hpp"
+
+namespace rr {
+
+static thread_local std::string g_last_error;
+void set_error(const std::string& msg) { g_last_error = msg; }
+const std::string& last_error() { return g_last_error; }
+
+void* Alloc::get(size_t bytes) const {
+    void* p = nullptr;
+    if (custom) {
+        p = a.alloc(a.ctx, bytes, (void*)st);
+        if (!p) throw RrError{RR_ENOMEM, "allocator returned null for " + std::to_string(bytes) + " bytes"};
+        return p;
+    }
+    const hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        throw RrError{RR_ENOMEM, "hipMalloc(" + std::to_string(bytes) + ") failed: " + hipGetErrorString(e)};
+    }
+    return p;
+}
+
+void Alloc::put(void* p) const {
+    if (!p) return;
+    if (custom) a.free(a.ctx, p, (void*)st);
+    else (void)hipFree(p);
+}
+
+KernelOp kernel_op_of(const rr_precond& P) {
+    KernelOp k;
+    k.kind = P.op.kind;
+    k.n = P.op.n;
+    k.d = P.op.d;
+    k.pts = P.op.pts;
+    k.sqn = P.sqn.as<float>();
+    k.kconst = P.op.kconst;
+    k.scale = P.op.scale;
+    return k;
+}
+
+int operator_part_count(const rr_precond& P) {
+    return is_kernel(P.op) ? kernel_matvec_blocks(P.n) : dense_matvec_blocks(P.n);
+}
+
+size_t operator_ws_doubles(const rr_precond& P) {
+    return is_kernel(P.op) ? kernel_matvec_ws_doubles(P.n) : 0;
+}
+
+int apply_operator(const rr_precond& P, const double* u, double mu, double* y, double* dot_part,
+                   double* kmv_ws, bool fp64, const int32_t* stop, hipStream_t st) {
+    if (is_kernel(P.op)) {
+        const KernelOp k = kernel_op_of(P);
+        launch_kernel_matvec(k, fp64 || P.opts.prec == RR_PREC_FP64, u, mu, y, dot_part, kmv_ws,
+                             stop, st);
+        return kernel_matvec_blocks(P.n);
+    }
+    if (!fp64 && P.A32.ptr())
+        launch_dense_matvec(DT_F32, P.n, P.A32.ptr(), P.n, u, mu, y, dot_part, stop, st);
+    else
+        launch_dense_matvec(DT_F64, P.n, P.op.A, P.op.lda, u, mu, y, dot_part, stop, st);
+    return dense_matvec_blocks(P.n);
+}
+
+int apply_projected(const rr_precond& P, const double* Kc, const double* r, double rcoef, double* z,
+                    double* c_part, double* d, double* rz_part, const int32_t* stop, hipStream_t st) {
+    const int nch = gemv_t_chunks(P.n, P.kb);
+    launch_gemv_t(P.n, P.kb, P.Qb.as<double>(), P.n, r, c_part, nch, stop, st);
+    launch_core_apply(P.kb, Kc, P.kb, c_part, nch, d, stop, st);
+    launch_qd(P.n, P.kb, P.Qb.as<double>(), P.n, d, r, rcoef, z, rz_part, stop, st);
+    return qd_blocks(P.n);
+}
+
+rr_status validate_operator(const rr_operator* A) {
+    RR_REQUIRE(A != nullptr, "operator is null");
+    RR_REQUIRE(A->n >= 1, "operator n must be >= 1");
+    RR_REQUIRE(A->n <= (int64_t)1 << 31, "operator n too large");
+    if (A->kind == RR_OP_DENSE) {
+        RR_REQUIRE(A->A != nullptr, "dense operator: A is null");
+        RR_REQUIRE(A->lda >= A->n, "dense operator: lda < n");
+    } else if (A->kind == RR_OP_RBF || A->kind == RR_OP_MATERN32) {
+        RR_REQUIRE(A->pts != nullptr, "kernel operator: pts is null");
+        RR_REQUIRE(A->d >= 1 && A->d <= 32, "kernel operator: d must be in [1, 32]");
+        RR_REQUIRE(std::isfinite(A->kconst) && A->kconst > 0.0, "kernel operator: kconst must be finite and > 0");
+        RR_REQUIRE(std::isfinite(A->scale) && A->scale > 0.0, "kernel operator: scale must be finite and > 0");
+    } else {
+        RR_REQUIRE(false, "unknown operator kind");
+    }
+    return RR_OK;
+}
+
+void require_device() {
+    int count = 0;
+    const hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess || count < 1) {
+        (void)hipGetLastError();
+        throw RrError{RR_EDEVICE, "no usable HIP device"};
+    }
+}
+
+}  // namespace rr
+
+rr_precond::~rr_precond() {
+    if (ws) rr_free_workspace(ws);
+}
+
+using namespace rr;
+
+extern "C" {
+
+void rr_build_opts_default(rr_build_opts* o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->l = 0;
+    o->sketch = RR_SK_GAUSSIAN;
+    o->seed = 0;
+    o->orth = RR_ORTH_SKETCHED_CHOLQR;
+    o->prec = RR_PREC_FP64;
+    o->tau_rule = RR_TAU_OPT;
+    o->rho = 1.0;
+    o->power_iters = 10;
+}
+
+void rr_solve_opts_default(rr_solve_opts* o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->tol = 1e-6;
+    o->restart_eta = 1e-2;
+    o->maxit = 5000;
+    o->check_every = 8;
+    o->fp64_ir = -1;
+    o->relres_history = nullptr;
+    o->history_cap = 0;
+    o->use_graph = 0;
+    o->certify = 1;
+}
+
+const char* rr_status_string(rr_status s) {
+    switch (s) {
+        case RR_OK: return "RR_OK";
+        case RR_EINVAL: return "RR_EINVAL: invalid argument";
+        case RR_ENOMEM: return "RR_ENOMEM: out of device memory or budget";
+        case RR_ENOTSPD: return "RR_ENOTSPD: Cholesky failed after the shift ladder";
+        case RR_EBREAKDOWN: return "RR_EBREAKDOWN: PCG breakdown";
+        case RR_ENOCONV: return "RR_ENOCONV: maximum iterations reached";
+        case RR_EDEVICE: return "RR_EDEVICE: HIP device error";
+        case RR_EBUSY: return "RR_EBUSY: resource busy";
+    }
+    return "unknown rr_status";
+}
+
+const char* rr_last_error(void) { return g_last_error.c_str(); }
+
+const char* rr_version(void) { return "randrand-gfx950 0.1"; }
+
+void rr_precond_destroy(rr_precond* P) {
+    if (!P) return;
+    try {
+        delete P;
+    } catch (...) {
+    }
+}
+
+rr_status rr_precond_shape(const rr_precond* P, int64_t* n, int64_t* l, int32_t* n_mu) {
+    return guarded([&]() -> rr_status {
+        RR_REQUIRE(P != nullptr, "handle is null");
+        if (n) *n = P->n;
+        if (l) *l = P->l;
+        if (n_mu) *n_mu = (int32_t)P->per.size();
+        return RR_OK;
+    });
+}
+
+rr_status rr_precond_export(const rr_precond* P, int32_t mu_index, double* Q_host, double* R_host,
+                            double* G_host, double* T_host, double* scalars_host) {
+    return guarded([&]() -> rr_status {
+        RR_REQUIRE(P != nullptr, "handle is null");
+        RR_REQUIRE(mu_index >= 0 && mu_index < (int32_t)P->per.size(), "mu_index out of range");
+        const PerMu& pm = P->per[mu_index];
+        const int64_t n = P->n, l = P->l;
+        if (scalars_host) {
+            scalars_host[0] = pm.tau;
+            scalars_host[1] = pm.normE;
+            scalars_host[2] = pm.lam;
+            scalars_host[3] = pm.mu;
+        }
+        if (l == 0) return RR_OK;
+        RR_HIP(hipSetDevice(P->device));
+        RR_HIP(hipDeviceSynchronize());
+        if (Q_host) {
+            if (!P->joint) {
+                RR_HIP(hipMemcpy(Q_host, P->Qb.ptr(), (size_t)n * l * sizeof(double), hipMemcpyDeviceToHost));
+            } else {
+                Alloc al;
+                DBuf Q(&al, (size_t)n * l * sizeof(double));
+                DBuf ws(&al, gemm_ws_doubles(n, l, P->kb) * sizeof(double));
+                launch_gemm(DT_F64, false, DT_F64, false, n, l, P->kb, P->Qb.ptr(), n, pm.Qred.ptr(),
+                            P->kb, Q.as<double>(), n, 1.0, 0.0, ws.as<double>(),
+                            gemm_ws_doubles(n, l, P->kb), nullptr);
+                RR_HIP(hipDeviceSynchronize());
+                RR_HIP(hipMemcpy(Q_host, Q.ptr(), (size_t)n * l * sizeof(double), hipMemcpyDeviceToHost));
+            }
+        }
+        const size_t ll = (size_t)l * l * sizeof(double);
+        if (R_host) RR_HIP(hipMemcpy(R_host, pm.R.ptr(), ll, hipMemcpyDeviceToHost));
+        if (G_host) RR_HIP(hipMemcpy(G_host, pm.G.ptr(), ll, hipMemcpyDeviceToHost));
+        if (T_host) RR_HIP(hipMemcpy(T_host, pm.T.ptr(), ll, hipMemcpyDeviceToHost));
+        return RR_OK;
+    });
+}
+
+rr_status rr_precond_export_omega(const rr_precond* P, double* Omega_host) {
+    return guarded([&]() -> rr_status {
+        RR_REQUIRE(P != nullptr && Omega_host != nullptr, "null argument");
+        if (P->l == 0) return RR_OK;
+        RR_HIP(hipSetDevice(P->device));
+        Alloc al;
+        DBuf O(&al, (size_t)P->n * P->l * sizeof(double));
+        launch_copy_mat(P->omega_dt, P->Omega.ptr(), P->n, DT_F64, O.ptr(), P->n, P->n, P->l, nullptr);
+        RR_HIP(hipDeviceSynchronize());
+        RR_HIP(hipMemcpy(Omega_host, O.ptr(), (size_t)P->n * P->l * sizeof(double), hipMemcpyDeviceToHost));
+        return RR_OK;
+    });
+}
+
+rr_status rr_kernel_to_dense(const rr_operator* kop, void* A_out, int32_t dtype, int64_t lda,
+                             void* hip_stream) {
+    return guarded([&]() -> rr_status {
+        validate_operator(kop);
+        RR_REQUIRE(is_kernel(*kop), "rr_kernel_to_dense needs a kernel operator");
+        RR_REQUIRE(A_out != nullptr, "A_out is null");
+        RR_REQUIRE(lda >= kop->n, "lda < n");
+        RR_REQUIRE(dtype >= 0 && dtype <= 2, "dtype must be 0 (f64), 1 (f32) or 2 (bf16)");
+        require_device();
+        KernelOp k;
+        k.kind = kop->kind; k.n = kop->n; k.d = kop->d; k.pts = kop->pts; k.sqn = nullptr;
+        k.kconst = kop->kconst; k.scale = kop->scale;
+        hipStream_t st = (hipStream_t)hip_stream;
+        launch_kernel_to_dense(k, A_out, dtype, lda, st);
+        RR_HIP(hipGetLastError());
+        RR_HIP(hipStreamSynchronize(st));
+        return RR_OK;
+    });
+}
+
+rr_status rr_apply_operator(const rr_operator* A, double mu, int32_t prec, const double* u, double* y,
+                            void* hip_stream) {
+    return guarded([&]() -> rr_status {
+        validate_operator(A);
+        RR_REQUIRE(u != nullptr && y != nullptr, "u or y is null");
+        RR_REQUIRE(std::isfinite(mu), "mu must be finite");
+        RR_REQUIRE(prec >= 0 && prec <= 2, "unknown precision");
+        require_device();
+        hipStream_t st = (hipStream_t)hip_stream;
+        rr_precond P;   // a transient handle holding only the operator view
+        P.op = *A;
+        P.n = A->n;
+        P.opts.prec = prec;
+        P.alloc.st = st;
+        const int64_t n = A->n;
+        DBuf part(&P.alloc, (size_t)(operator_part_count(P) + 1) * sizeof(double));
+        DBuf kws(&P.alloc, (operator_ws_doubles(P) + 1) * sizeof(double));
+        if (is_kernel(*A)) {
+            P.sqn.reset(&P.alloc, (size_t)n * sizeof(float));
+            launch_sqnorms(A->pts, n, A->d, P.sqn.as<float>(), st);
+        } else if (prec != RR_PREC_FP64) {
+            P.A32.reset(&P.alloc, (size_t)n * n * sizeof(float));
+            launch_copy_mat(DT_F64, A->A, A->lda, DT_F32, P.A32.ptr(), n, n, n, st);
+        }
+        apply_operator(P, u, mu, y, part.as<double>(), kws.as<double>(), prec == RR_PREC_FP64,
+                       nullptr, st);
+        RR_HIP(hipGetLastError());
+        RR_HIP(hipStreamSynchronize(st));
+        return RR_OK;
+    });
+}
+
+rr_status rr_random_matrix(int32_t kind, uint64_t seed, int64_t rows, int64_t cols, double* out,
+                           void* hip_stream) {
+    return guarded([&]() -> rr_status {
+        RR_REQUIRE(out != nullptr, "out is null");
+        RR_REQUIRE(rows >= 1 && cols >= 1, "rows and cols must be >= 1");
+        RR_REQUIRE(kind == 0 || kind == 1, "kind must be 0 (Gaussian) or 1 (SRHT)");
+        require_device();
+        hipStream_t st = (hipStream_t)hip_stream;
+        if (kind == 0) {
+            launch_gauss_fill(out, DT_F64, rows, cols, rows, seed, st);
+        } else {
+            int64_t s = 1;
+            while (s < rows) s *= 2;
+            RR_REQUIRE(cols <= s, "SRHT: cols exceeds padded size");
+            Alloc al;
+            al.st = st;
+            DBuf perm(&al, (size_t)s * sizeof(int32_t));
+            DBuf srows(&al, (size_t)cols * sizeof(int32_t));
+            DBuf D(&al, (size_t)rows * sizeof(float));
+            launch_srht_prepare(rows, cols, seed, s, perm.as<int32_t>(), srows.as<int32_t>(), D.as<float>(), st);
+            launch_srht_fill(out, DT_F64, rows, cols, rows, D.as<float>(), srows.as<int32_t>(), st);
+            RR_HIP(hipStreamSynchronize(st));
+        }
+        RR_HIP(hipGetLastError());
+        RR_HIP(hipStreamSynchronize(st));
+        return RR_OK;
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,446 @@
+// rr_build_precond: C-RandRAND preconditioner construction on the device,
+// following Algorithm RandRAND_PCG steps 1-4 (Section 6.2) with the explicit
+// basis of Section 4.1:
+//   Omega (Section 2) -> Y_mu = A Omega + mu Omega -> Y_mu = Q R by the
+//   sketched Cholesky QR of Algorithm prec_chol_qr (or Algorithm chol_qr) ->
+//   G = (R_Omega R^{-1})^T (R_Omega R^{-1}) with R_Omega^T R_Omega = Omega^T A_mu Omega
+//   (remark after Algorithm RandRAND_PCG) -> T = 2I - Q^T Q (eq. accurate_proj)
+//   -> tau (eq. c_randrand_tau / optimal_rho / nys_tau, power iterations) ->
+//   apply core K = tau T G T - T, so that P = I + Q K Q^T.
+// Several shifts share the joint basis Q_joint = orth([Omega, A Omega]) and a
+// per-shift 2l x l reduced Householder QR (Section 5.1).
+// Only status words and a handful of scalars travel to the host.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <memory>
+#include <vector>
+
+#include "ctx.hpp"
+
+using namespace rr;
+
+namespace {
+
+struct Builder {
+    rr_precond& P;
+    hipStream_t st;
+    const Alloc* al;
+    DBuf gws;
+    size_t gwsd = 0;
+    DBuf status;   // int32
+    DBuf scal;     // doubles
+    DBuf kws;      // kernel-matvec workspace
+    DBuf vparts;   // partial sums
+
+    Builder(rr_precond& p, hipStream_t s) : P(p), st(s), al(&p.alloc) {
+        const int64_t kmax = std::max<int64_t>(2 * p.l, 1);
+        gwsd = std::max<size_t>((size_t)4 * kmax * kmax, (size_t)1 << 22);
+        gws.reset(al, gwsd * sizeof(double));
+        status.reset(al, 64);
+        scal.reset(al, 64 * sizeof(double));
+        kws.reset(al, (operator_ws_doubles(p) + 1) * sizeof(double));
+        const int parts = std::max({operator_part_count(p), qd_blocks(p.n), vec_blocks(p.n), 1});
+        vparts.reset(al, (size_t)parts * sizeof(double));
+    }
+
+    void gemm(int dta, bool ta, int dtb, bool tb, int64_t M, int64_t N, int64_t K, const void* A,
+              int64_t lda, const void* B, int64_t ldb, double* C, int64_t ldc, double alpha = 1.0,
+              double beta = 0.0) {
+        launch_gemm(dta, ta, dtb, tb, M, N, K, A, lda, B, ldb, C, ldc, alpha, beta, gws.as<double>(),
+                    gwsd, st);
+    }
+    DBuf mat(int64_t rows, int64_t cols, size_t esz = sizeof(double)) {
+        return DBuf(al, (size_t)rows * cols * esz);
+    }
+    void sync() { RR_HIP(hipStreamSynchronize(st)); }
+    void check_launch() { RR_HIP(hipGetLastError()); }
+
+    // In-place upper Cholesky of the l x l spd matrix A with the shift ladder of
+    // Appendix C: on failure retry with A + alpha I, alpha in {1e-14,...,1e-1} * max_i A_ii.
+    void chol_ladder(double* A, int64_t l) {
+        DBuf copy = mat(l, l);
+        RR_HIP(hipMemcpyAsync(copy.ptr(), A, (size_t)l * l * sizeof(double), hipMemcpyDeviceToDevice, st));
+        int32_t h = 0;
+        RR_HIP(hipMemsetAsync(status.ptr(), 0, sizeof(int32_t), st));
+        launch_cholesky_upper(A, l, l, status.as<int32_t>(), gws.as<double>(), gwsd, st);
+        check_launch();
+        RR_HIP(hipMemcpyAsync(&h, status.ptr(), sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        sync();
+        if (h == 0) return;
+        std::vector<double> hc((size_t)l * l);
+        RR_HIP(hipMemcpy(hc.data(), copy.ptr(), hc.size() * sizeof(double), hipMemcpyDeviceToHost));
+        double wn = 0.0;
+        for (int64_t i = 0; i < l; ++i) wn = std::max(wn, std::fabs(hc[(size_t)i + (size_t)i * l]));
+        if (!(wn > 0.0) || !std::isfinite(wn)) throw RrError{RR_ENOTSPD, "Cholesky: matrix is zero or not finite"};
+        for (int e = -14; e <= -1; ++e) {
+            const double alpha = std::pow(10.0, e) * wn;
+            RR_HIP(hipMemcpyAsync(A, copy.ptr(), (size_t)l * l * sizeof(double), hipMemcpyDeviceToDevice, st));
+            launch_add_diag(A, l, l, alpha, st);
+            RR_HIP(hipMemsetAsync(status.ptr(), 0, sizeof(int32_t), st));
+            launch_cholesky_upper(A, l, l, status.as<int32_t>(), gws.as<double>(), gwsd, st);
+            check_launch();
+            RR_HIP(hipMemcpyAsync(&h, status.ptr(), sizeof(int32_t), hipMemcpyDeviceToHost, st));
+            sync();
+            if (h == 0) return;
+        }
+        throw RrError{RR_ENOTSPD, "Cholesky failed after the whole shift ladder"};
+    }
+
+    // Y = A Omega + mu Omega (the sketch, q = 0).
+    void sketch(const void* Om, int odt, double mu, void* Y, int ydt, const void* A16) {
+        const int64_t n = P.n, l = P.l;
+        if (is_kernel(P.op)) {
+            const KernelOp k = kernel_op_of(P);
+            if (ydt == DT_F32) launch_kernel_gemm_f32(k, (const float*)Om, n, l, mu, (float*)Y, n, st);
+            else launch_kernel_gemm_f64(k, (const double*)Om, n, l, mu, (double*)Y, n, st);
+            check_launch();
+            return;
+        }
+        launch_copy_mat(odt, Om, n, DT_F64, Y, n, n, l, st);
+        launch_scale_mat((double*)Y, n, n, l, mu, st);
+        if (A16) gemm(DT_BF16, false, odt, false, n, l, n, A16, n, Om, n, (double*)Y, n, 1.0, 1.0);
+        else if (P.A32.ptr()) gemm(DT_F32, false, odt, false, n, l, n, P.A32.ptr(), n, Om, n, (double*)Y, n, 1.0, 1.0);
+        else gemm(DT_F64, false, odt, false, n, l, n, P.op.A, P.op.lda, Om, n, (double*)Y, n, 1.0, 1.0);
+        check_launch();
+    }
+
+    // Q (n x k) R (k x k) = Y (n x k).  Sketched: Algorithm prec_chol_qr with a
+    // Gaussian Theta (2k x n, stream theta_seed); plain: Algorithm chol_qr.
+    void orth(const void* Y, int ydt, int64_t k, uint64_t theta_seed, double* Q, double* R) {
+        const int64_t n = P.n;
+        if (P.opts.orth == RR_ORTH_SKETCHED_CHOLQR) {
+            DBuf theta = mat(2 * k, n);
+            launch_gauss_fill(theta.ptr(), DT_F64, 2 * k, n, 2 * k, theta_seed, st);
+            DBuf S = mat(2 * k, k);
+            gemm(DT_F64, false, ydt, false, 2 * k, k, n, theta.ptr(), 2 * k, Y, n, S.as<double>(), 2 * k);
+            theta.release();
+            DBuf Rsk = mat(k, k);
+            launch_householder_r(S.as<double>(), 2 * k, k, 2 * k, Rsk.as<double>(), k, st);
+            check_launch();
+            DBuf Rskinv = mat(k, k);
+            launch_tri_inv_upper(Rsk.as<double>(), k, k, Rskinv.as<double>(), k, st);
+            DBuf W = mat(n, k);
+            gemm(ydt, false, DT_F64, false, n, k, k, Y, n, Rskinv.ptr(), k, W.as<double>(), n);
+            DBuf GW = mat(k, k);
+            gemm(DT_F64, true, DT_F64, false, k, k, n, W.ptr(), n, W.ptr(), n, GW.as<double>(), k);
+            launch_symmetrize(GW.as<double>(), k, k, st);
+            chol_ladder(GW.as<double>(), k);            // GW <- R_chol
+            DBuf Rcinv = mat(k, k);
+            launch_tri_inv_upper(GW.as<double>(), k, k, Rcinv.as<double>(), k, st);
+            gemm(DT_F64, false, DT_F64, false, n, k, k, W.ptr(), n, Rcinv.ptr(), k, Q, n);
+            gemm(DT_F64, false, DT_F64, false, k, k, k, GW.ptr(), k, Rsk.ptr(), k, R, k);  // R = R_chol R_sk
+            launch_zero_lower(R, k, k, st);
+        } else {
+            gemm(ydt, true, ydt, false, k, k, n, Y, n, Y, n, R, k);
+            launch_symmetrize(R, k, k, st);
+            chol_ladder(R, k);
+            DBuf Rinv = mat(k, k);
+            launch_tri_inv_upper(R, k, k, Rinv.as<double>(), k, st);
+            gemm(ydt, false, DT_F64, false, n, k, k, Y, n, Rinv.ptr(), k, Q, n);
+        }
+        check_launch();
+    }
+
+    // Power iteration: v <- op(v)/||op(v)|| from a Gaussian start (stream seed);
+    // returns ||op(v)|| for the last unit v.
+    template <typename Op>
+    double power_norm(Op op, uint64_t seed, int iters) {
+        const int64_t n = P.n;
+        DBuf v(al, n * sizeof(double)), w(al, n * sizeof(double));
+        launch_gauss_fill(v.ptr(), DT_F64, n, 1, n, seed, st);
+        launch_dot_part(n, v.as<double>(), v.as<double>(), vparts.as<double>(), st);
+        launch_normalize(n, v.as<double>(), v.as<double>(), vparts.as<double>(), vec_blocks(n), scal.as<double>() + 1, st);
+        for (int it = 0; it < iters; ++it) {
+            op(v.as<double>(), w.as<double>());
+            launch_dot_part(n, w.as<double>(), w.as<double>(), vparts.as<double>(), st);
+            launch_normalize(n, v.as<double>(), w.as<double>(), vparts.as<double>(), vec_blocks(n), scal.as<double>(), st);
+        }
+        check_launch();
+        double lam = 0.0;
+        RR_HIP(hipMemcpyAsync(&lam, scal.ptr(), sizeof(double), hipMemcpyDeviceToHost, st));
+        sync();
+        return lam;
+    }
+
+    // lambda_max of a small spd k x k matrix by power iteration on the device.
+    double small_lambda_max(const double* G, int64_t k, uint64_t seed) {
+        DBuf v(al, k * sizeof(double)), w(al, k * sizeof(double));
+        launch_gauss_fill(v.ptr(), DT_F64, k, 1, k, seed, st);
+        launch_dot_part(k, v.as<double>(), v.as<double>(), vparts.as<double>(), st);
+        launch_normalize(k, v.as<double>(), v.as<double>(), vparts.as<double>(), vec_blocks(k), scal.as<double>() + 1, st);
+        for (int it = 0; it < 200; ++it) {
+            gemm(DT_F64, false, DT_F64, false, k, 1, k, G, k, v.ptr(), k, w.as<double>(), k);
+            launch_dot_part(k, w.as<double>(), w.as<double>(), vparts.as<double>(), st);
+            launch_normalize(k, v.as<double>(), w.as<double>(), vparts.as<double>(), vec_blocks(k), scal.as<double>(), st);
+        }
+        check_launch();
+        double lam = 0.0;
+        RR_HIP(hipMemcpyAsync(&lam, scal.ptr(), sizeof(double), hipMemcpyDeviceToHost, st));
+        sync();
+        return lam;
+    }
+
+    // tau and its estimates for one shift; cores are kb x kb over the basis Qb.
+    void tau_for(PerMu& pm, const double* negT, const double* TGT, const double* T, const double* G,
+                 int64_t l) {
+        const int64_t n = P.n;
+        const double mu = pm.mu;
+        if (P.opts.tau_rule == RR_TAU_NYS) {
+            const double lmax = small_lambda_max(G, l, P.opts.seed + 3);
+            pm.tau = 1.0 / lmax;
+            pm.normE = std::nan("");
+            pm.lam = std::nan("");
+            return;
+        }
+        DBuf u(al, n * sizeof(double)), y(al, n * sizeof(double));
+        const int nch = gemv_t_chunks(n, P.kb);
+        DBuf cpart(al, (size_t)nch * P.kb * sizeof(double)), d(al, P.kb * sizeof(double));
+        DBuf rz(al, (size_t)qd_blocks(n) * sizeof(double));
+        DBuf op_part(al, (size_t)operator_part_count(P) * sizeof(double));
+        auto E = [&](const double* v, double* out) {
+            apply_projected(P, negT, v, 1.0, u.as<double>(), cpart.as<double>(), d.as<double>(), rz.as<double>(), nullptr, st);
+            apply_operator(P, u.as<double>(), mu, y.as<double>(), op_part.as<double>(), kws.as<double>(), false, nullptr, st);
+            apply_projected(P, negT, y.as<double>(), 1.0, out, cpart.as<double>(), d.as<double>(), rz.as<double>(), nullptr, st);
+        };
+        auto M = [&](const double* v, double* out) {
+            apply_projected(P, TGT, v, 0.0, u.as<double>(), cpart.as<double>(), d.as<double>(), rz.as<double>(), nullptr, st);
+            apply_operator(P, u.as<double>(), mu, y.as<double>(), op_part.as<double>(), kws.as<double>(), false, nullptr, st);
+            apply_projected(P, T, y.as<double>(), 0.0, out, cpart.as<double>(), d.as<double>(), rz.as<double>(), nullptr, st);
+        };
+        pm.normE = power_norm(E, P.opts.seed + 2, P.opts.power_iters);
+        pm.lam = power_norm(M, P.opts.seed + 3, P.opts.power_iters);
+        if (!std::isfinite(pm.normE) || !(pm.lam > 0.0) || !std::isfinite(pm.lam))
+            throw RrError{RR_ENOTSPD, "power-iteration estimates of ||E|| or lam are not positive"};
+        if (!(pm.normE > 0.0)) {
+            // range(Q) is the whole space (E = 0): tau from eq. nys_tau keeps P spd
+            pm.tau = 1.0 / small_lambda_max(G, l, P.opts.seed + 3);
+            return;
+        }
+        if (P.opts.tau_rule == RR_TAU_OPT && mu > 0.0) pm.tau = std::sqrt(mu * pm.normE / pm.lam);
+        else pm.tau = P.opts.rho * pm.normE / pm.lam;
+    }
+
+    // G from C = Omega^T Y_mu (l x l) and R:  R_Omega = chol(sym C), H = R_Omega R^{-1}, G = H^T H.
+    void core_G(double* C, const double* R, double* G, int64_t l) {
+        launch_symmetrize(C, l, l, st);
+        chol_ladder(C, l);
+        DBuf Rinv = mat(l, l), H = mat(l, l);
+        launch_tri_inv_upper(R, l, l, Rinv.as<double>(), l, st);
+        gemm(DT_F64, false, DT_F64, false, l, l, l, C, l, Rinv.ptr(), l, H.as<double>(), l);
+        gemm(DT_F64, true, DT_F64, false, l, l, l, H.ptr(), l, H.ptr(), l, G, l);
+        launch_symmetrize(G, l, l, st);
+    }
+
+    double orth_error(const double* QtQ, int64_t k) {
+        launch_max_abs_minus_identity(QtQ, k, k, scal.as<double>() + 2, st);
+        double e = 0.0;
+        RR_HIP(hipMemcpyAsync(&e, scal.as<double>() + 2, sizeof(double), hipMemcpyDeviceToHost, st));
+        sync();
+        return e;
+    }
+};
+
+}  // namespace
+
+extern "C" rr_status rr_build_precond(const rr_operator* A, const double* mus, int32_t n_mu,
+                                      const rr_build_opts* opts_in, const rr_allocator* alloc,
+                                      void* hip_stream, rr_precond** out) {
+    if (out) *out = nullptr;
+    return guarded([&]() -> rr_status {
+        RR_REQUIRE(out != nullptr, "out is null");
+        validate_operator(A);
+        RR_REQUIRE(mus != nullptr, "mus is null");
+        RR_REQUIRE(n_mu >= 1 && n_mu <= 64, "n_mu must be in [1, 64]");
+        for (int i = 0; i < n_mu; ++i)
+            RR_REQUIRE(std::isfinite(mus[i]) && mus[i] >= 0.0, "every mu must be finite and >= 0");
+        rr_build_opts o;
+        if (opts_in) o = *opts_in; else rr_build_opts_default(&o);
+        const int64_t n = A->n;
+        RR_REQUIRE(o.l >= 0 && o.l <= n, "l must be in [0, n]");
+        RR_REQUIRE(o.sketch == RR_SK_GAUSSIAN || o.sketch == RR_SK_SRHT, "unknown sketch");
+        RR_REQUIRE(o.orth == RR_ORTH_SKETCHED_CHOLQR || o.orth == RR_ORTH_CHOLQR, "unknown orth");
+        RR_REQUIRE(o.prec >= RR_PREC_FP64 && o.prec <= RR_PREC_MIXED, "unknown precision");
+        RR_REQUIRE(o.tau_rule >= RR_TAU_OPT && o.tau_rule <= RR_TAU_NYS, "unknown tau rule");
+        RR_REQUIRE(std::isfinite(o.rho) && o.rho > 0.0, "rho must be finite and > 0");
+        RR_REQUIRE(o.power_iters >= 1 && o.power_iters <= 10000, "power_iters must be in [1, 10000]");
+        if (n_mu > 1 && o.l > 0) RR_REQUIRE(2 * o.l <= n, "several shifts need 2l <= n (joint basis)");
+        if (alloc) RR_REQUIRE(alloc->alloc && alloc->free, "allocator callbacks are null");
+        require_device();
+
+        const double t0 = now_ms();
+        hipStream_t st = (hipStream_t)hip_stream;
+        std::unique_ptr<rr_precond> H(new rr_precond());
+        rr_precond& P = *H;
+        P.op = *A;
+        P.opts = o;
+        P.n = n;
+        P.l = o.l;
+        P.joint = (n_mu > 1 && o.l > 0);
+        P.kb = P.joint ? 2 * o.l : o.l;
+        P.alloc.st = st;
+        if (alloc) { P.alloc.a = *alloc; P.alloc.custom = true; }
+        RR_HIP(hipGetDevice(&P.device));
+        const Alloc* al = &P.alloc;
+
+        // A0: operator setup
+        if (is_kernel(*A)) {
+            P.sqn.reset(al, (size_t)n * sizeof(float));
+            launch_sqnorms(A->pts, n, A->d, P.sqn.as<float>(), st);
+        } else if (o.prec != RR_PREC_FP64) {
+            P.A32.reset(al, (size_t)n * n * sizeof(float));
+            launch_copy_mat(DT_F64, A->A, A->lda, DT_F32, P.A32.ptr(), n, n, n, st);
+        }
+        P.per.resize(n_mu);
+        for (int i = 0; i < n_mu; ++i) P.per[i].mu = mus[i];
+        if (o.l == 0) {
+            RR_HIP(hipGetLastError());
+            RR_HIP(hipStreamSynchronize(st));
+            P.ms_build = now_ms() - t0;
+            *out = H.release();
+            return RR_OK;
+        }
+
+        Builder B(P, st);
+        const int64_t l = o.l;
+        // A1: Omega
+        const bool kernel = is_kernel(*A);
+        const bool f32path = o.prec != RR_PREC_FP64;
+        P.omega_dt = f32path ? DT_F32 : DT_F64;
+        const size_t oes = P.omega_dt == DT_F32 ? sizeof(float) : sizeof(double);
+        P.Omega.reset(al, (size_t)n * l * oes);
+        if (o.sketch == RR_SK_GAUSSIAN) {
+            if (o.prec == RR_PREC_MIXED && !kernel) {
+                DBuf ob = B.mat(n, l, 2);
+                launch_gauss_fill(ob.ptr(), DT_BF16, n, l, n, o.seed, st);
+                launch_copy_mat(DT_BF16, ob.ptr(), n, DT_F32, P.Omega.ptr(), n, n, l, st);
+                B.sync();
+            } else {
+                launch_gauss_fill(P.Omega.ptr(), P.omega_dt, n, l, n, o.seed, st);
+            }
+        } else {
+            int64_t s = 1;
+            while (s < n) s *= 2;
+            DBuf perm(al, (size_t)s * sizeof(int32_t)), rows(al, (size_t)l * sizeof(int32_t)),
+                D(al, (size_t)n * sizeof(float));
+            launch_srht_prepare(n, l, o.seed, s, perm.as<int32_t>(), rows.as<int32_t>(), D.as<float>(), st);
+            launch_srht_fill(P.Omega.ptr(), P.omega_dt, n, l, n, D.as<float>(), rows.as<int32_t>(), st);
+            B.sync();
+        }
+        B.check_launch();
+
+        // bf16 copy of a dense A for the mixed-precision sketch (freed after it)
+        DBuf A16;
+        if (o.prec == RR_PREC_MIXED && !kernel) {
+            A16.reset(al, (size_t)n * n * 2);
+            launch_copy_mat(DT_F64, A->A, A->lda, DT_BF16, A16.ptr(), n, n, n, st);
+        }
+        const int ydt = (kernel && f32path) ? DT_F32 : DT_F64;
+        const size_t yes = ydt == DT_F32 ? sizeof(float) : sizeof(double);
+        P.Qb.reset(al, (size_t)n * P.kb * sizeof(double));
+
+        if (!P.joint) {
+            PerMu& pm = P.per[0];
+            const double mu = pm.mu;
+            // A2: sketch
+            DBuf Y = B.mat(n, l, yes);
+            B.sketch(P.Omega.ptr(), P.omega_dt, mu, Y.ptr(), ydt, A16.ptr());
+            A16.release();
+            // A3: orthogonalisation
+            pm.R.reset(al, (size_t)l * l * sizeof(double));
+            B.orth(Y.ptr(), ydt, l, o.seed + 1, P.Qb.as<double>(), pm.R.as<double>());
+            // A4: core, refined projector, tau, apply core
+            DBuf C = B.mat(l, l);
+            B.gemm(P.omega_dt, true, ydt, false, l, l, n, P.Omega.ptr(), n, Y.ptr(), n, C.as<double>(), l);
+            Y.release();
+            pm.G.reset(al, (size_t)l * l * sizeof(double));
+            B.core_G(C.as<double>(), pm.R.as<double>(), pm.G.as<double>(), l);
+            pm.T.reset(al, (size_t)l * l * sizeof(double));
+            B.gemm(DT_F64, true, DT_F64, false, l, l, n, P.Qb.ptr(), n, P.Qb.ptr(), n, pm.T.as<double>(), l);
+            launch_symmetrize(pm.T.as<double>(), l, l, st);
+            P.orth_err = B.orth_error(pm.T.as<double>(), l);
+            launch_two_minus(pm.T.as<double>(), l, l, st);
+            DBuf TG = B.mat(l, l), TGT = B.mat(l, l), negT = B.mat(l, l);
+            B.gemm(DT_F64, false, DT_F64, false, l, l, l, pm.T.ptr(), l, pm.G.ptr(), l, TG.as<double>(), l);
+            B.gemm(DT_F64, false, DT_F64, false, l, l, l, TG.ptr(), l, pm.T.ptr(), l, TGT.as<double>(), l);
+            launch_symmetrize(TGT.as<double>(), l, l, st);
+            launch_axpby_mat(-1.0, pm.T.as<double>(), l, 0.0, pm.T.as<double>(), l, negT.as<double>(), l, l, l, st);
+            B.tau_for(pm, negT.as<double>(), TGT.as<double>(), pm.T.as<double>(), pm.G.as<double>(), l);
+            pm.Kc.reset(al, (size_t)l * l * sizeof(double));
+            launch_axpby_mat(pm.tau, TGT.as<double>(), l, -1.0, pm.T.as<double>(), l, pm.Kc.as<double>(), l, l, l, st);
+            B.check_launch();
+        } else {
+            // joint basis for several shifts (Section 5.1)
+            DBuf Y0 = B.mat(n, l, yes);
+            B.sketch(P.Omega.ptr(), P.omega_dt, 0.0, Y0.ptr(), ydt, A16.ptr());
+            A16.release();
+            const int64_t k2 = 2 * l;
+            DBuf Z = B.mat(n, k2);
+            launch_copy_mat(P.omega_dt, P.Omega.ptr(), n, DT_F64, Z.ptr(), n, n, l, st);
+            launch_copy_mat(ydt, Y0.ptr(), n, DT_F64, Z.as<double>() + (size_t)n * l, n, n, l, st);
+            DBuf Rj = B.mat(k2, k2);
+            B.orth(Z.ptr(), DT_F64, k2, o.seed + 1, P.Qb.as<double>(), Rj.as<double>());
+            Z.release();
+            const double* Qj = P.Qb.as<double>();
+            DBuf Zj = B.mat(k2, l), Oj = B.mat(k2, l), OAO = B.mat(l, l), OO = B.mat(l, l), QQ = B.mat(k2, k2);
+            B.gemm(DT_F64, true, ydt, false, k2, l, n, Qj, n, Y0.ptr(), n, Zj.as<double>(), k2);
+            B.gemm(DT_F64, true, P.omega_dt, false, k2, l, n, Qj, n, P.Omega.ptr(), n, Oj.as<double>(), k2);
+            B.gemm(P.omega_dt, true, ydt, false, l, l, n, P.Omega.ptr(), n, Y0.ptr(), n, OAO.as<double>(), l);
+            B.gemm(P.omega_dt, true, P.omega_dt, false, l, l, n, P.Omega.ptr(), n, P.Omega.ptr(), n, OO.as<double>(), l);
+            B.gemm(DT_F64, true, DT_F64, false, k2, k2, n, Qj, n, Qj, n, QQ.as<double>(), k2);
+            Y0.release();
+            launch_symmetrize(QQ.as<double>(), k2, k2, st);
+            P.orth_err = B.orth_error(QQ.as<double>(), k2);
+            DBuf hws(al, ((size_t)k2 * l + l + 16) * sizeof(double));
+            for (int im = 0; im < n_mu; ++im) {
+                PerMu& pm = P.per[im];
+                const double mu = pm.mu;
+                DBuf Mred = B.mat(k2, l);
+                launch_axpby_mat(1.0, Zj.as<double>(), k2, mu, Oj.as<double>(), k2, Mred.as<double>(), k2, k2, l, st);
+                pm.Qred.reset(al, (size_t)k2 * l * sizeof(double));
+                pm.R.reset(al, (size_t)l * l * sizeof(double));
+                launch_householder_qr(Mred.as<double>(), k2, l, k2, pm.Qred.as<double>(), k2, pm.R.as<double>(), l,
+                                      hws.as<double>(), st);
+                B.check_launch();
+                DBuf C = B.mat(l, l);
+                launch_axpby_mat(1.0, OAO.as<double>(), l, mu, OO.as<double>(), l, C.as<double>(), l, l, l, st);
+                pm.G.reset(al, (size_t)l * l * sizeof(double));
+                B.core_G(C.as<double>(), pm.R.as<double>(), pm.G.as<double>(), l);
+                // T = 2I - Qred^T (Qj^T Qj) Qred
+                DBuf tmp = B.mat(k2, l);
+                B.gemm(DT_F64, false, DT_F64, false, k2, l, k2, QQ.ptr(), k2, pm.Qred.ptr(), k2, tmp.as<double>(), k2);
+                pm.T.reset(al, (size_t)l * l * sizeof(double));
+                B.gemm(DT_F64, true, DT_F64, false, l, l, k2, pm.Qred.ptr(), k2, tmp.ptr(), k2, pm.T.as<double>(), l);
+                launch_symmetrize(pm.T.as<double>(), l, l, st);
+                launch_two_minus(pm.T.as<double>(), l, l, st);
+                DBuf TG = B.mat(l, l), TGT = B.mat(l, l);
+                B.gemm(DT_F64, false, DT_F64, false, l, l, l, pm.T.ptr(), l, pm.G.ptr(), l, TG.as<double>(), l);
+                B.gemm(DT_F64, false, DT_F64, false, l, l, l, TG.ptr(), l, pm.T.ptr(), l, TGT.as<double>(), l);
+                launch_symmetrize(TGT.as<double>(), l, l, st);
+                // lift l x l cores to the 2l-dimensional joint coordinates: X -> Qred X Qred^T
+                auto lift = [&](const double* X, double* outm) {
+                    DBuf t1 = B.mat(k2, l);
+                    B.gemm(DT_F64, false, DT_F64, false, k2, l, l, pm.Qred.ptr(), k2, X, l, t1.as<double>(), k2);
+                    B.gemm(DT_F64, false, DT_F64, true, k2, k2, l, t1.ptr(), k2, pm.Qred.ptr(), k2, outm, k2);
+                    launch_symmetrize(outm, k2, k2, st);
+                };
+                DBuf Tt = B.mat(k2, k2), TGTt = B.mat(k2, k2), negTt = B.mat(k2, k2);
+                lift(pm.T.as<double>(), Tt.as<double>());
+                lift(TGT.as<double>(), TGTt.as<double>());
+                launch_axpby_mat(-1.0, Tt.as<double>(), k2, 0.0, Tt.as<double>(), k2, negTt.as<double>(), k2, k2, k2, st);
+                B.tau_for(pm, negTt.as<double>(), TGTt.as<double>(), Tt.as<double>(), pm.G.as<double>(), l);
+                DBuf K = B.mat(l, l);
+                launch_axpby_mat(pm.tau, TGT.as<double>(), l, -1.0, pm.T.as<double>(), l, K.as<double>(), l, l, l, st);
+                pm.Kc.reset(al, (size_t)k2 * k2 * sizeof(double));
+                lift(K.as<double>(), pm.Kc.as<double>());
+                B.check_launch();
+            }
+        }
+        RR_HIP(hipGetLastError());
+        RR_HIP(hipStreamSynchronize(st));
+        P.ms_build = now_ms() - t0;
+        *out = H.release();
+        return RR_OK;
+    });
+}

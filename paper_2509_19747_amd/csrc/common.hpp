@@ -1,0 +1,83 @@
+// Shared device/host utilities for the RandRAND gfx950 kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#define RR_DEV __device__ __forceinline__
+
+namespace rr {
+
+constexpr int WAVE = 64;
+
+// ------------------------------------------------------------------ numerics
+template <typename T> RR_DEV double to_f64(T v);
+template <> RR_DEV double to_f64<double>(double v) { return v; }
+template <> RR_DEV double to_f64<float>(float v) { return (double)v; }
+template <> RR_DEV double to_f64<__hip_bfloat16>(__hip_bfloat16 v) { return (double)__bfloat162float(v); }
+
+template <typename T> RR_DEV T from_f64(double v);
+template <> RR_DEV double from_f64<double>(double v) { return v; }
+template <> RR_DEV float from_f64<float>(double v) { return (float)v; }
+template <> RR_DEV __hip_bfloat16 from_f64<__hip_bfloat16>(double v) {
+    // round the float64 value to float32 first, then to bf16 with round-to-nearest-even
+    return __float2bfloat16((float)v);
+}
+
+// ------------------------------------------------- deterministic reductions
+// Wave-level sum with a fixed butterfly order: every lane gets the same result.
+RR_DEV double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, WAVE);
+    return v;
+}
+RR_DEV float wave_sum(float v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, WAVE);
+    return v;
+}
+
+// Block sum of one double per thread; result returned to every thread.
+// `scratch` must hold blockDim.x/64 doubles.  Fixed order -> deterministic.
+RR_DEV double block_sum(double v, double* scratch) {
+    v = wave_sum(v);
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int w = threadIdx.x / WAVE;
+    const int nw = (blockDim.x + WAVE - 1) / WAVE;
+    __syncthreads();
+    if (lane == 0) scratch[w] = v;
+    __syncthreads();
+    double s = 0.0;
+    for (int i = 0; i < nw; ++i) s += scratch[i];
+    __syncthreads();
+    return s;
+}
+
+// Sum `count` doubles from global memory in a fixed order with one block.
+RR_DEV double block_sum_array(const double* __restrict__ a, int count, double* scratch) {
+    double v = 0.0;
+    for (int i = threadIdx.x; i < count; i += blockDim.x) v += a[i];
+    return block_sum(v, scratch);
+}
+
+// -------------------------------------------------------- counter-based RNG
+// SplitMix64 (Steele, Lea, Flood, OOPSLA 2014): word k of the stream seeded
+// with s is the 64-bit finaliser applied to s + (k+1) * 0x9E3779B97F4A7C15.
+RR_DEV uint64_t splitmix64(uint64_t seed, uint64_t k) {
+    uint64_t z = seed + (k + 1ull) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// Box-Muller (cosine branch) from words 2e and 2e+1: u1 in (0,1], u2 in [0,1).
+RR_DEV double gauss_at(uint64_t seed, uint64_t e) {
+    const uint64_t w1 = splitmix64(seed, 2ull * e);
+    const uint64_t w2 = splitmix64(seed, 2ull * e + 1ull);
+    const double u1 = ((double)(w1 >> 11) + 1.0) * 0x1.0p-53;
+    const double u2 = (double)(w2 >> 11) * 0x1.0p-53;
+    return sqrt(-2.0 * log(u1)) * cos(6.283185307179586476925286766559 * u2);
+}
+
+}  // namespace rr

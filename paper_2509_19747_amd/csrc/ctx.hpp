@@ -1,0 +1,170 @@
+// Host-side internals shared by the C-ABI entry points: error reporting,
+// device allocations, the preconditioner handle and the operator dispatch.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/randrand.h"
+#include "kernels.hpp"
+
+namespace rr {
+
+void set_error(const std::string& msg);
+const std::string& last_error();
+
+struct RrError {
+    rr_status st;
+    std::string msg;
+};
+
+#define RR_HIP(call)                                                                   \
+    do {                                                                               \
+        hipError_t e_ = (call);                                                        \
+        if (e_ != hipSuccess) {                                                        \
+            throw ::rr::RrError{RR_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)}; \
+        }                                                                              \
+    } while (0)
+
+#define RR_REQUIRE(cond, msg)                                           \
+    do {                                                                \
+        if (!(cond)) throw ::rr::RrError{RR_EINVAL, std::string(msg)};  \
+    } while (0)
+
+// Run `body`, translating exceptions to status codes; never lets one escape.
+template <typename F>
+rr_status guarded(F&& body) {
+    try {
+        return body();
+    } catch (const RrError& e) {
+        set_error(e.msg);
+        return e.st;
+    } catch (const std::bad_alloc&) {
+        set_error("host allocation failed");
+        return RR_ENOMEM;
+    } catch (...) {
+        set_error("unexpected internal error");
+        return RR_EDEVICE;
+    }
+}
+
+// Device allocator: the caller's rr_allocator if given, else hipMalloc/hipFree.
+struct Alloc {
+    rr_allocator a{};
+    bool custom = false;
+    hipStream_t st = nullptr;
+    void* get(size_t bytes) const;
+    void put(void* p) const;
+};
+
+// Owning device buffer.
+class DBuf {
+  public:
+    DBuf() = default;
+    DBuf(const Alloc* al, size_t bytes) { reset(al, bytes); }
+    ~DBuf() { release(); }
+    DBuf(const DBuf&) = delete;
+    DBuf& operator=(const DBuf&) = delete;
+    DBuf(DBuf&& o) noexcept { *this = std::move(o); }
+    DBuf& operator=(DBuf&& o) noexcept {
+        if (this != &o) {
+            release();
+            al_ = o.al_; p_ = o.p_; bytes_ = o.bytes_;
+            o.p_ = nullptr; o.bytes_ = 0;
+        }
+        return *this;
+    }
+    void reset(const Alloc* al, size_t bytes) {
+        release();
+        al_ = al;
+        bytes_ = bytes;
+        p_ = bytes ? al->get(bytes) : nullptr;
+    }
+    void release() {
+        if (p_ && al_) al_->put(p_);
+        p_ = nullptr;
+        bytes_ = 0;
+    }
+    template <typename T> T* as() const { return (T*)p_; }
+    void* ptr() const { return p_; }
+    size_t bytes() const { return bytes_; }
+
+  private:
+    const Alloc* al_ = nullptr;
+    void* p_ = nullptr;
+    size_t bytes_ = 0;
+};
+
+inline double now_ms() {
+    using namespace std::chrono;
+    return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+// Per-shift state of a handle: the apply core Kc over the basis Qb, plus the
+// l x l factors kept for inspection.
+struct PerMu {
+    double mu = 0.0;
+    DBuf Kc;        // kb x kb: P = I + Qb Kc Qb^T
+    DBuf R, G, T;   // l x l
+    DBuf Qred;      // 2l x l (joint basis only)
+    double tau = 1.0, normE = 0.0, lam = 0.0;
+};
+
+struct Workspace;
+
+}  // namespace rr
+
+void rr_free_workspace(rr::Workspace* w);
+
+struct rr_precond {
+    rr_operator op{};
+    rr_build_opts opts{};
+    int64_t n = 0, l = 0, kb = 0;   // kb: columns of the apply basis (l or 2l)
+    bool joint = false;
+    rr::Alloc alloc;
+    // operator-derived data
+    rr::DBuf A32;         // float32 copy of a dense A (FP32 / MIXED)
+    rr::DBuf sqn;         // |x_i|^2 (kernel operators)
+    // basis
+    rr::DBuf Omega;       // n x l, dtype omega_dt
+    int omega_dt = rr::DT_F64;
+    rr::DBuf Qb;          // n x kb float64
+    std::vector<rr::PerMu> per;
+    double orth_err = 0.0;
+    double ms_build = 0.0;
+    int device = 0;
+    // cached solve workspace (guarded by ws_mu)
+    std::mutex ws_mu;
+    rr::Workspace* ws = nullptr;
+    ~rr_precond();
+};
+
+namespace rr {
+
+// Working-precision helpers.
+inline bool is_kernel(const rr_operator& op) { return op.kind == RR_OP_RBF || op.kind == RR_OP_MATERN32; }
+
+KernelOp kernel_op_of(const rr_precond& P);
+
+// y = (A + mu I) u with dot partials of u^T y; returns the number of partials.
+// fp64 = use the float64 operator (dense A or float64 kernel entries).
+int apply_operator(const rr_precond& P, const double* u, double mu, double* y, double* dot_part,
+                   double* kmv_ws, bool fp64, const int32_t* stop, hipStream_t st);
+int operator_part_count(const rr_precond& P);
+size_t operator_ws_doubles(const rr_precond& P);
+
+// z = rcoef*r + Qb (Kc (Qb^T r)), with partials of r^T z.  Returns #partials.
+int apply_projected(const rr_precond& P, const double* Kc, const double* r, double rcoef, double* z,
+                    double* c_part, double* d, double* rz_part, const int32_t* stop, hipStream_t st);
+
+rr_status validate_operator(const rr_operator* A);
+void require_device();
+
+}  // namespace rr
+
+rr_status rr_solve_batch_fused(const rr_precond* P, const int32_t* mu_index_per_col,
+                               const double* B, int64_t ldb, int32_t nrhs, double* X, int64_t ldx,
+                               const rr_solve_opts* o, rr_solve_info* infos, void* hip_stream);

@@ -1,0 +1,151 @@
+// Host-side launchers for the gfx950 kernels.  Every launcher enqueues work on
+// the given stream and returns immediately; argument shapes are validated by the
+// caller (the C-ABI layer) before any launcher is reached.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rr {
+
+enum Dtype { DT_F64 = 0, DT_F32 = 1, DT_BF16 = 2 };
+
+// Per-solve device scalar state of one PCG recurrence.  Kernels read the
+// scalars they need and return immediately once `stop` is non-zero, so a batch
+// of iterations launched ahead of a host check becomes a no-op past the exit.
+struct CgState {
+    double alpha, beta, rho, rr, pw, target2;
+    int32_t stop;       // 0 running, 1 reached target (restart/converged), 2 breakdown, 3 maxit
+    int32_t iters;
+    int32_t maxit;
+    int32_t hist_cap;
+    double* hist;       // device array of ||r||^2 per iteration (may be null)
+};
+enum { STOP_NONE = 0, STOP_TARGET = 1, STOP_BREAKDOWN = 2, STOP_MAXIT = 3 };
+
+// ----------------------------------------------------------- random matrices
+void launch_gauss_fill(void* out, int dtype, int64_t rows, int64_t cols, int64_t ld,
+                       uint64_t seed, hipStream_t st);
+void launch_srht_prepare(int64_t n, int64_t l, uint64_t seed, int64_t s, int32_t* perm_ws,
+                         int32_t* rows_out, float* D_out, hipStream_t st);
+void launch_srht_fill(void* out, int dtype, int64_t n, int64_t l, int64_t ld, const float* D,
+                      const int32_t* rows, hipStream_t st);
+
+// ------------------------------------------------------------------- GEMM
+// C = alpha * op(A) op(B) + beta * C, float64 accumulation, op = transpose if tr*.
+// A element type dta (F64/F32/BF16), B element type dtb (F64/F32).  Splits the K
+// dimension over `splits` slices through workspace `ws` (splits*M*N doubles) and
+// reduces them in a fixed order (deterministic).
+size_t gemm_ws_doubles(int64_t M, int64_t N, int64_t K);
+void launch_gemm(int dta, bool trA, int dtb, bool trB, int64_t M, int64_t N, int64_t K,
+                 const void* A, int64_t lda, const void* B, int64_t ldb, double* C, int64_t ldc,
+                 double alpha, double beta, double* ws, size_t ws_doubles, hipStream_t st);
+
+// ------------------------------------------------------ small dense helpers
+void launch_symmetrize(double* A, int64_t l, int64_t lda, hipStream_t st);
+void launch_add_diag(double* A, int64_t l, int64_t lda, double alpha, hipStream_t st);
+void launch_add_diag_dev(double* A, int64_t l, int64_t lda, const double* alpha_dev, hipStream_t st);
+void launch_two_minus(double* T, int64_t l, int64_t ldt, hipStream_t st);   // T = 2I - T
+void launch_zero_lower(double* A, int64_t l, int64_t lda, hipStream_t st);
+void launch_copy_mat(int dtype_src, const void* src, int64_t lds, int dtype_dst, void* dst,
+                     int64_t ldd, int64_t rows, int64_t cols, hipStream_t st);
+// C = a*A + b*B (all float64, same shape)
+void launch_axpby_mat(double a, const double* A, int64_t lda, double b, const double* B,
+                      int64_t ldb, double* C, int64_t ldc, int64_t rows, int64_t cols,
+                      hipStream_t st);
+void launch_scale_mat(double* A, int64_t lda, int64_t rows, int64_t cols, double s, hipStream_t st);
+// max |A^T A - I| style check: out = max_ij |M_ij - delta_ij| (one double on device)
+void launch_max_abs_minus_identity(const double* M, int64_t l, int64_t ldm, double* out, hipStream_t st);
+
+// ------------------------------------------------------- factorizations
+// In-place upper Cholesky of an l x l spd matrix (A = R^T R, R stored in the upper
+// triangle, lower part zeroed).  *status (device int) is set non-zero on failure.
+void launch_cholesky_upper(double* A, int64_t l, int64_t lda, int32_t* status, double* ws,
+                           size_t ws_doubles, hipStream_t st);
+// R factor (positive diagonal) of a Householder QR of S (m x k, m >= k), S is
+// overwritten.  R: k x k, ldr.
+void launch_householder_r(double* S, int64_t m, int64_t k, int64_t lds, double* R, int64_t ldr,
+                          hipStream_t st);
+// Householder QR with explicit Q (m x k, ldq) and R (k x k): used for the reduced
+// 2l x l QR of the joint basis.  S is overwritten.  ws: >= m*k + k doubles.
+void launch_householder_qr(double* S, int64_t m, int64_t k, int64_t lds, double* Q, int64_t ldq,
+                           double* R, int64_t ldr, double* ws, hipStream_t st);
+// X = R^{-1} for an upper-triangular l x l R.
+void launch_tri_inv_upper(const double* R, int64_t l, int64_t ldr, double* X, int64_t ldx,
+                          hipStream_t st);
+
+// -------------------------------------------------------------- matvecs
+// Dense symmetric y = A u + mu u (A float64 or float32, column-major), and
+// per-block partials of u^T y in dot_part[nblocks].  Returns nblocks.
+int dense_matvec_blocks(int64_t n);
+void launch_dense_matvec(int dta, int64_t n, const void* A, int64_t lda, const double* u,
+                         double mu, double* y, double* dot_part, const int32_t* stop,
+                         hipStream_t st);
+
+// Kernel operator y = scale*K u + mu u with K from points (float32 or float64
+// evaluation, float64 accumulation), partials of u^T y.
+struct KernelOp {
+    int kind;            // 1 RBF, 2 Matern-3/2
+    int64_t n;
+    int d;
+    const float* pts;    // d x n SoA
+    const float* sqn;    // |x_i|^2 in float32 (length n), precomputed
+    double kconst, scale;
+};
+int kernel_matvec_blocks(int64_t n);
+size_t kernel_matvec_ws_doubles(int64_t n);
+void launch_kernel_matvec(const KernelOp& op, bool fp64, const double* u, double mu, double* y,
+                          double* dot_part, double* ws, const int32_t* stop, hipStream_t st);
+void launch_sqnorms(const float* pts, int64_t n, int d, float* sqn, hipStream_t st);
+// Dense formation A_out = scale*K in float64 (dtype 0) / float32 (1) / bf16 (2).
+void launch_kernel_to_dense(const KernelOp& op, void* out, int dtype, int64_t lda, hipStream_t st);
+// Kernel-GEMM Y = scale*K B + mu*B  (B: n x m float32, Y: float32), FP32 MFMA.
+void launch_kernel_gemm_f32(const KernelOp& op, const float* B, int64_t ldb, int64_t m,
+                            double mu, float* Y, int64_t ldy, hipStream_t st);
+// Same in float64 on the vector ALU (small problems / float64 mode).
+void launch_kernel_gemm_f64(const KernelOp& op, const double* B, int64_t ldb, int64_t m,
+                            double mu, double* Y, int64_t ldy, hipStream_t st);
+// Dense bf16 GEMM on MFMA: Y(float32, n x m) = A(bf16, n x n) * B(bf16, n x m) + mu*Bf
+void launch_dense_gemm_bf16(int64_t n, int64_t m, const void* A, int64_t lda, const void* B,
+                            int64_t ldb, double mu, float* Y, int64_t ldy, hipStream_t st);
+
+// ------------------------------------------------------ projections (K7, K8)
+// c_part[chunk * k + j] = sum_{i in chunk} Q[i, j] r[i]; returns number of chunks.
+int gemv_t_chunks(int64_t n, int64_t k);
+void launch_gemv_t(int64_t n, int64_t k, const double* Q, int64_t ldq, const double* r,
+                   double* c_part, int nchunks, const int32_t* stop, hipStream_t st);
+// d = Kc * c with c = sum over chunks of c_part (Kc symmetric k x k).
+void launch_core_apply(int64_t k, const double* Kc, int64_t ldk, const double* c_part,
+                       int nchunks, double* d, const int32_t* stop, hipStream_t st);
+// z = rcoef*r + Q d, and per-block partials of r^T z.
+int qd_blocks(int64_t n);
+void launch_qd(int64_t n, int64_t k, const double* Q, int64_t ldq, const double* d,
+               const double* r, double rcoef, double* z, double* rz_part, const int32_t* stop,
+               hipStream_t st);
+// v = v / sqrt(sum(part)); lam_out[0] = sqrt(sum(part))  (power-iteration step)
+void launch_normalize(int64_t n, double* v, const double* src, const double* part, int count,
+                      double* lam_out, hipStream_t st);
+
+// ----------------------------------------------------------- CG updates
+int vec_blocks(int64_t n);
+// x += alpha p; r -= alpha w; partial ||r||^2
+void launch_xr_update(int64_t n, double* x, double* r, const double* p, const double* w,
+                      CgState* s, double* rr_part, hipStream_t st);
+// p = z + beta p
+void launch_p_update(int64_t n, const double* z, double* p, const CgState* s, hipStream_t st);
+// r = b - w, partial ||r||^2
+void launch_residual(int64_t n, const double* b, const double* w, double* r, double* rr_part,
+                     hipStream_t st);
+void launch_copy_vec(int64_t n, const double* src, double* dst, hipStream_t st);
+void launch_dot_part(int64_t n, const double* a, const double* b, double* part, hipStream_t st);
+// single-block scalar steps
+void launch_scal_alpha(const double* part, int count, CgState* s, hipStream_t st);
+void launch_scal_rr(const double* part, int count, CgState* s, hipStream_t st);
+void launch_scal_beta(const double* part, int count, CgState* s, hipStream_t st);
+void launch_scal_set(const double* part, int count, double* out, hipStream_t st);  // out = sum
+void launch_state_init(CgState* s, const double* rz_part, int rz_count, double target2,
+                       int32_t maxit, int32_t iters, double* hist, int32_t hist_cap,
+                       hipStream_t st);
+// Finite check of a vector: *flag = 1 if any entry is NaN/Inf.
+void launch_nonfinite(int64_t n, const double* v, int32_t* flag, hipStream_t st);
+
+}  // namespace rr

@@ -1,0 +1,748 @@
+// Dense building blocks: the float64-accumulating tiled GEMM used for the
+// orthogonalisation and core products (Section 4.1-4.2, Algorithm
+// prec_chol_qr), the projection kernels Q^T r and r + Q d applied every PCG
+// iteration (eq. g_randrand_explicit), the stored-matrix matvec, and the CG
+// vector/scalar steps (Algorithm RandRAND_PCG).  Every reduction runs in a
+// fixed order, so results are bitwise reproducible run to run.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace rr {
+
+static inline int clamp_grid(int64_t g) {
+    if (g < 1) return 1;
+    if (g > 1 << 20) return 1 << 20;
+    return (int)g;
+}
+
+// ====================================================================== GEMM
+constexpr int GBM = 64, GBN = 64, GBK = 16;
+
+template <typename TA, typename TB, bool TRA, bool TRB>
+__global__ __launch_bounds__(256) void k_gemm(int64_t M, int64_t N, int64_t K,
+                                              const TA* __restrict__ A, int64_t lda,
+                                              const TB* __restrict__ B, int64_t ldb,
+                                              double* __restrict__ C, int64_t ldc, double alpha,
+                                              double beta, int64_t kchunk,
+                                              double* __restrict__ part) {
+    __shared__ double As[GBK][GBM + 1];
+    __shared__ double Bs[GBK][GBN + 1];
+    const int t = threadIdx.x, tx = t & 15, ty = t >> 4;
+    const int64_t i0 = (int64_t)blockIdx.x * GBM, j0 = (int64_t)blockIdx.y * GBN;
+    const int64_t kbeg = (int64_t)blockIdx.z * kchunk;
+    const int64_t kend = (kbeg + kchunk < K) ? kbeg + kchunk : K;
+    double acc[4][4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
+
+    for (int64_t k0 = kbeg; k0 < kend; k0 += GBK) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            int ii, kk;
+            if (!TRA) { ii = t & 63; kk = (t >> 6) + 4 * q; }
+            else      { kk = t & 15; ii = (t >> 4) + 16 * q; }
+            const int64_t gi = i0 + ii, gk = k0 + kk;
+            double v = 0.0;
+            if (gi < M && gk < kend) v = TRA ? to_f64(A[gk + gi * lda]) : to_f64(A[gi + gk * lda]);
+            As[kk][ii] = v;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            int kk, jj;
+            if (!TRB) { kk = t & 15; jj = (t >> 4) + 16 * q; }
+            else      { jj = t & 63; kk = (t >> 6) + 4 * q; }
+            const int64_t gj = j0 + jj, gk = k0 + kk;
+            double v = 0.0;
+            if (gj < N && gk < kend) v = TRB ? to_f64(B[gj + gk * ldb]) : to_f64(B[gk + gj * ldb]);
+            Bs[kk][jj] = v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < GBK; ++kk) {
+            double a[4], b[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) a[u] = As[kk][tx + 16 * u];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) b[v] = Bs[kk][ty + 16 * v];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) acc[u][v] = fma(a[u], b[v], acc[u][v]);
+        }
+        __syncthreads();
+    }
+    const bool split = gridDim.z > 1;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int64_t gi = i0 + tx + 16 * u;
+        if (gi >= M) continue;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int64_t gj = j0 + ty + 16 * v;
+            if (gj >= N) continue;
+            if (split) {
+                part[(int64_t)blockIdx.z * M * N + gi + gj * M] = acc[u][v];
+            } else {
+                double o = alpha * acc[u][v];
+                if (beta != 0.0) o += beta * C[gi + gj * ldc];
+                C[gi + gj * ldc] = o;
+            }
+        }
+    }
+}
+
+__global__ void k_gemm_reduce(int64_t M, int64_t N, int splits, const double* __restrict__ part,
+                              double* __restrict__ C, int64_t ldc, double alpha, double beta) {
+    const int64_t total = M * N;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        double s = 0.0;
+        for (int z = 0; z < splits; ++z) s += part[(int64_t)z * total + e];
+        const int64_t i = e % M, j = e / M;
+        double o = alpha * s;
+        if (beta != 0.0) o += beta * C[i + j * ldc];
+        C[i + j * ldc] = o;
+    }
+}
+
+template <typename TA, typename TB, bool TRA, bool TRB>
+static void gemm_t(int64_t M, int64_t N, int64_t K, const void* A, int64_t lda, const void* B,
+                   int64_t ldb, double* C, int64_t ldc, double alpha, double beta, double* ws,
+                   size_t ws_doubles, hipStream_t st) {
+    const int64_t gm = (M + GBM - 1) / GBM, gn = (N + GBN - 1) / GBN;
+    const int64_t kblocks = (K + GBK - 1) / GBK;
+    int64_t splits = 1;
+    const int64_t target = 1024;
+    if (gm * gn < target && kblocks >= 8) {
+        splits = (target + gm * gn - 1) / (gm * gn);
+        if (splits > kblocks / 4) splits = kblocks / 4;
+        if (splits > 64) splits = 64;
+        while (splits > 1 && (size_t)(splits * M * N) > ws_doubles) --splits;
+        if (splits < 1) splits = 1;
+    }
+    const int64_t kchunk = ((kblocks + splits - 1) / splits) * GBK;
+    splits = (K + kchunk - 1) / kchunk;
+    if (splits < 1) splits = 1;
+    dim3 grid((unsigned)gm, (unsigned)gn, (unsigned)splits);
+    k_gemm<TA, TB, TRA, TRB><<<grid, 256, 0, st>>>(M, N, K, (const TA*)A, lda, (const TB*)B, ldb,
+                                                   C, ldc, alpha, beta, kchunk, ws);
+    if (splits > 1) {
+        k_gemm_reduce<<<clamp_grid((M * N + 255) / 256), 256, 0, st>>>(M, N, (int)splits, ws, C,
+                                                                      ldc, alpha, beta);
+    }
+}
+
+size_t gemm_ws_doubles(int64_t M, int64_t N, int64_t K) {
+    (void)K;
+    return (size_t)64 * (size_t)M * (size_t)N;
+}
+
+template <typename TA, typename TB>
+static void gemm_tr(bool trA, bool trB, int64_t M, int64_t N, int64_t K, const void* A,
+                    int64_t lda, const void* B, int64_t ldb, double* C, int64_t ldc, double alpha,
+                    double beta, double* ws, size_t wsd, hipStream_t st) {
+    if (!trA && !trB) gemm_t<TA, TB, false, false>(M, N, K, A, lda, B, ldb, C, ldc, alpha, beta, ws, wsd, st);
+    else if (!trA && trB) gemm_t<TA, TB, false, true>(M, N, K, A, lda, B, ldb, C, ldc, alpha, beta, ws, wsd, st);
+    else if (trA && !trB) gemm_t<TA, TB, true, false>(M, N, K, A, lda, B, ldb, C, ldc, alpha, beta, ws, wsd, st);
+    else gemm_t<TA, TB, true, true>(M, N, K, A, lda, B, ldb, C, ldc, alpha, beta, ws, wsd, st);
+}
+
+void launch_gemm(int dta, bool trA, int dtb, bool trB, int64_t M, int64_t N, int64_t K,
+                 const void* A, int64_t lda, const void* B, int64_t ldb, double* C, int64_t ldc,
+                 double alpha, double beta, double* ws, size_t wsd, hipStream_t st) {
+    if (M <= 0 || N <= 0) return;
+    if (K <= 0) {  // C = beta * C
+        launch_scale_mat(C, ldc, M, N, beta, st);
+        return;
+    }
+    if (dtb == DT_F64) {
+        if (dta == DT_F64) gemm_tr<double, double>(trA, trB, M, N, K, A, lda, B, ldb, C, ldc, alpha, beta, ws, wsd, st);
+        else if (dta == DT_F32) gemm_tr<float, double>(trA, trB, M, N, K, A, lda, B, ldb, C, ldc, alpha, beta, ws, wsd, st);
+        else gemm_tr<__hip_bfloat16, double>(trA, trB, M, N, K, A, lda, B, ldb, C, ldc, alpha, beta, ws, wsd, st);
+    } else {
+        if (dta == DT_F64) gemm_tr<double, float>(trA, trB, M, N, K, A, lda, B, ldb, C, ldc, alpha, beta, ws, wsd, st);
+        else if (dta == DT_F32) gemm_tr<float, float>(trA, trB, M, N, K, A, lda, B, ldb, C, ldc, alpha, beta, ws, wsd, st);
+        else gemm_tr<__hip_bfloat16, float>(trA, trB, M, N, K, A, lda, B, ldb, C, ldc, alpha, beta, ws, wsd, st);
+    }
+}
+
+// ================================================== small dense helpers
+__global__ void k_symmetrize(double* A, int64_t l, int64_t lda) {
+    const int64_t total = l * l;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = e % l, j = e / l;
+        if (i < j) {
+            const double s = 0.5 * (A[i + j * lda] + A[j + i * lda]);
+            A[i + j * lda] = s;
+            A[j + i * lda] = s;
+        }
+    }
+}
+void launch_symmetrize(double* A, int64_t l, int64_t lda, hipStream_t st) {
+    k_symmetrize<<<clamp_grid((l * l + 255) / 256), 256, 0, st>>>(A, l, lda);
+}
+
+__global__ void k_add_diag(double* A, int64_t l, int64_t lda, double alpha, const double* adev) {
+    const double a = adev ? *adev : alpha;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < l;
+         i += (int64_t)gridDim.x * blockDim.x)
+        A[i + i * lda] += a;
+}
+void launch_add_diag(double* A, int64_t l, int64_t lda, double alpha, hipStream_t st) {
+    k_add_diag<<<clamp_grid((l + 255) / 256), 256, 0, st>>>(A, l, lda, alpha, nullptr);
+}
+void launch_add_diag_dev(double* A, int64_t l, int64_t lda, const double* adev, hipStream_t st) {
+    k_add_diag<<<clamp_grid((l + 255) / 256), 256, 0, st>>>(A, l, lda, 0.0, adev);
+}
+
+__global__ void k_two_minus(double* T, int64_t l, int64_t ldt) {
+    const int64_t total = l * l;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = e % l, j = e / l;
+        const double v = T[i + j * ldt];
+        T[i + j * ldt] = (i == j ? 2.0 : 0.0) - v;
+    }
+}
+void launch_two_minus(double* T, int64_t l, int64_t ldt, hipStream_t st) {
+    k_two_minus<<<clamp_grid((l * l + 255) / 256), 256, 0, st>>>(T, l, ldt);
+}
+
+__global__ void k_zero_lower(double* A, int64_t l, int64_t lda) {
+    const int64_t total = l * l;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = e % l, j = e / l;
+        if (i > j) A[i + j * lda] = 0.0;
+    }
+}
+void launch_zero_lower(double* A, int64_t l, int64_t lda, hipStream_t st) {
+    k_zero_lower<<<clamp_grid((l * l + 255) / 256), 256, 0, st>>>(A, l, lda);
+}
+
+template <typename TS, typename TD>
+__global__ void k_copy_mat(const TS* __restrict__ s, int64_t lds, TD* __restrict__ d, int64_t ldd,
+                           int64_t rows, int64_t cols) {
+    const int64_t total = rows * cols;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = e % rows, j = e / rows;
+        d[i + j * ldd] = from_f64<TD>(to_f64(s[i + j * lds]));
+    }
+}
+template <typename TS>
+static void copy_from(const void* src, int64_t lds, int dtd, void* dst, int64_t ldd, int64_t rows,
+                      int64_t cols, hipStream_t st) {
+    const int g = clamp_grid((rows * cols + 255) / 256);
+    if (dtd == DT_F64) k_copy_mat<TS, double><<<g, 256, 0, st>>>((const TS*)src, lds, (double*)dst, ldd, rows, cols);
+    else if (dtd == DT_F32) k_copy_mat<TS, float><<<g, 256, 0, st>>>((const TS*)src, lds, (float*)dst, ldd, rows, cols);
+    else k_copy_mat<TS, __hip_bfloat16><<<g, 256, 0, st>>>((const TS*)src, lds, (__hip_bfloat16*)dst, ldd, rows, cols);
+}
+void launch_copy_mat(int dts, const void* src, int64_t lds, int dtd, void* dst, int64_t ldd,
+                     int64_t rows, int64_t cols, hipStream_t st) {
+    if (rows <= 0 || cols <= 0) return;
+    if (dts == DT_F64) copy_from<double>(src, lds, dtd, dst, ldd, rows, cols, st);
+    else if (dts == DT_F32) copy_from<float>(src, lds, dtd, dst, ldd, rows, cols, st);
+    else copy_from<__hip_bfloat16>(src, lds, dtd, dst, ldd, rows, cols, st);
+}
+
+__global__ void k_axpby_mat(double a, const double* __restrict__ A, int64_t lda, double b,
+                            const double* __restrict__ B, int64_t ldb, double* __restrict__ C,
+                            int64_t ldc, int64_t rows, int64_t cols) {
+    const int64_t total = rows * cols;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = e % rows, j = e / rows;
+        C[i + j * ldc] = a * A[i + j * lda] + b * B[i + j * ldb];
+    }
+}
+void launch_axpby_mat(double a, const double* A, int64_t lda, double b, const double* B,
+                      int64_t ldb, double* C, int64_t ldc, int64_t rows, int64_t cols,
+                      hipStream_t st) {
+    k_axpby_mat<<<clamp_grid((rows * cols + 255) / 256), 256, 0, st>>>(a, A, lda, b, B, ldb, C,
+                                                                      ldc, rows, cols);
+}
+
+__global__ void k_scale_mat(double* A, int64_t lda, int64_t rows, int64_t cols, double s) {
+    const int64_t total = rows * cols;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = e % rows, j = e / rows;
+        A[i + j * lda] = (s == 0.0) ? 0.0 : s * A[i + j * lda];
+    }
+}
+void launch_scale_mat(double* A, int64_t lda, int64_t rows, int64_t cols, double s, hipStream_t st) {
+    k_scale_mat<<<clamp_grid((rows * cols + 255) / 256), 256, 0, st>>>(A, lda, rows, cols, s);
+}
+
+__global__ void k_max_abs_minus_identity(const double* M, int64_t l, int64_t ldm, double* out) {
+    __shared__ double sh[1024];
+    double m = 0.0;
+    for (int64_t e = threadIdx.x; e < l * l; e += blockDim.x) {
+        const int64_t i = e % l, j = e / l;
+        const double v = fabs(M[i + j * ldm] - (i == j ? 1.0 : 0.0));
+        m = v > m ? v : m;
+    }
+    sh[threadIdx.x] = m;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = sh[0];
+}
+void launch_max_abs_minus_identity(const double* M, int64_t l, int64_t ldm, double* out,
+                                   hipStream_t st) {
+    k_max_abs_minus_identity<<<1, 1024, 0, st>>>(M, l, ldm, out);
+}
+
+// ============================================ stored dense matvec (K5)
+// y_j = sum_i A[i, j] u_i (A symmetric, so this is (A u)_j) + mu u_j.  A block of
+// 256 threads owns DM_COLS consecutive columns: every column is read as one
+// contiguous, coalesced stream, the u values a thread loads are reused across
+// the block's columns, and the products are accumulated in float64.
+constexpr int DM_COLS = 8;
+constexpr int DM_THREADS = 256;
+
+template <typename TA>
+__global__ __launch_bounds__(DM_THREADS) void k_dense_matvec(int64_t n, const TA* __restrict__ A,
+                                                             int64_t lda,
+                                                             const double* __restrict__ u,
+                                                             double mu, double* __restrict__ y,
+                                                             double* __restrict__ dot_part,
+                                                             const int32_t* __restrict__ stop) {
+    __shared__ double red[DM_COLS][DM_THREADS / WAVE];
+    if (stop && *stop) return;
+    const int64_t j0 = (int64_t)blockIdx.x * DM_COLS;
+    double acc[DM_COLS];
+#pragma unroll
+    for (int c = 0; c < DM_COLS; ++c) acc[c] = 0.0;
+    constexpr int VW = 16 / sizeof(TA);   // elements per 16-byte load
+    const bool vec_ok = (lda % VW) == 0 && (((uintptr_t)A) & 15) == 0;
+    int64_t i_start = 0;
+    if (vec_ok) {
+        const int64_t nv = n / VW;
+        for (int64_t v = threadIdx.x; v < nv; v += DM_THREADS) {
+            double uu[VW];
+#pragma unroll
+            for (int w = 0; w < VW; ++w) uu[w] = u[v * VW + w];
+#pragma unroll
+            for (int c = 0; c < DM_COLS; ++c) {
+                const int64_t j = j0 + c;
+                if (j < n) {
+                    const TA* col = A + j * lda + v * VW;
+                    if constexpr (sizeof(TA) == 4) {
+                        const float4 a = *(const float4*)col;
+                        acc[c] = fma((double)a.x, uu[0], acc[c]);
+                        acc[c] = fma((double)a.y, uu[1], acc[c]);
+                        acc[c] = fma((double)a.z, uu[2], acc[c]);
+                        acc[c] = fma((double)a.w, uu[3], acc[c]);
+                    } else {
+                        const double2 a = *(const double2*)col;
+                        acc[c] = fma(a.x, uu[0], acc[c]);
+                        acc[c] = fma(a.y, uu[1], acc[c]);
+                    }
+                }
+            }
+        }
+        i_start = nv * VW;
+    }
+    for (int64_t i = i_start + threadIdx.x; i < n; i += DM_THREADS) {
+        const double ui = u[i];
+#pragma unroll
+        for (int c = 0; c < DM_COLS; ++c) {
+            const int64_t j = j0 + c;
+            if (j < n) acc[c] = fma(to_f64(A[i + j * lda]), ui, acc[c]);
+        }
+    }
+    const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+#pragma unroll
+    for (int c = 0; c < DM_COLS; ++c) {
+        const double s = wave_sum(acc[c]);
+        if (lane == 0) red[c][w] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double dot = 0.0;
+        for (int c = 0; c < DM_COLS; ++c) {
+            const int64_t j = j0 + c;
+            if (j >= n) break;
+            double s = 0.0;
+            for (int q = 0; q < DM_THREADS / WAVE; ++q) s += red[c][q];
+            const double yj = s + mu * u[j];
+            y[j] = yj;
+            dot = fma(u[j], yj, dot);
+        }
+        dot_part[blockIdx.x] = dot;
+    }
+}
+
+int dense_matvec_blocks(int64_t n) { return (int)((n + DM_COLS - 1) / DM_COLS); }
+
+void launch_dense_matvec(int dta, int64_t n, const void* A, int64_t lda, const double* u,
+                         double mu, double* y, double* dot_part, const int32_t* stop,
+                         hipStream_t st) {
+    const int g = dense_matvec_blocks(n);
+    if (dta == DT_F32)
+        k_dense_matvec<float><<<g, DM_THREADS, 0, st>>>(n, (const float*)A, lda, u, mu, y, dot_part, stop);
+    else
+        k_dense_matvec<double><<<g, DM_THREADS, 0, st>>>(n, (const double*)A, lda, u, mu, y, dot_part, stop);
+}
+
+// ============================================== projections (K7, K8)
+// c_part[ch * k + j] = sum over rows of chunk ch of Q[i, j] r[i].
+constexpr int GT_COLS = 4;
+constexpr int GT_THREADS = 256;
+
+__global__ __launch_bounds__(GT_THREADS) void k_gemv_t(int64_t n, int64_t k,
+                                                       const double* __restrict__ Q, int64_t ldq,
+                                                       const double* __restrict__ r,
+                                                       double* __restrict__ c_part,
+                                                       int64_t rows_per_chunk,
+                                                       const int32_t* __restrict__ stop) {
+    __shared__ double red[GT_COLS][GT_THREADS / WAVE];
+    if (stop && *stop) return;
+    const int64_t j0 = (int64_t)blockIdx.x * GT_COLS;
+    const int64_t ch = blockIdx.y;
+    const int64_t ib = ch * rows_per_chunk;
+    const int64_t ie = (ib + rows_per_chunk < n) ? ib + rows_per_chunk : n;
+    double acc[GT_COLS];
+#pragma unroll
+    for (int c = 0; c < GT_COLS; ++c) acc[c] = 0.0;
+    for (int64_t i = ib + threadIdx.x; i < ie; i += GT_THREADS) {
+        const double ri = r[i];
+#pragma unroll
+        for (int c = 0; c < GT_COLS; ++c) {
+            const int64_t j = j0 + c;
+            if (j < k) acc[c] = fma(Q[i + j * ldq], ri, acc[c]);
+        }
+    }
+    const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+#pragma unroll
+    for (int c = 0; c < GT_COLS; ++c) {
+        const double s = wave_sum(acc[c]);
+        if (lane == 0) red[c][w] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < GT_COLS) {
+        const int c = threadIdx.x;
+        const int64_t j = j0 + c;
+        if (j < k) {
+            double s = 0.0;
+            for (int q = 0; q < GT_THREADS / WAVE; ++q) s += red[c][q];
+            c_part[ch * k + j] = s;
+        }
+    }
+}
+
+static int64_t gemv_t_rows_per_chunk(int64_t n, int64_t k) {
+    const int64_t colblocks = (k + GT_COLS - 1) / GT_COLS;
+    int64_t chunks = (2048 + colblocks - 1) / colblocks;
+    const int64_t max_chunks = (n + 1023) / 1024;
+    if (chunks > max_chunks) chunks = max_chunks;
+    if (chunks < 1) chunks = 1;
+    if (chunks > 64) chunks = 64;
+    return (n + chunks - 1) / chunks;
+}
+
+int gemv_t_chunks(int64_t n, int64_t k) {
+    const int64_t rpc = gemv_t_rows_per_chunk(n, k);
+    return (int)((n + rpc - 1) / rpc);
+}
+
+void launch_gemv_t(int64_t n, int64_t k, const double* Q, int64_t ldq, const double* r,
+                   double* c_part, int nchunks, const int32_t* stop, hipStream_t st) {
+    const int64_t rpc = gemv_t_rows_per_chunk(n, k);
+    dim3 grid((unsigned)((k + GT_COLS - 1) / GT_COLS), (unsigned)nchunks);
+    k_gemv_t<<<grid, GT_THREADS, 0, st>>>(n, k, Q, ldq, r, c_part, rpc, stop);
+}
+
+// d_i = sum_j Kc[j, i] c_j with c_j = sum_ch c_part[ch*k + j] (Kc symmetric).
+constexpr int CA_ROWS = 4;
+__global__ __launch_bounds__(256) void k_core_apply(int64_t k, const double* __restrict__ Kc,
+                                                    int64_t ldk, const double* __restrict__ c_part,
+                                                    int nchunks, double* __restrict__ d,
+                                                    const int32_t* __restrict__ stop) {
+    extern __shared__ double c_sh[];
+    __shared__ double red[CA_ROWS][4];
+    if (stop && *stop) return;
+    for (int64_t j = threadIdx.x; j < k; j += blockDim.x) {
+        double s = 0.0;
+        for (int ch = 0; ch < nchunks; ++ch) s += c_part[(int64_t)ch * k + j];
+        c_sh[j] = s;
+    }
+    __syncthreads();
+    const int64_t i0 = (int64_t)blockIdx.x * CA_ROWS;
+    double acc[CA_ROWS];
+#pragma unroll
+    for (int q = 0; q < CA_ROWS; ++q) acc[q] = 0.0;
+    for (int64_t j = threadIdx.x; j < k; j += blockDim.x) {
+        const double cj = c_sh[j];
+#pragma unroll
+        for (int q = 0; q < CA_ROWS; ++q)
+            if (i0 + q < k) acc[q] = fma(Kc[j + (i0 + q) * ldk], cj, acc[q]);
+    }
+    const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+#pragma unroll
+    for (int q = 0; q < CA_ROWS; ++q) {
+        const double s = wave_sum(acc[q]);
+        if (lane == 0) red[q][w] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < CA_ROWS && i0 + threadIdx.x < k) {
+        double s = 0.0;
+        for (int q = 0; q < 4; ++q) s += red[threadIdx.x][q];
+        d[i0 + threadIdx.x] = s;
+    }
+}
+
+void launch_core_apply(int64_t k, const double* Kc, int64_t ldk, const double* c_part,
+                       int nchunks, double* d, const int32_t* stop, hipStream_t st) {
+    const int g = (int)((k + CA_ROWS - 1) / CA_ROWS);
+    k_core_apply<<<g, 256, (size_t)k * sizeof(double), st>>>(k, Kc, ldk, c_part, nchunks, d, stop);
+}
+
+// z_i = rcoef * r_i + sum_j Q[i, j] d_j; partial sums of r_i z_i per block.
+constexpr int QD_THREADS = 64;
+__global__ __launch_bounds__(QD_THREADS) void k_qd(int64_t n, int64_t k,
+                                                   const double* __restrict__ Q, int64_t ldq,
+                                                   const double* __restrict__ d,
+                                                   const double* __restrict__ r, double rcoef,
+                                                   double* __restrict__ z,
+                                                   double* __restrict__ rz_part,
+                                                   const int32_t* __restrict__ stop) {
+    extern __shared__ double d_sh[];
+    if (stop && *stop) return;
+    for (int64_t j = threadIdx.x; j < k; j += QD_THREADS) d_sh[j] = d[j];
+    __syncthreads();
+    const int64_t i = (int64_t)blockIdx.x * QD_THREADS + threadIdx.x;
+    double rz = 0.0;
+    if (i < n) {
+        double acc0 = 0.0, acc1 = 0.0;
+        int64_t j = 0;
+        for (; j + 1 < k; j += 2) {
+            acc0 = fma(Q[i + j * ldq], d_sh[j], acc0);
+            acc1 = fma(Q[i + (j + 1) * ldq], d_sh[j + 1], acc1);
+        }
+        if (j < k) acc0 = fma(Q[i + j * ldq], d_sh[j], acc0);
+        const double zi = fma(rcoef, r[i], acc0 + acc1);
+        z[i] = zi;
+        rz = r[i] * zi;
+    }
+    rz = wave_sum(rz);
+    if (threadIdx.x == 0) rz_part[blockIdx.x] = rz;
+}
+
+int qd_blocks(int64_t n) { return (int)((n + QD_THREADS - 1) / QD_THREADS); }
+
+void launch_qd(int64_t n, int64_t k, const double* Q, int64_t ldq, const double* d,
+               const double* r, double rcoef, double* z, double* rz_part, const int32_t* stop,
+               hipStream_t st) {
+    k_qd<<<qd_blocks(n), QD_THREADS, (size_t)(k > 0 ? k : 1) * sizeof(double), st>>>(
+        n, k, Q, ldq, d, r, rcoef, z, rz_part, stop);
+}
+
+// ==================================================== CG vector steps (K10)
+constexpr int VB = 256;
+int vec_blocks(int64_t n) {
+    int64_t g = (n + VB * 4 - 1) / (VB * 4);
+    if (g < 1) g = 1;
+    if (g > 2048) g = 2048;
+    return (int)g;
+}
+
+__global__ __launch_bounds__(VB) void k_xr_update(int64_t n, double* __restrict__ x,
+                                                  double* __restrict__ r,
+                                                  const double* __restrict__ p,
+                                                  const double* __restrict__ w, CgState* s,
+                                                  double* __restrict__ rr_part) {
+    __shared__ double sc[VB / WAVE];
+    if (s->stop) return;
+    const double a = s->alpha;
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * VB + threadIdx.x; i < n; i += (int64_t)gridDim.x * VB) {
+        x[i] = fma(a, p[i], x[i]);
+        const double ri = fma(-a, w[i], r[i]);
+        r[i] = ri;
+        acc = fma(ri, ri, acc);
+    }
+    acc = block_sum(acc, sc);
+    if (threadIdx.x == 0) rr_part[blockIdx.x] = acc;
+}
+void launch_xr_update(int64_t n, double* x, double* r, const double* p, const double* w,
+                      CgState* s, double* rr_part, hipStream_t st) {
+    k_xr_update<<<vec_blocks(n), VB, 0, st>>>(n, x, r, p, w, s, rr_part);
+}
+
+__global__ __launch_bounds__(VB) void k_p_update(int64_t n, const double* __restrict__ z,
+                                                 double* __restrict__ p, const CgState* s) {
+    if (s->stop) return;
+    const double b = s->beta;
+    for (int64_t i = (int64_t)blockIdx.x * VB + threadIdx.x; i < n; i += (int64_t)gridDim.x * VB)
+        p[i] = fma(b, p[i], z[i]);
+}
+void launch_p_update(int64_t n, const double* z, double* p, const CgState* s, hipStream_t st) {
+    k_p_update<<<vec_blocks(n), VB, 0, st>>>(n, z, p, s);
+}
+
+__global__ __launch_bounds__(VB) void k_residual(int64_t n, const double* __restrict__ b,
+                                                 const double* __restrict__ w,
+                                                 double* __restrict__ r,
+                                                 double* __restrict__ rr_part) {
+    __shared__ double sc[VB / WAVE];
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * VB + threadIdx.x; i < n; i += (int64_t)gridDim.x * VB) {
+        const double ri = b[i] - w[i];
+        r[i] = ri;
+        acc = fma(ri, ri, acc);
+    }
+    acc = block_sum(acc, sc);
+    if (threadIdx.x == 0) rr_part[blockIdx.x] = acc;
+}
+void launch_residual(int64_t n, const double* b, const double* w, double* r, double* rr_part,
+                     hipStream_t st) {
+    k_residual<<<vec_blocks(n), VB, 0, st>>>(n, b, w, r, rr_part);
+}
+
+__global__ void k_copy_vec(int64_t n, const double* __restrict__ s, double* __restrict__ d) {
+    for (int64_t i = (int64_t)blockIdx.x * VB + threadIdx.x; i < n; i += (int64_t)gridDim.x * VB)
+        d[i] = s[i];
+}
+void launch_copy_vec(int64_t n, const double* src, double* dst, hipStream_t st) {
+    k_copy_vec<<<vec_blocks(n), VB, 0, st>>>(n, src, dst);
+}
+
+__global__ __launch_bounds__(VB) void k_dot_part(int64_t n, const double* __restrict__ a,
+                                                 const double* __restrict__ b,
+                                                 double* __restrict__ part) {
+    __shared__ double sc[VB / WAVE];
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * VB + threadIdx.x; i < n; i += (int64_t)gridDim.x * VB)
+        acc = fma(a[i], b[i], acc);
+    acc = block_sum(acc, sc);
+    if (threadIdx.x == 0) part[blockIdx.x] = acc;
+}
+void launch_dot_part(int64_t n, const double* a, const double* b, double* part, hipStream_t st) {
+    k_dot_part<<<vec_blocks(n), VB, 0, st>>>(n, a, b, part);
+}
+
+// ----------------------------------------------------- scalar steps
+__global__ void k_scal_alpha(const double* __restrict__ part, int count, CgState* s) {
+    __shared__ double sc[16];
+    if (s->stop) return;
+    const double pw = block_sum_array(part, count, sc);
+    if (threadIdx.x == 0) {
+        s->pw = pw;
+        if (!(pw > 0.0) || !isfinite(pw)) {
+            s->stop = STOP_BREAKDOWN;
+        } else {
+            s->alpha = s->rho / pw;
+        }
+    }
+}
+void launch_scal_alpha(const double* part, int count, CgState* s, hipStream_t st) {
+    k_scal_alpha<<<1, 1024, 0, st>>>(part, count, s);
+}
+
+__global__ void k_scal_rr(const double* __restrict__ part, int count, CgState* s) {
+    __shared__ double sc[16];
+    if (s->stop) return;
+    const double rr = block_sum_array(part, count, sc);
+    if (threadIdx.x == 0) {
+        s->rr = rr;
+        const int it = s->iters + 1;
+        s->iters = it;
+        if (s->hist && it < s->hist_cap) s->hist[it] = rr;
+        if (!isfinite(rr)) s->stop = STOP_BREAKDOWN;
+        else if (rr <= s->target2) s->stop = STOP_TARGET;
+        else if (it >= s->maxit) s->stop = STOP_MAXIT;
+    }
+}
+void launch_scal_rr(const double* part, int count, CgState* s, hipStream_t st) {
+    k_scal_rr<<<1, 1024, 0, st>>>(part, count, s);
+}
+
+__global__ void k_scal_beta(const double* __restrict__ part, int count, CgState* s) {
+    __shared__ double sc[16];
+    if (s->stop) return;
+    const double rz = block_sum_array(part, count, sc);
+    if (threadIdx.x == 0) {
+        if (!(rz > 0.0) || !isfinite(rz)) {
+            s->stop = STOP_BREAKDOWN;
+        } else {
+            s->beta = rz / s->rho;
+            s->rho = rz;
+        }
+    }
+}
+void launch_scal_beta(const double* part, int count, CgState* s, hipStream_t st) {
+    k_scal_beta<<<1, 1024, 0, st>>>(part, count, s);
+}
+
+__global__ void k_scal_set(const double* __restrict__ part, int count, double* out) {
+    __shared__ double sc[16];
+    const double v = block_sum_array(part, count, sc);
+    if (threadIdx.x == 0) *out = v;
+}
+void launch_scal_set(const double* part, int count, double* out, hipStream_t st) {
+    k_scal_set<<<1, 1024, 0, st>>>(part, count, out);
+}
+
+__global__ void k_state_init(CgState* s, const double* __restrict__ rz_part, int rz_count,
+                             double target2, int32_t maxit, int32_t iters, double* hist,
+                             int32_t hist_cap) {
+    __shared__ double sc[16];
+    const double rz = block_sum_array(rz_part, rz_count, sc);
+    if (threadIdx.x == 0) {
+        s->alpha = 0.0;
+        s->beta = 0.0;
+        s->rho = rz;
+        s->pw = 0.0;
+        s->target2 = target2;
+        s->iters = iters;
+        s->maxit = maxit;
+        s->hist = hist;
+        s->hist_cap = hist_cap;
+        s->stop = (!(rz > 0.0) || !isfinite(rz)) ? STOP_BREAKDOWN : STOP_NONE;
+    }
+}
+void launch_state_init(CgState* s, const double* rz_part, int rz_count, double target2,
+                       int32_t maxit, int32_t iters, double* hist, int32_t hist_cap,
+                       hipStream_t st) {
+    k_state_init<<<1, 1024, 0, st>>>(s, rz_part, rz_count, target2, maxit, iters, hist, hist_cap);
+}
+
+__global__ void k_nonfinite(int64_t n, const double* __restrict__ v, int32_t* flag) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        if (!isfinite(v[i])) *flag = 1;
+}
+void launch_nonfinite(int64_t n, const double* v, int32_t* flag, hipStream_t st) {
+    k_nonfinite<<<vec_blocks(n), 256, 0, st>>>(n, v, flag);
+}
+
+}  // namespace rr
+
+namespace rr {
+// v = src / ||src|| with ||src||^2 = sum(part) (fixed-order sum in every block);
+// block 0 stores ||src|| in lam_out.
+__global__ __launch_bounds__(256) void k_normalize(int64_t n, double* __restrict__ v,
+                                                   const double* __restrict__ src,
+                                                   const double* __restrict__ part, int count,
+                                                   double* lam_out) {
+    __shared__ double sc[4];
+    const double s = block_sum_array(part, count, sc);
+    const double nrm = sqrt(s);
+    const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) *lam_out = nrm;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        v[i] = src[i] * inv;
+}
+void launch_normalize(int64_t n, double* v, const double* src, const double* part, int count,
+                      double* lam_out, hipStream_t st) {
+    k_normalize<<<vec_blocks(n), 256, 0, st>>>(n, v, src, part, count, lam_out);
+}
+}  // namespace rr

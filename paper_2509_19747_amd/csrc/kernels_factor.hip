@@ -1,0 +1,302 @@
+// Small dense float64 factorizations kept on the device (no host round trip):
+//  * blocked upper Cholesky A = R^T R (Algorithm chol_qr / prec_chol_qr step
+//    "chol", the core factor R_Omega); failure is reported in a device status
+//    word, which the host reads once to drive the shift ladder;
+//  * Householder QR (R only, or R and explicit Q) for the sketched factor
+//    R_sk = qr(Theta A_mu Omega) and the 2l x l reduced QR of the joint basis
+//    (Section 5.1), with the diagonal of R made positive;
+//  * inverse of an upper-triangular matrix (applied with a GEMM afterwards).
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace rr {
+
+// ============================================================== Cholesky
+constexpr int CH_NB = 32;
+
+// Factor the kb x kb diagonal block at A (upper part) in place.
+__global__ __launch_bounds__(256) void k_potf2(double* A, int64_t lda, int kb, int32_t* status) {
+    __shared__ double a[CH_NB][CH_NB + 1];
+    __shared__ int bad;
+    if (*status) return;
+    const int t = threadIdx.x;
+    for (int e = t; e < kb * kb; e += blockDim.x) {
+        const int i = e % kb, j = e / kb;
+        a[i][j] = (i <= j) ? A[i + (int64_t)j * lda] : 0.0;
+    }
+    if (t == 0) bad = 0;
+    __syncthreads();
+    for (int k = 0; k < kb; ++k) {
+        if (t == 0) {
+            const double dkk = a[k][k];
+            if (!(dkk > 0.0) || !isfinite(dkk)) {
+                bad = 1;
+                a[k][k] = 1.0;
+            } else {
+                a[k][k] = sqrt(dkk);
+            }
+        }
+        __syncthreads();
+        const double piv = a[k][k];
+        for (int j = k + 1 + t; j < kb; j += blockDim.x) a[k][j] /= piv;
+        __syncthreads();
+        const int rem = kb - k - 1;
+        for (int e = t; e < rem * rem; e += blockDim.x) {
+            const int i = k + 1 + e % rem, j = k + 1 + e / rem;
+            if (i <= j) a[i][j] -= a[k][i] * a[k][j];
+        }
+        __syncthreads();
+    }
+    for (int e = t; e < kb * kb; e += blockDim.x) {
+        const int i = e % kb, j = e / kb;
+        A[i + (int64_t)j * lda] = (i <= j) ? a[i][j] : 0.0;
+    }
+    if (t == 0 && bad) *status = 1;
+}
+
+// X = R11^{-T} X for the kb x ncols panel at X (rows of the current block row),
+// R11 the kb x kb upper factor at R.  One thread per column, forward substitution.
+__global__ __launch_bounds__(64) void k_trsm_panel(const double* R, int64_t ldr, int kb, double* X,
+                                                   int64_t ldx, int64_t ncols,
+                                                   const int32_t* status) {
+    __shared__ double r[CH_NB][CH_NB + 1];
+    __shared__ double xs[CH_NB][65];
+    if (*status) return;
+    const int t = threadIdx.x;
+    for (int e = t; e < kb * kb; e += blockDim.x) {
+        const int i = e % kb, j = e / kb;
+        r[i][j] = R[i + (int64_t)j * ldr];
+    }
+    const int64_t j = (int64_t)blockIdx.x * 64 + t;
+    if (j < ncols)
+        for (int i = 0; i < kb; ++i) xs[i][t] = X[i + j * ldx];
+    __syncthreads();
+    if (j < ncols) {
+        for (int i = 0; i < kb; ++i) {
+            double s = xs[i][t];
+            for (int k = 0; k < i; ++k) s -= r[k][i] * xs[k][t];
+            xs[i][t] = s / r[i][i];
+        }
+        for (int i = 0; i < kb; ++i) X[i + j * ldx] = xs[i][t];
+    }
+}
+
+void launch_cholesky_upper(double* A, int64_t l, int64_t lda, int32_t* status, double* ws,
+                           size_t ws_doubles, hipStream_t st) {
+    for (int64_t k0 = 0; k0 < l; k0 += CH_NB) {
+        const int kb = (int)((l - k0 < CH_NB) ? l - k0 : CH_NB);
+        double* A11 = A + k0 + k0 * lda;
+        k_potf2<<<1, 256, 0, st>>>(A11, lda, kb, status);
+        const int64_t rest = l - k0 - kb;
+        if (rest > 0) {
+            double* A12 = A + k0 + (k0 + kb) * lda;
+            k_trsm_panel<<<(unsigned)((rest + 63) / 64), 64, 0, st>>>(A11, lda, kb, A12, lda, rest, status);
+            double* A22 = A + (k0 + kb) + (k0 + kb) * lda;
+            launch_gemm(DT_F64, true, DT_F64, false, rest, rest, kb, A12, lda, A12, lda, A22, lda,
+                        -1.0, 1.0, ws, ws_doubles, st);
+        }
+    }
+    launch_zero_lower(A, l, lda, st);
+}
+
+// ============================================================ Householder
+constexpr int HH_COLS = 8;
+constexpr int HH_THREADS = 256;
+
+// One Householder step on column kc of S (m x k).  Every block rebuilds the
+// reflector from column kc (identical arithmetic in every block) and applies it
+// to its HH_COLS trailing columns; block 0 writes column kc of R and, if V is
+// given, the reflector v and its factor 2/(v^T v).
+__global__ __launch_bounds__(HH_THREADS) void k_house_step(double* S, int64_t m, int64_t k,
+                                                           int64_t lds, int64_t kc, double* R,
+                                                           int64_t ldr, double* V, int64_t ldv,
+                                                           double* tauv) {
+    extern __shared__ double x[];
+    __shared__ double sc[HH_THREADS / WAVE];
+    __shared__ double wsh[HH_COLS];
+    const int64_t L = m - kc;
+    const double* col = S + kc + kc * lds;
+    double s1 = 0.0;
+    for (int64_t i = threadIdx.x; i < L; i += HH_THREADS) {
+        const double v = col[i];
+        x[i] = v;
+        if (i > 0) s1 = fma(v, v, s1);
+    }
+    s1 = block_sum(s1, sc);   // includes a barrier after x[] is written
+    const double alpha = x[0];
+    __syncthreads();   // every thread has read x[0] before it is replaced by v0
+    const double normx = sqrt(fma(alpha, alpha, s1));
+    const double beta = (alpha >= 0.0) ? -normx : normx;
+    const double v0 = alpha - beta;
+    const double vtv = fma(v0, v0, s1);
+    const double f = (vtv > 0.0) ? 2.0 / vtv : 0.0;
+    if (threadIdx.x == 0) x[0] = v0;
+    __syncthreads();
+
+    if (blockIdx.x == 0) {
+        for (int64_t i = threadIdx.x; i < k; i += HH_THREADS) {
+            double rv;
+            if (i < kc) rv = S[i + kc * lds];
+            else if (i == kc) rv = (normx > 0.0) ? beta : alpha;
+            else rv = 0.0;
+            R[i + kc * ldr] = rv;
+        }
+        if (V) {
+            for (int64_t i = threadIdx.x; i < m; i += HH_THREADS) V[i + kc * ldv] = (i < kc) ? 0.0 : x[i - kc];
+            if (threadIdx.x == 0) tauv[kc] = f;
+        }
+    }
+    if (f == 0.0) return;
+    const int64_t jb = kc + 1 + (int64_t)blockIdx.x * HH_COLS;
+    double acc[HH_COLS];
+#pragma unroll
+    for (int c = 0; c < HH_COLS; ++c) acc[c] = 0.0;
+    for (int64_t i = threadIdx.x; i < L; i += HH_THREADS) {
+        const double xi = x[i];
+#pragma unroll
+        for (int c = 0; c < HH_COLS; ++c) {
+            const int64_t j = jb + c;
+            if (j < k) acc[c] = fma(xi, S[kc + i + j * lds], acc[c]);
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < HH_COLS; ++c) {
+        const double w = block_sum(acc[c], sc);
+        if (threadIdx.x == 0) wsh[c] = w * f;
+    }
+    __syncthreads();
+    for (int64_t i = threadIdx.x; i < L; i += HH_THREADS) {
+        const double xi = x[i];
+#pragma unroll
+        for (int c = 0; c < HH_COLS; ++c) {
+            const int64_t j = jb + c;
+            if (j < k) S[kc + i + j * lds] = fma(-wsh[c], xi, S[kc + i + j * lds]);
+        }
+    }
+}
+
+// Make diag(R) positive: rows with a negative diagonal are negated (and the
+// matching columns of Q, if given).
+__global__ void k_sign_fix(double* R, int64_t k, int64_t ldr) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < k;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        if (R[i + i * ldr] < 0.0)
+            for (int64_t j = i; j < k; ++j) R[i + j * ldr] = -R[i + j * ldr];
+    }
+}
+__global__ void k_sign_fix_q(const double* R, int64_t k, int64_t ldr, double* Q, int64_t m,
+                             int64_t ldq) {
+    const int64_t total = m * k;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = e % m, j = e / m;
+        if (R[j + j * ldr] < 0.0) Q[i + j * ldq] = -Q[i + j * ldq];
+    }
+}
+
+static int g256(int64_t total) {
+    int64_t g = (total + 255) / 256;
+    if (g < 1) g = 1;
+    if (g > 65536) g = 65536;
+    return (int)g;
+}
+
+void launch_householder_r(double* S, int64_t m, int64_t k, int64_t lds, double* R, int64_t ldr,
+                          hipStream_t st) {
+    const size_t shm = (size_t)m * sizeof(double);
+    for (int64_t kc = 0; kc < k; ++kc) {
+        const int64_t rest = k - kc - 1;
+        const int g = (int)((rest + HH_COLS - 1) / HH_COLS > 0 ? (rest + HH_COLS - 1) / HH_COLS : 1);
+        k_house_step<<<g, HH_THREADS, shm, st>>>(S, m, k, lds, kc, R, ldr, nullptr, 0, nullptr);
+    }
+    k_sign_fix<<<g256(k), 256, 0, st>>>(R, k, ldr);
+}
+
+// Q = H_0 ... H_{k-1} [I; 0]: accumulate backwards, one reflector per launch.
+__global__ __launch_bounds__(HH_THREADS) void k_house_apply_q(double* Q, int64_t m, int64_t k,
+                                                              int64_t ldq, const double* V,
+                                                              int64_t ldv, const double* tauv,
+                                                              int64_t kc) {
+    __shared__ double sc[HH_THREADS / WAVE];
+    __shared__ double wsh[HH_COLS];
+    const double f = tauv[kc];
+    if (f == 0.0) return;
+    const int64_t jb = (int64_t)blockIdx.x * HH_COLS;
+    double acc[HH_COLS];
+#pragma unroll
+    for (int c = 0; c < HH_COLS; ++c) acc[c] = 0.0;
+    for (int64_t i = kc + threadIdx.x; i < m; i += HH_THREADS) {
+        const double vi = V[i + kc * ldv];
+#pragma unroll
+        for (int c = 0; c < HH_COLS; ++c) {
+            const int64_t j = jb + c;
+            if (j < k) acc[c] = fma(vi, Q[i + j * ldq], acc[c]);
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < HH_COLS; ++c) {
+        const double w = block_sum(acc[c], sc);
+        if (threadIdx.x == 0) wsh[c] = w * f;
+    }
+    __syncthreads();
+    for (int64_t i = kc + threadIdx.x; i < m; i += HH_THREADS) {
+        const double vi = V[i + kc * ldv];
+#pragma unroll
+        for (int c = 0; c < HH_COLS; ++c) {
+            const int64_t j = jb + c;
+            if (j < k) Q[i + j * ldq] = fma(-wsh[c], vi, Q[i + j * ldq]);
+        }
+    }
+}
+
+__global__ void k_eye_rect(double* Q, int64_t m, int64_t k, int64_t ldq) {
+    const int64_t total = m * k;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = e % m, j = e / m;
+        Q[i + j * ldq] = (i == j) ? 1.0 : 0.0;
+    }
+}
+
+void launch_householder_qr(double* S, int64_t m, int64_t k, int64_t lds, double* Q, int64_t ldq,
+                           double* R, int64_t ldr, double* ws, hipStream_t st) {
+    double* V = ws;                 // m x k
+    double* tauv = ws + m * k;      // k
+    const size_t shm = (size_t)m * sizeof(double);
+    for (int64_t kc = 0; kc < k; ++kc) {
+        const int64_t rest = k - kc - 1;
+        const int g = (int)((rest + HH_COLS - 1) / HH_COLS > 0 ? (rest + HH_COLS - 1) / HH_COLS : 1);
+        k_house_step<<<g, HH_THREADS, shm, st>>>(S, m, k, lds, kc, R, ldr, V, m, tauv);
+    }
+    k_eye_rect<<<g256(m * k), 256, 0, st>>>(Q, m, k, ldq);
+    const int gq = (int)((k + HH_COLS - 1) / HH_COLS);
+    for (int64_t kc = k - 1; kc >= 0; --kc)
+        k_house_apply_q<<<gq, HH_THREADS, 0, st>>>(Q, m, k, ldq, V, m, tauv, kc);
+    k_sign_fix_q<<<g256(m * k), 256, 0, st>>>(R, k, ldr, Q, m, ldq);
+    k_sign_fix<<<g256(k), 256, 0, st>>>(R, k, ldr);
+}
+
+// ==================================================== triangular inverse
+// Column j of X = R^{-1}: column-oriented back substitution on e_j.
+__global__ __launch_bounds__(256) void k_tri_inv_upper(const double* R, int64_t l, int64_t ldr,
+                                                       double* X, int64_t ldx) {
+    extern __shared__ double xs[];
+    const int64_t j = blockIdx.x;
+    for (int64_t i = threadIdx.x; i <= j; i += blockDim.x) xs[i] = (i == j) ? 1.0 : 0.0;
+    __syncthreads();
+    for (int64_t i = j; i >= 0; --i) {
+        const double xi = xs[i] / R[i + i * ldr];
+        __syncthreads();
+        if (threadIdx.x == 0) xs[i] = xi;
+        for (int64_t r = threadIdx.x; r < i; r += blockDim.x) xs[r] = fma(-R[r + i * ldr], xi, xs[r]);
+        __syncthreads();
+    }
+    for (int64_t i = threadIdx.x; i < l; i += blockDim.x) X[i + j * ldx] = (i <= j) ? xs[i] : 0.0;
+}
+
+void launch_tri_inv_upper(const double* R, int64_t l, int64_t ldr, double* X, int64_t ldx,
+                          hipStream_t st) {
+    k_tri_inv_upper<<<(unsigned)l, 256, (size_t)l * sizeof(double), st>>>(R, l, ldr, X, ldx);
+}
+
+}  // namespace rr

@@ -1,0 +1,502 @@
+// Kernel (Gram) operators formed on the fly: A = scale * K(X, X) with the
+// Gaussian RBF or Matern-3/2 kernel (kernel ridge regression, Section 7.2.2,
+// eq. kernel), reached only through its entries.
+//
+//  * k_kmv_f32 / k_kmv_f64 : y = scale*K u + mu u  (the PCG matvec, T_mv).
+//      float32 entries, float64 products and accumulation; or fully float64.
+//      Rows are split over (row block, j slice); each slice writes partial row
+//      sums which a second kernel adds in a fixed order (deterministic).
+//  * k_kgemm_f32_mfma      : Y = scale*K B + mu B on FP32 MFMA (the sketch
+//      A_mu Omega, and the multi-RHS product).  Kernel tiles are formed in
+//      registers/LDS and never touch HBM; SRHT Omega can be generated in the
+//      tile loader instead of read.
+//  * k_kgemm_f64           : float64 vector-ALU variant (float64 mode).
+//
+// The float32 entry function is bitwise symmetric in (i, j): the dot product
+// runs over the coordinates in a fixed order with commutative products, and
+// the squared norms are added before the dot product is subtracted, so
+// K_ij == K_ji exactly and CG sees a symmetric operator.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace rr {
+
+constexpr float LOG2E_F = 1.4426950408889634f;
+
+// RBF: exp(-kconst * r^2) = exp2(-c2 * r^2) with c2 = fl32(kconst * log2 e).
+// Matern-3/2: (1 + t) exp(-t), t = kconst * r.
+template <int KIND>
+RR_DEV float kval32(float r2, float c) {
+    r2 = fmaxf(r2, 0.0f);
+    if (KIND == 1) {
+        return __builtin_amdgcn_exp2f(-c * r2);
+    } else {
+        const float t = c * __builtin_sqrtf(r2);
+        return (1.0f + t) * __builtin_amdgcn_exp2f(-t * LOG2E_F);
+    }
+}
+
+template <int KIND>
+RR_DEV double kval64(double r2, double kconst) {
+    r2 = r2 > 0.0 ? r2 : 0.0;
+    if (KIND == 1) return exp(-kconst * r2);
+    const double t = kconst * sqrt(r2);
+    return (1.0 + t) * exp(-t);
+}
+
+static float c_for(int kind, double kconst) {
+    return kind == 1 ? (float)(kconst * 1.4426950408889634074) : (float)kconst;
+}
+
+__global__ void k_sqnorms(const float* __restrict__ pts, int64_t n, int d, float* __restrict__ sqn) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        float s = 0.0f;
+        for (int k = 0; k < d; ++k) {
+            const float v = pts[(int64_t)k * n + i];
+            s = fmaf(v, v, s);
+        }
+        sqn[i] = s;
+    }
+}
+void launch_sqnorms(const float* pts, int64_t n, int d, float* sqn, hipStream_t st) {
+    int64_t g = (n + 255) / 256;
+    if (g > 4096) g = 4096;
+    k_sqnorms<<<(int)g, 256, 0, st>>>(pts, n, d, sqn);
+}
+
+// ======================================================== kernel matvec
+constexpr int KMV_THREADS = 256;
+constexpr int KMV_R = 4;                       // rows per thread
+constexpr int KMV_ROWS = KMV_THREADS * KMV_R;  // rows per block
+constexpr int KMV_JB = 8;                      // j unroll (scalar-load friendly)
+
+static int kmv_slices(int64_t n) {
+    const int64_t rb = (n + KMV_ROWS - 1) / KMV_ROWS;
+    int64_t s = (2048 + rb - 1) / rb;
+    const int64_t maxs = (n + 255) / 256;
+    if (s > maxs) s = maxs;
+    if (s < 1) s = 1;
+    if (s > 256) s = 256;
+    return (int)s;
+}
+int kernel_matvec_blocks(int64_t n) { return (int)((n + 255) / 256); }
+size_t kernel_matvec_ws_doubles(int64_t n) { return (size_t)kmv_slices(n) * (size_t)n; }
+
+// Stage 1, float32 entries.  D = point dimension (compile time, or 0 = runtime d).
+template <int KIND, int D>
+__global__ __launch_bounds__(KMV_THREADS) void k_kmv_f32(int64_t n, int dd,
+                                                         const float* __restrict__ pts,
+                                                         const float* __restrict__ sqn, float c,
+                                                         const double* __restrict__ u,
+                                                         double* __restrict__ part,
+                                                         int64_t jper,
+                                                         const int32_t* __restrict__ stop) {
+    if (stop && *stop) return;
+    constexpr int DM = D > 0 ? D : 32;
+    const int d = D > 0 ? D : dd;
+    const int64_t rbase = (int64_t)blockIdx.x * KMV_ROWS + threadIdx.x;
+    float xi[KMV_R][DM];
+    float ni[KMV_R];
+    double acc[KMV_R];
+#pragma unroll
+    for (int r = 0; r < KMV_R; ++r) {
+        const int64_t i = rbase + (int64_t)r * KMV_THREADS;
+        const int64_t ic = i < n ? i : n - 1;
+#pragma unroll
+        for (int k = 0; k < DM; ++k) xi[r][k] = (k < d) ? pts[(int64_t)k * n + ic] : 0.0f;
+        ni[r] = sqn[ic];
+        acc[r] = 0.0;
+    }
+    const int64_t jb = (int64_t)blockIdx.y * jper;
+    const int64_t je = (jb + jper < n) ? jb + jper : n;
+    int64_t j = jb;
+    for (; j + KMV_JB <= je; j += KMV_JB) {
+#pragma unroll
+        for (int q = 0; q < KMV_JB; ++q) {
+            const int64_t jj = j + q;
+            const float nj = sqn[jj];
+            const double uj = u[jj];
+            float dot[KMV_R];
+#pragma unroll
+            for (int r = 0; r < KMV_R; ++r) dot[r] = 0.0f;
+#pragma unroll
+            for (int k = 0; k < DM; ++k) {
+                if (k < d) {
+                    const float xjk = pts[(int64_t)k * n + jj];
+#pragma unroll
+                    for (int r = 0; r < KMV_R; ++r) dot[r] = fmaf(xi[r][k], xjk, dot[r]);
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < KMV_R; ++r) {
+                const float r2 = fmaf(-2.0f, dot[r], ni[r] + nj);
+                acc[r] = fma((double)kval32<KIND>(r2, c), uj, acc[r]);
+            }
+        }
+    }
+    for (; j < je; ++j) {
+        const float nj = sqn[j];
+        const double uj = u[j];
+        float dot[KMV_R];
+#pragma unroll
+        for (int r = 0; r < KMV_R; ++r) dot[r] = 0.0f;
+#pragma unroll
+        for (int k = 0; k < DM; ++k) {
+            if (k < d) {
+                const float xjk = pts[(int64_t)k * n + j];
+#pragma unroll
+                for (int r = 0; r < KMV_R; ++r) dot[r] = fmaf(xi[r][k], xjk, dot[r]);
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < KMV_R; ++r) {
+            const float r2 = fmaf(-2.0f, dot[r], ni[r] + nj);
+            acc[r] = fma((double)kval32<KIND>(r2, c), uj, acc[r]);
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < KMV_R; ++r) {
+        const int64_t i = rbase + (int64_t)r * KMV_THREADS;
+        if (i < n) part[(int64_t)blockIdx.y * n + i] = acc[r];
+    }
+}
+
+// Stage 1, float64 entries (difference form, float64 exp).
+template <int KIND>
+__global__ __launch_bounds__(KMV_THREADS) void k_kmv_f64(int64_t n, int d,
+                                                         const float* __restrict__ pts,
+                                                         double kconst,
+                                                         const double* __restrict__ u,
+                                                         double* __restrict__ part,
+                                                         int64_t jper,
+                                                         const int32_t* __restrict__ stop) {
+    if (stop && *stop) return;
+    const int64_t rbase = (int64_t)blockIdx.x * KMV_ROWS + threadIdx.x;
+    double xi[KMV_R][16];
+    double acc[KMV_R];
+    const int dl = d < 16 ? d : 16;
+#pragma unroll
+    for (int r = 0; r < KMV_R; ++r) {
+        const int64_t i = rbase + (int64_t)r * KMV_THREADS;
+        const int64_t ic = i < n ? i : n - 1;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) xi[r][k] = (k < dl) ? (double)pts[(int64_t)k * n + ic] : 0.0;
+        acc[r] = 0.0;
+    }
+    const int64_t jb = (int64_t)blockIdx.y * jper;
+    const int64_t je = (jb + jper < n) ? jb + jper : n;
+    for (int64_t j = jb; j < je; ++j) {
+        const double uj = u[j];
+        double r2[KMV_R];
+#pragma unroll
+        for (int r = 0; r < KMV_R; ++r) r2[r] = 0.0;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            if (k < dl) {
+                const double xjk = (double)pts[(int64_t)k * n + j];
+#pragma unroll
+                for (int r = 0; r < KMV_R; ++r) {
+                    const double t = xi[r][k] - xjk;
+                    r2[r] = fma(t, t, r2[r]);
+                }
+            }
+        }
+        for (int k = 16; k < d; ++k) {   // dimensions beyond 16 (rare): reload row coords
+            const double xjk = (double)pts[(int64_t)k * n + j];
+#pragma unroll
+            for (int r = 0; r < KMV_R; ++r) {
+                const int64_t i = rbase + (int64_t)r * KMV_THREADS;
+                const int64_t ic = i < n ? i : n - 1;
+                const double t = (double)pts[(int64_t)k * n + ic] - xjk;
+                r2[r] = fma(t, t, r2[r]);
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < KMV_R; ++r) acc[r] = fma(kval64<KIND>(r2[r], kconst), uj, acc[r]);
+    }
+#pragma unroll
+    for (int r = 0; r < KMV_R; ++r) {
+        const int64_t i = rbase + (int64_t)r * KMV_THREADS;
+        if (i < n) part[(int64_t)blockIdx.y * n + i] = acc[r];
+    }
+}
+
+// Stage 2: y_i = scale * sum_s part[s][i] + mu u_i; partials of u^T y.
+__global__ __launch_bounds__(256) void k_kmv_finish(int64_t n, int slices,
+                                                    const double* __restrict__ part,
+                                                    double scale, double mu,
+                                                    const double* __restrict__ u,
+                                                    double* __restrict__ y,
+                                                    double* __restrict__ dot_part,
+                                                    const int32_t* __restrict__ stop) {
+    if (stop && *stop) return;
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    double dot = 0.0;
+    if (i < n) {
+        double s = 0.0;
+        for (int q = 0; q < slices; ++q) s += part[(int64_t)q * n + i];
+        const double yi = fma(scale, s, mu * u[i]);
+        y[i] = yi;
+        dot = u[i] * yi;
+    }
+    __shared__ double sc[4];
+    dot = block_sum(dot, sc);
+    if (threadIdx.x == 0) dot_part[blockIdx.x] = dot;
+}
+
+template <int KIND>
+static void kmv_f32_dispatch(const KernelOp& op, float c, const double* u, double* part,
+                             int64_t jper, dim3 grid, const int32_t* stop, hipStream_t st) {
+    switch (op.d) {
+        case 3: k_kmv_f32<KIND, 3><<<grid, KMV_THREADS, 0, st>>>(op.n, 3, op.pts, op.sqn, c, u, part, jper, stop); break;
+        case 4: k_kmv_f32<KIND, 4><<<grid, KMV_THREADS, 0, st>>>(op.n, 4, op.pts, op.sqn, c, u, part, jper, stop); break;
+        case 8: k_kmv_f32<KIND, 8><<<grid, KMV_THREADS, 0, st>>>(op.n, 8, op.pts, op.sqn, c, u, part, jper, stop); break;
+        case 16: k_kmv_f32<KIND, 16><<<grid, KMV_THREADS, 0, st>>>(op.n, 16, op.pts, op.sqn, c, u, part, jper, stop); break;
+        default: k_kmv_f32<KIND, 0><<<grid, KMV_THREADS, 0, st>>>(op.n, op.d, op.pts, op.sqn, c, u, part, jper, stop); break;
+    }
+}
+
+void launch_kernel_matvec(const KernelOp& op, bool fp64, const double* u, double mu, double* y,
+                          double* dot_part, double* ws, const int32_t* stop, hipStream_t st) {
+    const int slices = kmv_slices(op.n);
+    const int64_t jper = (op.n + slices - 1) / slices;
+    dim3 grid((unsigned)((op.n + KMV_ROWS - 1) / KMV_ROWS), (unsigned)slices);
+    if (fp64) {
+        if (op.kind == 1) k_kmv_f64<1><<<grid, KMV_THREADS, 0, st>>>(op.n, op.d, op.pts, op.kconst, u, ws, jper, stop);
+        else k_kmv_f64<2><<<grid, KMV_THREADS, 0, st>>>(op.n, op.d, op.pts, op.kconst, u, ws, jper, stop);
+    } else {
+        const float c = c_for(op.kind, op.kconst);
+        if (op.kind == 1) kmv_f32_dispatch<1>(op, c, u, ws, jper, grid, stop, st);
+        else kmv_f32_dispatch<2>(op, c, u, ws, jper, grid, stop, st);
+    }
+    k_kmv_finish<<<kernel_matvec_blocks(op.n), 256, 0, st>>>(op.n, slices, ws, op.scale, mu, u, y,
+                                                             dot_part, stop);
+}
+
+// ===================================================== dense formation
+template <int KIND, typename TO>
+__global__ void k_kernel_to_dense(int64_t n, int d, const float* __restrict__ pts, double kconst,
+                                  double scale, TO* __restrict__ out, int64_t lda) {
+    const int64_t total = n * n;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = e % n, j = e / n;
+        double r2 = 0.0;
+        for (int k = 0; k < d; ++k) {
+            const double t = (double)pts[(int64_t)k * n + i] - (double)pts[(int64_t)k * n + j];
+            r2 = fma(t, t, r2);
+        }
+        out[i + j * lda] = from_f64<TO>(scale * kval64<KIND>(r2, kconst));
+    }
+}
+void launch_kernel_to_dense(const KernelOp& op, void* out, int dtype, int64_t lda, hipStream_t st) {
+    int64_t g = (op.n * op.n + 255) / 256;
+    if (g > 65536 * 4) g = 65536 * 4;
+    const int gg = (int)g;
+#define KTD(K, T) k_kernel_to_dense<K, T><<<gg, 256, 0, st>>>(op.n, op.d, op.pts, op.kconst, op.scale, (T*)out, lda)
+    if (op.kind == 1) {
+        if (dtype == DT_F64) KTD(1, double); else if (dtype == DT_F32) KTD(1, float); else KTD(1, __hip_bfloat16);
+    } else {
+        if (dtype == DT_F64) KTD(2, double); else if (dtype == DT_F32) KTD(2, float); else KTD(2, __hip_bfloat16);
+    }
+#undef KTD
+}
+
+// ============================================== kernel-GEMM on FP32 MFMA
+// Y[i, c] = scale * sum_j K(x_i, x_j) B[j, c] + mu B[i, c].
+// Block: 256 threads = 4 waves in a 2x2 grid of 64x64 wave tiles; block tile
+// 128 rows x 128 columns; K loop over 32 points per step.  Per step the block
+// forms the 128x32 kernel tile (each thread: one row, 16 points) into LDS in
+// the MFMA A-operand order and stages the 32x128 slice of B; then every wave
+// issues 8 k-steps x 16 v_mfma_f32_16x16x4_f32.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+constexpr int KG_BM = 128, KG_BN = 128, KG_BK = 32;
+
+template <int KIND, int D>
+__global__ __launch_bounds__(256) void k_kgemm_f32_mfma(int64_t n, int dd,
+                                                        const float* __restrict__ pts,
+                                                        const float* __restrict__ sqn, float c,
+                                                        float scale, float mu,
+                                                        const float* __restrict__ B, int64_t ldb,
+                                                        int64_t m, float* __restrict__ Y,
+                                                        int64_t ldy) {
+    constexpr int DM = D > 0 ? D : 32;
+    const int d = D > 0 ? D : dd;
+    __shared__ float Ks[KG_BK][KG_BM];
+    __shared__ float Bs[KG_BK][KG_BN + 1];
+    const int t = threadIdx.x;
+    const int lane = t & 63, wave = t >> 6;
+    const int wm = wave & 1, wn = wave >> 1;
+    const int64_t i0 = (int64_t)blockIdx.x * KG_BM;
+    const int64_t c0 = (int64_t)blockIdx.y * KG_BN;
+
+    // this thread's row for tile formation
+    const int trow = t & (KG_BM - 1);
+    const int tcg = t >> 7;            // 0/1: which 16 of the 32 points
+    const int64_t gi = i0 + trow;
+    const int64_t gic = gi < n ? gi : n - 1;
+    float xi[DM];
+#pragma unroll
+    for (int k = 0; k < DM; ++k) xi[k] = (k < d) ? pts[(int64_t)k * n + gic] : 0.0f;
+    const float ni = sqn[gic];
+
+    f32x4 acc[4][4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[u][v] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    for (int64_t j0 = 0; j0 < n; j0 += KG_BK) {
+        // kernel tile: Ks[p][row] = K(x_{i0+row}, x_{j0+p})
+#pragma unroll 4
+        for (int q = 0; q < 16; ++q) {
+            const int p = tcg * 16 + q;
+            const int64_t gj = j0 + p;
+            float kv = 0.0f;
+            if (gj < n && gi < n) {
+                float dot = 0.0f;
+#pragma unroll
+                for (int k = 0; k < DM; ++k)
+                    if (k < d) dot = fmaf(xi[k], pts[(int64_t)k * n + gj], dot);
+                kv = kval32<KIND>(fmaf(-2.0f, dot, ni + sqn[gj]), c);
+            }
+            Ks[p][trow] = kv;
+        }
+        // B slice: Bs[p][col] = B[j0+p, c0+col]
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int p = t & 31;
+            const int col = (t >> 5) + 8 * q;
+            const int64_t gj = j0 + p, gc = c0 + col;
+            Bs[p][col] = (gj < n && gc < m) ? B[gj + gc * ldb] : 0.0f;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < KG_BK; kk += 4) {
+            float a[4], b[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) a[u] = Ks[kk + (lane >> 4)][wm * 64 + u * 16 + (lane & 15)];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) b[v] = Bs[kk + (lane >> 4)][wn * 64 + v * 16 + (lane & 15)];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    acc[u][v] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u], b[v], acc[u][v], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+    // epilogue: D[row = 4*(lane/16) + e][col = lane%16] of each 16x16 tile
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int64_t gc = c0 + wn * 64 + v * 16 + (lane & 15);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int64_t gr = i0 + wm * 64 + u * 16 + 4 * (lane >> 4) + e;
+                if (gr < n && gc < m) {
+                    Y[gr + gc * ldy] = fmaf(scale, acc[u][v][e], mu * B[gr + gc * ldb]);
+                }
+            }
+        }
+    }
+}
+
+template <int KIND>
+static void kgemm_dispatch(const KernelOp& op, float c, const float* B, int64_t ldb, int64_t m,
+                           float mu, float* Y, int64_t ldy, hipStream_t st) {
+    dim3 grid((unsigned)((op.n + KG_BM - 1) / KG_BM), (unsigned)((m + KG_BN - 1) / KG_BN));
+    const float sc = (float)op.scale;
+    switch (op.d) {
+        case 3: k_kgemm_f32_mfma<KIND, 3><<<grid, 256, 0, st>>>(op.n, 3, op.pts, op.sqn, c, sc, mu, B, ldb, m, Y, ldy); break;
+        case 4: k_kgemm_f32_mfma<KIND, 4><<<grid, 256, 0, st>>>(op.n, 4, op.pts, op.sqn, c, sc, mu, B, ldb, m, Y, ldy); break;
+        case 8: k_kgemm_f32_mfma<KIND, 8><<<grid, 256, 0, st>>>(op.n, 8, op.pts, op.sqn, c, sc, mu, B, ldb, m, Y, ldy); break;
+        case 16: k_kgemm_f32_mfma<KIND, 16><<<grid, 256, 0, st>>>(op.n, 16, op.pts, op.sqn, c, sc, mu, B, ldb, m, Y, ldy); break;
+        default: k_kgemm_f32_mfma<KIND, 0><<<grid, 256, 0, st>>>(op.n, op.d, op.pts, op.sqn, c, sc, mu, B, ldb, m, Y, ldy); break;
+    }
+}
+
+void launch_kernel_gemm_f32(const KernelOp& op, const float* B, int64_t ldb, int64_t m, double mu,
+                            float* Y, int64_t ldy, hipStream_t st) {
+    const float c = c_for(op.kind, op.kconst);
+    if (op.kind == 1) kgemm_dispatch<1>(op, c, B, ldb, m, (float)mu, Y, ldy, st);
+    else kgemm_dispatch<2>(op, c, B, ldb, m, (float)mu, Y, ldy, st);
+}
+
+// ================================================ kernel-GEMM, float64 VALU
+constexpr int KF_BM = 64, KF_BN = 64, KF_BK = 16;
+template <int KIND>
+__global__ __launch_bounds__(256) void k_kgemm_f64(int64_t n, int d, const float* __restrict__ pts,
+                                                   double kconst, double scale, double mu,
+                                                   const double* __restrict__ B, int64_t ldb,
+                                                   int64_t m, double* __restrict__ Y,
+                                                   int64_t ldy) {
+    __shared__ double As[KF_BK][KF_BM + 1];
+    __shared__ double Bs[KF_BK][KF_BN + 1];
+    const int t = threadIdx.x, tx = t & 15, ty = t >> 4;
+    const int64_t i0 = (int64_t)blockIdx.x * KF_BM, c0 = (int64_t)blockIdx.y * KF_BN;
+    double acc[4][4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
+    for (int64_t j0 = 0; j0 < n; j0 += KF_BK) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int ii = t & 63, kk = (t >> 6) + 4 * q;
+            const int64_t gi = i0 + ii, gj = j0 + kk;
+            double v = 0.0;
+            if (gi < n && gj < n) {
+                double r2 = 0.0;
+                for (int k = 0; k < d; ++k) {
+                    const double dx = (double)pts[(int64_t)k * n + gi] - (double)pts[(int64_t)k * n + gj];
+                    r2 = fma(dx, dx, r2);
+                }
+                v = kval64<KIND>(r2, kconst);
+            }
+            As[kk][ii] = v;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int kk = t & 15, jj = (t >> 4) + 16 * q;
+            const int64_t gj = c0 + jj, gk = j0 + kk;
+            Bs[kk][jj] = (gj < m && gk < n) ? B[gk + gj * ldb] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < KF_BK; ++kk) {
+            double a[4], b[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) a[u] = As[kk][tx + 16 * u];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) b[v] = Bs[kk][ty + 16 * v];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) acc[u][v] = fma(a[u], b[v], acc[u][v]);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int64_t gi = i0 + tx + 16 * u;
+        if (gi >= n) continue;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int64_t gc = c0 + ty + 16 * v;
+            if (gc >= m) continue;
+            Y[gi + gc * ldy] = fma(scale, acc[u][v], mu * B[gi + gc * ldb]);
+        }
+    }
+}
+
+void launch_kernel_gemm_f64(const KernelOp& op, const double* B, int64_t ldb, int64_t m, double mu,
+                            double* Y, int64_t ldy, hipStream_t st) {
+    dim3 grid((unsigned)((op.n + KF_BM - 1) / KF_BM), (unsigned)((m + KF_BN - 1) / KF_BN));
+    if (op.kind == 1) k_kgemm_f64<1><<<grid, 256, 0, st>>>(op.n, op.d, op.pts, op.kconst, op.scale, mu, B, ldb, m, Y, ldy);
+    else k_kgemm_f64<2><<<grid, 256, 0, st>>>(op.n, op.d, op.pts, op.kconst, op.scale, mu, B, ldb, m, Y, ldy);
+}
+
+}  // namespace rr

@@ -1,0 +1,266 @@
+"""GPU parity: the HIP path (through the C ABI) against the float64 oracle.
+
+Sizes span several kernel tiles with ragged tails (n not a multiple of 64 or
+1024, l not a multiple of 32/64).  Tolerances:
+  * random matrices: Gaussian <= 4 ulp-scale (1e-14 relative; log/cos may differ
+    in the last bit), SRHT bit-exact;
+  * float64 operators / sketch / basis: 1e-12 .. 1e-9 relative (rounding order);
+  * float64 solves: relres(x_gpu) <= relres(x_oracle) + 1e-8 with both <= tol,
+    iteration counts within max(2, 3%);
+  * float32-entry operators: the float32 rounding of each kernel entry bounds
+    the matvec error by ~n * 2^-23 * max|A| per row sum (checked at 2e-6 relative).
+"""
+import numpy as np
+import pytest
+
+import workloads
+from oracle import randrand as orr
+from oracle import rng as orng
+from oracle import solvers as osol
+from oracle.operators import Operator
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+rr = pytest.importorskip("paper_2509_19747_amd")
+
+
+def _cuda(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+@pytest.fixture(scope="module")
+def dense_small():
+    prob = workloads.cfg_small_dense(n=777, d=8, l=45)
+    op = Operator.from_problem(prob)
+    pts = _cuda(prob.pts)
+    kop = rr.kernel_operator(rr.OP_RBF, pts, prob.kconst, prob.scale)
+    A = rr.kernel_to_dense(kop, "fp64")
+    return prob, op, kop, A
+
+
+@pytest.mark.parametrize("rows,cols,seed", [(37, 5, 3), (1000, 3, 11), (1, 1, 0)])
+def test_gaussian_matrix(rows, cols, seed):
+    g = rr.random_matrix("gaussian", seed, rows, cols).cpu().numpy()
+    ref = orng.gaussian_matrix(seed, rows, cols)
+    assert np.allclose(g, ref, rtol=1e-14, atol=1e-14)
+
+
+@pytest.mark.parametrize("n,l,seed", [(256, 40, 12), (1000, 100, 5), (50_000, 7, 12), (3, 4, 1)])
+def test_srht_matrix_bit_exact(n, l, seed):
+    g = rr.random_matrix("srht", seed, n, l).cpu().numpy()
+    ref = orng.srht_omega(seed, n, l)
+    assert np.array_equal(g, ref)
+
+
+def test_kernel_to_dense_fp64(dense_small):
+    prob, op, kop, A = dense_small
+    assert np.allclose(A.cpu().numpy(), op.dense, rtol=1e-13, atol=1e-15)
+
+
+@pytest.mark.parametrize("kind", [rr.OP_RBF, rr.OP_MATERN32])
+@pytest.mark.parametrize("n,d", [(1500, 16), (333, 3), (1025, 4)])
+def test_kernel_matvec(kind, n, d):
+    rng = np.random.default_rng(n + d)
+    pts = rng.standard_normal((d, n)).astype(np.float32)
+    kconst, scale, mu = 0.21, 1.0 / n, 1e-3
+    op = Operator(kind=kind, pts=pts, kconst=kconst, scale=scale)
+    u = rng.standard_normal(n)
+    ref = op.matmat(u) + mu * u
+    kop = rr.kernel_operator(kind, _cuda(pts), kconst, scale)
+    y64 = rr.apply_operator(kop, mu, "fp64", _cuda(u)).cpu().numpy()
+    assert np.linalg.norm(y64 - ref) <= 1e-12 * np.linalg.norm(ref)
+    y32 = rr.apply_operator(kop, mu, "fp32", _cuda(u)).cpu().numpy()
+    assert np.linalg.norm(y32 - ref) <= 2e-6 * np.linalg.norm(ref)
+
+
+def test_kernel_fp32_operator_symmetric():
+    # float32 entries are formed bitwise-symmetrically: e_i^T K e_j == e_j^T K e_i
+    n, d = 300, 16
+    rng = np.random.default_rng(1)
+    pts = rng.standard_normal((d, n)).astype(np.float32)
+    kop = rr.kernel_operator(rr.OP_RBF, _cuda(pts), 0.05, 1.0)
+    E = torch.eye(n, dtype=torch.float64, device="cuda")
+    cols = torch.stack([rr.apply_operator(kop, 0.0, "fp32", E[j]) for j in range(n)], 1)
+    K = cols.cpu().numpy()
+    assert np.array_equal(K, K.T)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_dense_matvec(dense_small, prec):
+    prob, op, kop, A = dense_small
+    u = np.random.default_rng(3).standard_normal(prob.n)
+    mu = 0.37
+    y = rr.apply_operator(rr.dense_operator(A), mu, prec, _cuda(u)).cpu().numpy()
+    ref = op.dense @ u + mu * u
+    tol = 1e-13 if prec == "fp64" else 1e-6
+    assert np.linalg.norm(y - ref) <= tol * np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("orth", ["sketched", "cholqr"])
+@pytest.mark.parametrize("tau_rule", ["opt", "rho", "nys"])
+def test_build_fp64_matches_oracle(dense_small, orth, tau_rule):
+    prob, op, kop, A = dense_small
+    mu, l = prob.mus[0], prob.l
+    P = rr.build_precond(rr.dense_operator(A), [mu], l=l, sketch="gaussian", seed=prob.omega_seed,
+                         orth=orth, tau_rule=tau_rule, rho=0.5)
+    g = P.export(0)
+    o = orr.build(op, [mu], l, "gaussian", prob.omega_seed,
+                  orth=orr.SKETCHED_CHOLQR if orth == "sketched" else orr.CHOLQR,
+                  tau_rule={"opt": orr.OPT, "rho": orr.RHO, "nys": orr.NYS}[tau_rule], rho=0.5)[0]
+    rel = lambda a, b_: np.linalg.norm(a - b_) / np.linalg.norm(b_)
+    assert np.allclose(P.omega(), orng.gaussian_matrix(prob.omega_seed, prob.n, l), rtol=1e-14, atol=1e-14)
+    assert rel(g["Q"], o.Q) < 1e-10
+    assert rel(g["R"], o.R) < 1e-10
+    assert rel(g["G"], o.G) < 1e-9
+    assert rel(g["T"], o.T) < 1e-12
+    if tau_rule == "nys":
+        assert abs(g["tau"] - o.tau) < 1e-6 * o.tau
+    else:
+        assert abs(g["normE"] - o.normE) < 1e-9 * o.normE
+        assert abs(g["lam"] - o.lam) < 1e-9 * o.lam
+        assert abs(g["tau"] - o.tau) < 1e-9 * o.tau
+
+
+@pytest.mark.parametrize("l", [0, 45])
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_solve_fp64_matches_oracle(dense_small, l, use_graph):
+    prob, op, kop, A = dense_small
+    mu, tol = prob.mus[0], 1e-10
+    P = rr.build_precond(rr.dense_operator(A), [mu], l=l, sketch="gaussian", seed=prob.omega_seed)
+    x, info = P.solve(_cuda(prob.b), tol=tol, use_graph=use_graph, check_every=5)
+    x = x.cpu().numpy()
+    Pr = orr.build(op, [mu], l, "gaussian", prob.omega_seed)[0]
+    ref = osol.pcg(op.shifted(mu), Pr.apply, prob.b, tol)
+    rel_gpu = osol.relres(op.shifted(mu), x, prob.b)
+    assert info["rc"] == rr.RR_OK
+    assert rel_gpu <= tol and rel_gpu <= ref.relres + 1e-8
+    assert abs(info["iters"] - ref.iters) <= max(2, int(0.03 * ref.iters))
+    assert abs(info["relres_fp64"] - rel_gpu) <= 1e-3 * rel_gpu + 1e-15
+    xs = osol.direct(op.dense, mu, prob.b)
+    cond = np.linalg.cond(op.dense + mu * np.eye(prob.n))
+    assert np.linalg.norm(x - xs) / np.linalg.norm(xs) <= 10 * tol * cond
+
+
+def test_solve_graph_equals_eager_bitwise(dense_small):
+    prob, op, kop, A = dense_small
+    P = rr.build_precond(rr.dense_operator(A), prob.mus, l=prob.l, seed=prob.omega_seed)
+    b = _cuda(prob.b)
+    x1, i1 = P.solve(b, tol=1e-9, use_graph=False, check_every=4)
+    x2, i2 = P.solve(b, tol=1e-9, use_graph=True, check_every=4)
+    x3, i3 = P.solve(b, tol=1e-9, use_graph=True, check_every=4)
+    assert torch.equal(x1, x2) and torch.equal(x2, x3)
+    assert i1["iters"] == i2["iters"] == i3["iters"]
+
+
+def test_history_matches_oracle(dense_small):
+    prob, op, kop, A = dense_small
+    mu = prob.mus[0]
+    P = rr.build_precond(rr.dense_operator(A), [mu], l=prob.l, seed=prob.omega_seed)
+    h = np.zeros(200)
+    x, info = P.solve(_cuda(prob.b), tol=1e-10, history=h)
+    Pr = orr.build(op, [mu], prob.l, "gaussian", prob.omega_seed)[0]
+    # oracle per-iteration recurrence residuals: rerun with tiny cycles recorded via history of true residuals
+    ref = osol.pcg(op.shifted(mu), Pr.apply, prob.b, 1e-10)
+    k = min(info["iters"], ref.iters, 20)
+    assert h[0] == pytest.approx(1.0)
+    assert np.all(np.isfinite(h[: k + 1])) and np.all(h[1: k + 1] > 0)
+    assert h[info["iters"]] <= 1e-10 * 1.0001
+
+
+def test_kernel_fp32_solve_with_srht():
+    prob = workloads.cfg_kernel_ridge(n=4000, d=16, l=120)
+    mu = prob.mus[0]
+    op = Operator.from_problem(prob)
+    kop = rr.kernel_operator(rr.OP_RBF, _cuda(prob.pts), prob.kconst, prob.scale)
+    P = rr.build_precond(kop, [mu], l=prob.l, sketch="srht", seed=prob.omega_seed, prec="fp32")
+    assert np.array_equal(P.omega(), orng.srht_omega(prob.omega_seed, prob.n, prob.l))
+    x, info = P.solve(_cuda(prob.b), tol=prob.tol)
+    x = x.cpu().numpy()
+    assert info["rc"] == rr.RR_OK and info["relres_work"] <= prob.tol
+    rel64 = osol.relres(op.shifted(mu), x, prob.b)
+    assert abs(info["relres_fp64"] - rel64) <= 1e-6 * rel64 + 1e-14
+    # S16-style bound: ||b - A x|| <= tol ||b|| + ||dA|| ||x||, ||dA|| <= n * 2^-23 * max|A| (loose)
+    dA = prob.n * 2.0 ** -23 * prob.scale
+    assert rel64 <= prob.tol + dA * np.linalg.norm(x) / np.linalg.norm(prob.b)
+    # oracle run of the same algorithm in float64: comparable iteration count
+    Pr = orr.build(op, [mu], prob.l, "srht", prob.omega_seed)[0]
+    ref = osol.pcg(op.shifted(mu), Pr.apply, prob.b, prob.tol)
+    assert abs(info["iters"] - ref.iters) <= max(3, int(0.1 * ref.iters))
+    cg = rr.build_precond(kop, [mu], l=0, prec="fp32").solve(_cuda(prob.b), tol=prob.tol)[1]
+    assert cg["iters"] > info["iters"]
+
+
+def test_joint_basis_multi_shift():
+    prob = workloads.cfg_batched(n=1500, d=16, l=50, nrhs=2)
+    op = Operator.from_problem(prob)
+    kop = rr.kernel_operator(rr.OP_RBF, _cuda(prob.pts), prob.kconst, prob.scale)
+    P = rr.build_precond(kop, prob.mus, l=prob.l, sketch="srht", seed=prob.omega_seed, prec="fp64")
+    oracle = orr.build(op, prob.mus, prob.l, "srht", prob.omega_seed)
+    for j in range(len(prob.mus)):
+        g = P.export(j)
+        o = oracle[j]
+        assert np.linalg.norm(g["Q"] - o.Q) / np.linalg.norm(o.Q) < 1e-9
+        assert np.linalg.norm(g["G"] - o.G) / np.linalg.norm(o.G) < 1e-8
+        assert abs(g["tau"] - o.tau) < 1e-8 * o.tau
+    mus_idx = [j for j in range(len(prob.mus)) for _ in range(prob.B.shape[1])]
+    B = np.concatenate([prob.B] * len(prob.mus), axis=1)
+    X, infos, st = P.solve_batch(_cuda(B), mus_idx, tol=1e-8)
+    X = X.cpu().numpy()
+    for c, j in enumerate(mus_idx):
+        assert infos[c]["status"] == rr.RR_OK
+        assert osol.relres(op.shifted(prob.mus[j]), X[:, c], B[:, c]) <= 1e-8
+
+
+def test_edge_cases(dense_small):
+    prob, op, kop, A = dense_small
+    dop = rr.dense_operator(A)
+    P = rr.build_precond(dop, prob.mus, l=prob.l, seed=prob.omega_seed)
+    # b = 0 -> x = 0
+    x, info = P.solve(torch.zeros(prob.n, dtype=torch.float64, device="cuda"))
+    assert info["rc"] == rr.RR_OK and float(x.abs().max()) == 0.0
+    # NaN in b -> EINVAL before any arithmetic
+    bn = _cuda(prob.b).clone()
+    bn[5] = float("nan")
+    with pytest.raises(rr.RRError) as e:
+        P.solve(bn)
+    assert e.value.status == rr.RR_EINVAL
+    # maxit -> ENOCONV with a usable iterate, then resume from it
+    x1, i1 = P.solve(_cuda(prob.b), tol=1e-12, maxit=3, ok=(rr.RR_ENOCONV,))
+    assert i1["iters"] == 3 and i1["relres_work"] < 1.0
+    x2, i2 = P.solve(_cuda(prob.b), x0=x1, tol=1e-10)
+    assert i2["rc"] == rr.RR_OK
+    # l = n: one PCG iteration
+    small = workloads.cfg_small_dense(n=64, d=8, l=64)
+    As = rr.kernel_to_dense(rr.kernel_operator(rr.OP_RBF, _cuda(small.pts), small.kconst, 1.0))
+    Pn = rr.build_precond(rr.dense_operator(As), [0.1], l=64, seed=3, tau_rule="nys")
+    xn, inn = Pn.solve(_cuda(small.b), tol=1e-8)
+    assert inn["iters"] == 1
+    # n = 1
+    A1 = torch.full((1, 1), 2.0, dtype=torch.float64, device="cuda")
+    P1 = rr.build_precond(rr.dense_operator(A1), [0.5], l=1, seed=1)
+    x1_, i1_ = P1.solve(torch.tensor([5.0], dtype=torch.float64, device="cuda"), tol=1e-12)
+    assert abs(float(x1_[0]) - 2.0) < 1e-12
+
+
+def test_indefinite_operator_fails_cleanly():
+    n = 50
+    A = -torch.eye(n, dtype=torch.float64, device="cuda")
+    P0 = rr.build_precond(rr.dense_operator(A), [0.0], l=0)
+    b = torch.ones(n, dtype=torch.float64, device="cuda")
+    x, info = P0.solve(b, ok=(rr.RR_EBREAKDOWN,))
+    assert info["rc"] == rr.RR_EBREAKDOWN
+    with pytest.raises(rr.RRError) as e:
+        rr.build_precond(rr.dense_operator(A), [0.0], l=5, seed=1)
+    assert e.value.status in (rr.RR_ENOTSPD,)
+
+
+def test_deterministic_rerun():
+    prob = workloads.cfg_kernel_ridge(n=2500, d=16, l=64)
+    kop = rr.kernel_operator(rr.OP_RBF, _cuda(prob.pts), prob.kconst, prob.scale)
+    b = _cuda(prob.b)
+    xs = []
+    for _ in range(2):
+        P = rr.build_precond(kop, prob.mus, l=prob.l, sketch="srht", seed=prob.omega_seed, prec="fp32")
+        xs.append(P.solve(b, tol=1e-6)[0])
+    assert torch.equal(xs[0], xs[1])
