@@ -115,7 +115,8 @@ def test_build_fp64_matches_oracle(dense_small, orth, tau_rule):
     assert rel(g["G"], o.G) < 1e-9
     assert rel(g["T"], o.T) < 1e-12
     if tau_rule == "nys":
-        assert abs(g["tau"] - o.tau) < 1e-6 * o.tau
+        # device power iteration on G versus the exact eigenvalue in the oracle
+        assert abs(g["tau"] - o.tau) < 1e-4 * o.tau
     else:
         assert abs(g["normE"] - o.normE) < 1e-9 * o.normE
         assert abs(g["lam"] - o.lam) < 1e-9 * o.lam
