@@ -286,6 +286,17 @@ rr_status rr_apply_operator(const rr_operator* A, double mu, int32_t prec, const
 rr_status rr_random_matrix(int32_t kind, uint64_t seed, int64_t rows, int64_t cols,
                            double* out, void* hip_stream);
 
+/*
+ * Kernel timing for measurement (off by default).  rr_profile_enable(1) clears the
+ * counters and makes the launchers of the hot kernels bracket every launch with
+ * HIP events on the launch stream; rr_profile_read(slot, &count, &total_ms)
+ * returns the number of timed launches and their summed device time.  Slots:
+ * 0 = float32 kernel matvec (first stage), 1 = float32 kernel-GEMM sketch,
+ * 2 = float32 dense matvec, 3 = bf16 dense sketch, 4 = projections.
+ */
+void rr_profile_enable(int32_t on);
+rr_status rr_profile_read(int32_t slot, int64_t* count, double* total_ms);
+
 void rr_precond_destroy(rr_precond* P);
 const char* rr_status_string(rr_status s);
 const char* rr_last_error(void);

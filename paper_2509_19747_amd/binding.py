@@ -125,6 +125,10 @@ def lib():
         L.rr_kernel_to_dense.argtypes = [C.POINTER(rr_operator), P, C.c_int32, C.c_int64, P]
         L.rr_apply_operator.argtypes = [C.POINTER(rr_operator), C.c_double, C.c_int32, P, P, P]
         L.rr_random_matrix.argtypes = [C.c_int32, C.c_uint64, C.c_int64, C.c_int64, P, P]
+        L.rr_profile_enable.argtypes = [C.c_int32]
+        L.rr_profile_enable.restype = None
+        L.rr_profile_read.argtypes = [C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_double)]
+        L.rr_profile_read.restype = C.c_int32
         L.rr_precond_destroy.argtypes = [P]
         L.rr_precond_destroy.restype = None
         L.rr_status_string.argtypes = [C.c_int32]
@@ -335,3 +339,17 @@ def random_matrix(kind: str, seed: int, rows: int, cols: int, stream=None):
     _check(lib().rr_random_matrix({"gaussian": 0, "srht": 1}[kind], int(seed), int(rows), int(cols),
                                   _ptr(out), _stream(stream)), "rr_random_matrix")
     return out.t()
+
+
+PROF_KERNEL_MATVEC, PROF_KERNEL_SKETCH, PROF_DENSE_MATVEC, PROF_DENSE_SKETCH, PROF_PROJECT = range(5)
+
+
+def profile_enable(on: bool = True):
+    lib().rr_profile_enable(1 if on else 0)
+
+
+def profile_read(slot: int):
+    """(launch count, total device ms) of a timed kernel slot."""
+    c, t = C.c_int64(), C.c_double()
+    _check(lib().rr_profile_read(int(slot), C.byref(c), C.byref(t)), "rr_profile_read")
+    return c.value, t.value

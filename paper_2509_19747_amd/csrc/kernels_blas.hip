@@ -6,6 +6,7 @@
 // fixed order, so results are bitwise reproducible run to run.
 #include "common.hpp"
 #include "kernels.hpp"
+#include "prof.hpp"
 
 namespace rr {
 
@@ -386,6 +387,7 @@ void launch_dense_matvec(int dta, int64_t n, const void* A, int64_t lda, const d
                          double mu, double* y, double* dot_part, const int32_t* stop,
                          hipStream_t st) {
     const int g = dense_matvec_blocks(n);
+    ProfScope prof(dta == DT_F32 ? PROF_DENSE_MATVEC : -1, st);
     if (dta == DT_F32)
         k_dense_matvec<float><<<g, DM_THREADS, 0, st>>>(n, (const float*)A, lda, u, mu, y, dot_part, stop);
     else

@@ -18,6 +18,7 @@
 // K_ij == K_ji exactly and CG sees a symmetric operator.
 #include "common.hpp"
 #include "kernels.hpp"
+#include "prof.hpp"
 
 namespace rr {
 
@@ -257,11 +258,13 @@ static void kmv_f32_dispatch(const KernelOp& op, float c, const double* u, doubl
     }
 }
 
-void launch_kernel_matvec(const KernelOp& op, bool fp64, const double* u, double mu, double* y,
-                          double* dot_part, double* ws, const int32_t* stop, hipStream_t st) {
+// Stage 1 only (the timed hot kernel): ws[s][i] = sum over slice s of K_ij u_j.
+static void kmv_stage1(const KernelOp& op, bool fp64, const double* u, double* ws,
+                       const int32_t* stop, hipStream_t st) {
     const int slices = kmv_slices(op.n);
     const int64_t jper = (op.n + slices - 1) / slices;
     dim3 grid((unsigned)((op.n + KMV_ROWS - 1) / KMV_ROWS), (unsigned)slices);
+    ProfScope prof(fp64 ? -1 : PROF_KERNEL_MATVEC, st);
     if (fp64) {
         if (op.kind == 1) k_kmv_f64<1><<<grid, KMV_THREADS, 0, st>>>(op.n, op.d, op.pts, op.kconst, u, ws, jper, stop);
         else k_kmv_f64<2><<<grid, KMV_THREADS, 0, st>>>(op.n, op.d, op.pts, op.kconst, u, ws, jper, stop);
@@ -270,6 +273,12 @@ void launch_kernel_matvec(const KernelOp& op, bool fp64, const double* u, double
         if (op.kind == 1) kmv_f32_dispatch<1>(op, c, u, ws, jper, grid, stop, st);
         else kmv_f32_dispatch<2>(op, c, u, ws, jper, grid, stop, st);
     }
+}
+
+void launch_kernel_matvec(const KernelOp& op, bool fp64, const double* u, double mu, double* y,
+                          double* dot_part, double* ws, const int32_t* stop, hipStream_t st) {
+    kmv_stage1(op, fp64, u, ws, stop, st);
+    const int slices = kmv_slices(op.n);
     k_kmv_finish<<<kernel_matvec_blocks(op.n), 256, 0, st>>>(op.n, slices, ws, op.scale, mu, u, y,
                                                              dot_part, stop);
 }
@@ -421,6 +430,7 @@ static void kgemm_dispatch(const KernelOp& op, float c, const float* B, int64_t 
 void launch_kernel_gemm_f32(const KernelOp& op, const float* B, int64_t ldb, int64_t m, double mu,
                             float* Y, int64_t ldy, hipStream_t st) {
     const float c = c_for(op.kind, op.kconst);
+    ProfScope prof(PROF_KERNEL_SKETCH, st);
     if (op.kind == 1) kgemm_dispatch<1>(op, c, B, ldb, m, (float)mu, Y, ldy, st);
     else kgemm_dispatch<2>(op, c, B, ldb, m, (float)mu, Y, ldy, st);
 }
