@@ -199,14 +199,19 @@ def _tau(rule, mu, rho, Amu, Q, T, G, seed, n, power_iters):
 
 def build(op, mus: List[float], l: int, sketch: str = "gaussian", seed: int = 0,
           orth: int = SKETCHED_CHOLQR, tau_rule: int = OPT, rho: float = 1.0,
-          power_iters: int = 10, Omega: Optional[np.ndarray] = None) -> List[Precond]:
-    """Build one C-RandRAND preconditioner per shift (Algorithm RandRAND_PCG steps 1-4)."""
+          power_iters: int = 10, Omega: Optional[np.ndarray] = None,
+          omega_bf16: bool = False) -> List[Precond]:
+    """Build one C-RandRAND preconditioner per shift (Algorithm RandRAND_PCG steps 1-4).
+
+    omega_bf16: the test matrix is drawn in bfloat16 (as the float32-precision
+    kernel path and the mixed-precision dense path do); SRHT entries are unchanged.
+    """
     n = op.n
     if l == 0:
         return [Precond(mu, None, None, None, None, None, 1.0, float("nan"), float("nan"))
                 for mu in mus]
     if Omega is None:
-        Omega = _rng.omega(sketch, seed, n, l)
+        Omega = _rng.omega(sketch, seed, n, l, bf16=omega_bf16)
     out = []
     if len(mus) == 1:
         mu = mus[0]

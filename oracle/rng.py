@@ -103,9 +103,19 @@ def srht_omega(seed: int, n: int, l: int) -> np.ndarray:
     return D[:, None] * H
 
 
-def omega(kind: str, seed: int, n: int, l: int) -> np.ndarray:
+def round_bf16(x) -> np.ndarray:
+    """Round to bfloat16 (via float32, round-to-nearest-even on the top 16 bits)."""
+    f = np.ascontiguousarray(np.asarray(x, dtype=np.float32))
+    u = f.view(np.uint32).astype(np.uint64)
+    r = (((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16).astype(np.uint32)
+    return r.view(np.float32).astype(np.float64)
+
+
+def omega(kind: str, seed: int, n: int, l: int, bf16: bool = False) -> np.ndarray:
+    """The test matrix; `bf16` draws it in bfloat16 (Gaussian entries rounded once)."""
     if kind == "gaussian":
-        return gaussian_matrix(seed, n, l)
+        g = gaussian_matrix(seed, n, l)
+        return round_bf16(g) if bf16 else g
     if kind == "srht":
         return srht_omega(seed, n, l)
     raise ValueError(kind)

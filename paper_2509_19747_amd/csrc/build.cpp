@@ -33,6 +33,8 @@ struct Builder {
     DBuf scal;     // doubles
     DBuf kws;      // kernel-matvec workspace
     DBuf vparts;   // partial sums
+    const void* Ob = nullptr;   // bf16 copy of Omega (float32-mode kernel sketch)
+    int64_t ldo = 0;
 
     Builder(rr_precond& p, hipStream_t s) : P(p), st(s), al(&p.alloc) {
         const int64_t kmax = std::max<int64_t>(2 * p.l, 1);
@@ -93,7 +95,7 @@ struct Builder {
         const int64_t n = P.n, l = P.l;
         if (is_kernel(P.op)) {
             const KernelOp k = kernel_op_of(P);
-            if (ydt == DT_F32) launch_kernel_gemm_f32(k, (const float*)Om, n, l, mu, (float*)Y, n, st);
+            if (ydt == DT_F32) launch_kernel_gemm_bf16x2(k, Ob, ldo, l, mu, (float*)Y, n, st);
             else launch_kernel_gemm_f64(k, (const double*)Om, n, l, mu, (double*)Y, n, st);
             check_launch();
             return;
@@ -310,24 +312,30 @@ extern "C" rr_status rr_build_precond(const rr_operator* A, const double* mus, i
         P.omega_dt = f32path ? DT_F32 : DT_F64;
         const size_t oes = P.omega_dt == DT_F32 ? sizeof(float) : sizeof(double);
         P.Omega.reset(al, (size_t)n * l * oes);
+        // In float32 mode for kernels and in mixed mode for dense operators Omega is
+        // drawn in bf16 (SRHT entries are exact; Gaussian entries are rounded once),
+        // so the bf16 MFMA sketch sees the test matrix exactly.
+        const bool bf16_omega = (kernel && f32path) || (!kernel && o.prec == RR_PREC_MIXED);
+        DBuf Ob;
+        const int64_t ldo = (n + 7) / 8 * 8;
+        if (bf16_omega) Ob.reset(al, (size_t)ldo * l * 2);
+        void* gen = bf16_omega ? Ob.ptr() : P.Omega.ptr();
+        const int gdt = bf16_omega ? DT_BF16 : P.omega_dt;
+        const int64_t gld = bf16_omega ? ldo : n;
         if (o.sketch == RR_SK_GAUSSIAN) {
-            if (o.prec == RR_PREC_MIXED && !kernel) {
-                DBuf ob = B.mat(n, l, 2);
-                launch_gauss_fill(ob.ptr(), DT_BF16, n, l, n, o.seed, st);
-                launch_copy_mat(DT_BF16, ob.ptr(), n, DT_F32, P.Omega.ptr(), n, n, l, st);
-                B.sync();
-            } else {
-                launch_gauss_fill(P.Omega.ptr(), P.omega_dt, n, l, n, o.seed, st);
-            }
+            launch_gauss_fill(gen, gdt, n, l, gld, o.seed, st);
         } else {
             int64_t s = 1;
             while (s < n) s *= 2;
             DBuf perm(al, (size_t)s * sizeof(int32_t)), rows(al, (size_t)l * sizeof(int32_t)),
                 D(al, (size_t)n * sizeof(float));
             launch_srht_prepare(n, l, o.seed, s, perm.as<int32_t>(), rows.as<int32_t>(), D.as<float>(), st);
-            launch_srht_fill(P.Omega.ptr(), P.omega_dt, n, l, n, D.as<float>(), rows.as<int32_t>(), st);
+            launch_srht_fill(gen, gdt, n, l, gld, D.as<float>(), rows.as<int32_t>(), st);
             B.sync();
         }
+        if (bf16_omega) launch_copy_mat(DT_BF16, Ob.ptr(), ldo, P.omega_dt, P.Omega.ptr(), n, n, l, st);
+        B.Ob = Ob.ptr();
+        B.ldo = ldo;
         B.check_launch();
 
         // bf16 copy of a dense A for the mixed-precision sketch (freed after it)

@@ -101,6 +101,10 @@ void launch_kernel_to_dense(const KernelOp& op, void* out, int dtype, int64_t ld
 // Kernel-GEMM Y = scale*K B + mu*B  (B: n x m float32, Y: float32), FP32 MFMA.
 void launch_kernel_gemm_f32(const KernelOp& op, const float* B, int64_t ldb, int64_t m,
                             double mu, float* Y, int64_t ldy, hipStream_t st);
+// Kernel-GEMM on BF16 MFMA with hi/lo-split kernel entries; B (n x m, ldb, a
+// multiple of 8) holds bf16 values (the test matrix, exact in bf16); Y float32.
+void launch_kernel_gemm_bf16x2(const KernelOp& op, const void* Bbf16, int64_t ldb, int64_t m,
+                               double mu, float* Y, int64_t ldy, hipStream_t st);
 // Same in float64 on the vector ALU (small problems / float64 mode).
 void launch_kernel_gemm_f64(const KernelOp& op, const double* B, int64_t ldb, int64_t m,
                             double mu, double* Y, int64_t ldy, hipStream_t st);

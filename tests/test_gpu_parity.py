@@ -265,3 +265,28 @@ def test_deterministic_rerun():
         P = rr.build_precond(kop, prob.mus, l=prob.l, sketch="srht", seed=prob.omega_seed, prec="fp32")
         xs.append(P.solve(b, tol=1e-6)[0])
     assert torch.equal(xs[0], xs[1])
+
+
+@pytest.mark.parametrize("n,l,sketch", [(3001, 200, "gaussian"), (1100, 600, "srht"), (700, 37, "gaussian")])
+def test_kernel_fp32_bf16_sketch_basis(n, l, sketch):
+    # float32-mode kernel build: Omega drawn in bf16, sketch on bf16 MFMA with a hi/lo
+    # split kernel tile.  The basis must span (to the split's ~2^-16 accuracy) the
+    # oracle's float64 range of A_mu Omega for the same Omega.
+    prob = workloads.cfg_kernel_ridge(n=n, d=16, l=l)
+    mu = prob.mus[0]
+    op = Operator.from_problem(prob)
+    kop = rr.kernel_operator(rr.OP_RBF, _cuda(prob.pts), prob.kconst, prob.scale)
+    P = rr.build_precond(kop, [mu], l=l, sketch=sketch, seed=prob.omega_seed, prec="fp32")
+    Om = orng.omega(sketch, prob.omega_seed, n, l, bf16=True)
+    assert np.array_equal(P.omega(), Om)
+    g = P.export(0)
+    o = orr.build(op, [mu], l, sketch, prob.omega_seed, omega_bf16=True)[0]
+    Qg, Qo = g["Q"], o.Q
+    assert np.linalg.norm(Qg.T @ Qg - np.eye(l), 2) < 1e-12
+    # the sketches differ by the split rounding; compare Y = Q R directly
+    Yg, Yo = Qg @ g["R"], Qo @ o.R
+    assert np.linalg.norm(Yg - Yo) <= 3e-5 * np.linalg.norm(Yo)
+    x, info = P.solve(_cuda(prob.b), tol=1e-6)
+    assert info["rc"] == rr.RR_OK
+    ref = osol.pcg(op.shifted(mu), o.apply, prob.b, 1e-6)
+    assert abs(info["iters"] - ref.iters) <= max(3, int(0.1 * ref.iters))

@@ -70,3 +70,11 @@ def test_srht_structure(n, l):
 def test_srht_signs_balanced():
     _, D, _ = rng.srht_descriptor(5, 100_000, 10)
     assert abs(D.mean()) < 0.02
+
+
+def test_round_bf16_matches_torch():
+    import torch
+    x = np.concatenate([rng.gaussian_vector(3, 5000) * 10.0 ** np.arange(-3, 2).repeat(1000),
+                        [0.0, 1.0, -1.0, 1.00390625, 1.005859375]])
+    ref = torch.from_numpy(x.astype(np.float32)).to(torch.bfloat16).to(torch.float64).numpy()
+    assert np.array_equal(rng.round_bf16(x), ref)
