@@ -261,6 +261,14 @@ rr_status rr_precond_export(const rr_precond* P, int32_t mu_index, double* Q_hos
 /* Write Omega (n x l, float64, host) as the handle drew it. */
 rr_status rr_precond_export_omega(const rr_precond* P, double* Omega_host);
 
+/*
+ * The sketch step alone (Algorithm RandRAND_PCG step 1, q = 0): Y_out (device,
+ * n x l float64) = A Omega + mu Omega, computed exactly as rr_build_precond does
+ * with the same options (test matrix from opts->seed, precision opts->prec).
+ */
+rr_status rr_sketch(const rr_operator* A, double mu, const rr_build_opts* opts, double* Y_out,
+                    void* hip_stream);
+
 /* Number of rows n, columns l and shifts of a handle (any pointer may be NULL). */
 rr_status rr_precond_shape(const rr_precond* P, int64_t* n, int64_t* l, int32_t* n_mu);
 

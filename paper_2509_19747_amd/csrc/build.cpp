@@ -90,6 +90,41 @@ struct Builder {
         throw RrError{RR_ENOTSPD, "Cholesky failed after the whole shift ladder"};
     }
 
+    // Omega (n x l) into P.Omega.  In float32 mode for kernels and in mixed mode for
+    // dense operators Omega is drawn in bf16 (SRHT entries are exact, Gaussian
+    // entries are rounded once) so the bf16 MFMA sketch sees the test matrix
+    // exactly; P.Omega then holds the same values in float32.
+    DBuf ob_buf;
+    void make_omega() {
+        const int64_t n = P.n, l = P.l;
+        const rr_build_opts& o = P.opts;
+        const bool kernel = is_kernel(P.op);
+        const bool f32path = o.prec != RR_PREC_FP64;
+        P.omega_dt = f32path ? DT_F32 : DT_F64;
+        const size_t oes = P.omega_dt == DT_F32 ? sizeof(float) : sizeof(double);
+        P.Omega.reset(al, (size_t)n * l * oes);
+        const bool bf16_omega = (kernel && f32path) || (!kernel && o.prec == RR_PREC_MIXED);
+        ldo = (n + 7) / 8 * 8;
+        if (bf16_omega) ob_buf.reset(al, (size_t)ldo * l * 2);
+        void* gen = bf16_omega ? ob_buf.ptr() : P.Omega.ptr();
+        const int gdt = bf16_omega ? DT_BF16 : P.omega_dt;
+        const int64_t gld = bf16_omega ? ldo : n;
+        if (o.sketch == RR_SK_GAUSSIAN) {
+            launch_gauss_fill(gen, gdt, n, l, gld, o.seed, st);
+        } else {
+            int64_t s = 1;
+            while (s < n) s *= 2;
+            DBuf perm(al, (size_t)s * sizeof(int32_t)), rows(al, (size_t)l * sizeof(int32_t)),
+                D(al, (size_t)n * sizeof(float));
+            launch_srht_prepare(n, l, o.seed, s, perm.as<int32_t>(), rows.as<int32_t>(), D.as<float>(), st);
+            launch_srht_fill(gen, gdt, n, l, gld, D.as<float>(), rows.as<int32_t>(), st);
+            sync();
+        }
+        if (bf16_omega) launch_copy_mat(DT_BF16, ob_buf.ptr(), ldo, P.omega_dt, P.Omega.ptr(), n, n, l, st);
+        Ob = ob_buf.ptr();
+        check_launch();
+    }
+
     // Y = A Omega + mu Omega (the sketch, q = 0).
     void sketch(const void* Om, int odt, double mu, void* Y, int ydt, const void* A16) {
         const int64_t n = P.n, l = P.l;
@@ -307,36 +342,9 @@ extern "C" rr_status rr_build_precond(const rr_operator* A, const double* mus, i
         Builder B(P, st);
         const int64_t l = o.l;
         // A1: Omega
+        B.make_omega();
         const bool kernel = is_kernel(*A);
         const bool f32path = o.prec != RR_PREC_FP64;
-        P.omega_dt = f32path ? DT_F32 : DT_F64;
-        const size_t oes = P.omega_dt == DT_F32 ? sizeof(float) : sizeof(double);
-        P.Omega.reset(al, (size_t)n * l * oes);
-        // In float32 mode for kernels and in mixed mode for dense operators Omega is
-        // drawn in bf16 (SRHT entries are exact; Gaussian entries are rounded once),
-        // so the bf16 MFMA sketch sees the test matrix exactly.
-        const bool bf16_omega = (kernel && f32path) || (!kernel && o.prec == RR_PREC_MIXED);
-        DBuf Ob;
-        const int64_t ldo = (n + 7) / 8 * 8;
-        if (bf16_omega) Ob.reset(al, (size_t)ldo * l * 2);
-        void* gen = bf16_omega ? Ob.ptr() : P.Omega.ptr();
-        const int gdt = bf16_omega ? DT_BF16 : P.omega_dt;
-        const int64_t gld = bf16_omega ? ldo : n;
-        if (o.sketch == RR_SK_GAUSSIAN) {
-            launch_gauss_fill(gen, gdt, n, l, gld, o.seed, st);
-        } else {
-            int64_t s = 1;
-            while (s < n) s *= 2;
-            DBuf perm(al, (size_t)s * sizeof(int32_t)), rows(al, (size_t)l * sizeof(int32_t)),
-                D(al, (size_t)n * sizeof(float));
-            launch_srht_prepare(n, l, o.seed, s, perm.as<int32_t>(), rows.as<int32_t>(), D.as<float>(), st);
-            launch_srht_fill(gen, gdt, n, l, gld, D.as<float>(), rows.as<int32_t>(), st);
-            B.sync();
-        }
-        if (bf16_omega) launch_copy_mat(DT_BF16, Ob.ptr(), ldo, P.omega_dt, P.Omega.ptr(), n, n, l, st);
-        B.Ob = Ob.ptr();
-        B.ldo = ldo;
-        B.check_launch();
 
         // bf16 copy of a dense A for the mixed-precision sketch (freed after it)
         DBuf A16;
@@ -449,6 +457,53 @@ extern "C" rr_status rr_build_precond(const rr_operator* A, const double* mus, i
         RR_HIP(hipStreamSynchronize(st));
         P.ms_build = now_ms() - t0;
         *out = H.release();
+        return RR_OK;
+    });
+}
+
+// The sketch step alone, for inspection: Y = A Omega + mu Omega exactly as
+// rr_build_precond computes it with the same options.
+extern "C" rr_status rr_sketch(const rr_operator* A, double mu, const rr_build_opts* opts,
+                               double* Y_out, void* hip_stream) {
+    return guarded([&]() -> rr_status {
+        validate_operator(A);
+        RR_REQUIRE(opts != nullptr && Y_out != nullptr, "opts or Y_out is null");
+        RR_REQUIRE(std::isfinite(mu) && mu >= 0.0, "mu must be finite and >= 0");
+        RR_REQUIRE(opts->l >= 1 && opts->l <= A->n, "l must be in [1, n]");
+        RR_REQUIRE(opts->sketch == RR_SK_GAUSSIAN || opts->sketch == RR_SK_SRHT, "unknown sketch");
+        RR_REQUIRE(opts->prec >= RR_PREC_FP64 && opts->prec <= RR_PREC_MIXED, "unknown precision");
+        require_device();
+        hipStream_t st = (hipStream_t)hip_stream;
+        rr_precond P;
+        P.op = *A;
+        P.opts = *opts;
+        P.n = A->n;
+        P.l = opts->l;
+        P.kb = P.l;
+        P.alloc.st = st;
+        RR_HIP(hipGetDevice(&P.device));
+        const int64_t n = P.n, l = P.l;
+        const bool kernel = is_kernel(*A);
+        if (kernel) {
+            P.sqn.reset(&P.alloc, (size_t)n * sizeof(float));
+            launch_sqnorms(A->pts, n, A->d, P.sqn.as<float>(), st);
+        } else if (opts->prec != RR_PREC_FP64) {
+            P.A32.reset(&P.alloc, (size_t)n * n * sizeof(float));
+            launch_copy_mat(DT_F64, A->A, A->lda, DT_F32, P.A32.ptr(), n, n, n, st);
+        }
+        Builder B(P, st);
+        B.make_omega();
+        DBuf A16;
+        if (opts->prec == RR_PREC_MIXED && !kernel) {
+            A16.reset(&P.alloc, (size_t)n * n * 2);
+            launch_copy_mat(DT_F64, A->A, A->lda, DT_BF16, A16.ptr(), n, n, n, st);
+        }
+        const int ydt = (kernel && opts->prec != RR_PREC_FP64) ? DT_F32 : DT_F64;
+        DBuf Y = B.mat(n, l, ydt == DT_F32 ? sizeof(float) : sizeof(double));
+        B.sketch(P.Omega.ptr(), P.omega_dt, mu, Y.ptr(), ydt, A16.ptr());
+        launch_copy_mat(ydt, Y.ptr(), n, DT_F64, Y_out, n, n, l, st);
+        RR_HIP(hipGetLastError());
+        RR_HIP(hipStreamSynchronize(st));
         return RR_OK;
     });
 }

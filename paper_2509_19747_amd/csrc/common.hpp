@@ -22,7 +22,10 @@ template <> RR_DEV double from_f64<double>(double v) { return v; }
 template <> RR_DEV float from_f64<float>(double v) { return (float)v; }
 template <> RR_DEV __hip_bfloat16 from_f64<__hip_bfloat16>(double v) {
     // round the float64 value to float32 first, then to bf16 with round-to-nearest-even
-    return __float2bfloat16((float)v);
+    // on the top 16 bits (finite inputs)
+    const uint32_t u = __float_as_uint((float)v);
+    const uint16_t b = (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+    return __builtin_bit_cast(__hip_bfloat16, b);
 }
 
 // ------------------------------------------------- deterministic reductions

@@ -267,6 +267,25 @@ def test_deterministic_rerun():
     assert torch.equal(xs[0], xs[1])
 
 
+@pytest.mark.parametrize("n,l,sketch,prec", [
+    (3001, 200, "gaussian", "fp32"), (1100, 600, "srht", "fp32"), (700, 37, "gaussian", "fp32"),
+    (1100, 600, "srht", "fp64"), (257, 70, "gaussian", "fp64")])
+def test_kernel_sketch_matches_oracle(n, l, sketch, prec):
+    # the sketch step alone (Y = A Omega + mu Omega) against the float64 oracle with the
+    # same test matrix; float32 mode: bf16 hi/lo split entries -> |dY| <= 2^-15 |A||Omega|
+    prob = workloads.cfg_kernel_ridge(n=n, d=16, l=l)
+    mu = prob.mus[0]
+    op = Operator.from_problem(prob)
+    kop = rr.kernel_operator(rr.OP_RBF, _cuda(prob.pts), prob.kconst, prob.scale)
+    Y = rr.sketch(kop, mu, l, sketch=sketch, seed=prob.omega_seed, prec=prec).cpu().numpy()
+    Om = orng.omega(sketch, prob.omega_seed, n, l, bf16=(prec != "fp64"))
+    Yo = op.matmat(Om) + mu * Om
+    bound = (np.abs(op.to_dense()) @ np.abs(Om)) * (2.0 ** -15 if prec != "fp64" else 1e-13)
+    err = np.abs(Y - Yo)
+    worst = np.unravel_index(np.argmax(err / (bound + 1e-300)), err.shape)
+    assert np.all(err <= bound + 1e-300), f"worst at {worst}: err {err[worst]:.3e} bound {bound[worst]:.3e}"
+
+
 @pytest.mark.parametrize("n,l,sketch", [(3001, 200, "gaussian"), (1100, 600, "srht"), (700, 37, "gaussian")])
 def test_kernel_fp32_bf16_sketch_basis(n, l, sketch):
     # float32-mode kernel build: Omega drawn in bf16, sketch on bf16 MFMA with a hi/lo
