@@ -266,8 +266,8 @@ rr_status rr_precond_export_omega(const rr_precond* P, double* Omega_host);
  * n x l float64) = A Omega + mu Omega, computed exactly as rr_build_precond does
  * with the same options (test matrix from opts->seed, precision opts->prec).
  */
-rr_status rr_sketch(const rr_operator* A, double mu, const rr_build_opts* opts, double* Y_out,
-                    void* hip_stream);
+rr_status rr_sketch_apply(const rr_operator* A, double mu, const rr_build_opts* opts,
+                          double* Y_out, void* hip_stream);
 
 /* Number of rows n, columns l and shifts of a handle (any pointer may be NULL). */
 rr_status rr_precond_shape(const rr_precond* P, int64_t* n, int64_t* l, int32_t* n_mu);

@@ -125,7 +125,8 @@ def lib():
         L.rr_kernel_to_dense.argtypes = [C.POINTER(rr_operator), P, C.c_int32, C.c_int64, P]
         L.rr_apply_operator.argtypes = [C.POINTER(rr_operator), C.c_double, C.c_int32, P, P, P]
         L.rr_random_matrix.argtypes = [C.c_int32, C.c_uint64, C.c_int64, C.c_int64, P, P]
-        L.rr_sketch.argtypes = [C.POINTER(rr_operator), C.c_double, C.POINTER(rr_build_opts), P, P]
+        L.rr_sketch_apply.argtypes = [C.POINTER(rr_operator), C.c_double, C.POINTER(rr_build_opts),
+                                      P, P]
         L.rr_profile_enable.argtypes = [C.c_int32]
         L.rr_profile_enable.restype = None
         L.rr_profile_read.argtypes = [C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_double)]
@@ -138,7 +139,7 @@ def lib():
         L.rr_version.restype = C.c_char_p
         for name in ("rr_build_precond", "rr_solve", "rr_solve_batch", "rr_serve",
                      "rr_precond_export", "rr_precond_export_omega", "rr_precond_shape",
-                     "rr_kernel_to_dense", "rr_apply_operator", "rr_random_matrix", "rr_sketch"):
+                     "rr_kernel_to_dense", "rr_apply_operator", "rr_random_matrix", "rr_sketch_apply"):
             getattr(L, name).restype = C.c_int32
         _lib = L
     return _lib
@@ -361,6 +362,6 @@ def sketch(op: Operator, mu: float, l: int, stream=None, **kw):
     import torch
     o = build_opts(l=l, **kw)
     out = torch.empty((l, op.n), dtype=torch.float64, device="cuda")
-    _check(lib().rr_sketch(C.byref(op.struct), float(mu), C.byref(o), _ptr(out), _stream(stream)),
-           "rr_sketch")
+    _check(lib().rr_sketch_apply(C.byref(op.struct), float(mu), C.byref(o), _ptr(out),
+                                 _stream(stream)), "rr_sketch_apply")
     return out.t()

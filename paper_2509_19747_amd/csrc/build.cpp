@@ -463,7 +463,7 @@ extern "C" rr_status rr_build_precond(const rr_operator* A, const double* mus, i
 
 // The sketch step alone, for inspection: Y = A Omega + mu Omega exactly as
 // rr_build_precond computes it with the same options.
-extern "C" rr_status rr_sketch(const rr_operator* A, double mu, const rr_build_opts* opts,
+extern "C" rr_status rr_sketch_apply(const rr_operator* A, double mu, const rr_build_opts* opts,
                                double* Y_out, void* hip_stream) {
     return guarded([&]() -> rr_status {
         validate_operator(A);
