@@ -71,6 +71,20 @@ int apply_operator(const rr_precond& P, const double* u, double mu, double* y, d
     return dense_matvec_blocks(P.n);
 }
 
+void apply_operator_multi(const rr_precond& P, const double* U, int nr, double mu, double* Y,
+                          double* dot_part, double* kmv_ws, bool fp64, hipStream_t st) {
+    if (is_kernel(P.op)) {
+        const KernelOp k = kernel_op_of(P);
+        launch_kernel_matvec_multi(k, fp64 || P.opts.prec == RR_PREC_FP64, U, nr, mu, Y, dot_part,
+                                   kmv_ws, nullptr, st);
+        return;
+    }
+    const int np = operator_part_count(P);
+    for (int q = 0; q < nr; ++q)
+        apply_operator(P, U + (size_t)q * P.n, mu, Y + (size_t)q * P.n, dot_part + (size_t)q * np,
+                       kmv_ws, fp64, nullptr, st);
+}
+
 int apply_projected(const rr_precond& P, const double* Kc, const double* r, double rcoef, double* z,
                     double* c_part, double* d, double* rz_part, const int32_t* stop, hipStream_t st) {
     const int nch = gemv_t_chunks(P.n, P.kb);

@@ -231,23 +231,50 @@ struct Builder {
             pm.lam = std::nan("");
             return;
         }
-        DBuf u(al, n * sizeof(double)), y(al, n * sizeof(double));
+        // The two power iterations run side by side so each step costs one
+        // two-column operator pass (every kernel entry evaluated once):
+        //   ||E||: v <- (I-Pi) A_mu (I-Pi) v,   lam: v <- Pi A_mu Pi~ v.
+        DBuf U(al, 2 * n * sizeof(double)), Yv(al, 2 * n * sizeof(double));
+        DBuf V(al, 2 * n * sizeof(double)), Wv(al, 2 * n * sizeof(double));
         const int nch = gemv_t_chunks(n, P.kb);
         DBuf cpart(al, (size_t)nch * P.kb * sizeof(double)), d(al, P.kb * sizeof(double));
         DBuf rz(al, (size_t)qd_blocks(n) * sizeof(double));
-        DBuf op_part(al, (size_t)operator_part_count(P) * sizeof(double));
-        auto E = [&](const double* v, double* out) {
-            apply_projected(P, negT, v, 1.0, u.as<double>(), cpart.as<double>(), d.as<double>(), rz.as<double>(), nullptr, st);
-            apply_operator(P, u.as<double>(), mu, y.as<double>(), op_part.as<double>(), kws.as<double>(), false, nullptr, st);
-            apply_projected(P, negT, y.as<double>(), 1.0, out, cpart.as<double>(), d.as<double>(), rz.as<double>(), nullptr, st);
-        };
-        auto M = [&](const double* v, double* out) {
-            apply_projected(P, TGT, v, 0.0, u.as<double>(), cpart.as<double>(), d.as<double>(), rz.as<double>(), nullptr, st);
-            apply_operator(P, u.as<double>(), mu, y.as<double>(), op_part.as<double>(), kws.as<double>(), false, nullptr, st);
-            apply_projected(P, T, y.as<double>(), 0.0, out, cpart.as<double>(), d.as<double>(), rz.as<double>(), nullptr, st);
-        };
-        pm.normE = power_norm(E, P.opts.seed + 2, P.opts.power_iters);
-        pm.lam = power_norm(M, P.opts.seed + 3, P.opts.power_iters);
+        DBuf op_part(al, (size_t)2 * operator_part_count(P) * sizeof(double));
+        double* u0 = U.as<double>();
+        double* u1 = u0 + n;
+        double* y0 = Yv.as<double>();
+        double* y1 = y0 + n;
+        double* v0 = V.as<double>();
+        double* v1 = v0 + n;
+        double* w0 = Wv.as<double>();
+        double* w1 = w0 + n;
+        double* lam_dev = scal.as<double>();   // [0] ||E||, [1] lam, [2..3] start norms
+        launch_gauss_fill(v0, DT_F64, n, 1, n, P.opts.seed + 2, st);
+        launch_gauss_fill(v1, DT_F64, n, 1, n, P.opts.seed + 3, st);
+        launch_dot_part(n, v0, v0, vparts.as<double>(), st);
+        launch_normalize(n, v0, v0, vparts.as<double>(), vec_blocks(n), lam_dev + 2, st);
+        launch_dot_part(n, v1, v1, vparts.as<double>(), st);
+        launch_normalize(n, v1, v1, vparts.as<double>(), vec_blocks(n), lam_dev + 3, st);
+        double* cp = cpart.as<double>();
+        double* dd = d.as<double>();
+        double* rzp = rz.as<double>();
+        for (int it = 0; it < P.opts.power_iters; ++it) {
+            apply_projected(P, negT, v0, 1.0, u0, cp, dd, rzp, nullptr, st);    // (I-Pi) v
+            apply_projected(P, TGT, v1, 0.0, u1, cp, dd, rzp, nullptr, st);     // Pi~ v
+            apply_operator_multi(P, u0, 2, mu, y0, op_part.as<double>(), kws.as<double>(), false, st);
+            apply_projected(P, negT, y0, 1.0, w0, cp, dd, rzp, nullptr, st);    // (I-Pi) A u
+            apply_projected(P, T, y1, 0.0, w1, cp, dd, rzp, nullptr, st);       // Pi A u
+            launch_dot_part(n, w0, w0, vparts.as<double>(), st);
+            launch_normalize(n, v0, w0, vparts.as<double>(), vec_blocks(n), lam_dev + 0, st);
+            launch_dot_part(n, w1, w1, vparts.as<double>(), st);
+            launch_normalize(n, v1, w1, vparts.as<double>(), vec_blocks(n), lam_dev + 1, st);
+        }
+        check_launch();
+        double lams[2] = {0.0, 0.0};
+        RR_HIP(hipMemcpyAsync(lams, lam_dev, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+        sync();
+        pm.normE = lams[0];
+        pm.lam = lams[1];
         if (!std::isfinite(pm.normE) || !(pm.lam > 0.0) || !std::isfinite(pm.lam))
             throw RrError{RR_ENOTSPD, "power-iteration estimates of ||E|| or lam are not positive"};
         if (!(pm.normE > 0.0)) {

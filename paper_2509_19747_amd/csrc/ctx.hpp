@@ -153,6 +153,10 @@ KernelOp kernel_op_of(const rr_precond& P);
 // fp64 = use the float64 operator (dense A or float64 kernel entries).
 int apply_operator(const rr_precond& P, const double* u, double mu, double* y, double* dot_part,
                    double* kmv_ws, bool fp64, const int32_t* stop, hipStream_t st);
+// Same for nr (1 or 2) columns U, Y (n x nr); dot partials of column q start at
+// dot_part + q * operator_part_count(P).
+void apply_operator_multi(const rr_precond& P, const double* U, int nr, double mu, double* Y,
+                          double* dot_part, double* kmv_ws, bool fp64, hipStream_t st);
 int operator_part_count(const rr_precond& P);
 size_t operator_ws_doubles(const rr_precond& P);
 

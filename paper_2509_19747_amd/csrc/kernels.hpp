@@ -95,6 +95,12 @@ int kernel_matvec_blocks(int64_t n);
 size_t kernel_matvec_ws_doubles(int64_t n);
 void launch_kernel_matvec(const KernelOp& op, bool fp64, const double* u, double mu, double* y,
                           double* dot_part, double* ws, const int32_t* stop, hipStream_t st);
+// nr (1 or 2) right-hand sides at once: u, y are n x nr (leading dimension n);
+// dot partials of column q at dot_part[q * kernel_matvec_blocks(n) + b].  Each
+// kernel entry is evaluated once and applied to every column.
+void launch_kernel_matvec_multi(const KernelOp& op, bool fp64, const double* u, int nr, double mu,
+                                double* y, double* dot_part, double* ws, const int32_t* stop,
+                                hipStream_t st);
 void launch_sqnorms(const float* pts, int64_t n, int d, float* sqn, hipStream_t st);
 // Dense formation A_out = scale*K in float64 (dtype 0) / float32 (1) / bf16 (2).
 void launch_kernel_to_dense(const KernelOp& op, void* out, int dtype, int64_t lda, hipStream_t st);

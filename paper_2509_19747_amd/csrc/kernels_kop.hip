@@ -20,22 +20,28 @@
 #include "kernels.hpp"
 #include "prof.hpp"
 
+#include <algorithm>
+
 namespace rr {
 
 constexpr float LOG2E_F = 1.4426950408889634f;
 
-// RBF: exp(-kconst * r^2) = exp2(-c2 * r^2) with c2 = fl32(kconst * log2 e).
-// Matern-3/2: (1 + t) exp(-t), t = kconst * r.
+// Float32 kernel entry from s = x_i.x_j - (|x_i|^2 + |x_j|^2)/2 = -r^2/2.  Callers
+// form s symmetrically: start from fl(-0.5 (|x_i|^2 + |x_j|^2)) (one rounding of an
+// exact sum) and add the coordinate products in a fixed order.
+//   RBF        exp(-kconst r^2) = exp2(c min(s, 0)),   c = fl32(2 kconst log2 e)
+//   Matern-3/2 (1 + t) exp(-t),  t = kconst sqrt(max(-2 s, 0)),  c = fl32(kconst)
 template <int KIND>
-RR_DEV float kval32(float r2, float c) {
-    r2 = fmaxf(r2, 0.0f);
+RR_DEV float kval32(float s, float c) {
     if (KIND == 1) {
-        return __builtin_amdgcn_exp2f(-c * r2);
+        return __builtin_amdgcn_exp2f(c * fminf(s, 0.0f));
     } else {
-        const float t = c * __builtin_sqrtf(r2);
+        const float t = c * __builtin_sqrtf(fmaxf(-2.0f * s, 0.0f));
         return (1.0f + t) * __builtin_amdgcn_exp2f(-t * LOG2E_F);
     }
 }
+// s starting value for the pair (i, j) from the row's -|x_i|^2/2 and |x_j|^2.
+RR_DEV float kpair_init(float mhalf_ni, float nj) { return fmaf(-0.5f, nj, mhalf_ni); }
 
 template <int KIND>
 RR_DEV double kval64(double r2, double kconst) {
@@ -46,7 +52,7 @@ RR_DEV double kval64(double r2, double kconst) {
 }
 
 static float c_for(int kind, double kconst) {
-    return kind == 1 ? (float)(kconst * 1.4426950408889634074) : (float)kconst;
+    return kind == 1 ? (float)(2.0 * kconst * 1.4426950408889634074) : (float)kconst;
 }
 
 __global__ void k_sqnorms(const float* __restrict__ pts, int64_t n, int d, float* __restrict__ sqn) {
@@ -68,9 +74,9 @@ void launch_sqnorms(const float* pts, int64_t n, int d, float* sqn, hipStream_t 
 
 // ======================================================== kernel matvec
 constexpr int KMV_THREADS = 256;
-constexpr int KMV_R = 4;                       // rows per thread
+constexpr int KMV_R = 8;                       // rows per thread
 constexpr int KMV_ROWS = KMV_THREADS * KMV_R;  // rows per block
-constexpr int KMV_JB = 8;                      // j unroll (scalar-load friendly)
+constexpr int KMV_JB = 4;                      // points per unrolled step (fits in SGPRs)
 
 static int kmv_slices(int64_t n) {
     const int64_t rb = (n + KMV_ROWS - 1) / KMV_ROWS;
@@ -82,10 +88,12 @@ static int kmv_slices(int64_t n) {
     return (int)s;
 }
 int kernel_matvec_blocks(int64_t n) { return (int)((n + 255) / 256); }
-size_t kernel_matvec_ws_doubles(int64_t n) { return (size_t)kmv_slices(n) * (size_t)n; }
 
 // Stage 1, float32 entries.  D = point dimension (compile time, or 0 = runtime d).
-template <int KIND, int D>
+// Each thread owns KMV_R rows (coordinates in VGPRs); the points j of the block's
+// slice are wave-uniform, so their coordinates arrive through scalar loads and
+// every kernel entry costs d FMAs, the exp2 and one float64 FMA.
+template <int KIND, int D, int NR>
 __global__ __launch_bounds__(KMV_THREADS) void k_kmv_f32(int64_t n, int dd,
                                                          const float* __restrict__ pts,
                                                          const float* __restrict__ sqn, float c,
@@ -98,16 +106,17 @@ __global__ __launch_bounds__(KMV_THREADS) void k_kmv_f32(int64_t n, int dd,
     const int d = D > 0 ? D : dd;
     const int64_t rbase = (int64_t)blockIdx.x * KMV_ROWS + threadIdx.x;
     float xi[KMV_R][DM];
-    float ni[KMV_R];
-    double acc[KMV_R];
+    float mhn[KMV_R];
+    double acc[KMV_R][NR];
 #pragma unroll
     for (int r = 0; r < KMV_R; ++r) {
         const int64_t i = rbase + (int64_t)r * KMV_THREADS;
         const int64_t ic = i < n ? i : n - 1;
 #pragma unroll
         for (int k = 0; k < DM; ++k) xi[r][k] = (k < d) ? pts[(int64_t)k * n + ic] : 0.0f;
-        ni[r] = sqn[ic];
-        acc[r] = 0.0;
+        mhn[r] = -0.5f * sqn[ic];
+#pragma unroll
+        for (int q = 0; q < NR; ++q) acc[r][q] = 0.0;
     }
     const int64_t jb = (int64_t)blockIdx.y * jper;
     const int64_t je = (jb + jper < n) ? jb + jper : n;
@@ -117,54 +126,64 @@ __global__ __launch_bounds__(KMV_THREADS) void k_kmv_f32(int64_t n, int dd,
         for (int q = 0; q < KMV_JB; ++q) {
             const int64_t jj = j + q;
             const float nj = sqn[jj];
-            const double uj = u[jj];
-            float dot[KMV_R];
+            double uj[NR];
 #pragma unroll
-            for (int r = 0; r < KMV_R; ++r) dot[r] = 0.0f;
+            for (int q = 0; q < NR; ++q) uj[q] = u[(int64_t)q * n + jj];
+            float s[KMV_R];
+#pragma unroll
+            for (int r = 0; r < KMV_R; ++r) s[r] = kpair_init(mhn[r], nj);
 #pragma unroll
             for (int k = 0; k < DM; ++k) {
                 if (k < d) {
                     const float xjk = pts[(int64_t)k * n + jj];
 #pragma unroll
-                    for (int r = 0; r < KMV_R; ++r) dot[r] = fmaf(xi[r][k], xjk, dot[r]);
+                    for (int r = 0; r < KMV_R; ++r) s[r] = fmaf(xi[r][k], xjk, s[r]);
                 }
             }
 #pragma unroll
             for (int r = 0; r < KMV_R; ++r) {
-                const float r2 = fmaf(-2.0f, dot[r], ni[r] + nj);
-                acc[r] = fma((double)kval32<KIND>(r2, c), uj, acc[r]);
+                const double kv = (double)kval32<KIND>(s[r], c);
+#pragma unroll
+                for (int q = 0; q < NR; ++q) acc[r][q] = fma(kv, uj[q], acc[r][q]);
             }
         }
     }
     for (; j < je; ++j) {
         const float nj = sqn[j];
-        const double uj = u[j];
-        float dot[KMV_R];
+        double uj[NR];
 #pragma unroll
-        for (int r = 0; r < KMV_R; ++r) dot[r] = 0.0f;
+        for (int q = 0; q < NR; ++q) uj[q] = u[(int64_t)q * n + j];
+        float s[KMV_R];
+#pragma unroll
+        for (int r = 0; r < KMV_R; ++r) s[r] = kpair_init(mhn[r], nj);
 #pragma unroll
         for (int k = 0; k < DM; ++k) {
             if (k < d) {
                 const float xjk = pts[(int64_t)k * n + j];
 #pragma unroll
-                for (int r = 0; r < KMV_R; ++r) dot[r] = fmaf(xi[r][k], xjk, dot[r]);
+                for (int r = 0; r < KMV_R; ++r) s[r] = fmaf(xi[r][k], xjk, s[r]);
             }
         }
 #pragma unroll
         for (int r = 0; r < KMV_R; ++r) {
-            const float r2 = fmaf(-2.0f, dot[r], ni[r] + nj);
-            acc[r] = fma((double)kval32<KIND>(r2, c), uj, acc[r]);
+            const double kv = (double)kval32<KIND>(s[r], c);
+#pragma unroll
+            for (int q = 0; q < NR; ++q) acc[r][q] = fma(kv, uj[q], acc[r][q]);
         }
     }
 #pragma unroll
     for (int r = 0; r < KMV_R; ++r) {
         const int64_t i = rbase + (int64_t)r * KMV_THREADS;
-        if (i < n) part[(int64_t)blockIdx.y * n + i] = acc[r];
+        if (i < n)
+#pragma unroll
+            for (int q = 0; q < NR; ++q) part[((int64_t)blockIdx.y * NR + q) * n + i] = acc[r][q];
     }
 }
 
 // Stage 1, float64 entries (difference form, float64 exp).
-template <int KIND>
+constexpr int KMV64_R = 4;
+constexpr int KMV64_ROWS = KMV_THREADS * KMV64_R;
+template <int KIND, int NR>
 __global__ __launch_bounds__(KMV_THREADS) void k_kmv_f64(int64_t n, int d,
                                                          const float* __restrict__ pts,
                                                          double kconst,
@@ -173,40 +192,40 @@ __global__ __launch_bounds__(KMV_THREADS) void k_kmv_f64(int64_t n, int d,
                                                          int64_t jper,
                                                          const int32_t* __restrict__ stop) {
     if (stop && *stop) return;
-    const int64_t rbase = (int64_t)blockIdx.x * KMV_ROWS + threadIdx.x;
-    double xi[KMV_R][16];
-    double acc[KMV_R];
+    const int64_t rbase = (int64_t)blockIdx.x * KMV64_ROWS + threadIdx.x;
+    double xi[KMV64_R][16];
+    double acc[KMV64_R][NR];
     const int dl = d < 16 ? d : 16;
 #pragma unroll
-    for (int r = 0; r < KMV_R; ++r) {
+    for (int r = 0; r < KMV64_R; ++r) {
         const int64_t i = rbase + (int64_t)r * KMV_THREADS;
         const int64_t ic = i < n ? i : n - 1;
 #pragma unroll
         for (int k = 0; k < 16; ++k) xi[r][k] = (k < dl) ? (double)pts[(int64_t)k * n + ic] : 0.0;
-        acc[r] = 0.0;
+#pragma unroll
+        for (int q = 0; q < NR; ++q) acc[r][q] = 0.0;
     }
     const int64_t jb = (int64_t)blockIdx.y * jper;
     const int64_t je = (jb + jper < n) ? jb + jper : n;
     for (int64_t j = jb; j < je; ++j) {
-        const double uj = u[j];
-        double r2[KMV_R];
+        double r2[KMV64_R];
 #pragma unroll
-        for (int r = 0; r < KMV_R; ++r) r2[r] = 0.0;
+        for (int r = 0; r < KMV64_R; ++r) r2[r] = 0.0;
 #pragma unroll
         for (int k = 0; k < 16; ++k) {
             if (k < dl) {
                 const double xjk = (double)pts[(int64_t)k * n + j];
 #pragma unroll
-                for (int r = 0; r < KMV_R; ++r) {
+                for (int r = 0; r < KMV64_R; ++r) {
                     const double t = xi[r][k] - xjk;
                     r2[r] = fma(t, t, r2[r]);
                 }
             }
         }
-        for (int k = 16; k < d; ++k) {   // dimensions beyond 16 (rare): reload row coords
+        for (int k = 16; k < d; ++k) {   // dimensions beyond 16: reload row coordinates
             const double xjk = (double)pts[(int64_t)k * n + j];
 #pragma unroll
-            for (int r = 0; r < KMV_R; ++r) {
+            for (int r = 0; r < KMV64_R; ++r) {
                 const int64_t i = rbase + (int64_t)r * KMV_THREADS;
                 const int64_t ic = i < n ? i : n - 1;
                 const double t = (double)pts[(int64_t)k * n + ic] - xjk;
@@ -214,73 +233,109 @@ __global__ __launch_bounds__(KMV_THREADS) void k_kmv_f64(int64_t n, int d,
             }
         }
 #pragma unroll
-        for (int r = 0; r < KMV_R; ++r) acc[r] = fma(kval64<KIND>(r2[r], kconst), uj, acc[r]);
+        for (int r = 0; r < KMV64_R; ++r) {
+            const double kv = kval64<KIND>(r2[r], kconst);
+#pragma unroll
+            for (int q = 0; q < NR; ++q) acc[r][q] = fma(kv, u[(int64_t)q * n + j], acc[r][q]);
+        }
     }
 #pragma unroll
-    for (int r = 0; r < KMV_R; ++r) {
+    for (int r = 0; r < KMV64_R; ++r) {
         const int64_t i = rbase + (int64_t)r * KMV_THREADS;
-        if (i < n) part[(int64_t)blockIdx.y * n + i] = acc[r];
+        if (i < n)
+#pragma unroll
+            for (int q = 0; q < NR; ++q) part[((int64_t)blockIdx.y * NR + q) * n + i] = acc[r][q];
     }
 }
 
-// Stage 2: y_i = scale * sum_s part[s][i] + mu u_i; partials of u^T y.
-__global__ __launch_bounds__(256) void k_kmv_finish(int64_t n, int slices,
+// Stage 2: y_q = scale * sum_s part[s][q] + mu u_q per column q; partials of u_q^T y_q
+// in dot_part[q * gridDim.x + block].
+__global__ __launch_bounds__(256) void k_kmv_finish(int64_t n, int slices, int nr,
                                                     const double* __restrict__ part,
                                                     double scale, double mu,
                                                     const double* __restrict__ u,
                                                     double* __restrict__ y,
                                                     double* __restrict__ dot_part,
                                                     const int32_t* __restrict__ stop) {
+    __shared__ double sc[4];
     if (stop && *stop) return;
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    double dot = 0.0;
-    if (i < n) {
-        double s = 0.0;
-        for (int q = 0; q < slices; ++q) s += part[(int64_t)q * n + i];
-        const double yi = fma(scale, s, mu * u[i]);
-        y[i] = yi;
-        dot = u[i] * yi;
+    for (int q = 0; q < nr; ++q) {
+        double dot = 0.0;
+        if (i < n) {
+            double s = 0.0;
+            for (int z = 0; z < slices; ++z) s += part[((int64_t)z * nr + q) * n + i];
+            const double ui = u[(int64_t)q * n + i];
+            const double yi = fma(scale, s, mu * ui);
+            y[(int64_t)q * n + i] = yi;
+            dot = ui * yi;
+        }
+        dot = block_sum(dot, sc);
+        if (threadIdx.x == 0) dot_part[(int64_t)q * gridDim.x + blockIdx.x] = dot;
     }
-    __shared__ double sc[4];
-    dot = block_sum(dot, sc);
-    if (threadIdx.x == 0) dot_part[blockIdx.x] = dot;
 }
 
-template <int KIND>
+template <int KIND, int NR>
 static void kmv_f32_dispatch(const KernelOp& op, float c, const double* u, double* part,
                              int64_t jper, dim3 grid, const int32_t* stop, hipStream_t st) {
     switch (op.d) {
-        case 3: k_kmv_f32<KIND, 3><<<grid, KMV_THREADS, 0, st>>>(op.n, 3, op.pts, op.sqn, c, u, part, jper, stop); break;
-        case 4: k_kmv_f32<KIND, 4><<<grid, KMV_THREADS, 0, st>>>(op.n, 4, op.pts, op.sqn, c, u, part, jper, stop); break;
-        case 8: k_kmv_f32<KIND, 8><<<grid, KMV_THREADS, 0, st>>>(op.n, 8, op.pts, op.sqn, c, u, part, jper, stop); break;
-        case 16: k_kmv_f32<KIND, 16><<<grid, KMV_THREADS, 0, st>>>(op.n, 16, op.pts, op.sqn, c, u, part, jper, stop); break;
-        default: k_kmv_f32<KIND, 0><<<grid, KMV_THREADS, 0, st>>>(op.n, op.d, op.pts, op.sqn, c, u, part, jper, stop); break;
+        case 3: k_kmv_f32<KIND, 3, NR><<<grid, KMV_THREADS, 0, st>>>(op.n, 3, op.pts, op.sqn, c, u, part, jper, stop); break;
+        case 4: k_kmv_f32<KIND, 4, NR><<<grid, KMV_THREADS, 0, st>>>(op.n, 4, op.pts, op.sqn, c, u, part, jper, stop); break;
+        case 8: k_kmv_f32<KIND, 8, NR><<<grid, KMV_THREADS, 0, st>>>(op.n, 8, op.pts, op.sqn, c, u, part, jper, stop); break;
+        case 16: k_kmv_f32<KIND, 16, NR><<<grid, KMV_THREADS, 0, st>>>(op.n, 16, op.pts, op.sqn, c, u, part, jper, stop); break;
+        default: k_kmv_f32<KIND, 0, NR><<<grid, KMV_THREADS, 0, st>>>(op.n, op.d, op.pts, op.sqn, c, u, part, jper, stop); break;
     }
 }
 
-// Stage 1 only (the timed hot kernel): ws[s][i] = sum over slice s of K_ij u_j.
-static void kmv_stage1(const KernelOp& op, bool fp64, const double* u, double* ws,
-                       const int32_t* stop, hipStream_t st) {
+static int kmv64_slices(int64_t n) {
+    const int64_t rb = (n + KMV64_ROWS - 1) / KMV64_ROWS;
+    int64_t s = (2048 + rb - 1) / rb;
+    const int64_t maxs = (n + 255) / 256;
+    if (s > maxs) s = maxs;
+    if (s < 1) s = 1;
+    if (s > 256) s = 256;
+    return (int)s;
+}
+
+// Stage 1 only (the timed hot kernel): ws[s][q][i] = sum over slice s of K_ij u_q[j].
+// Returns the number of slices.
+static int kmv_stage1(const KernelOp& op, bool fp64, const double* u, int nr, double* ws,
+                      const int32_t* stop, hipStream_t st) {
+    if (fp64) {
+        const int slices = kmv64_slices(op.n);
+        const int64_t jper = (op.n + slices - 1) / slices;
+        dim3 grid((unsigned)((op.n + KMV64_ROWS - 1) / KMV64_ROWS), (unsigned)slices);
+#define KF64(K, R) k_kmv_f64<K, R><<<grid, KMV_THREADS, 0, st>>>(op.n, op.d, op.pts, op.kconst, u, ws, jper, stop)
+        if (op.kind == 1) { if (nr == 1) KF64(1, 1); else KF64(1, 2); }
+        else { if (nr == 1) KF64(2, 1); else KF64(2, 2); }
+#undef KF64
+        return slices;
+    }
     const int slices = kmv_slices(op.n);
     const int64_t jper = (op.n + slices - 1) / slices;
     dim3 grid((unsigned)((op.n + KMV_ROWS - 1) / KMV_ROWS), (unsigned)slices);
-    ProfScope prof(fp64 ? -1 : PROF_KERNEL_MATVEC, st);
-    if (fp64) {
-        if (op.kind == 1) k_kmv_f64<1><<<grid, KMV_THREADS, 0, st>>>(op.n, op.d, op.pts, op.kconst, u, ws, jper, stop);
-        else k_kmv_f64<2><<<grid, KMV_THREADS, 0, st>>>(op.n, op.d, op.pts, op.kconst, u, ws, jper, stop);
-    } else {
-        const float c = c_for(op.kind, op.kconst);
-        if (op.kind == 1) kmv_f32_dispatch<1>(op, c, u, ws, jper, grid, stop, st);
-        else kmv_f32_dispatch<2>(op, c, u, ws, jper, grid, stop, st);
-    }
+    ProfScope prof(nr == 1 ? PROF_KERNEL_MATVEC : -1, st);
+    const float c = c_for(op.kind, op.kconst);
+    if (op.kind == 1) { if (nr == 1) kmv_f32_dispatch<1, 1>(op, c, u, ws, jper, grid, stop, st); else kmv_f32_dispatch<1, 2>(op, c, u, ws, jper, grid, stop, st); }
+    else { if (nr == 1) kmv_f32_dispatch<2, 1>(op, c, u, ws, jper, grid, stop, st); else kmv_f32_dispatch<2, 2>(op, c, u, ws, jper, grid, stop, st); }
+    return slices;
+}
+
+size_t kernel_matvec_ws_doubles(int64_t n) {
+    return (size_t)2 * (size_t)std::max(kmv_slices(n), kmv64_slices(n)) * (size_t)n;
+}
+
+void launch_kernel_matvec_multi(const KernelOp& op, bool fp64, const double* u, int nr, double mu,
+                                double* y, double* dot_part, double* ws, const int32_t* stop,
+                                hipStream_t st) {
+    const int slices = kmv_stage1(op, fp64, u, nr, ws, stop, st);
+    k_kmv_finish<<<kernel_matvec_blocks(op.n), 256, 0, st>>>(op.n, slices, nr, ws, op.scale, mu, u,
+                                                             y, dot_part, stop);
 }
 
 void launch_kernel_matvec(const KernelOp& op, bool fp64, const double* u, double mu, double* y,
                           double* dot_part, double* ws, const int32_t* stop, hipStream_t st) {
-    kmv_stage1(op, fp64, u, ws, stop, st);
-    const int slices = kmv_slices(op.n);
-    k_kmv_finish<<<kernel_matvec_blocks(op.n), 256, 0, st>>>(op.n, slices, ws, op.scale, mu, u, y,
-                                                             dot_part, stop);
+    launch_kernel_matvec_multi(op, fp64, u, 1, mu, y, dot_part, ws, stop, st);
 }
 
 // ===================================================== dense formation
@@ -364,11 +419,11 @@ __global__ __launch_bounds__(256) void k_kgemm_f32_mfma(int64_t n, int dd,
             const int64_t gj = j0 + p;
             float kv = 0.0f;
             if (gj < n && gi < n) {
-                float dot = 0.0f;
+                float sv = kpair_init(-0.5f * ni, sqn[gj]);
 #pragma unroll
                 for (int k = 0; k < DM; ++k)
-                    if (k < d) dot = fmaf(xi[k], pts[(int64_t)k * n + gj], dot);
-                kv = kval32<KIND>(fmaf(-2.0f, dot, ni + sqn[gj]), c);
+                    if (k < d) sv = fmaf(xi[k], pts[(int64_t)k * n + gj], sv);
+                kv = kval32<KIND>(sv, c);
             }
             Ks[p][trow] = kv;
         }
@@ -505,11 +560,11 @@ __global__ __launch_bounds__(KB_THREADS) void k_kgemm_bf16x2(int64_t n, int dd,
                     const int64_t gj = j0 + 8 * pg + 2 * e2 + h;
                     float kv = 0.0f;
                     if (gj < n && gi < n) {
-                        float dot = 0.0f;
+                        float sv = kpair_init(-0.5f * ni, sqn[gj]);
 #pragma unroll
                         for (int k = 0; k < DM; ++k)
-                            if (k < d) dot = fmaf(xi[k], pts[(int64_t)k * n + gj], dot);
-                        kv = kval32<KIND>(fmaf(-2.0f, dot, ni + sqn[gj]), c);
+                            if (k < d) sv = fmaf(xi[k], pts[(int64_t)k * n + gj], sv);
+                        kv = kval32<KIND>(sv, c);
                     }
                     const uint32_t hbits = bf16_rne_bits(kv);
                     const float hf = __uint_as_float(hbits << 16);
