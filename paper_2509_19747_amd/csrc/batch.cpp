@@ -1,26 +1,256 @@
-// Batched solves: several right-hand sides / shifts against one handle.
+// rr_solve_batch: m independent C-RandRAND PCG recurrences (one per column, each
+// with its own shift from the handle) advanced together.
+//
+// Per iteration, for all columns at once:
+//   W = A_mu P      one operator product for all columns (kernel operators: the
+//                   float32 kernel entries widened to float64 on FP64 MFMA)
+//   alpha_j, x_j, r_j, ||r_j||^2, per-column stop test (column run flags)
+//   Z = R + Qb (Kc_{mu(j)} (Qb^T R))   (GEMMs over the joint basis, Section 5.1)
+//   beta_j, p_j
+// Restarts follow the single solve exactly per column (Algorithm RandRAND_PCG
+// step 10 with eta): a column that reaches its cycle target stops; at the next
+// host check its true residual b_j - A_mu x_j is recomputed and it either finishes
+// or starts a new cycle.  Columns that have stopped are not updated.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <vector>
 
 #include "ctx.hpp"
 
 using namespace rr;
 
-// Column-at-a-time driver: each column runs its own PCG recurrence with the
-// handle's shared basis.
-rr_status rr_solve_batch_fused(const rr_precond* P, const int32_t* mu_index_per_col,
+namespace {
+
+struct Batch {
+    const rr_precond& P;
+    hipStream_t st;
+    int64_t n, m, kb;
+    const Alloc* al;
+    DBuf R, Pm, Z, W, T, parts, C, Dall, D, state, start, target2, mucol, muidx, gws;
+    size_t gwsd = 0;
+    std::vector<int> mus_used;
+    int nch = 1;
+
+    Batch(const rr_precond& p, hipStream_t s, int64_t mcols) : P(p), st(s), n(p.n), m(mcols), kb(p.kb), al(&p.alloc) {
+        const size_t nm = (size_t)n * m * sizeof(double);
+        R.reset(al, nm); Pm.reset(al, nm); Z.reset(al, nm); W.reset(al, nm); T.reset(al, nm);
+        nch = coldot_chunks(n);
+        parts.reset(al, (size_t)nch * m * sizeof(double));
+        if (kb > 0) {
+            C.reset(al, (size_t)kb * m * sizeof(double));
+            D.reset(al, (size_t)kb * m * sizeof(double));
+            Dall.reset(al, (size_t)p.per.size() * kb * m * sizeof(double));
+        }
+        state.reset(al, (size_t)m * sizeof(BState));
+        start.reset(al, (size_t)m * sizeof(int32_t));
+        target2.reset(al, (size_t)m * sizeof(double));
+        mucol.reset(al, (size_t)m * sizeof(double));
+        muidx.reset(al, (size_t)m * sizeof(int32_t));
+        gwsd = std::max<size_t>((size_t)8 * std::max<int64_t>(kb, 1) * m, (size_t)1 << 20);
+        gws.reset(al, gwsd * sizeof(double));
+        RR_HIP(hipMemsetAsync(state.ptr(), 0, (size_t)m * sizeof(BState), st));
+    }
+
+    void gemm(bool ta, bool tb, int64_t M, int64_t N, int64_t K, const void* A, int64_t lda,
+              const void* B, int64_t ldb, double* Cm, int64_t ldc, double alpha, double beta,
+              int dta = DT_F64) {
+        launch_gemm(dta, ta, DT_F64, tb, M, N, K, A, lda, B, ldb, Cm, ldc, alpha, beta, gws.as<double>(), gwsd, st);
+    }
+
+    // Wout = A_mu Pin for every column (fp64: float64 operator)
+    void matmat(const double* Pin, int64_t ldp, double* Wout, bool fp64) {
+        if (is_kernel(P.op)) {
+            const KernelOp k = kernel_op_of(P);
+            launch_kernel_matmat_f64(k, fp64 || P.opts.prec == RR_PREC_FP64, mucol.as<double>(), Pin, ldp, m,
+                                     Wout, n, st);
+        } else {
+            if (!fp64 && P.A32.ptr()) gemm(false, false, n, m, n, P.A32.ptr(), n, Pin, ldp, Wout, n, 1.0, 0.0, DT_F32);
+            else gemm(false, false, n, m, n, P.op.A, P.op.lda, Pin, ldp, Wout, n, 1.0, 0.0);
+            launch_add_shift_cols(n, m, mucol.as<double>(), Pin, ldp, Wout, n, st);
+        }
+    }
+
+    // Zout = P_{mu(j)} Rin for every column
+    void precond(const double* Rin, double* Zout) {
+        launch_copy_mat(DT_F64, Rin, n, DT_F64, Zout, n, n, m, st);
+        if (kb == 0) return;
+        const double* Qb = P.Qb.as<double>();
+        gemm(true, false, kb, m, n, Qb, n, Rin, n, C.as<double>(), kb, 1.0, 0.0);
+        for (int g : mus_used)
+            gemm(false, false, kb, m, kb, P.per[g].Kc.ptr(), kb, C.ptr(), kb,
+                 Dall.as<double>() + (size_t)g * kb * m, kb, 1.0, 0.0);
+        launch_select_cols(kb, m, Dall.as<double>(), muidx.as<int32_t>(), D.as<double>(), st);
+        gemm(false, false, n, m, kb, Qb, n, D.ptr(), kb, Zout, n, 1.0, 1.0);
+    }
+
+    // per-column sums of A_j^T B_j on the host (fixed order)
+    std::vector<double> coldots(const double* A, int64_t lda, const double* B, int64_t ldb) {
+        launch_coldot(n, m, A, lda, B, ldb, parts.as<double>(), st);
+        std::vector<double> h((size_t)nch * m), out((size_t)m, 0.0);
+        RR_HIP(hipMemcpyAsync(h.data(), parts.ptr(), h.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+        RR_HIP(hipStreamSynchronize(st));
+        for (int64_t j = 0; j < m; ++j)
+            for (int c = 0; c < nch; ++c) out[j] += h[(size_t)c * m + j];
+        return out;
+    }
+
+    void iteration(double* X, int64_t ldx) {
+        BState* s = state.as<BState>();
+        double* r = R.as<double>();
+        double* p = Pm.as<double>();
+        double* w = W.as<double>();
+        double* z = Z.as<double>();
+        double* pp = parts.as<double>();
+        matmat(p, n, w, false);
+        launch_coldot(n, m, p, n, w, n, pp, st);
+        launch_bscal_alpha(pp, nch, m, s, st);
+        launch_bxr(n, m, X, ldx, r, p, w, s, st);
+        launch_coldot(n, m, r, n, r, n, pp, st);
+        launch_bscal_rr(pp, nch, m, s, st);
+        precond(r, z);
+        launch_coldot(n, m, r, n, z, n, pp, st);
+        launch_bscal_beta(pp, nch, m, s, st);
+        launch_bp(n, m, z, p, s, st);
+    }
+};
+
+}  // namespace
+
+rr_status rr_solve_batch_fused(const rr_precond* Pc, const int32_t* mu_index_per_col,
                                const double* B, int64_t ldb, int32_t nrhs, double* X, int64_t ldx,
                                const rr_solve_opts* o, rr_solve_info* infos, void* hip_stream) {
-    rr_status first = RR_OK;
-    for (int32_t j = 0; j < nrhs; ++j) {
-        rr_solve_info inf{};
-        const rr_status s = rr_solve(P, mu_index_per_col[j], B + (size_t)j * ldb,
-                                     X + (size_t)j * ldx, o, &inf, hip_stream);
-        if (infos) infos[j] = inf;
-        if (s != RR_OK && first == RR_OK) first = s;
-        if (s == RR_EDEVICE || s == RR_EINVAL) return s;
-    }
-    return first;
+    if (infos)
+        for (int j = 0; j < nrhs; ++j) { std::memset(&infos[j], 0, sizeof(rr_solve_info)); infos[j].status = RR_EINVAL; }
+    return guarded([&]() -> rr_status {
+        require_device();
+        const rr_precond& P = *Pc;
+        hipStream_t st = (hipStream_t)hip_stream;
+        const int64_t n = P.n, m = nrhs;
+        const double t0 = now_ms();
+        Batch Bt(P, st, m);
+        // per-column shifts and the set of shifts in use
+        std::vector<double> hmu(m);
+        std::vector<int> used(P.per.size(), 0);
+        for (int64_t j = 0; j < m; ++j) { hmu[j] = P.per[mu_index_per_col[j]].mu; used[mu_index_per_col[j]] = 1; }
+        for (size_t g = 0; g < used.size(); ++g) if (used[g]) Bt.mus_used.push_back((int)g);
+        RR_HIP(hipMemcpyAsync(Bt.mucol.ptr(), hmu.data(), m * sizeof(double), hipMemcpyHostToDevice, st));
+        RR_HIP(hipMemcpyAsync(Bt.muidx.ptr(), mu_index_per_col, m * sizeof(int32_t), hipMemcpyHostToDevice, st));
+
+        // NaN / Inf scan
+        {
+            DBuf flag(&P.alloc, 16);
+            RR_HIP(hipMemsetAsync(flag.ptr(), 0, sizeof(int32_t), st));
+            for (int64_t j = 0; j < m; ++j) {
+                launch_nonfinite(n, B + j * ldb, flag.as<int32_t>(), st);
+                launch_nonfinite(n, X + j * ldx, flag.as<int32_t>(), st);
+            }
+            int32_t bad = 0;
+            RR_HIP(hipMemcpyAsync(&bad, flag.ptr(), sizeof(int32_t), hipMemcpyDeviceToHost, st));
+            RR_HIP(hipStreamSynchronize(st));
+            RR_REQUIRE(bad == 0, "B or X0 contains NaN or Inf");
+        }
+        const bool ir = (o->fp64_ir == 1) || (o->fp64_ir == -1 && P.opts.prec == RR_PREC_MIXED);
+        const std::vector<double> bb = Bt.coldots(B, ldb, B, ldb);
+        std::vector<double> nb(m);
+        for (int64_t j = 0; j < m; ++j) nb[j] = std::sqrt(bb[j]);
+
+        std::vector<int> done(m, 0), cycles(m, 0), status(m, RR_ENOCONV), iters(m, 0);
+        std::vector<double> relres(m, 1.0);
+        std::vector<int32_t> hstart(m, 0);
+        std::vector<double> htarget(m, 0.0);
+        std::vector<BState> hs(m);
+        std::vector<int> pending(m, 1);   // needs a true-residual check
+        double* Xd = X;
+
+        auto restart_pass = [&]() {
+            // T = B - A_mu X for every column; decide per pending column
+            Bt.matmat(Xd, ldx, Bt.T.as<double>(), ir);
+            launch_bresid(n, m, B, ldb, Bt.T.as<double>(), Bt.T.as<double>(), st);
+            const std::vector<double> rr = Bt.coldots(Bt.T.as<double>(), n, Bt.T.as<double>(), n);
+            bool any = false;
+            for (int64_t j = 0; j < m; ++j) {
+                hstart[j] = 0;
+                if (!pending[j] || done[j]) continue;
+                pending[j] = 0;
+                const double rn = std::sqrt(rr[j]);
+                relres[j] = nb[j] > 0.0 ? rn / nb[j] : 0.0;
+                if (nb[j] == 0.0 || rn <= o->tol * nb[j]) { done[j] = 1; status[j] = RR_OK; continue; }
+                if (!std::isfinite(rn)) { done[j] = 1; status[j] = RR_EBREAKDOWN; continue; }
+                if (iters[j] >= o->maxit) { done[j] = 1; status[j] = RR_ENOCONV; continue; }
+                ++cycles[j];
+                const double target = std::max(o->restart_eta * rn, o->tol * nb[j]);
+                htarget[j] = target * target;
+                hstart[j] = 1;
+                any = true;
+            }
+            if (!any) return false;
+            RR_HIP(hipMemcpyAsync(Bt.start.ptr(), hstart.data(), m * sizeof(int32_t), hipMemcpyHostToDevice, st));
+            RR_HIP(hipMemcpyAsync(Bt.target2.ptr(), htarget.data(), m * sizeof(double), hipMemcpyHostToDevice, st));
+            // new cycle for the started columns: r = T, z = P r, rho = r^T z, p = z
+            launch_copy_flagged(n, m, Bt.T.as<double>(), n, Bt.R.as<double>(), n, Bt.start.as<int32_t>(), st);
+            Bt.precond(Bt.T.as<double>(), Bt.Z.as<double>());
+            launch_coldot(n, m, Bt.T.as<double>(), n, Bt.Z.as<double>(), n, Bt.parts.as<double>(), st);
+            launch_bstate_start(Bt.parts.as<double>(), Bt.nch, m, Bt.state.as<BState>(), Bt.start.as<int32_t>(),
+                                Bt.target2.as<double>(), o->maxit, st);
+            launch_copy_flagged(n, m, Bt.Z.as<double>(), n, Bt.Pm.as<double>(), n, Bt.start.as<int32_t>(), st);
+            RR_HIP(hipGetLastError());
+            return true;
+        };
+
+        // iteration counters live in the device state; seed them
+        for (int64_t j = 0; j < m; ++j) { hs[j] = BState{}; hs[j].iters = 0; }
+        RR_HIP(hipMemcpyAsync(Bt.state.ptr(), hs.data(), m * sizeof(BState), hipMemcpyHostToDevice, st));
+        bool running = restart_pass();
+        while (running) {
+            for (int k = 0; k < o->check_every; ++k) Bt.iteration(X, ldx);
+            RR_HIP(hipGetLastError());
+            RR_HIP(hipMemcpyAsync(hs.data(), Bt.state.ptr(), m * sizeof(BState), hipMemcpyDeviceToHost, st));
+            RR_HIP(hipStreamSynchronize(st));
+            int active = 0, need = 0;
+            for (int64_t j = 0; j < m; ++j) {
+                if (done[j]) continue;
+                iters[j] = hs[j].iters;
+                if (hs[j].run) { ++active; continue; }
+                if (hs[j].code == STOP_BREAKDOWN) { done[j] = 1; status[j] = RR_EBREAKDOWN; continue; }
+                if (!pending[j]) { pending[j] = 1; ++need; }
+            }
+            if (need > 0) {
+                const bool started = restart_pass();
+                if (!started && active == 0) break;
+            } else if (active == 0) {
+                break;
+            }
+        }
+        const double t_solve = now_ms() - t0;
+        std::vector<double> rel64(m, std::nan(""));
+        if (o->certify) {
+            Bt.matmat(X, ldx, Bt.T.as<double>(), true);
+            launch_bresid(n, m, B, ldb, Bt.T.as<double>(), Bt.T.as<double>(), st);
+            const std::vector<double> rr = Bt.coldots(Bt.T.as<double>(), n, Bt.T.as<double>(), n);
+            for (int64_t j = 0; j < m; ++j) rel64[j] = nb[j] > 0 ? std::sqrt(rr[j]) / nb[j] : 0.0;
+        }
+        rr_status first = RR_OK;
+        for (int64_t j = 0; j < m; ++j) {
+            if (!done[j]) status[j] = RR_ENOCONV;
+            if (status[j] != RR_OK && first == RR_OK) first = (rr_status)status[j];
+            if (infos) {
+                rr_solve_info& inf = infos[j];
+                const PerMu& pm = P.per[mu_index_per_col[j]];
+                inf.iters = iters[j];
+                inf.restarts = std::max(cycles[j] - 1, 0);
+                inf.relres_work = relres[j];
+                inf.relres_fp64 = rel64[j];
+                inf.tau = pm.tau; inf.normE = pm.normE; inf.lamhat = pm.lam;
+                inf.orth_err = P.orth_err;
+                inf.ms_build = P.ms_build;
+                inf.ms_solve = t_solve;
+                inf.status = status[j];
+            }
+        }
+        if (first != RR_OK) set_error("at least one column did not converge (see infos)");
+        return first;
+    });
 }

@@ -22,6 +22,15 @@ struct CgState {
 };
 enum { STOP_NONE = 0, STOP_TARGET = 1, STOP_BREAKDOWN = 2, STOP_MAXIT = 3 };
 
+// Per-column state of the batched solve (one PCG recurrence per column).
+struct BState {
+    double alpha, beta, rho, rr, pw, target2;
+    int32_t run;      // 1 while the column iterates in the current cycle
+    int32_t code;     // STOP_* reason the column left the cycle
+    int32_t iters;
+    int32_t maxit;
+};
+
 // ----------------------------------------------------------- random matrices
 void launch_gauss_fill(void* out, int dtype, int64_t rows, int64_t cols, int64_t ld,
                        uint64_t seed, hipStream_t st);
@@ -117,6 +126,32 @@ void launch_kernel_gemm_f64(const KernelOp& op, const double* B, int64_t ldb, in
 // Dense bf16 GEMM on MFMA: Y(float32, n x m) = A(bf16, n x n) * B(bf16, n x m) + mu*Bf
 void launch_dense_gemm_bf16(int64_t n, int64_t m, const void* A, int64_t lda, const void* B,
                             int64_t ldb, double mu, float* Y, int64_t ldy, hipStream_t st);
+
+// ------------------------------------------------------------ batched solve
+// W = scale*K P + diag(mucol) P for m columns on float64 MFMA; entries in float32
+// (the same values as the single-vector matvec) or, with f64_entries, float64.
+void launch_kernel_matmat_f64(const KernelOp& op, bool f64_entries, const double* mucol,
+                              const double* P, int64_t ldp, int64_t m, double* W, int64_t ldw,
+                              hipStream_t st);
+void launch_add_shift_cols(int64_t n, int64_t m, const double* mucol, const double* P, int64_t ldp,
+                           double* W, int64_t ldw, hipStream_t st);
+int coldot_chunks(int64_t n);
+void launch_coldot(int64_t n, int64_t m, const double* A, int64_t lda, const double* B, int64_t ldb,
+                   double* part, hipStream_t st);
+void launch_bscal_alpha(const double* part, int nch, int64_t m, BState* st, hipStream_t s);
+void launch_bscal_rr(const double* part, int nch, int64_t m, BState* st, hipStream_t s);
+void launch_bscal_beta(const double* part, int nch, int64_t m, BState* st, hipStream_t s);
+void launch_bstate_start(const double* part, int nch, int64_t m, BState* st, const int32_t* start,
+                         const double* target2, int32_t maxit, hipStream_t s);
+void launch_bxr(int64_t n, int64_t m, double* X, int64_t ldx, double* R, const double* P,
+                const double* W, const BState* st, hipStream_t s);
+void launch_bp(int64_t n, int64_t m, const double* Z, double* P, const BState* st, hipStream_t s);
+void launch_copy_flagged(int64_t n, int64_t m, const double* src, int64_t lds, double* dst,
+                         int64_t ldd, const int32_t* flag, hipStream_t s);
+void launch_bresid(int64_t n, int64_t m, const double* B, int64_t ldb, const double* T, double* Rt,
+                   hipStream_t s);
+void launch_select_cols(int64_t k, int64_t m, const double* Dall, const int32_t* mu_idx, double* D,
+                        hipStream_t s);
 
 // ------------------------------------------------------ projections (K7, K8)
 // c_part[chunk * k + j] = sum_{i in chunk} Q[i, j] r[i]; returns number of chunks.

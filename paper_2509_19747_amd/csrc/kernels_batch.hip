@@ -1,0 +1,361 @@
+// Kernels of the batched solve: many independent PCG recurrences (one per
+// column, each with its own shift mu_j) advanced by fused launches.
+//
+//  * k_kgemm_f64_mfma : W = scale * K P + diag(mu_col) P for m columns at once.
+//      The kernel entries are the same float32 values as the single-vector
+//      matvec (bitwise: same formula, same order), widened to float64 and
+//      multiplied on v_mfma_f64_16x16x4_f64 with float64 accumulation, so every
+//      column sees the same operator to float64 rounding.
+//  * per-column dot partials, scalar steps and vector updates with a per-column
+//      run flag: converged or restarting columns are left untouched.
+#include "common.hpp"
+#include "kernels.hpp"
+#include "prof.hpp"
+
+namespace rr {
+
+constexpr float LOG2E_FB = 1.4426950408889634f;
+
+// float32 kernel entry, identical to the single-vector matvec's
+template <int KIND>
+RR_DEV float kval32b(float s, float c) {
+    if (KIND == 1) return __builtin_amdgcn_exp2f(c * fminf(s, 0.0f));
+    const float t = c * __builtin_sqrtf(fmaxf(-2.0f * s, 0.0f));
+    return (1.0f + t) * __builtin_amdgcn_exp2f(-t * LOG2E_FB);
+}
+
+template <int KIND>
+RR_DEV double kval64b(double r2, double kconst) {
+    r2 = r2 > 0.0 ? r2 : 0.0;
+    if (KIND == 1) return exp(-kconst * r2);
+    const double t = kconst * sqrt(r2);
+    return (1.0 + t) * exp(-t);
+}
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+constexpr int KD_BM = 256, KD_BN = 128, KD_BK = 16, KD_THREADS = 512;
+
+// Block: 8 waves in a 4 (rows) x 2 (columns) grid of 64 x 64 wave tiles.
+// Per step of 16 points the block forms the 256 x 16 kernel tile (thread: one
+// row, 8 points) into LDS (k-major) and stages the 16 x 128 slice of P.
+// F64E: entries in float64 (difference form, float64 exp) instead of float32.
+template <int KIND, int D, bool F64E>
+__global__ __launch_bounds__(KD_THREADS) void k_kgemm_f64_mfma(
+    int64_t n, int dd, const float* __restrict__ pts, const float* __restrict__ sqn, float c,
+    double kconst, double scale, const double* __restrict__ mucol, const double* __restrict__ P, int64_t ldp,
+    int64_t m, double* __restrict__ W, int64_t ldw) {
+    constexpr int DM = D > 0 ? D : 32;
+    const int d = D > 0 ? D : dd;
+    __shared__ double As[KD_BK][KD_BM + 2];
+    __shared__ double Bs[KD_BK][KD_BN + 2];
+    const int t = threadIdx.x;
+    const int lane = t & 63, wave = t >> 6;
+    const int wm = wave & 3, wn = wave >> 2;
+    const int64_t i0 = (int64_t)blockIdx.x * KD_BM;
+    const int64_t c0 = (int64_t)blockIdx.y * KD_BN;
+
+    const int trow = t & (KD_BM - 1);
+    const int pg = __builtin_amdgcn_readfirstlane(t >> 8);   // 0/1: which 8 of the 16 points
+    const int64_t gi = i0 + trow;
+    const int64_t gic = gi < n ? gi : n - 1;
+    float xi[DM];
+#pragma unroll
+    for (int k = 0; k < DM; ++k) xi[k] = (k < d) ? pts[(int64_t)k * n + gic] : 0.0f;
+    const float mhn = -0.5f * sqn[gic];
+
+    f64x4 acc[4][4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[u][v] = f64x4{0.0, 0.0, 0.0, 0.0};
+
+    for (int64_t j0 = 0; j0 < n; j0 += KD_BK) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int p = pg * 8 + e;
+            const int64_t gj = j0 + p;
+            const int64_t gjc = gj < n ? gj : n - 1;
+            double kv;
+            if (F64E) {
+                double r2 = 0.0;
+#pragma unroll
+                for (int k = 0; k < DM; ++k)
+                    if (k < d) {
+                        const double df = (double)xi[k] - (double)pts[(int64_t)k * n + gjc];
+                        r2 = fma(df, df, r2);
+                    }
+                kv = kval64b<KIND>(r2, kconst);
+            } else {
+                float sv = fmaf(-0.5f, sqn[gjc], mhn);
+#pragma unroll
+                for (int k = 0; k < DM; ++k)
+                    if (k < d) sv = fmaf(xi[k], pts[(int64_t)k * n + gjc], sv);
+                kv = (double)kval32b<KIND>(sv, c);
+            }
+            As[p][trow] = (gj < n) ? kv : 0.0;
+        }
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int k = t & 15;
+            const int col = (t >> 4) + 32 * s;
+            const int64_t gj = j0 + k, gc = c0 + col;
+            Bs[k][col] = (gj < n && gc < m) ? P[gj + gc * ldp] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kc = 0; kc < KD_BK; kc += 4) {
+            double a[4], b[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) a[u] = As[kc + (lane >> 4)][wm * 64 + u * 16 + (lane & 15)];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) b[v] = Bs[kc + (lane >> 4)][wn * 64 + v * 16 + (lane & 15)];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    acc[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b[v], acc[u][v], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int64_t gc = c0 + wn * 64 + v * 16 + (lane & 15);
+            if (gc >= m) continue;
+            const double mu = mucol[gc];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int64_t gr = i0 + wm * 64 + u * 16 + 4 * (lane >> 4) + e;
+                if (gr < n) W[gr + gc * ldw] = fma(scale, acc[u][v][e], mu * P[gr + gc * ldp]);
+            }
+        }
+    }
+}
+
+static float c_for_b(int kind, double kconst) {
+    return kind == 1 ? (float)(2.0 * kconst * 1.4426950408889634074) : (float)kconst;
+}
+
+template <int KIND, bool F64E>
+static void kd_dispatch(const KernelOp& op, float c, const double* mucol, const double* P,
+                        int64_t ldp, int64_t m, double* W, int64_t ldw, hipStream_t st) {
+    dim3 grid((unsigned)((op.n + KD_BM - 1) / KD_BM), (unsigned)((m + KD_BN - 1) / KD_BN));
+#define KDL(DD) k_kgemm_f64_mfma<KIND, DD, F64E><<<grid, KD_THREADS, 0, st>>>(op.n, op.d, op.pts, op.sqn, c, op.kconst, op.scale, mucol, P, ldp, m, W, ldw)
+    switch (op.d) {
+        case 3: KDL(3); break;
+        case 4: KDL(4); break;
+        case 8: KDL(8); break;
+        case 16: KDL(16); break;
+        default: KDL(0); break;
+    }
+#undef KDL
+}
+
+void launch_kernel_matmat_f64(const KernelOp& op, bool f64_entries, const double* mucol,
+                              const double* P, int64_t ldp, int64_t m, double* W, int64_t ldw,
+                              hipStream_t st) {
+    const float c = c_for_b(op.kind, op.kconst);
+    ProfScope prof(f64_entries ? -1 : PROF_KERNEL_MATMAT, st);
+    if (op.kind == 1) {
+        if (f64_entries) kd_dispatch<1, true>(op, c, mucol, P, ldp, m, W, ldw, st);
+        else kd_dispatch<1, false>(op, c, mucol, P, ldp, m, W, ldw, st);
+    } else {
+        if (f64_entries) kd_dispatch<2, true>(op, c, mucol, P, ldp, m, W, ldw, st);
+        else kd_dispatch<2, false>(op, c, mucol, P, ldp, m, W, ldw, st);
+    }
+}
+
+// W[:, j] += mu_j P[:, j] for a dense operator product computed by the GEMM.
+__global__ void k_add_shift_cols(int64_t n, int64_t m, const double* __restrict__ mucol,
+                                 const double* __restrict__ P, int64_t ldp, double* __restrict__ W,
+                                 int64_t ldw) {
+    const int64_t total = n * m;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = e % n, j = e / n;
+        W[i + j * ldw] = fma(mucol[j], P[i + j * ldp], W[i + j * ldw]);
+    }
+}
+void launch_add_shift_cols(int64_t n, int64_t m, const double* mucol, const double* P, int64_t ldp,
+                           double* W, int64_t ldw, hipStream_t st) {
+    int64_t g = (n * m + 255) / 256;
+    if (g > 65536) g = 65536;
+    k_add_shift_cols<<<(int)g, 256, 0, st>>>(n, m, mucol, P, ldp, W, ldw);
+}
+
+// =========================================================== per-column CG
+constexpr int BC_THREADS = 256;
+
+int coldot_chunks(int64_t n) {
+    int64_t c = (n + 8191) / 8192;
+    if (c < 1) c = 1;
+    if (c > 32) c = 32;
+    return (int)c;
+}
+
+// part[ch * m + j] = sum_{i in chunk ch} A[i, j] B[i, j]
+__global__ __launch_bounds__(BC_THREADS) void k_coldot(int64_t n, int64_t m,
+                                                      const double* __restrict__ A, int64_t lda,
+                                                      const double* __restrict__ B, int64_t ldb,
+                                                      double* __restrict__ part, int64_t rpc) {
+    __shared__ double sc[BC_THREADS / WAVE];
+    const int64_t j = blockIdx.x, ch = blockIdx.y;
+    const int64_t ib = ch * rpc;
+    const int64_t ie = (ib + rpc < n) ? ib + rpc : n;
+    double acc = 0.0;
+    for (int64_t i = ib + threadIdx.x; i < ie; i += BC_THREADS) acc = fma(A[i + j * lda], B[i + j * ldb], acc);
+    acc = block_sum(acc, sc);
+    if (threadIdx.x == 0) part[ch * m + j] = acc;
+}
+void launch_coldot(int64_t n, int64_t m, const double* A, int64_t lda, const double* B, int64_t ldb,
+                   double* part, hipStream_t st) {
+    const int nch = coldot_chunks(n);
+    const int64_t rpc = (n + nch - 1) / nch;
+    dim3 grid((unsigned)m, (unsigned)nch);
+    k_coldot<<<grid, BC_THREADS, 0, st>>>(n, m, A, lda, B, ldb, part, rpc);
+}
+
+RR_DEV double colsum(const double* part, int nch, int64_t m, int64_t j) {
+    double s = 0.0;
+    for (int c = 0; c < nch; ++c) s += part[(int64_t)c * m + j];
+    return s;
+}
+
+__global__ void k_bscal_alpha(const double* __restrict__ part, int nch, int64_t m, BState* st) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= m || !st[j].run) return;
+    const double pw = colsum(part, nch, m, j);
+    st[j].pw = pw;
+    if (!(pw > 0.0) || !isfinite(pw)) {
+        st[j].run = 0;
+        st[j].code = STOP_BREAKDOWN;
+    } else {
+        st[j].alpha = st[j].rho / pw;
+    }
+}
+__global__ void k_bscal_rr(const double* __restrict__ part, int nch, int64_t m, BState* st) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= m || !st[j].run) return;
+    const double rr = colsum(part, nch, m, j);
+    st[j].rr = rr;
+    const int it = st[j].iters + 1;
+    st[j].iters = it;
+    if (!isfinite(rr)) { st[j].run = 0; st[j].code = STOP_BREAKDOWN; }
+    else if (rr <= st[j].target2) { st[j].run = 0; st[j].code = STOP_TARGET; }
+    else if (it >= st[j].maxit) { st[j].run = 0; st[j].code = STOP_MAXIT; }
+}
+__global__ void k_bscal_beta(const double* __restrict__ part, int nch, int64_t m, BState* st) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= m || !st[j].run) return;
+    const double rz = colsum(part, nch, m, j);
+    if (!(rz > 0.0) || !isfinite(rz)) { st[j].run = 0; st[j].code = STOP_BREAKDOWN; return; }
+    st[j].beta = rz / st[j].rho;
+    st[j].rho = rz;
+}
+// start a cycle for the columns flagged in `start`: rho = r^T z, run = 1
+__global__ void k_bstate_start(const double* __restrict__ part, int nch, int64_t m, BState* st,
+                               const int32_t* __restrict__ start, const double* __restrict__ target2,
+                               int32_t maxit) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= m || !start[j]) return;
+    const double rz = colsum(part, nch, m, j);
+    st[j].rho = rz;
+    st[j].alpha = st[j].beta = 0.0;
+    st[j].target2 = target2[j];
+    st[j].maxit = maxit;
+    st[j].code = STOP_NONE;
+    st[j].run = 1;
+    if (!(rz > 0.0) || !isfinite(rz)) { st[j].run = 0; st[j].code = STOP_BREAKDOWN; }
+}
+static int cgrid(int64_t m) { return (int)((m + 255) / 256); }
+void launch_bscal_alpha(const double* part, int nch, int64_t m, BState* st, hipStream_t s) { k_bscal_alpha<<<cgrid(m), 256, 0, s>>>(part, nch, m, st); }
+void launch_bscal_rr(const double* part, int nch, int64_t m, BState* st, hipStream_t s) { k_bscal_rr<<<cgrid(m), 256, 0, s>>>(part, nch, m, st); }
+void launch_bscal_beta(const double* part, int nch, int64_t m, BState* st, hipStream_t s) { k_bscal_beta<<<cgrid(m), 256, 0, s>>>(part, nch, m, st); }
+void launch_bstate_start(const double* part, int nch, int64_t m, BState* st, const int32_t* start,
+                         const double* target2, int32_t maxit, hipStream_t s) {
+    k_bstate_start<<<cgrid(m), 256, 0, s>>>(part, nch, m, st, start, target2, maxit);
+}
+
+// column blocks: grid (row chunks, m); the column's run flag is uniform per block
+__global__ __launch_bounds__(BC_THREADS) void k_bxr(int64_t n, double* __restrict__ X, int64_t ldx,
+                                                   double* __restrict__ R, const double* __restrict__ P,
+                                                   const double* __restrict__ W, const BState* st) {
+    const int64_t j = blockIdx.y;
+    if (!st[j].run) return;
+    const double a = st[j].alpha;
+    for (int64_t i = (int64_t)blockIdx.x * BC_THREADS + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * BC_THREADS) {
+        X[i + j * ldx] = fma(a, P[i + j * n], X[i + j * ldx]);
+        R[i + j * n] = fma(-a, W[i + j * n], R[i + j * n]);
+    }
+}
+__global__ __launch_bounds__(BC_THREADS) void k_bp(int64_t n, const double* __restrict__ Z,
+                                                  double* __restrict__ P, const BState* st) {
+    const int64_t j = blockIdx.y;
+    if (!st[j].run) return;
+    const double b = st[j].beta;
+    for (int64_t i = (int64_t)blockIdx.x * BC_THREADS + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * BC_THREADS)
+        P[i + j * n] = fma(b, P[i + j * n], Z[i + j * n]);
+}
+static dim3 vgrid(int64_t n, int64_t m) {
+    int64_t gx = (n + BC_THREADS * 8 - 1) / (BC_THREADS * 8);
+    if (gx < 1) gx = 1;
+    return dim3((unsigned)gx, (unsigned)m);
+}
+void launch_bxr(int64_t n, int64_t m, double* X, int64_t ldx, double* R, const double* P,
+                const double* W, const BState* st, hipStream_t s) {
+    k_bxr<<<vgrid(n, m), BC_THREADS, 0, s>>>(n, X, ldx, R, P, W, st);
+}
+void launch_bp(int64_t n, int64_t m, const double* Z, double* P, const BState* st, hipStream_t s) {
+    k_bp<<<vgrid(n, m), BC_THREADS, 0, s>>>(n, Z, P, st);
+}
+
+// For flagged columns: dst[:, j] = src[:, j]
+__global__ __launch_bounds__(BC_THREADS) void k_copy_flagged(int64_t n, const double* __restrict__ src,
+                                                            int64_t lds, double* __restrict__ dst,
+                                                            int64_t ldd, const int32_t* __restrict__ flag) {
+    const int64_t j = blockIdx.y;
+    if (!flag[j]) return;
+    for (int64_t i = (int64_t)blockIdx.x * BC_THREADS + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * BC_THREADS)
+        dst[i + j * ldd] = src[i + j * lds];
+}
+void launch_copy_flagged(int64_t n, int64_t m, const double* src, int64_t lds, double* dst,
+                         int64_t ldd, const int32_t* flag, hipStream_t s) {
+    k_copy_flagged<<<vgrid(n, m), BC_THREADS, 0, s>>>(n, src, lds, dst, ldd, flag);
+}
+
+// R = B - T (all columns), used for true residuals
+__global__ __launch_bounds__(BC_THREADS) void k_bresid(int64_t n, const double* __restrict__ B,
+                                                      int64_t ldb, const double* __restrict__ T,
+                                                      double* __restrict__ Rt) {
+    const int64_t j = blockIdx.y;
+    for (int64_t i = (int64_t)blockIdx.x * BC_THREADS + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * BC_THREADS)
+        Rt[i + j * n] = B[i + j * ldb] - T[i + j * n];
+}
+void launch_bresid(int64_t n, int64_t m, const double* B, int64_t ldb, const double* T, double* Rt,
+                   hipStream_t s) {
+    k_bresid<<<vgrid(n, m), BC_THREADS, 0, s>>>(n, B, ldb, T, Rt);
+}
+
+// D[:, j] = Dall[mu_idx[j]][:, j]  (per-column choice among the per-shift cores)
+__global__ void k_select_cols(int64_t k, int64_t m, const double* __restrict__ Dall,
+                              const int32_t* __restrict__ mu_idx, double* __restrict__ D) {
+    const int64_t total = k * m;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = e % k, j = e / k;
+        D[i + j * k] = Dall[(int64_t)mu_idx[j] * k * m + i + j * k];
+    }
+}
+void launch_select_cols(int64_t k, int64_t m, const double* Dall, const int32_t* mu_idx, double* D,
+                        hipStream_t s) {
+    int64_t g = (k * m + 255) / 256;
+    if (g > 65536) g = 65536;
+    k_select_cols<<<(int)g, 256, 0, s>>>(k, m, Dall, mu_idx, D);
+}
+
+}  // namespace rr

@@ -308,3 +308,54 @@ def test_kernel_fp32_bf16_sketch_basis(n, l, sketch):
     assert info["rc"] == rr.RR_OK
     ref = osol.pcg(op.shifted(mu), o.apply, prob.b, 1e-6)
     assert abs(info["iters"] - ref.iters) <= max(3, int(0.1 * ref.iters))
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_batched_multi_shift_matches_single_and_oracle(prec):
+    # every RHS under every shift (joint basis), one fused batched solve, compared with
+    # the single-column solve of the same column and with the float64 oracle
+    prob = workloads.cfg_batched(n=2500, d=16, l=60, nrhs=3)
+    op = Operator.from_problem(prob)
+    kop = rr.kernel_operator(rr.OP_RBF, _cuda(prob.pts), prob.kconst, prob.scale)
+    P = rr.build_precond(kop, prob.mus, l=prob.l, sketch="srht", seed=prob.omega_seed, prec=prec)
+    k = prob.B.shape[1]
+    mus_idx = [j for j in range(len(prob.mus)) for _ in range(k)]
+    B = np.concatenate([prob.B] * len(prob.mus), axis=1)
+    tol = 1e-6
+    X, infos, st = P.solve_batch(_cuda(B), mus_idx, tol=tol, check_every=4)
+    X = X.cpu().numpy()
+    assert st == rr.RR_OK
+    for c, j in enumerate(mus_idx):
+        mu = prob.mus[j]
+        assert infos[c]["status"] == rr.RR_OK
+        rel64 = osol.relres(op.shifted(mu), X[:, c], B[:, c])
+        assert abs(infos[c]["relres_fp64"] - rel64) <= 1e-6 * rel64 + 1e-14
+        x1, i1 = P.solve(_cuda(B[:, c]), mu_index=j, tol=tol)
+        assert abs(i1["iters"] - infos[c]["iters"]) <= 2
+        if prec == "fp64":
+            assert rel64 <= tol * 1.0001
+        else:
+            dA = prob.n * 2.0 ** -23 * prob.scale
+            assert rel64 <= tol + dA * np.linalg.norm(X[:, c]) / np.linalg.norm(B[:, c])
+        xs = x1.cpu().numpy()
+        assert np.linalg.norm(xs - X[:, c]) <= 50 * tol / mu * np.linalg.norm(B[:, c]) * prob.scale * 0 + \
+            np.linalg.norm(xs) * 1e-3 + 1e-12
+    # the same column alone in a batch of one and inside the full batch
+    X1, inf1, _ = P.solve_batch(_cuda(B[:, 5:6]), [mus_idx[5]], tol=tol, check_every=4)
+    assert inf1[0]["iters"] == infos[5]["iters"]
+    assert np.allclose(X1.cpu().numpy()[:, 0], X[:, 5], rtol=0, atol=1e-9 * np.abs(X[:, 5]).max())
+
+
+def test_batched_dense_operator():
+    prob = workloads.cfg_small_dense(n=900, d=8, l=30)
+    kop = rr.kernel_operator(rr.OP_RBF, _cuda(prob.pts), prob.kconst, 1.0)
+    A = rr.kernel_to_dense(kop, "fp64")
+    op = Operator.from_problem(prob)
+    mus = [1e-2, 1e-3]
+    P = rr.build_precond(rr.dense_operator(A), mus, l=30, seed=3)
+    B = np.random.default_rng(7).standard_normal((prob.n, 4))
+    X, infos, st = P.solve_batch(_cuda(B), [0, 1, 0, 1], tol=1e-9)
+    X = X.cpu().numpy()
+    assert st == rr.RR_OK
+    for c in range(4):
+        assert osol.relres(op.shifted(mus[c % 2]), X[:, c], B[:, c]) <= 1e-9 * 1.0001
