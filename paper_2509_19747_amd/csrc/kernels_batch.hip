@@ -124,9 +124,11 @@ __global__ __launch_bounds__(KD_THREADS) void k_kgemm_f64_mfma(
             const int64_t gc = c0 + wn * 64 + v * 16 + (lane & 15);
             if (gc >= m) continue;
             const double mu = mucol[gc];
+            // v_mfma_f64_16x16x4_f64 result layout: element e of lane l is row 4*e + l/16,
+            // column l%16 (unlike the f32 16x16x4 form, whose rows are 4*(l/16) + e)
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const int64_t gr = i0 + wm * 64 + u * 16 + 4 * (lane >> 4) + e;
+                const int64_t gr = i0 + wm * 64 + u * 16 + 4 * e + (lane >> 4);
                 if (gr < n) W[gr + gc * ldw] = fma(scale, acc[u][v][e], mu * P[gr + gc * ldp]);
             }
         }
