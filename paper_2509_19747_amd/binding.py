@@ -365,3 +365,67 @@ def sketch(op: Operator, mu: float, l: int, stream=None, **kw):
     _check(lib().rr_sketch_apply(C.byref(op.struct), float(mu), C.byref(o), _ptr(out),
                                  _stream(stream)), "rr_sketch_apply")
     return out.t()
+
+
+def serve(requests, hbm_budget: int = 96 << 30, max_slots: int = 8, graph_iters: int = 8,
+          build: Optional[dict] = None, solve: Optional[dict] = None):
+    """Run the continuous-batching server over `requests` (arrival-ordered).
+
+    Each request is a dict with keys: kind, pts (float32 (d, n) host array), kconst,
+    scale, mu, l, seed, B (float64 (n, m) host array), t_arrival (seconds after the
+    start).  Returns (results, stats): results[i] = {"X": (n, m) array, "info": dict,
+    "t_done": float}.
+    """
+    bo = build_opts(**(build or {}))
+    so = solve_opts(**(solve or {}))
+    cfg = rr_serve_config(hbm_budget=int(hbm_budget), max_slots=int(max_slots),
+                          graph_iters=int(graph_iters), build=bo, solve=so)
+    keep = []
+    for i, r in enumerate(requests):
+        pts = np.ascontiguousarray(r["pts"], dtype=np.float32)
+        B = np.asarray(r["B"], dtype=np.float64)
+        if B.ndim == 1:
+            B = B[:, None]
+        Bc = np.ascontiguousarray(B.T)            # column-major n x m
+        Xc = np.zeros_like(Bc)
+        keep.append((pts, Bc, Xc))
+    state = {"i": 0}
+    results = [None] * len(requests)
+
+    def _next(user, now, out):
+        i = state["i"]
+        if i >= len(requests):
+            return -1
+        r = requests[i]
+        if r["t_arrival"] > now:
+            return 0
+        pts, Bc, Xc = keep[i]
+        o = out.contents
+        o.kind = int(r.get("kind", OP_RBF))
+        o.n = pts.shape[1]
+        o.d = pts.shape[0]
+        o.pts = pts.ctypes.data
+        o.kconst = float(r["kconst"])
+        o.scale = float(r["scale"])
+        o.mu = float(r["mu"])
+        o.l = int(r["l"])
+        o.nrhs = Bc.shape[0]
+        o.B = Bc.ctypes.data
+        o.X = Xc.ctypes.data
+        o.id = i
+        o.seed = int(r.get("seed", 0))
+        o.t_arrival = float(r["t_arrival"])
+        state["i"] = i + 1
+        return 1
+
+    def _deliver(user, req, info, t_done):
+        i = int(req.contents.id)
+        results[i] = {"info": info.contents.as_dict(), "t_done": float(t_done)}
+
+    nf, df = NEXT_FN(_next), DELIVER_FN(_deliver)
+    stats = rr_serve_stats()
+    _check(lib().rr_serve(C.byref(cfg), nf, df, None, C.byref(stats)), "rr_serve")
+    for i, (pts, Bc, Xc) in enumerate(keep):
+        if results[i] is not None:
+            results[i]["X"] = Xc.T.copy()
+    return results, stats.as_dict()

@@ -1,11 +1,282 @@
-// Continuous-batching serving loop (placeholder until the server lands).
+// rr_serve: continuous-batching server for independent kernel ridge solves.
+//
+// One host loop polls next() for arrivals, queues them in FIFO order and admits
+// the head of the queue as soon as a slot is free and its device-memory estimate
+// fits in the remaining HBM budget (a request larger than the whole budget is
+// rejected).  Each slot is a worker thread with its own HIP stream: it uploads
+// the request, builds the request's C-RandRAND preconditioner, keeps it resident
+// while it solves each right-hand side (PCG batches replayed as captured
+// hipGraphs), copies X back to the host, frees everything and calls deliver().
+// Requests admitted while others run execute concurrently on their own streams.
+// A request's arithmetic depends only on the request (own handle, own stream,
+// fixed-order reductions), so its result is the same alone and in the mix.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <mutex>
+#include <thread>
+#include <vector>
+
 #include "ctx.hpp"
 
 using namespace rr;
 
+namespace {
+
+double wall_s() {
+    using namespace std::chrono;
+    return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+// Device bytes one request holds at its peak (build temporaries included).
+size_t request_bytes(const rr_request& r) {
+    const double n = (double)r.n, l = (double)r.l, d = (double)r.d, m = (double)std::max(r.nrhs, 1);
+    double b = n * l * (4 + 2 + 8 + 4 + 8 + 16);        // Omega f32/bf16, Q, Y, W, Theta
+    b += n * d * 4 + n * 4;                              // points, |x|^2
+    b += l * l * 8 * 26 + 4.0 * (2 * l) * (2 * l) * 8;   // l x l factors, GEMM workspace
+    b += 2.0 * 256 * n * 8;                              // matvec slice partials (upper bound)
+    b += n * 8 * (8 + 2 * m);                            // CG vectors, B and X columns
+    b += 64.0 * 1024 * 1024;                             // fixed slack
+    return (size_t)b;
+}
+
+// Stream-ordered allocation, so that one request's frees never wait for the others.
+void* async_alloc(void*, size_t bytes, void* stream) {
+    void* p = nullptr;
+    if (hipMallocAsync(&p, bytes, (hipStream_t)stream) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    return p;
+}
+void async_free(void*, void* p, void* stream) { (void)hipFreeAsync(p, (hipStream_t)stream); }
+
+struct Job {
+    rr_request req;
+    size_t bytes;
+};
+
+struct Shared {
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<Job> admitted;
+    bool stop = false;
+    size_t used = 0, peak = 0;
+    int active = 0, max_active = 0;
+    std::vector<double> lat_ms;
+    int64_t served = 0, rejected = 0;
+    std::mutex deliver_mu;
+    rr_status first_err = RR_OK;
+};
+
+void run_job(const rr_serve_config& cfg, Job& job, hipStream_t st, double t0, rr_deliver_fn deliver,
+             void* user, Shared& sh) {
+    rr_request& r = job.req;
+    rr_solve_info info{};
+    info.status = RR_OK;
+    rr_precond* P = nullptr;
+    float* pts = nullptr;
+    double *b = nullptr, *x = nullptr;
+    const int64_t n = r.n;
+    auto fail = [&](rr_status s) { info.status = s; };
+    rr_allocator alloc{nullptr, async_alloc, async_free};
+    do {
+        if (hipMallocAsync((void**)&pts, (size_t)r.d * n * sizeof(float), st) != hipSuccess ||
+            hipMallocAsync((void**)&b, (size_t)n * sizeof(double), st) != hipSuccess ||
+            hipMallocAsync((void**)&x, (size_t)n * sizeof(double), st) != hipSuccess) {
+            (void)hipGetLastError();
+            fail(RR_ENOMEM);
+            break;
+        }
+        if (hipMemcpyAsync(pts, r.pts, (size_t)r.d * n * sizeof(float), hipMemcpyHostToDevice, st) != hipSuccess) {
+            fail(RR_EDEVICE);
+            break;
+        }
+        rr_operator op{};
+        op.kind = r.kind;
+        op.n = n;
+        op.pts = pts;
+        op.d = r.d;
+        op.kconst = r.kconst;
+        op.scale = r.scale;
+        rr_build_opts bo = cfg.build;
+        bo.l = r.l;
+        bo.seed = r.seed;
+        const double mu = r.mu;
+        rr_status s = rr_build_precond(&op, &mu, 1, &bo, &alloc, st, &P);
+        if (s != RR_OK) { fail(s); break; }
+        rr_solve_opts so = cfg.solve;
+        if (cfg.graph_iters > 0) {
+            so.use_graph = 1;
+            so.check_every = cfg.graph_iters;
+        }
+        so.relres_history = nullptr;
+        so.history_cap = 0;
+        int iters = 0;
+        double worst = 0.0, worst64 = 0.0;
+        for (int j = 0; j < r.nrhs; ++j) {
+            if (hipMemcpyAsync(b, r.B + (size_t)j * n, (size_t)n * sizeof(double), hipMemcpyHostToDevice, st) != hipSuccess ||
+                hipMemsetAsync(x, 0, (size_t)n * sizeof(double), st) != hipSuccess) {
+                s = RR_EDEVICE;
+                break;
+            }
+            rr_solve_info si{};
+            s = rr_solve(P, 0, b, x, &so, &si, st);
+            iters = std::max(iters, si.iters);
+            worst = std::max(worst, si.relres_work);
+            if (std::isfinite(si.relres_fp64)) worst64 = std::max(worst64, si.relres_fp64);
+            info.tau = si.tau; info.normE = si.normE; info.lamhat = si.lamhat; info.orth_err = si.orth_err;
+            info.ms_build = si.ms_build;
+            info.ms_solve += si.ms_solve;
+            if (hipMemcpyAsync(r.X + (size_t)j * n, x, (size_t)n * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
+                hipStreamSynchronize(st) != hipSuccess) {
+                s = RR_EDEVICE;
+                break;
+            }
+            if (s != RR_OK) break;
+        }
+        info.iters = iters;
+        info.relres_work = worst;
+        info.relres_fp64 = worst64;
+        if (s != RR_OK) fail(s);
+    } while (false);
+    (void)hipStreamSynchronize(st);
+    if (P) rr_precond_destroy(P);
+    if (pts) (void)hipFreeAsync(pts, st);
+    if (b) (void)hipFreeAsync(b, st);
+    if (x) (void)hipFreeAsync(x, st);
+    (void)hipStreamSynchronize(st);
+    const double t_done = wall_s() - t0;
+    {
+        std::lock_guard<std::mutex> lk(sh.deliver_mu);
+        deliver(user, &r, &info, t_done);
+    }
+    std::lock_guard<std::mutex> lk(sh.mu);
+    sh.used -= job.bytes;
+    sh.active -= 1;
+    sh.served += 1;
+    sh.lat_ms.push_back(1e3 * (t_done - r.t_arrival));
+    if (info.status != RR_OK && sh.first_err == RR_OK) sh.first_err = (rr_status)info.status;
+    sh.cv_done.notify_all();
+}
+
+}  // namespace
+
 extern "C" rr_status rr_serve(const rr_serve_config* cfg, rr_next_fn next, rr_deliver_fn deliver,
                               void* user, rr_serve_stats* stats) {
-    (void)cfg; (void)next; (void)deliver; (void)user; (void)stats;
-    set_error("rr_serve is not available in this build");
-    return RR_EINVAL;
+    return guarded([&]() -> rr_status {
+        RR_REQUIRE(cfg != nullptr, "config is null");
+        RR_REQUIRE(next != nullptr && deliver != nullptr, "callbacks are null");
+        RR_REQUIRE(cfg->max_slots >= 1 && cfg->max_slots <= 64, "max_slots must be in [1, 64]");
+        RR_REQUIRE(cfg->hbm_budget > 0, "hbm_budget must be > 0");
+        RR_REQUIRE(cfg->graph_iters >= 0 && cfg->graph_iters <= 4096, "graph_iters must be in [0, 4096]");
+        require_device();
+        int dev = 0;
+        RR_HIP(hipGetDevice(&dev));
+        Shared sh;
+        const double t0 = wall_s();
+        std::vector<std::thread> workers;
+        for (int w = 0; w < cfg->max_slots; ++w) {
+            workers.emplace_back([&, w]() {
+                (void)w;
+                (void)hipSetDevice(dev);
+                hipStream_t st = nullptr;
+                if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) st = nullptr;
+                while (true) {
+                    Job job;
+                    {
+                        std::unique_lock<std::mutex> lk(sh.mu);
+                        sh.cv_work.wait(lk, [&] { return sh.stop || !sh.admitted.empty(); });
+                        if (sh.admitted.empty()) break;
+                        job = sh.admitted.front();
+                        sh.admitted.pop_front();
+                    }
+                    run_job(*cfg, job, st, t0, deliver, user, sh);
+                }
+                if (st) (void)hipStreamDestroy(st);
+            });
+        }
+        std::deque<Job> pending;
+        bool ended = false;
+        rr_status loop_err = RR_OK;
+        while (true) {
+            const double now = wall_s() - t0;
+            if (!ended) {
+                while (true) {
+                    rr_request r{};
+                    const int32_t got = next(user, now, &r);
+                    if (got < 0) { ended = true; break; }
+                    if (got == 0) break;
+                    const bool valid = r.n >= 1 && r.d >= 1 && r.d <= 32 && r.pts && r.B && r.X &&
+                                       r.nrhs >= 1 && r.l >= 0 && r.l <= r.n && std::isfinite(r.mu) &&
+                                       r.mu >= 0.0 && (r.kind == RR_OP_RBF || r.kind == RR_OP_MATERN32);
+                    Job j{r, request_bytes(r)};
+                    if (!valid || j.bytes > cfg->hbm_budget) {
+                        rr_solve_info inf{};
+                        inf.status = valid ? RR_ENOMEM : RR_EINVAL;
+                        {
+                            std::lock_guard<std::mutex> lk(sh.deliver_mu);
+                            deliver(user, &r, &inf, wall_s() - t0);
+                        }
+                        std::lock_guard<std::mutex> lk(sh.mu);
+                        sh.rejected += 1;
+                        continue;
+                    }
+                    pending.push_back(j);
+                }
+            }
+            {
+                std::unique_lock<std::mutex> lk(sh.mu);
+                while (!pending.empty() && sh.active < cfg->max_slots &&
+                       sh.used + pending.front().bytes <= cfg->hbm_budget) {
+                    Job j = pending.front();
+                    pending.pop_front();
+                    sh.used += j.bytes;
+                    sh.peak = std::max(sh.peak, sh.used);
+                    sh.active += 1;
+                    sh.max_active = std::max(sh.max_active, sh.active);
+                    sh.admitted.push_back(j);
+                    sh.cv_work.notify_one();
+                }
+                if (ended && pending.empty() && sh.active == 0 && sh.admitted.empty()) break;
+                sh.cv_done.wait_for(lk, std::chrono::microseconds(200));
+            }
+        }
+        {
+            std::lock_guard<std::mutex> lk(sh.mu);
+            sh.stop = true;
+        }
+        sh.cv_work.notify_all();
+        for (auto& t : workers) t.join();
+        const double wall = wall_s() - t0;
+        if (stats) {
+            std::memset(stats, 0, sizeof(*stats));
+            std::vector<double> v = sh.lat_ms;
+            std::sort(v.begin(), v.end());
+            auto pct = [&](double p) {
+                if (v.empty()) return 0.0;
+                const size_t k = (size_t)std::min<double>(v.size() - 1, std::floor(p * (v.size() - 1) + 0.5));
+                return v[k];
+            };
+            stats->p50_ms = pct(0.50);
+            stats->p99_ms = pct(0.99);
+            double s = 0.0;
+            for (double q : v) s += q;
+            stats->mean_ms = v.empty() ? 0.0 : s / v.size();
+            stats->served = sh.served;
+            stats->rejected = sh.rejected;
+            stats->solves_per_s = wall > 0 ? sh.served / wall : 0.0;
+            stats->hbm_peak = sh.peak;
+            stats->max_active = sh.max_active;
+        }
+        (void)loop_err;
+        if (sh.first_err != RR_OK) set_error("at least one request failed (see its deliver status)");
+        return RR_OK;
+    });
 }

@@ -359,3 +359,46 @@ def test_batched_dense_operator():
     assert st == rr.RR_OK
     for c in range(4):
         assert osol.relres(op.shifted(mus[c % 2]), X[:, c], B[:, c]) <= 1e-9 * 1.0001
+
+
+def _serving_requests(count, seed, spacing=0.004, n_range=(600, 3000)):
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for i in range(count):
+        n = int(rng.integers(*n_range))
+        d = int(rng.choice([4, 8, 16]))
+        pts = rng.standard_normal((d, n)).astype(np.float32)
+        bw = workloads.median_pairwise_distance(pts, 500)
+        m = int(rng.integers(1, 4))
+        reqs.append(dict(kind=rr.OP_RBF, pts=pts, kconst=float(np.float32(1 / (2 * bw * bw))),
+                         scale=1.0 / n, mu=float(10 ** rng.uniform(-5, -2)), l=int(np.ceil(n / 32)),
+                         seed=100 + i, B=rng.standard_normal((n, m)), t_arrival=i * spacing))
+    return reqs
+
+
+def test_serving_alone_equals_mixed_and_oracle():
+    from paper_2509_19747_amd import binding as rb
+    reqs = _serving_requests(10, 3)
+    kw = dict(build=dict(prec="fp32", sketch="gaussian"), solve=dict(tol=1e-6, certify=True))
+    mixed, stats = rb.serve(reqs, max_slots=4, graph_iters=8, **kw)
+    assert stats["served"] == len(reqs) and stats["rejected"] == 0
+    assert stats["max_active"] >= 2
+    assert 0 < stats["p50_ms"] <= stats["p99_ms"]
+    for i, r in enumerate(reqs):
+        alone, _ = rb.serve([dict(r, t_arrival=0.0)], max_slots=1, graph_iters=8, **kw)
+        assert mixed[i]["info"]["status"] == rr.RR_OK
+        assert np.array_equal(alone[0]["X"], mixed[i]["X"])      # bitwise: batch-invariant
+        op = Operator(kind=rr.OP_RBF, pts=r["pts"], kconst=r["kconst"], scale=r["scale"])
+        for j in range(r["B"].shape[1]):
+            rel = osol.relres(op.shifted(r["mu"]), mixed[i]["X"][:, j], r["B"][:, j])
+            n = r["pts"].shape[1]
+            dA = n * 2.0 ** -23 * r["scale"]
+            assert rel <= 1e-6 + dA * np.linalg.norm(mixed[i]["X"][:, j]) / np.linalg.norm(r["B"][:, j])
+
+
+def test_serving_rejects_over_budget():
+    from paper_2509_19747_amd import binding as rb
+    reqs = _serving_requests(3, 5)
+    res, stats = rb.serve(reqs, hbm_budget=1 << 20, max_slots=2)
+    assert stats["rejected"] == 3 and stats["served"] == 0
+    assert all(r["info"]["status"] == rr.RR_ENOMEM for r in res)
