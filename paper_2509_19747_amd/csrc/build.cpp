@@ -135,6 +135,11 @@ struct Builder {
             check_launch();
             return;
         }
+        if (A16 && ydt == DT_F32) {   // mixed precision: bf16 MFMA, float32 Y
+            launch_dense_gemm_bf16(n, l, A16, n, Ob, ldo, mu, (float*)Y, n, st);
+            check_launch();
+            return;
+        }
         launch_copy_mat(odt, Om, n, DT_F64, Y, n, n, l, st);
         launch_scale_mat((double*)Y, n, n, l, mu, st);
         if (A16) gemm(DT_BF16, false, odt, false, n, l, n, A16, n, Om, n, (double*)Y, n, 1.0, 1.0);
@@ -379,7 +384,7 @@ extern "C" rr_status rr_build_precond(const rr_operator* A, const double* mus, i
             A16.reset(al, (size_t)n * n * 2);
             launch_copy_mat(DT_F64, A->A, A->lda, DT_BF16, A16.ptr(), n, n, n, st);
         }
-        const int ydt = (kernel && f32path) ? DT_F32 : DT_F64;
+        const int ydt = ((kernel && f32path) || (!kernel && o.prec == RR_PREC_MIXED)) ? DT_F32 : DT_F64;
         const size_t yes = ydt == DT_F32 ? sizeof(float) : sizeof(double);
         P.Qb.reset(al, (size_t)n * P.kb * sizeof(double));
 
@@ -525,7 +530,8 @@ extern "C" rr_status rr_sketch_apply(const rr_operator* A, double mu, const rr_b
             A16.reset(&P.alloc, (size_t)n * n * 2);
             launch_copy_mat(DT_F64, A->A, A->lda, DT_BF16, A16.ptr(), n, n, n, st);
         }
-        const int ydt = (kernel && opts->prec != RR_PREC_FP64) ? DT_F32 : DT_F64;
+        const int ydt = ((kernel && opts->prec != RR_PREC_FP64) || (!kernel && opts->prec == RR_PREC_MIXED))
+                            ? DT_F32 : DT_F64;
         DBuf Y = B.mat(n, l, ydt == DT_F32 ? sizeof(float) : sizeof(double));
         B.sketch(P.Omega.ptr(), P.omega_dt, mu, Y.ptr(), ydt, A16.ptr());
         launch_copy_mat(ydt, Y.ptr(), n, DT_F64, Y_out, n, n, l, st);

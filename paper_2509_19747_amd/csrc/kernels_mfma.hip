@@ -1,0 +1,122 @@
+// Dense sketch on bf16 MFMA: Y = A Omega + mu Omega for a stored symmetric A held
+// in bf16 (mixed-precision mode) and a bf16 test matrix, float32 accumulation.
+//
+// A is symmetric, so row i of A (the MFMA A-operand: 8 consecutive k per lane)
+// is read as column i of the column-major bf16 copy -- contiguous 16-byte loads.
+// Block: 512 threads = 8 waves in a 4 (rows) x 2 (columns) grid of 64 x 128 wave
+// tiles; block tile 256 x 256; k step 32 (one v_mfma_f32_16x16x32_bf16 depth).
+// The A and Omega slices are staged in LDS with padded rows; the next step's
+// global loads are issued before the current step's MFMAs.
+#include "common.hpp"
+#include "kernels.hpp"
+#include "prof.hpp"
+
+namespace rr {
+
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+constexpr int DG_BM = 256, DG_BN = 256, DG_BK = 32, DG_THREADS = 512;
+constexpr int DG_LD = 40;   // padded LDS row (bf16)
+
+__global__ __launch_bounds__(DG_THREADS) void k_dense_gemm_bf16(
+    int64_t n, int64_t m, const uint16_t* __restrict__ A, int64_t lda,
+    const uint16_t* __restrict__ B, int64_t ldb, float mu, float* __restrict__ Y, int64_t ldy) {
+    __shared__ __attribute__((aligned(16))) uint16_t As[DG_BM * DG_LD];
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[DG_BN * DG_LD];
+    const int t = threadIdx.x;
+    const int lane = t & 63, wave = t >> 6;
+    const int wm = wave & 3, wn = wave >> 2;
+    const int64_t i0 = (int64_t)blockIdx.x * DG_BM;
+    const int64_t c0 = (int64_t)blockIdx.y * DG_BN;
+    const bool vec_a = (lda % 8) == 0, vec_b = (ldb % 8) == 0;
+
+    f32x4_t acc[4][8];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 8; ++v) acc[u][v] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+
+    // chunk q (0..1023) of a 256 x 32 slice: row q>>2, 8 k values at 8*(q&3)
+    auto load_chunk = [&](const uint16_t* base, int64_t ld, int64_t lim_row, int64_t row0,
+                          int64_t k0, int q, bool vec) -> uint4 {
+        const int r = q >> 2, part = q & 3;
+        const int64_t gr = row0 + r, gk = k0 + 8 * part;
+        uint4 v = make_uint4(0u, 0u, 0u, 0u);
+        if (gr < lim_row) {
+            const uint16_t* src = base + gr * ld + gk;
+            if (vec && gk + 8 <= n) {
+                v = *(const uint4*)src;
+            } else {
+                uint32_t w[4] = {0u, 0u, 0u, 0u};
+                for (int e = 0; e < 8; ++e)
+                    if (gk + e < n) w[e >> 1] |= (uint32_t)src[e] << (16 * (e & 1));
+                v = make_uint4(w[0], w[1], w[2], w[3]);
+            }
+        }
+        return v;
+    };
+
+    uint4 ra[2], rb[2];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        ra[s] = load_chunk(A, lda, n, i0, 0, t + DG_THREADS * s, vec_a);
+        rb[s] = load_chunk(B, ldb, m, c0, 0, t + DG_THREADS * s, vec_b);
+    }
+    for (int64_t k0 = 0; k0 < n; k0 += DG_BK) {
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            const int q = t + DG_THREADS * s;
+            *(uint4*)&As[(q >> 2) * DG_LD + 8 * (q & 3)] = ra[s];
+            *(uint4*)&Bs[(q >> 2) * DG_LD + 8 * (q & 3)] = rb[s];
+        }
+        __syncthreads();
+        if (k0 + DG_BK < n) {
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                ra[s] = load_chunk(A, lda, n, i0, k0 + DG_BK, t + DG_THREADS * s, vec_a);
+                rb[s] = load_chunk(B, ldb, m, c0, k0 + DG_BK, t + DG_THREADS * s, vec_b);
+            }
+        }
+        bf16x8_t a[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int row = wm * 64 + u * 16 + (lane & 15);
+            a[u] = __builtin_bit_cast(bf16x8_t, *(const uint4*)&As[row * DG_LD + 8 * (lane >> 4)]);
+        }
+#pragma unroll
+        for (int v = 0; v < 8; ++v) {
+            const int col = wn * 128 + v * 16 + (lane & 15);
+            const bf16x8_t b = __builtin_bit_cast(bf16x8_t, *(const uint4*)&Bs[col * DG_LD + 8 * (lane >> 4)]);
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                acc[u][v] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[u], b, acc[u][v], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+#pragma unroll
+        for (int v = 0; v < 8; ++v) {
+            const int64_t gc = c0 + wn * 128 + v * 16 + (lane & 15);
+            if (gc >= m) continue;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int64_t gr = i0 + wm * 64 + u * 16 + 4 * (lane >> 4) + e;
+                if (gr < n) {
+                    const float bval = __uint_as_float((uint32_t)B[gc * ldb + gr] << 16);
+                    Y[gr + gc * ldy] = fmaf(mu, bval, acc[u][v][e]);
+                }
+            }
+        }
+    }
+}
+
+void launch_dense_gemm_bf16(int64_t n, int64_t m, const void* A, int64_t lda, const void* B,
+                            int64_t ldb, double mu, float* Y, int64_t ldy, hipStream_t st) {
+    dim3 grid((unsigned)((n + DG_BM - 1) / DG_BM), (unsigned)((m + DG_BN - 1) / DG_BN));
+    ProfScope prof(PROF_DENSE_SKETCH, st);
+    k_dense_gemm_bf16<<<grid, DG_THREADS, 0, st>>>(n, m, (const uint16_t*)A, lda, (const uint16_t*)B,
+                                                   ldb, (float)mu, Y, ldy);
+}
+
+}  // namespace rr

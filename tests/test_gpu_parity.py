@@ -361,6 +361,49 @@ def test_batched_dense_operator():
         assert osol.relres(op.shifted(mus[c % 2]), X[:, c], B[:, c]) <= 1e-9 * 1.0001
 
 
+@pytest.fixture(scope="module")
+def precision_small():
+    prob = workloads.cfg_precision(n=3001, l=130)
+    op = Operator.from_problem(prob)
+    kop = rr.kernel_operator(rr.OP_MATERN32, _cuda(prob.pts), prob.kconst, 1.0)
+    A = rr.kernel_to_dense(kop, "fp64")
+    return prob, op, A
+
+
+def test_dense_mixed_sketch_matches_oracle(precision_small):
+    # bf16 A and bf16 Omega on MFMA, float32 accumulation: |dY| <= 2^-8 |A| |Omega| + 2^-20 |A||Omega|
+    prob, op, A = precision_small
+    mu, l, n = prob.mus[0], prob.l, prob.n
+    Y = rr.sketch(rr.dense_operator(A), mu, l, sketch="gaussian", seed=prob.omega_seed,
+                  prec="mixed").cpu().numpy()
+    Om = orng.omega("gaussian", prob.omega_seed, n, l, bf16=True)
+    Yo = op.dense @ Om + mu * Om
+    bound = (np.abs(op.dense) @ np.abs(Om)) * 2.0 ** -8
+    assert np.all(np.abs(Y - Yo) <= bound)
+
+
+def test_dense_mixed_solve_with_fp64_refinement(precision_small):
+    # float32 matvec inside PCG, float64 residual at every restart: the float64 relative
+    # residual reaches 1e-10 (outer iterative refinement)
+    prob, op, A = precision_small
+    mu, tol = prob.mus[0], 1e-10
+    P = rr.build_precond(rr.dense_operator(A), [mu], l=prob.l, sketch="gaussian",
+                         seed=prob.omega_seed, prec="mixed")
+    x, info = P.solve(_cuda(prob.b), tol=tol)
+    assert info["rc"] == rr.RR_OK
+    x = x.cpu().numpy()
+    rel = osol.relres(op.shifted(mu), x, prob.b)
+    assert rel <= tol * 1.0001
+    assert abs(info["relres_fp64"] - rel) <= 1e-3 * rel
+    xs = osol.direct(op.dense, mu, prob.b)
+    cond = np.linalg.cond(op.dense + mu * np.eye(prob.n))
+    assert np.linalg.norm(x - xs) / np.linalg.norm(xs) <= 10 * tol * cond
+    # plain CG with the same refinement needs more iterations
+    i0 = rr.build_precond(rr.dense_operator(A), [mu], l=0, prec="mixed").solve(
+        _cuda(prob.b), tol=tol, maxit=20000)[1]
+    assert i0["rc"] == rr.RR_OK and i0["iters"] > info["iters"]
+
+
 def _serving_requests(count, seed, spacing=0.004, n_range=(600, 3000)):
     rng = np.random.default_rng(seed)
     reqs = []
