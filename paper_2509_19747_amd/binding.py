@@ -343,7 +343,8 @@ def random_matrix(kind: str, seed: int, rows: int, cols: int, stream=None):
     return out.t()
 
 
-PROF_KERNEL_MATVEC, PROF_KERNEL_SKETCH, PROF_DENSE_MATVEC, PROF_DENSE_SKETCH, PROF_PROJECT = range(5)
+(PROF_KERNEL_MATVEC, PROF_KERNEL_SKETCH, PROF_DENSE_MATVEC, PROF_DENSE_SKETCH, PROF_PROJECT,
+ PROF_KERNEL_MATMAT) = range(6)
 
 
 def profile_enable(on: bool = True):

@@ -92,9 +92,9 @@ def gaussian_mixture_points(rng, n: int, d: int, ncomp: int = 10,
 
 
 def rbf_problem(name, pts, mus, l, sketch, omega_seed, tol, rng, scale_by_n=True,
-                bandwidth=None, nrhs=None, dense=False):
+                bandwidth=None, nrhs=None, dense=False, bw_sample=2000):
     if bandwidth is None:
-        bandwidth = median_pairwise_distance(pts)
+        bandwidth = median_pairwise_distance(pts, bw_sample)
     kconst = _f32(1.0 / (2.0 * bandwidth * bandwidth))
     n = pts.shape[1]
     p = KernelProblem(name=name, kind=RBF, pts=pts, kconst=kconst,
@@ -183,7 +183,8 @@ def serving_stream(num: int = 2200, rate: float = 200.0, seed: int = 5,
 
     Inter-arrival ~ Exp(rate); n log-uniform in [n_min, n_max]; d uniform in
     d_choices; mu log-uniform in [1e-6, 1e-2]; l = ceil(n/32); 1-8 RHS each;
-    points N(0, I_d) rounded to float32; median-rule bandwidth; A = K/n.
+    points N(0, I_d) rounded to float32; median-rule bandwidth over the first
+    400 points of each request (enough for an i.i.d. Gaussian cloud); A = K/n.
     """
     rng = np.random.default_rng(seed)
     t = 0.0
@@ -197,7 +198,7 @@ def serving_stream(num: int = 2200, rate: float = 200.0, seed: int = 5,
         l = int(math.ceil(n / 32))
         pts = np.ascontiguousarray(rng.standard_normal((n, d)).T.astype(np.float32))
         prob = rbf_problem(f"req{rid}", pts, [mu], l, "gaussian", 1000 + rid, tol, rng,
-                           nrhs=nrhs)
+                           nrhs=nrhs, bw_sample=400)
         out.append(Request(rid=rid, t_arrival=t, problem=prob))
     return out
 
