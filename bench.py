@@ -114,6 +114,7 @@ def main():
     ap.add_argument("--rate", type=float, default=200.0, help="serving: arrivals per second")
     ap.add_argument("--slots", type=int, default=16, help="serving: concurrent requests")
     ap.add_argument("--budget-gb", type=float, default=96.0, help="serving: HBM budget")
+    ap.add_argument("--dump", default="", help="serving: write per-request records (JSON lines)")
     ap.add_argument("--nrhs", type=int, default=256, help="batched: right-hand sides per shift")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -396,16 +397,30 @@ def bench_serving(args):
     lat = np.array([r["t_done"] - q["t_arrival"] for r, q in zip(res, reqs) if r is not None])
     warm = 200 if len(lat) > 400 else 0
     ok = sum(1 for r in res if r is not None and r["info"]["status"] == 0)
+    infos = [r["info"] for r in res if r is not None]
     out = {
         "metric": "serving latency and throughput at a Poisson arrival rate",
         "value": stats["solves_per_s"], "unit": "solves/s",
         "p50_ms": float(np.percentile(lat[warm:], 50) * 1e3),
         "p99_ms": float(np.percentile(lat[warm:], 99) * 1e3), "server_stats": stats,
         "requests": len(reqs), "ok": ok, "rate": args.rate, "slots": args.slots,
+        "mean_build_ms": float(np.mean([i["ms_build"] for i in infos])),
+        "mean_solve_ms": float(np.mean([i["ms_solve"] for i in infos])),
+        "mean_iters": float(np.mean([i["iters"] for i in infos])),
         "config": {"workload": "RBF ridge requests, n log-uniform [1000, 32768], d in {4,8,16}, "
                                "mu log-uniform [1e-6, 1e-2], l=ceil(n/32), 1-8 RHS, tol 1e-6"},
     }
     print(json.dumps(out), flush=True)
+    if args.dump:
+        with open(args.dump, "w") as f:
+            for q, r in zip(reqs, res):
+                if r is not None:
+                    i = r["info"]
+                    f.write(json.dumps({"n": q["pts"].shape[1], "d": q["pts"].shape[0], "l": q["l"],
+                                        "nrhs": q["B"].shape[1], "mu": q["mu"],
+                                        "t_arrival": q["t_arrival"], "t_done": r["t_done"],
+                                        "ms_build": i["ms_build"], "ms_solve": i["ms_solve"],
+                                        "iters": i["iters"], "status": i["status"]}) + "\n")
 
 
 if __name__ == "__main__":
