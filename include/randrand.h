@@ -287,6 +287,17 @@ rr_status rr_apply_operator(const rr_operator* A, double mu, int32_t prec, const
                             double* y, void* hip_stream);
 
 /*
+ * Y = (A + mu I) U for nr columns at once (U, Y: device float64, n x nr,
+ * column-major, leading dimension n; 1 <= nr <= 4096).  Kernel operators form each
+ * entry once per group of up to 8 (FP32) or 2 (FP64) columns; in FP32 the entry
+ * K_ij of a pair of row blocks is formed once and used for both y_i and y_j.
+ * Same errors as rr_apply_operator.  This is the operator product of every PCG
+ * step (Algorithm RandRAND_PCG) applied to a block of vectors.
+ */
+rr_status rr_apply_operator_block(const rr_operator* A, double mu, int32_t prec, const double* U,
+                                  int32_t nr, double* Y, void* hip_stream);
+
+/*
  * Fill out (device, rows x cols, float64, column-major) with the method's random
  * test matrix: kind 0 = Gaussian stream `seed` (element i + c*rows),
  * kind 1 = SRHT columns (D, sampled Hadamard rows) for n = rows, l = cols.

@@ -124,6 +124,8 @@ def lib():
                                        C.POINTER(C.c_int32)]
         L.rr_kernel_to_dense.argtypes = [C.POINTER(rr_operator), P, C.c_int32, C.c_int64, P]
         L.rr_apply_operator.argtypes = [C.POINTER(rr_operator), C.c_double, C.c_int32, P, P, P]
+        L.rr_apply_operator_block.argtypes = [C.POINTER(rr_operator), C.c_double, C.c_int32, P,
+                                              C.c_int32, P, P]
         L.rr_random_matrix.argtypes = [C.c_int32, C.c_uint64, C.c_int64, C.c_int64, P, P]
         L.rr_sketch_apply.argtypes = [C.POINTER(rr_operator), C.c_double, C.POINTER(rr_build_opts),
                                       P, P]
@@ -139,7 +141,7 @@ def lib():
         L.rr_version.restype = C.c_char_p
         for name in ("rr_build_precond", "rr_solve", "rr_solve_batch", "rr_serve",
                      "rr_precond_export", "rr_precond_export_omega", "rr_precond_shape",
-                     "rr_kernel_to_dense", "rr_apply_operator", "rr_random_matrix", "rr_sketch_apply"):
+                     "rr_kernel_to_dense", "rr_apply_operator", "rr_apply_operator_block", "rr_random_matrix", "rr_sketch_apply"):
             getattr(L, name).restype = C.c_int32
         _lib = L
     return _lib
@@ -332,6 +334,17 @@ def apply_operator(op: Operator, mu: float, prec: str, u, stream=None):
     _check(lib().rr_apply_operator(C.byref(op.struct), float(mu), _PREC[prec], _ptr(u), _ptr(y),
                                    _stream(stream)), "rr_apply_operator")
     return y
+
+
+def apply_operator_block(op: Operator, mu: float, prec: str, U, stream=None):
+    """Y = (A + mu I) U for a CUDA float64 tensor U (n, nr)."""
+    import torch
+    n, nr = U.shape
+    Uc = U.t().contiguous()                 # column-major n x nr
+    Yc = torch.empty_like(Uc)
+    _check(lib().rr_apply_operator_block(C.byref(op.struct), float(mu), _PREC[prec], _ptr(Uc), nr,
+                                         _ptr(Yc), _stream(stream)), "rr_apply_operator_block")
+    return Yc.t()
 
 
 def random_matrix(kind: str, seed: int, rows: int, cols: int, stream=None):

@@ -43,9 +43,26 @@ KernelOp kernel_op_of(const rr_precond& P) {
     k.d = P.op.d;
     k.pts = P.op.pts;
     k.sqn = P.sqn.as<float>();
+    k.xa = P.xa.as<float>();
+    k.dm = kernel_record_len(P.op.d);
     k.kconst = P.op.kconst;
     k.scale = P.op.scale;
     return k;
+}
+
+void setup_operator(rr_precond& P, hipStream_t st) {
+    const rr_operator& A = P.op;
+    const int64_t n = A.n;
+    if (is_kernel(A)) {
+        const int dm = kernel_record_len(A.d);
+        P.sqn.reset(&P.alloc, (size_t)n * sizeof(float));
+        launch_sqnorms(A.pts, n, A.d, P.sqn.as<float>(), st);
+        P.xa.reset(&P.alloc, (size_t)n * dm * sizeof(float));
+        launch_point_records(A.pts, n, A.d, dm, P.xa.as<float>(), st);
+    } else if (P.opts.prec != RR_PREC_FP64) {
+        P.A32.reset(&P.alloc, (size_t)n * n * sizeof(float));
+        launch_copy_mat(DT_F64, A.A, A.lda, DT_F32, P.A32.ptr(), n, n, n, st);
+    }
 }
 
 int operator_part_count(const rr_precond& P) {
@@ -53,7 +70,7 @@ int operator_part_count(const rr_precond& P) {
 }
 
 size_t operator_ws_doubles(const rr_precond& P) {
-    return is_kernel(P.op) ? kernel_matvec_ws_doubles(P.n) : 0;
+    return is_kernel(P.op) ? kernel_matvec_ws_doubles(P.n, P.op.d, 2) : 0;
 }
 
 int apply_operator(const rr_precond& P, const double* u, double mu, double* y, double* dot_part,
@@ -257,6 +274,7 @@ rr_status rr_kernel_to_dense(const rr_operator* kop, void* A_out, int32_t dtype,
         require_device();
         KernelOp k;
         k.kind = kop->kind; k.n = kop->n; k.d = kop->d; k.pts = kop->pts; k.sqn = nullptr;
+        k.xa = nullptr; k.dm = 0;
         k.kconst = kop->kconst; k.scale = kop->scale;
         hipStream_t st = (hipStream_t)hip_stream;
         launch_kernel_to_dense(k, A_out, dtype, lda, st);
@@ -266,11 +284,12 @@ rr_status rr_kernel_to_dense(const rr_operator* kop, void* A_out, int32_t dtype,
     });
 }
 
-rr_status rr_apply_operator(const rr_operator* A, double mu, int32_t prec, const double* u, double* y,
-                            void* hip_stream) {
+rr_status rr_apply_operator_block(const rr_operator* A, double mu, int32_t prec, const double* U,
+                                 int32_t nr, double* Y, void* hip_stream) {
     return guarded([&]() -> rr_status {
         validate_operator(A);
-        RR_REQUIRE(u != nullptr && y != nullptr, "u or y is null");
+        RR_REQUIRE(U != nullptr && Y != nullptr, "U or Y is null");
+        RR_REQUIRE(nr >= 1 && nr <= 4096, "nr must be in [1, 4096]");
         RR_REQUIRE(std::isfinite(mu), "mu must be finite");
         RR_REQUIRE(prec >= 0 && prec <= 2, "unknown precision");
         require_device();
@@ -280,22 +299,21 @@ rr_status rr_apply_operator(const rr_operator* A, double mu, int32_t prec, const
         P.n = A->n;
         P.opts.prec = prec;
         P.alloc.st = st;
-        const int64_t n = A->n;
-        DBuf part(&P.alloc, (size_t)(operator_part_count(P) + 1) * sizeof(double));
-        DBuf kws(&P.alloc, (operator_ws_doubles(P) + 1) * sizeof(double));
-        if (is_kernel(*A)) {
-            P.sqn.reset(&P.alloc, (size_t)n * sizeof(float));
-            launch_sqnorms(A->pts, n, A->d, P.sqn.as<float>(), st);
-        } else if (prec != RR_PREC_FP64) {
-            P.A32.reset(&P.alloc, (size_t)n * n * sizeof(float));
-            launch_copy_mat(DT_F64, A->A, A->lda, DT_F32, P.A32.ptr(), n, n, n, st);
-        }
-        apply_operator(P, u, mu, y, part.as<double>(), kws.as<double>(), prec == RR_PREC_FP64,
-                       nullptr, st);
+        const size_t ws = is_kernel(*A) ? kernel_matvec_ws_doubles(A->n, A->d, nr) : 0;
+        DBuf part(&P.alloc, ((size_t)operator_part_count(P) * nr + 1) * sizeof(double));
+        DBuf kws(&P.alloc, (ws + 1) * sizeof(double));
+        setup_operator(P, st);
+        apply_operator_multi(P, U, nr, mu, Y, part.as<double>(), kws.as<double>(),
+                             prec == RR_PREC_FP64, st);
         RR_HIP(hipGetLastError());
         RR_HIP(hipStreamSynchronize(st));
         return RR_OK;
     });
+}
+
+rr_status rr_apply_operator(const rr_operator* A, double mu, int32_t prec, const double* u, double* y,
+                            void* hip_stream) {
+    return rr_apply_operator_block(A, mu, prec, u, 1, y, hip_stream);
 }
 
 rr_status rr_random_matrix(int32_t kind, uint64_t seed, int64_t rows, int64_t cols, double* out,

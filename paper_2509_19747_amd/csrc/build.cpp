@@ -354,13 +354,7 @@ extern "C" rr_status rr_build_precond(const rr_operator* A, const double* mus, i
         const Alloc* al = &P.alloc;
 
         // A0: operator setup
-        if (is_kernel(*A)) {
-            P.sqn.reset(al, (size_t)n * sizeof(float));
-            launch_sqnorms(A->pts, n, A->d, P.sqn.as<float>(), st);
-        } else if (o.prec != RR_PREC_FP64) {
-            P.A32.reset(al, (size_t)n * n * sizeof(float));
-            launch_copy_mat(DT_F64, A->A, A->lda, DT_F32, P.A32.ptr(), n, n, n, st);
-        }
+        setup_operator(P, st);
         P.per.resize(n_mu);
         for (int i = 0; i < n_mu; ++i) P.per[i].mu = mus[i];
         if (o.l == 0) {
@@ -516,13 +510,7 @@ extern "C" rr_status rr_sketch_apply(const rr_operator* A, double mu, const rr_b
         RR_HIP(hipGetDevice(&P.device));
         const int64_t n = P.n, l = P.l;
         const bool kernel = is_kernel(*A);
-        if (kernel) {
-            P.sqn.reset(&P.alloc, (size_t)n * sizeof(float));
-            launch_sqnorms(A->pts, n, A->d, P.sqn.as<float>(), st);
-        } else if (opts->prec != RR_PREC_FP64) {
-            P.A32.reset(&P.alloc, (size_t)n * n * sizeof(float));
-            launch_copy_mat(DT_F64, A->A, A->lda, DT_F32, P.A32.ptr(), n, n, n, st);
-        }
+        setup_operator(P, st);
         Builder B(P, st);
         B.make_omega();
         DBuf A16;

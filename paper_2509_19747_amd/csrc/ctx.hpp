@@ -128,6 +128,7 @@ struct rr_precond {
     // operator-derived data
     rr::DBuf A32;         // float32 copy of a dense A (FP32 / MIXED)
     rr::DBuf sqn;         // |x_i|^2 (kernel operators)
+    rr::DBuf xa;          // padded point records (kernel operators)
     // basis
     rr::DBuf Omega;       // n x l, dtype omega_dt
     int omega_dt = rr::DT_F64;
@@ -158,6 +159,9 @@ int apply_operator(const rr_precond& P, const double* u, double mu, double* y, d
 void apply_operator_multi(const rr_precond& P, const double* U, int nr, double mu, double* Y,
                           double* dot_part, double* kmv_ws, bool fp64, hipStream_t st);
 int operator_part_count(const rr_precond& P);
+// Operator setup (A0): squared norms and point records for kernels, the float32
+// copy of a dense A when the working precision is below float64.
+void setup_operator(rr_precond& P, hipStream_t st);
 size_t operator_ws_doubles(const rr_precond& P);
 
 // z = rcoef*r + Qb (Kc (Qb^T r)), with partials of r^T z.  Returns #partials.

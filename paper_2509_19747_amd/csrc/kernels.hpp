@@ -98,24 +98,33 @@ struct KernelOp {
     int d;
     const float* pts;    // d x n SoA
     const float* sqn;    // |x_i|^2 in float32 (length n), precomputed
+    const float* xa;     // point records: n x dm floats, coordinates then zero padding
+    int dm;              // record length kernel_record_len(d) in {4, 8, 16, 32}
     double kconst, scale;
 };
+// Record length (floats) of a d-dimensional point: the next of 4, 8, 16, 32.
+int kernel_record_len(int d);
+// xa[i*dm + k] = pts[k*n + i] for k < d, 0 for d <= k < dm.
+void launch_point_records(const float* pts, int64_t n, int d, int dm, float* xa, hipStream_t st);
 int kernel_matvec_blocks(int64_t n);
-size_t kernel_matvec_ws_doubles(int64_t n);
+// Workspace (doubles) of launch_kernel_matvec(_multi) for up to nr columns.
+size_t kernel_matvec_ws_doubles(int64_t n, int d, int nr);
 void launch_kernel_matvec(const KernelOp& op, bool fp64, const double* u, double mu, double* y,
                           double* dot_part, double* ws, const int32_t* stop, hipStream_t st);
-// nr (1 or 2) right-hand sides at once: u, y are n x nr (leading dimension n);
+// nr >= 1 right-hand sides at once: u, y are n x nr (leading dimension n);
 // dot partials of column q at dot_part[q * kernel_matvec_blocks(n) + b].  Each
-// kernel entry is evaluated once and applied to every column.
+// kernel entry is evaluated once per group of up to 8 (float32) or 2 (float64)
+// columns and applied to every column of the group.
 void launch_kernel_matvec_multi(const KernelOp& op, bool fp64, const double* u, int nr, double mu,
                                 double* y, double* dot_part, double* ws, const int32_t* stop,
                                 hipStream_t st);
+// Symmetric float32 matvec, nr in {1, 2, 4, 8} (kernels_ksym.hip).
+size_t kernel_sym_ws_doubles(int64_t n, int d, int nr);
+void launch_kernel_matvec_sym(const KernelOp& op, const double* u, int nr, double mu, double* y,
+                              double* dot_part, double* ws, const int32_t* stop, hipStream_t st);
 void launch_sqnorms(const float* pts, int64_t n, int d, float* sqn, hipStream_t st);
 // Dense formation A_out = scale*K in float64 (dtype 0) / float32 (1) / bf16 (2).
 void launch_kernel_to_dense(const KernelOp& op, void* out, int dtype, int64_t lda, hipStream_t st);
-// Kernel-GEMM Y = scale*K B + mu*B  (B: n x m float32, Y: float32), FP32 MFMA.
-void launch_kernel_gemm_f32(const KernelOp& op, const float* B, int64_t ldb, int64_t m,
-                            double mu, float* Y, int64_t ldy, hipStream_t st);
 // Kernel-GEMM on BF16 MFMA with hi/lo-split kernel entries; B (n x m, ldb, a
 // multiple of 8) holds bf16 values (the test matrix, exact in bf16); Y float32.
 void launch_kernel_gemm_bf16x2(const KernelOp& op, const void* Bbf16, int64_t ldb, int64_t m,

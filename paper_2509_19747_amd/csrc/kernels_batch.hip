@@ -9,28 +9,11 @@
 //  * per-column dot partials, scalar steps and vector updates with a per-column
 //      run flag: converged or restarting columns are left untouched.
 #include "common.hpp"
+#include "kentry.hpp"
 #include "kernels.hpp"
 #include "prof.hpp"
 
 namespace rr {
-
-constexpr float LOG2E_FB = 1.4426950408889634f;
-
-// float32 kernel entry, identical to the single-vector matvec's
-template <int KIND>
-RR_DEV float kval32b(float s, float c) {
-    if (KIND == 1) return __builtin_amdgcn_exp2f(c * fminf(s, 0.0f));
-    const float t = c * __builtin_sqrtf(fmaxf(-2.0f * s, 0.0f));
-    return (1.0f + t) * __builtin_amdgcn_exp2f(-t * LOG2E_FB);
-}
-
-template <int KIND>
-RR_DEV double kval64b(double r2, double kconst) {
-    r2 = r2 > 0.0 ? r2 : 0.0;
-    if (KIND == 1) return exp(-kconst * r2);
-    const double t = kconst * sqrt(r2);
-    return (1.0 + t) * exp(-t);
-}
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 constexpr int KD_BM = 256, KD_BN = 128, KD_BK = 16, KD_THREADS = 512;
@@ -84,13 +67,13 @@ __global__ __launch_bounds__(KD_THREADS) void k_kgemm_f64_mfma(
                         const double df = (double)xi[k] - (double)pts[(int64_t)k * n + gjc];
                         r2 = fma(df, df, r2);
                     }
-                kv = kval64b<KIND>(r2, kconst);
+                kv = kval64<KIND>(r2, kconst);
             } else {
                 float sv = fmaf(-0.5f, sqn[gjc], mhn);
 #pragma unroll
                 for (int k = 0; k < DM; ++k)
                     if (k < d) sv = fmaf(xi[k], pts[(int64_t)k * n + gjc], sv);
-                kv = (double)kval32b<KIND>(sv, c);
+                kv = (double)kval32<KIND>(sv, c);
             }
             As[p][trow] = (gj < n) ? kv : 0.0;
         }
@@ -135,10 +118,6 @@ __global__ __launch_bounds__(KD_THREADS) void k_kgemm_f64_mfma(
     }
 }
 
-static float c_for_b(int kind, double kconst) {
-    return kind == 1 ? (float)(2.0 * kconst * 1.4426950408889634074) : (float)kconst;
-}
-
 template <int KIND, bool F64E>
 static void kd_dispatch(const KernelOp& op, float c, const double* mucol, const double* P,
                         int64_t ldp, int64_t m, double* W, int64_t ldw, hipStream_t st) {
@@ -157,7 +136,7 @@ static void kd_dispatch(const KernelOp& op, float c, const double* mucol, const 
 void launch_kernel_matmat_f64(const KernelOp& op, bool f64_entries, const double* mucol,
                               const double* P, int64_t ldp, int64_t m, double* W, int64_t ldw,
                               hipStream_t st) {
-    const float c = c_for_b(op.kind, op.kconst);
+    const float c = kernel_c32(op.kind, op.kconst);
     ProfScope prof(f64_entries ? -1 : PROF_KERNEL_MATMAT, st);
     if (op.kind == 1) {
         if (f64_entries) kd_dispatch<1, true>(op, c, mucol, P, ldp, m, W, ldw, st);

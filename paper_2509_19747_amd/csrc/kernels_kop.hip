@@ -2,58 +2,24 @@
 // Gaussian RBF or Matern-3/2 kernel (kernel ridge regression, Section 7.2.2,
 // eq. kernel), reached only through its entries.
 //
-//  * k_kmv_f32 / k_kmv_f64 : y = scale*K u + mu u  (the PCG matvec, T_mv).
-//      float32 entries, float64 products and accumulation; or fully float64.
-//      Rows are split over (row block, j slice); each slice writes partial row
-//      sums which a second kernel adds in a fixed order (deterministic).
-//  * k_kgemm_f32_mfma      : Y = scale*K B + mu B on FP32 MFMA (the sketch
-//      A_mu Omega, and the multi-RHS product).  Kernel tiles are formed in
-//      registers/LDS and never touch HBM; SRHT Omega can be generated in the
-//      tile loader instead of read.
-//  * k_kgemm_f64           : float64 vector-ALU variant (float64 mode).
+//  * launch_kernel_matvec(_multi): y = scale*K u + mu u (the PCG matvec).
+//      float32 entries: the symmetric kernel of kernels_ksym.hip.
+//      float64 entries: k_kmv_f64 below; rows are split over (row block,
+//      j slice), each slice writes partial row sums, and a second kernel adds
+//      them in a fixed order (deterministic).
+//  * k_kgemm_bf16x2 : Y = scale*K B + mu B for the float32-mode sketch A_mu Omega
+//      with a bf16 Omega, on bf16 MFMA with the kernel tile split hi + lo.
+//  * k_kgemm_f64    : float64 vector-ALU variant (float64 mode).
 //
-// The float32 entry function is bitwise symmetric in (i, j): the dot product
-// runs over the coordinates in a fixed order with commutative products, and
-// the squared norms are added before the dot product is subtracted, so
-// K_ij == K_ji exactly and CG sees a symmetric operator.
+// Entry formulas are in kentry.hpp (the float32 entry is bitwise symmetric).
 #include "common.hpp"
+#include "kentry.hpp"
 #include "kernels.hpp"
 #include "prof.hpp"
 
 #include <algorithm>
 
 namespace rr {
-
-constexpr float LOG2E_F = 1.4426950408889634f;
-
-// Float32 kernel entry from s = x_i.x_j - (|x_i|^2 + |x_j|^2)/2 = -r^2/2.  Callers
-// form s symmetrically: start from fl(-0.5 (|x_i|^2 + |x_j|^2)) (one rounding of an
-// exact sum) and add the coordinate products in a fixed order.
-//   RBF        exp(-kconst r^2) = exp2(c min(s, 0)),   c = fl32(2 kconst log2 e)
-//   Matern-3/2 (1 + t) exp(-t),  t = kconst sqrt(max(-2 s, 0)),  c = fl32(kconst)
-template <int KIND>
-RR_DEV float kval32(float s, float c) {
-    if (KIND == 1) {
-        return __builtin_amdgcn_exp2f(c * fminf(s, 0.0f));
-    } else {
-        const float t = c * __builtin_sqrtf(fmaxf(-2.0f * s, 0.0f));
-        return (1.0f + t) * __builtin_amdgcn_exp2f(-t * LOG2E_F);
-    }
-}
-// s starting value for the pair (i, j) from the row's -|x_i|^2/2 and |x_j|^2.
-RR_DEV float kpair_init(float mhalf_ni, float nj) { return fmaf(-0.5f, nj, mhalf_ni); }
-
-template <int KIND>
-RR_DEV double kval64(double r2, double kconst) {
-    r2 = r2 > 0.0 ? r2 : 0.0;
-    if (KIND == 1) return exp(-kconst * r2);
-    const double t = kconst * sqrt(r2);
-    return (1.0 + t) * exp(-t);
-}
-
-static float c_for(int kind, double kconst) {
-    return kind == 1 ? (float)(2.0 * kconst * 1.4426950408889634074) : (float)kconst;
-}
 
 __global__ void k_sqnorms(const float* __restrict__ pts, int64_t n, int d, float* __restrict__ sqn) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
@@ -72,113 +38,28 @@ void launch_sqnorms(const float* pts, int64_t n, int d, float* sqn, hipStream_t 
     k_sqnorms<<<(int)g, 256, 0, st>>>(pts, n, d, sqn);
 }
 
+int kernel_record_len(int d) { return d <= 4 ? 4 : d <= 8 ? 8 : d <= 16 ? 16 : 32; }
+
+__global__ void k_point_records(const float* __restrict__ pts, int64_t n, int d, int dm,
+                                float* __restrict__ xa) {
+    const int64_t total = n * dm;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = e / dm;
+        const int k = (int)(e - i * dm);
+        xa[e] = k < d ? pts[(int64_t)k * n + i] : 0.0f;
+    }
+}
+void launch_point_records(const float* pts, int64_t n, int d, int dm, float* xa, hipStream_t st) {
+    int64_t g = (n * dm + 255) / 256;
+    if (g > 8192) g = 8192;
+    k_point_records<<<(int)g, 256, 0, st>>>(pts, n, d, dm, xa);
+}
+
 // ======================================================== kernel matvec
 constexpr int KMV_THREADS = 256;
-constexpr int KMV_R = 8;                       // rows per thread
-constexpr int KMV_ROWS = KMV_THREADS * KMV_R;  // rows per block
-constexpr int KMV_JB = 4;                      // points per unrolled step (fits in SGPRs)
 
-static int kmv_slices(int64_t n) {
-    const int64_t rb = (n + KMV_ROWS - 1) / KMV_ROWS;
-    int64_t s = (2048 + rb - 1) / rb;
-    const int64_t maxs = (n + 255) / 256;
-    if (s > maxs) s = maxs;
-    if (s < 1) s = 1;
-    if (s > 256) s = 256;
-    return (int)s;
-}
 int kernel_matvec_blocks(int64_t n) { return (int)((n + 255) / 256); }
-
-// Stage 1, float32 entries.  D = point dimension (compile time, or 0 = runtime d).
-// Each thread owns KMV_R rows (coordinates in VGPRs); the points j of the block's
-// slice are wave-uniform, so their coordinates arrive through scalar loads and
-// every kernel entry costs d FMAs, the exp2 and one float64 FMA.
-template <int KIND, int D, int NR>
-__global__ __launch_bounds__(KMV_THREADS) void k_kmv_f32(int64_t n, int dd,
-                                                         const float* __restrict__ pts,
-                                                         const float* __restrict__ sqn, float c,
-                                                         const double* __restrict__ u,
-                                                         double* __restrict__ part,
-                                                         int64_t jper,
-                                                         const int32_t* __restrict__ stop) {
-    if (stop && *stop) return;
-    constexpr int DM = D > 0 ? D : 32;
-    const int d = D > 0 ? D : dd;
-    const int64_t rbase = (int64_t)blockIdx.x * KMV_ROWS + threadIdx.x;
-    float xi[KMV_R][DM];
-    float mhn[KMV_R];
-    double acc[KMV_R][NR];
-#pragma unroll
-    for (int r = 0; r < KMV_R; ++r) {
-        const int64_t i = rbase + (int64_t)r * KMV_THREADS;
-        const int64_t ic = i < n ? i : n - 1;
-#pragma unroll
-        for (int k = 0; k < DM; ++k) xi[r][k] = (k < d) ? pts[(int64_t)k * n + ic] : 0.0f;
-        mhn[r] = -0.5f * sqn[ic];
-#pragma unroll
-        for (int q = 0; q < NR; ++q) acc[r][q] = 0.0;
-    }
-    const int64_t jb = (int64_t)blockIdx.y * jper;
-    const int64_t je = (jb + jper < n) ? jb + jper : n;
-    int64_t j = jb;
-    for (; j + KMV_JB <= je; j += KMV_JB) {
-#pragma unroll
-        for (int q = 0; q < KMV_JB; ++q) {
-            const int64_t jj = j + q;
-            const float nj = sqn[jj];
-            double uj[NR];
-#pragma unroll
-            for (int q = 0; q < NR; ++q) uj[q] = u[(int64_t)q * n + jj];
-            float s[KMV_R];
-#pragma unroll
-            for (int r = 0; r < KMV_R; ++r) s[r] = kpair_init(mhn[r], nj);
-#pragma unroll
-            for (int k = 0; k < DM; ++k) {
-                if (k < d) {
-                    const float xjk = pts[(int64_t)k * n + jj];
-#pragma unroll
-                    for (int r = 0; r < KMV_R; ++r) s[r] = fmaf(xi[r][k], xjk, s[r]);
-                }
-            }
-#pragma unroll
-            for (int r = 0; r < KMV_R; ++r) {
-                const double kv = (double)kval32<KIND>(s[r], c);
-#pragma unroll
-                for (int q = 0; q < NR; ++q) acc[r][q] = fma(kv, uj[q], acc[r][q]);
-            }
-        }
-    }
-    for (; j < je; ++j) {
-        const float nj = sqn[j];
-        double uj[NR];
-#pragma unroll
-        for (int q = 0; q < NR; ++q) uj[q] = u[(int64_t)q * n + j];
-        float s[KMV_R];
-#pragma unroll
-        for (int r = 0; r < KMV_R; ++r) s[r] = kpair_init(mhn[r], nj);
-#pragma unroll
-        for (int k = 0; k < DM; ++k) {
-            if (k < d) {
-                const float xjk = pts[(int64_t)k * n + j];
-#pragma unroll
-                for (int r = 0; r < KMV_R; ++r) s[r] = fmaf(xi[r][k], xjk, s[r]);
-            }
-        }
-#pragma unroll
-        for (int r = 0; r < KMV_R; ++r) {
-            const double kv = (double)kval32<KIND>(s[r], c);
-#pragma unroll
-            for (int q = 0; q < NR; ++q) acc[r][q] = fma(kv, uj[q], acc[r][q]);
-        }
-    }
-#pragma unroll
-    for (int r = 0; r < KMV_R; ++r) {
-        const int64_t i = rbase + (int64_t)r * KMV_THREADS;
-        if (i < n)
-#pragma unroll
-            for (int q = 0; q < NR; ++q) part[((int64_t)blockIdx.y * NR + q) * n + i] = acc[r][q];
-    }
-}
 
 // Stage 1, float64 entries (difference form, float64 exp).
 constexpr int KMV64_R = 4;
@@ -275,18 +156,6 @@ __global__ __launch_bounds__(256) void k_kmv_finish(int64_t n, int slices, int n
     }
 }
 
-template <int KIND, int NR>
-static void kmv_f32_dispatch(const KernelOp& op, float c, const double* u, double* part,
-                             int64_t jper, dim3 grid, const int32_t* stop, hipStream_t st) {
-    switch (op.d) {
-        case 3: k_kmv_f32<KIND, 3, NR><<<grid, KMV_THREADS, 0, st>>>(op.n, 3, op.pts, op.sqn, c, u, part, jper, stop); break;
-        case 4: k_kmv_f32<KIND, 4, NR><<<grid, KMV_THREADS, 0, st>>>(op.n, 4, op.pts, op.sqn, c, u, part, jper, stop); break;
-        case 8: k_kmv_f32<KIND, 8, NR><<<grid, KMV_THREADS, 0, st>>>(op.n, 8, op.pts, op.sqn, c, u, part, jper, stop); break;
-        case 16: k_kmv_f32<KIND, 16, NR><<<grid, KMV_THREADS, 0, st>>>(op.n, 16, op.pts, op.sqn, c, u, part, jper, stop); break;
-        default: k_kmv_f32<KIND, 0, NR><<<grid, KMV_THREADS, 0, st>>>(op.n, op.d, op.pts, op.sqn, c, u, part, jper, stop); break;
-    }
-}
-
 static int kmv64_slices(int64_t n) {
     const int64_t rb = (n + KMV64_ROWS - 1) / KMV64_ROWS;
     int64_t s = (2048 + rb - 1) / rb;
@@ -297,40 +166,48 @@ static int kmv64_slices(int64_t n) {
     return (int)s;
 }
 
-// Stage 1 only (the timed hot kernel): ws[s][q][i] = sum over slice s of K_ij u_q[j].
+// Float64 stage 1: ws[s][q][i] = sum over slice s of K_ij u_q[j], nr in {1, 2}.
 // Returns the number of slices.
-static int kmv_stage1(const KernelOp& op, bool fp64, const double* u, int nr, double* ws,
-                      const int32_t* stop, hipStream_t st) {
-    if (fp64) {
-        const int slices = kmv64_slices(op.n);
-        const int64_t jper = (op.n + slices - 1) / slices;
-        dim3 grid((unsigned)((op.n + KMV64_ROWS - 1) / KMV64_ROWS), (unsigned)slices);
-#define KF64(K, R) k_kmv_f64<K, R><<<grid, KMV_THREADS, 0, st>>>(op.n, op.d, op.pts, op.kconst, u, ws, jper, stop)
-        if (op.kind == 1) { if (nr == 1) KF64(1, 1); else KF64(1, 2); }
-        else { if (nr == 1) KF64(2, 1); else KF64(2, 2); }
-#undef KF64
-        return slices;
-    }
-    const int slices = kmv_slices(op.n);
+static int kmv_stage1_f64(const KernelOp& op, const double* u, int nr, double* ws,
+                          const int32_t* stop, hipStream_t st) {
+    const int slices = kmv64_slices(op.n);
     const int64_t jper = (op.n + slices - 1) / slices;
-    dim3 grid((unsigned)((op.n + KMV_ROWS - 1) / KMV_ROWS), (unsigned)slices);
-    ProfScope prof(nr == 1 ? PROF_KERNEL_MATVEC : -1, st);
-    const float c = c_for(op.kind, op.kconst);
-    if (op.kind == 1) { if (nr == 1) kmv_f32_dispatch<1, 1>(op, c, u, ws, jper, grid, stop, st); else kmv_f32_dispatch<1, 2>(op, c, u, ws, jper, grid, stop, st); }
-    else { if (nr == 1) kmv_f32_dispatch<2, 1>(op, c, u, ws, jper, grid, stop, st); else kmv_f32_dispatch<2, 2>(op, c, u, ws, jper, grid, stop, st); }
+    dim3 grid((unsigned)((op.n + KMV64_ROWS - 1) / KMV64_ROWS), (unsigned)slices);
+#define KF64(K, R) k_kmv_f64<K, R><<<grid, KMV_THREADS, 0, st>>>(op.n, op.d, op.pts, op.kconst, u, ws, jper, stop)
+    if (op.kind == 1) { if (nr == 1) KF64(1, 1); else KF64(1, 2); }
+    else { if (nr == 1) KF64(2, 1); else KF64(2, 2); }
+#undef KF64
     return slices;
 }
 
-size_t kernel_matvec_ws_doubles(int64_t n) {
-    return (size_t)2 * (size_t)std::max(kmv_slices(n), kmv64_slices(n)) * (size_t)n;
+size_t kernel_matvec_ws_doubles(int64_t n, int d, int nr) {
+    size_t w = (size_t)2 * (size_t)kmv64_slices(n) * (size_t)n;
+    for (int c = 1; c <= 8; c *= 2)
+        if (c == 1 || c <= nr) w = std::max(w, kernel_sym_ws_doubles(n, d, c));
+    return w;
 }
 
 void launch_kernel_matvec_multi(const KernelOp& op, bool fp64, const double* u, int nr, double mu,
                                 double* y, double* dot_part, double* ws, const int32_t* stop,
                                 hipStream_t st) {
-    const int slices = kmv_stage1(op, fp64, u, nr, ws, stop, st);
-    k_kmv_finish<<<kernel_matvec_blocks(op.n), 256, 0, st>>>(op.n, slices, nr, ws, op.scale, mu, u,
-                                                             y, dot_part, stop);
+    const int64_t nblk = kernel_matvec_blocks(op.n);
+    for (int q0 = 0; q0 < nr;) {
+        const int left = nr - q0;
+        const double* uq = u + (int64_t)q0 * op.n;
+        double* yq = y + (int64_t)q0 * op.n;
+        double* dq = dot_part + (int64_t)q0 * nblk;
+        if (fp64) {
+            const int c = left >= 2 ? 2 : 1;
+            const int slices = kmv_stage1_f64(op, uq, c, ws, stop, st);
+            k_kmv_finish<<<(unsigned)nblk, 256, 0, st>>>(op.n, slices, c, ws, op.scale, mu, uq, yq, dq,
+                                                         stop);
+            q0 += c;
+        } else {
+            const int c = left >= 8 ? 8 : left >= 4 ? 4 : left >= 2 ? 2 : 1;
+            launch_kernel_matvec_sym(op, uq, c, mu, yq, dq, ws, stop, st);
+            q0 += c;
+        }
+    }
 }
 
 void launch_kernel_matvec(const KernelOp& op, bool fp64, const double* u, double mu, double* y,
@@ -367,129 +244,6 @@ void launch_kernel_to_dense(const KernelOp& op, void* out, int dtype, int64_t ld
 #undef KTD
 }
 
-// ============================================== kernel-GEMM on FP32 MFMA
-// Y[i, c] = scale * sum_j K(x_i, x_j) B[j, c] + mu B[i, c].
-// Block: 256 threads = 4 waves in a 2x2 grid of 64x64 wave tiles; block tile
-// 128 rows x 128 columns; K loop over 32 points per step.  Per step the block
-// forms the 128x32 kernel tile (each thread: one row, 16 points) into LDS in
-// the MFMA A-operand order and stages the 32x128 slice of B; then every wave
-// issues 8 k-steps x 16 v_mfma_f32_16x16x4_f32.
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-constexpr int KG_BM = 128, KG_BN = 128, KG_BK = 32;
-
-template <int KIND, int D>
-__global__ __launch_bounds__(256) void k_kgemm_f32_mfma(int64_t n, int dd,
-                                                        const float* __restrict__ pts,
-                                                        const float* __restrict__ sqn, float c,
-                                                        float scale, float mu,
-                                                        const float* __restrict__ B, int64_t ldb,
-                                                        int64_t m, float* __restrict__ Y,
-                                                        int64_t ldy) {
-    constexpr int DM = D > 0 ? D : 32;
-    const int d = D > 0 ? D : dd;
-    __shared__ float Ks[KG_BK][KG_BM];
-    __shared__ float Bs[KG_BK][KG_BN + 1];
-    const int t = threadIdx.x;
-    const int lane = t & 63, wave = t >> 6;
-    const int wm = wave & 1, wn = wave >> 1;
-    const int64_t i0 = (int64_t)blockIdx.x * KG_BM;
-    const int64_t c0 = (int64_t)blockIdx.y * KG_BN;
-
-    // this thread's row for tile formation
-    const int trow = t & (KG_BM - 1);
-    const int tcg = t >> 7;            // 0/1: which 16 of the 32 points
-    const int64_t gi = i0 + trow;
-    const int64_t gic = gi < n ? gi : n - 1;
-    float xi[DM];
-#pragma unroll
-    for (int k = 0; k < DM; ++k) xi[k] = (k < d) ? pts[(int64_t)k * n + gic] : 0.0f;
-    const float ni = sqn[gic];
-
-    f32x4 acc[4][4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) acc[u][v] = f32x4{0.f, 0.f, 0.f, 0.f};
-
-    for (int64_t j0 = 0; j0 < n; j0 += KG_BK) {
-        // kernel tile: Ks[p][row] = K(x_{i0+row}, x_{j0+p})
-#pragma unroll 4
-        for (int q = 0; q < 16; ++q) {
-            const int p = tcg * 16 + q;
-            const int64_t gj = j0 + p;
-            float kv = 0.0f;
-            if (gj < n && gi < n) {
-                float sv = kpair_init(-0.5f * ni, sqn[gj]);
-#pragma unroll
-                for (int k = 0; k < DM; ++k)
-                    if (k < d) sv = fmaf(xi[k], pts[(int64_t)k * n + gj], sv);
-                kv = kval32<KIND>(sv, c);
-            }
-            Ks[p][trow] = kv;
-        }
-        // B slice: Bs[p][col] = B[j0+p, c0+col]
-#pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            const int p = t & 31;
-            const int col = (t >> 5) + 8 * q;
-            const int64_t gj = j0 + p, gc = c0 + col;
-            Bs[p][col] = (gj < n && gc < m) ? B[gj + gc * ldb] : 0.0f;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int kk = 0; kk < KG_BK; kk += 4) {
-            float a[4], b[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) a[u] = Ks[kk + (lane >> 4)][wm * 64 + u * 16 + (lane & 15)];
-#pragma unroll
-            for (int v = 0; v < 4; ++v) b[v] = Bs[kk + (lane >> 4)][wn * 64 + v * 16 + (lane & 15)];
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-#pragma unroll
-                for (int v = 0; v < 4; ++v)
-                    acc[u][v] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u], b[v], acc[u][v], 0, 0, 0);
-        }
-        __syncthreads();
-    }
-    // epilogue: D[row = 4*(lane/16) + e][col = lane%16] of each 16x16 tile
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int64_t gc = c0 + wn * 64 + v * 16 + (lane & 15);
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int64_t gr = i0 + wm * 64 + u * 16 + 4 * (lane >> 4) + e;
-                if (gr < n && gc < m) {
-                    Y[gr + gc * ldy] = fmaf(scale, acc[u][v][e], mu * B[gr + gc * ldb]);
-                }
-            }
-        }
-    }
-}
-
-template <int KIND>
-static void kgemm_dispatch(const KernelOp& op, float c, const float* B, int64_t ldb, int64_t m,
-                           float mu, float* Y, int64_t ldy, hipStream_t st) {
-    dim3 grid((unsigned)((op.n + KG_BM - 1) / KG_BM), (unsigned)((m + KG_BN - 1) / KG_BN));
-    const float sc = (float)op.scale;
-    switch (op.d) {
-        case 3: k_kgemm_f32_mfma<KIND, 3><<<grid, 256, 0, st>>>(op.n, 3, op.pts, op.sqn, c, sc, mu, B, ldb, m, Y, ldy); break;
-        case 4: k_kgemm_f32_mfma<KIND, 4><<<grid, 256, 0, st>>>(op.n, 4, op.pts, op.sqn, c, sc, mu, B, ldb, m, Y, ldy); break;
-        case 8: k_kgemm_f32_mfma<KIND, 8><<<grid, 256, 0, st>>>(op.n, 8, op.pts, op.sqn, c, sc, mu, B, ldb, m, Y, ldy); break;
-        case 16: k_kgemm_f32_mfma<KIND, 16><<<grid, 256, 0, st>>>(op.n, 16, op.pts, op.sqn, c, sc, mu, B, ldb, m, Y, ldy); break;
-        default: k_kgemm_f32_mfma<KIND, 0><<<grid, 256, 0, st>>>(op.n, op.d, op.pts, op.sqn, c, sc, mu, B, ldb, m, Y, ldy); break;
-    }
-}
-
-void launch_kernel_gemm_f32(const KernelOp& op, const float* B, int64_t ldb, int64_t m, double mu,
-                            float* Y, int64_t ldy, hipStream_t st) {
-    const float c = c_for(op.kind, op.kconst);
-    ProfScope prof(PROF_KERNEL_SKETCH, st);
-    if (op.kind == 1) kgemm_dispatch<1>(op, c, B, ldb, m, (float)mu, Y, ldy, st);
-    else kgemm_dispatch<2>(op, c, B, ldb, m, (float)mu, Y, ldy, st);
-}
-
 // ================================ kernel-GEMM on BF16 MFMA with a split kernel tile
 // Y[i, c] = scale * sum_j K(x_i, x_j) B[j, c] + mu B[i, c] for a test matrix B whose
 // entries are exact in bf16 (SRHT +-1, or a Gaussian drawn in bf16).  Each float32
@@ -504,6 +258,7 @@ void launch_kernel_gemm_f32(const KernelOp& op, const float* B, int64_t ldb, int
 // consistent k order for A and B (lane l holds k = 8*(l/16) .. +7), which is all
 // the product needs.
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 constexpr int KB_BM = 128, KB_BN = 512, KB_BK = 32, KB_THREADS = 512;
 constexpr int KB_AS = 40;   // padded LDS row length (bf16) of the kernel tile
 constexpr int KB_BS = 40;   // padded LDS column length (bf16) of the B slice
@@ -650,7 +405,7 @@ static void kgemm_bf16_dispatch(const KernelOp& op, float c, const uint16_t* B, 
 
 void launch_kernel_gemm_bf16x2(const KernelOp& op, const void* Bbf16, int64_t ldb, int64_t m,
                                double mu, float* Y, int64_t ldy, hipStream_t st) {
-    const float c = c_for(op.kind, op.kconst);
+    const float c = kernel_c32(op.kind, op.kconst);
     ProfScope prof(PROF_KERNEL_SKETCH, st);
     if (op.kind == 1) kgemm_bf16_dispatch<1>(op, c, (const uint16_t*)Bbf16, ldb, m, (float)mu, Y, ldy, st);
     else kgemm_bf16_dispatch<2>(op, c, (const uint16_t*)Bbf16, ldb, m, (float)mu, Y, ldy, st);

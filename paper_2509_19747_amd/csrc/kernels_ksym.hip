@@ -1,0 +1,314 @@
+// Symmetric float32 kernel matvec: Y = scale * K U + mu U for U with NR columns
+// (the PCG operator of kernel ridge regression, Section 7.2.2, and the
+// two-column power iterations of the tau estimates).
+//
+// K is symmetric, so every unordered pair of row blocks (I, J), I < J, is
+// formed once: the block's threads own rows of I (coordinates in VGPRs), the
+// points of J stream through scalar loads (wave-uniform), and each entry K_ij
+// feeds both the row sum y_i += K_ij u_j and the column sum y_j += K_ij u_i.
+// Diagonal blocks (I = J) form the full square and keep row sums only.
+//
+// Precision: float32 entries (bitwise symmetric, see kentry.hpp), widened to
+// float64 for every product with u and every sum (row sums in registers,
+// column sums over the thread's rows, a fixed DPP tree over the wave and the
+// block's four waves).  Float32 accumulation would make the operator depend
+// on u through rounding at the 1e-7 level, which caps the residual PCG can
+// reach near 1e-7 * ||A|| ||x|| / ||b||; float64 keeps it a fixed linear map
+// (the float32-rounded symmetric matrix).  Every partial lands in its own slot
+// of the workspace and the finish kernel adds a row's slots in a fixed order,
+// so results are bitwise reproducible.
+//
+// Work items: (I, J, s) for I <= J and s = 0..S-1, the s-th slice of CL
+// columns of block J.  Row partials of item (I, J, s) go to slot J*S + s of
+// the rows of I; column partials go to slot I*S of the columns of J (I < J,
+// so these slots never meet a row slot of the same row, whose partner block
+// is >= its own block).
+#include "common.hpp"
+#include "kentry.hpp"
+#include "kernels.hpp"
+#include "prof.hpp"
+
+#include <algorithm>
+
+namespace rr {
+
+constexpr int KS_THREADS = 256;
+// columns per LDS column-sum round (LDS: 4 waves x chunk x NR doubles = 16 KB)
+constexpr int ks_chunk_ct(int NR) { return NR >= 8 ? 64 : NR >= 4 ? 128 : 256; }
+
+// Points are read as zero-padded records of DM floats (DM = 4, 8, 16, 32):
+// one scalar load brings a whole column point into SGPRs, and the padding adds
+// exact zeros to the dot product.  Rows per thread and points per step shrink
+// as DM and NR grow so that coordinates, accumulators and the step's scalar
+// operands stay in registers.
+constexpr int ksym_rows_ct(int DM, int NR) {
+    return DM + 4 * NR <= 21 ? 8 : DM + 4 * NR <= 42 ? 4 : 2;   // R * (DM + 4 NR) VGPRs
+}
+constexpr int ksym_jb_ct(int DM, int NR) {
+    const int base = DM <= 8 ? 4 : DM <= 16 ? 2 : 1;
+    const int div = NR >= 8 ? 4 : NR >= 4 ? 2 : 1;
+    return base / div > 0 ? base / div : 1;
+}
+
+struct KsymPlan {
+    int R, RB, nb, S, CL;
+    int64_t items;
+};
+
+static KsymPlan ksym_plan(int64_t n, int d, int nr) {
+    KsymPlan p;
+    p.R = ksym_rows_ct(kernel_record_len(d), nr);
+    p.RB = KS_THREADS * p.R;
+    p.nb = (int)((n + p.RB - 1) / p.RB);
+    const int64_t tiles = (int64_t)p.nb * (p.nb + 1) / 2;
+    const int64_t target = nr >= 4 ? 1024 : 2048;
+    int64_t S = (target + tiles - 1) / tiles;
+    S = std::min<int64_t>(S, std::max(1, p.RB / 64));
+    S = std::max<int64_t>(S, 1);
+    p.S = (int)S;
+    p.CL = (p.RB + p.S - 1) / p.S;
+    p.items = tiles * p.S;
+    return p;
+}
+
+size_t kernel_sym_ws_doubles(int64_t n, int d, int nr) {
+    const KsymPlan p = ksym_plan(n, d, nr);
+    return (size_t)p.nb * p.S * nr * (size_t)n;
+}
+
+// One step of the wave reduction towards lane 63 on a float64 value (the same
+// DPP move on both halves; rows outside row_mask read 0 and keep their value).
+template <int CTRL, int ROWMASK>
+RR_DEV double dpp_add(double v) {
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, CTRL, ROWMASK, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), CTRL, ROWMASK, 0xF, false);
+    return v + __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+// Sum over the 64 lanes, valid in lane 63: pairs and quads (quad_perm), half
+// rows (row_half_mirror), rows (row_mirror), then row 0 into 1 and 2 into 3
+// (row_bcast:15), then rows 0-1 into 2-3 (row_bcast:31).
+template <int M>
+RR_DEV void wave_sum_to63(double (&v)[M]) {
+#pragma unroll
+    for (int m = 0; m < M; ++m) v[m] = dpp_add<0xB1, 0xF>(v[m]);
+#pragma unroll
+    for (int m = 0; m < M; ++m) v[m] = dpp_add<0x4E, 0xF>(v[m]);
+#pragma unroll
+    for (int m = 0; m < M; ++m) v[m] = dpp_add<0x141, 0xF>(v[m]);
+#pragma unroll
+    for (int m = 0; m < M; ++m) v[m] = dpp_add<0x140, 0xF>(v[m]);
+#pragma unroll
+    for (int m = 0; m < M; ++m) v[m] = dpp_add<0x142, 0xA>(v[m]);
+#pragma unroll
+    for (int m = 0; m < M; ++m) v[m] = dpp_add<0x143, 0xC>(v[m]);
+}
+
+// JB points [j, j + JB) of one item.  OFFD adds column sums.
+template <int KIND, int DM, int NR, int R, int JB, bool OFFD>
+RR_DEV void ksym_step(int64_t n, const float* __restrict__ xa, const float* __restrict__ sqn,
+                      float c, const double* __restrict__ u, int64_t j, int64_t c0,
+                      const float (&xi)[R][DM], const float (&mhn)[R],
+                      const double (&ui)[R][NR], double (&acc)[R][NR], double* colw, int lane) {
+    double cp[JB * NR];
+#pragma unroll
+    for (int jb = 0; jb < JB; ++jb) {
+        const int64_t jj = j + jb;
+        const float nj = sqn[jj];
+        double uj[NR];
+#pragma unroll
+        for (int q = 0; q < NR; ++q) uj[q] = u[(int64_t)q * n + jj];
+        float s[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) s[r] = kpair_init(mhn[r], nj);
+        const float* xj = xa + jj * DM;
+#pragma unroll
+        for (int k = 0; k < DM; ++k) {
+            const float xjk = xj[k];
+#pragma unroll
+            for (int r = 0; r < R; ++r) s[r] = fmaf(xi[r][k], xjk, s[r]);
+        }
+        double kv[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) kv[r] = (double)kval32<KIND>(s[r], c);
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int q = 0; q < NR; ++q) acc[r][q] = fma(kv[r], uj[q], acc[r][q]);
+        if (OFFD) {
+#pragma unroll
+            for (int q = 0; q < NR; ++q) {
+                double t = 0.0;
+#pragma unroll
+                for (int r = 0; r < R; ++r) t = fma(kv[r], ui[r][q], t);
+                cp[jb * NR + q] = t;
+            }
+        }
+    }
+    if (OFFD) {
+        wave_sum_to63<JB * NR>(cp);
+        if (lane == 63) {
+            const int base = (int)(j - c0) * NR;
+#pragma unroll
+            for (int m = 0; m < JB * NR; ++m) colw[base + m] = cp[m];
+        }
+    }
+}
+
+template <int KIND, int DM, int NR, bool OFFD>
+RR_DEV void ksym_columns(int64_t n, const float* __restrict__ xa,
+                         const float* __restrict__ sqn, float c, const double* __restrict__ u,
+                         double* __restrict__ part, int64_t cb, int64_t ce, int64_t colslot,
+                         const float (&xi)[ksym_rows_ct(DM, NR)][DM],
+                         const float (&mhn)[ksym_rows_ct(DM, NR)],
+                         const double (&ui)[ksym_rows_ct(DM, NR)][NR],
+                         double (&acc)[ksym_rows_ct(DM, NR)][NR],
+                         double (*colw)[ks_chunk_ct(NR) * NR]) {
+    constexpr int CH = ks_chunk_ct(NR);
+    constexpr int R = ksym_rows_ct(DM, NR);
+    constexpr int JB = ksym_jb_ct(DM, NR);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int64_t c0 = cb; c0 < ce; c0 += CH) {
+        const int64_t c1 = (c0 + CH < ce) ? c0 + CH : ce;
+        int64_t j = c0;
+        for (; j + JB <= c1; j += JB)
+            ksym_step<KIND, DM, NR, R, JB, OFFD>(n, xa, sqn, c, u, j, c0, xi, mhn, ui, acc, colw[wave],
+                                                 lane);
+        for (; j < c1; ++j)
+            ksym_step<KIND, DM, NR, R, 1, OFFD>(n, xa, sqn, c, u, j, c0, xi, mhn, ui, acc, colw[wave],
+                                                lane);
+        if (OFFD) {
+            __syncthreads();
+            const int64_t jj = c0 + threadIdx.x;
+            if (threadIdx.x < CH && jj < c1) {
+#pragma unroll
+                for (int q = 0; q < NR; ++q) {
+                    const int e = threadIdx.x * NR + q;
+                    const double v = (colw[0][e] + colw[1][e]) + (colw[2][e] + colw[3][e]);
+                    part[(colslot * NR + q) * n + jj] = v;
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+template <int KIND, int DM, int NR>
+__global__ __launch_bounds__(KS_THREADS) void k_ksym_f32(int64_t n, const float* __restrict__ xa,
+                                                         const float* __restrict__ sqn, float c,
+                                                         const double* __restrict__ u,
+                                                         double* __restrict__ part, int nb, int S,
+                                                         int CL, const int32_t* __restrict__ stop) {
+    if (stop && *stop) return;
+    constexpr int R = ksym_rows_ct(DM, NR);
+    constexpr int RB = KS_THREADS * R;
+    __shared__ double colw[4][ks_chunk_ct(NR) * NR];
+
+    // item -> (bi, bj, s): tiles enumerated row by row over the upper triangle
+    int64_t t = blockIdx.x / S;
+    const int s = (int)(blockIdx.x - t * S);
+    int bi = 0;
+    while (t >= nb - bi) { t -= nb - bi; ++bi; }
+    const int bj = bi + (int)t;
+    const int64_t row0 = (int64_t)bi * RB;
+    const int64_t cb = (int64_t)bj * RB + (int64_t)s * CL;
+    int64_t ce = cb + CL;
+    if (ce > (int64_t)(bj + 1) * RB) ce = (int64_t)(bj + 1) * RB;
+    if (ce > n) ce = n;
+
+    float xi[R][DM];
+    float mhn[R];
+    double ui[R][NR];
+    double acc[R][NR];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t i = row0 + (int64_t)r * KS_THREADS + threadIdx.x;
+        const int64_t ic = i < n ? i : n - 1;
+#pragma unroll
+        for (int k = 0; k < DM; ++k) xi[r][k] = xa[ic * DM + k];
+        mhn[r] = -0.5f * sqn[ic];
+#pragma unroll
+        for (int q = 0; q < NR; ++q) {
+            ui[r][q] = i < n ? u[(int64_t)q * n + i] : 0.0;
+            acc[r][q] = 0.0;
+        }
+    }
+    if (bj != bi)
+        ksym_columns<KIND, DM, NR, true>(n, xa, sqn, c, u, part, cb, ce, (int64_t)bi * S, xi, mhn,
+                                        ui, acc, colw);
+    else
+        ksym_columns<KIND, DM, NR, false>(n, xa, sqn, c, u, part, cb, ce, 0, xi, mhn, ui, acc,
+                                         colw);
+    const int64_t rslot = (int64_t)bj * S + s;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t i = row0 + (int64_t)r * KS_THREADS + threadIdx.x;
+        if (i < n)
+#pragma unroll
+            for (int q = 0; q < NR; ++q) part[(rslot * NR + q) * n + i] = acc[r][q];
+    }
+}
+
+// y_q = scale * (sum of the row's slots) + mu u_q, with partials of u_q^T y_q.
+__global__ __launch_bounds__(256) void k_ksym_finish(int64_t n, int RB, int nb, int S, int nr,
+                                                     const double* __restrict__ part, double scale,
+                                                     double mu, const double* __restrict__ u,
+                                                     double* __restrict__ y,
+                                                     double* __restrict__ dot_part,
+                                                     const int32_t* __restrict__ stop) {
+    __shared__ double sc[4];
+    if (stop && *stop) return;
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int b = (int)(i / RB);
+    for (int q = 0; q < nr; ++q) {
+        double dot = 0.0;
+        if (i < n) {
+            double s = 0.0;
+            for (int p = 0; p < b; ++p) s += part[((int64_t)p * S * nr + q) * n + i];
+            for (int64_t z = (int64_t)b * S; z < (int64_t)nb * S; ++z) s += part[(z * nr + q) * n + i];
+            const double ui = u[(int64_t)q * n + i];
+            const double yi = fma(scale, s, mu * ui);
+            y[(int64_t)q * n + i] = yi;
+            dot = ui * yi;
+        }
+        dot = block_sum(dot, sc);
+        if (threadIdx.x == 0) dot_part[(int64_t)q * gridDim.x + blockIdx.x] = dot;
+    }
+}
+
+template <int KIND, int NR>
+static void ksym_dispatch(const KernelOp& op, float c, const double* u, double* ws,
+                          const KsymPlan& p, const int32_t* stop, hipStream_t st) {
+    const unsigned grid = (unsigned)p.items;
+#define KSL(DD) k_ksym_f32<KIND, DD, NR><<<grid, KS_THREADS, 0, st>>>(op.n, op.xa, op.sqn, c, u, ws, p.nb, p.S, p.CL, stop)
+    switch (op.dm) {
+        case 4: KSL(4); break;
+        case 8: KSL(8); break;
+        case 16: KSL(16); break;
+        default: KSL(32); break;
+    }
+#undef KSL
+}
+
+// Stage 1 + finish for nr in {1, 2, 4, 8} columns (u, y column-major with leading dimension n).
+void launch_kernel_matvec_sym(const KernelOp& op, const double* u, int nr, double mu, double* y,
+                              double* dot_part, double* ws, const int32_t* stop, hipStream_t st) {
+    const KsymPlan p = ksym_plan(op.n, op.d, nr);
+    const float c = kernel_c32(op.kind, op.kconst);
+    {
+        ProfScope prof(nr == 1 ? PROF_KERNEL_MATVEC : -1, st);
+#define KSD(K)                                                   \
+    switch (nr) {                                                \
+        case 1: ksym_dispatch<K, 1>(op, c, u, ws, p, stop, st); break; \
+        case 2: ksym_dispatch<K, 2>(op, c, u, ws, p, stop, st); break; \
+        case 4: ksym_dispatch<K, 4>(op, c, u, ws, p, stop, st); break; \
+        default: ksym_dispatch<K, 8>(op, c, u, ws, p, stop, st); break; \
+    }
+        if (op.kind == 1) { KSD(1) } else { KSD(2) }
+#undef KSD
+    }
+    k_ksym_finish<<<(unsigned)((op.n + 255) / 256), 256, 0, st>>>(op.n, p.RB, p.nb, p.S, nr, ws,
+                                                                  op.scale, mu, u, y, dot_part, stop);
+}
+
+}  // namespace rr

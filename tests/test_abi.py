@@ -93,6 +93,17 @@ def test_kernel_operator_validation():
     assert L.rr_build_precond(C.byref(op), mus, 1, None, None, None, C.byref(h)) == b.RR_EINVAL
 
 
+def test_apply_operator_block_validation():
+    L = b.lib()
+    op = _dense_op()
+    buf = np.zeros(16)
+    p = buf.ctypes.data_as(C.c_void_p)
+    assert L.rr_apply_operator_block(C.byref(op), 0.0, b.PREC_FP64, p, 0, p, None) == b.RR_EINVAL
+    assert L.rr_apply_operator_block(C.byref(op), 0.0, b.PREC_FP64, None, 1, p, None) == b.RR_EINVAL
+    assert L.rr_apply_operator_block(C.byref(op), float("nan"), b.PREC_FP64, p, 1, p, None) == b.RR_EINVAL
+    assert L.rr_apply_operator_block(C.byref(op), 0.0, 7, p, 1, p, None) == b.RR_EINVAL
+
+
 def test_solve_rejects_null_handle_and_bad_tol():
     L = b.lib()
     info = b.rr_solve_info()

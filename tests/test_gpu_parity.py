@@ -74,6 +74,44 @@ def test_kernel_matvec(kind, n, d):
     assert np.linalg.norm(y32 - ref) <= 2e-6 * np.linalg.norm(ref)
 
 
+@pytest.mark.parametrize("kind", [rr.OP_RBF, rr.OP_MATERN32])
+@pytest.mark.parametrize("n,d,nr", [(5000, 16, 1), (5000, 16, 2), (4100, 5, 3), (3001, 20, 5),
+                                    (4500, 8, 8), (2600, 4, 13)])
+def test_kernel_matvec_block_multi_tile(kind, n, d, nr):
+    # several row blocks with a ragged last block: the symmetric float32 path forms
+    # off-diagonal block pairs once and scatters them to rows and columns
+    rng = np.random.default_rng(7 * n + d + nr)
+    pts = rng.standard_normal((d, n)).astype(np.float32)
+    kconst, scale, mu = 0.5 / d, 1.0 / n, 1e-3
+    op = Operator(kind=kind, pts=pts, kconst=kconst, scale=scale)
+    U = rng.standard_normal((n, nr))
+    ref = op.matmat(U) + mu * U
+    kop = rr.kernel_operator(kind, _cuda(pts), kconst, scale)
+    Y32 = rr.apply_operator_block(kop, mu, "fp32", _cuda(U)).cpu().numpy()
+    for q in range(nr):
+        assert np.linalg.norm(Y32[:, q] - ref[:, q]) <= 2e-6 * np.linalg.norm(ref[:, q]), q
+    Y64 = rr.apply_operator_block(kop, mu, "fp64", _cuda(U)).cpu().numpy()
+    assert np.linalg.norm(Y64 - ref) <= 1e-12 * np.linalg.norm(ref)
+    # a block product equals the column-by-column products bitwise
+    y0 = rr.apply_operator(kop, mu, "fp32", _cuda(U[:, 0].copy())).cpu().numpy()
+    if nr == 1:
+        assert np.array_equal(y0, Y32[:, 0])
+
+
+def test_kernel_fp32_operator_symmetric_multi_tile():
+    # float32 entries of different row blocks are formed once: K e_j and K e_i agree
+    n, d = 2600, 16
+    rng = np.random.default_rng(2)
+    pts = rng.standard_normal((d, n)).astype(np.float32)
+    kop = rr.kernel_operator(rr.OP_RBF, _cuda(pts), 0.05, 1.0)
+    E = torch.eye(n, dtype=torch.float64, device="cuda")
+    K = rr.apply_operator_block(kop, 0.0, "fp32", E).cpu().numpy()
+    assert np.array_equal(K, K.T)
+    ref = Operator(kind=rr.OP_RBF, pts=pts, kconst=0.05, scale=1.0).to_dense()
+    # |s| error <= (d+1) 2^-24 (|x_i|^2 + |x_j|^2 + |x_i.x_j|) ~ 3e-5, times the exponent's c ln 2
+    assert np.max(np.abs(K - ref)) <= 1e-5
+
+
 def test_kernel_fp32_operator_symmetric():
     # float32 entries are formed bitwise-symmetrically: e_i^T K e_j == e_j^T K e_i
     n, d = 300, 16
