@@ -105,7 +105,11 @@ struct Builder {
         P.Omega.reset(al, (size_t)n * l * oes);
         const bool bf16_omega = (kernel && f32path) || (!kernel && o.prec == RR_PREC_MIXED);
         ldo = (n + 7) / 8 * 8;
-        if (bf16_omega) ob_buf.reset(al, (size_t)ldo * l * 2);
+        if (bf16_omega) {
+            // padding rows [n, ldo) stay zero: the bf16 MFMA sketches read whole 8-row chunks
+            ob_buf.reset(al, (size_t)ldo * l * 2);
+            RR_HIP(hipMemsetAsync(ob_buf.ptr(), 0, (size_t)ldo * l * 2, st));
+        }
         void* gen = bf16_omega ? ob_buf.ptr() : P.Omega.ptr();
         const int gdt = bf16_omega ? DT_BF16 : P.omega_dt;
         const int64_t gld = bf16_omega ? ldo : n;
@@ -130,8 +134,12 @@ struct Builder {
         const int64_t n = P.n, l = P.l;
         if (is_kernel(P.op)) {
             const KernelOp k = kernel_op_of(P);
-            if (ydt == DT_F32) launch_kernel_gemm_bf16x2(k, Ob, ldo, l, mu, (float*)Y, n, st);
-            else launch_kernel_gemm_f64(k, (const double*)Om, n, l, mu, (double*)Y, n, st);
+            if (ydt == DT_F32) {
+                DBuf ws(al, (kernel_sketch_ws_floats(n, l) + 1) * sizeof(float));
+                launch_kernel_gemm_bf16x2(k, Ob, ldo, l, mu, (float*)Y, n, ws.as<float>(), st);
+            } else {
+                launch_kernel_gemm_f64(k, (const double*)Om, n, l, mu, (double*)Y, n, st);
+            }
             check_launch();
             return;
         }

@@ -125,10 +125,13 @@ void launch_kernel_matvec_sym(const KernelOp& op, const double* u, int nr, doubl
 void launch_sqnorms(const float* pts, int64_t n, int d, float* sqn, hipStream_t st);
 // Dense formation A_out = scale*K in float64 (dtype 0) / float32 (1) / bf16 (2).
 void launch_kernel_to_dense(const KernelOp& op, void* out, int dtype, int64_t lda, hipStream_t st);
-// Kernel-GEMM on BF16 MFMA with hi/lo-split kernel entries; B (n x m, ldb, a
-// multiple of 8) holds bf16 values (the test matrix, exact in bf16); Y float32.
+// Kernel-GEMM on BF16 MFMA with hi/lo-split kernel entries; B (n x m, ldb a
+// multiple of 8 and >= round8(n), rows [n, round8(n)) zero) holds bf16 values
+// (the test matrix, exact in bf16); Y float32.
 void launch_kernel_gemm_bf16x2(const KernelOp& op, const void* Bbf16, int64_t ldb, int64_t m,
-                               double mu, float* Y, int64_t ldy, hipStream_t st);
+                               double mu, float* Y, int64_t ldy, float* ws, hipStream_t st);
+// Workspace (floats) of launch_kernel_gemm_bf16x2 for n points and m columns (0: none).
+size_t kernel_sketch_ws_floats(int64_t n, int64_t m);
 // Same in float64 on the vector ALU (small problems / float64 mode).
 void launch_kernel_gemm_f64(const KernelOp& op, const double* B, int64_t ldb, int64_t m,
                             double mu, double* Y, int64_t ldy, hipStream_t st);

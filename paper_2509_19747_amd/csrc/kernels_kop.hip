@@ -7,8 +7,7 @@
 //      float64 entries: k_kmv_f64 below; rows are split over (row block,
 //      j slice), each slice writes partial row sums, and a second kernel adds
 //      them in a fixed order (deterministic).
-//  * k_kgemm_bf16x2 : Y = scale*K B + mu B for the float32-mode sketch A_mu Omega
-//      with a bf16 Omega, on bf16 MFMA with the kernel tile split hi + lo.
+//  * the float32-mode sketch A_mu Omega on bf16 MFMA is in kernels_ksketch.hip.
 //  * k_kgemm_f64    : float64 vector-ALU variant (float64 mode).
 //
 // Entry formulas are in kentry.hpp (the float32 entry is bitwise symmetric).
@@ -242,173 +241,6 @@ void launch_kernel_to_dense(const KernelOp& op, void* out, int dtype, int64_t ld
         if (dtype == DT_F64) KTD(2, double); else if (dtype == DT_F32) KTD(2, float); else KTD(2, __hip_bfloat16);
     }
 #undef KTD
-}
-
-// ================================ kernel-GEMM on BF16 MFMA with a split kernel tile
-// Y[i, c] = scale * sum_j K(x_i, x_j) B[j, c] + mu B[i, c] for a test matrix B whose
-// entries are exact in bf16 (SRHT +-1, or a Gaussian drawn in bf16).  Each float32
-// kernel entry is split into hi = bf16(k) and lo = bf16(k - hi) (about 16
-// significant bits together) and both parts go through v_mfma_f32_16x16x32_bf16
-// with float32 accumulation.  Block: 512 threads = 8 waves, tile 128 rows x 512
-// columns (all l <= 512 columns at once, so every kernel entry is formed once);
-// wave w owns rows 64*(w&1)..+63 and columns 128*(w>>1)..+127 (4 x 8 MFMA tiles).
-// Per step of 32 points the block forms the 128 x 32 kernel tile in LDS (each
-// thread: one row, 8 consecutive points, one 16-byte store per part) and stages
-// the 32 x 512 bf16 slice of B column-major in LDS.  The MFMA operands use one
-// consistent k order for A and B (lane l holds k = 8*(l/16) .. +7), which is all
-// the product needs.
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-constexpr int KB_BM = 128, KB_BN = 512, KB_BK = 32, KB_THREADS = 512;
-constexpr int KB_AS = 40;   // padded LDS row length (bf16) of the kernel tile
-constexpr int KB_BS = 40;   // padded LDS column length (bf16) of the B slice
-
-RR_DEV uint32_t bf16_rne_bits(float f) {
-    const uint32_t u = __float_as_uint(f);
-    return (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
-}
-
-template <int KIND, int D>
-__global__ __launch_bounds__(KB_THREADS) void k_kgemm_bf16x2(int64_t n, int dd,
-                                                             const float* __restrict__ pts,
-                                                             const float* __restrict__ sqn, float c,
-                                                             float scale, float mu,
-                                                             const uint16_t* __restrict__ Bm,
-                                                             int64_t ldb, int64_t m,
-                                                             float* __restrict__ Y, int64_t ldy) {
-    constexpr int DM = D > 0 ? D : 32;
-    const int d = D > 0 ? D : dd;
-    __shared__ __attribute__((aligned(16))) uint16_t As_hi[KB_BM * KB_AS];
-    __shared__ __attribute__((aligned(16))) uint16_t As_lo[KB_BM * KB_AS];
-    __shared__ __attribute__((aligned(16))) uint16_t Bs[KB_BN * KB_BS];
-    const int t = threadIdx.x;
-    const int lane = t & 63, wave = t >> 6;
-    const int rh = wave & 1, cq = wave >> 1;
-    const int64_t i0 = (int64_t)blockIdx.x * KB_BM;
-    const int64_t c0 = (int64_t)blockIdx.y * KB_BN;
-
-    // tile-formation role: one row, 8 consecutive points
-    const int trow = t & (KB_BM - 1);
-    const int pg = __builtin_amdgcn_readfirstlane(t >> 7);   // wave-uniform point group 0..3
-    const int64_t gi = i0 + trow;
-    const int64_t gic = gi < n ? gi : n - 1;
-    float xi[DM];
-#pragma unroll
-    for (int k = 0; k < DM; ++k) xi[k] = (k < d) ? pts[(int64_t)k * n + gic] : 0.0f;
-    const float ni = sqn[gic];
-
-    f32x4 acc[4][8];
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int v = 0; v < 8; ++v) acc[u][v] = f32x4{0.f, 0.f, 0.f, 0.f};
-
-    for (int64_t j0 = 0; j0 < n; j0 += KB_BK) {
-        // ---- kernel tile: rows trow, points j0 + 8*pg + e
-        {
-            uint32_t hi2[4], lo2[4];
-#pragma unroll
-            for (int e2 = 0; e2 < 4; ++e2) {
-                uint32_t hb[2], lb[2];
-#pragma unroll
-                for (int h = 0; h < 2; ++h) {
-                    const int64_t gj = j0 + 8 * pg + 2 * e2 + h;
-                    float kv = 0.0f;
-                    if (gj < n && gi < n) {
-                        float sv = kpair_init(-0.5f * ni, sqn[gj]);
-#pragma unroll
-                        for (int k = 0; k < DM; ++k)
-                            if (k < d) sv = fmaf(xi[k], pts[(int64_t)k * n + gj], sv);
-                        kv = kval32<KIND>(sv, c);
-                    }
-                    const uint32_t hbits = bf16_rne_bits(kv);
-                    const float hf = __uint_as_float(hbits << 16);
-                    hb[h] = hbits;
-                    lb[h] = bf16_rne_bits(kv - hf);
-                }
-                hi2[e2] = hb[0] | (hb[1] << 16);
-                lo2[e2] = lb[0] | (lb[1] << 16);
-            }
-            *(uint4*)&As_hi[trow * KB_AS + 8 * pg] = make_uint4(hi2[0], hi2[1], hi2[2], hi2[3]);
-            *(uint4*)&As_lo[trow * KB_AS + 8 * pg] = make_uint4(lo2[0], lo2[1], lo2[2], lo2[3]);
-        }
-        // ---- B slice: Bs[col][k] = B[j0 + k, c0 + col]
-#pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            const int q = t + KB_THREADS * s;    // 0..2047
-            const int col = q >> 2, part = q & 3;
-            const int64_t gc = c0 + col;
-            const int64_t gj = j0 + 8 * part;
-            uint4 v = make_uint4(0u, 0u, 0u, 0u);
-            if (gc < m) {
-                const uint16_t* src = Bm + gc * ldb + gj;
-                if (gj + 8 <= n) {
-                    v = *(const uint4*)src;
-                } else if (gj < n) {
-                    uint32_t w[4] = {0u, 0u, 0u, 0u};
-                    for (int e = 0; e < 8 && gj + e < n; ++e) w[e >> 1] |= (uint32_t)src[e] << (16 * (e & 1));
-                    v = make_uint4(w[0], w[1], w[2], w[3]);
-                }
-            }
-            *(uint4*)&Bs[col * KB_BS + 8 * part] = v;
-        }
-        __syncthreads();
-        bf16x8 ah[4], al[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int row = rh * 64 + u * 16 + (lane & 15);
-            ah[u] = __builtin_bit_cast(bf16x8, *(const uint4*)&As_hi[row * KB_AS + 8 * (lane >> 4)]);
-            al[u] = __builtin_bit_cast(bf16x8, *(const uint4*)&As_lo[row * KB_AS + 8 * (lane >> 4)]);
-        }
-#pragma unroll
-        for (int v = 0; v < 8; ++v) {
-            const int col = cq * 128 + v * 16 + (lane & 15);
-            const bf16x8 bv = __builtin_bit_cast(bf16x8, *(const uint4*)&Bs[col * KB_BS + 8 * (lane >> 4)]);
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                acc[u][v] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[u], bv, acc[u][v], 0, 0, 0);
-                acc[u][v] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[u], bv, acc[u][v], 0, 0, 0);
-            }
-        }
-        __syncthreads();
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-#pragma unroll
-        for (int v = 0; v < 8; ++v) {
-            const int64_t gc = c0 + cq * 128 + v * 16 + (lane & 15);
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int64_t gr = i0 + rh * 64 + u * 16 + 4 * (lane >> 4) + e;
-                if (gr < n && gc < m) {
-                    const float bval = __uint_as_float((uint32_t)Bm[gc * ldb + gr] << 16);
-                    Y[gr + gc * ldy] = fmaf(scale, acc[u][v][e], mu * bval);
-                }
-            }
-        }
-    }
-}
-
-template <int KIND>
-static void kgemm_bf16_dispatch(const KernelOp& op, float c, const uint16_t* B, int64_t ldb,
-                                int64_t m, float mu, float* Y, int64_t ldy, hipStream_t st) {
-    dim3 grid((unsigned)((op.n + KB_BM - 1) / KB_BM), (unsigned)((m + KB_BN - 1) / KB_BN));
-    const float sc = (float)op.scale;
-    switch (op.d) {
-        case 3: k_kgemm_bf16x2<KIND, 3><<<grid, KB_THREADS, 0, st>>>(op.n, 3, op.pts, op.sqn, c, sc, mu, B, ldb, m, Y, ldy); break;
-        case 4: k_kgemm_bf16x2<KIND, 4><<<grid, KB_THREADS, 0, st>>>(op.n, 4, op.pts, op.sqn, c, sc, mu, B, ldb, m, Y, ldy); break;
-        case 8: k_kgemm_bf16x2<KIND, 8><<<grid, KB_THREADS, 0, st>>>(op.n, 8, op.pts, op.sqn, c, sc, mu, B, ldb, m, Y, ldy); break;
-        case 16: k_kgemm_bf16x2<KIND, 16><<<grid, KB_THREADS, 0, st>>>(op.n, 16, op.pts, op.sqn, c, sc, mu, B, ldb, m, Y, ldy); break;
-        default: k_kgemm_bf16x2<KIND, 0><<<grid, KB_THREADS, 0, st>>>(op.n, op.d, op.pts, op.sqn, c, sc, mu, B, ldb, m, Y, ldy); break;
-    }
-}
-
-void launch_kernel_gemm_bf16x2(const KernelOp& op, const void* Bbf16, int64_t ldb, int64_t m,
-                               double mu, float* Y, int64_t ldy, hipStream_t st) {
-    const float c = kernel_c32(op.kind, op.kconst);
-    ProfScope prof(PROF_KERNEL_SKETCH, st);
-    if (op.kind == 1) kgemm_bf16_dispatch<1>(op, c, (const uint16_t*)Bbf16, ldb, m, (float)mu, Y, ldy, st);
-    else kgemm_bf16_dispatch<2>(op, c, (const uint16_t*)Bbf16, ldb, m, (float)mu, Y, ldy, st);
 }
 
 // ================================================ kernel-GEMM, float64 VALU

@@ -1,0 +1,294 @@
+// Kernel sketch on bf16 MFMA: Y = scale * K Omega + mu Omega (the sketch
+// A_mu Omega of Algorithm RandRAND_PCG, step 2, for a kernel operator in
+// float32 mode).  Omega's entries are exact in bf16 (SRHT +-1, or a Gaussian
+// drawn in bf16); each float32 kernel entry is split into hi = bf16(k) and
+// lo = bf16(k - hi) (about 16 significant bits together) and both parts go
+// through v_mfma_f32_32x32x16_bf16 with float32 accumulation (the 32x32x16
+// form sustains close to the bf16 peak; 16x16x32 about half of it).
+//
+// Block: 512 threads = 8 waves, tile 128 rows x 512 columns (l <= 512 in one
+// column tile, so every kernel entry is formed once per row tile); wave w owns
+// rows 64*(w&1)..+63 and columns 128*((w>>1)&3)..+127 (2 x 4 MFMA tiles of
+// 32 x 32).  Per step of 32 points the block forms the 128 x 32 kernel tile
+// (thread: one row, 8 consecutive points whose records arrive through scalar
+// loads) and stages the 32 x 512 slice of Omega in LDS (thread t: column t,
+// loaded into registers one step ahead).  The tiles are double-buffered: while
+// a step's MFMAs run, the next step's tile is formed.  Waves 0-3 issue the
+// MFMAs first and waves 4-7 the tile formation first, so the two waves that
+// share a SIMD keep its matrix core and its vector ALU busy at the same time.
+// The point range may be split over several blocks (split-K) to fill the GPU
+// evenly; partial sums then go to a workspace and a second kernel adds them in
+// a fixed order.  The MFMA operands use one consistent k order for A and B
+// (lane l holds k = 8*(l/32) .. +7 of a 16-point half step), which is all the
+// product needs.  Accumulator element j of lane l is row 8*(j/4) + 4*(l/32) +
+// (j%4), column l%32 of its 32 x 32 tile.
+#include "common.hpp"
+#include "kentry.hpp"
+#include "kernels.hpp"
+#include "prof.hpp"
+
+#include <algorithm>
+
+namespace rr {
+
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float f32x16_t __attribute__((ext_vector_type(16)));
+constexpr int KS2_BM = 128, KS2_BN = 512, KS2_BK = 32, KS2_THREADS = 512;
+constexpr int KS2_AS = 40;   // padded LDS row length (bf16) of the kernel tile
+constexpr int KS2_BS = 40;   // padded LDS column length (bf16) of the Omega slice
+
+struct Ks2Smem {
+    uint16_t a_hi[2][KS2_BM * KS2_AS];
+    uint16_t a_lo[2][KS2_BM * KS2_AS];
+    uint16_t b[2][KS2_BN * KS2_BS];
+};
+
+RR_DEV uint32_t bf16_bits(float f) { return (uint32_t)__builtin_bit_cast(uint16_t, (__bf16)f); }
+
+// Kernel tile of step k0 into buffer `buf`: row trow, points k0 + 8*g + e for
+// e = 0..7 (one 16-byte store per part).  FULL: all 32 points of the step are
+// < n (no clamping or masking).
+template <int KIND, int DM, bool FULL>
+RR_DEV void ks2_form_t(Ks2Smem& sm, int buf, int64_t n, const float* __restrict__ xa,
+                       const float* __restrict__ sqn, float c, int64_t k0, int trow, int g,
+                       const float (&xi)[DM], float mhn) {
+    const int64_t jb = k0 + 8 * g;
+    const float* xj0 = xa + jb * DM;
+    const float* nj0 = sqn + jb;
+    uint32_t hi2[4], lo2[4];
+#pragma unroll
+    for (int e2 = 0; e2 < 4; ++e2) {
+        uint32_t hb[2], lb[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int e = 2 * e2 + h;
+            const float* xj;
+            float nj;
+            if (FULL) {
+                xj = xj0 + e * DM;
+                nj = nj0[e];
+            } else {
+                const int64_t gjc = jb + e < n ? jb + e : n - 1;
+                xj = xa + gjc * DM;
+                nj = sqn[gjc];
+            }
+            float sv = kpair_init(mhn, nj);
+#pragma unroll
+            for (int k = 0; k < DM; ++k) sv = fmaf(xi[k], xj[k], sv);
+            float kv = kval32<KIND>(sv, c);
+            if (!FULL) kv = jb + e < n ? kv : 0.0f;
+            const uint32_t hbits = bf16_bits(kv);
+            hb[h] = hbits;
+            lb[h] = bf16_bits(kv - __uint_as_float(hbits << 16));
+        }
+        hi2[e2] = hb[0] | (hb[1] << 16);
+        lo2[e2] = lb[0] | (lb[1] << 16);
+    }
+    *(uint4*)&sm.a_hi[buf][trow * KS2_AS + 8 * g] = make_uint4(hi2[0], hi2[1], hi2[2], hi2[3]);
+    *(uint4*)&sm.a_lo[buf][trow * KS2_AS + 8 * g] = make_uint4(lo2[0], lo2[1], lo2[2], lo2[3]);
+}
+template <int KIND, int DM>
+RR_DEV void ks2_form(Ks2Smem& sm, int buf, int64_t n, const float* __restrict__ xa,
+                     const float* __restrict__ sqn, float c, int64_t k0, int trow, int g,
+                     const float (&xi)[DM], float mhn) {
+    if (k0 + KS2_BK <= n) ks2_form_t<KIND, DM, true>(sm, buf, n, xa, sqn, c, k0, trow, g, xi, mhn);
+    else ks2_form_t<KIND, DM, false>(sm, buf, n, xa, sqn, c, k0, trow, g, xi, mhn);
+}
+
+// Omega slice of one step: thread t owns column c0 + t and its 32 points, as
+// four 16-byte chunks (global loads into registers one step ahead; the LDS
+// store of consecutive columns hits distinct banks).  B's rows [n, round8(n))
+// are zero, so a chunk is either inside the padded column or wholly past it.
+RR_DEV void ks2_load_b(const uint16_t* src, int64_t npad, int64_t k0, uint4 (&rb)[4]) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const int64_t gj = k0 + 8 * s;
+        rb[s] = (src && gj < npad) ? *(const uint4*)(src + gj) : make_uint4(0u, 0u, 0u, 0u);
+    }
+}
+RR_DEV void ks2_store_b(Ks2Smem& sm, int buf, int t, const uint4 (&rb)[4]) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) *(uint4*)&sm.b[buf][t * KS2_BS + 8 * s] = rb[s];
+}
+
+// One step of MFMAs for the wave's 64 x 128 tile, in two half steps of 16 points.
+RR_DEV void ks2_mfma(const Ks2Smem& sm, int buf, int lane, int rh, int cq, f32x16_t (&acc)[2][4]) {
+    const int kq = 8 * (lane >> 5);
+#pragma unroll
+    for (int kh = 0; kh < 2; ++kh) {
+        __builtin_amdgcn_sched_barrier(0);
+        bf16x8_t ah[2], al[2], bv[4];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int row = rh * 64 + u * 32 + (lane & 31);
+            ah[u] = __builtin_bit_cast(bf16x8_t, *(const uint4*)&sm.a_hi[buf][row * KS2_AS + 16 * kh + kq]);
+            al[u] = __builtin_bit_cast(bf16x8_t, *(const uint4*)&sm.a_lo[buf][row * KS2_AS + 16 * kh + kq]);
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int col = cq * 128 + v * 32 + (lane & 31);
+            bv[v] = __builtin_bit_cast(bf16x8_t, *(const uint4*)&sm.b[buf][col * KS2_BS + 16 * kh + kq]);
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                acc[u][v] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[u], bv[v], acc[u][v], 0, 0, 0);
+                acc[u][v] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[u], bv[v], acc[u][v], 0, 0, 0);
+            }
+    }
+}
+
+// part == nullptr: Y = scale * acc + mu * B.  Otherwise part[z] (n x m, leading
+// dimension n) = acc over the block's point range [z*kper, (z+1)*kper).
+template <int KIND, int DM>
+__global__ __launch_bounds__(KS2_THREADS) void k_ksketch_bf16x2(
+    int64_t n, const float* __restrict__ xa, const float* __restrict__ sqn, float c, float scale,
+    float mu, const uint16_t* __restrict__ Bm, int64_t ldb, int64_t m, float* __restrict__ Y,
+    int64_t ldy, int64_t kper, float* __restrict__ part) {
+    __shared__ __attribute__((aligned(16))) Ks2Smem sm;
+    const int t = threadIdx.x;
+    const int lane = t & 63, wave = t >> 6;
+    const int rh = wave & 1, cq = (wave >> 1) & 3;
+    const bool mfma_first = (wave >> 2) == 0;
+    const int64_t i0 = (int64_t)blockIdx.x * KS2_BM;
+    const int64_t c0 = (int64_t)blockIdx.y * KS2_BN;
+    const int64_t kb = (int64_t)blockIdx.z * kper;
+    const int64_t ke = (kb + kper < n) ? kb + kper : n;
+
+    const int trow = t & (KS2_BM - 1);
+    const int pg = __builtin_amdgcn_readfirstlane(t >> 7);   // wave-uniform point group 0..3
+    const int64_t gi = i0 + trow;
+    const int64_t gic = gi < n ? gi : n - 1;
+    float xi[DM];
+#pragma unroll
+    for (int k = 0; k < DM; ++k) xi[k] = xa[gic * DM + k];
+    const float mhn = -0.5f * sqn[gic];
+
+    f32x16_t acc[2][4];
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+#pragma unroll
+            for (int j = 0; j < 16; ++j) acc[u][v][j] = 0.0f;
+
+    const uint16_t* bsrc = (c0 + t < m) ? Bm + (c0 + t) * ldb : nullptr;
+    const int64_t npad = (n + 7) & ~(int64_t)7;   // B rows [n, npad) hold zeros
+    uint4 rb[4];
+    if (kb < ke) {
+        ks2_load_b(bsrc, npad, kb, rb);
+        ks2_store_b(sm, 0, t, rb);
+        ks2_form<KIND, DM>(sm, 0, n, xa, sqn, c, kb, trow, pg, xi, mhn);
+        if (kb + KS2_BK < ke) ks2_load_b(bsrc, npad, kb + KS2_BK, rb);
+    }
+    __syncthreads();
+    int buf = 0;
+    for (int64_t k0 = kb; k0 < ke; k0 += KS2_BK) {
+        const int64_t k1 = k0 + KS2_BK, k2 = k0 + 2 * KS2_BK;
+        // one copy of the MFMA block (the accumulators stay in place); the next
+        // step's staging runs before it on waves 4-7 and after it on waves 0-3
+        if (!mfma_first && k1 < ke) {
+            ks2_store_b(sm, buf ^ 1, t, rb);
+            if (k2 < ke) ks2_load_b(bsrc, npad, k2, rb);
+            ks2_form<KIND, DM>(sm, buf ^ 1, n, xa, sqn, c, k1, trow, pg, xi, mhn);
+        }
+        ks2_mfma(sm, buf, lane, rh, cq, acc);
+        if (mfma_first && k1 < ke) {
+            ks2_store_b(sm, buf ^ 1, t, rb);
+            if (k2 < ke) ks2_load_b(bsrc, npad, k2, rb);
+            ks2_form<KIND, DM>(sm, buf ^ 1, n, xa, sqn, c, k1, trow, pg, xi, mhn);
+        }
+        __syncthreads();
+        buf ^= 1;
+    }
+    float* out = part ? part + (int64_t)blockIdx.z * ldy * m : Y;
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int64_t gc = c0 + cq * 128 + v * 32 + (lane & 31);
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                const int64_t gr = i0 + rh * 64 + u * 32 + 8 * (j >> 2) + 4 * (lane >> 5) + (j & 3);
+                if (gr < n && gc < m) {
+                    if (part) {
+                        out[gr + gc * ldy] = acc[u][v][j];
+                    } else {
+                        const float bval = __uint_as_float((uint32_t)Bm[gc * ldb + gr] << 16);
+                        out[gr + gc * ldy] = fmaf(scale, acc[u][v][j], mu * bval);
+                    }
+                }
+            }
+        }
+    }
+}
+
+// Y = scale * sum_z part[z] + mu * B, the splits added in order.
+__global__ void k_ksketch_finish(int64_t n, int64_t m, int nsplit, const float* __restrict__ part,
+                                 float scale, float mu, const uint16_t* __restrict__ Bm, int64_t ldb,
+                                 float* __restrict__ Y, int64_t ldy) {
+    const int64_t total = n * m;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t c = e / n, i = e - c * n;
+        float s = 0.0f;
+        for (int z = 0; z < nsplit; ++z) s += part[(int64_t)z * ldy * m + i + c * ldy];
+        const float bval = __uint_as_float((uint32_t)Bm[c * ldb + i] << 16);
+        Y[i + c * ldy] = fmaf(scale, s, mu * bval);
+    }
+}
+
+// Number of point-range splits: fills whole rounds of the 256 compute units
+// (one block each) as evenly as possible, at most 4.
+static int ks2_splits(int64_t n, int64_t m) {
+    const int64_t tiles = ((n + KS2_BM - 1) / KS2_BM) * ((m + KS2_BN - 1) / KS2_BN);
+    const int64_t steps = (n + KS2_BK - 1) / KS2_BK;
+    int best = 1;
+    double best_eff = 0.0;
+    for (int s = 1; s <= 4; ++s) {
+        if (s > 1 && steps < 16 * s) break;
+        const int64_t items = tiles * s;
+        const int64_t rounds = (items + 255) / 256;
+        const double eff = (double)items / (double)(rounds * 256);
+        if (eff > best_eff + 0.03) { best_eff = eff; best = s; }
+    }
+    return best;
+}
+
+size_t kernel_sketch_ws_floats(int64_t n, int64_t m) {
+    const int s = ks2_splits(n, m);
+    return s > 1 ? (size_t)s * (size_t)n * (size_t)m : 0;
+}
+
+void launch_kernel_gemm_bf16x2(const KernelOp& op, const void* Bbf16, int64_t ldb, int64_t m,
+                               double mu, float* Y, int64_t ldy, float* ws, hipStream_t st) {
+    const float c = kernel_c32(op.kind, op.kconst);
+    const int ns = ks2_splits(op.n, m);
+    const int64_t steps = (op.n + KS2_BK - 1) / KS2_BK;
+    const int64_t kper = ((steps + ns - 1) / ns) * KS2_BK;
+    float* part = ns > 1 ? ws : nullptr;
+    dim3 grid((unsigned)((op.n + KS2_BM - 1) / KS2_BM), (unsigned)((m + KS2_BN - 1) / KS2_BN),
+              (unsigned)ns);
+    const uint16_t* B = (const uint16_t*)Bbf16;
+    const float sc = (float)op.scale, fmu = (float)mu;
+    ProfScope prof(PROF_KERNEL_SKETCH, st);
+#define KS2L(K, DD) k_ksketch_bf16x2<K, DD><<<grid, KS2_THREADS, 0, st>>>(op.n, op.xa, op.sqn, c, sc, fmu, B, ldb, m, Y, ldy, kper, part)
+#define KS2D(K)                              \
+    switch (op.dm) {                         \
+        case 4: KS2L(K, 4); break;           \
+        case 8: KS2L(K, 8); break;           \
+        case 16: KS2L(K, 16); break;         \
+        default: KS2L(K, 32); break;         \
+    }
+    if (op.kind == 1) { KS2D(1) } else { KS2D(2) }
+#undef KS2D
+#undef KS2L
+    if (part) {
+        int64_t g = (op.n * m + 255) / 256;
+        if (g > 16384) g = 16384;
+        k_ksketch_finish<<<(unsigned)g, 256, 0, st>>>(op.n, m, ns, part, sc, fmu, B, ldb, Y, ldy);
+    }
+}
+
+}  // namespace rr

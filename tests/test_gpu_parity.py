@@ -305,13 +305,17 @@ def test_deterministic_rerun():
     assert torch.equal(xs[0], xs[1])
 
 
-@pytest.mark.parametrize("n,l,sketch,prec", [
-    (3001, 200, "gaussian", "fp32"), (1100, 600, "srht", "fp32"), (700, 37, "gaussian", "fp32"),
-    (1100, 600, "srht", "fp64"), (257, 70, "gaussian", "fp64")])
-def test_kernel_sketch_matches_oracle(n, l, sketch, prec):
+@pytest.mark.parametrize("n,l,sketch,prec,d", [
+    (3001, 200, "gaussian", "fp32", 16), (1100, 600, "srht", "fp32", 16),
+    (700, 37, "gaussian", "fp32", 16), (2600, 130, "srht", "fp32", 5),
+    (1500, 513, "gaussian", "fp32", 20), (9000, 64, "srht", "fp32", 16),
+    (1100, 600, "srht", "fp64", 16), (257, 70, "gaussian", "fp64", 16)])
+def test_kernel_sketch_matches_oracle(n, l, sketch, prec, d):
     # the sketch step alone (Y = A Omega + mu Omega) against the float64 oracle with the
-    # same test matrix; float32 mode: bf16 hi/lo split entries -> |dY| <= 2^-15 |A||Omega|
-    prob = workloads.cfg_kernel_ridge(n=n, d=16, l=l)
+    # same test matrix; float32 mode: bf16 hi/lo split entries -> |dY| <= 2^-15 |A||Omega|.
+    # Sizes cover ragged row and column tiles, two column tiles (l > 512), padded
+    # point records (d = 5, 20) and split point ranges.
+    prob = workloads.cfg_kernel_ridge(n=n, d=d, l=l)
     mu = prob.mus[0]
     op = Operator.from_problem(prob)
     kop = rr.kernel_operator(rr.OP_RBF, _cuda(prob.pts), prob.kconst, prob.scale)
