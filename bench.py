@@ -171,12 +171,17 @@ def main():
 
     cg = None
     if not args.no_cg:
+        def cg_step():
+            P0 = rr.build_precond(kop, [mu], l=0, prec="fp32")
+            return P0.solve(b, tol=prob.tol, certify=False, use_graph=args.graph, check_every=8)
+        for _ in range(max(args.warmup, 1)):
+            cg_step()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        P0 = rr.build_precond(kop, [mu], l=0, prec="fp32")
-        x0, i0 = P0.solve(b, tol=prob.tol, certify=False, use_graph=args.graph, check_every=8)
+        for _ in range(args.steps):
+            x0, i0 = cg_step()
         torch.cuda.synchronize()
-        t_cg = time.perf_counter() - t0
+        t_cg = (time.perf_counter() - t0) / args.steps
         r0 = b - rr.apply_operator(kop, mu, "fp64", x0)
         cg = {"ms": 1e3 * t_cg, "iters": i0["iters"], "restarts": i0["restarts"],
               "relres_work": i0["relres_work"],

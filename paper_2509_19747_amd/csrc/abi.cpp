@@ -4,6 +4,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -15,6 +16,27 @@ static thread_local std::string g_last_error;
 void set_error(const std::string& msg) { g_last_error = msg; }
 const std::string& last_error() { return g_last_error; }
 
+// Without a caller allocator, buffers come from the device's stream-ordered
+// pool (hipMallocAsync / hipFreeAsync on the Alloc's stream).  The pool keeps
+// freed memory for reuse, so the many short-lived buffers of a build or a solve
+// cost neither a device synchronisation (hipFree has one) nor a driver call.
+static void keep_pool_memory() {
+    static std::mutex mu;
+    static std::vector<int> done;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return;
+    std::lock_guard<std::mutex> lk(mu);
+    for (int d : done)
+        if (d == dev) return;
+    hipMemPool_t pool;
+    if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+        uint64_t thr = UINT64_MAX;
+        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+    }
+    (void)hipGetLastError();
+    done.push_back(dev);
+}
+
 void* Alloc::get(size_t bytes) const {
     void* p = nullptr;
     if (custom) {
@@ -22,10 +44,11 @@ void* Alloc::get(size_t bytes) const {
         if (!p) throw RrError{RR_ENOMEM, "allocator returned null for " + std::to_string(bytes) + " bytes"};
         return p;
     }
-    const hipError_t e = hipMalloc(&p, bytes);
+    keep_pool_memory();
+    const hipError_t e = hipMallocAsync(&p, bytes, st);
     if (e != hipSuccess) {
         (void)hipGetLastError();
-        throw RrError{RR_ENOMEM, "hipMalloc(" + std::to_string(bytes) + ") failed: " + hipGetErrorString(e)};
+        throw RrError{RR_ENOMEM, "hipMallocAsync(" + std::to_string(bytes) + ") failed: " + hipGetErrorString(e)};
     }
     return p;
 }
@@ -33,7 +56,7 @@ void* Alloc::get(size_t bytes) const {
 void Alloc::put(void* p) const {
     if (!p) return;
     if (custom) a.free(a.ctx, p, (void*)st);
-    else (void)hipFree(p);
+    else (void)hipFreeAsync(p, st);
 }
 
 KernelOp kernel_op_of(const rr_precond& P) {
@@ -89,11 +112,11 @@ int apply_operator(const rr_precond& P, const double* u, double mu, double* y, d
 }
 
 void apply_operator_multi(const rr_precond& P, const double* U, int nr, double mu, double* Y,
-                          double* dot_part, double* kmv_ws, bool fp64, hipStream_t st) {
+                          double* dot_part, double* kmv_ws, bool fp64, hipStream_t st, bool estimate) {
     if (is_kernel(P.op)) {
         const KernelOp k = kernel_op_of(P);
         launch_kernel_matvec_multi(k, fp64 || P.opts.prec == RR_PREC_FP64, U, nr, mu, Y, dot_part,
-                                   kmv_ws, nullptr, st);
+                                   kmv_ws, nullptr, st, estimate);
         return;
     }
     const int np = operator_part_count(P);
@@ -196,6 +219,14 @@ const char* rr_version(void) { return "randrand-gfx950 0.1"; }
 void rr_precond_destroy(rr_precond* P) {
     if (!P) return;
     try {
+        if (!P->alloc.custom) {
+            // the handle's buffers were ordered on the build (and solve) streams, which
+            // the caller may have destroyed since: finish all work, then free on the
+            // null stream
+            (void)hipDeviceSynchronize();
+            P->alloc.st = nullptr;
+            rr_workspace_null_stream(P->ws);
+        }
         delete P;
     } catch (...) {
     }

@@ -28,13 +28,16 @@ struct Batch {
     const rr_precond& P;
     hipStream_t st;
     int64_t n, m, kb;
+    Alloc alloc;          // the handle's allocator, ordered on the solve stream
     const Alloc* al;
     DBuf R, Pm, Z, W, T, parts, C, Dall, D, state, start, target2, mucol, muidx, gws;
     size_t gwsd = 0;
     std::vector<int> mus_used;
     int nch = 1;
 
-    Batch(const rr_precond& p, hipStream_t s, int64_t mcols) : P(p), st(s), n(p.n), m(mcols), kb(p.kb), al(&p.alloc) {
+    Batch(const rr_precond& p, hipStream_t s, int64_t mcols)
+        : P(p), st(s), n(p.n), m(mcols), kb(p.kb), alloc(p.alloc), al(&alloc) {
+        alloc.st = s;
         const size_t nm = (size_t)n * m * sizeof(double);
         R.reset(al, nm); Pm.reset(al, nm); Z.reset(al, nm); W.reset(al, nm); T.reset(al, nm);
         nch = coldot_chunks(n);
@@ -141,7 +144,7 @@ rr_status rr_solve_batch_fused(const rr_precond* Pc, const int32_t* mu_index_per
 
         // NaN / Inf scan
         {
-            DBuf flag(&P.alloc, 16);
+            DBuf flag(Bt.al, 16);
             RR_HIP(hipMemsetAsync(flag.ptr(), 0, sizeof(int32_t), st));
             for (int64_t j = 0; j < m; ++j) {
                 launch_nonfinite(n, B + j * ldb, flag.as<int32_t>(), st);

@@ -167,7 +167,11 @@ struct Builder {
             gemm(DT_F64, false, ydt, false, 2 * k, k, n, theta.ptr(), 2 * k, Y, n, S.as<double>(), 2 * k);
             theta.release();
             DBuf Rsk = mat(k, k);
-            launch_householder_r(S.as<double>(), 2 * k, k, 2 * k, Rsk.as<double>(), k, st);
+            const size_t hwd = householder_ws_doubles(2 * k, k);
+            DBuf hws(al, hwd * sizeof(double));
+            launch_householder_r(S.as<double>(), 2 * k, k, 2 * k, Rsk.as<double>(), k, hws.as<double>(),
+                                 hwd, st);
+            hws.release();
             check_launch();
             DBuf Rskinv = mat(k, k);
             launch_tri_inv_upper(Rsk.as<double>(), k, k, Rskinv.as<double>(), k, st);
@@ -247,6 +251,8 @@ struct Builder {
         // The two power iterations run side by side so each step costs one
         // two-column operator pass (every kernel entry evaluated once):
         //   ||E||: v <- (I-Pi) A_mu (I-Pi) v,   lam: v <- Pi A_mu Pi~ v.
+        // They only estimate two scalars to a few digits, so a float32-mode
+        // kernel operator may add its products in float32 here.
         DBuf U(al, 2 * n * sizeof(double)), Yv(al, 2 * n * sizeof(double));
         DBuf V(al, 2 * n * sizeof(double)), Wv(al, 2 * n * sizeof(double));
         const int nch = gemv_t_chunks(n, P.kb);
@@ -274,7 +280,8 @@ struct Builder {
         for (int it = 0; it < P.opts.power_iters; ++it) {
             apply_projected(P, negT, v0, 1.0, u0, cp, dd, rzp, nullptr, st);    // (I-Pi) v
             apply_projected(P, TGT, v1, 0.0, u1, cp, dd, rzp, nullptr, st);     // Pi~ v
-            apply_operator_multi(P, u0, 2, mu, y0, op_part.as<double>(), kws.as<double>(), false, st);
+            apply_operator_multi(P, u0, 2, mu, y0, op_part.as<double>(), kws.as<double>(), false, st,
+                                 true);
             apply_projected(P, negT, y0, 1.0, w0, cp, dd, rzp, nullptr, st);    // (I-Pi) A u
             apply_projected(P, T, y1, 0.0, w1, cp, dd, rzp, nullptr, st);       // Pi A u
             launch_dot_part(n, w0, w0, vparts.as<double>(), st);
@@ -442,7 +449,8 @@ extern "C" rr_status rr_build_precond(const rr_operator* A, const double* mus, i
             Y0.release();
             launch_symmetrize(QQ.as<double>(), k2, k2, st);
             P.orth_err = B.orth_error(QQ.as<double>(), k2);
-            DBuf hws(al, ((size_t)k2 * l + l + 16) * sizeof(double));
+            const size_t hwd = std::max<size_t>((size_t)k2 * l + l + 16, householder_ws_doubles(k2, l));
+            DBuf hws(al, hwd * sizeof(double));
             for (int im = 0; im < n_mu; ++im) {
                 PerMu& pm = P.per[im];
                 const double mu = pm.mu;
@@ -451,7 +459,7 @@ extern "C" rr_status rr_build_precond(const rr_operator* A, const double* mus, i
                 pm.Qred.reset(al, (size_t)k2 * l * sizeof(double));
                 pm.R.reset(al, (size_t)l * l * sizeof(double));
                 launch_householder_qr(Mred.as<double>(), k2, l, k2, pm.Qred.as<double>(), k2, pm.R.as<double>(), l,
-                                      hws.as<double>(), st);
+                                      hws.as<double>(), hwd, st);
                 B.check_launch();
                 DBuf C = B.mat(l, l);
                 launch_axpby_mat(1.0, OAO.as<double>(), l, mu, OO.as<double>(), l, C.as<double>(), l, l, l, st);

@@ -41,6 +41,39 @@ RR_DEV float wave_sum(float v) {
     return v;
 }
 
+// DPP wave reduction towards lane 63.  One step on a float64 value (the same
+// DPP move on both halves; rows outside row_mask read 0 and keep their value).
+template <int CTRL, int ROWMASK>
+RR_DEV double dpp_add(double v) {
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, CTRL, ROWMASK, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), CTRL, ROWMASK, 0xF, false);
+    return v + __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+template <int CTRL, int ROWMASK>
+RR_DEV float dpp_add(float v) {
+    const int t = __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, ROWMASK, 0xF, false);
+    return v + __builtin_bit_cast(float, t);
+}
+// Sum over the 64 lanes, valid in lane 63: pairs and quads (quad_perm), half
+// rows (row_half_mirror), rows (row_mirror), then row 0 into 1 and 2 into 3
+// (row_bcast:15), then rows 0-1 into 2-3 (row_bcast:31).
+template <typename T, int M>
+RR_DEV void wave_sum_to63(T (&v)[M]) {
+#pragma unroll
+    for (int m = 0; m < M; ++m) v[m] = dpp_add<0xB1, 0xF>(v[m]);
+#pragma unroll
+    for (int m = 0; m < M; ++m) v[m] = dpp_add<0x4E, 0xF>(v[m]);
+#pragma unroll
+    for (int m = 0; m < M; ++m) v[m] = dpp_add<0x141, 0xF>(v[m]);
+#pragma unroll
+    for (int m = 0; m < M; ++m) v[m] = dpp_add<0x140, 0xF>(v[m]);
+#pragma unroll
+    for (int m = 0; m < M; ++m) v[m] = dpp_add<0x142, 0xA>(v[m]);
+#pragma unroll
+    for (int m = 0; m < M; ++m) v[m] = dpp_add<0x143, 0xC>(v[m]);
+}
+
 // Block sum of one double per thread; result returned to every thread.
 // `scratch` must hold blockDim.x/64 doubles.  Fixed order -> deterministic.
 RR_DEV double block_sum(double v, double* scratch) {

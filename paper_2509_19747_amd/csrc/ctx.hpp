@@ -118,6 +118,7 @@ struct Workspace;
 }  // namespace rr
 
 void rr_free_workspace(rr::Workspace* w);
+void rr_workspace_null_stream(rr::Workspace* w);   // free on the null stream from now on
 
 struct rr_precond {
     rr_operator op{};
@@ -156,8 +157,11 @@ int apply_operator(const rr_precond& P, const double* u, double mu, double* y, d
                    double* kmv_ws, bool fp64, const int32_t* stop, hipStream_t st);
 // Same for nr (1 or 2) columns U, Y (n x nr); dot partials of column q start at
 // dot_part + q * operator_part_count(P).
+// Several columns at once; estimate: float32 sums allowed for kernel operators in
+// float32 mode (the power iterations of the tau estimates).
 void apply_operator_multi(const rr_precond& P, const double* U, int nr, double mu, double* Y,
-                          double* dot_part, double* kmv_ws, bool fp64, hipStream_t st);
+                          double* dot_part, double* kmv_ws, bool fp64, hipStream_t st,
+                          bool estimate = false);
 int operator_part_count(const rr_precond& P);
 // Operator setup (A0): squared norms and point records for kernels, the float32
 // copy of a dense A when the working precision is below float64.

@@ -49,6 +49,13 @@ void launch_gemm(int dta, bool trA, int dtb, bool trB, int64_t M, int64_t N, int
                  const void* A, int64_t lda, const void* B, int64_t ldb, double* C, int64_t ldc,
                  double alpha, double beta, double* ws, size_t ws_doubles, hipStream_t st);
 
+// The same on float64 MFMA for float64/float32 operands with M, N >= 32 (returns
+// false, doing nothing, otherwise); launch_gemm tries it first.
+bool launch_gemm_mfma(int dta, bool trA, int dtb, bool trB, int64_t M, int64_t N, int64_t K,
+                      const void* A, int64_t lda, const void* B, int64_t ldb, double* C,
+                      int64_t ldc, double alpha, double beta, double* ws, size_t wsd,
+                      hipStream_t st);
+
 // ------------------------------------------------------ small dense helpers
 void launch_symmetrize(double* A, int64_t l, int64_t lda, hipStream_t st);
 void launch_add_diag(double* A, int64_t l, int64_t lda, double alpha, hipStream_t st);
@@ -71,13 +78,23 @@ void launch_max_abs_minus_identity(const double* M, int64_t l, int64_t ldm, doub
 void launch_cholesky_upper(double* A, int64_t l, int64_t lda, int32_t* status, double* ws,
                            size_t ws_doubles, hipStream_t st);
 // R factor (positive diagonal) of a Householder QR of S (m x k, m >= k), S is
-// overwritten.  R: k x k, ldr.
+// overwritten.  R: k x k, ldr.  ws: householder_ws_doubles(m, k) doubles (blocked
+// panels with compact-WY GEMM updates; a smaller ws falls back to one reflector
+// per launch, which needs none).
+size_t householder_ws_doubles(int64_t m, int64_t k);
+bool householder_blocked_ok(int64_t m, int64_t k);
 void launch_householder_r(double* S, int64_t m, int64_t k, int64_t lds, double* R, int64_t ldr,
-                          hipStream_t st);
+                          double* ws, size_t wsd, hipStream_t st);
 // Householder QR with explicit Q (m x k, ldq) and R (k x k): used for the reduced
-// 2l x l QR of the joint basis.  S is overwritten.  ws: >= m*k + k doubles.
+// 2l x l QR of the joint basis.  S is overwritten.  ws: >= max(m*k + k,
+// householder_ws_doubles(m, k)) doubles.
 void launch_householder_qr(double* S, int64_t m, int64_t k, int64_t lds, double* Q, int64_t ldq,
-                           double* R, int64_t ldr, double* ws, hipStream_t st);
+                           double* R, int64_t ldr, double* ws, size_t wsd, hipStream_t st);
+void launch_householder_r_blocked(double* S, int64_t m, int64_t k, int64_t lds, double* R,
+                                  int64_t ldr, double* ws, size_t wsd, hipStream_t st);
+void launch_householder_qr_blocked(double* S, int64_t m, int64_t k, int64_t lds, double* Q,
+                                   int64_t ldq, double* R, int64_t ldr, double* ws, size_t wsd,
+                                   hipStream_t st);
 // X = R^{-1} for an upper-triangular l x l R.
 void launch_tri_inv_upper(const double* R, int64_t l, int64_t ldr, double* X, int64_t ldx,
                           hipStream_t st);
@@ -115,13 +132,16 @@ void launch_kernel_matvec(const KernelOp& op, bool fp64, const double* u, double
 // dot partials of column q at dot_part[q * kernel_matvec_blocks(n) + b].  Each
 // kernel entry is evaluated once per group of up to 8 (float32) or 2 (float64)
 // columns and applied to every column of the group.
+// estimate: float32 sums allowed (power iterations of the tau estimates).
 void launch_kernel_matvec_multi(const KernelOp& op, bool fp64, const double* u, int nr, double mu,
                                 double* y, double* dot_part, double* ws, const int32_t* stop,
-                                hipStream_t st);
+                                hipStream_t st, bool estimate = false);
 // Symmetric float32 matvec, nr in {1, 2, 4, 8} (kernels_ksym.hip).
 size_t kernel_sym_ws_doubles(int64_t n, int d, int nr);
+// a32: float32 products and sums (estimate grade, nr <= 2), for power iterations.
 void launch_kernel_matvec_sym(const KernelOp& op, const double* u, int nr, double mu, double* y,
-                              double* dot_part, double* ws, const int32_t* stop, hipStream_t st);
+                              double* dot_part, double* ws, const int32_t* stop, hipStream_t st,
+                              bool a32 = false);
 void launch_sqnorms(const float* pts, int64_t n, int d, float* sqn, hipStream_t st);
 // Dense formation A_out = scale*K in float64 (dtype 0) / float32 (1) / bf16 (2).
 void launch_kernel_to_dense(const KernelOp& op, void* out, int dtype, int64_t lda, hipStream_t st);

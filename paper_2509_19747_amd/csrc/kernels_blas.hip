@@ -158,6 +158,8 @@ void launch_gemm(int dta, bool trA, int dtb, bool trB, int64_t M, int64_t N, int
         launch_scale_mat(C, ldc, M, N, beta, st);
         return;
     }
+    if (launch_gemm_mfma(dta, trA, dtb, trB, M, N, K, A, lda, B, ldb, C, ldc, alpha, beta, ws, wsd, st))
+        return;
     if (dtb == DT_F64) {
         if (dta == DT_F64) gemm_tr<double, double>(trA, trB, M, N, K, A, lda, B, ldb, C, ldc, alpha, beta, ws, wsd, st);
         else if (dta == DT_F32) gemm_tr<float, double>(trA, trB, M, N, K, A, lda, B, ldb, C, ldc, alpha, beta, ws, wsd, st);

@@ -201,8 +201,8 @@ static int g256(int64_t total) {
     return (int)g;
 }
 
-void launch_householder_r(double* S, int64_t m, int64_t k, int64_t lds, double* R, int64_t ldr,
-                          hipStream_t st) {
+static void householder_r_unblocked(double* S, int64_t m, int64_t k, int64_t lds, double* R,
+                                    int64_t ldr, hipStream_t st) {
     const size_t shm = (size_t)m * sizeof(double);
     for (int64_t kc = 0; kc < k; ++kc) {
         const int64_t rest = k - kc - 1;
@@ -258,8 +258,8 @@ __global__ void k_eye_rect(double* Q, int64_t m, int64_t k, int64_t ldq) {
     }
 }
 
-void launch_householder_qr(double* S, int64_t m, int64_t k, int64_t lds, double* Q, int64_t ldq,
-                           double* R, int64_t ldr, double* ws, hipStream_t st) {
+static void householder_qr_unblocked(double* S, int64_t m, int64_t k, int64_t lds, double* Q,
+                                     int64_t ldq, double* R, int64_t ldr, double* ws, hipStream_t st) {
     double* V = ws;                 // m x k
     double* tauv = ws + m * k;      // k
     const size_t shm = (size_t)m * sizeof(double);
@@ -274,6 +274,23 @@ void launch_householder_qr(double* S, int64_t m, int64_t k, int64_t lds, double*
         k_house_apply_q<<<gq, HH_THREADS, 0, st>>>(Q, m, k, ldq, V, m, tauv, kc);
     k_sign_fix_q<<<g256(m * k), 256, 0, st>>>(R, k, ldr, Q, m, ldq);
     k_sign_fix<<<g256(k), 256, 0, st>>>(R, k, ldr);
+}
+
+// Blocked panels when the panel fits the register layout (m <= 2048), one
+// reflector per launch otherwise.
+void launch_householder_r(double* S, int64_t m, int64_t k, int64_t lds, double* R, int64_t ldr,
+                          double* ws, size_t wsd, hipStream_t st) {
+    if (householder_blocked_ok(m, k) && wsd >= householder_ws_doubles(m, k))
+        launch_householder_r_blocked(S, m, k, lds, R, ldr, ws, wsd, st);
+    else
+        householder_r_unblocked(S, m, k, lds, R, ldr, st);
+}
+void launch_householder_qr(double* S, int64_t m, int64_t k, int64_t lds, double* Q, int64_t ldq,
+                           double* R, int64_t ldr, double* ws, size_t wsd, hipStream_t st) {
+    if (householder_blocked_ok(m, k) && wsd >= householder_ws_doubles(m, k))
+        launch_householder_qr_blocked(S, m, k, lds, Q, ldq, R, ldr, ws, wsd, st);
+    else
+        householder_qr_unblocked(S, m, k, lds, Q, ldq, R, ldr, ws, st);
 }
 
 // ==================================================== triangular inverse

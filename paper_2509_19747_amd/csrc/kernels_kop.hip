@@ -188,7 +188,7 @@ size_t kernel_matvec_ws_doubles(int64_t n, int d, int nr) {
 
 void launch_kernel_matvec_multi(const KernelOp& op, bool fp64, const double* u, int nr, double mu,
                                 double* y, double* dot_part, double* ws, const int32_t* stop,
-                                hipStream_t st) {
+                                hipStream_t st, bool estimate) {
     const int64_t nblk = kernel_matvec_blocks(op.n);
     for (int q0 = 0; q0 < nr;) {
         const int left = nr - q0;
@@ -203,7 +203,7 @@ void launch_kernel_matvec_multi(const KernelOp& op, bool fp64, const double* u, 
             q0 += c;
         } else {
             const int c = left >= 8 ? 8 : left >= 4 ? 4 : left >= 2 ? 2 : 1;
-            launch_kernel_matvec_sym(op, uq, c, mu, yq, dq, ws, stop, st);
+            launch_kernel_matvec_sym(op, uq, c, mu, yq, dq, ws, stop, st, estimate);
             q0 += c;
         }
     }

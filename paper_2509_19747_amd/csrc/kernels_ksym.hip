@@ -41,8 +41,10 @@ constexpr int ks_chunk_ct(int NR) { return NR >= 8 ? 64 : NR >= 4 ? 128 : 256; }
 // exact zeros to the dot product.  Rows per thread and points per step shrink
 // as DM and NR grow so that coordinates, accumulators and the step's scalar
 // operands stay in registers.
-constexpr int ksym_rows_ct(int DM, int NR) {
-    return DM + 4 * NR <= 21 ? 8 : DM + 4 * NR <= 42 ? 4 : 2;   // R * (DM + 4 NR) VGPRs
+constexpr int ksym_rows_ct(int DM, int NR, bool A32 = false) {
+    // R * (DM + 4 NR) (float64 sums) or R * (DM + 3 NR) (float32 estimate) VGPRs
+    return A32 ? (DM + 3 * NR <= 24 ? 8 : DM + 3 * NR <= 42 ? 4 : 2)
+               : (DM + 4 * NR <= 21 ? 8 : DM + 4 * NR <= 42 ? 4 : 2);
 }
 constexpr int ksym_jb_ct(int DM, int NR) {
     const int base = DM <= 8 ? 4 : DM <= 16 ? 2 : 1;
@@ -55,9 +57,9 @@ struct KsymPlan {
     int64_t items;
 };
 
-static KsymPlan ksym_plan(int64_t n, int d, int nr) {
+static KsymPlan ksym_plan(int64_t n, int d, int nr, bool a32 = false) {
     KsymPlan p;
-    p.R = ksym_rows_ct(kernel_record_len(d), nr);
+    p.R = ksym_rows_ct(kernel_record_len(d), nr, a32);
     p.RB = KS_THREADS * p.R;
     p.nb = (int)((n + p.RB - 1) / p.RB);
     const int64_t tiles = (int64_t)p.nb * (p.nb + 1) / 2;
@@ -72,52 +74,42 @@ static KsymPlan ksym_plan(int64_t n, int d, int nr) {
 }
 
 size_t kernel_sym_ws_doubles(int64_t n, int d, int nr) {
-    const KsymPlan p = ksym_plan(n, d, nr);
-    return (size_t)p.nb * p.S * nr * (size_t)n;
+    size_t w = 0;
+    for (int a = 0; a < 2; ++a) {
+        const KsymPlan p = ksym_plan(n, d, nr, a == 1);
+        w = std::max(w, (size_t)p.nb * p.S * nr * (size_t)n);
+    }
+    return w;
 }
 
-// One step of the wave reduction towards lane 63 on a float64 value (the same
-// DPP move on both halves; rows outside row_mask read 0 and keep their value).
-template <int CTRL, int ROWMASK>
-RR_DEV double dpp_add(double v) {
-    const uint64_t b = __builtin_bit_cast(uint64_t, v);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, CTRL, ROWMASK, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), CTRL, ROWMASK, 0xF, false);
-    return v + __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
-}
-// Sum over the 64 lanes, valid in lane 63: pairs and quads (quad_perm), half
-// rows (row_half_mirror), rows (row_mirror), then row 0 into 1 and 2 into 3
-// (row_bcast:15), then rows 0-1 into 2-3 (row_bcast:31).
-template <int M>
-RR_DEV void wave_sum_to63(double (&v)[M]) {
-#pragma unroll
-    for (int m = 0; m < M; ++m) v[m] = dpp_add<0xB1, 0xF>(v[m]);
-#pragma unroll
-    for (int m = 0; m < M; ++m) v[m] = dpp_add<0x4E, 0xF>(v[m]);
-#pragma unroll
-    for (int m = 0; m < M; ++m) v[m] = dpp_add<0x141, 0xF>(v[m]);
-#pragma unroll
-    for (int m = 0; m < M; ++m) v[m] = dpp_add<0x140, 0xF>(v[m]);
-#pragma unroll
-    for (int m = 0; m < M; ++m) v[m] = dpp_add<0x142, 0xA>(v[m]);
-#pragma unroll
-    for (int m = 0; m < M; ++m) v[m] = dpp_add<0x143, 0xC>(v[m]);
-}
+// JB points [j, j + JB) of one item.  OFFD adds column sums.  A32: products
+// and sums in float32 (an estimate-grade operator for the power iterations of
+// the tau estimates; row sums still go to float64 every JB points).
+template <bool A32> struct KsymT { typedef double U; };
+template <> struct KsymT<true> { typedef float U; };
 
-// JB points [j, j + JB) of one item.  OFFD adds column sums.
-template <int KIND, int DM, int NR, int R, int JB, bool OFFD>
+template <int KIND, int DM, int NR, int R, int JB, bool OFFD, bool A32>
 RR_DEV void ksym_step(int64_t n, const float* __restrict__ xa, const float* __restrict__ sqn,
                       float c, const double* __restrict__ u, int64_t j, int64_t c0,
                       const float (&xi)[R][DM], const float (&mhn)[R],
-                      const double (&ui)[R][NR], double (&acc)[R][NR], double* colw, int lane) {
-    double cp[JB * NR];
+                      const typename KsymT<A32>::U (&ui)[R][NR], double (&acc)[R][NR], double* colw,
+                      int lane) {
+    typedef typename KsymT<A32>::U U;
+    U cp[JB * NR];
+    float a32[R][NR];
+    if constexpr (A32) {
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int q = 0; q < NR; ++q) a32[r][q] = 0.0f;
+    }
 #pragma unroll
     for (int jb = 0; jb < JB; ++jb) {
         const int64_t jj = j + jb;
         const float nj = sqn[jj];
-        double uj[NR];
+        U uj[NR];
 #pragma unroll
-        for (int q = 0; q < NR; ++q) uj[q] = u[(int64_t)q * n + jj];
+        for (int q = 0; q < NR; ++q) uj[q] = (U)u[(int64_t)q * n + jj];
         float s[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) s[r] = kpair_init(mhn[r], nj);
@@ -128,55 +120,68 @@ RR_DEV void ksym_step(int64_t n, const float* __restrict__ xa, const float* __re
 #pragma unroll
             for (int r = 0; r < R; ++r) s[r] = fmaf(xi[r][k], xjk, s[r]);
         }
-        double kv[R];
+        U kv[R];
 #pragma unroll
-        for (int r = 0; r < R; ++r) kv[r] = (double)kval32<KIND>(s[r], c);
+        for (int r = 0; r < R; ++r) kv[r] = (U)kval32<KIND>(s[r], c);
+        if constexpr (A32) {
 #pragma unroll
-        for (int r = 0; r < R; ++r)
+            for (int r = 0; r < R; ++r)
 #pragma unroll
-            for (int q = 0; q < NR; ++q) acc[r][q] = fma(kv[r], uj[q], acc[r][q]);
+                for (int q = 0; q < NR; ++q) a32[r][q] = fmaf(kv[r], uj[q], a32[r][q]);
+        } else {
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+#pragma unroll
+                for (int q = 0; q < NR; ++q) acc[r][q] = fma(kv[r], uj[q], acc[r][q]);
+        }
         if (OFFD) {
 #pragma unroll
             for (int q = 0; q < NR; ++q) {
-                double t = 0.0;
+                U t = 0;
 #pragma unroll
-                for (int r = 0; r < R; ++r) t = fma(kv[r], ui[r][q], t);
+                for (int r = 0; r < R; ++r) t = kv[r] * ui[r][q] + t;
                 cp[jb * NR + q] = t;
             }
         }
     }
+    if constexpr (A32) {
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int q = 0; q < NR; ++q) acc[r][q] += (double)a32[r][q];
+    }
     if (OFFD) {
-        wave_sum_to63<JB * NR>(cp);
+        wave_sum_to63(cp);
         if (lane == 63) {
             const int base = (int)(j - c0) * NR;
 #pragma unroll
-            for (int m = 0; m < JB * NR; ++m) colw[base + m] = cp[m];
+            for (int m = 0; m < JB * NR; ++m) colw[base + m] = (double)cp[m];
         }
     }
 }
 
-template <int KIND, int DM, int NR, bool OFFD>
+template <int KIND, int DM, int NR, bool OFFD, bool A32>
 RR_DEV void ksym_columns(int64_t n, const float* __restrict__ xa,
                          const float* __restrict__ sqn, float c, const double* __restrict__ u,
                          double* __restrict__ part, int64_t cb, int64_t ce, int64_t colslot,
-                         const float (&xi)[ksym_rows_ct(DM, NR)][DM],
-                         const float (&mhn)[ksym_rows_ct(DM, NR)],
-                         const double (&ui)[ksym_rows_ct(DM, NR)][NR],
-                         double (&acc)[ksym_rows_ct(DM, NR)][NR],
+                         const float (&xi)[ksym_rows_ct(DM, NR, A32)][DM],
+                         const float (&mhn)[ksym_rows_ct(DM, NR, A32)],
+                         const typename KsymT<A32>::U (&ui)[ksym_rows_ct(DM, NR, A32)][NR],
+                         double (&acc)[ksym_rows_ct(DM, NR, A32)][NR],
                          double (*colw)[ks_chunk_ct(NR) * NR]) {
     constexpr int CH = ks_chunk_ct(NR);
-    constexpr int R = ksym_rows_ct(DM, NR);
+    constexpr int R = ksym_rows_ct(DM, NR, A32);
     constexpr int JB = ksym_jb_ct(DM, NR);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int64_t c0 = cb; c0 < ce; c0 += CH) {
         const int64_t c1 = (c0 + CH < ce) ? c0 + CH : ce;
         int64_t j = c0;
         for (; j + JB <= c1; j += JB)
-            ksym_step<KIND, DM, NR, R, JB, OFFD>(n, xa, sqn, c, u, j, c0, xi, mhn, ui, acc, colw[wave],
-                                                 lane);
+            ksym_step<KIND, DM, NR, R, JB, OFFD, A32>(n, xa, sqn, c, u, j, c0, xi, mhn, ui, acc,
+                                                      colw[wave], lane);
         for (; j < c1; ++j)
-            ksym_step<KIND, DM, NR, R, 1, OFFD>(n, xa, sqn, c, u, j, c0, xi, mhn, ui, acc, colw[wave],
-                                                lane);
+            ksym_step<KIND, DM, NR, R, 1, OFFD, A32>(n, xa, sqn, c, u, j, c0, xi, mhn, ui, acc,
+                                                     colw[wave], lane);
         if (OFFD) {
             __syncthreads();
             const int64_t jj = c0 + threadIdx.x;
@@ -193,14 +198,14 @@ RR_DEV void ksym_columns(int64_t n, const float* __restrict__ xa,
     }
 }
 
-template <int KIND, int DM, int NR>
+template <int KIND, int DM, int NR, bool A32>
 __global__ __launch_bounds__(KS_THREADS) void k_ksym_f32(int64_t n, const float* __restrict__ xa,
                                                          const float* __restrict__ sqn, float c,
                                                          const double* __restrict__ u,
                                                          double* __restrict__ part, int nb, int S,
                                                          int CL, const int32_t* __restrict__ stop) {
     if (stop && *stop) return;
-    constexpr int R = ksym_rows_ct(DM, NR);
+    constexpr int R = ksym_rows_ct(DM, NR, A32);
     constexpr int RB = KS_THREADS * R;
     __shared__ double colw[4][ks_chunk_ct(NR) * NR];
 
@@ -218,7 +223,7 @@ __global__ __launch_bounds__(KS_THREADS) void k_ksym_f32(int64_t n, const float*
 
     float xi[R][DM];
     float mhn[R];
-    double ui[R][NR];
+    typename KsymT<A32>::U ui[R][NR];
     double acc[R][NR];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -229,16 +234,16 @@ __global__ __launch_bounds__(KS_THREADS) void k_ksym_f32(int64_t n, const float*
         mhn[r] = -0.5f * sqn[ic];
 #pragma unroll
         for (int q = 0; q < NR; ++q) {
-            ui[r][q] = i < n ? u[(int64_t)q * n + i] : 0.0;
+            ui[r][q] = i < n ? (typename KsymT<A32>::U)u[(int64_t)q * n + i] : 0;
             acc[r][q] = 0.0;
         }
     }
     if (bj != bi)
-        ksym_columns<KIND, DM, NR, true>(n, xa, sqn, c, u, part, cb, ce, (int64_t)bi * S, xi, mhn,
-                                        ui, acc, colw);
+        ksym_columns<KIND, DM, NR, true, A32>(n, xa, sqn, c, u, part, cb, ce, (int64_t)bi * S, xi,
+                                             mhn, ui, acc, colw);
     else
-        ksym_columns<KIND, DM, NR, false>(n, xa, sqn, c, u, part, cb, ce, 0, xi, mhn, ui, acc,
-                                         colw);
+        ksym_columns<KIND, DM, NR, false, A32>(n, xa, sqn, c, u, part, cb, ce, 0, xi, mhn, ui, acc,
+                                              colw);
     const int64_t rslot = (int64_t)bj * S + s;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -276,11 +281,11 @@ __global__ __launch_bounds__(256) void k_ksym_finish(int64_t n, int RB, int nb, 
     }
 }
 
-template <int KIND, int NR>
+template <int KIND, int NR, bool A32>
 static void ksym_dispatch(const KernelOp& op, float c, const double* u, double* ws,
                           const KsymPlan& p, const int32_t* stop, hipStream_t st) {
     const unsigned grid = (unsigned)p.items;
-#define KSL(DD) k_ksym_f32<KIND, DD, NR><<<grid, KS_THREADS, 0, st>>>(op.n, op.xa, op.sqn, c, u, ws, p.nb, p.S, p.CL, stop)
+#define KSL(DD) k_ksym_f32<KIND, DD, NR, A32><<<grid, KS_THREADS, 0, st>>>(op.n, op.xa, op.sqn, c, u, ws, p.nb, p.S, p.CL, stop)
     switch (op.dm) {
         case 4: KSL(4); break;
         case 8: KSL(8); break;
@@ -290,19 +295,27 @@ static void ksym_dispatch(const KernelOp& op, float c, const double* u, double* 
 #undef KSL
 }
 
-// Stage 1 + finish for nr in {1, 2, 4, 8} columns (u, y column-major with leading dimension n).
+// Stage 1 + finish for nr in {1, 2, 4, 8} columns (u, y column-major with leading
+// dimension n); a32 (nr <= 2 only) selects the float32 estimate-grade sums.
 void launch_kernel_matvec_sym(const KernelOp& op, const double* u, int nr, double mu, double* y,
-                              double* dot_part, double* ws, const int32_t* stop, hipStream_t st) {
-    const KsymPlan p = ksym_plan(op.n, op.d, nr);
+                              double* dot_part, double* ws, const int32_t* stop, hipStream_t st,
+                              bool a32) {
+    a32 = a32 && nr <= 2;
+    const KsymPlan p = ksym_plan(op.n, op.d, nr, a32);
     const float c = kernel_c32(op.kind, op.kconst);
     {
-        ProfScope prof(nr == 1 ? PROF_KERNEL_MATVEC : -1, st);
-#define KSD(K)                                                   \
-    switch (nr) {                                                \
-        case 1: ksym_dispatch<K, 1>(op, c, u, ws, p, stop, st); break; \
-        case 2: ksym_dispatch<K, 2>(op, c, u, ws, p, stop, st); break; \
-        case 4: ksym_dispatch<K, 4>(op, c, u, ws, p, stop, st); break; \
-        default: ksym_dispatch<K, 8>(op, c, u, ws, p, stop, st); break; \
+        ProfScope prof(nr == 1 && !a32 ? PROF_KERNEL_MATVEC : -1, st);
+#define KSD(K)                                                                   \
+    if (a32) {                                                                   \
+        if (nr == 1) ksym_dispatch<K, 1, true>(op, c, u, ws, p, stop, st);       \
+        else ksym_dispatch<K, 2, true>(op, c, u, ws, p, stop, st);               \
+    } else {                                                                     \
+        switch (nr) {                                                            \
+            case 1: ksym_dispatch<K, 1, false>(op, c, u, ws, p, stop, st); break; \
+            case 2: ksym_dispatch<K, 2, false>(op, c, u, ws, p, stop, st); break; \
+            case 4: ksym_dispatch<K, 4, false>(op, c, u, ws, p, stop, st); break; \
+            default: ksym_dispatch<K, 8, false>(op, c, u, ws, p, stop, st); break; \
+        }                                                                        \
     }
         if (op.kind == 1) { KSD(1) } else { KSD(2) }
 #undef KSD

@@ -37,9 +37,10 @@ struct Workspace {
     ~Workspace() { if (cap) (void)hipStreamDestroy(cap); }
 };
 
-static Workspace* make_workspace(const rr_precond& P, int32_t maxit) {
+static Workspace* make_workspace(const rr_precond& P, int32_t maxit, hipStream_t st) {
     Workspace* W = new Workspace();
     W->al = P.alloc;
+    if (!W->al.custom) W->al.st = st;   // ordered with the solve that first uses it
     W->n = P.n;
     W->kb = P.kb;
     const int64_t n = P.n;
@@ -67,6 +68,9 @@ static Workspace* make_workspace(const rr_precond& P, int32_t maxit) {
 }  // namespace rr
 
 void rr_free_workspace(rr::Workspace* w) { delete w; }
+void rr_workspace_null_stream(rr::Workspace* w) {
+    if (w && !w->al.custom) w->al.st = nullptr;
+}
 
 namespace {
 
@@ -161,7 +165,7 @@ extern "C" rr_status rr_solve(const rr_precond* Pc, int32_t mu_index, const doub
         if (!P.ws || P.ws->hist_cap < o.maxit + 2) {
             if (P.ws) rr_free_workspace(P.ws);
             P.ws = nullptr;
-            P.ws = make_workspace(P, o.maxit);
+            P.ws = make_workspace(P, o.maxit, st);
         }
         Workspace& W = *P.ws;
         const PerMu& pm = P.per[mu_index];
