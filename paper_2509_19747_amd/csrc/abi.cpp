@@ -134,6 +134,16 @@ int apply_projected(const rr_precond& P, const double* Kc, const double* r, doub
     return qd_blocks(P.n);
 }
 
+void apply_projected_pair(const rr_precond& P, const double* K0, const double* K1, const double* R,
+                          double rc0, double rc1, double* Z, double* c_part, double* d,
+                          double* rz_part, hipStream_t st) {
+    const int nch = gemv_t_chunks(P.n, P.kb);
+    launch_gemv_t_multi(2, P.n, P.kb, P.Qb.as<double>(), P.n, R, P.n, c_part, nch, nullptr, st);
+    launch_core_apply(P.kb, K0, P.kb, c_part, nch, d, nullptr, st);
+    launch_core_apply(P.kb, K1, P.kb, c_part + (size_t)nch * P.kb, nch, d + P.kb, nullptr, st);
+    launch_qd_multi(2, P.n, P.kb, P.Qb.as<double>(), P.n, d, R, P.n, rc0, rc1, Z, rz_part, nullptr, st);
+}
+
 rr_status validate_operator(const rr_operator* A) {
     RR_REQUIRE(A != nullptr, "operator is null");
     RR_REQUIRE(A->n >= 1, "operator n must be >= 1");

@@ -256,13 +256,11 @@ struct Builder {
         DBuf U(al, 2 * n * sizeof(double)), Yv(al, 2 * n * sizeof(double));
         DBuf V(al, 2 * n * sizeof(double)), Wv(al, 2 * n * sizeof(double));
         const int nch = gemv_t_chunks(n, P.kb);
-        DBuf cpart(al, (size_t)nch * P.kb * sizeof(double)), d(al, P.kb * sizeof(double));
-        DBuf rz(al, (size_t)qd_blocks(n) * sizeof(double));
+        DBuf cpart(al, (size_t)2 * nch * P.kb * sizeof(double)), d(al, 2 * P.kb * sizeof(double));
+        DBuf rz(al, (size_t)2 * qd_blocks(n) * sizeof(double));
         DBuf op_part(al, (size_t)2 * operator_part_count(P) * sizeof(double));
         double* u0 = U.as<double>();
-        double* u1 = u0 + n;
         double* y0 = Yv.as<double>();
-        double* y1 = y0 + n;
         double* v0 = V.as<double>();
         double* v1 = v0 + n;
         double* w0 = Wv.as<double>();
@@ -278,12 +276,12 @@ struct Builder {
         double* dd = d.as<double>();
         double* rzp = rz.as<double>();
         for (int it = 0; it < P.opts.power_iters; ++it) {
-            apply_projected(P, negT, v0, 1.0, u0, cp, dd, rzp, nullptr, st);    // (I-Pi) v
-            apply_projected(P, TGT, v1, 0.0, u1, cp, dd, rzp, nullptr, st);     // Pi~ v
+            // [(I-Pi) v0, Pi~ v1], A_mu on both, [(I-Pi) y0, Pi y1]; each pair of
+            // projections reads Q once
+            apply_projected_pair(P, negT, TGT, v0, 1.0, 0.0, u0, cp, dd, rzp, st);
             apply_operator_multi(P, u0, 2, mu, y0, op_part.as<double>(), kws.as<double>(), false, st,
                                  true);
-            apply_projected(P, negT, y0, 1.0, w0, cp, dd, rzp, nullptr, st);    // (I-Pi) A u
-            apply_projected(P, T, y1, 0.0, w1, cp, dd, rzp, nullptr, st);       // Pi A u
+            apply_projected_pair(P, negT, T, y0, 1.0, 0.0, w0, cp, dd, rzp, st);
             launch_dot_part(n, w0, w0, vparts.as<double>(), st);
             launch_normalize(n, v0, w0, vparts.as<double>(), vec_blocks(n), lam_dev + 0, st);
             launch_dot_part(n, w1, w1, vparts.as<double>(), st);

@@ -171,6 +171,12 @@ size_t operator_ws_doubles(const rr_precond& P);
 // z = rcoef*r + Qb (Kc (Qb^T r)), with partials of r^T z.  Returns #partials.
 int apply_projected(const rr_precond& P, const double* Kc, const double* r, double rcoef, double* z,
                     double* c_part, double* d, double* rz_part, const int32_t* stop, hipStream_t st);
+// Two vectors at once (R, Z: n x 2, leading dimension n), each with its own core:
+// Z[:, q] = rc_q R[:, q] + Q K_q Q^T R[:, q].  c_part: 2 * nchunks * kb doubles,
+// d: 2 * kb, rz_part: 2 * qd_blocks(n).
+void apply_projected_pair(const rr_precond& P, const double* K0, const double* K1, const double* R,
+                          double rc0, double rc1, double* Z, double* c_part, double* d,
+                          double* rz_part, hipStream_t st);
 
 rr_status validate_operator(const rr_operator* A);
 void require_device();

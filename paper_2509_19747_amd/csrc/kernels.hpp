@@ -185,11 +185,15 @@ void launch_bresid(int64_t n, int64_t m, const double* B, int64_t ldb, const dou
 void launch_select_cols(int64_t k, int64_t m, const double* Dall, const int32_t* mu_idx, double* D,
                         hipStream_t s);
 
-// ------------------------------------------------------ projections (K7, K8)
+// ------------------------------------------------------ projections
 // c_part[chunk * k + j] = sum_{i in chunk} Q[i, j] r[i]; returns number of chunks.
 int gemv_t_chunks(int64_t n, int64_t k);
 void launch_gemv_t(int64_t n, int64_t k, const double* Q, int64_t ldq, const double* r,
                    double* c_part, int nchunks, const int32_t* stop, hipStream_t st);
+// nr = 1 or 2 vectors (R: n x nr, leading dimension ldr); vector q's partials at
+// c_part + q * nchunks * k.
+void launch_gemv_t_multi(int nr, int64_t n, int64_t k, const double* Q, int64_t ldq, const double* R,
+                         int64_t ldr, double* c_part, int nchunks, const int32_t* stop, hipStream_t st);
 // d = Kc * c with c = sum over chunks of c_part (Kc symmetric k x k).
 void launch_core_apply(int64_t k, const double* Kc, int64_t ldk, const double* c_part,
                        int nchunks, double* d, const int32_t* stop, hipStream_t st);
@@ -198,6 +202,11 @@ int qd_blocks(int64_t n);
 void launch_qd(int64_t n, int64_t k, const double* Q, int64_t ldq, const double* d,
                const double* r, double rcoef, double* z, double* rz_part, const int32_t* stop,
                hipStream_t st);
+// Z[:, q] = rc_q R[:, q] + Q D[:, q] for nr = 1 or 2 (D: k x nr, leading dimension k;
+// R, Z: leading dimension ldr); partials of column q at rz_part + q * qd_blocks(n).
+void launch_qd_multi(int nr, int64_t n, int64_t k, const double* Q, int64_t ldq, const double* D,
+                     const double* R, int64_t ldr, double rc0, double rc1, double* Z, double* rz_part,
+                     const int32_t* stop, hipStream_t st);
 // v = v / sqrt(sum(part)); lam_out[0] = sqrt(sum(part))  (power-iteration step)
 void launch_normalize(int64_t n, double* v, const double* src, const double* part, int count,
                       double* lam_out, hipStream_t st);

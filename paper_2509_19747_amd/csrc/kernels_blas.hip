@@ -396,48 +396,80 @@ void launch_dense_matvec(int dta, int64_t n, const void* A, int64_t lda, const d
         k_dense_matvec<double><<<g, DM_THREADS, 0, st>>>(n, (const double*)A, lda, u, mu, y, dot_part, stop);
 }
 
-// ============================================== projections (K7, K8)
-// c_part[ch * k + j] = sum over rows of chunk ch of Q[i, j] r[i].
+// ============================================== projections
+// C[:, q] = Q^T R[:, q] and Z[:, q] = rcoef_q R[:, q] + Q D[:, q] for NR = 1 or 2
+// vectors at once, so Q (n x k, the HBM-bound operand) is read once for both.
+
+// c_part[q * nchunks * k + ch * k + j] = sum over rows of chunk ch of Q[i, j] R[i, q].
 constexpr int GT_COLS = 4;
 constexpr int GT_THREADS = 256;
 
+template <int NR>
 __global__ __launch_bounds__(GT_THREADS) void k_gemv_t(int64_t n, int64_t k,
                                                        const double* __restrict__ Q, int64_t ldq,
-                                                       const double* __restrict__ r,
-                                                       double* __restrict__ c_part,
+                                                       const double* __restrict__ R, int64_t ldr,
+                                                       double* __restrict__ c_part, int nchunks,
                                                        int64_t rows_per_chunk,
                                                        const int32_t* __restrict__ stop) {
-    __shared__ double red[GT_COLS][GT_THREADS / WAVE];
+    __shared__ double red[GT_COLS * NR][GT_THREADS / WAVE];
     if (stop && *stop) return;
     const int64_t j0 = (int64_t)blockIdx.x * GT_COLS;
     const int64_t ch = blockIdx.y;
     const int64_t ib = ch * rows_per_chunk;
     const int64_t ie = (ib + rows_per_chunk < n) ? ib + rows_per_chunk : n;
-    double acc[GT_COLS];
+    double acc[GT_COLS][NR];
 #pragma unroll
-    for (int c = 0; c < GT_COLS; ++c) acc[c] = 0.0;
-    for (int64_t i = ib + threadIdx.x; i < ie; i += GT_THREADS) {
-        const double ri = r[i];
+    for (int c = 0; c < GT_COLS; ++c)
 #pragma unroll
-        for (int c = 0; c < GT_COLS; ++c) {
-            const int64_t j = j0 + c;
-            if (j < k) acc[c] = fma(Q[i + j * ldq], ri, acc[c]);
+        for (int q = 0; q < NR; ++q) acc[c][q] = 0.0;
+    // two rows per thread per pass: eight independent loads of Q in flight
+    const int ncol = (int)((k - j0) < GT_COLS ? (k - j0) : GT_COLS);
+    int64_t i = ib + threadIdx.x;
+    for (; i + GT_THREADS < ie; i += 2 * GT_THREADS) {
+        double ri[2][NR], qv[2][GT_COLS];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+#pragma unroll
+            for (int q = 0; q < NR; ++q) ri[h][q] = R[i + h * GT_THREADS + q * ldr];
+#pragma unroll
+            for (int c = 0; c < GT_COLS; ++c)
+                qv[h][c] = c < ncol ? Q[i + h * GT_THREADS + (j0 + c) * ldq] : 0.0;
         }
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int c = 0; c < GT_COLS; ++c)
+#pragma unroll
+                for (int q = 0; q < NR; ++q) acc[c][q] = fma(qv[h][c], ri[h][q], acc[c][q]);
+    }
+    for (; i < ie; i += GT_THREADS) {
+        double ri[NR];
+#pragma unroll
+        for (int q = 0; q < NR; ++q) ri[q] = R[i + q * ldr];
+#pragma unroll
+        for (int c = 0; c < GT_COLS; ++c)
+            if (c < ncol) {
+                const double qij = Q[i + (j0 + c) * ldq];
+#pragma unroll
+                for (int q = 0; q < NR; ++q) acc[c][q] = fma(qij, ri[q], acc[c][q]);
+            }
     }
     const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
 #pragma unroll
-    for (int c = 0; c < GT_COLS; ++c) {
-        const double s = wave_sum(acc[c]);
-        if (lane == 0) red[c][w] = s;
-    }
+    for (int c = 0; c < GT_COLS; ++c)
+#pragma unroll
+        for (int q = 0; q < NR; ++q) {
+            const double s = wave_sum(acc[c][q]);
+            if (lane == 0) red[c * NR + q][w] = s;
+        }
     __syncthreads();
-    if (threadIdx.x < GT_COLS) {
-        const int c = threadIdx.x;
+    if (threadIdx.x < GT_COLS * NR) {
+        const int c = threadIdx.x / NR, q = threadIdx.x % NR;
         const int64_t j = j0 + c;
         if (j < k) {
             double s = 0.0;
-            for (int q = 0; q < GT_THREADS / WAVE; ++q) s += red[c][q];
-            c_part[ch * k + j] = s;
+            for (int w2 = 0; w2 < GT_THREADS / WAVE; ++w2) s += red[threadIdx.x][w2];
+            c_part[(int64_t)q * nchunks * k + ch * k + j] = s;
         }
     }
 }
@@ -457,11 +489,18 @@ int gemv_t_chunks(int64_t n, int64_t k) {
     return (int)((n + rpc - 1) / rpc);
 }
 
-void launch_gemv_t(int64_t n, int64_t k, const double* Q, int64_t ldq, const double* r,
-                   double* c_part, int nchunks, const int32_t* stop, hipStream_t st) {
+void launch_gemv_t_multi(int nr, int64_t n, int64_t k, const double* Q, int64_t ldq, const double* R,
+                         int64_t ldr, double* c_part, int nchunks, const int32_t* stop, hipStream_t st) {
     const int64_t rpc = gemv_t_rows_per_chunk(n, k);
     dim3 grid((unsigned)((k + GT_COLS - 1) / GT_COLS), (unsigned)nchunks);
-    k_gemv_t<<<grid, GT_THREADS, 0, st>>>(n, k, Q, ldq, r, c_part, rpc, stop);
+    if (nr == 2)
+        k_gemv_t<2><<<grid, GT_THREADS, 0, st>>>(n, k, Q, ldq, R, ldr, c_part, nchunks, rpc, stop);
+    else
+        k_gemv_t<1><<<grid, GT_THREADS, 0, st>>>(n, k, Q, ldq, R, ldr, c_part, nchunks, rpc, stop);
+}
+void launch_gemv_t(int64_t n, int64_t k, const double* Q, int64_t ldq, const double* r,
+                   double* c_part, int nchunks, const int32_t* stop, hipStream_t st) {
+    launch_gemv_t_multi(1, n, k, Q, ldq, r, n, c_part, nchunks, stop, st);
 }
 
 // d_i = sum_j Kc[j, i] c_j with c_j = sum_ch c_part[ch*k + j] (Kc symmetric).
@@ -509,44 +548,86 @@ void launch_core_apply(int64_t k, const double* Kc, int64_t ldk, const double* c
     k_core_apply<<<g, 256, (size_t)k * sizeof(double), st>>>(k, Kc, ldk, c_part, nchunks, d, stop);
 }
 
-// z_i = rcoef * r_i + sum_j Q[i, j] d_j; partial sums of r_i z_i per block.
-constexpr int QD_THREADS = 64;
+// Z[i, q] = rcoef_q R[i, q] + sum_j Q[i, j] D[j, q]; partial sums of R[i, q] Z[i, q]
+// per block in rz_part[q * gridDim.x + block].  Block: 64 rows, its four waves
+// split the k columns (lane = row, loads of Q coalesced along the column) and add
+// their partial row sums in a fixed order.
+constexpr int QD_ROWS = 64;
+constexpr int QD_THREADS = 256;
+template <int NR>
 __global__ __launch_bounds__(QD_THREADS) void k_qd(int64_t n, int64_t k,
                                                    const double* __restrict__ Q, int64_t ldq,
-                                                   const double* __restrict__ d,
-                                                   const double* __restrict__ r, double rcoef,
-                                                   double* __restrict__ z,
+                                                   const double* __restrict__ D,
+                                                   const double* __restrict__ R, int64_t ldr,
+                                                   double rc0, double rc1,
+                                                   double* __restrict__ Z,
                                                    double* __restrict__ rz_part,
                                                    const int32_t* __restrict__ stop) {
-    extern __shared__ double d_sh[];
+    extern __shared__ double d_sh[];   // NR * k
+    __shared__ double part[QD_THREADS / WAVE][NR][QD_ROWS];
     if (stop && *stop) return;
-    for (int64_t j = threadIdx.x; j < k; j += QD_THREADS) d_sh[j] = d[j];
+    for (int64_t e = threadIdx.x; e < (int64_t)NR * k; e += QD_THREADS) d_sh[e] = D[e];
     __syncthreads();
-    const int64_t i = (int64_t)blockIdx.x * QD_THREADS + threadIdx.x;
-    double rz = 0.0;
+    const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+    const int64_t i = (int64_t)blockIdx.x * QD_ROWS + lane;
+    const int64_t per = (k + 3) / 4;
+    const int64_t jb = w * per, je = (jb + per < k) ? jb + per : k;
+    double acc[NR][2];
+#pragma unroll
+    for (int q = 0; q < NR; ++q) acc[q][0] = acc[q][1] = 0.0;
     if (i < n) {
-        double acc0 = 0.0, acc1 = 0.0;
-        int64_t j = 0;
-        for (; j + 1 < k; j += 2) {
-            acc0 = fma(Q[i + j * ldq], d_sh[j], acc0);
-            acc1 = fma(Q[i + (j + 1) * ldq], d_sh[j + 1], acc1);
+        const double* qi = Q + i;
+        int64_t j = jb;
+        for (; j + 8 <= je; j += 8) {
+            double qv[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) qv[u] = qi[(j + u) * ldq];
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+#pragma unroll
+                for (int q = 0; q < NR; ++q) acc[q][u & 1] = fma(qv[u], d_sh[q * k + j + u], acc[q][u & 1]);
         }
-        if (j < k) acc0 = fma(Q[i + j * ldq], d_sh[j], acc0);
-        const double zi = fma(rcoef, r[i], acc0 + acc1);
-        z[i] = zi;
-        rz = r[i] * zi;
+        for (; j < je; ++j) {
+            const double qv = qi[j * ldq];
+#pragma unroll
+            for (int q = 0; q < NR; ++q) acc[q][0] = fma(qv, d_sh[q * k + j], acc[q][0]);
+        }
     }
-    rz = wave_sum(rz);
-    if (threadIdx.x == 0) rz_part[blockIdx.x] = rz;
+#pragma unroll
+    for (int q = 0; q < NR; ++q) part[w][q][lane] = acc[q][0] + acc[q][1];
+    __syncthreads();
+    if (w == 0) {
+#pragma unroll
+        for (int q = 0; q < NR; ++q) {
+            double rz = 0.0;
+            if (i < n) {
+                const double s = (part[0][q][lane] + part[1][q][lane]) + (part[2][q][lane] + part[3][q][lane]);
+                const double ri = R[i + q * ldr];
+                const double zi = fma(q == 0 ? rc0 : rc1, ri, s);
+                Z[i + q * ldr] = zi;
+                rz = ri * zi;
+            }
+            rz = wave_sum(rz);
+            if (lane == 0) rz_part[(int64_t)q * gridDim.x + blockIdx.x] = rz;
+        }
+    }
 }
 
-int qd_blocks(int64_t n) { return (int)((n + QD_THREADS - 1) / QD_THREADS); }
+int qd_blocks(int64_t n) { return (int)((n + QD_ROWS - 1) / QD_ROWS); }
 
+void launch_qd_multi(int nr, int64_t n, int64_t k, const double* Q, int64_t ldq, const double* D,
+                     const double* R, int64_t ldr, double rc0, double rc1, double* Z, double* rz_part,
+                     const int32_t* stop, hipStream_t st) {
+    const size_t shm = (size_t)std::max<int64_t>(nr * k, 1) * sizeof(double);
+    if (nr == 2)
+        k_qd<2><<<qd_blocks(n), QD_THREADS, shm, st>>>(n, k, Q, ldq, D, R, ldr, rc0, rc1, Z, rz_part, stop);
+    else
+        k_qd<1><<<qd_blocks(n), QD_THREADS, shm, st>>>(n, k, Q, ldq, D, R, ldr, rc0, rc1, Z, rz_part, stop);
+}
 void launch_qd(int64_t n, int64_t k, const double* Q, int64_t ldq, const double* d,
                const double* r, double rcoef, double* z, double* rz_part, const int32_t* stop,
                hipStream_t st) {
-    k_qd<<<qd_blocks(n), QD_THREADS, (size_t)(k > 0 ? k : 1) * sizeof(double), st>>>(
-        n, k, Q, ldq, d, r, rcoef, z, rz_part, stop);
+    launch_qd_multi(1, n, k, Q, ldq, d, r, n, rcoef, 0.0, z, rz_part, stop, st);
 }
 
 // ==================================================== CG vector steps (K10)

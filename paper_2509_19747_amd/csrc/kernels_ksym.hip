@@ -268,9 +268,20 @@ __global__ __launch_bounds__(256) void k_ksym_finish(int64_t n, int RB, int nb, 
     for (int q = 0; q < nr; ++q) {
         double dot = 0.0;
         if (i < n) {
-            double s = 0.0;
-            for (int p = 0; p < b; ++p) s += part[((int64_t)p * S * nr + q) * n + i];
-            for (int64_t z = (int64_t)b * S; z < (int64_t)nb * S; ++z) s += part[(z * nr + q) * n + i];
+            // slots in a fixed order, four running sums so that loads stay in flight
+            double s4[4] = {0.0, 0.0, 0.0, 0.0};
+            int p = 0;
+            for (; p + 4 <= b; p += 4)
+#pragma unroll
+                for (int u = 0; u < 4; ++u) s4[u] += part[((int64_t)(p + u) * S * nr + q) * n + i];
+            for (; p < b; ++p) s4[0] += part[((int64_t)p * S * nr + q) * n + i];
+            const int64_t z1 = (int64_t)nb * S;
+            int64_t z = (int64_t)b * S;
+            for (; z + 4 <= z1; z += 4)
+#pragma unroll
+                for (int u = 0; u < 4; ++u) s4[u] += part[((z + u) * nr + q) * n + i];
+            for (; z < z1; ++z) s4[0] += part[(z * nr + q) * n + i];
+            const double s = (s4[0] + s4[1]) + (s4[2] + s4[3]);
             const double ui = u[(int64_t)q * n + i];
             const double yi = fma(scale, s, mu * ui);
             y[(int64_t)q * n + i] = yi;
