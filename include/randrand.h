@@ -309,9 +309,12 @@ rr_status rr_random_matrix(int32_t kind, uint64_t seed, int64_t rows, int64_t co
  * Kernel timing for measurement (off by default).  rr_profile_enable(1) clears the
  * counters and makes the launchers of the hot kernels bracket every launch with
  * HIP events on the launch stream; rr_profile_read(slot, &count, &total_ms)
- * returns the number of timed launches and their summed device time.  Slots:
+ * returns the number of timed launches and their summed device time, leaving out
+ * launches shorter than a tenth of the slot's median (iterations past convergence,
+ * which the device-side stop flag turns into no-ops).  Slots:
  * 0 = float32 kernel matvec (first stage), 1 = float32 kernel-GEMM sketch,
- * 2 = float32 dense matvec, 3 = bf16 dense sketch, 4 = projections.
+ * 2 = float32 dense matvec, 3 = bf16 dense sketch, 4 = projections,
+ * 5 = float64 kernel matrix-matrix product of the batched solve.
  */
 void rr_profile_enable(int32_t on);
 rr_status rr_profile_read(int32_t slot, int64_t* count, double* total_ms);

@@ -3,9 +3,9 @@
 //
 //  * k_kgemm_f64_mfma : W = scale * K P + diag(mu_col) P for m columns at once.
 //      The kernel entries are the same float32 values as the single-vector
-//      matvec (bitwise: same formula, same order), widened to float64 and
-//      multiplied on v_mfma_f64_16x16x4_f64 with float64 accumulation, so every
-//      column sees the same operator to float64 rounding.
+//      matvec (bitwise: same formula over the same padded point records),
+//      widened to float64 and multiplied on v_mfma_f64_16x16x4_f64 with float64
+//      accumulation, so every column sees the same operator to float64 rounding.
 //  * per-column dot partials, scalar steps and vector updates with a per-column
 //      run flag: converged or restarting columns are left untouched.
 #include "common.hpp"
@@ -16,19 +16,19 @@
 namespace rr {
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
-constexpr int KD_BM = 256, KD_BN = 128, KD_BK = 16, KD_THREADS = 512;
+constexpr int KD_BM = 256, KD_BN = 128, KD_BK = 16, KD_THREADS = 1024;
 
-// Block: 8 waves in a 4 (rows) x 2 (columns) grid of 64 x 64 wave tiles.
-// Per step of 16 points the block forms the 256 x 16 kernel tile (thread: one
-// row, 8 points) into LDS (k-major) and stages the 16 x 128 slice of P.
+// Block: 16 waves in a 4 (rows) x 4 (columns) grid of 64 x 32 wave tiles (4 x 2
+// MFMA tiles, 32 float64 accumulators per lane), four waves per SIMD: the float64
+// MFMA pipe needs several resident waves to stay busy.  Per step of 16 points the
+// block forms the 256 x 16 kernel tile (thread: one row, 4 points whose records
+// arrive through scalar loads) into LDS (k-major) and stages the 16 x 128 slice of P.
 // F64E: entries in float64 (difference form, float64 exp) instead of float32.
-template <int KIND, int D, bool F64E>
+template <int KIND, int DM, bool F64E>
 __global__ __launch_bounds__(KD_THREADS) void k_kgemm_f64_mfma(
-    int64_t n, int dd, const float* __restrict__ pts, const float* __restrict__ sqn, float c,
-    double kconst, double scale, const double* __restrict__ mucol, const double* __restrict__ P, int64_t ldp,
-    int64_t m, double* __restrict__ W, int64_t ldw) {
-    constexpr int DM = D > 0 ? D : 32;
-    const int d = D > 0 ? D : dd;
+    int64_t n, const float* __restrict__ xa, const float* __restrict__ sqn, float c,
+    double kconst, double scale, const double* __restrict__ mucol, const double* __restrict__ P,
+    int64_t ldp, int64_t m, double* __restrict__ W, int64_t ldw) {
     __shared__ double As[KD_BK][KD_BM + 2];
     __shared__ double Bs[KD_BK][KD_BN + 2];
     const int t = threadIdx.x;
@@ -38,64 +38,63 @@ __global__ __launch_bounds__(KD_THREADS) void k_kgemm_f64_mfma(
     const int64_t c0 = (int64_t)blockIdx.y * KD_BN;
 
     const int trow = t & (KD_BM - 1);
-    const int pg = __builtin_amdgcn_readfirstlane(t >> 8);   // 0/1: which 8 of the 16 points
+    const int pg = __builtin_amdgcn_readfirstlane(t >> 8);   // 0..3: which 4 of the 16 points
     const int64_t gi = i0 + trow;
     const int64_t gic = gi < n ? gi : n - 1;
     float xi[DM];
 #pragma unroll
-    for (int k = 0; k < DM; ++k) xi[k] = (k < d) ? pts[(int64_t)k * n + gic] : 0.0f;
+    for (int k = 0; k < DM; ++k) xi[k] = xa[gic * DM + k];
     const float mhn = -0.5f * sqn[gic];
 
-    f64x4 acc[4][4];
+    f64x4 acc[4][2];
 #pragma unroll
     for (int u = 0; u < 4; ++u)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) acc[u][v] = f64x4{0.0, 0.0, 0.0, 0.0};
+        for (int v = 0; v < 2; ++v) acc[u][v] = f64x4{0.0, 0.0, 0.0, 0.0};
 
     for (int64_t j0 = 0; j0 < n; j0 += KD_BK) {
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const int p = pg * 8 + e;
+        for (int e = 0; e < 4; ++e) {
+            const int p = pg * 4 + e;
             const int64_t gj = j0 + p;
             const int64_t gjc = gj < n ? gj : n - 1;
+            const float* xj = xa + gjc * DM;
             double kv;
             if (F64E) {
                 double r2 = 0.0;
 #pragma unroll
-                for (int k = 0; k < DM; ++k)
-                    if (k < d) {
-                        const double df = (double)xi[k] - (double)pts[(int64_t)k * n + gjc];
-                        r2 = fma(df, df, r2);
-                    }
+                for (int k = 0; k < DM; ++k) {
+                    const double df = (double)xi[k] - (double)xj[k];
+                    r2 = fma(df, df, r2);
+                }
                 kv = kval64<KIND>(r2, kconst);
             } else {
-                float sv = fmaf(-0.5f, sqn[gjc], mhn);
+                float sv = kpair_init(mhn, sqn[gjc]);
 #pragma unroll
-                for (int k = 0; k < DM; ++k)
-                    if (k < d) sv = fmaf(xi[k], pts[(int64_t)k * n + gjc], sv);
+                for (int k = 0; k < DM; ++k) sv = fmaf(xi[k], xj[k], sv);
                 kv = (double)kval32<KIND>(sv, c);
             }
             As[p][trow] = (gj < n) ? kv : 0.0;
         }
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
+        for (int s = 0; s < 2; ++s) {
             const int k = t & 15;
-            const int col = (t >> 4) + 32 * s;
+            const int col = (t >> 4) + 64 * s;
             const int64_t gj = j0 + k, gc = c0 + col;
             Bs[k][col] = (gj < n && gc < m) ? P[gj + gc * ldp] : 0.0;
         }
         __syncthreads();
 #pragma unroll
         for (int kc = 0; kc < KD_BK; kc += 4) {
-            double a[4], b[4];
+            double a[4], b[2];
 #pragma unroll
             for (int u = 0; u < 4; ++u) a[u] = As[kc + (lane >> 4)][wm * 64 + u * 16 + (lane & 15)];
 #pragma unroll
-            for (int v = 0; v < 4; ++v) b[v] = Bs[kc + (lane >> 4)][wn * 64 + v * 16 + (lane & 15)];
+            for (int v = 0; v < 2; ++v) b[v] = Bs[kc + (lane >> 4)][wn * 32 + v * 16 + (lane & 15)];
 #pragma unroll
             for (int u = 0; u < 4; ++u)
 #pragma unroll
-                for (int v = 0; v < 4; ++v)
+                for (int v = 0; v < 2; ++v)
                     acc[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b[v], acc[u][v], 0, 0, 0);
         }
         __syncthreads();
@@ -103,8 +102,8 @@ __global__ __launch_bounds__(KD_THREADS) void k_kgemm_f64_mfma(
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int64_t gc = c0 + wn * 64 + v * 16 + (lane & 15);
+        for (int v = 0; v < 2; ++v) {
+            const int64_t gc = c0 + wn * 32 + v * 16 + (lane & 15);
             if (gc >= m) continue;
             const double mu = mucol[gc];
             // v_mfma_f64_16x16x4_f64 result layout: element e of lane l is row 4*e + l/16,
@@ -122,13 +121,12 @@ template <int KIND, bool F64E>
 static void kd_dispatch(const KernelOp& op, float c, const double* mucol, const double* P,
                         int64_t ldp, int64_t m, double* W, int64_t ldw, hipStream_t st) {
     dim3 grid((unsigned)((op.n + KD_BM - 1) / KD_BM), (unsigned)((m + KD_BN - 1) / KD_BN));
-#define KDL(DD) k_kgemm_f64_mfma<KIND, DD, F64E><<<grid, KD_THREADS, 0, st>>>(op.n, op.d, op.pts, op.sqn, c, op.kconst, op.scale, mucol, P, ldp, m, W, ldw)
-    switch (op.d) {
-        case 3: KDL(3); break;
+#define KDL(DD) k_kgemm_f64_mfma<KIND, DD, F64E><<<grid, KD_THREADS, 0, st>>>(op.n, op.xa, op.sqn, c, op.kconst, op.scale, mucol, P, ldp, m, W, ldw)
+    switch (op.dm) {
         case 4: KDL(4); break;
         case 8: KDL(8); break;
         case 16: KDL(16); break;
-        default: KDL(0); break;
+        default: KDL(32); break;
     }
 #undef KDL
 }

@@ -1,6 +1,7 @@
 // Event-based kernel timing (see prof.hpp) and its C-ABI accessors.
 #include "prof.hpp"
 
+#include <algorithm>
 #include <atomic>
 #include <cstring>
 #include <mutex>
@@ -14,8 +15,7 @@ namespace rr {
 static std::atomic<int> g_on{0};
 static std::mutex g_mu;
 static std::vector<std::pair<hipEvent_t, hipEvent_t>> g_pending[PROF_NSLOTS];
-static double g_total_ms[PROF_NSLOTS];
-static int64_t g_count[PROF_NSLOTS];
+static std::vector<float> g_ms[PROF_NSLOTS];
 
 bool prof_enabled() { return g_on.load(std::memory_order_relaxed) != 0; }
 
@@ -46,8 +46,7 @@ static void drain(int slot) {
         float ms = 0.0f;
         if (hipEventSynchronize(e.second) == hipSuccess &&
             hipEventElapsedTime(&ms, e.first, e.second) == hipSuccess) {
-            g_total_ms[slot] += ms;
-            g_count[slot] += 1;
+            g_ms[slot].push_back(ms);
         }
         (void)hipEventDestroy(e.first);
         (void)hipEventDestroy(e.second);
@@ -63,8 +62,7 @@ void rr_profile_enable(int32_t on) {
     std::lock_guard<std::mutex> lk(rr::g_mu);
     for (int s = 0; s < rr::PROF_NSLOTS; ++s) {
         rr::drain(s);
-        rr::g_total_ms[s] = 0.0;
-        rr::g_count[s] = 0;
+        rr::g_ms[s].clear();
     }
     rr::g_on.store(on ? 1 : 0);
 }
@@ -73,8 +71,21 @@ rr_status rr_profile_read(int32_t slot, int64_t* count, double* total_ms) {
     if (slot < 0 || slot >= rr::PROF_NSLOTS || !count || !total_ms) return RR_EINVAL;
     std::lock_guard<std::mutex> lk(rr::g_mu);
     rr::drain(slot);
-    *count = rr::g_count[slot];
-    *total_ms = rr::g_total_ms[slot];
+    // launches that a device-side stop flag turned into no-ops (an iteration batch
+    // running past convergence) last a few microseconds: count only launches of at
+    // least a tenth of the median duration
+    std::vector<float> v = rr::g_ms[slot];
+    double tot = 0.0;
+    int64_t c = 0;
+    if (!v.empty()) {
+        std::vector<float> srt = v;
+        std::nth_element(srt.begin(), srt.begin() + srt.size() / 2, srt.end());
+        const float floor_ms = 0.1f * srt[srt.size() / 2];
+        for (float x : v)
+            if (x >= floor_ms) { tot += x; ++c; }
+    }
+    *count = c;
+    *total_ms = tot;
     return RR_OK;
 }
 
