@@ -24,6 +24,8 @@ using namespace rr;
 
 namespace {
 
+constexpr int64_t KMULTI_MAX = 32;
+
 struct Batch {
     const rr_precond& P;
     hipStream_t st;
@@ -31,6 +33,8 @@ struct Batch {
     Alloc alloc;          // the handle's allocator, ordered on the solve stream
     const Alloc* al;
     DBuf R, Pm, Z, W, T, parts, C, Dall, D, state, start, target2, mucol, muidx, gws;
+    DBuf kws, kdot;       // symmetric multi-column kernel matvec (few columns)
+    bool kmulti = false;
     size_t gwsd = 0;
     std::vector<int> mus_used;
     int nch = 1;
@@ -54,6 +58,13 @@ struct Batch {
         muidx.reset(al, (size_t)m * sizeof(int32_t));
         gwsd = std::max<size_t>((size_t)8 * std::max<int64_t>(kb, 1) * m, (size_t)1 << 20);
         gws.reset(al, gwsd * sizeof(double));
+        // a few columns: the symmetric matvec kernel (each entry formed once per
+        // group of up to 8 columns, float64 sums) beats a 128-column MFMA tile
+        kmulti = is_kernel(p.op) && p.opts.prec != RR_PREC_FP64 && m <= KMULTI_MAX;
+        if (kmulti) {
+            kws.reset(al, (kernel_matvec_ws_doubles(n, p.op.d, (int)std::min<int64_t>(m, 8)) + 1) * sizeof(double));
+            kdot.reset(al, (size_t)kernel_matvec_blocks(n) * m * sizeof(double));
+        }
         RR_HIP(hipMemsetAsync(state.ptr(), 0, (size_t)m * sizeof(BState), st));
     }
 
@@ -65,6 +76,13 @@ struct Batch {
 
     // Wout = A_mu Pin for every column (fp64: float64 operator)
     void matmat(const double* Pin, int64_t ldp, double* Wout, bool fp64) {
+        if (kmulti && !fp64 && ldp == n) {
+            const KernelOp k = kernel_op_of(P);
+            launch_kernel_matvec_multi(k, false, Pin, (int)m, 0.0, Wout, kdot.as<double>(), kws.as<double>(),
+                                       nullptr, st);
+            launch_add_shift_cols(n, m, mucol.as<double>(), Pin, ldp, Wout, n, st);
+            return;
+        }
         if (is_kernel(P.op)) {
             const KernelOp k = kernel_op_of(P);
             launch_kernel_matmat_f64(k, fp64 || P.opts.prec == RR_PREC_FP64, mucol.as<double>(), Pin, ldp, m,
@@ -206,9 +224,41 @@ rr_status rr_solve_batch_fused(const rr_precond* Pc, const int32_t* mu_index_per
         // iteration counters live in the device state; seed them
         for (int64_t j = 0; j < m; ++j) { hs[j] = BState{}; hs[j].iters = 0; }
         RR_HIP(hipMemcpyAsync(Bt.state.ptr(), hs.data(), m * sizeof(BState), hipMemcpyHostToDevice, st));
+        // optional hipGraph of one batch of check_every iterations, captured on a
+        // private stream the first time and replayed after every host check
+        hipStream_t cap = nullptr;
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t gexec = nullptr;
+        struct GraphGuard {
+            hipStream_t* s; hipGraph_t* g; hipGraphExec_t* e;
+            ~GraphGuard() {
+                if (*e) (void)hipGraphExecDestroy(*e);
+                if (*g) (void)hipGraphDestroy(*g);
+                if (*s) (void)hipStreamDestroy(*s);
+            }
+        } gguard{&cap, &graph, &gexec};
+        auto run_batch = [&]() {
+            if (!o->use_graph) {
+                for (int k = 0; k < o->check_every; ++k) Bt.iteration(X, ldx);
+                return;
+            }
+            RR_HIP(hipStreamSynchronize(st));   // everything queued on st precedes the replay
+            if (!gexec) {
+                RR_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+                Bt.st = cap;
+                RR_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+                for (int k = 0; k < o->check_every; ++k) Bt.iteration(X, ldx);
+                const hipError_t ce = hipStreamEndCapture(cap, &graph);
+                Bt.st = st;
+                RR_HIP(ce);
+                RR_HIP(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
+            }
+            RR_HIP(hipGraphLaunch(gexec, cap));
+            RR_HIP(hipStreamSynchronize(cap));
+        };
         bool running = restart_pass();
         while (running) {
-            for (int k = 0; k < o->check_every; ++k) Bt.iteration(X, ldx);
+            run_batch();
             RR_HIP(hipGetLastError());
             RR_HIP(hipMemcpyAsync(hs.data(), Bt.state.ptr(), m * sizeof(BState), hipMemcpyDeviceToHost, st));
             RR_HIP(hipStreamSynchronize(st));

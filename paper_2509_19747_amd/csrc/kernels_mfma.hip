@@ -4,9 +4,12 @@
 // A is symmetric, so row i of A (the MFMA A-operand: 8 consecutive k per lane)
 // is read as column i of the column-major bf16 copy -- contiguous 16-byte loads.
 // Block: 512 threads = 8 waves in a 4 (rows) x 2 (columns) grid of 64 x 128 wave
-// tiles; block tile 256 x 256; k step 32 (one v_mfma_f32_16x16x32_bf16 depth).
-// The A and Omega slices are staged in LDS with padded rows; the next step's
-// global loads are issued before the current step's MFMAs.
+// tiles (2 x 4 tiles of v_mfma_f32_32x32x16_bf16, which sustains close to the bf16
+// peak where the 16x16x32 form reaches about half); block tile 256 x 256; k step
+// 32 (two MFMA depths).  The A and Omega slices are staged in LDS with padded
+// rows; the next step's global loads are issued before the current step's MFMAs.
+// Accumulator element j of lane l is row 8*(j/4) + 4*(l/32) + (j%4), column l%32
+// of its 32 x 32 tile.
 #include "common.hpp"
 #include "kernels.hpp"
 #include "prof.hpp"
@@ -14,7 +17,7 @@
 namespace rr {
 
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
-typedef float f32x4_t __attribute__((ext_vector_type(4)));
+typedef float f32x16_t __attribute__((ext_vector_type(16)));
 constexpr int DG_BM = 256, DG_BN = 256, DG_BK = 32, DG_THREADS = 512;
 constexpr int DG_LD = 40;   // padded LDS row (bf16)
 
@@ -30,11 +33,13 @@ __global__ __launch_bounds__(DG_THREADS) void k_dense_gemm_bf16(
     const int64_t c0 = (int64_t)blockIdx.y * DG_BN;
     const bool vec_a = (lda % 8) == 0, vec_b = (ldb % 8) == 0;
 
-    f32x4_t acc[4][8];
+    f32x16_t acc[2][4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+    for (int u = 0; u < 2; ++u)
 #pragma unroll
-        for (int v = 0; v < 8; ++v) acc[u][v] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+        for (int v = 0; v < 4; ++v)
+#pragma unroll
+            for (int j = 0; j < 16; ++j) acc[u][v][j] = 0.0f;
 
     // chunk q (0..1023) of a 256 x 32 slice: row q>>2, 8 k values at 8*(q&3)
     auto load_chunk = [&](const uint16_t* base, int64_t ld, int64_t lim_row, int64_t row0,
@@ -77,34 +82,41 @@ __global__ __launch_bounds__(DG_THREADS) void k_dense_gemm_bf16(
                 rb[s] = load_chunk(B, ldb, m, c0, k0 + DG_BK, t + DG_THREADS * s, vec_b);
             }
         }
-        bf16x8_t a[4];
+        const int kq = 8 * (lane >> 5);
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int row = wm * 64 + u * 16 + (lane & 15);
-            a[u] = __builtin_bit_cast(bf16x8_t, *(const uint4*)&As[row * DG_LD + 8 * (lane >> 4)]);
-        }
+        for (int kh = 0; kh < 2; ++kh) {
+            __builtin_amdgcn_sched_barrier(0);
+            bf16x8_t a[2], b[4];
 #pragma unroll
-        for (int v = 0; v < 8; ++v) {
-            const int col = wn * 128 + v * 16 + (lane & 15);
-            const bf16x8_t b = __builtin_bit_cast(bf16x8_t, *(const uint4*)&Bs[col * DG_LD + 8 * (lane >> 4)]);
+            for (int u = 0; u < 2; ++u) {
+                const int row = wm * 64 + u * 32 + (lane & 31);
+                a[u] = __builtin_bit_cast(bf16x8_t, *(const uint4*)&As[row * DG_LD + 16 * kh + kq]);
+            }
 #pragma unroll
-            for (int u = 0; u < 4; ++u)
-                acc[u][v] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[u], b, acc[u][v], 0, 0, 0);
+            for (int v = 0; v < 4; ++v) {
+                const int col = wn * 128 + v * 32 + (lane & 31);
+                b[v] = __builtin_bit_cast(bf16x8_t, *(const uint4*)&Bs[col * DG_LD + 16 * kh + kq]);
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+#pragma unroll
+                for (int u = 0; u < 2; ++u)
+                    acc[u][v] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[u], b[v], acc[u][v], 0, 0, 0);
         }
         __syncthreads();
     }
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < 2; ++u) {
 #pragma unroll
-        for (int v = 0; v < 8; ++v) {
-            const int64_t gc = c0 + wn * 128 + v * 16 + (lane & 15);
+        for (int v = 0; v < 4; ++v) {
+            const int64_t gc = c0 + wn * 128 + v * 32 + (lane & 31);
             if (gc >= m) continue;
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int64_t gr = i0 + wm * 64 + u * 16 + 4 * (lane >> 4) + e;
+            for (int j = 0; j < 16; ++j) {
+                const int64_t gr = i0 + wm * 64 + u * 32 + 8 * (j >> 2) + 4 * (lane >> 5) + (j & 3);
                 if (gr < n) {
                     const float bval = __uint_as_float((uint32_t)B[gc * ldb + gr] << 16);
-                    Y[gr + gc * ldy] = fmaf(mu, bval, acc[u][v][e]);
+                    Y[gr + gc * ldy] = fmaf(mu, bval, acc[u][v][j]);
                 }
             }
         }

@@ -40,8 +40,10 @@ size_t request_bytes(const rr_request& r) {
     double b = n * l * (4 + 2 + 8 + 4 + 8 + 16);        // Omega f32/bf16, Q, Y, W, Theta
     b += n * d * 4 + n * 4;                              // points, |x|^2
     b += l * l * 8 * 26 + 4.0 * (2 * l) * (2 * l) * 8;   // l x l factors, GEMM workspace
-    b += 2.0 * 256 * n * 8;                              // matvec slice partials (upper bound)
-    b += n * 8 * (8 + 2 * m);                            // CG vectors, B and X columns
+    const int nr = (int)std::min<double>(m, 8.0);
+    b += 8.0 * (double)std::max(rr::kernel_matvec_ws_doubles(r.n, r.d, nr),   // matvec slot partials
+                                rr::kernel_matvec_ws_doubles(r.n, r.d, 2));
+    b += n * 8 * (8 + 8 * m);                            // CG vectors, batched PCG blocks, B and X
     b += 64.0 * 1024 * 1024;                             // fixed slack
     return (size_t)b;
 }
@@ -84,17 +86,20 @@ void run_job(const rr_serve_config& cfg, Job& job, hipStream_t st, double t0, rr
     float* pts = nullptr;
     double *b = nullptr, *x = nullptr;
     const int64_t n = r.n;
+    const int64_t nr = std::max<int32_t>(r.nrhs, 1);
     auto fail = [&](rr_status s) { info.status = s; };
     rr_allocator alloc{nullptr, async_alloc, async_free};
     do {
         if (hipMallocAsync((void**)&pts, (size_t)r.d * n * sizeof(float), st) != hipSuccess ||
-            hipMallocAsync((void**)&b, (size_t)n * sizeof(double), st) != hipSuccess ||
-            hipMallocAsync((void**)&x, (size_t)n * sizeof(double), st) != hipSuccess) {
+            hipMallocAsync((void**)&b, (size_t)n * nr * sizeof(double), st) != hipSuccess ||
+            hipMallocAsync((void**)&x, (size_t)n * nr * sizeof(double), st) != hipSuccess) {
             (void)hipGetLastError();
             fail(RR_ENOMEM);
             break;
         }
-        if (hipMemcpyAsync(pts, r.pts, (size_t)r.d * n * sizeof(float), hipMemcpyHostToDevice, st) != hipSuccess) {
+        if (hipMemcpyAsync(pts, r.pts, (size_t)r.d * n * sizeof(float), hipMemcpyHostToDevice, st) != hipSuccess ||
+            hipMemcpyAsync(b, r.B, (size_t)n * nr * sizeof(double), hipMemcpyHostToDevice, st) != hipSuccess ||
+            hipMemsetAsync(x, 0, (size_t)n * nr * sizeof(double), st) != hipSuccess) {
             fail(RR_EDEVICE);
             break;
         }
@@ -111,6 +116,8 @@ void run_job(const rr_serve_config& cfg, Job& job, hipStream_t st, double t0, rr
         const double mu = r.mu;
         rr_status s = rr_build_precond(&op, &mu, 1, &bo, &alloc, st, &P);
         if (s != RR_OK) { fail(s); break; }
+        // every right-hand side of the request in one fused batched PCG, its
+        // iteration batches replayed as a hipGraph
         rr_solve_opts so = cfg.solve;
         if (cfg.graph_iters > 0) {
             so.use_graph = 1;
@@ -118,28 +125,23 @@ void run_job(const rr_serve_config& cfg, Job& job, hipStream_t st, double t0, rr
         }
         so.relres_history = nullptr;
         so.history_cap = 0;
+        std::vector<int32_t> mu_idx((size_t)nr, 0);
+        std::vector<rr_solve_info> infos((size_t)nr);
+        s = rr_solve_batch(P, mu_idx.data(), b, n, (int32_t)nr, x, n, &so, infos.data(), st);
         int iters = 0;
         double worst = 0.0, worst64 = 0.0;
-        for (int j = 0; j < r.nrhs; ++j) {
-            if (hipMemcpyAsync(b, r.B + (size_t)j * n, (size_t)n * sizeof(double), hipMemcpyHostToDevice, st) != hipSuccess ||
-                hipMemsetAsync(x, 0, (size_t)n * sizeof(double), st) != hipSuccess) {
-                s = RR_EDEVICE;
-                break;
-            }
-            rr_solve_info si{};
-            s = rr_solve(P, 0, b, x, &so, &si, st);
+        for (const rr_solve_info& si : infos) {
             iters = std::max(iters, si.iters);
             worst = std::max(worst, si.relres_work);
             if (std::isfinite(si.relres_fp64)) worst64 = std::max(worst64, si.relres_fp64);
             info.tau = si.tau; info.normE = si.normE; info.lamhat = si.lamhat; info.orth_err = si.orth_err;
             info.ms_build = si.ms_build;
-            info.ms_solve += si.ms_solve;
-            if (hipMemcpyAsync(r.X + (size_t)j * n, x, (size_t)n * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
-                hipStreamSynchronize(st) != hipSuccess) {
-                s = RR_EDEVICE;
-                break;
-            }
-            if (s != RR_OK) break;
+            info.ms_solve = si.ms_solve;
+            info.restarts = std::max(info.restarts, si.restarts);
+        }
+        if (hipMemcpyAsync(r.X, x, (size_t)n * nr * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess) {
+            s = RR_EDEVICE;
         }
         info.iters = iters;
         info.relres_work = worst;

@@ -380,12 +380,39 @@ def test_batched_multi_shift_matches_single_and_oracle(prec):
             dA = prob.n * 2.0 ** -23 * prob.scale
             assert rel64 <= tol + dA * np.linalg.norm(X[:, c]) / np.linalg.norm(B[:, c])
         xs = x1.cpu().numpy()
-        assert np.linalg.norm(xs - X[:, c]) <= 50 * tol / mu * np.linalg.norm(B[:, c]) * prob.scale * 0 + \
-            np.linalg.norm(xs) * 1e-3 + 1e-12
+        assert np.linalg.norm(xs - X[:, c]) <= np.linalg.norm(xs) * 1e-3 + 1e-12
     # the same column alone in a batch of one and inside the full batch
     X1, inf1, _ = P.solve_batch(_cuda(B[:, 5:6]), [mus_idx[5]], tol=tol, check_every=4)
     assert inf1[0]["iters"] == infos[5]["iters"]
     assert np.allclose(X1.cpu().numpy()[:, 0], X[:, 5], rtol=0, atol=1e-9 * np.abs(X[:, 5]).max())
+
+
+def test_batched_graph_replay_and_wide_block():
+    # 40 columns take the float64-MFMA kernel product, 5 columns the symmetric
+    # few-column matvec; graph replay of the iteration batches must equal eager
+    prob = workloads.cfg_batched(n=3000, d=16, l=60, nrhs=40)
+    op = Operator.from_problem(prob)
+    mu = prob.mus[1]
+    kop = rr.kernel_operator(rr.OP_RBF, _cuda(prob.pts), prob.kconst, prob.scale)
+    P = rr.build_precond(kop, [mu], l=prob.l, sketch="srht", seed=prob.omega_seed, prec="fp32")
+    B = prob.B
+    tol = 1e-6
+    Xe, ie, st = P.solve_batch(_cuda(B), [0] * 40, tol=tol, check_every=4)
+    Xg, ig, sg = P.solve_batch(_cuda(B), [0] * 40, tol=tol, check_every=4, use_graph=True)
+    assert st == rr.RR_OK and sg == rr.RR_OK
+    assert torch.equal(Xe, Xg)
+    assert [i["iters"] for i in ie] == [i["iters"] for i in ig]
+    Xe = Xe.cpu().numpy()
+    dA = prob.n * 2.0 ** -23 * prob.scale
+    for c in range(40):
+        rel64 = osol.relres(op.shifted(mu), Xe[:, c], B[:, c])
+        assert rel64 <= tol + dA * np.linalg.norm(Xe[:, c]) / np.linalg.norm(B[:, c])
+    X5, i5, s5 = P.solve_batch(_cuda(B[:, :5].copy()), [0] * 5, tol=tol, check_every=4)
+    assert s5 == rr.RR_OK
+    X5 = X5.cpu().numpy()
+    for c in range(5):
+        assert abs(i5[c]["iters"] - ie[c]["iters"]) <= 2
+        assert np.linalg.norm(X5[:, c] - Xe[:, c]) <= 1e-3 * np.linalg.norm(Xe[:, c])
 
 
 def test_batched_dense_operator():
