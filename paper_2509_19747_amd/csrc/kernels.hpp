@@ -136,6 +136,12 @@ void launch_kernel_matvec(const KernelOp& op, bool fp64, const double* u, double
 void launch_kernel_matvec_multi(const KernelOp& op, bool fp64, const double* u, int nr, double mu,
                                 double* y, double* dot_part, double* ws, const int32_t* stop,
                                 hipStream_t st, bool estimate = false);
+// Symmetric kernel matvec with the pair terms on bf16 MFMA (three-piece split,
+// float32-class entries, float64 sums), nr in {1, 2} (kernels_ksym_mma.hip).
+bool kernel_mma_ok(int64_t n, int d);
+size_t kernel_mma_ws_doubles(int64_t n, int nr);
+void launch_kernel_matvec_mma(const KernelOp& op, const double* u, int nr, double mu, double* y,
+                              double* dot_part, double* ws, const int32_t* stop, hipStream_t st);
 // Symmetric float32 matvec, nr in {1, 2, 4, 8} (kernels_ksym.hip).
 size_t kernel_sym_ws_doubles(int64_t n, int d, int nr);
 // a32: float32 products and sums (estimate grade, nr <= 2), for power iterations.

@@ -183,6 +183,7 @@ size_t kernel_matvec_ws_doubles(int64_t n, int d, int nr) {
     size_t w = (size_t)2 * (size_t)kmv64_slices(n) * (size_t)n;
     for (int c = 1; c <= 8; c *= 2)
         if (c == 1 || c <= nr) w = std::max(w, kernel_sym_ws_doubles(n, d, c));
+    if (kernel_mma_ok(n, d)) w = std::max(w, kernel_mma_ws_doubles(n, std::min(nr, 2)));
     return w;
 }
 
@@ -200,6 +201,14 @@ void launch_kernel_matvec_multi(const KernelOp& op, bool fp64, const double* u, 
             const int slices = kmv_stage1_f64(op, uq, c, ws, stop, st);
             k_kmv_finish<<<(unsigned)nblk, 256, 0, st>>>(op.n, slices, c, ws, op.scale, mu, uq, yq, dq,
                                                          stop);
+            q0 += c;
+        } else if (kernel_mma_ok(op.n, op.d)) {
+            // pair terms on bf16 MFMA, two columns at a time: every column goes through
+            // the same arithmetic whatever the block width, so a column solved alone
+            // and inside a block gives bitwise the same products (this path also
+            // serves the power iterations)
+            const int c = left >= 2 ? 2 : 1;
+            launch_kernel_matvec_mma(op, uq, c, mu, yq, dq, ws, stop, st);
             q0 += c;
         } else {
             const int c = left >= 8 ? 8 : left >= 4 ? 4 : left >= 2 ? 2 : 1;

@@ -1,0 +1,462 @@
+// Symmetric kernel matvec with the pair terms on bf16 MFMA:
+// Y = scale * K U + mu U for NR = 1 or 2 columns (the PCG operator of kernel
+// ridge regression, Section 7.2.2, and the two-column power iterations of the
+// shift estimates).
+//
+// The exponent of an entry is one inner product of augmented point records:
+//   row    a_i = [g x_i, -g |x_i|^2 / 2, 1]
+//   column b_j = [x_j,   1, -g |x_j|^2 / 2]
+//   a_i . b_j = g (x_i . x_j - |x_i|^2 / 2 - |x_j|^2 / 2) = -g |x_i - x_j|^2 / 2
+// with g = c = 2 kconst log2(e) for the RBF kernel, so K_ij = exp2(a_i . b_j),
+// and g = 1 for Matern-3/2, where the product is s_ij of kval32.
+//
+// Float32 accuracy on bf16 MFMA: every float32 term v splits exactly into three
+// bf16 pieces v = v0 + v1 + v2 (each piece rounds the remainder of the previous
+// ones to 8 significant bits; 24 bits in all).  A product x y is then the six
+// piece products with a + b <= 2 (x0 y0, x0 y1, x1 y0, x0 y2, x1 y1, x2 y0); the
+// three dropped ones are below 2^-24 |x y|.  Each piece product is exact in
+// float32 and v_mfma_f32_32x32x16_bf16 adds them in float32, so the exponent
+// carries float32-class rounding.  The record terms are laid out as six segments
+// of DM coordinates (the piece pairs above), then the two augmented terms as
+// [p0, p1, p2, 1, 1, 1] x [1, 1, 1, q0, q1, q2], then zeros: 6 DM + 6 terms in
+// KB steps of 16.
+//
+// Rows are grouped in blocks of 256 (8 waves x 32 rows).  Work item (I, r, s)
+// covers row block I against the column blocks J of run r (J = I + r m, ..., up to
+// m of them, J < nb), restricted to the s-th of S column ranges.  Each pair (i, j)
+// is evaluated once and its entry feeds y_i (row sums in registers) and y_j
+// (column sums: the lane's 16 rows, then the two half-waves, then the eight waves
+// in a fixed order): off the diagonal blocks by construction, and inside a
+// diagonal block because wave w forms only the column tiles >= w and, in its own
+// 32 x 32 tile, only the pairs with row <= column.  So the operator is exactly
+// symmetric.
+//
+// Partial slots (float64, n per slot and column): the row sums of item (I, r, s) go
+// to slot (I + r) S + s of the rows of I; column sums from row block I < J to slot
+// I S of the columns (exactly one range s covers a column); column sums inside the
+// diagonal block to slot nb S.  So row i of block b owns slots p S for p < b, the
+// slots from b S to (b + R_b) S (R_b = ceil((nb - b) / m) runs) and slot nb S, each
+// written by exactly one item, and the finish adds them in that order (bitwise
+// reproducible).
+//
+// MFMA layout (v_mfma_f32_32x32x16_bf16): lane l supplies A[row l%32][k 8(l/32) ..
+// 8(l/32)+7] and B[k 8(l/32) .. +7][col l%32] of a 16-deep step; accumulator
+// element e of lane l is row 8(e/4) + 4(l/32) + (e%4), column l%32.
+#include "common.hpp"
+#include "kentry.hpp"
+#include "kernels.hpp"
+#include "prof.hpp"
+
+#include <algorithm>
+#include <type_traits>
+
+namespace rr {
+
+typedef float f32x16_t __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+constexpr int KM_WAVES = 8;
+constexpr int KM_THREADS = 64 * KM_WAVES;
+constexpr int KM_RB = 32 * KM_WAVES;   // rows (and columns) per block
+constexpr int KM_CT = KM_RB / 32;      // column tiles per block
+constexpr int KM_MAX_SLOTS = 2048;     // partial slots per row (bounds the workspace)
+
+template <int DM>
+struct KmmaShape {
+    static constexpr int KT = 6 * DM + 6;       // record terms
+    static constexpr int KB = (KT + 15) / 16;   // MFMA steps
+    static constexpr int BSTR = 16 * KB;        // LDS stride (bf16) of a column record
+};
+
+// Piece of x (row side) and of y (column side) in segment seg.
+constexpr int kmma_apiece(int seg) { return seg == 2 || seg == 4 ? 1 : seg == 5 ? 2 : 0; }
+constexpr int kmma_bpiece(int seg) { return seg == 1 || seg == 4 ? 1 : seg == 3 ? 2 : 0; }
+
+// Exact split v = p[0] + p[1] + p[2] into bf16 pieces (normal-range v).
+RR_DEV void kmma_split3(float v, __bf16 (&p)[3]) {
+    p[0] = (__bf16)v;
+    const float r1 = v - (float)p[0];
+    p[1] = (__bf16)r1;
+    p[2] = (__bf16)(r1 - (float)p[1]);
+}
+
+// The KB record chunks (8 terms each) that half h of a wave supplies for one
+// point: terms kk = 16 s + 8 h + t, t < 8, of step s.  ROW: the row record
+// (coordinates scaled by g, augmented terms [p0, p1, p2, 1, 1, 1]); otherwise the
+// column record (augmented terms [1, 1, 1, q0, q1, q2]).  rec: the point's DM
+// coordinates; sq: its squared norm; emit(s, chunk) receives the chunks in order.
+template <int DM, bool ROW, typename Emit>
+RR_DEV void kmma_record(const float* __restrict__ rec, float sq, float g, int h, Emit&& emit) {
+    constexpr int KB = KmmaShape<DM>::KB;
+    const __bf16 one = (__bf16)1.0f, zero = (__bf16)0.0f;
+    __bf16 pa[3];
+    kmma_split3(-0.5f * g * sq, pa);
+    auto aug = [&](int ka) {   // augmented term ka >= 0 (past the six segments)
+        if (ka >= 6) return zero;
+        if (ROW) return ka < 3 ? pa[ka] : one;
+        return ka < 3 ? one : pa[ka - 3];
+    };
+    auto piece = [&](int seg) { return ROW ? kmma_apiece(seg) : kmma_bpiece(seg); };
+    if constexpr (DM >= 16) {
+        // step s covers segment 16 s / DM, coordinates (16 s) % DM + 8 h + t
+        __bf16 pc[DM / 16][8][3];
+#pragma unroll
+        for (int m = 0; m < DM / 16; ++m)
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                const float v = rec[16 * m + 8 * h + t];
+                kmma_split3(ROW ? g * v : v, pc[m][t]);
+            }
+#pragma unroll
+        for (int s = 0; s < KB; ++s) {
+            bf16x8_t o;
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                if (16 * s < 6 * DM) o[t] = pc[(16 * s % DM) / 16][t][piece(16 * s / DM)];
+                else o[t] = h == 0 ? aug(16 * s + t - 6 * DM) : zero;
+            }
+            emit(s, o);
+        }
+    } else {
+        __bf16 pc[DM][3];
+#pragma unroll
+        for (int k = 0; k < DM; ++k) kmma_split3(ROW ? g * rec[k] : rec[k], pc[k]);
+        auto val = [&](int kk) { return kk < 6 * DM ? pc[kk % DM][piece(kk / DM)] : aug(kk - 6 * DM); };
+#pragma unroll
+        for (int s = 0; s < KB; ++s) {
+            bf16x8_t o;
+#pragma unroll
+            for (int t = 0; t < 8; ++t) o[t] = h ? val(16 * s + 8 + t) : val(16 * s + t);
+            emit(s, o);
+        }
+    }
+}
+
+// Work items (I, r, s): row block I, run r of up to m column blocks starting at
+// I + r m, column range s of S (S > 1 only with m = 1, for small n).
+struct KmmaPlan {
+    int nb, m, S;
+    int64_t items;
+};
+
+static KmmaPlan kmma_plan(int64_t n) {
+    KmmaPlan p;
+    p.nb = (int)((n + KM_RB - 1) / KM_RB);
+    const int64_t tiles = (int64_t)p.nb * (p.nb + 1) / 2;
+    p.m = (int)std::min<int64_t>(8, std::max<int64_t>(1, tiles / 4096));
+    int S = 1;
+    while (p.m == 1 && S < KM_CT / 2 && tiles * S < 1024) S *= 2;   // a few items per compute unit
+    p.S = S;
+    int64_t runs = 0;
+    for (int I = 0; I < p.nb; ++I) runs += (p.nb - I + p.m - 1) / p.m;
+    p.items = runs * S;
+    return p;
+}
+
+// Entry from the record product t (see above).
+template <int KIND>
+RR_DEV float kmma_entry(float t, float c) {
+    // t is -g r^2 / 2 <= 0 up to rounding; near-coincident points may round to a
+    // tiny positive t and give an entry a few ulps above 1
+    if (KIND == 1) return __builtin_amdgcn_exp2f(t);
+    return kval32<2>(t, c);
+}
+
+// Sum over the 32 lanes of a half-wave of v[0..15] (reduce-scatter butterfly in a
+// fixed order): on return lanes 2e and 2e + 1 of the half hold the total of v[e].
+RR_DEV double kmma_rowsum16(double (&v)[16], int l32) {
+    double w8[8], w4[4], w2[2];
+    {
+        const bool b = (l32 >> 4) & 1;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const double keep = b ? v[8 + e] : v[e], send = b ? v[e] : v[8 + e];
+            w8[e] = keep + __shfl_xor(send, 16, 64);
+        }
+    }
+    {
+        const bool b = (l32 >> 3) & 1;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const double keep = b ? w8[4 + e] : w8[e], send = b ? w8[e] : w8[4 + e];
+            w4[e] = keep + __shfl_xor(send, 8, 64);
+        }
+    }
+    {
+        const bool b = (l32 >> 2) & 1;
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            const double keep = b ? w4[2 + e] : w4[e], send = b ? w4[e] : w4[2 + e];
+            w2[e] = keep + __shfl_xor(send, 4, 64);
+        }
+    }
+    const bool b = (l32 >> 1) & 1;
+    const double keep = b ? w2[1] : w2[0], send = b ? w2[0] : w2[1];
+    const double w1 = keep + __shfl_xor(send, 2, 64);
+    // lanes 2e and 2e + 1 add the same two partials in opposite order: equal sums
+    return w1 + __shfl_xor(w1, 1, 64);
+}
+
+template <int KIND, int DM, int NR>
+__global__ __launch_bounds__(KM_THREADS) __attribute__((amdgpu_waves_per_eu(NR == 1 ? 4 : 2))) void k_ksym_mma(
+    int64_t n, const float* __restrict__ xa, const float* __restrict__ sqn, float c,
+    const double* __restrict__ u, double* __restrict__ part, int nb, int m, int S,
+    const int32_t* __restrict__ stop) {
+    using Sh = KmmaShape<DM>;
+    constexpr int KB = Sh::KB, BSTR = Sh::BSTR;
+    __shared__ __attribute__((aligned(16))) __bf16 bs[KM_RB * BSTR];   // column records (B layout)
+    __shared__ double us[NR][KM_RB];                                    // column u_j
+    __shared__ __attribute__((aligned(16))) double ur[NR][KM_RB];       // row u_i
+    __shared__ double colw[KM_WAVES][NR][KM_RB];                        // column partials per wave
+    if (stop && *stop) return;
+
+    // item -> (bi, r, s)
+    int64_t t = blockIdx.x / S;
+    const int sr = (int)(blockIdx.x % S);
+    int bi = 0;
+    while (t >= (nb - bi + m - 1) / m) { t -= (nb - bi + m - 1) / m; ++bi; }
+    const int run = (int)t;
+    const int bj0 = bi + run * m, bj1 = std::min(bj0 + m, nb);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int h = lane >> 5, l32 = lane & 31;
+    const int64_t r0 = (int64_t)bi * KM_RB + 32 * wave;   // the wave's 32 rows
+    const int cpr = KM_CT / S;                             // column tiles of a range
+    const int ct0 = sr * cpr, ct1 = ct0 + cpr;
+    const float g = KIND == 1 ? c : 1.0f;
+
+    // the wave's rows: A operands, and u at the 16 rows of this lane's outputs
+    bf16x8_t areg[KB];
+    {
+        const int64_t i = r0 + l32;
+        const int64_t ic = i < n ? i : n - 1;
+        kmma_record<DM, true>(xa + ic * DM, sqn[ic], g, h, [&](int s, const bf16x8_t& v) { areg[s] = v; });
+    }
+    double acc[16][NR];
+#pragma unroll
+    for (int e = 0; e < 16; ++e)
+#pragma unroll
+        for (int q = 0; q < NR; ++q) acc[e][q] = 0.0;
+    for (int e = tid; e < NR * KM_RB; e += KM_THREADS) {
+        const int q = e / KM_RB, rl = e % KM_RB;
+        const int64_t i = (int64_t)bi * KM_RB + rl;
+        ur[q][rl] = i < n ? u[(int64_t)q * n + i] : 0.0;
+    }
+
+    auto dots = [&](int ct) {
+        const bf16x8_t* bp = reinterpret_cast<const bf16x8_t*>(&bs[(32 * ct + l32) * BSTR + 8 * h]);
+        // B chunks two steps ahead of the MFMA that uses them
+        bf16x8_t b0 = bp[0], b1 = KB > 1 ? bp[2] : b0;
+        f32x16_t d;
+#pragma unroll
+        for (int e = 0; e < 16; ++e) d[e] = 0.0f;
+#pragma unroll
+        for (int s = 0; s < KB; ++s) {
+            const bf16x8_t b2 = s + 2 < KB ? bp[2 * (s + 2)] : b1;
+            d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(areg[s], b0, d, 0, 0, 0);
+            b0 = b1;
+            b1 = b2;
+        }
+        return d;
+    };
+    // Columns past n carry u = 0 (no row-sum contribution; their column sums are
+    // not stored); rows past n carry u = 0 likewise.
+    // DG: the wave's own tile of a diagonal block; only pairs with row <= column
+    // count (row sums), and row < column (column sums)
+    auto entries = [&](int ct, const f32x16_t& dot, auto dg) {
+        constexpr bool DG = decltype(dg)::value;
+        const int jl = 32 * ct + l32;   // the lane's column within the block
+        const int uro = 32 * wave + 4 * h;
+        double uj[NR], cs[2][NR];
+#pragma unroll
+        for (int q = 0; q < NR; ++q) {
+            uj[q] = us[q][jl];
+            cs[0][q] = 0.0;
+            cs[1][q] = 0.0;
+        }
+#pragma unroll
+        for (int g4 = 0; g4 < 4; ++g4) {
+            // rows 8 g4 + 4 h + (0..3) of the wave: consecutive
+            double ui[4][NR];
+#pragma unroll
+            for (int q = 0; q < NR; ++q) {
+                const double2* up = reinterpret_cast<const double2*>(&ur[q][uro + 8 * g4]);
+                const double2 a = up[0], b = up[1];
+                ui[0][q] = a.x; ui[1][q] = a.y; ui[2][q] = b.x; ui[3][q] = b.y;
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int e = 4 * g4 + r;
+                const double kv = (double)kmma_entry<KIND>(dot[e], c);
+                double kr = kv, kc = kv;
+                if constexpr (DG) {
+                    const int rr = 8 * g4 + 4 * h + r;   // the entry's row within the tile
+                    kr = rr <= l32 ? kv : 0.0;
+                    kc = rr < l32 ? kv : 0.0;
+                }
+#pragma unroll
+                for (int q = 0; q < NR; ++q) {
+                    acc[e][q] = fma(kr, uj[q], acc[e][q]);
+                    cs[e & 1][q] = fma(kc, ui[r][q], cs[e & 1][q]);
+                }
+            }
+        }
+        // the two half-waves hold the same column for different rows; both store
+        // the same sum (addition is commutative)
+#pragma unroll
+        for (int q = 0; q < NR; ++q) {
+            const double v = cs[0][q] + cs[1][q];
+            colw[wave][q][jl] = v + __shfl_xor(v, 32, 64);
+        }
+    };
+
+    const int64_t cslot = (int64_t)bi * S;
+    const int64_t dslot = (int64_t)nb * S;   // column sums inside diagonal blocks
+#pragma unroll 1
+    for (int bj = bj0; bj < bj1; ++bj) {
+        const int64_t cbase = (int64_t)bj * KM_RB;
+        if (bj != bj0) __syncthreads();   // the previous block's records and partials are consumed
+        // stage the column records: two threads per column, one per half of the
+        // record chunks (columns past n: the last point, with u = 0)
+        for (int e = tid; e < 2 * 32 * cpr; e += KM_THREADS) {
+            const int jl = 32 * ct0 + (e >> 1), hh = e & 1;
+            const int64_t j = cbase + jl;
+            const int64_t jc = j < n ? j : n - 1;
+            __bf16* dst = &bs[jl * BSTR + 8 * hh];
+            kmma_record<DM, false>(xa + jc * DM, sqn[jc], g, hh, [&](int s, const bf16x8_t& v) {
+                *reinterpret_cast<bf16x8_t*>(dst + 16 * s) = v;
+            });
+            if (hh == 0) {
+#pragma unroll
+                for (int q = 0; q < NR; ++q) us[q][jl] = j < n ? u[(int64_t)q * n + j] : 0.0;
+            }
+        }
+        __syncthreads();
+        // in the diagonal block wave w forms only the column tiles >= w, so each pair
+        // is evaluated once and the operator stays exactly symmetric
+        const int wlo = bj == bi ? wave : -1;
+#pragma unroll 1
+        for (int ct = ct0; ct < ct1; ++ct) {
+            if (ct <= wlo) {
+                if (ct == wlo) {
+                    entries(ct, dots(ct), std::true_type{});
+                } else {
+#pragma unroll
+                    for (int q = 0; q < NR; ++q) colw[wave][q][32 * ct + l32] = 0.0;
+                }
+                continue;
+            }
+            entries(ct, dots(ct), std::false_type{});
+        }
+        __syncthreads();
+        const int64_t slot = bj != bi ? cslot : dslot;
+        for (int e = tid; e < NR * 32 * cpr; e += KM_THREADS) {
+            const int q = e / (32 * cpr), jl = 32 * ct0 + e % (32 * cpr);
+            const int64_t j = cbase + jl;
+            if (j < n) {
+                double v = 0.0;
+#pragma unroll
+                for (int w = 0; w < KM_WAVES; ++w) v += colw[w][q][jl];
+                part[(slot * NR + q) * n + j] = v;
+            }
+        }
+    }
+    // row sums of the run
+    const int64_t rslot = (int64_t)(bi + run) * S + sr;
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+        double v[16];
+#pragma unroll
+        for (int e = 0; e < 16; ++e) v[e] = acc[e][q];
+        const double tot = kmma_rowsum16(v, l32);
+        const int e = l32 >> 1;
+        const int64_t i = r0 + 8 * (e >> 2) + 4 * h + (e & 3);
+        if ((l32 & 1) == 0 && i < n) part[(rslot * NR + q) * n + i] = tot;
+    }
+}
+
+// y_q = scale * (sum of row i's slots) + mu u_q, with block partials of u_q^T y_q.
+__global__ __launch_bounds__(256) void k_ksym_mma_finish(int64_t n, int rb, int nb, int m, int S, int nr,
+                                                         const double* __restrict__ part,
+                                                         double scale, double mu,
+                                                         const double* __restrict__ u,
+                                                         double* __restrict__ y,
+                                                         double* __restrict__ dot_part,
+                                                         const int32_t* __restrict__ stop) {
+    __shared__ double sc[4];
+    if (stop && *stop) return;
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int b = (int)(i / rb);
+    for (int q = 0; q < nr; ++q) {
+        double dot = 0.0;
+        if (i < n) {
+            // slots in a fixed order, four running sums so that loads stay in flight
+            double s4[4] = {0.0, 0.0, 0.0, 0.0};
+            int p = 0;
+            for (; p + 4 <= b; p += 4)
+#pragma unroll
+                for (int w = 0; w < 4; ++w) s4[w] += part[((int64_t)(p + w) * S * nr + q) * n + i];
+            for (; p < b; ++p) s4[0] += part[((int64_t)p * S * nr + q) * n + i];
+            const int64_t z1 = (int64_t)(b + (nb - b + m - 1) / m) * S;
+            int64_t z = (int64_t)b * S;
+            for (; z + 4 <= z1; z += 4)
+#pragma unroll
+                for (int w = 0; w < 4; ++w) s4[w] += part[((z + w) * nr + q) * n + i];
+            for (; z < z1; ++z) s4[0] += part[(z * nr + q) * n + i];
+            const double s = ((s4[0] + s4[1]) + (s4[2] + s4[3])) + part[((int64_t)nb * S * nr + q) * n + i];
+            const double ui = u[(int64_t)q * n + i];
+            const double yi = fma(scale, s, mu * ui);
+            y[(int64_t)q * n + i] = yi;
+            dot = ui * yi;
+        }
+        dot = block_sum(dot, sc);
+        if (threadIdx.x == 0) dot_part[(int64_t)q * gridDim.x + blockIdx.x] = dot;
+    }
+}
+
+template <int KIND, int NR>
+static void kmma_dispatch(const KernelOp& op, float c, const double* u, double* ws,
+                          const KmmaPlan& p, const int32_t* stop, hipStream_t st) {
+    const unsigned grid = (unsigned)p.items;
+#define KML(DD)                                                                                 \
+    k_ksym_mma<KIND, DD, NR><<<grid, KM_THREADS, 0, st>>>(op.n, op.xa, op.sqn, c, u, ws, p.nb, \
+                                                          p.m, p.S, stop)
+    switch (op.dm) {
+        case 4: KML(4); break;
+        case 8: KML(8); break;
+        case 16: KML(16); break;
+        default: KML(32); break;
+    }
+#undef KML
+}
+
+bool kernel_mma_ok(int64_t n, int d) {
+    const KmmaPlan p = kmma_plan(n);
+    return d <= 32 && (int64_t)p.nb * p.S + 1 <= KM_MAX_SLOTS;
+}
+
+size_t kernel_mma_ws_doubles(int64_t n, int nr) {
+    const KmmaPlan p = kmma_plan(n);
+    return ((size_t)p.nb * p.S + 1) * nr * (size_t)n;
+}
+
+// nr in {1, 2}; u, y column-major with leading dimension n; ws holds
+// kernel_mma_ws_doubles(n, nr) doubles.
+void launch_kernel_matvec_mma(const KernelOp& op, const double* u, int nr, double mu, double* y,
+                              double* dot_part, double* ws, const int32_t* stop, hipStream_t st) {
+    const KmmaPlan p = kmma_plan(op.n);
+    const float c = kernel_c32(op.kind, op.kconst);
+    {
+        ProfScope prof(nr == 1 ? PROF_KERNEL_MATVEC : -1, st);
+        if (op.kind == 1) {
+            if (nr == 1) kmma_dispatch<1, 1>(op, c, u, ws, p, stop, st);
+            else kmma_dispatch<1, 2>(op, c, u, ws, p, stop, st);
+        } else {
+            if (nr == 1) kmma_dispatch<2, 1>(op, c, u, ws, p, stop, st);
+            else kmma_dispatch<2, 2>(op, c, u, ws, p, stop, st);
+        }
+    }
+    k_ksym_mma_finish<<<(unsigned)((op.n + 255) / 256), 256, 0, st>>>(op.n, KM_RB, p.nb, p.m, p.S, nr, ws,
+                                                                      op.scale, mu, u, y, dot_part,
+                                                                      stop);
+}
+
+}  // namespace rr
