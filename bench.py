@@ -189,21 +189,26 @@ def main():
               "relres_fp64": float(torch.linalg.norm(r0) / torch.linalg.norm(b))}
 
     # roofline of the dominant kernel (by device time inside the timed steps).  The
-    # symmetric kernel matvec must form n(n+1)/2 distinct entries; each costs at least
-    # d + 7 vector-ALU issue slots (d + 1 FMAs for s, min, mul, exp2, the float64
-    # widening and two float64 FMAs for the row and column sums), so the ALU roofline
-    # is lane-ops/s / (d + 7) pairs per second.
+    # symmetric kernel matvec evaluates the n(n+1)/2 distinct entries once each.  The
+    # pair terms (the exponents) come from bf16 MFMA (7 v_mfma_f32_32x32x16_bf16 per
+    # 32 x 32 tile at d = 16, 224 flops per pair), which runs beside the vector ALU;
+    # the vector ALU then needs at least 5 issue slots per pair: exp2 (half rate, 2
+    # slots), the float64 widening and two float64 FMAs (row and column sums).  The
+    # roofline is the vector-ALU lane-op rate / 5 pairs per second (the MFMA side
+    # would allow about 11 Tpair/s, so the vector ALU binds).
     pairs = n * (n + 1) / 2.0
     kmv_avg = kmv_ms / max(kmv_n, 1)
     sk_avg = sk_ms / max(sk_n, 1)
-    h = _src_hash("kernels_ksym.hip", "kentry.hpp", "common.hpp")
+    h = _src_hash("kernels_ksym_mma.hip", "kentry.hpp", "common.hpp")
     if kmv_ms >= sk_ms:
-        peak = PEAK_LANE_OPS / (d + 7) / 1e9
+        peak = PEAK_LANE_OPS / 5 / 1e9
         ach = pairs / (kmv_avg * 1e-3) / 1e9
-        roof = {"kernel": "k_ksym_f32 (symmetric kernel matvec)", "bound": "alu",
-                "achieved": ach, "peak": peak, "unit": "Gpair/s", "frac": ach / peak,
-                "traffic": _traffic("k_ksym_f32", h), "avg_ms": kmv_avg, "launches": kmv_n,
-                "per_unit": f"{d + 7} VALU slots per distinct pair, n(n+1)/2 pairs per launch"}
+        roof = {"kernel": "k_ksym_mma (symmetric kernel matvec, bf16-MFMA pair terms)",
+                "bound": "alu", "achieved": ach, "peak": peak, "unit": "Gpair/s",
+                "frac": ach / peak, "traffic": _traffic("k_ksym_mma", h), "avg_ms": kmv_avg,
+                "launches": kmv_n,
+                "per_unit": "5 VALU slots per distinct pair (exp2 at half rate, float64 widening, "
+                            "two float64 FMAs), n(n+1)/2 pairs per launch"}
     else:
         flops = 2.0 * n * n * l
         ach = flops / (sk_avg * 1e-3) / 1e12
@@ -229,7 +234,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 kernel entries, f64 accumulation/dots/projections; bf16 (hi+lo) MFMA sketch",
+        "dtype": "f32-class kernel entries (bf16x3 MFMA pair terms), f64 accumulation/dots/"
+                 "projections; bf16 (hi+lo) MFMA sketch",
         "data": "synthetic",
         "config": {"workload": "kernel-ridge RBF, n=50000, d=16, 10-component mixture, "
                                "median bandwidth, A=K/n, mu=1e-4, SRHT l=500, tol 1e-6",

@@ -140,8 +140,10 @@ void launch_kernel_matvec_multi(const KernelOp& op, bool fp64, const double* u, 
 // float32-class entries, float64 sums), nr in {1, 2} (kernels_ksym_mma.hip).
 bool kernel_mma_ok(int64_t n, int d);
 size_t kernel_mma_ws_doubles(int64_t n, int nr);
+// a32: float32 products and partial sums (estimate grade, power iterations).
 void launch_kernel_matvec_mma(const KernelOp& op, const double* u, int nr, double mu, double* y,
-                              double* dot_part, double* ws, const int32_t* stop, hipStream_t st);
+                              double* dot_part, double* ws, const int32_t* stop, hipStream_t st,
+                              bool a32 = false);
 // Symmetric float32 matvec, nr in {1, 2, 4, 8} (kernels_ksym.hip).
 size_t kernel_sym_ws_doubles(int64_t n, int d, int nr);
 // a32: float32 products and sums (estimate grade, nr <= 2), for power iterations.

@@ -208,7 +208,7 @@ void launch_kernel_matvec_multi(const KernelOp& op, bool fp64, const double* u, 
             // and inside a block gives bitwise the same products (this path also
             // serves the power iterations)
             const int c = left >= 2 ? 2 : 1;
-            launch_kernel_matvec_mma(op, uq, c, mu, yq, dq, ws, stop, st);
+            launch_kernel_matvec_mma(op, uq, c, mu, yq, dq, ws, stop, st, estimate);
             q0 += c;
         } else {
             const int c = left >= 8 ? 8 : left >= 4 ? 4 : left >= 2 ? 2 : 1;

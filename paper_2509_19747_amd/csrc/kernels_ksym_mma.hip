@@ -163,13 +163,14 @@ RR_DEV float kmma_entry(float t, float c) {
 
 // Sum over the 32 lanes of a half-wave of v[0..15] (reduce-scatter butterfly in a
 // fixed order): on return lanes 2e and 2e + 1 of the half hold the total of v[e].
-RR_DEV double kmma_rowsum16(double (&v)[16], int l32) {
-    double w8[8], w4[4], w2[2];
+template <typename T>
+RR_DEV T kmma_rowsum16(T (&v)[16], int l32) {
+    T w8[8], w4[4], w2[2];
     {
         const bool b = (l32 >> 4) & 1;
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
-            const double keep = b ? v[8 + e] : v[e], send = b ? v[e] : v[8 + e];
+            const T keep = b ? v[8 + e] : v[e], send = b ? v[e] : v[8 + e];
             w8[e] = keep + __shfl_xor(send, 16, 64);
         }
     }
@@ -177,7 +178,7 @@ RR_DEV double kmma_rowsum16(double (&v)[16], int l32) {
         const bool b = (l32 >> 3) & 1;
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-            const double keep = b ? w8[4 + e] : w8[e], send = b ? w8[e] : w8[4 + e];
+            const T keep = b ? w8[4 + e] : w8[e], send = b ? w8[e] : w8[4 + e];
             w4[e] = keep + __shfl_xor(send, 8, 64);
         }
     }
@@ -185,28 +186,30 @@ RR_DEV double kmma_rowsum16(double (&v)[16], int l32) {
         const bool b = (l32 >> 2) & 1;
 #pragma unroll
         for (int e = 0; e < 2; ++e) {
-            const double keep = b ? w4[2 + e] : w4[e], send = b ? w4[e] : w4[2 + e];
+            const T keep = b ? w4[2 + e] : w4[e], send = b ? w4[e] : w4[2 + e];
             w2[e] = keep + __shfl_xor(send, 4, 64);
         }
     }
     const bool b = (l32 >> 1) & 1;
-    const double keep = b ? w2[1] : w2[0], send = b ? w2[0] : w2[1];
-    const double w1 = keep + __shfl_xor(send, 2, 64);
+    const T keep = b ? w2[1] : w2[0], send = b ? w2[0] : w2[1];
+    const T w1 = keep + __shfl_xor(send, 2, 64);
     // lanes 2e and 2e + 1 add the same two partials in opposite order: equal sums
     return w1 + __shfl_xor(w1, 1, 64);
 }
 
-template <int KIND, int DM, int NR>
-__global__ __launch_bounds__(KM_THREADS) __attribute__((amdgpu_waves_per_eu(NR == 1 ? 4 : 2))) void k_ksym_mma(
+// T: the type of the products and partial sums (double; float for the estimate
+// grade of the power iterations, whose per-item partials are still stored as double).
+template <int KIND, int DM, int NR, typename T>
+__global__ __launch_bounds__(KM_THREADS) __attribute__((amdgpu_waves_per_eu(NR * sizeof(T) <= 8 ? 4 : 2))) void k_ksym_mma(
     int64_t n, const float* __restrict__ xa, const float* __restrict__ sqn, float c,
     const double* __restrict__ u, double* __restrict__ part, int nb, int m, int S,
     const int32_t* __restrict__ stop) {
     using Sh = KmmaShape<DM>;
     constexpr int KB = Sh::KB, BSTR = Sh::BSTR;
     __shared__ __attribute__((aligned(16))) __bf16 bs[KM_RB * BSTR];   // column records (B layout)
-    __shared__ double us[NR][KM_RB];                                    // column u_j
-    __shared__ __attribute__((aligned(16))) double ur[NR][KM_RB];       // row u_i
-    __shared__ double colw[KM_WAVES][NR][KM_RB];                        // column partials per wave
+    __shared__ T us[NR][KM_RB];                                         // column u_j
+    __shared__ __attribute__((aligned(16))) T ur[NR][KM_RB];            // row u_i
+    __shared__ T colw[KM_WAVES][NR][KM_RB];                             // column partials per wave
     if (stop && *stop) return;
 
     // item -> (bi, r, s)
@@ -230,15 +233,15 @@ __global__ __launch_bounds__(KM_THREADS) __attribute__((amdgpu_waves_per_eu(NR =
         const int64_t ic = i < n ? i : n - 1;
         kmma_record<DM, true>(xa + ic * DM, sqn[ic], g, h, [&](int s, const bf16x8_t& v) { areg[s] = v; });
     }
-    double acc[16][NR];
+    T acc[16][NR];
 #pragma unroll
     for (int e = 0; e < 16; ++e)
 #pragma unroll
-        for (int q = 0; q < NR; ++q) acc[e][q] = 0.0;
+        for (int q = 0; q < NR; ++q) acc[e][q] = T(0);
     for (int e = tid; e < NR * KM_RB; e += KM_THREADS) {
         const int q = e / KM_RB, rl = e % KM_RB;
         const int64_t i = (int64_t)bi * KM_RB + rl;
-        ur[q][rl] = i < n ? u[(int64_t)q * n + i] : 0.0;
+        ur[q][rl] = i < n ? T(u[(int64_t)q * n + i]) : T(0);
     }
 
     auto dots = [&](int ct) {
@@ -265,32 +268,30 @@ __global__ __launch_bounds__(KM_THREADS) __attribute__((amdgpu_waves_per_eu(NR =
         constexpr bool DG = decltype(dg)::value;
         const int jl = 32 * ct + l32;   // the lane's column within the block
         const int uro = 32 * wave + 4 * h;
-        double uj[NR], cs[2][NR];
+        T uj[NR], cs[2][NR];
 #pragma unroll
         for (int q = 0; q < NR; ++q) {
             uj[q] = us[q][jl];
-            cs[0][q] = 0.0;
-            cs[1][q] = 0.0;
+            cs[0][q] = T(0);
+            cs[1][q] = T(0);
         }
 #pragma unroll
         for (int g4 = 0; g4 < 4; ++g4) {
             // rows 8 g4 + 4 h + (0..3) of the wave: consecutive
-            double ui[4][NR];
+            T ui[4][NR];
 #pragma unroll
-            for (int q = 0; q < NR; ++q) {
-                const double2* up = reinterpret_cast<const double2*>(&ur[q][uro + 8 * g4]);
-                const double2 a = up[0], b = up[1];
-                ui[0][q] = a.x; ui[1][q] = a.y; ui[2][q] = b.x; ui[3][q] = b.y;
-            }
+            for (int q = 0; q < NR; ++q)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) ui[r][q] = ur[q][uro + 8 * g4 + r];
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int e = 4 * g4 + r;
-                const double kv = (double)kmma_entry<KIND>(dot[e], c);
-                double kr = kv, kc = kv;
+                const T kv = T(kmma_entry<KIND>(dot[e], c));
+                T kr = kv, kc = kv;
                 if constexpr (DG) {
                     const int rr = 8 * g4 + 4 * h + r;   // the entry's row within the tile
-                    kr = rr <= l32 ? kv : 0.0;
-                    kc = rr < l32 ? kv : 0.0;
+                    kr = rr <= l32 ? kv : T(0);
+                    kc = rr < l32 ? kv : T(0);
                 }
 #pragma unroll
                 for (int q = 0; q < NR; ++q) {
@@ -303,7 +304,7 @@ __global__ __launch_bounds__(KM_THREADS) __attribute__((amdgpu_waves_per_eu(NR =
         // the same sum (addition is commutative)
 #pragma unroll
         for (int q = 0; q < NR; ++q) {
-            const double v = cs[0][q] + cs[1][q];
+            const T v = cs[0][q] + cs[1][q];
             colw[wave][q][jl] = v + __shfl_xor(v, 32, 64);
         }
     };
@@ -326,7 +327,7 @@ __global__ __launch_bounds__(KM_THREADS) __attribute__((amdgpu_waves_per_eu(NR =
             });
             if (hh == 0) {
 #pragma unroll
-                for (int q = 0; q < NR; ++q) us[q][jl] = j < n ? u[(int64_t)q * n + j] : 0.0;
+                for (int q = 0; q < NR; ++q) us[q][jl] = j < n ? T(u[(int64_t)q * n + j]) : T(0);
             }
         }
         __syncthreads();
@@ -340,7 +341,7 @@ __global__ __launch_bounds__(KM_THREADS) __attribute__((amdgpu_waves_per_eu(NR =
                     entries(ct, dots(ct), std::true_type{});
                 } else {
 #pragma unroll
-                    for (int q = 0; q < NR; ++q) colw[wave][q][32 * ct + l32] = 0.0;
+                    for (int q = 0; q < NR; ++q) colw[wave][q][32 * ct + l32] = T(0);
                 }
                 continue;
             }
@@ -352,10 +353,10 @@ __global__ __launch_bounds__(KM_THREADS) __attribute__((amdgpu_waves_per_eu(NR =
             const int q = e / (32 * cpr), jl = 32 * ct0 + e % (32 * cpr);
             const int64_t j = cbase + jl;
             if (j < n) {
-                double v = 0.0;
+                T v = T(0);
 #pragma unroll
                 for (int w = 0; w < KM_WAVES; ++w) v += colw[w][q][jl];
-                part[(slot * NR + q) * n + j] = v;
+                part[(slot * NR + q) * n + j] = (double)v;
             }
         }
     }
@@ -363,13 +364,13 @@ __global__ __launch_bounds__(KM_THREADS) __attribute__((amdgpu_waves_per_eu(NR =
     const int64_t rslot = (int64_t)(bi + run) * S + sr;
 #pragma unroll
     for (int q = 0; q < NR; ++q) {
-        double v[16];
+        T v[16];
 #pragma unroll
         for (int e = 0; e < 16; ++e) v[e] = acc[e][q];
-        const double tot = kmma_rowsum16(v, l32);
+        const T tot = kmma_rowsum16(v, l32);
         const int e = l32 >> 1;
         const int64_t i = r0 + 8 * (e >> 2) + 4 * h + (e & 3);
-        if ((l32 & 1) == 0 && i < n) part[(rslot * NR + q) * n + i] = tot;
+        if ((l32 & 1) == 0 && i < n) part[(rslot * NR + q) * n + i] = (double)tot;
     }
 }
 
@@ -412,13 +413,13 @@ __global__ __launch_bounds__(256) void k_ksym_mma_finish(int64_t n, int rb, int 
     }
 }
 
-template <int KIND, int NR>
+template <int KIND, int NR, typename T>
 static void kmma_dispatch(const KernelOp& op, float c, const double* u, double* ws,
                           const KmmaPlan& p, const int32_t* stop, hipStream_t st) {
     const unsigned grid = (unsigned)p.items;
-#define KML(DD)                                                                                 \
-    k_ksym_mma<KIND, DD, NR><<<grid, KM_THREADS, 0, st>>>(op.n, op.xa, op.sqn, c, u, ws, p.nb, \
-                                                          p.m, p.S, stop)
+#define KML(DD)                                                                                    \
+    k_ksym_mma<KIND, DD, NR, T><<<grid, KM_THREADS, 0, st>>>(op.n, op.xa, op.sqn, c, u, ws, p.nb, \
+                                                             p.m, p.S, stop)
     switch (op.dm) {
         case 4: KML(4); break;
         case 8: KML(8); break;
@@ -439,20 +440,25 @@ size_t kernel_mma_ws_doubles(int64_t n, int nr) {
 }
 
 // nr in {1, 2}; u, y column-major with leading dimension n; ws holds
-// kernel_mma_ws_doubles(n, nr) doubles.
+// kernel_mma_ws_doubles(n, nr) doubles.  a32: float32 products and partial sums
+// (estimate grade).
 void launch_kernel_matvec_mma(const KernelOp& op, const double* u, int nr, double mu, double* y,
-                              double* dot_part, double* ws, const int32_t* stop, hipStream_t st) {
+                              double* dot_part, double* ws, const int32_t* stop, hipStream_t st,
+                              bool a32) {
     const KmmaPlan p = kmma_plan(op.n);
     const float c = kernel_c32(op.kind, op.kconst);
     {
-        ProfScope prof(nr == 1 ? PROF_KERNEL_MATVEC : -1, st);
-        if (op.kind == 1) {
-            if (nr == 1) kmma_dispatch<1, 1>(op, c, u, ws, p, stop, st);
-            else kmma_dispatch<1, 2>(op, c, u, ws, p, stop, st);
-        } else {
-            if (nr == 1) kmma_dispatch<2, 1>(op, c, u, ws, p, stop, st);
-            else kmma_dispatch<2, 2>(op, c, u, ws, p, stop, st);
-        }
+        ProfScope prof(nr == 1 && !a32 ? PROF_KERNEL_MATVEC : -1, st);
+#define KMD(K)                                                                   \
+    if (a32) {                                                                   \
+        if (nr == 1) kmma_dispatch<K, 1, float>(op, c, u, ws, p, stop, st);      \
+        else kmma_dispatch<K, 2, float>(op, c, u, ws, p, stop, st);              \
+    } else {                                                                     \
+        if (nr == 1) kmma_dispatch<K, 1, double>(op, c, u, ws, p, stop, st);     \
+        else kmma_dispatch<K, 2, double>(op, c, u, ws, p, stop, st);             \
+    }
+        if (op.kind == 1) { KMD(1) } else { KMD(2) }
+#undef KMD
     }
     k_ksym_mma_finish<<<(unsigned)((op.n + 255) / 256), 256, 0, st>>>(op.n, KM_RB, p.nb, p.m, p.S, nr, ws,
                                                                       op.scale, mu, u, y, dot_part,
