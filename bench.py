@@ -106,6 +106,9 @@ def main():
     ap.add_argument("--l", type=int, default=500)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-cg", action="store_true")
+    ap.add_argument("--context-mu", type=float, nargs="*", default=[1e-6],
+                    help="kernel-ridge: also time one RandRAND and one plain-CG solve at these "
+                         "smaller shifts (reported under 'context', outside the timed steps)")
     ap.add_argument("--graph", action="store_true", help="replay PCG batches as hipGraphs")
     ap.add_argument("--workload", default="kernel-ridge",
                     choices=["kernel-ridge", "precision", "batched", "serving"],
@@ -219,6 +222,35 @@ def main():
     sketch_tflops = (2.0 * n * n * l) / (sk_avg * 1e-3) / 1e12 if sk_n else None
     kmv_gpairs = pairs / (kmv_avg * 1e-3) / 1e9 if kmv_n else None
 
+    # the same matrix at smaller shifts (the paper's kernel-ridge runs go down to
+    # mu = 1e-6 and 1e-7), where plain CG needs many more iterations
+    context = []
+    for mu2 in (args.context_mu or []):
+        ok = (rr.RR_OK, rr.RR_ENOCONV)
+
+        def rr_solve(m=mu2):
+            P2 = rr.build_precond(kop, [m], **build_kw)
+            return P2.solve(b, ok=ok, maxit=20000, **solve_kw)
+        rr_solve()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, i2 = rr_solve()
+        torch.cuda.synchronize()
+        t_rr = 1e3 * (time.perf_counter() - t0)
+        entry = {"mu": mu2, "randrand_ms": t_rr, "randrand_iters": i2["iters"],
+                 "randrand_status": i2["rc"]}
+        if not args.no_cg:
+            t0 = time.perf_counter()
+            P0 = rr.build_precond(kop, [mu2], l=0, prec="fp32")
+            _, c2 = P0.solve(b, tol=prob.tol, certify=False, use_graph=args.graph, check_every=8,
+                             maxit=20000, ok=ok)
+            torch.cuda.synchronize()
+            t_cg2 = 1e3 * (time.perf_counter() - t0)
+            entry.update({"plain_cg_ms": t_cg2, "plain_cg_iters": c2["iters"],
+                          "plain_cg_status": c2["rc"], "speedup_vs_plain_cg": t_cg2 / t_rr})
+        context.append(entry)
+        _log(f"context mu={mu2:g}: {entry}")
+
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(prob, last["iters"], last["restarts"], 10)
@@ -251,6 +283,7 @@ def main():
         "speedup_vs_plain_cg": (cg["ms"] / ms_step) if cg else None,
         "kernel_matvec_gpairs_per_s": kmv_gpairs, "kernel_matvec_avg_ms": kmv_avg,
         "sketch_tflops": sketch_tflops, "sketch_avg_ms": sk_avg,
+        "context": context,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

@@ -3,36 +3,38 @@
 // float32 mode).  Omega's entries are exact in bf16 (SRHT +-1, or a Gaussian
 // drawn in bf16); each float32 kernel entry is split into hi = bf16(k) and
 // lo = bf16(k - hi) (about 16 significant bits together) and both parts go
-// through v_mfma_f32_32x32x16_bf16 with float32 accumulation (the 32x32x16
-// form sustains close to the bf16 peak; 16x16x32 about half of it).
+// through v_mfma_f32_32x32x16_bf16 with float32 accumulation.
 //
 // Block: 512 threads = 8 waves, tile 128 rows x 512 columns (l <= 512 in one
 // column tile, so every kernel entry is formed once per row tile); wave w owns
 // rows 64*(w&1)..+63 and columns 128*((w>>1)&3)..+127 (2 x 4 MFMA tiles of
-// 32 x 32).  Per step of 32 points the block forms the 128 x 32 kernel tile
-// (thread: one row, 8 consecutive points whose records arrive through scalar
-// loads) and stages the 32 x 512 slice of Omega in LDS (thread t: column t,
-// loaded into registers one step ahead).  The tiles are double-buffered: while
-// a step's MFMAs run, the next step's tile is formed.  Waves 0-3 issue the
-// MFMAs first and waves 4-7 the tile formation first, so the two waves that
-// share a SIMD keep its matrix core and its vector ALU busy at the same time.
+// 32 x 32).  Per step of 32 points the block forms the 128 x 32 kernel tile and
+// stages the 32 x 512 slice of Omega in LDS (thread t: column t, loaded into
+// registers one step ahead).  The kernel tile is formed on the matrix cores too:
+// waves 0-3 each form one 32 x 32 quarter as the product of augmented point
+// records (kmma.hpp: float32-class exponents from three-piece bf16 splits), then
+// exp2 and the hi/lo split on the vector ALU.  The records of the block's rows
+// are built once into LDS; those of the step's points are built by the forming
+// lanes from coordinates loaded one step ahead.  The tiles are double-buffered:
+// a step's product MFMAs read one buffer while waves 0-3 form the next step into
+// the other, so each SIMD pairs a forming wave with a wave that only multiplies.
 // The point range may be split over several blocks (split-K) to fill the GPU
-// evenly; partial sums then go to a workspace and a second kernel adds them in
-// a fixed order.  The MFMA operands use one consistent k order for A and B
-// (lane l holds k = 8*(l/32) .. +7 of a 16-point half step), which is all the
-// product needs.  Accumulator element j of lane l is row 8*(j/4) + 4*(l/32) +
-// (j%4), column l%32 of its 32 x 32 tile.
+// evenly; partial sums then go to a workspace and a second kernel adds them in a
+// fixed order.  The MFMA operands use one consistent k order for A and B (lane l
+// holds k = 8*(l/32) .. +7 of a 16-point half step), which is all the product
+// needs.  Accumulator element j of lane l is row 8*(j/4) + 4*(l/32) + (j%4),
+// column l%32 of its 32 x 32 tile.
 #include "common.hpp"
 #include "kentry.hpp"
 #include "kernels.hpp"
+#include "kmma.hpp"
 #include "prof.hpp"
 
 #include <algorithm>
 
 namespace rr {
 
-typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
-typedef float f32x16_t __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x4_t __attribute__((ext_vector_type(4)));
 constexpr int KS2_BM = 128, KS2_BN = 512, KS2_BK = 32, KS2_THREADS = 512;
 constexpr int KS2_AS = 40;   // padded LDS row length (bf16) of the kernel tile
 constexpr int KS2_BS = 40;   // padded LDS column length (bf16) of the Omega slice
@@ -42,58 +44,6 @@ struct Ks2Smem {
     uint16_t a_lo[2][KS2_BM * KS2_AS];
     uint16_t b[2][KS2_BN * KS2_BS];
 };
-
-RR_DEV uint32_t bf16_bits(float f) { return (uint32_t)__builtin_bit_cast(uint16_t, (__bf16)f); }
-
-// Kernel tile of step k0 into buffer `buf`: row trow, points k0 + 8*g + e for
-// e = 0..7 (one 16-byte store per part).  FULL: all 32 points of the step are
-// < n (no clamping or masking).
-template <int KIND, int DM, bool FULL>
-RR_DEV void ks2_form_t(Ks2Smem& sm, int buf, int64_t n, const float* __restrict__ xa,
-                       const float* __restrict__ sqn, float c, int64_t k0, int trow, int g,
-                       const float (&xi)[DM], float mhn) {
-    const int64_t jb = k0 + 8 * g;
-    const float* xj0 = xa + jb * DM;
-    const float* nj0 = sqn + jb;
-    uint32_t hi2[4], lo2[4];
-#pragma unroll
-    for (int e2 = 0; e2 < 4; ++e2) {
-        uint32_t hb[2], lb[2];
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int e = 2 * e2 + h;
-            const float* xj;
-            float nj;
-            if (FULL) {
-                xj = xj0 + e * DM;
-                nj = nj0[e];
-            } else {
-                const int64_t gjc = jb + e < n ? jb + e : n - 1;
-                xj = xa + gjc * DM;
-                nj = sqn[gjc];
-            }
-            float sv = kpair_init(mhn, nj);
-#pragma unroll
-            for (int k = 0; k < DM; ++k) sv = fmaf(xi[k], xj[k], sv);
-            float kv = kval32<KIND>(sv, c);
-            if (!FULL) kv = jb + e < n ? kv : 0.0f;
-            const uint32_t hbits = bf16_bits(kv);
-            hb[h] = hbits;
-            lb[h] = bf16_bits(kv - __uint_as_float(hbits << 16));
-        }
-        hi2[e2] = hb[0] | (hb[1] << 16);
-        lo2[e2] = lb[0] | (lb[1] << 16);
-    }
-    *(uint4*)&sm.a_hi[buf][trow * KS2_AS + 8 * g] = make_uint4(hi2[0], hi2[1], hi2[2], hi2[3]);
-    *(uint4*)&sm.a_lo[buf][trow * KS2_AS + 8 * g] = make_uint4(lo2[0], lo2[1], lo2[2], lo2[3]);
-}
-template <int KIND, int DM>
-RR_DEV void ks2_form(Ks2Smem& sm, int buf, int64_t n, const float* __restrict__ xa,
-                     const float* __restrict__ sqn, float c, int64_t k0, int trow, int g,
-                     const float (&xi)[DM], float mhn) {
-    if (k0 + KS2_BK <= n) ks2_form_t<KIND, DM, true>(sm, buf, n, xa, sqn, c, k0, trow, g, xi, mhn);
-    else ks2_form_t<KIND, DM, false>(sm, buf, n, xa, sqn, c, k0, trow, g, xi, mhn);
-}
 
 // Omega slice of one step: thread t owns column c0 + t and its 32 points, as
 // four 16-byte chunks (global loads into registers one step ahead; the LDS
@@ -146,24 +96,68 @@ __global__ __launch_bounds__(KS2_THREADS) void k_ksketch_bf16x2(
     int64_t n, const float* __restrict__ xa, const float* __restrict__ sqn, float c, float scale,
     float mu, const uint16_t* __restrict__ Bm, int64_t ldb, int64_t m, float* __restrict__ Y,
     int64_t ldy, int64_t kper, float* __restrict__ part) {
+    constexpr int KB = KmmaShape<DM>::KB, NX = kmma_ncoord<DM>();
+    // column-form records of the block's rows: in LDS, or for long records (which
+    // would not fit beside the tiles) in the forming lanes' registers
+    constexpr bool RREG = DM > 16;
     __shared__ __attribute__((aligned(16))) Ks2Smem sm;
+    __shared__ bf16x8_t rowrec[RREG ? 1 : KS2_BM * KB * 2];
+    bf16x8_t rowreg[RREG ? KB : 1];
     const int t = threadIdx.x;
     const int lane = t & 63, wave = t >> 6;
+    const int h = lane >> 5, l32 = lane & 31;
     const int rh = wave & 1, cq = (wave >> 1) & 3;
-    const bool mfma_first = (wave >> 2) == 0;
+    const bool former = wave < 4;   // forms kernel-tile rows 32*wave .. +31
     const int64_t i0 = (int64_t)blockIdx.x * KS2_BM;
     const int64_t c0 = (int64_t)blockIdx.y * KS2_BN;
     const int64_t kb = (int64_t)blockIdx.z * kper;
     const int64_t ke = (kb + kper < n) ? kb + kper : n;
+    const float g = KIND == 1 ? c : 1.0f;
 
-    const int trow = t & (KS2_BM - 1);
-    const int pg = __builtin_amdgcn_readfirstlane(t >> 7);   // wave-uniform point group 0..3
-    const int64_t gi = i0 + trow;
-    const int64_t gic = gi < n ? gi : n - 1;
-    float xi[DM];
+    // forming lanes: the record of row 32*wave + l32 into LDS, and the coordinates
+    // of the step's point kb + l32 (rows and points past n: the last point; its
+    // products meet zero rows of Omega or are not stored)
+    const int frow = 32 * (wave & 3) + l32;
+    float xr[NX], sqr = 0.0f;
+    if (former) {
+        const int64_t gi = i0 + frow;
+        const int64_t gic = gi < n ? gi : n - 1;
+        kmma_record<DM, false>(xa + gic * DM, sqn[gic], g, h, [&](int s, const bf16x8_t& v) {
+            if constexpr (RREG) rowreg[s] = v;
+            else rowrec[(frow * KB + s) * 2 + h] = v;
+        });
+        const int64_t gj = kb + l32 < n ? kb + l32 : n - 1;
+        kmma_coords<DM>(xa + gj * DM, h, xr);
+        sqr = sqn[gj];
+    }
+    // kernel tile of step k (points k .. k+31) into buffer b: the wave's 32 rows
+    auto form = [&](int64_t k, int b) {
+        f32x16_t d;
 #pragma unroll
-    for (int k = 0; k < DM; ++k) xi[k] = xa[gic * DM + k];
-    const float mhn = -0.5f * sqn[gic];
+        for (int e = 0; e < 16; ++e) d[e] = 0.0f;
+        kmma_record_x<DM, true>(xr, sqr, g, h, [&](int s, const bf16x8_t& v) {
+            const bf16x8_t rr = RREG ? rowreg[s] : rowrec[(frow * KB + s) * 2 + h];
+            d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(v, rr, d, 0, 0, 0);
+        });
+        // coordinates of the point one step further on
+        const int64_t gj = k + KS2_BK + l32 < n ? k + KS2_BK + l32 : n - 1;
+        kmma_coords<DM>(xa + gj * DM, h, xr);
+        sqr = sqn[gj];
+        // lane: row frow, points 8 g4 + 4 h + (0..3) of the step
+#pragma unroll
+        for (int g4 = 0; g4 < 4; ++g4) {
+            bf16x4_t hv, lv;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const float kv = kmma_entry<KIND>(d[4 * g4 + r], c);
+                const __bf16 hb = (__bf16)kv;
+                hv[r] = hb;
+                lv[r] = (__bf16)(kv - (float)hb);
+            }
+            *reinterpret_cast<bf16x4_t*>(&sm.a_hi[b][frow * KS2_AS + 8 * g4 + 4 * h]) = hv;
+            *reinterpret_cast<bf16x4_t*>(&sm.a_lo[b][frow * KS2_AS + 8 * g4 + 4 * h]) = lv;
+        }
+    };
 
     f32x16_t acc[2][4];
 #pragma unroll
@@ -176,29 +170,23 @@ __global__ __launch_bounds__(KS2_THREADS) void k_ksketch_bf16x2(
     const uint16_t* bsrc = (c0 + t < m) ? Bm + (c0 + t) * ldb : nullptr;
     const int64_t npad = (n + 7) & ~(int64_t)7;   // B rows [n, npad) hold zeros
     uint4 rb[4];
+    __syncthreads();   // row records
     if (kb < ke) {
         ks2_load_b(bsrc, npad, kb, rb);
         ks2_store_b(sm, 0, t, rb);
-        ks2_form<KIND, DM>(sm, 0, n, xa, sqn, c, kb, trow, pg, xi, mhn);
+        if (former) form(kb, 0);
         if (kb + KS2_BK < ke) ks2_load_b(bsrc, npad, kb + KS2_BK, rb);
     }
     __syncthreads();
     int buf = 0;
     for (int64_t k0 = kb; k0 < ke; k0 += KS2_BK) {
         const int64_t k1 = k0 + KS2_BK, k2 = k0 + 2 * KS2_BK;
-        // one copy of the MFMA block (the accumulators stay in place); the next
-        // step's staging runs before it on waves 4-7 and after it on waves 0-3
-        if (!mfma_first && k1 < ke) {
+        if (k1 < ke) {
             ks2_store_b(sm, buf ^ 1, t, rb);
             if (k2 < ke) ks2_load_b(bsrc, npad, k2, rb);
-            ks2_form<KIND, DM>(sm, buf ^ 1, n, xa, sqn, c, k1, trow, pg, xi, mhn);
         }
         ks2_mfma(sm, buf, lane, rh, cq, acc);
-        if (mfma_first && k1 < ke) {
-            ks2_store_b(sm, buf ^ 1, t, rb);
-            if (k2 < ke) ks2_load_b(bsrc, npad, k2, rb);
-            ks2_form<KIND, DM>(sm, buf ^ 1, n, xa, sqn, c, k1, trow, pg, xi, mhn);
-        }
+        if (former && k1 < ke) form(k1, buf ^ 1);
         __syncthreads();
         buf ^= 1;
     }

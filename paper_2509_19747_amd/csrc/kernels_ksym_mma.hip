@@ -3,23 +3,8 @@
 // ridge regression, Section 7.2.2, and the two-column power iterations of the
 // shift estimates).
 //
-// The exponent of an entry is one inner product of augmented point records:
-//   row    a_i = [g x_i, -g |x_i|^2 / 2, 1]
-//   column b_j = [x_j,   1, -g |x_j|^2 / 2]
-//   a_i . b_j = g (x_i . x_j - |x_i|^2 / 2 - |x_j|^2 / 2) = -g |x_i - x_j|^2 / 2
-// with g = c = 2 kconst log2(e) for the RBF kernel, so K_ij = exp2(a_i . b_j),
-// and g = 1 for Matern-3/2, where the product is s_ij of kval32.
-//
-// Float32 accuracy on bf16 MFMA: every float32 term v splits exactly into three
-// bf16 pieces v = v0 + v1 + v2 (each piece rounds the remainder of the previous
-// ones to 8 significant bits; 24 bits in all).  A product x y is then the six
-// piece products with a + b <= 2 (x0 y0, x0 y1, x1 y0, x0 y2, x1 y1, x2 y0); the
-// three dropped ones are below 2^-24 |x y|.  Each piece product is exact in
-// float32 and v_mfma_f32_32x32x16_bf16 adds them in float32, so the exponent
-// carries float32-class rounding.  The record terms are laid out as six segments
-// of DM coordinates (the piece pairs above), then the two augmented terms as
-// [p0, p1, p2, 1, 1, 1] x [1, 1, 1, q0, q1, q2], then zeros: 6 DM + 6 terms in
-// KB steps of 16.
+// The exponent of each entry is the product of two augmented point records on
+// bf16 MFMA, with float32-class accuracy (kmma.hpp).
 //
 // Rows are grouped in blocks of 256 (8 waves x 32 rows).  Work item (I, r, s)
 // covers row block I against the column blocks J of run r (J = I + r m, ..., up to
@@ -39,12 +24,10 @@
 // written by exactly one item, and the finish adds them in that order (bitwise
 // reproducible).
 //
-// MFMA layout (v_mfma_f32_32x32x16_bf16): lane l supplies A[row l%32][k 8(l/32) ..
-// 8(l/32)+7] and B[k 8(l/32) .. +7][col l%32] of a 16-deep step; accumulator
-// element e of lane l is row 8(e/4) + 4(l/32) + (e%4), column l%32.
 #include "common.hpp"
 #include "kentry.hpp"
 #include "kernels.hpp"
+#include "kmma.hpp"
 #include "prof.hpp"
 
 #include <algorithm>
@@ -52,84 +35,11 @@
 
 namespace rr {
 
-typedef float f32x16_t __attribute__((ext_vector_type(16)));
-typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 constexpr int KM_WAVES = 8;
 constexpr int KM_THREADS = 64 * KM_WAVES;
 constexpr int KM_RB = 32 * KM_WAVES;   // rows (and columns) per block
 constexpr int KM_CT = KM_RB / 32;      // column tiles per block
 constexpr int KM_MAX_SLOTS = 2048;     // partial slots per row (bounds the workspace)
-
-template <int DM>
-struct KmmaShape {
-    static constexpr int KT = 6 * DM + 6;       // record terms
-    static constexpr int KB = (KT + 15) / 16;   // MFMA steps
-    static constexpr int BSTR = 16 * KB;        // LDS stride (bf16) of a column record
-};
-
-// Piece of x (row side) and of y (column side) in segment seg.
-constexpr int kmma_apiece(int seg) { return seg == 2 || seg == 4 ? 1 : seg == 5 ? 2 : 0; }
-constexpr int kmma_bpiece(int seg) { return seg == 1 || seg == 4 ? 1 : seg == 3 ? 2 : 0; }
-
-// Exact split v = p[0] + p[1] + p[2] into bf16 pieces (normal-range v).
-RR_DEV void kmma_split3(float v, __bf16 (&p)[3]) {
-    p[0] = (__bf16)v;
-    const float r1 = v - (float)p[0];
-    p[1] = (__bf16)r1;
-    p[2] = (__bf16)(r1 - (float)p[1]);
-}
-
-// The KB record chunks (8 terms each) that half h of a wave supplies for one
-// point: terms kk = 16 s + 8 h + t, t < 8, of step s.  ROW: the row record
-// (coordinates scaled by g, augmented terms [p0, p1, p2, 1, 1, 1]); otherwise the
-// column record (augmented terms [1, 1, 1, q0, q1, q2]).  rec: the point's DM
-// coordinates; sq: its squared norm; emit(s, chunk) receives the chunks in order.
-template <int DM, bool ROW, typename Emit>
-RR_DEV void kmma_record(const float* __restrict__ rec, float sq, float g, int h, Emit&& emit) {
-    constexpr int KB = KmmaShape<DM>::KB;
-    const __bf16 one = (__bf16)1.0f, zero = (__bf16)0.0f;
-    __bf16 pa[3];
-    kmma_split3(-0.5f * g * sq, pa);
-    auto aug = [&](int ka) {   // augmented term ka >= 0 (past the six segments)
-        if (ka >= 6) return zero;
-        if (ROW) return ka < 3 ? pa[ka] : one;
-        return ka < 3 ? one : pa[ka - 3];
-    };
-    auto piece = [&](int seg) { return ROW ? kmma_apiece(seg) : kmma_bpiece(seg); };
-    if constexpr (DM >= 16) {
-        // step s covers segment 16 s / DM, coordinates (16 s) % DM + 8 h + t
-        __bf16 pc[DM / 16][8][3];
-#pragma unroll
-        for (int m = 0; m < DM / 16; ++m)
-#pragma unroll
-            for (int t = 0; t < 8; ++t) {
-                const float v = rec[16 * m + 8 * h + t];
-                kmma_split3(ROW ? g * v : v, pc[m][t]);
-            }
-#pragma unroll
-        for (int s = 0; s < KB; ++s) {
-            bf16x8_t o;
-#pragma unroll
-            for (int t = 0; t < 8; ++t) {
-                if (16 * s < 6 * DM) o[t] = pc[(16 * s % DM) / 16][t][piece(16 * s / DM)];
-                else o[t] = h == 0 ? aug(16 * s + t - 6 * DM) : zero;
-            }
-            emit(s, o);
-        }
-    } else {
-        __bf16 pc[DM][3];
-#pragma unroll
-        for (int k = 0; k < DM; ++k) kmma_split3(ROW ? g * rec[k] : rec[k], pc[k]);
-        auto val = [&](int kk) { return kk < 6 * DM ? pc[kk % DM][piece(kk / DM)] : aug(kk - 6 * DM); };
-#pragma unroll
-        for (int s = 0; s < KB; ++s) {
-            bf16x8_t o;
-#pragma unroll
-            for (int t = 0; t < 8; ++t) o[t] = h ? val(16 * s + 8 + t) : val(16 * s + t);
-            emit(s, o);
-        }
-    }
-}
 
 // Work items (I, r, s): row block I, run r of up to m column blocks starting at
 // I + r m, column range s of S (S > 1 only with m = 1, for small n).
@@ -150,15 +60,6 @@ static KmmaPlan kmma_plan(int64_t n) {
     for (int I = 0; I < p.nb; ++I) runs += (p.nb - I + p.m - 1) / p.m;
     p.items = runs * S;
     return p;
-}
-
-// Entry from the record product t (see above).
-template <int KIND>
-RR_DEV float kmma_entry(float t, float c) {
-    // t is -g r^2 / 2 <= 0 up to rounding; near-coincident points may round to a
-    // tiny positive t and give an entry a few ulps above 1
-    if (KIND == 1) return __builtin_amdgcn_exp2f(t);
-    return kval32<2>(t, c);
 }
 
 // Sum over the 32 lanes of a half-wave of v[0..15] (reduce-scatter butterfly in a
@@ -267,7 +168,10 @@ __global__ __launch_bounds__(KM_THREADS) __attribute__((amdgpu_waves_per_eu(NR *
     auto entries = [&](int ct, const f32x16_t& dot, auto dg) {
         constexpr bool DG = decltype(dg)::value;
         const int jl = 32 * ct + l32;   // the lane's column within the block
-        const int uro = 32 * wave + 4 * h;
+        // u of the lane's rows, re-read from LDS for every tile (an opaque offset
+        // keeps the compiler from holding all sixteen in registers)
+        int uro = 32 * wave + 4 * h;
+        asm volatile("" : "+v"(uro));
         T uj[NR], cs[2][NR];
 #pragma unroll
         for (int q = 0; q < NR; ++q) {

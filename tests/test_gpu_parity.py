@@ -98,6 +98,34 @@ def test_kernel_matvec_block_multi_tile(kind, n, d, nr):
         assert np.array_equal(y0, Y32[:, 0])
 
 
+@pytest.mark.parametrize("kind", [rr.OP_RBF, rr.OP_MATERN32])
+def test_kernel_fp32_matvec_large_multi_block_items(kind):
+    # n large enough that a work item runs over several column blocks (and row
+    # blocks own several runs): sampled rows against the oracle's kernel rows, the
+    # two-column block against the single-column product, and exact symmetry of
+    # the float32 operator seen through float64 sums (u.Kv = v.Ku to rounding)
+    from oracle.operators import kernel_block
+    n, d = 40_000, 16
+    rng = np.random.default_rng(41 + kind)
+    pts = rng.standard_normal((d, n)).astype(np.float32)
+    kconst, scale, mu = 0.5 / d, 1.0 / n, 1e-3
+    kop = rr.kernel_operator(kind, _cuda(pts), kconst, scale)
+    U = rng.standard_normal((n, 2))
+    Y = rr.apply_operator_block(kop, mu, "fp32", _cuda(U)).cpu().numpy()
+    y0 = rr.apply_operator(kop, mu, "fp32", _cuda(U[:, 0].copy())).cpu().numpy()
+    assert np.array_equal(y0, Y[:, 0])
+    X = pts.T.astype(np.float64)
+    rows = np.unique(np.concatenate([rng.integers(0, n, 48), [0, 255, 256, n - 1, n - 2]]))
+    Kr = scale * kernel_block(kind, kconst, X[rows], X)
+    ref = Kr @ U + mu * U[rows]
+    bound = np.abs(Kr) @ np.abs(U) + mu * np.abs(U[rows])
+    assert np.all(np.abs(Y[rows] - ref) <= 2e-6 * bound), np.max(np.abs(Y[rows] - ref) / bound)
+    uKv = U[:, 0] @ (Y[:, 1] - mu * U[:, 1])
+    vKu = U[:, 1] @ (Y[:, 0] - mu * U[:, 0])
+    # an asymmetric float32 operator would leave a gap near 1e-7
+    assert abs(uKv - vKu) <= 1e-11 * (np.abs(U[:, 0]) @ np.abs(Y[:, 1] - mu * U[:, 1]))
+
+
 def test_kernel_fp32_operator_symmetric_multi_tile():
     # float32 entries of different row blocks are formed once: K e_j and K e_i agree
     n, d = 2600, 16
