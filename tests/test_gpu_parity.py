@@ -356,6 +356,25 @@ def test_kernel_sketch_matches_oracle(n, l, sketch, prec, d):
     assert np.all(err <= bound + 1e-300), f"worst at {worst}: err {err[worst]:.3e} bound {bound[worst]:.3e}"
 
 
+@pytest.mark.parametrize("n,l,sketch,d", [(2600, 130, "srht", 5), (1500, 513, "gaussian", 20),
+                                          (3001, 64, "gaussian", 16)])
+def test_kernel_sketch_matern_matches_oracle(n, l, sketch, d):
+    # Matern-3/2 tiles from the augmented records: s from the record product, then
+    # (1 + t) exp(-t) with t = kconst sqrt(-2 s); float32 mode, against the oracle
+    prob = workloads.cfg_kernel_ridge(n=n, d=d, l=l)
+    mu, kconst = prob.mus[0], 0.7
+    op = Operator(kind=rr.OP_MATERN32, pts=prob.pts, kconst=kconst, scale=prob.scale)
+    kop = rr.kernel_operator(rr.OP_MATERN32, _cuda(prob.pts), kconst, prob.scale)
+    Y = rr.sketch(kop, mu, l, sketch=sketch, seed=prob.omega_seed, prec="fp32").cpu().numpy()
+    Om = orng.omega(sketch, prob.omega_seed, n, l, bf16=True)
+    Yo = op.matmat(Om) + mu * Om
+    # the hi/lo split bounds each entry by 2^-15 relative; the Matern entry adds the
+    # float32 rounding of its square root and exponential (a few 2^-24)
+    bound = (np.abs(op.to_dense()) @ np.abs(Om)) * 2.0 ** -15
+    err = np.abs(Y - Yo)
+    assert np.all(err <= bound + 1e-300), np.max(err / (bound + 1e-300))
+
+
 @pytest.mark.parametrize("n,l,sketch", [(3001, 200, "gaussian"), (4000, 520, "srht"), (700, 37, "gaussian")])
 def test_kernel_fp32_bf16_sketch_basis(n, l, sketch):
     # float32-mode kernel build: Omega drawn in bf16, sketch on bf16 MFMA with a hi/lo
