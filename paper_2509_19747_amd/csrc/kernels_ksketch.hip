@@ -17,7 +17,8 @@
 // are built once into LDS; those of the step's points are built by the forming
 // lanes from coordinates loaded one step ahead.  The tiles are double-buffered:
 // a step's product MFMAs read one buffer while waves 0-3 form the next step into
-// the other, so each SIMD pairs a forming wave with a wave that only multiplies.
+// the other, so each SIMD pairs a forming wave (formation first, then its product
+// MFMAs) with a wave that only multiplies.
 // The point range may be split over several blocks (split-K) to fill the GPU
 // evenly; partial sums then go to a workspace and a second kernel adds them in a
 // fixed order.  The MFMA operands use one consistent k order for A and B (lane l
@@ -61,32 +62,35 @@ RR_DEV void ks2_store_b(Ks2Smem& sm, int buf, int t, const uint4 (&rb)[4]) {
     for (int s = 0; s < 4; ++s) *(uint4*)&sm.b[buf][t * KS2_BS + 8 * s] = rb[s];
 }
 
-// One step of MFMAs for the wave's 64 x 128 tile, in two half steps of 16 points.
+// One step of MFMAs for the wave's 64 x 128 tile, in two half steps of 16 points;
+// the second half step's operands are read from LDS while the first one's MFMAs run.
 RR_DEV void ks2_mfma(const Ks2Smem& sm, int buf, int lane, int rh, int cq, f32x16_t (&acc)[2][4]) {
     const int kq = 8 * (lane >> 5);
-#pragma unroll
-    for (int kh = 0; kh < 2; ++kh) {
-        __builtin_amdgcn_sched_barrier(0);
-        bf16x8_t ah[2], al[2], bv[4];
+    bf16x8_t ah[2][2], al[2][2], bv[2][4];
+    auto load = [&](int kh) {
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
             const int row = rh * 64 + u * 32 + (lane & 31);
-            ah[u] = __builtin_bit_cast(bf16x8_t, *(const uint4*)&sm.a_hi[buf][row * KS2_AS + 16 * kh + kq]);
-            al[u] = __builtin_bit_cast(bf16x8_t, *(const uint4*)&sm.a_lo[buf][row * KS2_AS + 16 * kh + kq]);
+            ah[kh][u] = __builtin_bit_cast(bf16x8_t, *(const uint4*)&sm.a_hi[buf][row * KS2_AS + 16 * kh + kq]);
+            al[kh][u] = __builtin_bit_cast(bf16x8_t, *(const uint4*)&sm.a_lo[buf][row * KS2_AS + 16 * kh + kq]);
         }
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int col = cq * 128 + v * 32 + (lane & 31);
-            bv[v] = __builtin_bit_cast(bf16x8_t, *(const uint4*)&sm.b[buf][col * KS2_BS + 16 * kh + kq]);
+            bv[kh][v] = __builtin_bit_cast(bf16x8_t, *(const uint4*)&sm.b[buf][col * KS2_BS + 16 * kh + kq]);
         }
+    };
+    load(0);
+    load(1);
+#pragma unroll
+    for (int kh = 0; kh < 2; ++kh)
 #pragma unroll
         for (int v = 0; v < 4; ++v)
 #pragma unroll
             for (int u = 0; u < 2; ++u) {
-                acc[u][v] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[u], bv[v], acc[u][v], 0, 0, 0);
-                acc[u][v] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[u], bv[v], acc[u][v], 0, 0, 0);
+                acc[u][v] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[kh][u], bv[kh][v], acc[u][v], 0, 0, 0);
+                acc[u][v] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[kh][u], bv[kh][v], acc[u][v], 0, 0, 0);
             }
-    }
 }
 
 // part == nullptr: Y = scale * acc + mu * B.  Otherwise part[z] (n x m, leading
@@ -185,8 +189,10 @@ __global__ __launch_bounds__(KS2_THREADS) void k_ksketch_bf16x2(
             ks2_store_b(sm, buf ^ 1, t, rb);
             if (k2 < ke) ks2_load_b(bsrc, npad, k2, rb);
         }
-        ks2_mfma(sm, buf, lane, rh, cq, acc);
+        // the forming wave of each SIMD builds the next tile while its partner's
+        // product MFMAs run, then issues its own
         if (former && k1 < ke) form(k1, buf ^ 1);
+        ks2_mfma(sm, buf, lane, rh, cq, acc);
         __syncthreads();
         buf ^= 1;
     }
