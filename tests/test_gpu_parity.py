@@ -59,7 +59,7 @@ def test_kernel_to_dense_fp64(dense_small):
 
 
 @pytest.mark.parametrize("kind", [rr.OP_RBF, rr.OP_MATERN32])
-@pytest.mark.parametrize("n,d", [(1500, 16), (333, 3), (1025, 4)])
+@pytest.mark.parametrize("n,d", [(1500, 16), (333, 3), (1025, 4), (1, 2), (7, 32), (33, 9), (257, 17)])
 def test_kernel_matvec(kind, n, d):
     rng = np.random.default_rng(n + d)
     pts = rng.standard_normal((d, n)).astype(np.float32)
