@@ -106,6 +106,9 @@ def main():
     ap.add_argument("--l", type=int, default=500)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-cg", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="kernel-ridge: first copy 1 GiB device to device (a plain copy of known "
+                         "size that scales rocprofv3 FETCH_SIZE / WRITE_SIZE counters)")
     ap.add_argument("--context-mu", type=float, nargs="*", default=[1e-6],
                     help="kernel-ridge: also time one RandRAND and one plain-CG solve at these "
                          "smaller shifts (reported under 'context', outside the timed steps)")
@@ -138,6 +141,12 @@ def main():
     import workloads
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.copy_calibration:
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")   # 1 GiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     prob = workloads.cfg_kernel_ridge(n=args.n, l=args.l)
     mu, n, l, d = prob.mus[0], prob.n, prob.l, prob.d
     pts = torch.from_numpy(prob.pts).cuda()
@@ -202,7 +211,7 @@ def main():
     pairs = n * (n + 1) / 2.0
     kmv_avg = kmv_ms / max(kmv_n, 1)
     sk_avg = sk_ms / max(sk_n, 1)
-    h = _src_hash("kernels_ksym_mma.hip", "kentry.hpp", "common.hpp")
+    h = _src_hash("kernels_ksym_mma.hip", "kmma.hpp", "kentry.hpp", "common.hpp")
     if kmv_ms >= sk_ms:
         peak = PEAK_LANE_OPS / 5 / 1e9
         ach = pairs / (kmv_avg * 1e-3) / 1e9
