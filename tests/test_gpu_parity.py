@@ -98,6 +98,25 @@ def test_kernel_matvec_block_multi_tile(kind, n, d, nr):
         assert np.array_equal(y0, Y32[:, 0])
 
 
+def test_kernel_fp32_matvec_beyond_mfma_slot_bound():
+    # n = 600,000 exceeds the MFMA matvec's partial-slot bound, so the float32-mode
+    # operator takes the vector-ALU symmetric kernel: sampled rows against the oracle
+    from oracle.operators import kernel_block
+    n, d = 600_000, 4
+    rng = np.random.default_rng(17)
+    pts = rng.standard_normal((d, n)).astype(np.float32)
+    kconst, scale, mu = 2.0, 1.0 / n, 1e-3
+    kop = rr.kernel_operator(rr.OP_RBF, _cuda(pts), kconst, scale)
+    u = rng.standard_normal(n)
+    y = rr.apply_operator(kop, mu, "fp32", _cuda(u)).cpu().numpy()
+    X = pts.T.astype(np.float64)
+    rows = np.unique(np.concatenate([rng.integers(0, n, 12), [0, n - 1]]))
+    Kr = scale * kernel_block(rr.OP_RBF, kconst, X[rows], X)
+    ref = Kr @ u + mu * u[rows]
+    bound = np.abs(Kr) @ np.abs(u) + mu * np.abs(u[rows])
+    assert np.all(np.abs(y[rows] - ref) <= 2e-6 * bound), np.max(np.abs(y[rows] - ref) / bound)
+
+
 @pytest.mark.parametrize("kind", [rr.OP_RBF, rr.OP_MATERN32])
 def test_kernel_fp32_matvec_large_multi_block_items(kind):
     # n large enough that a work item runs over several column blocks (and row
