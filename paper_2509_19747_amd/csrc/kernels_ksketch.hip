@@ -36,7 +36,11 @@
 namespace rr {
 
 typedef __bf16 bf16x4_t __attribute__((ext_vector_type(4)));
-constexpr int KS2_BM = 128, KS2_BN = 512, KS2_BK = 32, KS2_THREADS = 512;
+constexpr int KS2_BM = 128, KS2_BN = 512, KS2_BK = 32;
+constexpr int KS2_WC = 4;                              // 32-column MFMA tiles per wave
+constexpr int KS2_WAVES = 2 * (KS2_BN / 32) / KS2_WC;  // two 64-row halves
+constexpr int KS2_THREADS = 64 * KS2_WAVES;
+constexpr int KS2_CPT = 4 * KS2_BN / KS2_THREADS;      // 16-byte Omega chunks per thread
 constexpr int KS2_AS = 40;   // padded LDS row length (bf16) of the kernel tile
 constexpr int KS2_BS = 40;   // padded LDS column length (bf16) of the Omega slice
 
@@ -50,23 +54,24 @@ struct Ks2Smem {
 // four 16-byte chunks (global loads into registers one step ahead; the LDS
 // store of consecutive columns hits distinct banks).  B's rows [n, round8(n))
 // are zero, so a chunk is either inside the padded column or wholly past it.
-RR_DEV void ks2_load_b(const uint16_t* src, int64_t npad, int64_t k0, uint4 (&rb)[4]) {
+RR_DEV void ks2_load_b(const uint16_t* src, int64_t npad, int64_t k0, int cb, uint4 (&rb)[KS2_CPT]) {
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-        const int64_t gj = k0 + 8 * s;
+    for (int s = 0; s < KS2_CPT; ++s) {
+        const int64_t gj = k0 + 8 * (cb + s);
         rb[s] = (src && gj < npad) ? *(const uint4*)(src + gj) : make_uint4(0u, 0u, 0u, 0u);
     }
 }
-RR_DEV void ks2_store_b(Ks2Smem& sm, int buf, int t, const uint4 (&rb)[4]) {
+RR_DEV void ks2_store_b(Ks2Smem& sm, int buf, int col, int cb, const uint4 (&rb)[KS2_CPT]) {
 #pragma unroll
-    for (int s = 0; s < 4; ++s) *(uint4*)&sm.b[buf][t * KS2_BS + 8 * s] = rb[s];
+    for (int s = 0; s < KS2_CPT; ++s) *(uint4*)&sm.b[buf][col * KS2_BS + 8 * (cb + s)] = rb[s];
 }
 
-// One step of MFMAs for the wave's 64 x 128 tile, in two half steps of 16 points;
-// the second half step's operands are read from LDS while the first one's MFMAs run.
-RR_DEV void ks2_mfma(const Ks2Smem& sm, int buf, int lane, int rh, int cq, f32x16_t (&acc)[2][4]) {
+// One step of MFMAs for the wave's 64 x (32 KS2_WC) tile, in two half steps of 16
+// points; the second half step's operands are read from LDS while the first one's
+// MFMAs run.
+RR_DEV void ks2_mfma(const Ks2Smem& sm, int buf, int lane, int rh, int cq, f32x16_t (&acc)[2][KS2_WC]) {
     const int kq = 8 * (lane >> 5);
-    bf16x8_t ah[2][2], al[2][2], bv[2][4];
+    bf16x8_t ah[2][2], al[2][2], bv[2][KS2_WC];
     auto load = [&](int kh) {
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
@@ -75,8 +80,8 @@ RR_DEV void ks2_mfma(const Ks2Smem& sm, int buf, int lane, int rh, int cq, f32x1
             al[kh][u] = __builtin_bit_cast(bf16x8_t, *(const uint4*)&sm.a_lo[buf][row * KS2_AS + 16 * kh + kq]);
         }
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int col = cq * 128 + v * 32 + (lane & 31);
+        for (int v = 0; v < KS2_WC; ++v) {
+            const int col = cq * 32 * KS2_WC + v * 32 + (lane & 31);
             bv[kh][v] = __builtin_bit_cast(bf16x8_t, *(const uint4*)&sm.b[buf][col * KS2_BS + 16 * kh + kq]);
         }
     };
@@ -85,7 +90,7 @@ RR_DEV void ks2_mfma(const Ks2Smem& sm, int buf, int lane, int rh, int cq, f32x1
 #pragma unroll
     for (int kh = 0; kh < 2; ++kh)
 #pragma unroll
-        for (int v = 0; v < 4; ++v)
+        for (int v = 0; v < KS2_WC; ++v)
 #pragma unroll
             for (int u = 0; u < 2; ++u) {
                 acc[u][v] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[kh][u], bv[kh][v], acc[u][v], 0, 0, 0);
@@ -110,7 +115,7 @@ __global__ __launch_bounds__(KS2_THREADS) void k_ksketch_bf16x2(
     const int t = threadIdx.x;
     const int lane = t & 63, wave = t >> 6;
     const int h = lane >> 5, l32 = lane & 31;
-    const int rh = wave & 1, cq = (wave >> 1) & 3;
+    const int rh = wave & 1, cq = wave >> 1;
     const bool former = wave < 4;   // forms kernel-tile rows 32*wave .. +31
     const int64_t i0 = (int64_t)blockIdx.x * KS2_BM;
     const int64_t c0 = (int64_t)blockIdx.y * KS2_BN;
@@ -163,31 +168,33 @@ __global__ __launch_bounds__(KS2_THREADS) void k_ksketch_bf16x2(
         }
     };
 
-    f32x16_t acc[2][4];
+    f32x16_t acc[2][KS2_WC];
 #pragma unroll
     for (int u = 0; u < 2; ++u)
 #pragma unroll
-        for (int v = 0; v < 4; ++v)
+        for (int v = 0; v < KS2_WC; ++v)
 #pragma unroll
             for (int j = 0; j < 16; ++j) acc[u][v][j] = 0.0f;
 
-    const uint16_t* bsrc = (c0 + t < m) ? Bm + (c0 + t) * ldb : nullptr;
+    // Omega staging: thread t owns chunks cb .. cb + KS2_CPT - 1 of column bcol
+    const int bcol = t / (4 / KS2_CPT), bcb = (t % (4 / KS2_CPT)) * KS2_CPT;
+    const uint16_t* bsrc = (c0 + bcol < m) ? Bm + (c0 + bcol) * ldb : nullptr;
     const int64_t npad = (n + 7) & ~(int64_t)7;   // B rows [n, npad) hold zeros
-    uint4 rb[4];
+    uint4 rb[KS2_CPT];
     __syncthreads();   // row records
     if (kb < ke) {
-        ks2_load_b(bsrc, npad, kb, rb);
-        ks2_store_b(sm, 0, t, rb);
+        ks2_load_b(bsrc, npad, kb, bcb, rb);
+        ks2_store_b(sm, 0, bcol, bcb, rb);
         if (former) form(kb, 0);
-        if (kb + KS2_BK < ke) ks2_load_b(bsrc, npad, kb + KS2_BK, rb);
+        if (kb + KS2_BK < ke) ks2_load_b(bsrc, npad, kb + KS2_BK, bcb, rb);
     }
     __syncthreads();
     int buf = 0;
     for (int64_t k0 = kb; k0 < ke; k0 += KS2_BK) {
         const int64_t k1 = k0 + KS2_BK, k2 = k0 + 2 * KS2_BK;
         if (k1 < ke) {
-            ks2_store_b(sm, buf ^ 1, t, rb);
-            if (k2 < ke) ks2_load_b(bsrc, npad, k2, rb);
+            ks2_store_b(sm, buf ^ 1, bcol, bcb, rb);
+            if (k2 < ke) ks2_load_b(bsrc, npad, k2, bcb, rb);
         }
         // the forming wave of each SIMD builds the next tile while its partner's
         // product MFMAs run, then issues its own
@@ -200,8 +207,8 @@ __global__ __launch_bounds__(KS2_THREADS) void k_ksketch_bf16x2(
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int64_t gc = c0 + cq * 128 + v * 32 + (lane & 31);
+        for (int v = 0; v < KS2_WC; ++v) {
+            const int64_t gc = c0 + cq * 32 * KS2_WC + v * 32 + (lane & 31);
 #pragma unroll
             for (int j = 0; j < 16; ++j) {
                 const int64_t gr = i0 + rh * 64 + u * 32 + 8 * (j >> 2) + 4 * (lane >> 5) + (j & 3);
