@@ -100,7 +100,7 @@ def sketched_cholqr(Y: np.ndarray, Theta: np.ndarray):
     S = Theta Y; R_sk = qr(S); W = Y R_sk^{-1}; G = W^T W; R_chol = chol(G);
     Q = W R_chol^{-1}; R = R_chol R_sk.
     """
-    S = Theta @ Y
+    S = np.asarray(Theta @ Y)
     R_sk = householder_r(S)
     W = Y @ tri_inv_upper(R_sk)
     R_c, _ = chol_upper_ladder(W.T @ W)

@@ -3,7 +3,7 @@
 The paper draws Omega = X^T from an oblivious subspace embedding (Section 1.1,
 eq. testmatrix; Section 2: Gaussian with iid entries, SRHT = S H D with zero
 padding to a power of two) and a second-level sketch Theta (Algorithm
-prec_chol_qr).  It fixes no generator, so both implementations use one
+prec_chol_qr, a sparse sign embedding).  It fixes no generator, so both implementations use one
 published counter-based generator, implemented independently on each side:
 
 * SplitMix64 (Steele, Lea and Flood, "Fast splittable pseudorandom number
@@ -121,6 +121,41 @@ def omega(kind: str, seed: int, n: int, l: int, bf16: bool = False) -> np.ndarra
     raise ValueError(kind)
 
 
-def theta(seed: int, n: int, l: int) -> np.ndarray:
-    """Second-level Gaussian sketch Theta (2l x n), stream seed+1, column-major counters."""
-    return gaussian_matrix(seed + 1, 2 * l, n)
+THETA_NNZ = 8   # nonzeros per column of Theta
+
+
+def theta_blocks(k: int):
+    """Row blocks of the sparse sign embedding Theta (2k rows): zeta = min(8, 2k)
+    blocks, block t = rows [floor(t 2k / zeta), floor((t+1) 2k / zeta))."""
+    lsk = 2 * k
+    zeta = min(THETA_NNZ, lsk)
+    return lsk, zeta, [t * lsk // zeta for t in range(zeta + 1)]
+
+
+def theta(seed: int, n: int, k: int):
+    """Second-level sketch Theta of Algorithm prec_chol_qr: a sparse sign embedding.
+
+    Section 4.2 asks for a fast transform of small size that embeds range(A_mu Omega)
+    (eq. epsilon_embedding) and names sparse embeddings with O(log n) nonzeros per
+    column among those that do.  Theta is 2k x n; column i has one entry +-1 in each
+    of zeta = min(8, 2k) row blocks (the block construction of a sparse
+    Johnson-Lindenstrauss transform, Kane and Nelson 2014).  Word w of stream
+    seed+1 at counter i*zeta + t gives, for block t of size b_t starting at row
+    r_t, the row r_t + floor(hi32(w) * b_t / 2^32) and the sign -1 if bit 0 of w
+    is set.  The scale 1/sqrt(zeta) is dropped: R_sk only preconditions, and
+    R = R_chol R_sk is unchanged by it.  Returned as a scipy.sparse CSR matrix.
+    """
+    import scipy.sparse as sp
+
+    lsk, zeta, starts = theta_blocks(k)
+    i = np.arange(n, dtype=np.uint64)
+    rows, cols, vals = [], [], []
+    for t in range(zeta):
+        w = splitmix64_words(seed + 1, i * np.uint64(zeta) + np.uint64(t))
+        size = np.uint64(starts[t + 1] - starts[t])
+        r = np.uint64(starts[t]) + (((w >> np.uint64(32)) * size) >> np.uint64(32))
+        rows.append(r.astype(np.int64))
+        cols.append(i.astype(np.int64))
+        vals.append(np.where((w & np.uint64(1)) == 0, 1.0, -1.0))
+    return sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                         shape=(lsk, n))

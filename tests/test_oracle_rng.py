@@ -78,3 +78,55 @@ def test_round_bf16_matches_torch():
                         [0.0, 1.0, -1.0, 1.00390625, 1.005859375]])
     ref = torch.from_numpy(x.astype(np.float32)).to(torch.bfloat16).to(torch.float64).numpy()
     assert np.array_equal(rng.round_bf16(x), ref)
+
+
+@pytest.mark.parametrize("n,k", [(1000, 50), (37, 3), (500, 1), (64, 40)])
+def test_theta_sparse_sign_structure(n, k):
+    """Theta (2k x n): every column holds exactly zeta = min(8, 2k) entries +-1, one in
+    each row block, so Theta^T Theta has zeta on its diagonal (Section 4.2, sparse
+    embeddings)."""
+    T = rng.theta(11, n, k)
+    lsk, zeta, starts = rng.theta_blocks(k)
+    assert T.shape == (lsk, n)
+    assert zeta == min(8, 2 * k)
+    assert starts[0] == 0 and starts[-1] == lsk and all(b > a for a, b in zip(starts, starts[1:]))
+    Td = T.toarray()
+    assert set(np.unique(Td)) <= {-1.0, 0.0, 1.0}
+    for t in range(zeta):
+        blk = Td[starts[t]:starts[t + 1]]
+        assert np.all(np.count_nonzero(blk, axis=0) == 1)
+    assert np.array_equal(np.diag(Td.T @ Td), np.full(n, float(zeta)))
+
+
+def test_theta_rows_uniform_and_signs_balanced():
+    """Within a block every row is equally likely, and the signs are fair."""
+    n, k = 200_000, 20
+    T = rng.theta(4, n, k).tocoo()
+    lsk, zeta, starts = rng.theta_blocks(k)
+    counts = np.bincount(T.row, minlength=lsk)
+    for t in range(zeta):
+        c = counts[starts[t]:starts[t + 1]]
+        assert stats.chisquare(c).pvalue > 1e-4
+    assert abs(np.mean(T.data)) < 5.0 / np.sqrt(T.nnz)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_theta_is_a_subspace_embedding(seed):
+    """eq. epsilon_embedding: for an orthonormal U (n x k) the singular values of
+    Theta U / sqrt(zeta) lie in [1 - eps, 1 + eps] with eps < 1, so Theta Y has full
+    column rank and cond(Y R_sk^{-1}) stays O(1)."""
+    n, k = 4000, 40
+    U, _ = np.linalg.qr(np.random.default_rng(seed).standard_normal((n, k)))
+    T = rng.theta(seed, n, k)
+    sv = np.linalg.svd(np.asarray(T @ U) / np.sqrt(8), compute_uv=False)
+    assert sv.min() > 0.15 and sv.max() < 1.85
+
+
+def test_theta_preserves_inner_products_in_expectation():
+    """E[<Theta x, Theta y>] = zeta <x, y>: averaged over independent streams."""
+    n, k = 3000, 30
+    g = np.random.default_rng(5)
+    x = g.standard_normal(n)
+    y = x + 0.5 * g.standard_normal(n)
+    vals = [float((rng.theta(s, n, k) @ x) @ (rng.theta(s, n, k) @ y)) / 8 for s in range(200)]
+    assert abs(np.mean(vals) - x @ y) < 4 * np.std(vals) / np.sqrt(len(vals))
