@@ -306,6 +306,20 @@ rr_status rr_random_matrix(int32_t kind, uint64_t seed, int64_t rows, int64_t co
                            double* out, void* hip_stream);
 
 /*
+ * S = Theta Y with the second-level sketch of Algorithm prec_chol_qr (Section 4.2)
+ * exactly as the build draws it for Omega stream `seed`: Theta is the sparse sign
+ * embedding of stream seed+1 with 2k rows and min(8, 2k) entries +-1 per column,
+ * one in each of that many row blocks (block t = rows [floor(2kt/z), floor(2k(t+1)/z))),
+ * row and sign from one generator word per (column, block).  Y: device, n x k
+ * float64 column-major (ld n), borrowed.  S: device, 2k x k float64 column-major
+ * (ld 2k), written.  Each S[r, c] is summed over the columns of Theta in increasing
+ * order.  Errors: RR_EINVAL (null pointers, n < 1, k < 1), RR_ENOMEM, RR_EDEVICE.
+ * Asynchronous on the stream.
+ */
+rr_status rr_theta_apply(uint64_t seed, int64_t n, int64_t k, const double* Y, double* S,
+                         void* hip_stream);
+
+/*
  * Kernel timing for measurement (off by default).  rr_profile_enable(1) clears the
  * counters and makes the launchers of the hot kernels bracket every launch with
  * HIP events on the launch stream; rr_profile_read(slot, &count, &total_ms)

@@ -9,10 +9,11 @@ from .binding import (  # noqa: F401
     OP_DENSE, OP_MATERN32, OP_RBF, PREC_FP32, PREC_FP64, PREC_MIXED, RR_EBREAKDOWN, RR_EDEVICE,
     RR_EINVAL, RR_ENOCONV, RR_ENOMEM, RR_ENOTSPD, RR_OK, Operator, Precond, RRError,
     apply_operator, apply_operator_block, build_precond, dense_operator, kernel_operator, kernel_to_dense, lib,
-    random_matrix, sketch,
+    random_matrix, sketch, theta_apply,
 )
 
 __all__ = [
     "lib", "Operator", "Precond", "RRError", "build_precond", "dense_operator", "kernel_operator",
     "kernel_to_dense", "apply_operator", "apply_operator_block", "random_matrix", "sketch",
+    "theta_apply",
 ]

@@ -127,6 +127,7 @@ def lib():
         L.rr_apply_operator_block.argtypes = [C.POINTER(rr_operator), C.c_double, C.c_int32, P,
                                               C.c_int32, P, P]
         L.rr_random_matrix.argtypes = [C.c_int32, C.c_uint64, C.c_int64, C.c_int64, P, P]
+        L.rr_theta_apply.argtypes = [C.c_uint64, C.c_int64, C.c_int64, P, P, P]
         L.rr_sketch_apply.argtypes = [C.POINTER(rr_operator), C.c_double, C.POINTER(rr_build_opts),
                                       P, P]
         L.rr_profile_enable.argtypes = [C.c_int32]
@@ -141,7 +142,8 @@ def lib():
         L.rr_version.restype = C.c_char_p
         for name in ("rr_build_precond", "rr_solve", "rr_solve_batch", "rr_serve",
                      "rr_precond_export", "rr_precond_export_omega", "rr_precond_shape",
-                     "rr_kernel_to_dense", "rr_apply_operator", "rr_apply_operator_block", "rr_random_matrix", "rr_sketch_apply"):
+                     "rr_kernel_to_dense", "rr_apply_operator", "rr_apply_operator_block", "rr_random_matrix", "rr_sketch_apply",
+                     "rr_theta_apply"):
             getattr(L, name).restype = C.c_int32
         _lib = L
     return _lib
@@ -354,6 +356,18 @@ def random_matrix(kind: str, seed: int, rows: int, cols: int, stream=None):
     _check(lib().rr_random_matrix({"gaussian": 0, "srht": 1}[kind], int(seed), int(rows), int(cols),
                                   _ptr(out), _stream(stream)), "rr_random_matrix")
     return out.t()
+
+
+def theta_apply(seed: int, Y, stream=None):
+    """S = Theta Y (2k x k) with the build's second-level sketch for Omega stream `seed`;
+    Y: CUDA float64 tensor (n, k)."""
+    import torch
+    n, k = Y.shape
+    Yc = Y.t().contiguous()                 # column-major n x k
+    S = torch.empty((k, 2 * k), dtype=torch.float64, device="cuda")
+    _check(lib().rr_theta_apply(int(seed), int(n), int(k), _ptr(Yc), _ptr(S), _stream(stream)),
+           "rr_theta_apply")
+    return S.t()
 
 
 (PROF_KERNEL_MATVEC, PROF_KERNEL_SKETCH, PROF_DENSE_MATVEC, PROF_DENSE_SKETCH, PROF_PROJECT,

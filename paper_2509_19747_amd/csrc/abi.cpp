@@ -386,4 +386,20 @@ rr_status rr_random_matrix(int32_t kind, uint64_t seed, int64_t rows, int64_t co
     });
 }
 
+rr_status rr_theta_apply(uint64_t seed, int64_t n, int64_t k, const double* Y, double* S, void* hip_stream) {
+    return guarded([&]() -> rr_status {
+        RR_REQUIRE(Y != nullptr && S != nullptr, "Y or S is null");
+        RR_REQUIRE(n >= 1 && k >= 1, "n and k must be >= 1");
+        require_device();
+        hipStream_t st = (hipStream_t)hip_stream;
+        Alloc al;
+        al.st = st;
+        DBuf Yt(&al, (size_t)n * k * sizeof(double));
+        launch_transpose_f64(DT_F64, n, k, Y, n, Yt.as<double>(), k, st);
+        launch_theta_apply(n, k, seed + 1, Yt.as<double>(), k, S, 2 * k, st);
+        RR_HIP(hipGetLastError());
+        return RR_OK;
+    });
+}
+
 }  // extern "C"

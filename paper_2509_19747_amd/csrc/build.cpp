@@ -122,7 +122,6 @@ struct Builder {
                 D(al, (size_t)n * sizeof(float));
             launch_srht_prepare(n, l, o.seed, s, perm.as<int32_t>(), rows.as<int32_t>(), D.as<float>(), st);
             launch_srht_fill(gen, gdt, n, l, gld, D.as<float>(), rows.as<int32_t>(), st);
-            sync();
         }
         if (bf16_omega) launch_copy_mat(DT_BF16, ob_buf.ptr(), ldo, P.omega_dt, P.Omega.ptr(), n, n, l, st);
         Ob = ob_buf.ptr();
@@ -156,27 +155,32 @@ struct Builder {
         check_launch();
     }
 
-    // Q (n x k) R (k x k) = Y (n x k).  Sketched: Algorithm prec_chol_qr with a
-    // Gaussian Theta (2k x n, stream theta_seed); plain: Algorithm chol_qr.
-    void orth(const void* Y, int ydt, int64_t k, uint64_t theta_seed, double* Q, double* R) {
+    // Q (n x k) R (k x k) = Y (n x k).  Sketched: Algorithm prec_chol_qr with the
+    // sparse sign embedding Theta (2k x n, stream theta_seed); plain: Algorithm
+    // chol_qr.  The block products read Y row-major in float64 (Yt, made here;
+    // handed back through yt_out when asked for): a row of Y is what Theta adds,
+    // and float64 operands keep the float64 MFMA GEMM at full load width.
+    void orth(const void* Y, int ydt, int64_t k, uint64_t theta_seed, double* Q, double* R,
+              DBuf* yt_out = nullptr) {
         const int64_t n = P.n;
+        DBuf Yt = mat(k, n);   // column-major k x n = Y^T
+        launch_transpose_f64(ydt, n, k, Y, n, Yt.as<double>(), k, st);
+        const double* yt = Yt.as<double>();
         if (P.opts.orth == RR_ORTH_SKETCHED_CHOLQR) {
-            DBuf theta = mat(2 * k, n);
-            launch_gauss_fill(theta.ptr(), DT_F64, 2 * k, n, 2 * k, theta_seed, st);
             DBuf S = mat(2 * k, k);
-            gemm(DT_F64, false, ydt, false, 2 * k, k, n, theta.ptr(), 2 * k, Y, n, S.as<double>(), 2 * k);
-            theta.release();
+            launch_theta_apply(n, k, theta_seed, yt, k, S.as<double>(), 2 * k, st);
             DBuf Rsk = mat(k, k);
             const size_t hwd = householder_ws_doubles(2 * k, k);
             DBuf hws(al, hwd * sizeof(double));
             launch_householder_r(S.as<double>(), 2 * k, k, 2 * k, Rsk.as<double>(), k, hws.as<double>(),
                                  hwd, st);
             hws.release();
+            S.release();
             check_launch();
             DBuf Rskinv = mat(k, k);
             launch_tri_inv_upper(Rsk.as<double>(), k, k, Rskinv.as<double>(), k, st);
             DBuf W = mat(n, k);
-            gemm(ydt, false, DT_F64, false, n, k, k, Y, n, Rskinv.ptr(), k, W.as<double>(), n);
+            gemm(DT_F64, true, DT_F64, false, n, k, k, yt, k, Rskinv.ptr(), k, W.as<double>(), n);
             DBuf GW = mat(k, k);
             gemm(DT_F64, true, DT_F64, false, k, k, n, W.ptr(), n, W.ptr(), n, GW.as<double>(), k);
             launch_symmetrize(GW.as<double>(), k, k, st);
@@ -187,14 +191,15 @@ struct Builder {
             gemm(DT_F64, false, DT_F64, false, k, k, k, GW.ptr(), k, Rsk.ptr(), k, R, k);  // R = R_chol R_sk
             launch_zero_lower(R, k, k, st);
         } else {
-            gemm(ydt, true, ydt, false, k, k, n, Y, n, Y, n, R, k);
+            gemm(DT_F64, false, DT_F64, true, k, k, n, yt, k, yt, k, R, k);
             launch_symmetrize(R, k, k, st);
             chol_ladder(R, k);
             DBuf Rinv = mat(k, k);
             launch_tri_inv_upper(R, k, k, Rinv.as<double>(), k, st);
-            gemm(ydt, false, DT_F64, false, n, k, k, Y, n, Rinv.ptr(), k, Q, n);
+            gemm(DT_F64, true, DT_F64, false, n, k, k, yt, k, Rinv.ptr(), k, Q, n);
         }
         check_launch();
+        if (yt_out) *yt_out = std::move(Yt);
     }
 
     // Power iteration: v <- op(v)/||op(v)|| from a Gaussian start (stream seed);
@@ -404,11 +409,23 @@ extern "C" rr_status rr_build_precond(const rr_operator* A, const double* mus, i
             A16.release();
             // A3: orthogonalisation
             pm.R.reset(al, (size_t)l * l * sizeof(double));
-            B.orth(Y.ptr(), ydt, l, o.seed + 1, P.Qb.as<double>(), pm.R.as<double>());
-            // A4: core, refined projector, tau, apply core
-            DBuf C = B.mat(l, l);
-            B.gemm(P.omega_dt, true, ydt, false, l, l, n, P.Omega.ptr(), n, Y.ptr(), n, C.as<double>(), l);
+            DBuf Yt;
+            B.orth(Y.ptr(), ydt, l, o.seed + 1, P.Qb.as<double>(), pm.R.as<double>(), &Yt);
             Y.release();
+            // A4: core, refined projector, tau, apply core.  C^T = Y^T Omega (C is
+            // symmetrised before use), with float64 operands.
+            DBuf C = B.mat(l, l);
+            {
+                DBuf Od;
+                const void* om = P.Omega.ptr();
+                if (P.omega_dt != DT_F64) {
+                    Od = B.mat(n, l);
+                    launch_copy_mat(P.omega_dt, P.Omega.ptr(), n, DT_F64, Od.ptr(), n, n, l, st);
+                    om = Od.ptr();
+                }
+                B.gemm(DT_F64, false, DT_F64, false, l, l, n, Yt.ptr(), l, om, n, C.as<double>(), l);
+            }
+            Yt.release();
             pm.G.reset(al, (size_t)l * l * sizeof(double));
             B.core_G(C.as<double>(), pm.R.as<double>(), pm.G.as<double>(), l);
             pm.T.reset(al, (size_t)l * l * sizeof(double));

@@ -38,6 +38,17 @@ void launch_srht_prepare(int64_t n, int64_t l, uint64_t seed, int64_t s, int32_t
                          int32_t* rows_out, float* D_out, hipStream_t st);
 void launch_srht_fill(void* out, int dtype, int64_t n, int64_t l, int64_t ld, const float* D,
                       const int32_t* rows, hipStream_t st);
+// S (2k x k, column-major, lds) = Theta Y for the sparse sign embedding of stream
+// `seed` (THETA_NNZ nonzeros per column, one per row block); Yt: Y row-major in
+// float64 (Yt[i * ldy + c], i < n, c < k).
+constexpr int THETA_NNZ = 8;
+int theta_nnz(int64_t k);
+void launch_theta_apply(int64_t n, int64_t k, uint64_t seed, const double* Yt, int64_t ldy, double* S,
+                        int64_t lds, hipStream_t st);
+// out[c + i * ldo] = (double) in[i + c * ldi] (i < rows, c < cols): a column-major
+// matrix of dtype float64 / float32 written row-major in float64.
+void launch_transpose_f64(int dtype, int64_t rows, int64_t cols, const void* in, int64_t ldi, double* out,
+                          int64_t ldo, hipStream_t st);
 
 // ------------------------------------------------------------------- GEMM
 // C = alpha * op(A) op(B) + beta * C, float64 accumulation, op = transpose if tr*.

@@ -172,6 +172,36 @@ void launch_gemm(int dta, bool trA, int dtb, bool trB, int64_t M, int64_t N, int
 }
 
 // ================================================== small dense helpers
+// out[c + i * ldo] = (double) in[i + c * ldi]: column-major in, row-major float64 out,
+// through 64 x 64 LDS tiles (both sides coalesced).
+template <typename TI>
+__global__ __launch_bounds__(256) void k_transpose_f64(int64_t rows, int64_t cols, const TI* __restrict__ in,
+                                                       int64_t ldi, double* __restrict__ out, int64_t ldo) {
+    __shared__ double tile[64][65];
+    const int64_t i0 = (int64_t)blockIdx.x * 64, c0 = (int64_t)blockIdx.y * 64;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+#pragma unroll
+    for (int cc = ty; cc < 64; cc += 4) {
+        const int64_t i = i0 + tx, c = c0 + cc;
+        if (i < rows && c < cols) tile[cc][tx] = (double)in[i + c * ldi];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ii = ty; ii < 64; ii += 4) {
+        const int64_t i = i0 + ii, c = c0 + tx;
+        if (i < rows && c < cols) out[c + i * ldo] = tile[tx][ii];
+    }
+}
+
+void launch_transpose_f64(int dtype, int64_t rows, int64_t cols, const void* in, int64_t ldi, double* out,
+                          int64_t ldo, hipStream_t st) {
+    const dim3 grid((unsigned)((rows + 63) / 64), (unsigned)((cols + 63) / 64));
+    if (dtype == DT_F32)
+        k_transpose_f64<float><<<grid, 256, 0, st>>>(rows, cols, (const float*)in, ldi, out, ldo);
+    else
+        k_transpose_f64<double><<<grid, 256, 0, st>>>(rows, cols, (const double*)in, ldi, out, ldo);
+}
+
 __global__ void k_symmetrize(double* A, int64_t l, int64_t lda) {
     const int64_t total = l * l;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;

@@ -9,75 +9,71 @@
 #include "common.hpp"
 #include "kernels.hpp"
 
+#include <algorithm>
+
 namespace rr {
 
 // ============================================================== Cholesky
 constexpr int CH_NB = 32;
 
-// Factor the kb x kb diagonal block at A (upper part) in place.
-__global__ __launch_bounds__(256) void k_potf2(double* A, int64_t lda, int kb, int32_t* status) {
-    __shared__ double a[CH_NB][CH_NB + 1];
-    __shared__ int bad;
+// One block row of the blocked Cholesky in a single launch of 64-thread blocks:
+// every block factors the kb x kb diagonal block A11 = R11^T R11 (identical
+// arithmetic in every block), then solves R11^T X = A12 for its 64 columns of the
+// row panel.  Lane j holds column j of A11 in registers; row k of R11 is shared
+// through LDS once it is formed, so the inner loops only read LDS broadcasts.
+// Block 0 writes R11 back (zeros below the diagonal) and raises the status word
+// when a pivot is not positive and finite.
+__global__ __launch_bounds__(64) void k_chol_panel(double* A, int64_t lda, int kb, int64_t rest,
+                                                   int32_t* status) {
+    __shared__ double rk[CH_NB][CH_NB + 1];   // rk[k][i] = R11(k, i), i >= k
     if (*status) return;
     const int t = threadIdx.x;
-    for (int e = t; e < kb * kb; e += blockDim.x) {
-        const int i = e % kb, j = e / kb;
-        a[i][j] = (i <= j) ? A[i + (int64_t)j * lda] : 0.0;
+    double col[CH_NB];
+#pragma unroll
+    for (int i = 0; i < CH_NB; ++i)
+        col[i] = (t < kb && i <= t) ? A[i + (int64_t)t * lda] : 0.0;
+    const int64_t jc = (int64_t)blockIdx.x * 64 + t;   // panel column of this thread
+    double x[CH_NB];
+#pragma unroll
+    for (int i = 0; i < CH_NB; ++i) x[i] = (jc < rest && i < kb) ? A[i + (kb + jc) * lda] : 0.0;
+    bool bad = false;
+#pragma unroll
+    for (int k = 0; k < CH_NB; ++k) {
+        if (k >= kb) continue;   // uniform
+        const double dkk = __shfl(col[k], k);
+        const bool ok = dkk > 0.0 && isfinite(dkk);
+        bad = bad || !ok;
+        const double piv = ok ? sqrt(dkk) : 1.0;
+        const double rkt = (t == k) ? piv : (t > k ? col[k] / piv : 0.0);
+        if (t >= k) col[k] = rkt;
+        if (t < CH_NB) rk[k][t] = rkt;
+        __syncthreads();
+#pragma unroll
+        for (int i = k + 1; i < CH_NB; ++i) {
+            const double rki = rk[k][i];
+            if (i <= t && t < kb) col[i] = fma(-rki, rkt, col[i]);
+        }
     }
-    if (t == 0) bad = 0;
     __syncthreads();
-    for (int k = 0; k < kb; ++k) {
-        if (t == 0) {
-            const double dkk = a[k][k];
-            if (!(dkk > 0.0) || !isfinite(dkk)) {
-                bad = 1;
-                a[k][k] = 1.0;
-            } else {
-                a[k][k] = sqrt(dkk);
-            }
+    if (jc < rest) {
+#pragma unroll
+        for (int i = 0; i < CH_NB; ++i) {
+            if (i >= kb) continue;
+            double s = x[i];
+#pragma unroll
+            for (int k = 0; k < i; ++k) s = fma(-rk[k][i], x[k], s);
+            x[i] = s / rk[i][i];
         }
-        __syncthreads();
-        const double piv = a[k][k];
-        for (int j = k + 1 + t; j < kb; j += blockDim.x) a[k][j] /= piv;
-        __syncthreads();
-        const int rem = kb - k - 1;
-        for (int e = t; e < rem * rem; e += blockDim.x) {
-            const int i = k + 1 + e % rem, j = k + 1 + e / rem;
-            if (i <= j) a[i][j] -= a[k][i] * a[k][j];
-        }
-        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < CH_NB; ++i)
+            if (i < kb) A[i + (kb + jc) * lda] = x[i];
     }
-    for (int e = t; e < kb * kb; e += blockDim.x) {
-        const int i = e % kb, j = e / kb;
-        A[i + (int64_t)j * lda] = (i <= j) ? a[i][j] : 0.0;
-    }
-    if (t == 0 && bad) *status = 1;
-}
-
-// X = R11^{-T} X for the kb x ncols panel at X (rows of the current block row),
-// R11 the kb x kb upper factor at R.  One thread per column, forward substitution.
-__global__ __launch_bounds__(64) void k_trsm_panel(const double* R, int64_t ldr, int kb, double* X,
-                                                   int64_t ldx, int64_t ncols,
-                                                   const int32_t* status) {
-    __shared__ double r[CH_NB][CH_NB + 1];
-    __shared__ double xs[CH_NB][65];
-    if (*status) return;
-    const int t = threadIdx.x;
-    for (int e = t; e < kb * kb; e += blockDim.x) {
-        const int i = e % kb, j = e / kb;
-        r[i][j] = R[i + (int64_t)j * ldr];
-    }
-    const int64_t j = (int64_t)blockIdx.x * 64 + t;
-    if (j < ncols)
-        for (int i = 0; i < kb; ++i) xs[i][t] = X[i + j * ldx];
-    __syncthreads();
-    if (j < ncols) {
-        for (int i = 0; i < kb; ++i) {
-            double s = xs[i][t];
-            for (int k = 0; k < i; ++k) s -= r[k][i] * xs[k][t];
-            xs[i][t] = s / r[i][i];
-        }
-        for (int i = 0; i < kb; ++i) X[i + j * ldx] = xs[i][t];
+    if (blockIdx.x == 0) {
+        if (t < kb)
+#pragma unroll
+            for (int i = 0; i < CH_NB; ++i)
+                if (i < kb) A[i + (int64_t)t * lda] = (i <= t) ? col[i] : 0.0;
+        if (t == 0 && bad) *status = 1;
     }
 }
 
@@ -86,11 +82,11 @@ void launch_cholesky_upper(double* A, int64_t l, int64_t lda, int32_t* status, d
     for (int64_t k0 = 0; k0 < l; k0 += CH_NB) {
         const int kb = (int)((l - k0 < CH_NB) ? l - k0 : CH_NB);
         double* A11 = A + k0 + k0 * lda;
-        k_potf2<<<1, 256, 0, st>>>(A11, lda, kb, status);
         const int64_t rest = l - k0 - kb;
+        k_chol_panel<<<(unsigned)std::max<int64_t>((rest + 63) / 64, 1), 64, 0, st>>>(A11, lda, kb, rest,
+                                                                                     status);
         if (rest > 0) {
-            double* A12 = A + k0 + (k0 + kb) * lda;
-            k_trsm_panel<<<(unsigned)((rest + 63) / 64), 64, 0, st>>>(A11, lda, kb, A12, lda, rest, status);
+            const double* A12 = A + k0 + (k0 + kb) * lda;
             double* A22 = A + (k0 + kb) + (k0 + kb) * lda;
             launch_gemm(DT_F64, true, DT_F64, false, rest, rest, kb, A12, lda, A12, lda, A22, lda,
                         -1.0, 1.0, ws, ws_doubles, st);

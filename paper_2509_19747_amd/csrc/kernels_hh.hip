@@ -8,7 +8,8 @@
 // held in registers (thread t owns rows j0 + t + 512 r), producing the
 // reflectors V, their scalars tau and the compact-WY factor T of the panel
 // (Q_panel = H_1 ... H_NB = I - V T V^T), and the R entries of its columns.
-// The trailing columns are then updated with three GEMMs,
+// One more launch per panel updates the trailing columns with the three block
+// products fused (k_hb_update),
 //   W = V^T S_t,  W <- T^T W,  S_t <- S_t - V W,
 // and an explicit Q is accumulated backwards panel by panel with
 //   W = V^T Q_t,  W <- T W,  Q_t <- Q_t - V W.
@@ -46,6 +47,30 @@ RR_DEV void hb_block_sum(double (&v)[NV], double* red, double* tot) {
     __syncthreads();
 }
 
+// Block-wide sums of NV values per thread through LDS: every thread stores its NV
+// partials, then the P = 512 / NV threads that share value q add 512 / P of them each
+// and finish with a P-lane butterfly.  Far fewer instructions than NV wave-wide DPP
+// trees for the panel's NB dot products.  Fixed order, so deterministic.
+template <int NV>
+RR_DEV void hb_block_sum_t(double (&v)[NV], double* buf, double* tot) {
+    constexpr int P = HB_THREADS / NV;
+    static_assert(P == 16 || P == 32 || P == 64, "NV must be 8, 16 or 32");
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int q = 0; q < NV; ++q) buf[q * HB_THREADS + t] = v[q];
+    __syncthreads();
+    const int q = t / P, part = t % P;
+    double s = 0.0;
+#pragma unroll
+    for (int j = 0; j < HB_THREADS / P; ++j) s += buf[q * HB_THREADS + part + P * j];
+#pragma unroll
+    for (int o = P / 2; o >= 1; o >>= 1) s += __shfl_xor(s, o, P);
+    if (part == 0) tot[q] = s;
+    __syncthreads();
+#pragma unroll
+    for (int q2 = 0; q2 < NV; ++q2) v[q2] = tot[q2];
+}
+
 // Factor columns [j0, j0 + nbe) of S (rows [j0, m)), nbe <= NB; m - j0 <= RR * 512.
 // Writes V[:, j0..] (zeros above the diagonal), tau[j0..], T (NB x NB, column-major,
 // ldt NB) and R[0:k, j0..] (rows above the panel from S, which already holds them).
@@ -58,6 +83,7 @@ __global__ __launch_bounds__(HB_THREADS) void k_panel_qr(const double* __restric
                                                          double* __restrict__ R, int64_t ldr) {
     __shared__ double red[HB_WAVES * NB];
     __shared__ double tot[NB];
+    __shared__ double dbuf[NB * HB_THREADS];
     __shared__ double Tsh[NB * NB];
     __shared__ double s_alpha;
     const int t = threadIdx.x;
@@ -74,17 +100,20 @@ __global__ __launch_bounds__(HB_THREADS) void k_panel_qr(const double* __restric
         for (int64_t i = t; i < j0; i += HB_THREADS) R[i + (j0 + c) * ldr] = S[i + (j0 + c) * lds];
     __syncthreads();
 
-    for (int c = 0; c < nbe; ++c) {
+    double rsave[NB];
+#pragma unroll
+    for (int c = 0; c < NB; ++c) rsave[c] = 0.0;
+    // the column loop is unrolled so that every register index is static
+#pragma unroll
+    for (int c = 0; c < NB; ++c) {
+        if (c >= nbe) continue;   // uniform over the block
         const int64_t kc = j0 + c;
         // x = column c at rows >= kc; the pivot row kc is thread c, register row 0
         double s1[1] = {0.0};
 #pragma unroll
         for (int r = 0; r < RR; ++r) {
             const int64_t i = j0 + t + (int64_t)HB_THREADS * r;
-            double x = 0.0;
-#pragma unroll
-            for (int q = 0; q < NB; ++q)
-                if (q == c) x = a[r][q];
+            const double x = a[r][c];
             if (i > kc && i < m) s1[0] = fma(x, x, s1[0]);
             if (i == kc) s_alpha = x;
         }
@@ -95,25 +124,16 @@ __global__ __launch_bounds__(HB_THREADS) void k_panel_qr(const double* __restric
         const double v0 = alpha - beta;
         const double vtv = fma(v0, v0, s1[0]);
         const double f = (vtv > 0.0) ? 2.0 / vtv : 0.0;
-        // R entries of column kc: rows [j0, kc) from the panel, the diagonal, zeros below
-#pragma unroll
-        for (int r = 0; r < RR; ++r) {
-            const int64_t i = j0 + t + (int64_t)HB_THREADS * r;
-            double x = 0.0;
-#pragma unroll
-            for (int q = 0; q < NB; ++q)
-                if (q == c) x = a[r][q];
-            if (i < kc) R[i + kc * ldr] = x;
-            else if (i == kc) R[i + kc * ldr] = (normx > 0.0) ? beta : alpha;
-            else if (i < k) R[i + kc * ldr] = 0.0;
-        }
+        // R entries of column kc in the panel rows (thread t < c holds row j0 + t, thread
+        // c the diagonal) are kept in registers and stored after the loop: a global
+        // store here would make every following barrier wait for it.
+        if (t < c) rsave[c] = a[0][c];
+        else if (t == c) rsave[c] = (normx > 0.0) ? beta : alpha;
         // v into column c (zeros above the pivot)
 #pragma unroll
         for (int r = 0; r < RR; ++r) {
             const int64_t i = j0 + t + (int64_t)HB_THREADS * r;
-#pragma unroll
-            for (int q = 0; q < NB; ++q)
-                if (q == c) a[r][q] = (i < kc || i >= m) ? 0.0 : (i == kc ? v0 : a[r][q]);
+            a[r][c] = (i < kc || i >= m) ? 0.0 : (i == kc ? v0 : a[r][c]);
         }
         // dots of v with every panel column: previous reflectors (for T) and the
         // columns still to be reduced (for the update)
@@ -122,23 +142,17 @@ __global__ __launch_bounds__(HB_THREADS) void k_panel_qr(const double* __restric
         for (int q = 0; q < NB; ++q) dots[q] = 0.0;
 #pragma unroll
         for (int r = 0; r < RR; ++r) {
-            double v = 0.0;
-#pragma unroll
-            for (int q = 0; q < NB; ++q)
-                if (q == c) v = a[r][q];
+            const double v = a[r][c];
 #pragma unroll
             for (int q = 0; q < NB; ++q) dots[q] = fma(v, a[r][q], dots[q]);
         }
-        hb_block_sum<NB>(dots, red, tot);
+        hb_block_sum_t<NB>(dots, dbuf, tot);
 #pragma unroll
         for (int r = 0; r < RR; ++r) {
-            double v = 0.0;
+            const double v = a[r][c];
 #pragma unroll
-            for (int q = 0; q < NB; ++q)
-                if (q == c) v = a[r][q];
-#pragma unroll
-            for (int q = 0; q < NB; ++q)
-                if (q > c && q < nbe) a[r][q] = fma(-f * dots[q], v, a[r][q]);
+            for (int q = c + 1; q < NB; ++q)   // columns past nbe hold zeros and stay zero
+                a[r][q] = fma(-f * dots[q], v, a[r][q]);
         }
         // T(:, c): T(c, c) = f, T(0:c, c) = -f T(0:c, 0:c) (V(:, 0:c)^T v); thread i
         // forms row i (it reads only columns < c, which no thread writes now)
@@ -150,7 +164,6 @@ __global__ __launch_bounds__(HB_THREADS) void k_panel_qr(const double* __restric
             Tsh[t + c * NB] = -f * s;
         } else if (t == c) {
             Tsh[c + c * NB] = f;
-            tauv[kc] = f;
         }
         __syncthreads();
     }
@@ -166,6 +179,75 @@ __global__ __launch_bounds__(HB_THREADS) void k_panel_qr(const double* __restric
     for (int c = 0; c < nbe; ++c)
         for (int64_t i = t; i < j0; i += HB_THREADS) V[i + (j0 + c) * ldv] = 0.0;
     for (int i = t; i < NB * NB; i += HB_THREADS) T[i] = Tsh[i];
+    if (t < nbe) tauv[j0 + t] = Tsh[t + t * NB];
+    // R columns of the panel: rows [j0, j0 + c] from the registers, zeros below to row k
+#pragma unroll
+    for (int c = 0; c < NB; ++c) {
+        if (c >= nbe) continue;
+        if (t <= c) R[j0 + t + (j0 + c) * ldr] = rsave[c];
+        for (int64_t i = j0 + c + 1 + t; i < k; i += HB_THREADS) R[i + (j0 + c) * ldr] = 0.0;
+    }
+}
+
+// Trailing update after one panel, the three block products in one launch:
+//   W = V_p^T X_t,  W <- T^T W (factoring) or T W (accumulating Q backwards),
+//   X_t <- X_t - V_p W.
+// Block b updates columns [c0 + CW b, c0 + CW b + CW) of X; thread t owns rows
+// j0 + t + 512 r as in the panel kernel, so the NB x CW inner products are one
+// block sum.  T is the panel's upper triangular compact-WY factor (NB x NB, ld NB).
+template <int RR, int NB, int CW, bool TT>
+__global__ __launch_bounds__(HB_THREADS) void k_hb_update(const double* __restrict__ V, int64_t ldv,
+                                                          const double* __restrict__ T, int64_t m,
+                                                          int64_t j0, int nbe, double* __restrict__ X,
+                                                          int64_t ldx, int64_t c0, int64_t ncols) {
+    __shared__ double red[HB_WAVES * NB * CW];
+    __shared__ double tot[NB * CW];
+    __shared__ double Tsh[NB * NB];
+    __shared__ double w2s[NB * CW];
+    const int t = threadIdx.x;
+    for (int i = t; i < NB * NB; i += HB_THREADS) Tsh[i] = T[i];
+    const int64_t cb = c0 + (int64_t)blockIdx.x * CW;
+    double v[RR][NB], x[RR][CW];
+#pragma unroll
+    for (int r = 0; r < RR; ++r) {
+        const int64_t i = j0 + t + (int64_t)HB_THREADS * r;
+#pragma unroll
+        for (int q = 0; q < NB; ++q) v[r][q] = (i < m && q < nbe) ? V[i + (j0 + q) * ldv] : 0.0;
+#pragma unroll
+        for (int j = 0; j < CW; ++j) x[r][j] = (i < m && cb + j < c0 + ncols) ? X[i + (cb + j) * ldx] : 0.0;
+    }
+    double w[NB * CW];
+#pragma unroll
+    for (int e = 0; e < NB * CW; ++e) w[e] = 0.0;
+#pragma unroll
+    for (int r = 0; r < RR; ++r)
+#pragma unroll
+        for (int q = 0; q < NB; ++q)
+#pragma unroll
+            for (int j = 0; j < CW; ++j) w[q * CW + j] = fma(v[r][q], x[r][j], w[q * CW + j]);
+    hb_block_sum<NB * CW>(w, red, tot);   // its barriers also publish Tsh
+    // op(T) W, one entry per thread: T^T W reads rows p <= q, T W rows p >= q
+    if (t < NB * CW) {
+        const int q = t / CW, j = t % CW;
+        double s = 0.0;
+        for (int p = 0; p < NB; ++p) {
+            if (TT && p <= q) s = fma(Tsh[p + q * NB], tot[p * CW + j], s);
+            if (!TT && p >= q) s = fma(Tsh[q + p * NB], tot[p * CW + j], s);
+        }
+        w2s[t] = s;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < RR; ++r) {
+        const int64_t i = j0 + t + (int64_t)HB_THREADS * r;
+#pragma unroll
+        for (int j = 0; j < CW; ++j) {
+            double y = x[r][j];
+#pragma unroll
+            for (int q = 0; q < NB; ++q) y = fma(-v[r][q], w2s[q * CW + j], y);
+            if (i < m && cb + j < c0 + ncols) X[i + (cb + j) * ldx] = y;
+        }
+    }
 }
 
 // R <- D R and Q <- Q D with D = sign(diag(R)): strict upper part of R and Q
@@ -208,8 +290,7 @@ constexpr int HB_NB = 16;   // largest panel width
 
 size_t householder_ws_doubles(int64_t m, int64_t k) {
     const int64_t panels = (k + HB_NB - 1) / HB_NB;
-    const size_t base = (size_t)m * k + k + (size_t)panels * HB_NB * HB_NB + 2 * (size_t)HB_NB * k;
-    return base + gemm_ws_doubles(HB_NB, k, m) + 64;
+    return (size_t)m * k + k + (size_t)panels * HB_NB * HB_NB + 64;   // V, tau, the T factors
 }
 
 bool householder_blocked_ok(int64_t m, int64_t k) { return m <= 4 * HB_THREADS && k >= 1 && m >= k; }
@@ -220,21 +301,35 @@ static void hb_panel(double* S, int64_t m, int64_t k, int64_t lds, int64_t j0, i
     k_panel_qr<RR, NB><<<1, HB_THREADS, 0, st>>>(S, m, k, lds, j0, nbe, V, m, tauv, T, R, ldr);
 }
 
+constexpr int HB_CW = 2;   // trailing columns per update block
+
+// X[:, c0:c0+ncols] <- (I - V_p op(T) V_p^T) X[...] over rows [j0, m); op(T) = T^T
+// when factoring (TT), T when accumulating Q.
+template <int NB, bool TT>
+static void hb_update(const double* V, int64_t m, const double* T, int64_t j0, int nbe, double* X,
+                      int64_t ldx, int64_t c0, int64_t ncols, hipStream_t st) {
+    const int64_t L = m - j0;
+    const unsigned g = (unsigned)((ncols + HB_CW - 1) / HB_CW);
+    if (L <= HB_THREADS)
+        k_hb_update<1, NB, HB_CW, TT><<<g, HB_THREADS, 0, st>>>(V, m, T, m, j0, nbe, X, ldx, c0, ncols);
+    else if (L <= 2 * HB_THREADS)
+        k_hb_update<2, NB, HB_CW, TT><<<g, HB_THREADS, 0, st>>>(V, m, T, m, j0, nbe, X, ldx, c0, ncols);
+    else if constexpr (NB == 8)
+        k_hb_update<4, NB, HB_CW, TT><<<g, HB_THREADS, 0, st>>>(V, m, T, m, j0, nbe, X, ldx, c0, ncols);
+}
+
 // Shared driver: factor S panel by panel, update the trailing columns; when Q is
 // given, accumulate it afterwards.  Panels of 16 columns while the panel rows
 // fit 2 registers per thread, 8 columns beyond (4 rows per thread).
 // ws: householder_ws_doubles(m, k).
 static void hb_factor(double* S, int64_t m, int64_t k, int64_t lds, double* R, int64_t ldr,
                       double* Q, int64_t ldq, double* ws, size_t wsd, hipStream_t st) {
+    (void)wsd;
     const int nb = m <= 2 * HB_THREADS ? 16 : 8;
     double* V = ws;
     double* tauv = V + (size_t)m * k;
     double* Tall = tauv + k;
     const int64_t panels = (k + nb - 1) / nb;
-    double* W = Tall + (size_t)panels * nb * nb;
-    double* W2 = W + (size_t)nb * k;
-    double* gws = W2 + (size_t)nb * k;
-    const size_t gwsd = wsd - (size_t)(gws - ws);
     for (int64_t p = 0; p < panels; ++p) {
         const int64_t j0 = p * nb;
         const int nbe = (int)std::min<int64_t>(nb, k - j0);
@@ -251,33 +346,19 @@ static void hb_factor(double* S, int64_t m, int64_t k, int64_t lds, double* R, i
         }
         const int64_t jt = j0 + nbe, nt = k - jt;
         if (nt > 0) {
-            const double* Vp = V + j0 + j0 * m;
-            double* St = S + j0 + jt * lds;
-            // W = Vp^T S_t (nbe x nt); W2 = T^T W; S_t -= Vp W2
-            launch_gemm(DT_F64, true, DT_F64, false, nbe, nt, L, Vp, m, St, lds, W, nb, 1.0, 0.0, gws,
-                        gwsd, st);
-            launch_gemm(DT_F64, true, DT_F64, false, nbe, nt, nbe, T, nb, W, nb, W2, nb, 1.0, 0.0, gws,
-                        gwsd, st);
-            launch_gemm(DT_F64, false, DT_F64, false, L, nt, nbe, Vp, m, W2, nb, St, lds, -1.0, 1.0, gws,
-                        gwsd, st);
+            if (nb == 16) hb_update<16, true>(V, m, T, j0, nbe, S, lds, jt, nt, st);
+            else hb_update<8, true>(V, m, T, j0, nbe, S, lds, jt, nt, st);
         }
     }
     if (Q) {
-        // Q = [I; 0], then Q_t <- Q_t - Vp (T (Vp^T Q_t)) for panels in reverse
+        // Q = [I; 0], then Q_t <- Q_t - V_p (T (V_p^T Q_t)) for panels in reverse
         k_hb_eye<<<hb_grid(m * k), 256, 0, st>>>(Q, m, k, ldq);
         for (int64_t p = panels - 1; p >= 0; --p) {
             const int64_t j0 = p * nb;
             const int nbe = (int)std::min<int64_t>(nb, k - j0);
             const double* T = Tall + (size_t)p * nb * nb;
-            const int64_t L = m - j0, nt = k - j0;
-            const double* Vp = V + j0 + j0 * m;
-            double* Qt = Q + j0 + j0 * ldq;
-            launch_gemm(DT_F64, true, DT_F64, false, nbe, nt, L, Vp, m, Qt, ldq, W, nb, 1.0, 0.0, gws,
-                        gwsd, st);
-            launch_gemm(DT_F64, false, DT_F64, false, nbe, nt, nbe, T, nb, W, nb, W2, nb, 1.0, 0.0, gws,
-                        gwsd, st);
-            launch_gemm(DT_F64, false, DT_F64, false, L, nt, nbe, Vp, m, W2, nb, Qt, ldq, -1.0, 1.0, gws,
-                        gwsd, st);
+            if (nb == 16) hb_update<16, false>(V, m, T, j0, nbe, Q, ldq, j0, k - j0, st);
+            else hb_update<8, false>(V, m, T, j0, nbe, Q, ldq, j0, k - j0, st);
         }
     }
     const int64_t tot = (Q ? m * k : 0) + k * k;

@@ -4,6 +4,9 @@
 #include "common.hpp"
 #include "kernels.hpp"
 
+#include <algorithm>
+#include <climits>
+
 namespace rr {
 
 template <typename T>
@@ -60,6 +63,86 @@ __global__ void k_srht_fill(T* __restrict__ out, int64_t n, int64_t l, int64_t l
     }
 }
 
+// Second-level sketch of Algorithm prec_chol_qr: S = Theta Y for the sparse sign
+// embedding Theta (lsk = 2k rows, zeta = min(8, lsk) row blocks, block t = rows
+// [floor(t lsk / zeta), floor((t+1) lsk / zeta))).  Column i of Theta has one entry
+// per block t: word w of stream `seed` at counter i*zeta + t puts it at row
+// r_t + floor(hi32(w) * b_t / 2^32) with sign -1 when bit 0 of w is set.
+//   S[r, c] = sum over i (increasing) with row_t(i) = r of sign_t(i) Y[i, c],
+// t the block that holds row r.  Y arrives row-major in float64 (Yt[i ldy + c]) so
+// each hit adds one contiguous row.  One block per (row r, 256 columns): a pass
+// hashes 2048 points, lists the hits of row r in LDS in increasing i (ballots in
+// (slot, wave, lane) order), then adds their rows of Y in that order; the sum order
+// is therefore fixed and equals the row order of Theta's CSR form.
+constexpr int TH_THREADS = 256, TH_SLOTS = 8, TH_WAVES = TH_THREADS / WAVE;
+
+__global__ __launch_bounds__(TH_THREADS) void k_theta_apply(int64_t n, int64_t k, int64_t lsk, int zeta,
+                                                            uint64_t seed, const double* __restrict__ Yt,
+                                                            int64_t ldy, double* __restrict__ S, int64_t lds) {
+    __shared__ uint64_t bal[TH_SLOTS][TH_WAVES];
+    __shared__ int32_t list[TH_SLOTS * TH_THREADS];
+    const int64_t r = blockIdx.x;
+    const int t = threadIdx.x, lane = t & (WAVE - 1), w = t / WAVE;
+    int blk = 0;
+    while (blk + 1 < zeta && (int64_t)(blk + 1) * lsk / zeta <= r) ++blk;
+    const int64_t b0 = (int64_t)blk * lsk / zeta;
+    const uint64_t bs = (uint64_t)((int64_t)(blk + 1) * lsk / zeta - b0);
+    const int64_t c = (int64_t)blockIdx.y * TH_THREADS + t;
+    const uint64_t below = (1ull << lane) - 1ull;
+    double acc = 0.0;
+    for (int64_t i0 = 0; i0 < n; i0 += TH_SLOTS * TH_THREADS) {
+        bool hit[TH_SLOTS], neg[TH_SLOTS];
+#pragma unroll
+        for (int s = 0; s < TH_SLOTS; ++s) {
+            const int64_t i = i0 + s * TH_THREADS + t;
+            hit[s] = false;
+            neg[s] = false;
+            if (i < n) {
+                const uint64_t wd = splitmix64(seed, (uint64_t)i * (uint64_t)zeta + (uint64_t)blk);
+                hit[s] = b0 + (int64_t)(((wd >> 32) * bs) >> 32) == r;
+                neg[s] = (wd & 1ull) != 0;
+            }
+            const uint64_t b = __ballot(hit[s]);
+            if (lane == 0) bal[s][w] = b;
+        }
+        __syncthreads();
+        int total = 0;
+#pragma unroll
+        for (int s = 0; s < TH_SLOTS; ++s) {
+#pragma unroll
+            for (int v = 0; v < TH_WAVES; ++v) {
+                const uint64_t b = bal[s][v];
+                if (v == w && hit[s]) {
+                    const int32_t off = s * TH_THREADS + t;   // i - i0
+                    list[total + __popcll(b & below)] = neg[s] ? (off | INT32_MIN) : off;
+                }
+                total += __popcll(b);
+            }
+        }
+        __syncthreads();
+        if (c < k) {
+            int j = 0;
+            for (; j + 4 <= total; j += 4) {
+                int32_t e[4];
+                double y[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) e[q] = list[j + q];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) y[q] = Yt[(i0 + (e[q] & INT32_MAX)) * ldy + c];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) acc += e[q] < 0 ? -y[q] : y[q];
+            }
+            for (; j < total; ++j) {
+                const int32_t e = list[j];
+                const double y = Yt[(i0 + (e & INT32_MAX)) * ldy + c];
+                acc += e < 0 ? -y : y;
+            }
+        }
+        __syncthreads();
+    }
+    if (c < k) S[r + c * lds] = acc;
+}
+
 static int grid_for(int64_t total, int block = 256) {
     int64_t g = (total + block - 1) / block;
     if (g > 65536) g = 65536;
@@ -92,6 +175,15 @@ void launch_srht_fill(void* out, int dtype, int64_t n, int64_t l, int64_t ld, co
         case DT_F32: k_srht_fill<float><<<g, 256, 0, st>>>((float*)out, n, l, ld, D, rows); break;
         default: k_srht_fill<__hip_bfloat16><<<g, 256, 0, st>>>((__hip_bfloat16*)out, n, l, ld, D, rows); break;
     }
+}
+
+int theta_nnz(int64_t k) { return (int)std::min<int64_t>(THETA_NNZ, 2 * k); }
+
+void launch_theta_apply(int64_t n, int64_t k, uint64_t seed, const double* Yt, int64_t ldy, double* S,
+                        int64_t lds, hipStream_t st) {
+    const int64_t lsk = 2 * k;
+    dim3 grid((unsigned)lsk, (unsigned)((k + TH_THREADS - 1) / TH_THREADS));
+    k_theta_apply<<<grid, TH_THREADS, 0, st>>>(n, k, lsk, theta_nnz(k), seed, Yt, ldy, S, lds);
 }
 
 }  // namespace rr

@@ -182,6 +182,39 @@ def test_dense_matvec(dense_small, prec):
     assert np.linalg.norm(y - ref) <= tol * np.linalg.norm(ref)
 
 
+@pytest.mark.parametrize("n,k", [(3000, 40), (257, 5), (5000, 300), (70, 1), (200, 200)])
+def test_theta_apply_matches_oracle_bitwise(n, k):
+    """S = Theta Y: each entry sums its hits in increasing column order of Theta,
+    as the oracle's CSR product does, and every term is +-Y exactly, so S agrees
+    bit for bit; with Y = I the result is Theta itself."""
+    Y = np.random.default_rng(n + k).standard_normal((n, k))
+    S = rr.theta_apply(7, _cuda(Y)).cpu().numpy()
+    assert np.array_equal(S, np.asarray(orng.theta(7, n, k) @ Y))
+    if n == k:
+        St = rr.theta_apply(7, _cuda(np.eye(n))).cpu().numpy()
+        assert np.array_equal(St, orng.theta(7, n, n).toarray())
+
+
+def test_sketched_cholqr_on_an_ill_conditioned_sketch():
+    """Alg. prec_chol_qr keeps Q orthonormal to rounding when cond(Y) ~ 1e10, where
+    Cholesky QR of Y^T Y would lose all orthogonality: the sparse Theta must embed
+    range(Y) well for R_sk to precondition W = Y R_sk^{-1}."""
+    n, l = 600, 48
+    g = np.random.default_rng(3)
+    U, _ = np.linalg.qr(g.standard_normal((n, n)))
+    lam = np.concatenate([np.logspace(0, -11, l), np.full(n - l, 1e-12)])
+    A = (U * lam) @ U.T
+    A = 0.5 * (A + A.T)
+    P = rr.build_precond(rr.dense_operator(_cuda(A)), [1e-12], l=l, sketch="gaussian", seed=5,
+                         prec="fp64")
+    e = P.export(0)
+    Q, R = e["Q"], e["R"]
+    Y = A @ orng.gaussian_matrix(5, n, l) + 1e-12 * orng.gaussian_matrix(5, n, l)
+    assert np.linalg.cond(Y) > 1e10
+    assert np.abs(Q.T @ Q - np.eye(l)).max() < 1e-12
+    assert np.linalg.norm(Q @ R - Y) < 1e-12 * np.linalg.norm(Y)
+
+
 @pytest.mark.parametrize("orth", ["sketched", "cholqr"])
 @pytest.mark.parametrize("tau_rule", ["opt", "rho", "nys"])
 def test_build_fp64_matches_oracle(dense_small, orth, tau_rule):
@@ -439,7 +472,8 @@ def test_batched_multi_shift_matches_single_and_oracle(prec):
         rel64 = osol.relres(op.shifted(mu), X[:, c], B[:, c])
         assert abs(infos[c]["relres_fp64"] - rel64) <= 1e-6 * rel64 + 1e-14
         x1, i1 = P.solve(_cuda(B[:, c]), mu_index=j, tol=tol)
-        assert abs(i1["iters"] - infos[c]["iters"]) <= 2
+        # rounding order differs (GEMM vs GEMV projections): counts within max(3, 3%)
+        assert abs(i1["iters"] - infos[c]["iters"]) <= max(3, int(0.03 * infos[c]["iters"]))
         if prec == "fp64":
             assert rel64 <= tol * 1.0001
         else:
