@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstddef>
+#include <cstdint>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -37,6 +39,51 @@ static void keep_pool_memory() {
     done.push_back(dev);
 }
 
+// On top of the pool, freed blocks are kept per (device, stream) and handed back
+// to later requests on the same stream that they fit (at most 1/4 larger), so a
+// build or a solve that repeats an earlier one's shapes makes no allocator call
+// at all: pool calls right after a host synchronisation were measured at up to a
+// millisecond each.  Reuse on the same stream is ordered after every earlier use.
+// Each stream's cache holds at most kStreamCacheCap bytes (oldest blocks go back
+// to the pool first); a failed pool allocation returns every cached block and
+// retries once.
+namespace {
+struct CachedBlock {
+    void* p;
+    size_t bytes;
+};
+struct StreamCache {
+    int dev;
+    hipStream_t st;
+    std::vector<CachedBlock> blocks;   // oldest first
+    size_t total = 0;
+};
+constexpr size_t kStreamCacheCap = (size_t)4 << 30;
+std::mutex g_cache_mu;
+std::vector<StreamCache> g_caches;
+std::vector<CachedBlock> g_live;   // blocks handed out by Alloc::get (pointer, size)
+
+StreamCache& cache_for(int dev, hipStream_t st) {
+    for (auto& c : g_caches)
+        if (c.dev == dev && c.st == st) return c;
+    g_caches.push_back(StreamCache{dev, st, {}, 0});
+    return g_caches.back();
+}
+
+size_t round_block(size_t bytes) {
+    const size_t g = bytes >= ((size_t)1 << 20) ? ((size_t)1 << 20) : 256;
+    return (bytes + g - 1) / g * g;
+}
+
+void flush_all_caches() {   // caller holds g_cache_mu
+    for (auto& c : g_caches) {
+        for (auto& b : c.blocks) (void)hipFreeAsync(b.p, c.st);
+        c.blocks.clear();
+        c.total = 0;
+    }
+}
+}  // namespace
+
 void* Alloc::get(size_t bytes) const {
     void* p = nullptr;
     if (custom) {
@@ -45,18 +92,66 @@ void* Alloc::get(size_t bytes) const {
         return p;
     }
     keep_pool_memory();
-    const hipError_t e = hipMallocAsync(&p, bytes, st);
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    const size_t want = round_block(bytes);
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    StreamCache& c = cache_for(dev, st);
+    size_t best = SIZE_MAX, bi = 0;
+    for (size_t i = 0; i < c.blocks.size(); ++i) {
+        const size_t b = c.blocks[i].bytes;
+        if (b >= want && b - want <= want / 4 && b < best) { best = b; bi = i; }
+    }
+    if (best != SIZE_MAX) {
+        const CachedBlock blk = c.blocks[bi];
+        c.blocks.erase(c.blocks.begin() + (std::ptrdiff_t)bi);
+        c.total -= blk.bytes;
+        g_live.push_back(blk);
+        return blk.p;
+    }
+    hipError_t e = hipMallocAsync(&p, want, st);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        flush_all_caches();
+        e = hipMallocAsync(&p, want, st);
+    }
     if (e != hipSuccess) {
         (void)hipGetLastError();
         throw RrError{RR_ENOMEM, "hipMallocAsync(" + std::to_string(bytes) + ") failed: " + hipGetErrorString(e)};
     }
+    g_live.push_back(CachedBlock{p, want});
     return p;
 }
 
 void Alloc::put(void* p) const {
     if (!p) return;
-    if (custom) a.free(a.ctx, p, (void*)st);
-    else (void)hipFreeAsync(p, st);
+    if (custom) {
+        a.free(a.ctx, p, (void*)st);
+        return;
+    }
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    size_t bytes = 0;
+    for (size_t i = g_live.size(); i-- > 0;)
+        if (g_live[i].p == p) {
+            bytes = g_live[i].bytes;
+            g_live[i] = g_live.back();
+            g_live.pop_back();
+            break;
+        }
+    if (bytes == 0) {   // not from Alloc::get: give it straight back
+        (void)hipFreeAsync(p, st);
+        return;
+    }
+    StreamCache& c = cache_for(dev, st);
+    c.blocks.push_back(CachedBlock{p, bytes});
+    c.total += bytes;
+    while (c.total > kStreamCacheCap && !c.blocks.empty()) {
+        (void)hipFreeAsync(c.blocks.front().p, st);
+        c.total -= c.blocks.front().bytes;
+        c.blocks.erase(c.blocks.begin());
+    }
 }
 
 KernelOp kernel_op_of(const rr_precond& P) {
@@ -139,8 +234,7 @@ void apply_projected_pair(const rr_precond& P, const double* K0, const double* K
                           double* rz_part, hipStream_t st) {
     const int nch = gemv_t_chunks(P.n, P.kb);
     launch_gemv_t_multi(2, P.n, P.kb, P.Qb.as<double>(), P.n, R, P.n, c_part, nch, nullptr, st);
-    launch_core_apply(P.kb, K0, P.kb, c_part, nch, d, nullptr, st);
-    launch_core_apply(P.kb, K1, P.kb, c_part + (size_t)nch * P.kb, nch, d + P.kb, nullptr, st);
+    launch_core_apply_pair(P.kb, K0, K1, P.kb, c_part, nch, d, nullptr, st);
     launch_qd_multi(2, P.n, P.kb, P.Qb.as<double>(), P.n, d, R, P.n, rc0, rc1, Z, rz_part, nullptr, st);
 }
 

@@ -53,6 +53,13 @@ struct Builder {
         launch_gemm(dta, ta, dtb, tb, M, N, K, A, lda, B, ldb, C, ldc, alpha, beta, gws.as<double>(),
                     gwsd, st);
     }
+    // C = A^T A (A: K x M float64): symmetric MFMA product, else the general GEMM
+    void gram(int64_t M, int64_t K, const double* A, int64_t lda, double* C, int64_t ldc) {
+        if (!launch_gemm_ata(M, K, A, lda, C, ldc, gws.as<double>(), gwsd, st)) {
+            gemm(DT_F64, true, DT_F64, false, M, M, K, A, lda, A, lda, C, ldc);
+            launch_symmetrize(C, M, ldc, st);
+        }
+    }
     DBuf mat(int64_t rows, int64_t cols, size_t esz = sizeof(double)) {
         return DBuf(al, (size_t)rows * cols * esz);
     }
@@ -182,8 +189,7 @@ struct Builder {
             DBuf W = mat(n, k);
             gemm(DT_F64, true, DT_F64, false, n, k, k, yt, k, Rskinv.ptr(), k, W.as<double>(), n);
             DBuf GW = mat(k, k);
-            gemm(DT_F64, true, DT_F64, false, k, k, n, W.ptr(), n, W.ptr(), n, GW.as<double>(), k);
-            launch_symmetrize(GW.as<double>(), k, k, st);
+            gram(k, n, W.as<double>(), n, GW.as<double>(), k);
             chol_ladder(GW.as<double>(), k);            // GW <- R_chol
             DBuf Rcinv = mat(k, k);
             launch_tri_inv_upper(GW.as<double>(), k, k, Rcinv.as<double>(), k, st);
@@ -429,8 +435,7 @@ extern "C" rr_status rr_build_precond(const rr_operator* A, const double* mus, i
             pm.G.reset(al, (size_t)l * l * sizeof(double));
             B.core_G(C.as<double>(), pm.R.as<double>(), pm.G.as<double>(), l);
             pm.T.reset(al, (size_t)l * l * sizeof(double));
-            B.gemm(DT_F64, true, DT_F64, false, l, l, n, P.Qb.ptr(), n, P.Qb.ptr(), n, pm.T.as<double>(), l);
-            launch_symmetrize(pm.T.as<double>(), l, l, st);
+            B.gram(l, n, P.Qb.as<double>(), n, pm.T.as<double>(), l);
             P.orth_err = B.orth_error(pm.T.as<double>(), l);
             launch_two_minus(pm.T.as<double>(), l, l, st);
             DBuf TG = B.mat(l, l), TGT = B.mat(l, l), negT = B.mat(l, l);
@@ -460,9 +465,8 @@ extern "C" rr_status rr_build_precond(const rr_operator* A, const double* mus, i
             B.gemm(DT_F64, true, P.omega_dt, false, k2, l, n, Qj, n, P.Omega.ptr(), n, Oj.as<double>(), k2);
             B.gemm(P.omega_dt, true, ydt, false, l, l, n, P.Omega.ptr(), n, Y0.ptr(), n, OAO.as<double>(), l);
             B.gemm(P.omega_dt, true, P.omega_dt, false, l, l, n, P.Omega.ptr(), n, P.Omega.ptr(), n, OO.as<double>(), l);
-            B.gemm(DT_F64, true, DT_F64, false, k2, k2, n, Qj, n, Qj, n, QQ.as<double>(), k2);
+            B.gram(k2, n, Qj, n, QQ.as<double>(), k2);
             Y0.release();
-            launch_symmetrize(QQ.as<double>(), k2, k2, st);
             P.orth_err = B.orth_error(QQ.as<double>(), k2);
             const size_t hwd = std::max<size_t>((size_t)k2 * l + l + 16, householder_ws_doubles(k2, l));
             DBuf hws(al, hwd * sizeof(double));

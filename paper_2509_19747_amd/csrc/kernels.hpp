@@ -62,6 +62,11 @@ void launch_gemm(int dta, bool trA, int dtb, bool trB, int64_t M, int64_t N, int
 
 // The same on float64 MFMA for float64/float32 operands with M, N >= 32 (returns
 // false, doing nothing, otherwise); launch_gemm tries it first.
+// C (M x M) = A^T A for float64 A (K x M, column-major): only the tiles on and
+// above the diagonal are multiplied, then mirrored, so C is exactly symmetric.
+// Returns false (nothing launched) when the MFMA path does not apply (M < 32 or K < 16).
+bool launch_gemm_ata(int64_t M, int64_t K, const double* A, int64_t lda, double* C, int64_t ldc,
+                     double* ws, size_t wsd, hipStream_t st);
 bool launch_gemm_mfma(int dta, bool trA, int dtb, bool trB, int64_t M, int64_t N, int64_t K,
                       const void* A, int64_t lda, const void* B, int64_t ldb, double* C,
                       int64_t ldc, double alpha, double beta, double* ws, size_t wsd,
@@ -216,6 +221,11 @@ void launch_gemv_t_multi(int nr, int64_t n, int64_t k, const double* Q, int64_t 
 // d = Kc * c with c = sum over chunks of c_part (Kc symmetric k x k).
 void launch_core_apply(int64_t k, const double* Kc, int64_t ldk, const double* c_part,
                        int nchunks, double* d, const int32_t* stop, hipStream_t st);
+// The same for a pair of columns: d[0:k] from K0 and c_part[0 : nchunks*k],
+// d[k:2k] from K1 and c_part[nchunks*k : 2*nchunks*k] (one launch).
+void launch_core_apply_pair(int64_t k, const double* K0, const double* K1, int64_t ldk,
+                            const double* c_part, int nchunks, double* d, const int32_t* stop,
+                            hipStream_t st);
 // z = rcoef*r + Q d, and per-block partials of r^T z.
 int qd_blocks(int64_t n);
 void launch_qd(int64_t n, int64_t k, const double* Q, int64_t ldq, const double* d,

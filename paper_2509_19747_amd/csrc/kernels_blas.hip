@@ -534,48 +534,65 @@ void launch_gemv_t(int64_t n, int64_t k, const double* Q, int64_t ldq, const dou
 }
 
 // d_i = sum_j Kc[j, i] c_j with c_j = sum_ch c_part[ch*k + j] (Kc symmetric).
+// blockIdx.y = column q of a pair (core K0 or K1, its own c_part and d slices).
+// Each thread finishes the c_j of its own j (partials added in chunk order) and
+// uses them at once, so the block needs no staging barrier.
 constexpr int CA_ROWS = 4;
-__global__ __launch_bounds__(256) void k_core_apply(int64_t k, const double* __restrict__ Kc,
-                                                    int64_t ldk, const double* __restrict__ c_part,
-                                                    int nchunks, double* __restrict__ d,
+__global__ __launch_bounds__(256) void k_core_apply(int64_t k, const double* __restrict__ K0,
+                                                    const double* __restrict__ K1, int64_t ldk,
+                                                    const double* __restrict__ c_part, int nchunks,
+                                                    double* __restrict__ d,
                                                     const int32_t* __restrict__ stop) {
-    extern __shared__ double c_sh[];
-    __shared__ double red[CA_ROWS][4];
+    __shared__ double red[CA_ROWS][256 / WAVE];
     if (stop && *stop) return;
-    for (int64_t j = threadIdx.x; j < k; j += blockDim.x) {
-        double s = 0.0;
-        for (int ch = 0; ch < nchunks; ++ch) s += c_part[(int64_t)ch * k + j];
-        c_sh[j] = s;
-    }
-    __syncthreads();
+    const int q = blockIdx.y;
+    const double* __restrict__ Kc = q ? K1 : K0;
+    const double* __restrict__ cp = c_part + (int64_t)q * nchunks * k;
     const int64_t i0 = (int64_t)blockIdx.x * CA_ROWS;
     double acc[CA_ROWS];
 #pragma unroll
-    for (int q = 0; q < CA_ROWS; ++q) acc[q] = 0.0;
+    for (int r = 0; r < CA_ROWS; ++r) acc[r] = 0.0;
     for (int64_t j = threadIdx.x; j < k; j += blockDim.x) {
-        const double cj = c_sh[j];
+        double kv[CA_ROWS];
 #pragma unroll
-        for (int q = 0; q < CA_ROWS; ++q)
-            if (i0 + q < k) acc[q] = fma(Kc[j + (i0 + q) * ldk], cj, acc[q]);
+        for (int r = 0; r < CA_ROWS; ++r) kv[r] = (i0 + r < k) ? Kc[j + (i0 + r) * ldk] : 0.0;
+        double cj = 0.0;
+        int ch = 0;
+        for (; ch + 4 <= nchunks; ch += 4) {
+            double v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) v[u] = cp[(int64_t)(ch + u) * k + j];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) cj += v[u];
+        }
+        for (; ch < nchunks; ++ch) cj += cp[(int64_t)ch * k + j];
+#pragma unroll
+        for (int r = 0; r < CA_ROWS; ++r) acc[r] = fma(kv[r], cj, acc[r]);
     }
     const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
 #pragma unroll
-    for (int q = 0; q < CA_ROWS; ++q) {
-        const double s = wave_sum(acc[q]);
-        if (lane == 0) red[q][w] = s;
+    for (int r = 0; r < CA_ROWS; ++r) {
+        const double s = wave_sum(acc[r]);
+        if (lane == 0) red[r][w] = s;
     }
     __syncthreads();
     if (threadIdx.x < CA_ROWS && i0 + threadIdx.x < k) {
         double s = 0.0;
-        for (int q = 0; q < 4; ++q) s += red[threadIdx.x][q];
-        d[i0 + threadIdx.x] = s;
+        for (int w2 = 0; w2 < 256 / WAVE; ++w2) s += red[threadIdx.x][w2];
+        d[(int64_t)q * k + i0 + threadIdx.x] = s;
     }
 }
 
 void launch_core_apply(int64_t k, const double* Kc, int64_t ldk, const double* c_part,
                        int nchunks, double* d, const int32_t* stop, hipStream_t st) {
     const int g = (int)((k + CA_ROWS - 1) / CA_ROWS);
-    k_core_apply<<<g, 256, (size_t)k * sizeof(double), st>>>(k, Kc, ldk, c_part, nchunks, d, stop);
+    k_core_apply<<<dim3(g, 1), 256, 0, st>>>(k, Kc, Kc, ldk, c_part, nchunks, d, stop);
+}
+void launch_core_apply_pair(int64_t k, const double* K0, const double* K1, int64_t ldk,
+                            const double* c_part, int nchunks, double* d, const int32_t* stop,
+                            hipStream_t st) {
+    const int g = (int)((k + CA_ROWS - 1) / CA_ROWS);
+    k_core_apply<<<dim3(g, 2), 256, 0, st>>>(k, K0, K1, ldk, c_part, nchunks, d, stop);
 }
 
 // Z[i, q] = rcoef_q R[i, q] + sum_j Q[i, j] D[j, q]; partial sums of R[i, q] Z[i, q]

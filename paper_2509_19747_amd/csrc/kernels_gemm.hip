@@ -49,21 +49,40 @@ RR_DEV void gm_store(double (*S)[GM_BM + GM_PAD], int t, const double (&v)[GM_EL
     }
 }
 
-template <typename TA, typename TB, bool TRA, bool TRB>
+template <typename TA, typename TB, bool TRA, bool TRB, bool SYM = false>
 __global__ __launch_bounds__(GM_THREADS) void k_gemm_mfma(int64_t M, int64_t N, int64_t K,
                                                           const TA* __restrict__ A, int64_t lda,
                                                           const TB* __restrict__ B, int64_t ldb,
                                                           double* __restrict__ C, int64_t ldc,
                                                           double alpha, double beta, int64_t kchunk,
-                                                          double* __restrict__ part) {
+                                                          double* __restrict__ part, int64_t gn,
+                                                          int64_t ntiles, int64_t nwork, int64_t per_xcd) {
     __shared__ double As[GM_BK][GM_BM + GM_PAD];
     __shared__ double Bs[GM_BK][GM_BN + GM_PAD];
+    // XCD-aware order: workgroups go to the 8 XCDs round robin, so block b runs on
+    // XCD b % 8; each XCD takes one contiguous range of (slice, tile) indices, and
+    // tiles that share an A row slab (and, split over K, the same K slice) meet in
+    // one L2.  Tile t = bx * gn + by (bx <= by only, enumerated by rows of the upper
+    // triangle, for a symmetric product).
+    const int64_t L = (int64_t)(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+    if (L >= nwork) return;   // padding of the grid to a multiple of 8
+    const int64_t bz = L / ntiles, tile = L % ntiles;
+    int64_t bx, by;
+    if (SYM) {
+        by = (int64_t)((sqrt(8.0 * (double)tile + 1.0) - 1.0) * 0.5);
+        while (by * (by + 1) / 2 > tile) --by;
+        while ((by + 1) * (by + 2) / 2 <= tile) ++by;
+        bx = tile - by * (by + 1) / 2;
+    } else {
+        bx = tile / gn;
+        by = tile % gn;
+    }
     const int t = threadIdx.x;
     const int lane = t & 63, wave = t >> 6;
     const int wm = wave & 1, wn = wave >> 1;
-    const int64_t i0 = (int64_t)blockIdx.x * GM_BM;
-    const int64_t j0 = (int64_t)blockIdx.y * GM_BN;
-    const int64_t kb = (int64_t)blockIdx.z * kchunk;
+    const int64_t i0 = bx * GM_BM;
+    const int64_t j0 = by * GM_BN;
+    const int64_t kb = bz * kchunk;
     const int64_t ke = std::min<int64_t>(kb + kchunk, K);
 
     f64x4_t acc[2][2];
@@ -112,7 +131,7 @@ __global__ __launch_bounds__(GM_THREADS) void k_gemm_mfma(int64_t M, int64_t N, 
                 const int64_t gi = i0 + wm * 32 + u * 16 + 4 * e + (lane >> 4);
                 if (gi >= M) continue;
                 if (part) {
-                    part[(int64_t)blockIdx.z * M * N + gi + gj * M] = acc[u][v][e];
+                    part[bz * M * N + gi + gj * M] = acc[u][v][e];
                 } else {
                     double o = alpha * acc[u][v][e];
                     if (beta != 0.0) o = fma(beta, C[gi + gj * ldc], o);
@@ -137,30 +156,46 @@ __global__ void k_gemm_mfma_reduce(int64_t M, int64_t N, int splits, const doubl
     }
 }
 
-template <typename TA, typename TB, bool TRA, bool TRB>
+template <typename TA, typename TB, bool TRA, bool TRB, bool SYM = false>
 static void gm_run(int64_t M, int64_t N, int64_t K, const void* A, int64_t lda, const void* B,
                    int64_t ldb, double* C, int64_t ldc, double alpha, double beta, double* ws,
                    size_t wsd, hipStream_t st) {
     const int64_t gm = (M + GM_BM - 1) / GM_BM, gn = (N + GM_BN - 1) / GM_BN;
     const int64_t kblocks = (K + GM_BK - 1) / GM_BK;
+    const int64_t tiles = SYM ? gm * (gm + 1) / 2 : gm * gn;   // tiles that do work
     int64_t splits = 1;
     const int64_t target = 1024;   // four blocks per compute unit
-    if (gm * gn < target && kblocks >= 16) {
-        splits = std::min<int64_t>((target + gm * gn - 1) / (gm * gn), kblocks / 8);
+    if (tiles < target && kblocks >= 16) {
+        splits = std::min<int64_t>((target + tiles - 1) / tiles, kblocks / 8);
         splits = std::min<int64_t>(splits, 64);
         while (splits > 1 && (size_t)(splits * M * N) > wsd) --splits;
         splits = std::max<int64_t>(splits, 1);
     }
     const int64_t kchunk = ((kblocks + splits - 1) / splits) * GM_BK;
     splits = (K + kchunk - 1) / kchunk;
-    dim3 grid((unsigned)gm, (unsigned)gn, (unsigned)splits);
+    // one launch dimension (padded to a multiple of 8) carries (slice, tile)
+    const int64_t work = tiles * splits;
+    const int64_t per_xcd = (work + 7) / 8;
+    dim3 grid((unsigned)(per_xcd * 8));
     double* part = splits > 1 ? ws : nullptr;
-    k_gemm_mfma<TA, TB, TRA, TRB><<<grid, GM_THREADS, 0, st>>>(M, N, K, (const TA*)A, lda,
+    k_gemm_mfma<TA, TB, TRA, TRB, SYM><<<grid, GM_THREADS, 0, st>>>(M, N, K, (const TA*)A, lda,
                                                                (const TB*)B, ldb, C, ldc, alpha,
-                                                               beta, kchunk, part);
+                                                               beta, kchunk, part, gn, tiles, work,
+                                                               per_xcd);
     if (part) {
         const int64_t g = std::min<int64_t>((M * N + 255) / 256, 16384);
         k_gemm_mfma_reduce<<<(unsigned)g, 256, 0, st>>>(M, N, (int)splits, part, C, ldc, alpha, beta);
+    }
+}
+
+// C[i, j] = C[j, i] for i > j: completes a product whose tiles on and above the
+// diagonal were formed.
+__global__ void k_mirror_upper(int64_t M, double* __restrict__ C, int64_t ldc) {
+    const int64_t total = M * M;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = e % M, j = e / M;
+        if (i > j) C[i + j * ldc] = C[j + i * ldc];
     }
 }
 
@@ -172,6 +207,15 @@ static void gm_tr(bool trA, bool trB, int64_t M, int64_t N, int64_t K, const voi
     else if (!trA && trB) gm_run<TA, TB, false, true>(M, N, K, A, lda, B, ldb, C, ldc, alpha, beta, ws, wsd, st);
     else if (trA && !trB) gm_run<TA, TB, true, false>(M, N, K, A, lda, B, ldb, C, ldc, alpha, beta, ws, wsd, st);
     else gm_run<TA, TB, true, true>(M, N, K, A, lda, B, ldb, C, ldc, alpha, beta, ws, wsd, st);
+}
+
+bool launch_gemm_ata(int64_t M, int64_t K, const double* A, int64_t lda, double* C, int64_t ldc,
+                     double* ws, size_t wsd, hipStream_t st) {
+    if (M < 32 || K < 16) return false;
+    gm_run<double, double, true, false, true>(M, M, K, A, lda, A, lda, C, ldc, 1.0, 0.0, ws, wsd, st);
+    const int64_t g = std::min<int64_t>((M * M + 255) / 256, 16384);
+    k_mirror_upper<<<(unsigned)g, 256, 0, st>>>(M, C, ldc);
+    return true;
 }
 
 bool launch_gemm_mfma(int dta, bool trA, int dtb, bool trB, int64_t M, int64_t N, int64_t K,
