@@ -102,6 +102,7 @@ struct Builder {
     // entries are rounded once) so the bf16 MFMA sketch sees the test matrix
     // exactly; P.Omega then holds the same values in float32.
     DBuf ob_buf;
+    DBuf srht_rows, srht_dbits;   // SRHT descriptor (sampled rows, sign bits of D)
     void make_omega() {
         const int64_t n = P.n, l = P.l;
         const rr_build_opts& o = P.opts;
@@ -125,10 +126,14 @@ struct Builder {
         } else {
             int64_t s = 1;
             while (s < n) s *= 2;
-            DBuf perm(al, (size_t)s * sizeof(int32_t)), rows(al, (size_t)l * sizeof(int32_t)),
-                D(al, (size_t)n * sizeof(float));
-            launch_srht_prepare(n, l, o.seed, s, perm.as<int32_t>(), rows.as<int32_t>(), D.as<float>(), st);
-            launch_srht_fill(gen, gdt, n, l, gld, D.as<float>(), rows.as<int32_t>(), st);
+            DBuf perm(al, (size_t)s * sizeof(int32_t)), D(al, (size_t)n * sizeof(float));
+            srht_rows.reset(al, (size_t)l * sizeof(int32_t));
+            launch_srht_prepare(n, l, o.seed, s, perm.as<int32_t>(), srht_rows.as<int32_t>(), D.as<float>(), st);
+            launch_srht_fill(gen, gdt, n, l, gld, D.as<float>(), srht_rows.as<int32_t>(), st);
+            if (kernel && f32path) {   // the kernel sketch generates this Omega itself
+                srht_dbits.reset(al, (size_t)((n + 31) / 32) * sizeof(uint32_t));
+                launch_srht_dbits(n, D.as<float>(), srht_dbits.as<uint32_t>(), st);
+            }
         }
         if (bf16_omega) launch_copy_mat(DT_BF16, ob_buf.ptr(), ldo, P.omega_dt, P.Omega.ptr(), n, n, l, st);
         Ob = ob_buf.ptr();
@@ -142,7 +147,9 @@ struct Builder {
             const KernelOp k = kernel_op_of(P);
             if (ydt == DT_F32) {
                 DBuf ws(al, (kernel_sketch_ws_floats(n, l) + 1) * sizeof(float));
-                launch_kernel_gemm_bf16x2(k, Ob, ldo, l, mu, (float*)Y, n, ws.as<float>(), st);
+                launch_kernel_gemm_bf16x2(k, Ob, ldo, l, mu, (float*)Y, n, ws.as<float>(), st,
+                                          srht_dbits.ptr() ? srht_rows.as<int32_t>() : nullptr,
+                                          srht_dbits.as<uint32_t>());
             } else {
                 launch_kernel_gemm_f64(k, (const double*)Om, n, l, mu, (double*)Y, n, st);
             }

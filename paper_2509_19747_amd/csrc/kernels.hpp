@@ -38,6 +38,8 @@ void launch_srht_prepare(int64_t n, int64_t l, uint64_t seed, int64_t s, int32_t
                          int32_t* rows_out, float* D_out, hipStream_t st);
 void launch_srht_fill(void* out, int dtype, int64_t n, int64_t l, int64_t ld, const float* D,
                       const int32_t* rows, hipStream_t st);
+// dbits[w] bit b = 1 when D[32 w + b] < 0 (i < n), words ceil(n / 32).
+void launch_srht_dbits(int64_t n, const float* D, uint32_t* dbits, hipStream_t st);
 // S (2k x k, column-major, lds) = Theta Y for the sparse sign embedding of stream
 // `seed` (THETA_NNZ nonzeros per column, one per row block); Yt: Y row-major in
 // float64 (Yt[i * ldy + c], i < n, c < k).
@@ -172,8 +174,13 @@ void launch_kernel_to_dense(const KernelOp& op, void* out, int dtype, int64_t ld
 // Kernel-GEMM on BF16 MFMA with hi/lo-split kernel entries; B (n x m, ldb a
 // multiple of 8 and >= round8(n), rows [n, round8(n)) zero) holds bf16 values
 // (the test matrix, exact in bf16); Y float32.
+// srht_rows / srht_dbits (both or neither): Omega is the SRHT with these sampled
+// Hadamard rows (m) and sign bits of D (bit i%32 of word i/32, set for D_i = -1);
+// its B fragments are then generated in registers instead of read from Bbf16
+// (Bbf16 still supplies the mu * Omega term).
 void launch_kernel_gemm_bf16x2(const KernelOp& op, const void* Bbf16, int64_t ldb, int64_t m,
-                               double mu, float* Y, int64_t ldy, float* ws, hipStream_t st);
+                               double mu, float* Y, int64_t ldy, float* ws, hipStream_t st,
+                               const int32_t* srht_rows = nullptr, const uint32_t* srht_dbits = nullptr);
 // Workspace (floats) of launch_kernel_gemm_bf16x2 for n points and m columns (0: none).
 size_t kernel_sketch_ws_floats(int64_t n, int64_t m);
 // Same in float64 on the vector ALU (small problems / float64 mode).

@@ -10,7 +10,7 @@
 // rows 64*(w&1)..+63 and columns 128*((w>>1)&3)..+127 (2 x 4 MFMA tiles of
 // 32 x 32).  Per step of 32 points the block forms the 128 x 32 kernel tile and
 // stages the 32 x 512 slice of Omega in LDS (thread t: column t, loaded into
-// registers one step ahead).  The kernel tile is formed on the matrix cores too:
+// registers up to three steps ahead).  The kernel tile is formed on the matrix cores too:
 // waves 0-3 each form one 32 x 32 quarter as the product of augmented point
 // records (kmma.hpp: float32-class exponents from three-piece bf16 splits), then
 // exp2 and the hi/lo split on the vector ALU.  The records of the block's rows
@@ -51,7 +51,7 @@ struct Ks2Smem {
 };
 
 // Omega slice of one step: thread t owns column c0 + t and its 32 points, as
-// four 16-byte chunks (global loads into registers one step ahead; the LDS
+// four 16-byte chunks (global loads into registers ahead of use; the LDS
 // store of consecutive columns hits distinct banks).  B's rows [n, round8(n))
 // are zero, so a chunk is either inside the padded column or wholly past it.
 RR_DEV void ks2_load_b(const uint16_t* src, int64_t npad, int64_t k0, int cb, uint4 (&rb)[KS2_CPT]) {
@@ -98,18 +98,80 @@ RR_DEV void ks2_mfma(const Ks2Smem& sm, int buf, int lane, int rh, int cq, f32x1
             }
 }
 
+// SRHT Omega generated in registers (no Omega stream): Omega[i, c] = D_i (-1)^
+// popcount(i & s_c) for i < n, zero past n.  The 8 points base .. base+7 of a B
+// fragment (base a multiple of 8) share popcount(base & s_c); point base + t adds
+// popcount(t & s_c & 7), whose parities over t are the column's 8-bit Walsh mask.
+// The 8 signs then index a 256-entry LDS table of +-1 bf16 vectors.
+struct Ks2Gen {
+    uint32_t s[KS2_WC];    // sampled Hadamard row of each of the lane's column tiles
+    uint32_t w8[KS2_WC];   // Walsh mask of its low 3 bits
+};
+RR_DEV bf16x8_t ks2_gen_frag(const uint4* table, uint32_t s, uint32_t w8, int64_t base, uint32_t d8,
+                             int64_t n) {
+    const uint32_t par = (uint32_t)__popcll((unsigned long long)((uint64_t)base & (uint64_t)s)) & 1u;
+    const uint32_t sg = ((0u - par) & 0xFFu) ^ w8 ^ d8;
+    uint4 v = table[sg];
+    if (base + 8 > n) {   // last step only: zero the points past n
+        const int64_t valid = n - base;
+        uint32_t* w = &v.x;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint32_t lo = (2 * j < valid) ? 0x0000FFFFu : 0u;
+            const uint32_t hi = (2 * j + 1 < valid) ? 0xFFFF0000u : 0u;
+            w[j] &= lo | hi;
+        }
+    }
+    return __builtin_bit_cast(bf16x8_t, v);
+}
+
+// One step of MFMAs with generated B fragments (same order as ks2_mfma).  dw: the
+// 32 sign bits of D for the step's points (bit p: point k0 + p has D = -1).
+RR_DEV void ks2_mfma_gen(const Ks2Smem& sm, int buf, int lane, int rh, const uint4* table,
+                         const Ks2Gen& gq, int64_t k0, uint32_t dw, int64_t n,
+                         f32x16_t (&acc)[2][KS2_WC]) {
+    const int kq = 8 * (lane >> 5);
+    bf16x8_t ah[2][2], al[2][2], bv[2][KS2_WC];
+#pragma unroll
+    for (int kh = 0; kh < 2; ++kh) {
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int row = rh * 64 + u * 32 + (lane & 31);
+            ah[kh][u] = __builtin_bit_cast(bf16x8_t, *(const uint4*)&sm.a_hi[buf][row * KS2_AS + 16 * kh + kq]);
+            al[kh][u] = __builtin_bit_cast(bf16x8_t, *(const uint4*)&sm.a_lo[buf][row * KS2_AS + 16 * kh + kq]);
+        }
+        const int64_t base = k0 + 16 * kh + kq;
+        const uint32_t d8 = (dw >> (16 * kh + kq)) & 0xFFu;
+#pragma unroll
+        for (int v = 0; v < KS2_WC; ++v) bv[kh][v] = ks2_gen_frag(table, gq.s[v], gq.w8[v], base, d8, n);
+    }
+#pragma unroll
+    for (int kh = 0; kh < 2; ++kh)
+#pragma unroll
+        for (int v = 0; v < KS2_WC; ++v)
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                acc[u][v] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[kh][u], bv[kh][v], acc[u][v], 0, 0, 0);
+                acc[u][v] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[kh][u], bv[kh][v], acc[u][v], 0, 0, 0);
+            }
+}
+
 // part == nullptr: Y = scale * acc + mu * B.  Otherwise part[z] (n x m, leading
 // dimension n) = acc over the block's point range [z*kper, (z+1)*kper).
-template <int KIND, int DM>
+// GEN: Omega is an SRHT given by its sampled rows srow (m) and the sign bits dbits
+// of D (bit i%32 of word i/32), and B fragments are generated instead of loaded.
+template <int KIND, int DM, bool GEN>
 __global__ __launch_bounds__(KS2_THREADS) void k_ksketch_bf16x2(
     int64_t n, const float* __restrict__ xa, const float* __restrict__ sqn, float c, float scale,
     float mu, const uint16_t* __restrict__ Bm, int64_t ldb, int64_t m, float* __restrict__ Y,
-    int64_t ldy, int64_t kper, float* __restrict__ part) {
+    int64_t ldy, int64_t kper, float* __restrict__ part, const int32_t* __restrict__ srow,
+    const uint32_t* __restrict__ dbits) {
     constexpr int KB = KmmaShape<DM>::KB, NX = kmma_ncoord<DM>();
     // column-form records of the block's rows: in LDS, or for long records (which
     // would not fit beside the tiles) in the forming lanes' registers
     constexpr bool RREG = DM > 16;
     __shared__ __attribute__((aligned(16))) Ks2Smem sm;
+    __shared__ uint4 gtable[GEN ? 256 : 1];
     __shared__ bf16x8_t rowrec[RREG ? 1 : KS2_BM * KB * 2];
     bf16x8_t rowreg[RREG ? KB : 1];
     const int t = threadIdx.x;
@@ -180,21 +242,61 @@ __global__ __launch_bounds__(KS2_THREADS) void k_ksketch_bf16x2(
     const int bcol = t / (4 / KS2_CPT), bcb = (t % (4 / KS2_CPT)) * KS2_CPT;
     const uint16_t* bsrc = (c0 + bcol < m) ? Bm + (c0 + bcol) * ldb : nullptr;
     const int64_t npad = (n + 7) & ~(int64_t)7;   // B rows [n, npad) hold zeros
-    uint4 rb[KS2_CPT];
+    if constexpr (GEN) {
+        // sign table: entry e = the 8 bf16 values (-1 where bit t of e is set, else +1)
+        if (t < 256) {
+            uint32_t w[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                w[j] = (((uint32_t)t >> (2 * j)) & 1u ? 0xBF80u : 0x3F80u) |
+                       ((((uint32_t)t >> (2 * j + 1)) & 1u ? 0xBF80u : 0x3F80u) << 16);
+            gtable[t] = make_uint4(w[0], w[1], w[2], w[3]);
+        }
+        Ks2Gen gq;
+#pragma unroll
+        for (int v = 0; v < KS2_WC; ++v) {
+            const int64_t gc = c0 + cq * 32 * KS2_WC + v * 32 + (lane & 31);
+            const uint32_t sv = gc < m ? (uint32_t)srow[gc] : 0u;   // columns past m are not stored
+            uint32_t w8 = 0;
+#pragma unroll
+            for (int tt = 0; tt < 8; ++tt) w8 |= ((uint32_t)__popc((uint32_t)tt & sv) & 1u) << tt;
+            gq.s[v] = sv;
+            gq.w8[v] = w8;
+        }
+        __syncthreads();   // row records, sign table
+        if (kb < ke && former) form(kb, 0);
+        __syncthreads();
+        int buf = 0;
+        for (int64_t k0 = kb; k0 < ke; k0 += KS2_BK) {
+            const int64_t k1 = k0 + KS2_BK;
+            if (former && k1 < ke) form(k1, buf ^ 1);
+            ks2_mfma_gen(sm, buf, lane, rh, gtable, gq, k0, dbits[k0 >> 5], n, acc);
+            __syncthreads();
+            buf ^= 1;
+        }
+    } else {
+    // Omega slices in registers, two sets used by alternate steps: the slice that a
+    // step stores into LDS was loaded two steps earlier (three steps before its
+    // product MFMAs run), which covers the latency of these column-strided loads.
+    // Loads past the block's point range stay inside B (rows past round8(n) read
+    // as zeros).
+    uint4 rx[KS2_CPT], ry[KS2_CPT];
     __syncthreads();   // row records
     if (kb < ke) {
-        ks2_load_b(bsrc, npad, kb, bcb, rb);
-        ks2_store_b(sm, 0, bcol, bcb, rb);
+        ks2_load_b(bsrc, npad, kb, bcb, rx);
+        ks2_store_b(sm, 0, bcol, bcb, rx);
         if (former) form(kb, 0);
-        if (kb + KS2_BK < ke) ks2_load_b(bsrc, npad, kb + KS2_BK, bcb, rb);
+        ks2_load_b(bsrc, npad, kb + KS2_BK, bcb, rx);
+        ks2_load_b(bsrc, npad, kb + 2 * KS2_BK, bcb, ry);
     }
     __syncthreads();
     int buf = 0;
-    for (int64_t k0 = kb; k0 < ke; k0 += KS2_BK) {
-        const int64_t k1 = k0 + KS2_BK, k2 = k0 + 2 * KS2_BK;
+    // one step at kc: rb holds slice kc + 32, refilled with slice kc + 96
+    auto step = [&](int64_t kc, uint4 (&rb)[KS2_CPT]) {
+        const int64_t k1 = kc + KS2_BK;
         if (k1 < ke) {
             ks2_store_b(sm, buf ^ 1, bcol, bcb, rb);
-            if (k2 < ke) ks2_load_b(bsrc, npad, k2, bcb, rb);
+            ks2_load_b(bsrc, npad, kc + 3 * KS2_BK, bcb, rb);
         }
         // the forming wave of each SIMD builds the next tile while its partner's
         // product MFMAs run, then issues its own
@@ -202,6 +304,11 @@ __global__ __launch_bounds__(KS2_THREADS) void k_ksketch_bf16x2(
         ks2_mfma(sm, buf, lane, rh, cq, acc);
         __syncthreads();
         buf ^= 1;
+    };
+    for (int64_t k0 = kb; k0 < ke; k0 += 2 * KS2_BK) {
+        step(k0, rx);
+        if (k0 + KS2_BK < ke) step(k0 + KS2_BK, ry);
+    }
     }
     float* out = part ? part + (int64_t)blockIdx.z * ldy * m : Y;
 #pragma unroll
@@ -263,7 +370,8 @@ size_t kernel_sketch_ws_floats(int64_t n, int64_t m) {
 }
 
 void launch_kernel_gemm_bf16x2(const KernelOp& op, const void* Bbf16, int64_t ldb, int64_t m,
-                               double mu, float* Y, int64_t ldy, float* ws, hipStream_t st) {
+                               double mu, float* Y, int64_t ldy, float* ws, hipStream_t st,
+                               const int32_t* srht_rows, const uint32_t* srht_dbits) {
     const float c = kernel_c32(op.kind, op.kconst);
     const int ns = ks2_splits(op.n, m);
     const int64_t steps = (op.n + KS2_BK - 1) / KS2_BK;
@@ -274,7 +382,16 @@ void launch_kernel_gemm_bf16x2(const KernelOp& op, const void* Bbf16, int64_t ld
     const uint16_t* B = (const uint16_t*)Bbf16;
     const float sc = (float)op.scale, fmu = (float)mu;
     ProfScope prof(PROF_KERNEL_SKETCH, st);
-#define KS2L(K, DD) k_ksketch_bf16x2<K, DD><<<grid, KS2_THREADS, 0, st>>>(op.n, op.xa, op.sqn, c, sc, fmu, B, ldb, m, Y, ldy, kper, part)
+    const bool gen = srht_rows && srht_dbits;
+#define KS2L(K, DD)                                                                                    \
+    do {                                                                                               \
+        if (gen)                                                                                       \
+            k_ksketch_bf16x2<K, DD, true><<<grid, KS2_THREADS, 0, st>>>(op.n, op.xa, op.sqn, c, sc, fmu, B, \
+                ldb, m, Y, ldy, kper, part, srht_rows, srht_dbits);                                    \
+        else                                                                                           \
+            k_ksketch_bf16x2<K, DD, false><<<grid, KS2_THREADS, 0, st>>>(op.n, op.xa, op.sqn, c, sc, fmu, B, \
+                ldb, m, Y, ldy, kper, part, nullptr, nullptr);                                         \
+    } while (0)
 #define KS2D(K)                              \
     switch (op.dm) {                         \
         case 4: KS2L(K, 4); break;           \

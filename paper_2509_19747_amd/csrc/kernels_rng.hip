@@ -143,6 +143,19 @@ __global__ __launch_bounds__(TH_THREADS) void k_theta_apply(int64_t n, int64_t k
     if (c < k) S[r + c * lds] = acc;
 }
 
+__global__ void k_srht_dbits(int64_t n, const float* __restrict__ D, uint32_t* __restrict__ dbits) {
+    const int64_t words = (n + 31) / 32;
+    for (int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; w < words;
+         w += (int64_t)gridDim.x * blockDim.x) {
+        uint32_t b = 0;
+        for (int q = 0; q < 32; ++q) {
+            const int64_t i = 32 * w + q;
+            if (i < n && D[i] < 0.0f) b |= 1u << q;
+        }
+        dbits[w] = b;
+    }
+}
+
 static int grid_for(int64_t total, int block = 256) {
     int64_t g = (total + block - 1) / block;
     if (g > 65536) g = 65536;
@@ -184,6 +197,11 @@ void launch_theta_apply(int64_t n, int64_t k, uint64_t seed, const double* Yt, i
     const int64_t lsk = 2 * k;
     dim3 grid((unsigned)lsk, (unsigned)((k + TH_THREADS - 1) / TH_THREADS));
     k_theta_apply<<<grid, TH_THREADS, 0, st>>>(n, k, lsk, theta_nnz(k), seed, Yt, ldy, S, lds);
+}
+
+void launch_srht_dbits(int64_t n, const float* D, uint32_t* dbits, hipStream_t st) {
+    const int64_t words = (n + 31) / 32;
+    k_srht_dbits<<<grid_for(words), 256, 0, st>>>(n, D, dbits);
 }
 
 }  // namespace rr
