@@ -270,7 +270,8 @@ struct Builder {
         // two-column operator pass (every kernel entry evaluated once):
         //   ||E||: v <- (I-Pi) A_mu (I-Pi) v,   lam: v <- Pi A_mu Pi~ v.
         // They only estimate two scalars to a few digits, so a float32-mode
-        // kernel operator may add its products in float32 here.
+        // kernel operator may add its products in float32 here, and the
+        // projections may read the basis rounded to float32.
         DBuf U(al, 2 * n * sizeof(double)), Yv(al, 2 * n * sizeof(double));
         DBuf V(al, 2 * n * sizeof(double)), Wv(al, 2 * n * sizeof(double));
         const int nch = gemv_t_chunks(n, P.kb);
@@ -293,13 +294,21 @@ struct Builder {
         double* cp = cpart.as<double>();
         double* dd = d.as<double>();
         double* rzp = rz.as<double>();
+        // in float32 and mixed modes the projections of the estimates read a float32
+        // copy of the basis (half the traffic of the float64 one)
+        DBuf Q32;
+        if (P.opts.prec != RR_PREC_FP64) {
+            Q32.reset(al, (size_t)n * P.kb * sizeof(float));
+            launch_copy_mat(DT_F64, P.Qb.ptr(), n, DT_F32, Q32.ptr(), n, n, P.kb, st);
+        }
+        const float* q32 = Q32.as<float>();
         for (int it = 0; it < P.opts.power_iters; ++it) {
             // [(I-Pi) v0, Pi~ v1], A_mu on both, [(I-Pi) y0, Pi y1]; each pair of
             // projections reads Q once
-            apply_projected_pair(P, negT, TGT, v0, 1.0, 0.0, u0, cp, dd, rzp, st);
+            apply_projected_pair(P, negT, TGT, v0, 1.0, 0.0, u0, cp, dd, rzp, st, q32);
             apply_operator_multi(P, u0, 2, mu, y0, op_part.as<double>(), kws.as<double>(), false, st,
                                  true);
-            apply_projected_pair(P, negT, T, y0, 1.0, 0.0, w0, cp, dd, rzp, st);
+            apply_projected_pair(P, negT, T, y0, 1.0, 0.0, w0, cp, dd, rzp, st, q32);
             launch_dot_part(n, w0, w0, vparts.as<double>(), st);
             launch_normalize(n, v0, w0, vparts.as<double>(), vec_blocks(n), lam_dev + 0, st);
             launch_dot_part(n, w1, w1, vparts.as<double>(), st);

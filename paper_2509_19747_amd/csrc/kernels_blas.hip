@@ -434,9 +434,9 @@ void launch_dense_matvec(int dta, int64_t n, const void* A, int64_t lda, const d
 constexpr int GT_COLS = 4;
 constexpr int GT_THREADS = 256;
 
-template <int NR>
+template <int NR, typename TQ = double>
 __global__ __launch_bounds__(GT_THREADS) void k_gemv_t(int64_t n, int64_t k,
-                                                       const double* __restrict__ Q, int64_t ldq,
+                                                       const TQ* __restrict__ Q, int64_t ldq,
                                                        const double* __restrict__ R, int64_t ldr,
                                                        double* __restrict__ c_part, int nchunks,
                                                        int64_t rows_per_chunk,
@@ -463,7 +463,7 @@ __global__ __launch_bounds__(GT_THREADS) void k_gemv_t(int64_t n, int64_t k,
             for (int q = 0; q < NR; ++q) ri[h][q] = R[i + h * GT_THREADS + q * ldr];
 #pragma unroll
             for (int c = 0; c < GT_COLS; ++c)
-                qv[h][c] = c < ncol ? Q[i + h * GT_THREADS + (j0 + c) * ldq] : 0.0;
+                qv[h][c] = c < ncol ? (double)Q[i + h * GT_THREADS + (j0 + c) * ldq] : 0.0;
         }
 #pragma unroll
         for (int h = 0; h < 2; ++h)
@@ -479,7 +479,7 @@ __global__ __launch_bounds__(GT_THREADS) void k_gemv_t(int64_t n, int64_t k,
 #pragma unroll
         for (int c = 0; c < GT_COLS; ++c)
             if (c < ncol) {
-                const double qij = Q[i + (j0 + c) * ldq];
+                const double qij = (double)Q[i + (j0 + c) * ldq];
 #pragma unroll
                 for (int q = 0; q < NR; ++q) acc[c][q] = fma(qij, ri[q], acc[c][q]);
             }
@@ -527,6 +527,12 @@ void launch_gemv_t_multi(int nr, int64_t n, int64_t k, const double* Q, int64_t 
         k_gemv_t<2><<<grid, GT_THREADS, 0, st>>>(n, k, Q, ldq, R, ldr, c_part, nchunks, rpc, stop);
     else
         k_gemv_t<1><<<grid, GT_THREADS, 0, st>>>(n, k, Q, ldq, R, ldr, c_part, nchunks, rpc, stop);
+}
+void launch_gemv_t_pair_f32(int64_t n, int64_t k, const float* Q, int64_t ldq, const double* R,
+                            int64_t ldr, double* c_part, int nchunks, hipStream_t st) {
+    const int64_t rpc = gemv_t_rows_per_chunk(n, k);
+    dim3 grid((unsigned)((k + GT_COLS - 1) / GT_COLS), (unsigned)nchunks);
+    k_gemv_t<2, float><<<grid, GT_THREADS, 0, st>>>(n, k, Q, ldq, R, ldr, c_part, nchunks, rpc, nullptr);
 }
 void launch_gemv_t(int64_t n, int64_t k, const double* Q, int64_t ldq, const double* r,
                    double* c_part, int nchunks, const int32_t* stop, hipStream_t st) {
@@ -601,9 +607,9 @@ void launch_core_apply_pair(int64_t k, const double* K0, const double* K1, int64
 // their partial row sums in a fixed order.
 constexpr int QD_ROWS = 64;
 constexpr int QD_THREADS = 256;
-template <int NR>
+template <int NR, typename TQ = double>
 __global__ __launch_bounds__(QD_THREADS) void k_qd(int64_t n, int64_t k,
-                                                   const double* __restrict__ Q, int64_t ldq,
+                                                   const TQ* __restrict__ Q, int64_t ldq,
                                                    const double* __restrict__ D,
                                                    const double* __restrict__ R, int64_t ldr,
                                                    double rc0, double rc1,
@@ -623,19 +629,19 @@ __global__ __launch_bounds__(QD_THREADS) void k_qd(int64_t n, int64_t k,
 #pragma unroll
     for (int q = 0; q < NR; ++q) acc[q][0] = acc[q][1] = 0.0;
     if (i < n) {
-        const double* qi = Q + i;
+        const TQ* qi = Q + i;
         int64_t j = jb;
         for (; j + 8 <= je; j += 8) {
             double qv[8];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) qv[u] = qi[(j + u) * ldq];
+            for (int u = 0; u < 8; ++u) qv[u] = (double)qi[(j + u) * ldq];
 #pragma unroll
             for (int u = 0; u < 8; ++u)
 #pragma unroll
                 for (int q = 0; q < NR; ++q) acc[q][u & 1] = fma(qv[u], d_sh[q * k + j + u], acc[q][u & 1]);
         }
         for (; j < je; ++j) {
-            const double qv = qi[j * ldq];
+            const double qv = (double)qi[j * ldq];
 #pragma unroll
             for (int q = 0; q < NR; ++q) acc[q][0] = fma(qv, d_sh[q * k + j], acc[q][0]);
         }
@@ -670,6 +676,12 @@ void launch_qd_multi(int nr, int64_t n, int64_t k, const double* Q, int64_t ldq,
         k_qd<2><<<qd_blocks(n), QD_THREADS, shm, st>>>(n, k, Q, ldq, D, R, ldr, rc0, rc1, Z, rz_part, stop);
     else
         k_qd<1><<<qd_blocks(n), QD_THREADS, shm, st>>>(n, k, Q, ldq, D, R, ldr, rc0, rc1, Z, rz_part, stop);
+}
+void launch_qd_pair_f32(int64_t n, int64_t k, const float* Q, int64_t ldq, const double* D,
+                        const double* R, int64_t ldr, double rc0, double rc1, double* Z, double* rz_part,
+                        hipStream_t st) {
+    const size_t shm = (size_t)std::max<int64_t>(2 * k, 1) * sizeof(double);
+    k_qd<2, float><<<qd_blocks(n), QD_THREADS, shm, st>>>(n, k, Q, ldq, D, R, ldr, rc0, rc1, Z, rz_part, nullptr);
 }
 void launch_qd(int64_t n, int64_t k, const double* Q, int64_t ldq, const double* d,
                const double* r, double rcoef, double* z, double* rz_part, const int32_t* stop,

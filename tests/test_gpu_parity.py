@@ -306,6 +306,11 @@ def test_kernel_fp32_solve_with_srht():
     Pr = orr.build(op, [mu], prob.l, "srht", prob.omega_seed)[0]
     ref = osol.pcg(op.shifted(mu), Pr.apply, prob.b, prob.tol)
     assert abs(info["iters"] - ref.iters) <= max(3, int(0.1 * ref.iters))
+    # the tau estimates (float32 entries and sums, float32 copy of Q in their
+    # projections) agree with the float64 oracle to a few digits
+    g = P.export(0, with_q=False)
+    for key in ("normE", "lam", "tau"):
+        assert abs(g[key] - getattr(Pr, key)) < 1e-3 * getattr(Pr, key), (key, g[key], getattr(Pr, key))
     cg = rr.build_precond(kop, [mu], l=0, prec="fp32").solve(_cuda(prob.b), tol=prob.tol)[1]
     assert cg["iters"] > info["iters"]
 
