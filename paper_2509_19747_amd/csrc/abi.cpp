@@ -231,13 +231,11 @@ int apply_projected(const rr_precond& P, const double* Kc, const double* r, doub
 
 void apply_projected_pair(const rr_precond& P, const double* K0, const double* K1, const double* R,
                           double rc0, double rc1, double* Z, double* c_part, double* d,
-                          double* rz_part, hipStream_t st, const float* Q32) {
+                          double* rz_part, hipStream_t st) {
     const int nch = gemv_t_chunks(P.n, P.kb);
-    if (Q32) launch_gemv_t_pair_f32(P.n, P.kb, Q32, P.n, R, P.n, c_part, nch, st);
-    else launch_gemv_t_multi(2, P.n, P.kb, P.Qb.as<double>(), P.n, R, P.n, c_part, nch, nullptr, st);
+    launch_gemv_t_multi(2, P.n, P.kb, P.Qb.as<double>(), P.n, R, P.n, c_part, nch, nullptr, st);
     launch_core_apply_pair(P.kb, K0, K1, P.kb, c_part, nch, d, nullptr, st);
-    if (Q32) launch_qd_pair_f32(P.n, P.kb, Q32, P.n, d, R, P.n, rc0, rc1, Z, rz_part, st);
-    else launch_qd_multi(2, P.n, P.kb, P.Qb.as<double>(), P.n, d, R, P.n, rc0, rc1, Z, rz_part, nullptr, st);
+    launch_qd_multi(2, P.n, P.kb, P.Qb.as<double>(), P.n, d, R, P.n, rc0, rc1, Z, rz_part, nullptr, st);
 }
 
 rr_status validate_operator(const rr_operator* A) {

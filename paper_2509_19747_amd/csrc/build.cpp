@@ -270,8 +270,7 @@ struct Builder {
         // two-column operator pass (every kernel entry evaluated once):
         //   ||E||: v <- (I-Pi) A_mu (I-Pi) v,   lam: v <- Pi A_mu Pi~ v.
         // They only estimate two scalars to a few digits, so a float32-mode
-        // kernel operator may add its products in float32 here, and the
-        // projections may read the basis rounded to float32.
+        // kernel operator may add its products in float32 here.
         DBuf U(al, 2 * n * sizeof(double)), Yv(al, 2 * n * sizeof(double));
         DBuf V(al, 2 * n * sizeof(double)), Wv(al, 2 * n * sizeof(double));
         const int nch = gemv_t_chunks(n, P.kb);
@@ -294,21 +293,13 @@ struct Builder {
         double* cp = cpart.as<double>();
         double* dd = d.as<double>();
         double* rzp = rz.as<double>();
-        // in float32 and mixed modes the projections of the estimates read a float32
-        // copy of the basis (half the traffic of the float64 one)
-        DBuf Q32;
-        if (P.opts.prec != RR_PREC_FP64) {
-            Q32.reset(al, (size_t)n * P.kb * sizeof(float));
-            launch_copy_mat(DT_F64, P.Qb.ptr(), n, DT_F32, Q32.ptr(), n, n, P.kb, st);
-        }
-        const float* q32 = Q32.as<float>();
         for (int it = 0; it < P.opts.power_iters; ++it) {
             // [(I-Pi) v0, Pi~ v1], A_mu on both, [(I-Pi) y0, Pi y1]; each pair of
             // projections reads Q once
-            apply_projected_pair(P, negT, TGT, v0, 1.0, 0.0, u0, cp, dd, rzp, st, q32);
+            apply_projected_pair(P, negT, TGT, v0, 1.0, 0.0, u0, cp, dd, rzp, st);
             apply_operator_multi(P, u0, 2, mu, y0, op_part.as<double>(), kws.as<double>(), false, st,
                                  true);
-            apply_projected_pair(P, negT, T, y0, 1.0, 0.0, w0, cp, dd, rzp, st, q32);
+            apply_projected_pair(P, negT, T, y0, 1.0, 0.0, w0, cp, dd, rzp, st);
             launch_dot_part(n, w0, w0, vparts.as<double>(), st);
             launch_normalize(n, v0, w0, vparts.as<double>(), vec_blocks(n), lam_dev + 0, st);
             launch_dot_part(n, w1, w1, vparts.as<double>(), st);
@@ -342,12 +333,11 @@ struct Builder {
         launch_symmetrize(G, l, l, st);
     }
 
-    double orth_error(const double* QtQ, int64_t k) {
-        launch_max_abs_minus_identity(QtQ, k, k, scal.as<double>() + 2, st);
-        double e = 0.0;
-        RR_HIP(hipMemcpyAsync(&e, scal.as<double>() + 2, sizeof(double), hipMemcpyDeviceToHost, st));
-        sync();
-        return e;
+    // max |Q^T Q - I| into a device word; read after the build's final synchronisation
+    DBuf oerr;
+    void orth_error(const double* QtQ, int64_t k) {
+        if (!oerr.ptr()) oerr.reset(al, sizeof(double));
+        launch_max_abs_minus_identity(QtQ, k, k, oerr.as<double>(), st);
     }
 };
 
@@ -452,7 +442,7 @@ extern "C" rr_status rr_build_precond(const rr_operator* A, const double* mus, i
             B.core_G(C.as<double>(), pm.R.as<double>(), pm.G.as<double>(), l);
             pm.T.reset(al, (size_t)l * l * sizeof(double));
             B.gram(l, n, P.Qb.as<double>(), n, pm.T.as<double>(), l);
-            P.orth_err = B.orth_error(pm.T.as<double>(), l);
+            B.orth_error(pm.T.as<double>(), l);
             launch_two_minus(pm.T.as<double>(), l, l, st);
             DBuf TG = B.mat(l, l), TGT = B.mat(l, l), negT = B.mat(l, l);
             B.gemm(DT_F64, false, DT_F64, false, l, l, l, pm.T.ptr(), l, pm.G.ptr(), l, TG.as<double>(), l);
@@ -483,7 +473,7 @@ extern "C" rr_status rr_build_precond(const rr_operator* A, const double* mus, i
             B.gemm(P.omega_dt, true, P.omega_dt, false, l, l, n, P.Omega.ptr(), n, P.Omega.ptr(), n, OO.as<double>(), l);
             B.gram(k2, n, Qj, n, QQ.as<double>(), k2);
             Y0.release();
-            P.orth_err = B.orth_error(QQ.as<double>(), k2);
+            B.orth_error(QQ.as<double>(), k2);
             const size_t hwd = std::max<size_t>((size_t)k2 * l + l + 16, householder_ws_doubles(k2, l));
             DBuf hws(al, hwd * sizeof(double));
             for (int im = 0; im < n_mu; ++im) {
@@ -531,6 +521,8 @@ extern "C" rr_status rr_build_precond(const rr_operator* A, const double* mus, i
             }
         }
         RR_HIP(hipGetLastError());
+        if (B.oerr.ptr())
+            RR_HIP(hipMemcpyAsync(&P.orth_err, B.oerr.ptr(), sizeof(double), hipMemcpyDeviceToHost, st));
         RR_HIP(hipStreamSynchronize(st));
         P.ms_build = now_ms() - t0;
         *out = H.release();

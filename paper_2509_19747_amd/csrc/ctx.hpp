@@ -176,8 +176,7 @@ int apply_projected(const rr_precond& P, const double* Kc, const double* r, doub
 // d: 2 * kb, rz_part: 2 * qd_blocks(n).
 void apply_projected_pair(const rr_precond& P, const double* K0, const double* K1, const double* R,
                           double rc0, double rc1, double* Z, double* c_part, double* d,
-                          double* rz_part, hipStream_t st,
-                          const float* Q32 = nullptr);
+                          double* rz_part, hipStream_t st);
 
 rr_status validate_operator(const rr_operator* A);
 void require_device();

@@ -230,14 +230,6 @@ void launch_core_apply(int64_t k, const double* Kc, int64_t ldk, const double* c
                        int nchunks, double* d, const int32_t* stop, hipStream_t st);
 // The same for a pair of columns: d[0:k] from K0 and c_part[0 : nchunks*k],
 // d[k:2k] from K1 and c_part[nchunks*k : 2*nchunks*k] (one launch).
-// Pair (NR = 2) variants of launch_gemv_t_multi / launch_qd_multi reading a float32
-// copy of Q (values widened exactly, float64 arithmetic): half the HBM traffic,
-// for estimates that need only a few digits.
-void launch_gemv_t_pair_f32(int64_t n, int64_t k, const float* Q, int64_t ldq, const double* R,
-                            int64_t ldr, double* c_part, int nchunks, hipStream_t st);
-void launch_qd_pair_f32(int64_t n, int64_t k, const float* Q, int64_t ldq, const double* D,
-                        const double* R, int64_t ldr, double rc0, double rc1, double* Z, double* rz_part,
-                        hipStream_t st);
 void launch_core_apply_pair(int64_t k, const double* K0, const double* K1, int64_t ldk,
                             const double* c_part, int nchunks, double* d, const int32_t* stop,
                             hipStream_t st);

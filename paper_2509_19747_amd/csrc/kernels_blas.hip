@@ -311,25 +311,33 @@ void launch_scale_mat(double* A, int64_t lda, int64_t rows, int64_t cols, double
     k_scale_mat<<<clamp_grid((rows * cols + 255) / 256), 256, 0, st>>>(A, lda, rows, cols, s);
 }
 
-__global__ void k_max_abs_minus_identity(const double* M, int64_t l, int64_t ldm, double* out) {
-    __shared__ double sh[1024];
+// max |M - I| over an l x l matrix: blocks take columns, threads rows; each block
+// folds its maximum into *out with an integer atomicMax on the bit pattern (for
+// non-negative doubles it orders like the values, so the result is exact and
+// independent of the order).  *out is cleared first on the stream.
+__global__ __launch_bounds__(256) void k_max_abs_minus_identity(const double* __restrict__ M, int64_t l,
+                                                                int64_t ldm, unsigned long long* out) {
+    __shared__ double sh[256 / WAVE];
     double m = 0.0;
-    for (int64_t e = threadIdx.x; e < l * l; e += blockDim.x) {
-        const int64_t i = e % l, j = e / l;
-        const double v = fabs(M[i + j * ldm] - (i == j ? 1.0 : 0.0));
-        m = v > m ? v : m;
-    }
-    sh[threadIdx.x] = m;
+    for (int64_t j = blockIdx.x; j < l; j += gridDim.x)
+        for (int64_t i = threadIdx.x; i < l; i += blockDim.x) {
+            const double v = fabs(M[i + j * ldm] - (i == j ? 1.0 : 0.0));
+            m = v > m ? v : m;
+        }
+    for (int o = WAVE / 2; o >= 1; o >>= 1) m = fmax(m, __shfl_xor(m, o));
+    if ((threadIdx.x & (WAVE - 1)) == 0) sh[threadIdx.x / WAVE] = m;
     __syncthreads();
-    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + s]);
-        __syncthreads();
+    if (threadIdx.x == 0) {
+        double b = sh[0];
+        for (int w = 1; w < 256 / WAVE; ++w) b = fmax(b, sh[w]);
+        atomicMax(out, (unsigned long long)__double_as_longlong(b));
     }
-    if (threadIdx.x == 0) *out = sh[0];
 }
 void launch_max_abs_minus_identity(const double* M, int64_t l, int64_t ldm, double* out,
                                    hipStream_t st) {
-    k_max_abs_minus_identity<<<1, 1024, 0, st>>>(M, l, ldm, out);
+    (void)hipMemsetAsync(out, 0, sizeof(double), st);
+    const int g = (int)std::min<int64_t>(std::max<int64_t>(l, 1), 1024);
+    k_max_abs_minus_identity<<<g, 256, 0, st>>>(M, l, ldm, (unsigned long long*)out);
 }
 
 // ============================================ stored dense matvec (K5)
@@ -434,9 +442,9 @@ void launch_dense_matvec(int dta, int64_t n, const void* A, int64_t lda, const d
 constexpr int GT_COLS = 4;
 constexpr int GT_THREADS = 256;
 
-template <int NR, typename TQ = double>
+template <int NR>
 __global__ __launch_bounds__(GT_THREADS) void k_gemv_t(int64_t n, int64_t k,
-                                                       const TQ* __restrict__ Q, int64_t ldq,
+                                                       const double* __restrict__ Q, int64_t ldq,
                                                        const double* __restrict__ R, int64_t ldr,
                                                        double* __restrict__ c_part, int nchunks,
                                                        int64_t rows_per_chunk,
@@ -463,7 +471,7 @@ __global__ __launch_bounds__(GT_THREADS) void k_gemv_t(int64_t n, int64_t k,
             for (int q = 0; q < NR; ++q) ri[h][q] = R[i + h * GT_THREADS + q * ldr];
 #pragma unroll
             for (int c = 0; c < GT_COLS; ++c)
-                qv[h][c] = c < ncol ? (double)Q[i + h * GT_THREADS + (j0 + c) * ldq] : 0.0;
+                qv[h][c] = c < ncol ? Q[i + h * GT_THREADS + (j0 + c) * ldq] : 0.0;
         }
 #pragma unroll
         for (int h = 0; h < 2; ++h)
@@ -479,7 +487,7 @@ __global__ __launch_bounds__(GT_THREADS) void k_gemv_t(int64_t n, int64_t k,
 #pragma unroll
         for (int c = 0; c < GT_COLS; ++c)
             if (c < ncol) {
-                const double qij = (double)Q[i + (j0 + c) * ldq];
+                const double qij = Q[i + (j0 + c) * ldq];
 #pragma unroll
                 for (int q = 0; q < NR; ++q) acc[c][q] = fma(qij, ri[q], acc[c][q]);
             }
@@ -527,12 +535,6 @@ void launch_gemv_t_multi(int nr, int64_t n, int64_t k, const double* Q, int64_t 
         k_gemv_t<2><<<grid, GT_THREADS, 0, st>>>(n, k, Q, ldq, R, ldr, c_part, nchunks, rpc, stop);
     else
         k_gemv_t<1><<<grid, GT_THREADS, 0, st>>>(n, k, Q, ldq, R, ldr, c_part, nchunks, rpc, stop);
-}
-void launch_gemv_t_pair_f32(int64_t n, int64_t k, const float* Q, int64_t ldq, const double* R,
-                            int64_t ldr, double* c_part, int nchunks, hipStream_t st) {
-    const int64_t rpc = gemv_t_rows_per_chunk(n, k);
-    dim3 grid((unsigned)((k + GT_COLS - 1) / GT_COLS), (unsigned)nchunks);
-    k_gemv_t<2, float><<<grid, GT_THREADS, 0, st>>>(n, k, Q, ldq, R, ldr, c_part, nchunks, rpc, nullptr);
 }
 void launch_gemv_t(int64_t n, int64_t k, const double* Q, int64_t ldq, const double* r,
                    double* c_part, int nchunks, const int32_t* stop, hipStream_t st) {
@@ -607,9 +609,9 @@ void launch_core_apply_pair(int64_t k, const double* K0, const double* K1, int64
 // their partial row sums in a fixed order.
 constexpr int QD_ROWS = 64;
 constexpr int QD_THREADS = 256;
-template <int NR, typename TQ = double>
+template <int NR>
 __global__ __launch_bounds__(QD_THREADS) void k_qd(int64_t n, int64_t k,
-                                                   const TQ* __restrict__ Q, int64_t ldq,
+                                                   const double* __restrict__ Q, int64_t ldq,
                                                    const double* __restrict__ D,
                                                    const double* __restrict__ R, int64_t ldr,
                                                    double rc0, double rc1,
@@ -629,19 +631,19 @@ __global__ __launch_bounds__(QD_THREADS) void k_qd(int64_t n, int64_t k,
 #pragma unroll
     for (int q = 0; q < NR; ++q) acc[q][0] = acc[q][1] = 0.0;
     if (i < n) {
-        const TQ* qi = Q + i;
+        const double* qi = Q + i;
         int64_t j = jb;
         for (; j + 8 <= je; j += 8) {
             double qv[8];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) qv[u] = (double)qi[(j + u) * ldq];
+            for (int u = 0; u < 8; ++u) qv[u] = qi[(j + u) * ldq];
 #pragma unroll
             for (int u = 0; u < 8; ++u)
 #pragma unroll
                 for (int q = 0; q < NR; ++q) acc[q][u & 1] = fma(qv[u], d_sh[q * k + j + u], acc[q][u & 1]);
         }
         for (; j < je; ++j) {
-            const double qv = (double)qi[j * ldq];
+            const double qv = qi[j * ldq];
 #pragma unroll
             for (int q = 0; q < NR; ++q) acc[q][0] = fma(qv, d_sh[q * k + j], acc[q][0]);
         }
@@ -676,12 +678,6 @@ void launch_qd_multi(int nr, int64_t n, int64_t k, const double* Q, int64_t ldq,
         k_qd<2><<<qd_blocks(n), QD_THREADS, shm, st>>>(n, k, Q, ldq, D, R, ldr, rc0, rc1, Z, rz_part, stop);
     else
         k_qd<1><<<qd_blocks(n), QD_THREADS, shm, st>>>(n, k, Q, ldq, D, R, ldr, rc0, rc1, Z, rz_part, stop);
-}
-void launch_qd_pair_f32(int64_t n, int64_t k, const float* Q, int64_t ldq, const double* D,
-                        const double* R, int64_t ldr, double rc0, double rc1, double* Z, double* rz_part,
-                        hipStream_t st) {
-    const size_t shm = (size_t)std::max<int64_t>(2 * k, 1) * sizeof(double);
-    k_qd<2, float><<<qd_blocks(n), QD_THREADS, shm, st>>>(n, k, Q, ldq, D, R, ldr, rc0, rc1, Z, rz_part, nullptr);
 }
 void launch_qd(int64_t n, int64_t k, const double* Q, int64_t ldq, const double* d,
                const double* r, double rcoef, double* z, double* rz_part, const int32_t* stop,

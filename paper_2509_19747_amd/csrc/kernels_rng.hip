@@ -42,6 +42,26 @@ __global__ void k_fisher_yates(int32_t* __restrict__ perm, int64_t s, int64_t n,
     }
 }
 
+// The same shuffle with the permutation held in LDS as 16-bit entries (s <= 65536):
+// the block fills it, then one thread makes the l swaps at LDS latency.
+constexpr int FY_LDS_MAX = 65536;
+__global__ __launch_bounds__(1024) void k_fisher_yates_lds(int64_t s, int64_t n, int64_t l, uint64_t seed,
+                                                            int32_t* __restrict__ rows_out) {
+    __shared__ uint16_t perm[FY_LDS_MAX];
+    for (int64_t i = threadIdx.x; i < s; i += blockDim.x) perm[i] = (uint16_t)i;
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    for (int64_t c = 0; c < l; ++c) {
+        const uint64_t w = splitmix64(seed, (uint64_t)(n + c));
+        const uint64_t span = (uint64_t)(s - c);
+        const int64_t j = c + (int64_t)(((w >> 32) * span) >> 32);
+        const uint16_t t = perm[c];
+        perm[c] = perm[j];
+        perm[j] = t;
+        rows_out[c] = (int32_t)perm[c];
+    }
+}
+
 __global__ void k_srht_signs(float* __restrict__ D, int64_t n, uint64_t seed) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x)
@@ -175,8 +195,12 @@ void launch_gauss_fill(void* out, int dtype, int64_t rows, int64_t cols, int64_t
 
 void launch_srht_prepare(int64_t n, int64_t l, uint64_t seed, int64_t s, int32_t* perm_ws,
                          int32_t* rows_out, float* D_out, hipStream_t st) {
-    k_iota<<<grid_for(s), 256, 0, st>>>(perm_ws, s);
-    k_fisher_yates<<<1, 64, 0, st>>>(perm_ws, s, n, l, seed, rows_out);
+    if (s <= FY_LDS_MAX) {
+        k_fisher_yates_lds<<<1, 1024, 0, st>>>(s, n, l, seed, rows_out);
+    } else {
+        k_iota<<<grid_for(s), 256, 0, st>>>(perm_ws, s);
+        k_fisher_yates<<<1, 64, 0, st>>>(perm_ws, s, n, l, seed, rows_out);
+    }
     k_srht_signs<<<grid_for(n), 256, 0, st>>>(D_out, n, seed);
 }
 

@@ -241,6 +241,24 @@ def test_build_fp64_matches_oracle(dense_small, orth, tau_rule):
         assert abs(g["tau"] - o.tau) < 1e-9 * o.tau
 
 
+def test_build_fp64_wide_basis_matches_oracle():
+    """l = 600 (triangular inverses of 600 x 600 factors, Householder panels past
+    512 rows of the 1200-row sketch) against the oracle."""
+    prob = workloads.cfg_small_dense(n=1400, d=8, l=600)
+    op = Operator.from_problem(prob)
+    kop = rr.kernel_operator(rr.OP_RBF, _cuda(prob.pts), prob.kconst, prob.scale)
+    A = rr.kernel_to_dense(kop, "fp64")
+    mu = prob.mus[0]
+    P = rr.build_precond(rr.dense_operator(A), [mu], l=prob.l, sketch="gaussian", seed=prob.omega_seed)
+    g = P.export(0)
+    o = orr.build(op, [mu], prob.l, "gaussian", prob.omega_seed)[0]
+    rel = lambda a, b_: np.linalg.norm(a - b_) / np.linalg.norm(b_)
+    assert rel(g["Q"], o.Q) < 1e-9
+    assert rel(g["R"], o.R) < 1e-9
+    assert rel(g["G"], o.G) < 1e-8
+    assert abs(g["tau"] - o.tau) < 1e-8 * o.tau
+
+
 @pytest.mark.parametrize("l", [0, 45])
 @pytest.mark.parametrize("use_graph", [False, True])
 def test_solve_fp64_matches_oracle(dense_small, l, use_graph):
@@ -306,8 +324,8 @@ def test_kernel_fp32_solve_with_srht():
     Pr = orr.build(op, [mu], prob.l, "srht", prob.omega_seed)[0]
     ref = osol.pcg(op.shifted(mu), Pr.apply, prob.b, prob.tol)
     assert abs(info["iters"] - ref.iters) <= max(3, int(0.1 * ref.iters))
-    # the tau estimates (float32 entries and sums, float32 copy of Q in their
-    # projections) agree with the float64 oracle to a few digits
+    # the tau estimates (float32 entries and sums) agree with the float64 oracle
+    # to a few digits
     g = P.export(0, with_q=False)
     for key in ("normE", "lam", "tau"):
         assert abs(g[key] - getattr(Pr, key)) < 1e-3 * getattr(Pr, key), (key, g[key], getattr(Pr, key))
