@@ -68,33 +68,74 @@ struct Builder {
 
     // In-place upper Cholesky of the l x l spd matrix A with the shift ladder of
     // Appendix C: on failure retry with A + alpha I, alpha in {1e-14,...,1e-1} * max_i A_ii.
-    void chol_ladder(double* A, int64_t l) {
-        DBuf copy = mat(l, l);
-        RR_HIP(hipMemcpyAsync(copy.ptr(), A, (size_t)l * l * sizeof(double), hipMemcpyDeviceToDevice, st));
-        int32_t h = 0;
-        RR_HIP(hipMemsetAsync(status.ptr(), 0, sizeof(int32_t), st));
-        launch_cholesky_upper(A, l, l, status.as<int32_t>(), gws.as<double>(), gwsd, st);
+    // chol_start enqueues the first attempt on stream s (copy keeps A for retries);
+    // chol_finish reads its status word (a host wait on s only) and runs the ladder.
+    void chol_start(double* A, int64_t l, double* copy, hipStream_t s, int32_t* stat, double* ws,
+                    size_t wsd) {
+        RR_HIP(hipMemcpyAsync(copy, A, (size_t)l * l * sizeof(double), hipMemcpyDeviceToDevice, s));
+        RR_HIP(hipMemsetAsync(stat, 0, sizeof(int32_t), s));
+        launch_cholesky_upper(A, l, l, stat, ws, wsd, s);
         check_launch();
-        RR_HIP(hipMemcpyAsync(&h, status.ptr(), sizeof(int32_t), hipMemcpyDeviceToHost, st));
-        sync();
+    }
+    void chol_finish(double* A, int64_t l, const double* copy, hipStream_t s, int32_t* stat, double* ws,
+                     size_t wsd) {
+        int32_t h = 0;
+        RR_HIP(hipMemcpyAsync(&h, stat, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        RR_HIP(hipStreamSynchronize(s));
         if (h == 0) return;
         std::vector<double> hc((size_t)l * l);
-        RR_HIP(hipMemcpy(hc.data(), copy.ptr(), hc.size() * sizeof(double), hipMemcpyDeviceToHost));
+        RR_HIP(hipMemcpyAsync(hc.data(), copy, hc.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+        RR_HIP(hipStreamSynchronize(s));
         double wn = 0.0;
         for (int64_t i = 0; i < l; ++i) wn = std::max(wn, std::fabs(hc[(size_t)i + (size_t)i * l]));
         if (!(wn > 0.0) || !std::isfinite(wn)) throw RrError{RR_ENOTSPD, "Cholesky: matrix is zero or not finite"};
         for (int e = -14; e <= -1; ++e) {
             const double alpha = std::pow(10.0, e) * wn;
-            RR_HIP(hipMemcpyAsync(A, copy.ptr(), (size_t)l * l * sizeof(double), hipMemcpyDeviceToDevice, st));
-            launch_add_diag(A, l, l, alpha, st);
-            RR_HIP(hipMemsetAsync(status.ptr(), 0, sizeof(int32_t), st));
-            launch_cholesky_upper(A, l, l, status.as<int32_t>(), gws.as<double>(), gwsd, st);
+            RR_HIP(hipMemcpyAsync(A, copy, (size_t)l * l * sizeof(double), hipMemcpyDeviceToDevice, s));
+            launch_add_diag(A, l, l, alpha, s);
+            RR_HIP(hipMemsetAsync(stat, 0, sizeof(int32_t), s));
+            launch_cholesky_upper(A, l, l, stat, ws, wsd, s);
             check_launch();
-            RR_HIP(hipMemcpyAsync(&h, status.ptr(), sizeof(int32_t), hipMemcpyDeviceToHost, st));
-            sync();
+            RR_HIP(hipMemcpyAsync(&h, stat, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+            RR_HIP(hipStreamSynchronize(s));
             if (h == 0) return;
         }
         throw RrError{RR_ENOTSPD, "Cholesky failed after the whole shift ladder"};
+    }
+    void chol_ladder(double* A, int64_t l) {
+        DBuf copy = mat(l, l);
+        chol_start(A, l, copy.as<double>(), st, status.as<int32_t>(), gws.as<double>(), gwsd);
+        chol_finish(A, l, copy.as<double>(), st, status.as<int32_t>(), gws.as<double>(), gwsd);
+    }
+
+    // A second stream for work that does not depend on the main chain (its own
+    // status word and GEMM workspace); side_begin orders it after everything queued
+    // on the main stream so far, side_join makes the main stream wait for it.
+    hipStream_t st2 = nullptr;
+    hipEvent_t ev_a = nullptr, ev_b = nullptr;
+    DBuf gws2, status2;
+    void side_begin() {
+        if (!st2) {
+            RR_HIP(hipStreamCreateWithFlags(&st2, hipStreamNonBlocking));
+            RR_HIP(hipEventCreateWithFlags(&ev_a, hipEventDisableTiming));
+            RR_HIP(hipEventCreateWithFlags(&ev_b, hipEventDisableTiming));
+            gws2.reset(al, gwsd * sizeof(double));
+            status2.reset(al, 64);
+        }
+        RR_HIP(hipEventRecord(ev_a, st));
+        RR_HIP(hipStreamWaitEvent(st2, ev_a, 0));
+    }
+    void side_join() {
+        RR_HIP(hipEventRecord(ev_b, st2));
+        RR_HIP(hipStreamWaitEvent(st, ev_b, 0));
+    }
+    ~Builder() {
+        if (st2) {
+            (void)hipStreamSynchronize(st2);
+            (void)hipStreamDestroy(st2);
+        }
+        if (ev_a) (void)hipEventDestroy(ev_a);
+        if (ev_b) (void)hipEventDestroy(ev_b);
     }
 
     // Omega (n x l) into P.Omega.  In float32 mode for kernels and in mixed mode for
@@ -174,12 +215,16 @@ struct Builder {
     // chol_qr.  The block products read Y row-major in float64 (Yt, made here;
     // handed back through yt_out when asked for): a row of Y is what Theta adds,
     // and float64 operands keep the float64 MFMA GEMM at full load width.
+    // side(yt), when given, is called once Y^T is queued, to start work that needs
+    // only Y (it may queue on the second stream).
+    template <typename Side>
     void orth(const void* Y, int ydt, int64_t k, uint64_t theta_seed, double* Q, double* R,
-              DBuf* yt_out = nullptr) {
+              DBuf* yt_out, Side&& side) {
         const int64_t n = P.n;
         DBuf Yt = mat(k, n);   // column-major k x n = Y^T
         launch_transpose_f64(ydt, n, k, Y, n, Yt.as<double>(), k, st);
         const double* yt = Yt.as<double>();
+        side(yt);
         if (P.opts.orth == RR_ORTH_SKETCHED_CHOLQR) {
             DBuf S = mat(2 * k, k);
             launch_theta_apply(n, k, theta_seed, yt, k, S.as<double>(), 2 * k, st);
@@ -213,6 +258,9 @@ struct Builder {
         }
         check_launch();
         if (yt_out) *yt_out = std::move(Yt);
+    }
+    void orth(const void* Y, int ydt, int64_t k, uint64_t theta_seed, double* Q, double* R) {
+        orth(Y, ydt, k, theta_seed, Q, R, nullptr, [](const double*) {});
     }
 
     // Power iteration: v <- op(v)/||op(v)|| from a Gaussian start (stream seed);
@@ -327,10 +375,16 @@ struct Builder {
         launch_symmetrize(C, l, l, st);
         chol_ladder(C, l);
         DBuf Rinv = mat(l, l), H = mat(l, l);
-        launch_tri_inv_upper(R, l, l, Rinv.as<double>(), l, st);
-        gemm(DT_F64, false, DT_F64, false, l, l, l, C, l, Rinv.ptr(), l, H.as<double>(), l);
-        gemm(DT_F64, true, DT_F64, false, l, l, l, H.ptr(), l, H.ptr(), l, G, l);
-        launch_symmetrize(G, l, l, st);
+        core_G_factored(C, R, G, l, Rinv.as<double>(), H.as<double>(), st, gws.as<double>());
+    }
+    // the same once C holds R_Omega, on stream s with GEMM workspace ws (gwsd doubles);
+    // Rinv and H are l x l scratch
+    void core_G_factored(const double* C, const double* R, double* G, int64_t l, double* Rinv, double* H,
+                         hipStream_t s, double* ws) {
+        launch_tri_inv_upper(R, l, l, Rinv, l, s);
+        launch_gemm(DT_F64, false, DT_F64, false, l, l, l, C, l, Rinv, l, H, l, 1.0, 0.0, ws, gwsd, s);
+        launch_gemm(DT_F64, true, DT_F64, false, l, l, l, H, l, H, l, G, l, 1.0, 0.0, ws, gwsd, s);
+        launch_symmetrize(G, l, l, s);
     }
 
     // max |Q^T Q - I| into a device word; read after the build's final synchronisation
@@ -421,29 +475,54 @@ extern "C" rr_status rr_build_precond(const rr_operator* A, const double* mus, i
             A16.release();
             // A3: orthogonalisation
             pm.R.reset(al, (size_t)l * l * sizeof(double));
-            DBuf Yt;
-            B.orth(Y.ptr(), ydt, l, o.seed + 1, P.Qb.as<double>(), pm.R.as<double>(), &Yt);
-            Y.release();
-            // A4: core, refined projector, tau, apply core.  C^T = Y^T Omega (C is
-            // symmetrised before use), with float64 operands.
-            DBuf C = B.mat(l, l);
-            {
-                DBuf Od;
+            // A4's C = Omega^T Y and its Cholesky R_Omega need only Y: they run on a
+            // second stream beside the orthogonalisation (C^T = Y^T Omega with
+            // float64 operands; C is symmetrised before it is factored).
+            // Buffers the second stream touches are allocated on the main stream before
+            // it is ordered after the main stream, and freed only after the join (or,
+            // on an error, after the guard below has waited for the second stream).
+            DBuf Yt, C = B.mat(l, l), Ccopy = B.mat(l, l), Od;
+            if (P.omega_dt != DT_F64) Od = B.mat(n, l);
+            struct SideGuard {
+                Builder& b;
+                ~SideGuard() {
+                    if (b.st2) (void)hipStreamSynchronize(b.st2);
+                }
+            } side_guard{B};
+            auto side = [&](const double* yt) {
+                B.side_begin();
                 const void* om = P.Omega.ptr();
                 if (P.omega_dt != DT_F64) {
-                    Od = B.mat(n, l);
-                    launch_copy_mat(P.omega_dt, P.Omega.ptr(), n, DT_F64, Od.ptr(), n, n, l, st);
+                    launch_copy_mat(P.omega_dt, P.Omega.ptr(), n, DT_F64, Od.ptr(), n, n, l, B.st2);
                     om = Od.ptr();
                 }
-                B.gemm(DT_F64, false, DT_F64, false, l, l, n, Yt.ptr(), l, om, n, C.as<double>(), l);
-            }
+                launch_gemm(DT_F64, false, DT_F64, false, l, l, n, yt, l, om, n, C.as<double>(), l, 1.0, 0.0,
+                            B.gws2.as<double>(), B.gwsd, B.st2);
+                launch_symmetrize(C.as<double>(), l, l, B.st2);
+                B.chol_start(C.as<double>(), l, Ccopy.as<double>(), B.st2, B.status2.as<int32_t>(),
+                             B.gws2.as<double>(), B.gwsd);
+            };
+            B.orth(Y.ptr(), ydt, l, o.seed + 1, P.Qb.as<double>(), pm.R.as<double>(), &Yt, side);
+            B.chol_finish(C.as<double>(), l, Ccopy.as<double>(), B.st2, B.status2.as<int32_t>(),
+                          B.gws2.as<double>(), B.gwsd);
+            B.side_join();
+            Y.release();
             Yt.release();
+            Od.release();
+            Ccopy.release();
+            // A4: core, refined projector, tau, apply core.  G (from R and R_Omega) on
+            // the second stream while the main one forms T = 2I - Q^T Q.
             pm.G.reset(al, (size_t)l * l * sizeof(double));
-            B.core_G(C.as<double>(), pm.R.as<double>(), pm.G.as<double>(), l);
+            DBuf Rinv = B.mat(l, l), H = B.mat(l, l);
+            SideGuard side_guard2{B};   // freed after the second stream is idle
+            B.side_begin();
+            B.core_G_factored(C.as<double>(), pm.R.as<double>(), pm.G.as<double>(), l, Rinv.as<double>(),
+                              H.as<double>(), B.st2, B.gws2.as<double>());
             pm.T.reset(al, (size_t)l * l * sizeof(double));
             B.gram(l, n, P.Qb.as<double>(), n, pm.T.as<double>(), l);
             B.orth_error(pm.T.as<double>(), l);
             launch_two_minus(pm.T.as<double>(), l, l, st);
+            B.side_join();
             DBuf TG = B.mat(l, l), TGT = B.mat(l, l), negT = B.mat(l, l);
             B.gemm(DT_F64, false, DT_F64, false, l, l, l, pm.T.ptr(), l, pm.G.ptr(), l, TG.as<double>(), l);
             B.gemm(DT_F64, false, DT_F64, false, l, l, l, TG.ptr(), l, pm.T.ptr(), l, TGT.as<double>(), l);
