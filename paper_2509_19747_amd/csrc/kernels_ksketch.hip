@@ -98,68 +98,39 @@ RR_DEV void ks2_mfma(const Ks2Smem& sm, int buf, int lane, int rh, int cq, f32x1
             }
 }
 
-// SRHT Omega generated in registers (no Omega stream): Omega[i, c] = D_i (-1)^
-// popcount(i & s_c) for i < n, zero past n.  The 8 points base .. base+7 of a B
-// fragment (base a multiple of 8) share popcount(base & s_c); point base + t adds
-// popcount(t & s_c & 7), whose parities over t are the column's 8-bit Walsh mask.
-// The 8 signs then index a 256-entry LDS table of +-1 bf16 vectors.
-struct Ks2Gen {
-    uint32_t s[KS2_WC];    // sampled Hadamard row of each of the lane's column tiles
-    uint32_t w8[KS2_WC];   // Walsh mask of its low 3 bits
-};
-RR_DEV bf16x8_t ks2_gen_frag(const uint4* table, uint32_t s, uint32_t w8, int64_t base, uint32_t d8,
-                             int64_t n) {
-    const uint32_t par = (uint32_t)__popcll((unsigned long long)((uint64_t)base & (uint64_t)s)) & 1u;
-    const uint32_t sg = ((0u - par) & 0xFFu) ^ w8 ^ d8;
-    uint4 v = table[sg];
-    if (base + 8 > n) {   // last step only: zero the points past n
-        const int64_t valid = n - base;
-        uint32_t* w = &v.x;
+// SRHT Omega generated on the device (no Omega stream): Omega[i, c] =
+// D_i (-1)^popcount(i & s_c) for i < n, zero past n.  For a step of 32 points
+// starting at k (a multiple of 32), popcount((k + p) & s) = popcount(k & s) +
+// popcount(p & s & 31), so the step's 32 signs of column c are one word:
+// (parity(k & s_c) ? ~0 : 0) ^ W_c ^ (sign bits of D at k .. k+31), with W_c the
+// column's 32-bit Walsh word.  Each byte of it indexes a 256-entry LDS table of
+// 8 bf16 values +-1, written into the Omega slice in LDS as if it had been loaded.
+RR_DEV void ks2_gen_slice(Ks2Smem& sm, int buf, int col, const uint4* table, uint64_t s, uint32_t w32,
+                          int64_t k, uint32_t dw, int64_t n) {
+    const uint32_t par = (uint32_t)__popcll((unsigned long long)((uint64_t)k & s)) & 1u;
+    const uint32_t sg = (0u - par) ^ w32 ^ dw;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const uint32_t lo = (2 * j < valid) ? 0x0000FFFFu : 0u;
-            const uint32_t hi = (2 * j + 1 < valid) ? 0xFFFF0000u : 0u;
-            w[j] &= lo | hi;
-        }
-    }
-    return __builtin_bit_cast(bf16x8_t, v);
-}
-
-// One step of MFMAs with generated B fragments (same order as ks2_mfma).  dw: the
-// 32 sign bits of D for the step's points (bit p: point k0 + p has D = -1).
-RR_DEV void ks2_mfma_gen(const Ks2Smem& sm, int buf, int lane, int rh, const uint4* table,
-                         const Ks2Gen& gq, int64_t k0, uint32_t dw, int64_t n,
-                         f32x16_t (&acc)[2][KS2_WC]) {
-    const int kq = 8 * (lane >> 5);
-    bf16x8_t ah[2][2], al[2][2], bv[2][KS2_WC];
+    for (int q = 0; q < 4; ++q) {
+        uint4 v = table[(sg >> (8 * q)) & 0xFFu];
+        const int64_t base = k + 8 * q;
+        if (base + 8 > n) {   // last step only: zero the points past n
+            const int64_t valid = n - base;
+            uint32_t* w = &v.x;
 #pragma unroll
-    for (int kh = 0; kh < 2; ++kh) {
-#pragma unroll
-        for (int u = 0; u < 2; ++u) {
-            const int row = rh * 64 + u * 32 + (lane & 31);
-            ah[kh][u] = __builtin_bit_cast(bf16x8_t, *(const uint4*)&sm.a_hi[buf][row * KS2_AS + 16 * kh + kq]);
-            al[kh][u] = __builtin_bit_cast(bf16x8_t, *(const uint4*)&sm.a_lo[buf][row * KS2_AS + 16 * kh + kq]);
-        }
-        const int64_t base = k0 + 16 * kh + kq;
-        const uint32_t d8 = (dw >> (16 * kh + kq)) & 0xFFu;
-#pragma unroll
-        for (int v = 0; v < KS2_WC; ++v) bv[kh][v] = ks2_gen_frag(table, gq.s[v], gq.w8[v], base, d8, n);
-    }
-#pragma unroll
-    for (int kh = 0; kh < 2; ++kh)
-#pragma unroll
-        for (int v = 0; v < KS2_WC; ++v)
-#pragma unroll
-            for (int u = 0; u < 2; ++u) {
-                acc[u][v] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[kh][u], bv[kh][v], acc[u][v], 0, 0, 0);
-                acc[u][v] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[kh][u], bv[kh][v], acc[u][v], 0, 0, 0);
+            for (int j = 0; j < 4; ++j) {
+                const uint32_t lo = (2 * j < valid) ? 0x0000FFFFu : 0u;
+                const uint32_t hi = (2 * j + 1 < valid) ? 0xFFFF0000u : 0u;
+                w[j] &= lo | hi;
             }
+        }
+        *(uint4*)&sm.b[buf][col * KS2_BS + 8 * q] = v;
+    }
 }
 
 // part == nullptr: Y = scale * acc + mu * B.  Otherwise part[z] (n x m, leading
 // dimension n) = acc over the block's point range [z*kper, (z+1)*kper).
 // GEN: Omega is an SRHT given by its sampled rows srow (m) and the sign bits dbits
-// of D (bit i%32 of word i/32), and B fragments are generated instead of loaded.
+// of D (bit i%32 of word i/32), and its slices are generated instead of loaded.
 template <int KIND, int DM, bool GEN>
 __global__ __launch_bounds__(KS2_THREADS) void k_ksketch_bf16x2(
     int64_t n, const float* __restrict__ xa, const float* __restrict__ sqn, float c, float scale,
@@ -252,25 +223,27 @@ __global__ __launch_bounds__(KS2_THREADS) void k_ksketch_bf16x2(
                        ((((uint32_t)t >> (2 * j + 1)) & 1u ? 0xBF80u : 0x3F80u) << 16);
             gtable[t] = make_uint4(w[0], w[1], w[2], w[3]);
         }
-        Ks2Gen gq;
+        // thread t generates column c0 + t of each slice (columns past m: zeros of no
+        // consequence, their products are not stored)
+        const int64_t gcol = c0 + t;
+        const uint64_t scol = gcol < m ? (uint64_t)(uint32_t)srow[gcol] : 0ull;
+        uint32_t w32 = 0;
 #pragma unroll
-        for (int v = 0; v < KS2_WC; ++v) {
-            const int64_t gc = c0 + cq * 32 * KS2_WC + v * 32 + (lane & 31);
-            const uint32_t sv = gc < m ? (uint32_t)srow[gc] : 0u;   // columns past m are not stored
-            uint32_t w8 = 0;
-#pragma unroll
-            for (int tt = 0; tt < 8; ++tt) w8 |= ((uint32_t)__popc((uint32_t)tt & sv) & 1u) << tt;
-            gq.s[v] = sv;
-            gq.w8[v] = w8;
-        }
+        for (int p = 0; p < 32; ++p) w32 |= ((uint32_t)__popc((uint32_t)p & (uint32_t)scol) & 1u) << p;
         __syncthreads();   // row records, sign table
-        if (kb < ke && former) form(kb, 0);
+        if (kb < ke) {
+            ks2_gen_slice(sm, 0, t, gtable, scol, w32, kb, dbits[kb >> 5], n);
+            if (former) form(kb, 0);
+        }
         __syncthreads();
         int buf = 0;
         for (int64_t k0 = kb; k0 < ke; k0 += KS2_BK) {
             const int64_t k1 = k0 + KS2_BK;
-            if (former && k1 < ke) form(k1, buf ^ 1);
-            ks2_mfma_gen(sm, buf, lane, rh, gtable, gq, k0, dbits[k0 >> 5], n, acc);
+            if (k1 < ke) {
+                ks2_gen_slice(sm, buf ^ 1, t, gtable, scol, w32, k1, dbits[k1 >> 5], n);
+                if (former) form(k1, buf ^ 1);
+            }
+            ks2_mfma(sm, buf, lane, rh, cq, acc);
             __syncthreads();
             buf ^= 1;
         }
