@@ -303,8 +303,9 @@ struct Builder {
     }
 
     // tau and its estimates for one shift; cores are kb x kb over the basis Qb.
+    // M: Qb^T Qb (kb x kb), for the merged projections below.
     void tau_for(PerMu& pm, const double* negT, const double* TGT, const double* T, const double* G,
-                 int64_t l) {
+                 int64_t l, const double* M) {
         const int64_t n = P.n;
         const double mu = pm.mu;
         if (P.opts.tau_rule == RR_TAU_NYS) {
@@ -316,16 +317,36 @@ struct Builder {
         }
         // The two power iterations run side by side so each step costs one
         // two-column operator pass (every kernel entry evaluated once):
-        //   ||E||: v <- (I-Pi) A_mu (I-Pi) v,   lam: v <- Pi A_mu Pi~ v.
+        //   ||E||: v <- (I-Pi) A_mu (I-Pi) v,   lam: v <- Pi A_mu Pi~ v,
+        // with Pi = Qb T Qb^T and Pi~ = Qb TGT Qb^T.  The output projection of a step
+        // and the input projection of the next are one projection, since scaling
+        // commutes with them:
+        //   (I-Pi)(I-Pi) = I - Qb (2T - T M T) Qb^T,   Pi~ Pi = Qb (TGT M T) Qb^T,
+        // and the norms the steps normalise by come along: ||(I-Pi) y||^2 is
+        // y^T (I-Pi)^2 y, the dot the projection kernel forms anyway, and
+        // ||Pi y||^2 = c^T (T M T) c with c = Qb^T y.  So a step costs one operator
+        // pass and one projection pair instead of two.
         // They only estimate two scalars to a few digits, so a float32-mode
         // kernel operator may add its products in float32 here.
+        const int64_t kb = P.kb;
         DBuf U(al, 2 * n * sizeof(double)), Yv(al, 2 * n * sizeof(double));
         DBuf V(al, 2 * n * sizeof(double)), Wv(al, 2 * n * sizeof(double));
-        const int nch = gemv_t_chunks(n, P.kb);
-        DBuf cpart(al, (size_t)2 * nch * P.kb * sizeof(double)), d(al, 2 * P.kb * sizeof(double));
+        const int nch = gemv_t_chunks(n, kb);
+        DBuf cpart(al, (size_t)2 * nch * kb * sizeof(double)), d(al, 2 * kb * sizeof(double));
         DBuf rz(al, (size_t)2 * qd_blocks(n) * sizeof(double));
         DBuf op_part(al, (size_t)2 * operator_part_count(P) * sizeof(double));
+        constexpr int QF_BLOCKS = 32;
+        DBuf qf(al, QF_BLOCKS * sizeof(double));
+        // merged cores: KE = T M T - 2T (with r added back: I - Qb (2T - TMT) Qb^T),
+        // KL = TGT M T, B1 = T M T
+        DBuf MT = mat(kb, kb), B1 = mat(kb, kb), KE = mat(kb, kb), KL = mat(kb, kb);
+        gemm(DT_F64, false, DT_F64, false, kb, kb, kb, M, kb, T, kb, MT.as<double>(), kb);
+        gemm(DT_F64, false, DT_F64, false, kb, kb, kb, T, kb, MT.ptr(), kb, B1.as<double>(), kb);
+        launch_symmetrize(B1.as<double>(), kb, kb, st);
+        launch_axpby_mat(1.0, B1.as<double>(), kb, -2.0, T, kb, KE.as<double>(), kb, kb, kb, st);
+        gemm(DT_F64, false, DT_F64, false, kb, kb, kb, TGT, kb, MT.ptr(), kb, KL.as<double>(), kb);
         double* u0 = U.as<double>();
+        double* u1 = u0 + n;
         double* y0 = Yv.as<double>();
         double* v0 = V.as<double>();
         double* v1 = v0 + n;
@@ -341,17 +362,16 @@ struct Builder {
         double* cp = cpart.as<double>();
         double* dd = d.as<double>();
         double* rzp = rz.as<double>();
+        // u = [(I-Pi) v0, Pi~ v1]
+        apply_projected_pair(P, negT, TGT, v0, 1.0, 0.0, u0, cp, dd, rzp, st);
         for (int it = 0; it < P.opts.power_iters; ++it) {
-            // [(I-Pi) v0, Pi~ v1], A_mu on both, [(I-Pi) y0, Pi y1]; each pair of
-            // projections reads Q once
-            apply_projected_pair(P, negT, TGT, v0, 1.0, 0.0, u0, cp, dd, rzp, st);
             apply_operator_multi(P, u0, 2, mu, y0, op_part.as<double>(), kws.as<double>(), false, st,
                                  true);
-            apply_projected_pair(P, negT, T, y0, 1.0, 0.0, w0, cp, dd, rzp, st);
-            launch_dot_part(n, w0, w0, vparts.as<double>(), st);
-            launch_normalize(n, v0, w0, vparts.as<double>(), vec_blocks(n), lam_dev + 0, st);
-            launch_dot_part(n, w1, w1, vparts.as<double>(), st);
-            launch_normalize(n, v1, w1, vparts.as<double>(), vec_blocks(n), lam_dev + 1, st);
+            // w = [(I-Pi)^2 y0, Pi~ Pi y1] (unnormalised next inputs), y0^T w0 in rzp
+            apply_projected_pair(P, KE.as<double>(), KL.as<double>(), y0, 1.0, 0.0, w0, cp, dd, rzp, st);
+            launch_quad_form(kb, B1.as<double>(), cp + (size_t)nch * kb, nch, qf.as<double>(), QF_BLOCKS, st);
+            launch_normalize(n, u0, w0, rzp, qd_blocks(n), lam_dev + 0, st);
+            launch_normalize(n, u1, w1, qf.as<double>(), QF_BLOCKS, lam_dev + 1, st);
         }
         check_launch();
         double lams[2] = {0.0, 0.0};
@@ -528,7 +548,13 @@ extern "C" rr_status rr_build_precond(const rr_operator* A, const double* mus, i
             B.gemm(DT_F64, false, DT_F64, false, l, l, l, TG.ptr(), l, pm.T.ptr(), l, TGT.as<double>(), l);
             launch_symmetrize(TGT.as<double>(), l, l, st);
             launch_axpby_mat(-1.0, pm.T.as<double>(), l, 0.0, pm.T.as<double>(), l, negT.as<double>(), l, l, l, st);
-            B.tau_for(pm, negT.as<double>(), TGT.as<double>(), pm.T.as<double>(), pm.G.as<double>(), l);
+            {
+                DBuf M = B.mat(l, l);   // Q^T Q = 2I - T
+                launch_axpby_mat(-1.0, pm.T.as<double>(), l, 0.0, pm.T.as<double>(), l, M.as<double>(), l, l, l, st);
+                launch_add_diag(M.as<double>(), l, l, 2.0, st);
+                B.tau_for(pm, negT.as<double>(), TGT.as<double>(), pm.T.as<double>(), pm.G.as<double>(), l,
+                          M.as<double>());
+            }
             pm.Kc.reset(al, (size_t)l * l * sizeof(double));
             launch_axpby_mat(pm.tau, TGT.as<double>(), l, -1.0, pm.T.as<double>(), l, pm.Kc.as<double>(), l, l, l, st);
             B.check_launch();
@@ -591,7 +617,8 @@ extern "C" rr_status rr_build_precond(const rr_operator* A, const double* mus, i
                 lift(pm.T.as<double>(), Tt.as<double>());
                 lift(TGT.as<double>(), TGTt.as<double>());
                 launch_axpby_mat(-1.0, Tt.as<double>(), k2, 0.0, Tt.as<double>(), k2, negTt.as<double>(), k2, k2, k2, st);
-                B.tau_for(pm, negTt.as<double>(), TGTt.as<double>(), Tt.as<double>(), pm.G.as<double>(), l);
+                B.tau_for(pm, negTt.as<double>(), TGTt.as<double>(), Tt.as<double>(), pm.G.as<double>(), l,
+                          QQ.as<double>());
                 DBuf K = B.mat(l, l);
                 launch_axpby_mat(pm.tau, TGT.as<double>(), l, -1.0, pm.T.as<double>(), l, K.as<double>(), l, l, l, st);
                 pm.Kc.reset(al, (size_t)k2 * k2 * sizeof(double));

@@ -230,6 +230,10 @@ void launch_core_apply(int64_t k, const double* Kc, int64_t ldk, const double* c
                        int nchunks, double* d, const int32_t* stop, hipStream_t st);
 // The same for a pair of columns: d[0:k] from K0 and c_part[0 : nchunks*k],
 // d[k:2k] from K1 and c_part[nchunks*k : 2*nchunks*k] (one launch).
+// part[0 .. nblocks) = shares of c^T B c (B symmetric k x k, c_j = sum over chunks of
+// c_part[ch * k + j]); their sum is the quadratic form.
+void launch_quad_form(int64_t k, const double* B, const double* c_part, int nchunks, double* part,
+                      int nblocks, hipStream_t st);
 void launch_core_apply_pair(int64_t k, const double* K0, const double* K1, int64_t ldk,
                             const double* c_part, int nchunks, double* d, const int32_t* stop,
                             hipStream_t st);

@@ -603,6 +603,40 @@ void launch_core_apply_pair(int64_t k, const double* K0, const double* K1, int64
     k_core_apply<<<dim3(g, 2), 256, 0, st>>>(k, K0, K1, ldk, c_part, nchunks, d, stop);
 }
 
+// part[b] = block b's share of c^T B c for a symmetric k x k B, with c_j =
+// sum_ch c_part[ch * k + j] (partials added in chunk order).  Block b takes the
+// columns j = b, b + gridDim.x, ...; the shares are added by the caller.
+__global__ __launch_bounds__(256) void k_quad_form(int64_t k, const double* __restrict__ B,
+                                                   const double* __restrict__ c_part, int nchunks,
+                                                   double* __restrict__ part) {
+    extern __shared__ double c_sh[];
+    __shared__ double red[256 / WAVE];
+    for (int64_t j = threadIdx.x; j < k; j += blockDim.x) {
+        double c = 0.0;
+        for (int ch = 0; ch < nchunks; ++ch) c += c_part[(int64_t)ch * k + j];
+        c_sh[j] = c;
+    }
+    __syncthreads();
+    double acc = 0.0;
+    for (int64_t j = blockIdx.x; j < k; j += gridDim.x) {
+        double bj = 0.0;
+        for (int64_t i = threadIdx.x; i < k; i += blockDim.x) bj = fma(B[i + j * k], c_sh[i], bj);
+        acc = fma(c_sh[j], bj, acc);
+    }
+    acc = wave_sum(acc);
+    if ((threadIdx.x & (WAVE - 1)) == 0) red[threadIdx.x / WAVE] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int w = 0; w < 256 / WAVE; ++w) s += red[w];
+        part[blockIdx.x] = s;
+    }
+}
+void launch_quad_form(int64_t k, const double* B, const double* c_part, int nchunks, double* part,
+                      int nblocks, hipStream_t st) {
+    k_quad_form<<<nblocks, 256, (size_t)std::max<int64_t>(k, 1) * sizeof(double), st>>>(k, B, c_part, nchunks, part);
+}
+
 // Z[i, q] = rcoef_q R[i, q] + sum_j Q[i, j] D[j, q]; partial sums of R[i, q] Z[i, q]
 // per block in rz_part[q * gridDim.x + block].  Block: 64 rows, its four waves
 // split the k columns (lane = row, loads of Q coalesced along the column) and add
@@ -875,7 +909,7 @@ __global__ __launch_bounds__(256) void k_normalize(int64_t n, double* __restrict
                                                    double* lam_out) {
     __shared__ double sc[4];
     const double s = block_sum_array(part, count, sc);
-    const double nrm = sqrt(s);
+    const double nrm = sqrt(s > 0.0 ? s : 0.0);   // a y^T (I-Pi)^2 y may round below zero
     const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
     if (blockIdx.x == 0 && threadIdx.x == 0) *lam_out = nrm;
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
