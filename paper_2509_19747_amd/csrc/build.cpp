@@ -332,11 +332,10 @@ struct Builder {
         DBuf U(al, 2 * n * sizeof(double)), Yv(al, 2 * n * sizeof(double));
         DBuf V(al, 2 * n * sizeof(double)), Wv(al, 2 * n * sizeof(double));
         const int nch = gemv_t_chunks(n, kb);
-        DBuf cpart(al, (size_t)2 * nch * kb * sizeof(double)), d(al, 2 * kb * sizeof(double));
+        DBuf cpart(al, (size_t)2 * nch * kb * sizeof(double)), d(al, 3 * kb * sizeof(double));
         DBuf rz(al, (size_t)2 * qd_blocks(n) * sizeof(double));
         DBuf op_part(al, (size_t)2 * operator_part_count(P) * sizeof(double));
-        constexpr int QF_BLOCKS = 32;
-        DBuf qf(al, QF_BLOCKS * sizeof(double));
+        DBuf c1(al, kb * sizeof(double)), qf(al, (size_t)vec_blocks(kb) * sizeof(double));
         // merged cores: KE = T M T - 2T (with r added back: I - Qb (2T - TMT) Qb^T),
         // KL = TGT M T, B1 = T M T
         DBuf MT = mat(kb, kb), B1 = mat(kb, kb), KE = mat(kb, kb), KL = mat(kb, kb);
@@ -367,11 +366,15 @@ struct Builder {
         for (int it = 0; it < P.opts.power_iters; ++it) {
             apply_operator_multi(P, u0, 2, mu, y0, op_part.as<double>(), kws.as<double>(), false, st,
                                  true);
-            // w = [(I-Pi)^2 y0, Pi~ Pi y1] (unnormalised next inputs), y0^T w0 in rzp
-            apply_projected_pair(P, KE.as<double>(), KL.as<double>(), y0, 1.0, 0.0, w0, cp, dd, rzp, st);
-            launch_quad_form(kb, B1.as<double>(), cp + (size_t)nch * kb, nch, qf.as<double>(), QF_BLOCKS, st);
+            // w = [(I-Pi)^2 y0, Pi~ Pi y1] (unnormalised next inputs), y0^T w0 in rzp,
+            // c1 = Qb^T y1 and T M T c1 for ||Pi y1||^2
+            launch_gemv_t_multi(2, n, kb, P.Qb.as<double>(), n, y0, n, cp, nch, nullptr, st);
+            launch_core_apply_triple(kb, KE.as<double>(), KL.as<double>(), B1.as<double>(), kb, cp, nch, dd,
+                                     c1.as<double>(), st);
+            launch_qd_multi(2, n, kb, P.Qb.as<double>(), n, dd, y0, n, 1.0, 0.0, w0, rzp, nullptr, st);
+            launch_dot_part(kb, c1.as<double>(), dd + 2 * kb, qf.as<double>(), st);
             launch_normalize(n, u0, w0, rzp, qd_blocks(n), lam_dev + 0, st);
-            launch_normalize(n, u1, w1, qf.as<double>(), QF_BLOCKS, lam_dev + 1, st);
+            launch_normalize(n, u1, w1, qf.as<double>(), vec_blocks(kb), lam_dev + 1, st);
         }
         check_launch();
         double lams[2] = {0.0, 0.0};

@@ -230,13 +230,13 @@ void launch_core_apply(int64_t k, const double* Kc, int64_t ldk, const double* c
                        int nchunks, double* d, const int32_t* stop, hipStream_t st);
 // The same for a pair of columns: d[0:k] from K0 and c_part[0 : nchunks*k],
 // d[k:2k] from K1 and c_part[nchunks*k : 2*nchunks*k] (one launch).
-// part[0 .. nblocks) = shares of c^T B c (B symmetric k x k, c_j = sum over chunks of
-// c_part[ch * k + j]); their sum is the quadratic form.
-void launch_quad_form(int64_t k, const double* B, const double* c_part, int nchunks, double* part,
-                      int nblocks, hipStream_t st);
 void launch_core_apply_pair(int64_t k, const double* K0, const double* K1, int64_t ldk,
                             const double* c_part, int nchunks, double* d, const int32_t* stop,
                             hipStream_t st);
+// Pair plus a third product on the second column: d[2k:3k) = K2 c_1, and c_1 itself
+// into c1_out (k doubles).
+void launch_core_apply_triple(int64_t k, const double* K0, const double* K1, const double* K2, int64_t ldk,
+                              const double* c_part, int nchunks, double* d, double* c1_out, hipStream_t st);
 // z = rcoef*r + Q d, and per-block partials of r^T z.
 int qd_blocks(int64_t n);
 void launch_qd(int64_t n, int64_t k, const double* Q, int64_t ldq, const double* d,

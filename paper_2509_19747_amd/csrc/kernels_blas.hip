@@ -546,16 +546,21 @@ void launch_gemv_t(int64_t n, int64_t k, const double* Q, int64_t ldq, const dou
 // Each thread finishes the c_j of its own j (partials added in chunk order) and
 // uses them at once, so the block needs no staging barrier.
 constexpr int CA_ROWS = 4;
+// blockIdx.y = 2 (launch_core_apply_triple): core K2 on column 1's c, into d[2k:3k);
+// c_out, when given, receives column 1's c.
 __global__ __launch_bounds__(256) void k_core_apply(int64_t k, const double* __restrict__ K0,
                                                     const double* __restrict__ K1, int64_t ldk,
                                                     const double* __restrict__ c_part, int nchunks,
                                                     double* __restrict__ d,
-                                                    const int32_t* __restrict__ stop) {
+                                                    const int32_t* __restrict__ stop,
+                                                    const double* __restrict__ K2 = nullptr,
+                                                    double* __restrict__ c_out = nullptr) {
     __shared__ double red[CA_ROWS][256 / WAVE];
     if (stop && *stop) return;
     const int q = blockIdx.y;
-    const double* __restrict__ Kc = q ? K1 : K0;
-    const double* __restrict__ cp = c_part + (int64_t)q * nchunks * k;
+    const double* __restrict__ Kc = q == 0 ? K0 : q == 1 ? K1 : K2;
+    const double* __restrict__ cp = c_part + (int64_t)(q ? 1 : 0) * nchunks * k;
+    const bool write_c = c_out && q == 1 && blockIdx.x == 0;
     const int64_t i0 = (int64_t)blockIdx.x * CA_ROWS;
     double acc[CA_ROWS];
 #pragma unroll
@@ -574,6 +579,7 @@ __global__ __launch_bounds__(256) void k_core_apply(int64_t k, const double* __r
             for (int u = 0; u < 4; ++u) cj += v[u];
         }
         for (; ch < nchunks; ++ch) cj += cp[(int64_t)ch * k + j];
+        if (write_c) c_out[j] = cj;
 #pragma unroll
         for (int r = 0; r < CA_ROWS; ++r) acc[r] = fma(kv[r], cj, acc[r]);
     }
@@ -602,39 +608,10 @@ void launch_core_apply_pair(int64_t k, const double* K0, const double* K1, int64
     const int g = (int)((k + CA_ROWS - 1) / CA_ROWS);
     k_core_apply<<<dim3(g, 2), 256, 0, st>>>(k, K0, K1, ldk, c_part, nchunks, d, stop);
 }
-
-// part[b] = block b's share of c^T B c for a symmetric k x k B, with c_j =
-// sum_ch c_part[ch * k + j] (partials added in chunk order).  Block b takes the
-// columns j = b, b + gridDim.x, ...; the shares are added by the caller.
-__global__ __launch_bounds__(256) void k_quad_form(int64_t k, const double* __restrict__ B,
-                                                   const double* __restrict__ c_part, int nchunks,
-                                                   double* __restrict__ part) {
-    extern __shared__ double c_sh[];
-    __shared__ double red[256 / WAVE];
-    for (int64_t j = threadIdx.x; j < k; j += blockDim.x) {
-        double c = 0.0;
-        for (int ch = 0; ch < nchunks; ++ch) c += c_part[(int64_t)ch * k + j];
-        c_sh[j] = c;
-    }
-    __syncthreads();
-    double acc = 0.0;
-    for (int64_t j = blockIdx.x; j < k; j += gridDim.x) {
-        double bj = 0.0;
-        for (int64_t i = threadIdx.x; i < k; i += blockDim.x) bj = fma(B[i + j * k], c_sh[i], bj);
-        acc = fma(c_sh[j], bj, acc);
-    }
-    acc = wave_sum(acc);
-    if ((threadIdx.x & (WAVE - 1)) == 0) red[threadIdx.x / WAVE] = acc;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double s = 0.0;
-        for (int w = 0; w < 256 / WAVE; ++w) s += red[w];
-        part[blockIdx.x] = s;
-    }
-}
-void launch_quad_form(int64_t k, const double* B, const double* c_part, int nchunks, double* part,
-                      int nblocks, hipStream_t st) {
-    k_quad_form<<<nblocks, 256, (size_t)std::max<int64_t>(k, 1) * sizeof(double), st>>>(k, B, c_part, nchunks, part);
+void launch_core_apply_triple(int64_t k, const double* K0, const double* K1, const double* K2, int64_t ldk,
+                              const double* c_part, int nchunks, double* d, double* c1_out, hipStream_t st) {
+    const int g = (int)((k + CA_ROWS - 1) / CA_ROWS);
+    k_core_apply<<<dim3(g, 3), 256, 0, st>>>(k, K0, K1, ldk, c_part, nchunks, d, nullptr, K2, c1_out);
 }
 
 // Z[i, q] = rcoef_q R[i, q] + sum_j Q[i, j] D[j, q]; partial sums of R[i, q] Z[i, q]
