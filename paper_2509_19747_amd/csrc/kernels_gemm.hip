@@ -91,19 +91,25 @@ __global__ __launch_bounds__(GM_THREADS) void k_gemm_mfma(int64_t M, int64_t N, 
 #pragma unroll
         for (int v = 0; v < 2; ++v) acc[u][v] = f64x4_t{0.0, 0.0, 0.0, 0.0};
 
-    // op(B)[k][j] is op(B^T)[j][k]: load it with the transposed flag
-    double ra[GM_EL], rb[GM_EL];
+    // op(B)[k][j] is op(B^T)[j][k]: load it with the transposed flag.  Two register
+    // sets alternate between k steps, so a tile is loaded two steps before it is
+    // stored to LDS (the load latency of a step alone is not covered).
+    double ra0[GM_EL], rb0[GM_EL], ra1[GM_EL], rb1[GM_EL];
     if (kb < ke) {
-        gm_load<TA, TRA>(A, lda, M, ke, i0, kb, t, ra);
-        gm_load<TB, !TRB>(B, ldb, N, ke, j0, kb, t, rb);
+        gm_load<TA, TRA>(A, lda, M, ke, i0, kb, t, ra0);
+        gm_load<TB, !TRB>(B, ldb, N, ke, j0, kb, t, rb0);
     }
-    for (int64_t k0 = kb; k0 < ke; k0 += GM_BK) {
+    if (kb + GM_BK < ke) {
+        gm_load<TA, TRA>(A, lda, M, ke, i0, kb + GM_BK, t, ra1);
+        gm_load<TB, !TRB>(B, ldb, N, ke, j0, kb + GM_BK, t, rb1);
+    }
+    auto step = [&](int64_t k0, double (&ra)[GM_EL], double (&rb)[GM_EL]) {
         gm_store<TRA>(As, t, ra);
         gm_store<!TRB>(Bs, t, rb);
         __syncthreads();
-        if (k0 + GM_BK < ke) {
-            gm_load<TA, TRA>(A, lda, M, ke, i0, k0 + GM_BK, t, ra);
-            gm_load<TB, !TRB>(B, ldb, N, ke, j0, k0 + GM_BK, t, rb);
+        if (k0 + 2 * GM_BK < ke) {
+            gm_load<TA, TRA>(A, lda, M, ke, i0, k0 + 2 * GM_BK, t, ra);
+            gm_load<TB, !TRB>(B, ldb, N, ke, j0, k0 + 2 * GM_BK, t, rb);
         }
 #pragma unroll
         for (int kc = 0; kc < GM_BK; kc += 4) {
@@ -119,6 +125,10 @@ __global__ __launch_bounds__(GM_THREADS) void k_gemm_mfma(int64_t M, int64_t N, 
                     acc[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b[v], acc[u][v], 0, 0, 0);
         }
         __syncthreads();
+    };
+    for (int64_t k0 = kb; k0 < ke; k0 += 2 * GM_BK) {
+        step(k0, ra0, rb0);
+        if (k0 + GM_BK < ke) step(k0 + GM_BK, ra1, rb1);
     }
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
