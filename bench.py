@@ -120,6 +120,8 @@ def main():
     ap.add_argument("--requests", type=int, default=2200, help="serving: number of requests")
     ap.add_argument("--rate", type=float, default=200.0, help="serving: arrivals per second")
     ap.add_argument("--slots", type=int, default=16, help="serving: concurrent requests")
+    ap.add_argument("--graph-iters", type=int, default=8,
+                    help="serving: PCG iterations per replayed hipGraph batch (0: plain launches)")
     ap.add_argument("--budget-gb", type=float, default=96.0, help="serving: HBM budget")
     ap.add_argument("--dump", default="", help="serving: write per-request records (JSON lines)")
     ap.add_argument("--nrhs", type=int, default=256, help="batched: right-hand sides per shift")
@@ -453,7 +455,7 @@ def bench_serving(args):
     kw = dict(build=dict(prec="fp32", sketch="gaussian"), solve=dict(tol=1e-6, certify=False))
     _log(f"serving: {len(reqs)} requests generated")
     res, stats = rb.serve(reqs, hbm_budget=int(args.budget_gb * (1 << 30)), max_slots=args.slots,
-                          graph_iters=8, **kw)
+                          graph_iters=args.graph_iters, **kw)
     lat = np.array([r["t_done"] - q["t_arrival"] for r, q in zip(res, reqs) if r is not None])
     warm = 200 if len(lat) > 400 else 0
     ok = sum(1 for r in res if r is not None and r["info"]["status"] == 0)
@@ -464,6 +466,7 @@ def bench_serving(args):
         "p50_ms": float(np.percentile(lat[warm:], 50) * 1e3),
         "p99_ms": float(np.percentile(lat[warm:], 99) * 1e3), "server_stats": stats,
         "requests": len(reqs), "ok": ok, "rate": args.rate, "slots": args.slots,
+        "graph_iters": args.graph_iters,
         "mean_build_ms": float(np.mean([i["ms_build"] for i in infos])),
         "mean_solve_ms": float(np.mean([i["ms_solve"] for i in infos])),
         "mean_iters": float(np.mean([i["iters"] for i in infos])),

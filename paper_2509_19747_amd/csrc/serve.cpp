@@ -48,17 +48,6 @@ size_t request_bytes(const rr_request& r) {
     return (size_t)b;
 }
 
-// Stream-ordered allocation, so that one request's frees never wait for the others.
-void* async_alloc(void*, size_t bytes, void* stream) {
-    void* p = nullptr;
-    if (hipMallocAsync(&p, bytes, (hipStream_t)stream) != hipSuccess) {
-        (void)hipGetLastError();
-        return nullptr;
-    }
-    return p;
-}
-void async_free(void*, void* p, void* stream) { (void)hipFreeAsync(p, (hipStream_t)stream); }
-
 struct Job {
     rr_request req;
     size_t bytes;
@@ -88,7 +77,6 @@ void run_job(const rr_serve_config& cfg, Job& job, hipStream_t st, double t0, rr
     const int64_t n = r.n;
     const int64_t nr = std::max<int32_t>(r.nrhs, 1);
     auto fail = [&](rr_status s) { info.status = s; };
-    rr_allocator alloc{nullptr, async_alloc, async_free};
     do {
         if (hipMallocAsync((void**)&pts, (size_t)r.d * n * sizeof(float), st) != hipSuccess ||
             hipMallocAsync((void**)&b, (size_t)n * nr * sizeof(double), st) != hipSuccess ||
@@ -114,7 +102,9 @@ void run_job(const rr_serve_config& cfg, Job& job, hipStream_t st, double t0, rr
         bo.l = r.l;
         bo.seed = r.seed;
         const double mu = r.mu;
-        rr_status s = rr_build_precond(&op, &mu, 1, &bo, &alloc, st, &P);
+        // the library's own allocation path: the worker's stream keeps its freed
+        // blocks, so the next request on this slot reuses them without pool calls
+        rr_status s = rr_build_precond(&op, &mu, 1, &bo, nullptr, st, &P);
         if (s != RR_OK) { fail(s); break; }
         // every right-hand side of the request in one fused batched PCG, its
         // iteration batches replayed as a hipGraph
