@@ -35,6 +35,8 @@ struct Batch {
     DBuf R, Pm, Z, W, T, parts, C, Dall, D, state, start, target2, mucol, muidx, gws;
     DBuf kws, kdot;       // symmetric multi-column kernel matvec (few columns)
     bool kmulti = false;
+    DBuf cpart, dcols, rzp;   // projection through the basis, groups of up to 8 columns
+    int pmax = 0, gch = 1;
     size_t gwsd = 0;
     std::vector<int> mus_used;
     int nch = 1;
@@ -68,6 +70,20 @@ struct Batch {
         RR_HIP(hipMemsetAsync(state.ptr(), 0, (size_t)m * sizeof(BState), st));
     }
 
+    // Few columns under one shift: the projection is a streaming pass over Qb per
+    // group of columns (Qb^T R, the core, R + Qb D) rather than GEMMs, which cuts
+    // the launches per iteration.  Group width limited by the qd kernel's LDS
+    // (D of the group plus its partial sums within 64 KiB).
+    void setup_projection() {
+        if (kb == 0 || m > KMULTI_MAX || mus_used.size() != 1) return;
+        pmax = kb <= 768 ? 8 : kb <= 1792 ? 4 : 0;
+        if (pmax == 0) return;
+        gch = gemv_t_chunks(n, kb);
+        cpart.reset(al, (size_t)pmax * gch * kb * sizeof(double));
+        dcols.reset(al, (size_t)pmax * kb * sizeof(double));
+        rzp.reset(al, (size_t)pmax * qd_blocks(n) * sizeof(double));
+    }
+
     void gemm(bool ta, bool tb, int64_t M, int64_t N, int64_t K, const void* A, int64_t lda,
               const void* B, int64_t ldb, double* Cm, int64_t ldc, double alpha, double beta,
               int dta = DT_F64) {
@@ -96,9 +112,22 @@ struct Batch {
 
     // Zout = P_{mu(j)} Rin for every column
     void precond(const double* Rin, double* Zout) {
+        const double* Qb = P.Qb.as<double>();
+        if (pmax > 0) {
+            const double* Kc = P.per[mus_used[0]].Kc.as<double>();
+            for (int64_t c0 = 0; c0 < m;) {
+                const int64_t left = m - c0;
+                const int nr = left >= pmax ? pmax : left >= 4 ? 4 : left >= 2 ? 2 : 1;
+                launch_gemv_t_multi(nr, n, kb, Qb, n, Rin + c0 * n, n, cpart.as<double>(), gch, nullptr, st);
+                launch_core_apply_cols(kb, Kc, kb, cpart.as<double>(), gch, nr, dcols.as<double>(), st);
+                launch_qd_multi(nr, n, kb, Qb, n, dcols.as<double>(), Rin + c0 * n, n, 1.0, 1.0, Zout + c0 * n,
+                                rzp.as<double>(), nullptr, st);
+                c0 += nr;
+            }
+            return;
+        }
         launch_copy_mat(DT_F64, Rin, n, DT_F64, Zout, n, n, m, st);
         if (kb == 0) return;
-        const double* Qb = P.Qb.as<double>();
         gemm(true, false, kb, m, n, Qb, n, Rin, n, C.as<double>(), kb, 1.0, 0.0);
         for (int g : mus_used)
             gemm(false, false, kb, m, kb, P.per[g].Kc.ptr(), kb, C.ptr(), kb,
@@ -157,6 +186,7 @@ rr_status rr_solve_batch_fused(const rr_precond* Pc, const int32_t* mu_index_per
         std::vector<int> used(P.per.size(), 0);
         for (int64_t j = 0; j < m; ++j) { hmu[j] = P.per[mu_index_per_col[j]].mu; used[mu_index_per_col[j]] = 1; }
         for (size_t g = 0; g < used.size(); ++g) if (used[g]) Bt.mus_used.push_back((int)g);
+        Bt.setup_projection();
         RR_HIP(hipMemcpyAsync(Bt.mucol.ptr(), hmu.data(), m * sizeof(double), hipMemcpyHostToDevice, st));
         RR_HIP(hipMemcpyAsync(Bt.muidx.ptr(), mu_index_per_col, m * sizeof(int32_t), hipMemcpyHostToDevice, st));
 

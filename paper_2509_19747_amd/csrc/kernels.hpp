@@ -235,6 +235,9 @@ void launch_core_apply_pair(int64_t k, const double* K0, const double* K1, int64
                             hipStream_t st);
 // Pair plus a third product on the second column: d[2k:3k) = K2 c_1, and c_1 itself
 // into c1_out (k doubles).
+// ncols columns with one core: d[q k : (q+1) k) = Kc c_q, c_q from column q of c_part.
+void launch_core_apply_cols(int64_t k, const double* Kc, int64_t ldk, const double* c_part, int nchunks,
+                            int ncols, double* d, hipStream_t st);
 void launch_core_apply_triple(int64_t k, const double* K0, const double* K1, const double* K2, int64_t ldk,
                               const double* c_part, int nchunks, double* d, double* c1_out, hipStream_t st);
 // z = rcoef*r + Q d, and per-block partials of r^T z.

@@ -531,10 +531,12 @@ void launch_gemv_t_multi(int nr, int64_t n, int64_t k, const double* Q, int64_t 
                          int64_t ldr, double* c_part, int nchunks, const int32_t* stop, hipStream_t st) {
     const int64_t rpc = gemv_t_rows_per_chunk(n, k);
     dim3 grid((unsigned)((k + GT_COLS - 1) / GT_COLS), (unsigned)nchunks);
-    if (nr == 2)
-        k_gemv_t<2><<<grid, GT_THREADS, 0, st>>>(n, k, Q, ldq, R, ldr, c_part, nchunks, rpc, stop);
-    else
-        k_gemv_t<1><<<grid, GT_THREADS, 0, st>>>(n, k, Q, ldq, R, ldr, c_part, nchunks, rpc, stop);
+    switch (nr) {
+        case 8: k_gemv_t<8><<<grid, GT_THREADS, 0, st>>>(n, k, Q, ldq, R, ldr, c_part, nchunks, rpc, stop); break;
+        case 4: k_gemv_t<4><<<grid, GT_THREADS, 0, st>>>(n, k, Q, ldq, R, ldr, c_part, nchunks, rpc, stop); break;
+        case 2: k_gemv_t<2><<<grid, GT_THREADS, 0, st>>>(n, k, Q, ldq, R, ldr, c_part, nchunks, rpc, stop); break;
+        default: k_gemv_t<1><<<grid, GT_THREADS, 0, st>>>(n, k, Q, ldq, R, ldr, c_part, nchunks, rpc, stop); break;
+    }
 }
 void launch_gemv_t(int64_t n, int64_t k, const double* Q, int64_t ldq, const double* r,
                    double* c_part, int nchunks, const int32_t* stop, hipStream_t st) {
@@ -554,12 +556,15 @@ __global__ __launch_bounds__(256) void k_core_apply(int64_t k, const double* __r
                                                     double* __restrict__ d,
                                                     const int32_t* __restrict__ stop,
                                                     const double* __restrict__ K2 = nullptr,
-                                                    double* __restrict__ c_out = nullptr) {
+                                                    double* __restrict__ c_out = nullptr,
+                                                    bool shared_core = false) {
     __shared__ double red[CA_ROWS][256 / WAVE];
     if (stop && *stop) return;
     const int q = blockIdx.y;
-    const double* __restrict__ Kc = q == 0 ? K0 : q == 1 ? K1 : K2;
-    const double* __restrict__ cp = c_part + (int64_t)(q ? 1 : 0) * nchunks * k;
+    // shared_core: column q of c_part with core K0 (any number of columns);
+    // otherwise the pair / triple layout above
+    const double* __restrict__ Kc = shared_core ? K0 : q == 0 ? K0 : q == 1 ? K1 : K2;
+    const double* __restrict__ cp = c_part + (int64_t)(shared_core ? q : (q ? 1 : 0)) * nchunks * k;
     const bool write_c = c_out && q == 1 && blockIdx.x == 0;
     const int64_t i0 = (int64_t)blockIdx.x * CA_ROWS;
     double acc[CA_ROWS];
@@ -607,6 +612,12 @@ void launch_core_apply_pair(int64_t k, const double* K0, const double* K1, int64
                             hipStream_t st) {
     const int g = (int)((k + CA_ROWS - 1) / CA_ROWS);
     k_core_apply<<<dim3(g, 2), 256, 0, st>>>(k, K0, K1, ldk, c_part, nchunks, d, stop);
+}
+void launch_core_apply_cols(int64_t k, const double* Kc, int64_t ldk, const double* c_part, int nchunks,
+                            int ncols, double* d, hipStream_t st) {
+    const int g = (int)((k + CA_ROWS - 1) / CA_ROWS);
+    k_core_apply<<<dim3(g, ncols), 256, 0, st>>>(k, Kc, Kc, ldk, c_part, nchunks, d, nullptr, Kc, nullptr,
+                                                 true);
 }
 void launch_core_apply_triple(int64_t k, const double* K0, const double* K1, const double* K2, int64_t ldk,
                               const double* c_part, int nchunks, double* d, double* c1_out, hipStream_t st) {
@@ -685,10 +696,12 @@ void launch_qd_multi(int nr, int64_t n, int64_t k, const double* Q, int64_t ldq,
                      const double* R, int64_t ldr, double rc0, double rc1, double* Z, double* rz_part,
                      const int32_t* stop, hipStream_t st) {
     const size_t shm = (size_t)std::max<int64_t>(nr * k, 1) * sizeof(double);
-    if (nr == 2)
-        k_qd<2><<<qd_blocks(n), QD_THREADS, shm, st>>>(n, k, Q, ldq, D, R, ldr, rc0, rc1, Z, rz_part, stop);
-    else
-        k_qd<1><<<qd_blocks(n), QD_THREADS, shm, st>>>(n, k, Q, ldq, D, R, ldr, rc0, rc1, Z, rz_part, stop);
+    switch (nr) {
+        case 8: k_qd<8><<<qd_blocks(n), QD_THREADS, shm, st>>>(n, k, Q, ldq, D, R, ldr, rc0, rc1, Z, rz_part, stop); break;
+        case 4: k_qd<4><<<qd_blocks(n), QD_THREADS, shm, st>>>(n, k, Q, ldq, D, R, ldr, rc0, rc1, Z, rz_part, stop); break;
+        case 2: k_qd<2><<<qd_blocks(n), QD_THREADS, shm, st>>>(n, k, Q, ldq, D, R, ldr, rc0, rc1, Z, rz_part, stop); break;
+        default: k_qd<1><<<qd_blocks(n), QD_THREADS, shm, st>>>(n, k, Q, ldq, D, R, ldr, rc0, rc1, Z, rz_part, stop); break;
+    }
 }
 void launch_qd(int64_t n, int64_t k, const double* Q, int64_t ldq, const double* d,
                const double* r, double rcoef, double* z, double* rz_part, const int32_t* stop,

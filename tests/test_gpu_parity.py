@@ -536,6 +536,20 @@ def test_batched_graph_replay_and_wide_block():
     for c in range(5):
         assert abs(i5[c]["iters"] - ie[c]["iters"]) <= 2
         assert np.linalg.norm(X5[:, c] - Xe[:, c]) <= 1e-3 * np.linalg.norm(Xe[:, c])
+    # 13 columns under one shift: the projection runs in column groups 8 + 4 + 1
+    # (streaming passes over the basis instead of GEMMs); eager and graph agree
+    B13 = _cuda(B[:, 7:20].copy())
+    X13, i13, s13 = P.solve_batch(B13, [0] * 13, tol=tol, check_every=4)
+    X13g, i13g, s13g = P.solve_batch(B13, [0] * 13, tol=tol, check_every=4, use_graph=True)
+    assert s13 == rr.RR_OK and s13g == rr.RR_OK
+    assert torch.equal(X13, X13g)
+    X13 = X13.cpu().numpy()
+    for c in range(13):
+        assert i13[c]["status"] == rr.RR_OK
+        assert abs(i13[c]["iters"] - ie[7 + c]["iters"]) <= 2
+        assert np.linalg.norm(X13[:, c] - Xe[:, 7 + c]) <= 1e-3 * np.linalg.norm(Xe[:, 7 + c])
+        rel64 = osol.relres(op.shifted(mu), X13[:, c], B[:, 7 + c])
+        assert rel64 <= tol + dA * np.linalg.norm(X13[:, c]) / np.linalg.norm(B[:, 7 + c])
 
 
 def test_batched_dense_operator():
