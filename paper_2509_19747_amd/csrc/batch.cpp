@@ -37,6 +37,9 @@ struct Batch {
     bool kmulti = false;
     DBuf cpart, dcols, rzp;   // projection through the basis, groups of up to 8 columns
     int pmax = 0, gch = 1;
+    DBuf rrp;                 // block partials of ||r_j||^2 from the x, r update
+    bool single = false;      // every column under one shift mu1
+    double mu1 = 0.0;
     size_t gwsd = 0;
     std::vector<int> mus_used;
     int nch = 1;
@@ -67,6 +70,7 @@ struct Batch {
             kws.reset(al, (kernel_matvec_ws_doubles(n, p.op.d, (int)std::min<int64_t>(m, 8)) + 1) * sizeof(double));
             kdot.reset(al, (size_t)kernel_matvec_blocks(n) * m * sizeof(double));
         }
+        rrp.reset(al, (size_t)bxr_blocks(n) * m * sizeof(double));
         RR_HIP(hipMemsetAsync(state.ptr(), 0, (size_t)m * sizeof(BState), st));
     }
 
@@ -74,14 +78,20 @@ struct Batch {
     // group of columns (Qb^T R, the core, R + Qb D) rather than GEMMs, which cuts
     // the launches per iteration.  Group width limited by the qd kernel's LDS
     // (D of the group plus its partial sums within 64 KiB).
-    void setup_projection() {
-        if (kb == 0 || m > KMULTI_MAX || mus_used.size() != 1) return;
+    // A single shift also folds mu into the kernel product, whose block partials
+    // of p_j^T w_j then serve alpha, and the projection's partials of r_j^T z_j
+    // serve beta (no separate column dots).
+    void setup_single_shift() {
+        if (mus_used.size() != 1) return;
+        single = true;
+        mu1 = P.per[mus_used[0]].mu;
+        if (kb == 0 || m > KMULTI_MAX) return;
         pmax = kb <= 768 ? 8 : kb <= 1792 ? 4 : 0;
         if (pmax == 0) return;
         gch = gemv_t_chunks(n, kb);
         cpart.reset(al, (size_t)pmax * gch * kb * sizeof(double));
         dcols.reset(al, (size_t)pmax * kb * sizeof(double));
-        rzp.reset(al, (size_t)pmax * qd_blocks(n) * sizeof(double));
+        rzp.reset(al, (size_t)m * qd_blocks(n) * sizeof(double));
     }
 
     void gemm(bool ta, bool tb, int64_t M, int64_t N, int64_t K, const void* A, int64_t lda,
@@ -90,14 +100,17 @@ struct Batch {
         launch_gemm(dta, ta, DT_F64, tb, M, N, K, A, lda, B, ldb, Cm, ldc, alpha, beta, gws.as<double>(), gwsd, st);
     }
 
-    // Wout = A_mu Pin for every column (fp64: float64 operator)
-    void matmat(const double* Pin, int64_t ldp, double* Wout, bool fp64) {
+    // Wout = A_mu Pin for every column (fp64: float64 operator).  Returns the block
+    // partials of Pin_j^T Wout_j when the product produced them (nch = 0 otherwise).
+    ColParts matmat(const double* Pin, int64_t ldp, double* Wout, bool fp64) {
         if (kmulti && !fp64 && ldp == n) {
             const KernelOp k = kernel_op_of(P);
-            launch_kernel_matvec_multi(k, false, Pin, (int)m, 0.0, Wout, kdot.as<double>(), kws.as<double>(),
-                                       nullptr, st);
+            const int nblk = kernel_matvec_blocks(n);
+            launch_kernel_matvec_multi(k, false, Pin, (int)m, single ? mu1 : 0.0, Wout, kdot.as<double>(),
+                                       kws.as<double>(), nullptr, st);
+            if (single) return ColParts{kdot.as<double>(), nblk, 1, nblk};
             launch_add_shift_cols(n, m, mucol.as<double>(), Pin, ldp, Wout, n, st);
-            return;
+            return ColParts{nullptr, 0, 0, 0};
         }
         if (is_kernel(P.op)) {
             const KernelOp k = kernel_op_of(P);
@@ -108,32 +121,36 @@ struct Batch {
             else gemm(false, false, n, m, n, P.op.A, P.op.lda, Pin, ldp, Wout, n, 1.0, 0.0);
             launch_add_shift_cols(n, m, mucol.as<double>(), Pin, ldp, Wout, n, st);
         }
+        return ColParts{nullptr, 0, 0, 0};
     }
 
-    // Zout = P_{mu(j)} Rin for every column
-    void precond(const double* Rin, double* Zout) {
+    // Zout = P_{mu(j)} Rin for every column.  Returns the block partials of
+    // Rin_j^T Zout_j when the projection produced them (nch = 0 otherwise).
+    ColParts precond(const double* Rin, double* Zout) {
         const double* Qb = P.Qb.as<double>();
         if (pmax > 0) {
             const double* Kc = P.per[mus_used[0]].Kc.as<double>();
+            const int nb = qd_blocks(n);
             for (int64_t c0 = 0; c0 < m;) {
                 const int64_t left = m - c0;
                 const int nr = left >= pmax ? pmax : left >= 4 ? 4 : left >= 2 ? 2 : 1;
                 launch_gemv_t_multi(nr, n, kb, Qb, n, Rin + c0 * n, n, cpart.as<double>(), gch, nullptr, st);
                 launch_core_apply_cols(kb, Kc, kb, cpart.as<double>(), gch, nr, dcols.as<double>(), st);
                 launch_qd_multi(nr, n, kb, Qb, n, dcols.as<double>(), Rin + c0 * n, n, 1.0, 1.0, Zout + c0 * n,
-                                rzp.as<double>(), nullptr, st);
+                                rzp.as<double>() + c0 * nb, nullptr, st);
                 c0 += nr;
             }
-            return;
+            return ColParts{rzp.as<double>(), nb, 1, nb};
         }
         launch_copy_mat(DT_F64, Rin, n, DT_F64, Zout, n, n, m, st);
-        if (kb == 0) return;
+        if (kb == 0) return ColParts{nullptr, 0, 0, 0};
         gemm(true, false, kb, m, n, Qb, n, Rin, n, C.as<double>(), kb, 1.0, 0.0);
         for (int g : mus_used)
             gemm(false, false, kb, m, kb, P.per[g].Kc.ptr(), kb, C.ptr(), kb,
                  Dall.as<double>() + (size_t)g * kb * m, kb, 1.0, 0.0);
         launch_select_cols(kb, m, Dall.as<double>(), muidx.as<int32_t>(), D.as<double>(), st);
         gemm(false, false, n, m, kb, Qb, n, D.ptr(), kb, Zout, n, 1.0, 1.0);
+        return ColParts{nullptr, 0, 0, 0};
     }
 
     // per-column sums of A_j^T B_j on the host (fixed order)
@@ -154,15 +171,16 @@ struct Batch {
         double* w = W.as<double>();
         double* z = Z.as<double>();
         double* pp = parts.as<double>();
-        matmat(p, n, w, false);
-        launch_coldot(n, m, p, n, w, n, pp, st);
-        launch_bscal_alpha(pp, nch, m, s, st);
-        launch_bxr(n, m, X, ldx, r, p, w, s, st);
-        launch_coldot(n, m, r, n, r, n, pp, st);
-        launch_bscal_rr(pp, nch, m, s, st);
-        precond(r, z);
-        launch_coldot(n, m, r, n, z, n, pp, st);
-        launch_bscal_beta(pp, nch, m, s, st);
+        const ColParts own{pp, nch, m, 1};
+        ColParts pw = matmat(p, n, w, false);
+        if (!pw.p) { launch_coldot(n, m, p, n, w, n, pp, st); pw = own; }
+        launch_bscal_alpha(pw, m, s, st);
+        const int gx = bxr_blocks(n);
+        launch_bxr(n, m, X, ldx, r, p, w, s, rrp.as<double>(), st);
+        launch_bscal_rr(ColParts{rrp.as<double>(), gx, 1, gx}, m, s, st);
+        ColParts rz = precond(r, z);
+        if (!rz.p) { launch_coldot(n, m, r, n, z, n, pp, st); rz = own; }
+        launch_bscal_beta(rz, m, s, st);
         launch_bp(n, m, z, p, s, st);
     }
 };
@@ -186,7 +204,7 @@ rr_status rr_solve_batch_fused(const rr_precond* Pc, const int32_t* mu_index_per
         std::vector<int> used(P.per.size(), 0);
         for (int64_t j = 0; j < m; ++j) { hmu[j] = P.per[mu_index_per_col[j]].mu; used[mu_index_per_col[j]] = 1; }
         for (size_t g = 0; g < used.size(); ++g) if (used[g]) Bt.mus_used.push_back((int)g);
-        Bt.setup_projection();
+        Bt.setup_single_shift();
         RR_HIP(hipMemcpyAsync(Bt.mucol.ptr(), hmu.data(), m * sizeof(double), hipMemcpyHostToDevice, st));
         RR_HIP(hipMemcpyAsync(Bt.muidx.ptr(), mu_index_per_col, m * sizeof(int32_t), hipMemcpyHostToDevice, st));
 
@@ -244,7 +262,8 @@ rr_status rr_solve_batch_fused(const rr_precond* Pc, const int32_t* mu_index_per
             launch_copy_flagged(n, m, Bt.T.as<double>(), n, Bt.R.as<double>(), n, Bt.start.as<int32_t>(), st);
             Bt.precond(Bt.T.as<double>(), Bt.Z.as<double>());
             launch_coldot(n, m, Bt.T.as<double>(), n, Bt.Z.as<double>(), n, Bt.parts.as<double>(), st);
-            launch_bstate_start(Bt.parts.as<double>(), Bt.nch, m, Bt.state.as<BState>(), Bt.start.as<int32_t>(),
+            launch_bstate_start(ColParts{Bt.parts.as<double>(), Bt.nch, m, 1}, m, Bt.state.as<BState>(),
+                                Bt.start.as<int32_t>(),
                                 Bt.target2.as<double>(), o->maxit, st);
             launch_copy_flagged(n, m, Bt.Z.as<double>(), n, Bt.Pm.as<double>(), n, Bt.start.as<int32_t>(), st);
             RR_HIP(hipGetLastError());

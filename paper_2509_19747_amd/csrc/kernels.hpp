@@ -201,13 +201,22 @@ void launch_add_shift_cols(int64_t n, int64_t m, const double* mucol, const doub
 int coldot_chunks(int64_t n);
 void launch_coldot(int64_t n, int64_t m, const double* A, int64_t lda, const double* B, int64_t ldb,
                    double* part, hipStream_t st);
-void launch_bscal_alpha(const double* part, int nch, int64_t m, BState* st, hipStream_t s);
-void launch_bscal_rr(const double* part, int nch, int64_t m, BState* st, hipStream_t s);
-void launch_bscal_beta(const double* part, int nch, int64_t m, BState* st, hipStream_t s);
-void launch_bstate_start(const double* part, int nch, int64_t m, BState* st, const int32_t* start,
+// Per-column block partials: partial c of column j at p[c * cs + j * js], c < nch.
+struct ColParts {
+    const double* p;
+    int nch;
+    int64_t cs, js;
+};
+void launch_bscal_alpha(ColParts part, int64_t m, BState* st, hipStream_t s);
+void launch_bscal_rr(ColParts part, int64_t m, BState* st, hipStream_t s);
+void launch_bscal_beta(ColParts part, int64_t m, BState* st, hipStream_t s);
+void launch_bstate_start(ColParts part, int64_t m, BState* st, const int32_t* start,
                          const double* target2, int32_t maxit, hipStream_t s);
+// x_j += alpha_j p_j, r_j -= alpha_j w_j for running columns; rr_part (optional)
+// receives block partials of the new ||r_j||^2 at rr_part[j * bxr_blocks(n) + block].
+int bxr_blocks(int64_t n);
 void launch_bxr(int64_t n, int64_t m, double* X, int64_t ldx, double* R, const double* P,
-                const double* W, const BState* st, hipStream_t s);
+                const double* W, const BState* st, double* rr_part, hipStream_t s);
 void launch_bp(int64_t n, int64_t m, const double* Z, double* P, const BState* st, hipStream_t s);
 void launch_copy_flagged(int64_t n, int64_t m, const double* src, int64_t lds, double* dst,
                          int64_t ldd, const int32_t* flag, hipStream_t s);

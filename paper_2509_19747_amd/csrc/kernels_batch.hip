@@ -195,16 +195,16 @@ void launch_coldot(int64_t n, int64_t m, const double* A, int64_t lda, const dou
     k_coldot<<<grid, BC_THREADS, 0, st>>>(n, m, A, lda, B, ldb, part, rpc);
 }
 
-RR_DEV double colsum(const double* part, int nch, int64_t m, int64_t j) {
+RR_DEV double colsum(const ColParts& pt, int64_t j) {
     double s = 0.0;
-    for (int c = 0; c < nch; ++c) s += part[(int64_t)c * m + j];
+    for (int c = 0; c < pt.nch; ++c) s += pt.p[(int64_t)c * pt.cs + j * pt.js];
     return s;
 }
 
-__global__ void k_bscal_alpha(const double* __restrict__ part, int nch, int64_t m, BState* st) {
+__global__ void k_bscal_alpha(ColParts part, int64_t m, BState* st) {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= m || !st[j].run) return;
-    const double pw = colsum(part, nch, m, j);
+    const double pw = colsum(part, j);
     st[j].pw = pw;
     if (!(pw > 0.0) || !isfinite(pw)) {
         st[j].run = 0;
@@ -213,10 +213,10 @@ __global__ void k_bscal_alpha(const double* __restrict__ part, int nch, int64_t 
         st[j].alpha = st[j].rho / pw;
     }
 }
-__global__ void k_bscal_rr(const double* __restrict__ part, int nch, int64_t m, BState* st) {
+__global__ void k_bscal_rr(ColParts part, int64_t m, BState* st) {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= m || !st[j].run) return;
-    const double rr = colsum(part, nch, m, j);
+    const double rr = colsum(part, j);
     st[j].rr = rr;
     const int it = st[j].iters + 1;
     st[j].iters = it;
@@ -224,21 +224,21 @@ __global__ void k_bscal_rr(const double* __restrict__ part, int nch, int64_t m, 
     else if (rr <= st[j].target2) { st[j].run = 0; st[j].code = STOP_TARGET; }
     else if (it >= st[j].maxit) { st[j].run = 0; st[j].code = STOP_MAXIT; }
 }
-__global__ void k_bscal_beta(const double* __restrict__ part, int nch, int64_t m, BState* st) {
+__global__ void k_bscal_beta(ColParts part, int64_t m, BState* st) {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= m || !st[j].run) return;
-    const double rz = colsum(part, nch, m, j);
+    const double rz = colsum(part, j);
     if (!(rz > 0.0) || !isfinite(rz)) { st[j].run = 0; st[j].code = STOP_BREAKDOWN; return; }
     st[j].beta = rz / st[j].rho;
     st[j].rho = rz;
 }
 // start a cycle for the columns flagged in `start`: rho = r^T z, run = 1
-__global__ void k_bstate_start(const double* __restrict__ part, int nch, int64_t m, BState* st,
+__global__ void k_bstate_start(ColParts part, int64_t m, BState* st,
                                const int32_t* __restrict__ start, const double* __restrict__ target2,
                                int32_t maxit) {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= m || !start[j]) return;
-    const double rz = colsum(part, nch, m, j);
+    const double rz = colsum(part, j);
     st[j].rho = rz;
     st[j].alpha = st[j].beta = 0.0;
     st[j].target2 = target2[j];
@@ -248,25 +248,35 @@ __global__ void k_bstate_start(const double* __restrict__ part, int nch, int64_t
     if (!(rz > 0.0) || !isfinite(rz)) { st[j].run = 0; st[j].code = STOP_BREAKDOWN; }
 }
 static int cgrid(int64_t m) { return (int)((m + 255) / 256); }
-void launch_bscal_alpha(const double* part, int nch, int64_t m, BState* st, hipStream_t s) { k_bscal_alpha<<<cgrid(m), 256, 0, s>>>(part, nch, m, st); }
-void launch_bscal_rr(const double* part, int nch, int64_t m, BState* st, hipStream_t s) { k_bscal_rr<<<cgrid(m), 256, 0, s>>>(part, nch, m, st); }
-void launch_bscal_beta(const double* part, int nch, int64_t m, BState* st, hipStream_t s) { k_bscal_beta<<<cgrid(m), 256, 0, s>>>(part, nch, m, st); }
-void launch_bstate_start(const double* part, int nch, int64_t m, BState* st, const int32_t* start,
+void launch_bscal_alpha(ColParts part, int64_t m, BState* st, hipStream_t s) { k_bscal_alpha<<<cgrid(m), 256, 0, s>>>(part, m, st); }
+void launch_bscal_rr(ColParts part, int64_t m, BState* st, hipStream_t s) { k_bscal_rr<<<cgrid(m), 256, 0, s>>>(part, m, st); }
+void launch_bscal_beta(ColParts part, int64_t m, BState* st, hipStream_t s) { k_bscal_beta<<<cgrid(m), 256, 0, s>>>(part, m, st); }
+void launch_bstate_start(ColParts part, int64_t m, BState* st, const int32_t* start,
                          const double* target2, int32_t maxit, hipStream_t s) {
-    k_bstate_start<<<cgrid(m), 256, 0, s>>>(part, nch, m, st, start, target2, maxit);
+    k_bstate_start<<<cgrid(m), 256, 0, s>>>(part, m, st, start, target2, maxit);
 }
 
 // column blocks: grid (row chunks, m); the column's run flag is uniform per block
+// rr_part (optional): block partials of the new ||r_j||^2 at rr_part[j * gridDim.x + block]
 __global__ __launch_bounds__(BC_THREADS) void k_bxr(int64_t n, double* __restrict__ X, int64_t ldx,
                                                    double* __restrict__ R, const double* __restrict__ P,
-                                                   const double* __restrict__ W, const BState* st) {
+                                                   const double* __restrict__ W, const BState* st,
+                                                   double* __restrict__ rr_part) {
+    __shared__ double sc[BC_THREADS / WAVE];
     const int64_t j = blockIdx.y;
     if (!st[j].run) return;
     const double a = st[j].alpha;
+    double acc = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * BC_THREADS + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * BC_THREADS) {
         X[i + j * ldx] = fma(a, P[i + j * n], X[i + j * ldx]);
-        R[i + j * n] = fma(-a, W[i + j * n], R[i + j * n]);
+        const double ri = fma(-a, W[i + j * n], R[i + j * n]);
+        R[i + j * n] = ri;
+        acc = fma(ri, ri, acc);
+    }
+    if (rr_part) {
+        acc = block_sum(acc, sc);
+        if (threadIdx.x == 0) rr_part[j * gridDim.x + blockIdx.x] = acc;
     }
 }
 __global__ __launch_bounds__(BC_THREADS) void k_bp(int64_t n, const double* __restrict__ Z,
@@ -283,9 +293,10 @@ static dim3 vgrid(int64_t n, int64_t m) {
     if (gx < 1) gx = 1;
     return dim3((unsigned)gx, (unsigned)m);
 }
+int bxr_blocks(int64_t n) { return (int)vgrid(n, 1).x; }
 void launch_bxr(int64_t n, int64_t m, double* X, int64_t ldx, double* R, const double* P,
-                const double* W, const BState* st, hipStream_t s) {
-    k_bxr<<<vgrid(n, m), BC_THREADS, 0, s>>>(n, X, ldx, R, P, W, st);
+                const double* W, const BState* st, double* rr_part, hipStream_t s) {
+    k_bxr<<<vgrid(n, m), BC_THREADS, 0, s>>>(n, X, ldx, R, P, W, st, rr_part);
 }
 void launch_bp(int64_t n, int64_t m, const double* Z, double* P, const BState* st, hipStream_t s) {
     k_bp<<<vgrid(n, m), BC_THREADS, 0, s>>>(n, Z, P, st);
