@@ -20,6 +20,7 @@
 #include "kernels.hpp"
 
 #include <algorithm>
+#include <utility>
 
 namespace rr {
 
@@ -71,6 +72,12 @@ RR_DEV void hb_block_sum_t(double (&v)[NV], double* buf, double* tot) {
     for (int q2 = 0; q2 < NV; ++q2) v[q2] = tot[q2];
 }
 
+// f(integral_constant<int, C>) for C in the sequence, in order
+template <typename F, int... C>
+RR_DEV void hb_unrolled(F& f, std::integer_sequence<int, C...>) {
+    (f(std::integral_constant<int, C>{}), ...);
+}
+
 // Factor columns [j0, j0 + nbe) of S (rows [j0, m)), nbe <= NB; m - j0 <= RR * 512.
 // Writes V[:, j0..] (zeros above the diagonal), tau[j0..], T (NB x NB, column-major,
 // ldt NB) and R[0:k, j0..] (rows above the panel from S, which already holds them).
@@ -81,11 +88,10 @@ __global__ __launch_bounds__(HB_THREADS) void k_panel_qr(const double* __restric
                                                          double* __restrict__ tauv,
                                                          double* __restrict__ T,
                                                          double* __restrict__ R, int64_t ldr) {
-    __shared__ double red[HB_WAVES * NB];
     __shared__ double tot[NB];
     __shared__ double dbuf[NB * HB_THREADS];
     __shared__ double Tsh[NB * NB];
-    __shared__ double s_alpha;
+    __shared__ double prow[2][NB];
     const int t = threadIdx.x;
     double a[RR][NB];
 #pragma unroll
@@ -103,59 +109,62 @@ __global__ __launch_bounds__(HB_THREADS) void k_panel_qr(const double* __restric
     double rsave[NB];
 #pragma unroll
     for (int c = 0; c < NB; ++c) rsave[c] = 0.0;
-    // the column loop is unrolled so that every register index is static
-#pragma unroll
-    for (int c = 0; c < NB; ++c) {
-        if (c >= nbe) continue;   // uniform over the block
+    // One block reduction per column.  With x = column c at rows >= kc and the
+    // pivot-row entries p_q = a[kc][q], the sums s_q = x^T a_q (all panel columns,
+    // q = c included) give everything the step needs:
+    //   ||x||^2 = s_c,  v = x - beta e_kc,  v^T a_q = s_q - beta p_q,
+    //   v^T v = v0^2 + (s_c - alpha^2)  (v0^2 >= alpha^2 dominates, so the
+    //   difference costs no relative accuracy).
+    // The previous reflectors (q < c) give V(:, q)^T v for T the same way.  The
+    // pivot row is published through LDS, double-buffered so that a thread still
+    // reading the previous column's entries never sees the next one's.
+    // one instance per column, so that every register index is static
+    auto column = [&](auto cc) {
+        constexpr int c = decltype(cc)::value;
+        if (c >= nbe) return;   // uniform over the block
         const int64_t kc = j0 + c;
-        // x = column c at rows >= kc; the pivot row kc is thread c, register row 0
-        double s1[1] = {0.0};
+        double* pr = prow[c & 1];
+        // the pivot row kc is thread c, register row 0
+        if (t == c)
 #pragma unroll
-        for (int r = 0; r < RR; ++r) {
-            const int64_t i = j0 + t + (int64_t)HB_THREADS * r;
-            const double x = a[r][c];
-            if (i > kc && i < m) s1[0] = fma(x, x, s1[0]);
-            if (i == kc) s_alpha = x;
-        }
-        hb_block_sum<1>(s1, red, tot);   // barriers also publish s_alpha
-        const double alpha = s_alpha;
-        const double normx = sqrt(fma(alpha, alpha, s1[0]));
-        const double beta = (alpha >= 0.0) ? -normx : normx;
-        const double v0 = alpha - beta;
-        const double vtv = fma(v0, v0, s1[0]);
-        const double f = (vtv > 0.0) ? 2.0 / vtv : 0.0;
-        // R entries of column kc in the panel rows (thread t < c holds row j0 + t, thread
-        // c the diagonal) are kept in registers and stored after the loop: a global
-        // store here would make every following barrier wait for it.
-        if (t < c) rsave[c] = a[0][c];
-        else if (t == c) rsave[c] = (normx > 0.0) ? beta : alpha;
-        // v into column c (zeros above the pivot)
-#pragma unroll
-        for (int r = 0; r < RR; ++r) {
-            const int64_t i = j0 + t + (int64_t)HB_THREADS * r;
-            a[r][c] = (i < kc || i >= m) ? 0.0 : (i == kc ? v0 : a[r][c]);
-        }
-        // dots of v with every panel column: previous reflectors (for T) and the
-        // columns still to be reduced (for the update)
+            for (int q = 0; q < NB; ++q) pr[q] = a[0][q];
         double dots[NB];
 #pragma unroll
         for (int q = 0; q < NB; ++q) dots[q] = 0.0;
 #pragma unroll
         for (int r = 0; r < RR; ++r) {
-            const double v = a[r][c];
+            const int64_t i = j0 + t + (int64_t)HB_THREADS * r;
+            const double x = (i >= kc && i < m) ? a[r][c] : 0.0;
 #pragma unroll
-            for (int q = 0; q < NB; ++q) dots[q] = fma(v, a[r][q], dots[q]);
+            for (int q = 0; q < NB; ++q) dots[q] = fma(x, a[r][q], dots[q]);
         }
-        hb_block_sum_t<NB>(dots, dbuf, tot);
+        hb_block_sum_t<NB>(dots, dbuf, tot);   // its barriers also publish the pivot row
+        const double alpha = pr[c];
+        const double sc = dots[c];
+        const double normx = sqrt(sc);
+        const double beta = (alpha >= 0.0) ? -normx : normx;
+        const double v0 = alpha - beta;
+        const double vtv = fma(v0, v0, sc - alpha * alpha);
+        const double f = (vtv > 0.0) ? 2.0 / vtv : 0.0;
+#pragma unroll
+        for (int q = 0; q < NB; ++q) dots[q] = fma(-beta, pr[q], dots[q]);
+        // R entries of column kc in the panel rows (thread t < c holds row j0 + t, thread
+        // c the diagonal) are kept in registers and stored after the loop: a global
+        // store here would make every following barrier wait for it.
+        if (t < c) rsave[c] = a[0][c];
+        else if (t == c) rsave[c] = (normx > 0.0) ? beta : alpha;
+        // v into column c (zeros above the pivot), then the columns still to be reduced
 #pragma unroll
         for (int r = 0; r < RR; ++r) {
-            const double v = a[r][c];
+            const int64_t i = j0 + t + (int64_t)HB_THREADS * r;
+            const double v = (i < kc || i >= m) ? 0.0 : (i == kc ? v0 : a[r][c]);
+            a[r][c] = v;
 #pragma unroll
             for (int q = c + 1; q < NB; ++q)   // columns past nbe hold zeros and stay zero
                 a[r][q] = fma(-f * dots[q], v, a[r][q]);
         }
         // T(:, c): T(c, c) = f, T(0:c, c) = -f T(0:c, 0:c) (V(:, 0:c)^T v); thread i
-        // forms row i (it reads only columns < c, which no thread writes now)
+        // forms row i of T and reads only its own row, so no barrier is needed
         if (t < c) {
             double s = 0.0;
 #pragma unroll
@@ -165,8 +174,9 @@ __global__ __launch_bounds__(HB_THREADS) void k_panel_qr(const double* __restric
         } else if (t == c) {
             Tsh[c + c * NB] = f;
         }
-        __syncthreads();
-    }
+    };
+    hb_unrolled(column, std::make_integer_sequence<int, NB>{});
+    __syncthreads();
     // reflectors out (rows < j0 are zero)
 #pragma unroll
     for (int r = 0; r < RR; ++r) {
