@@ -10,6 +10,7 @@
 #include "kernels.hpp"
 
 #include <algorithm>
+#include <type_traits>
 
 namespace rr {
 
@@ -307,9 +308,139 @@ __global__ __launch_bounds__(256) void k_tri_inv_upper(const double* R, int64_t 
     for (int64_t i = threadIdx.x; i < l; i += blockDim.x) X[i + j * ldx] = (i <= j) ? xs[i] : 0.0;
 }
 
+// One wave per column j of X = R^{-1}, for l <= 64 U: lane t holds rows t + 64 u
+// (u < U) of the column in registers.  Back substitution from row j up: row r's
+// value is final once the rows below it are done; the wave reads it from its lane
+// (readlane), scales it by 1 / R_rr and subtracts its multiple of column r of R
+// from the rows above it, so a step's dependency chain is a readlane, a multiply
+// and an FMA.  Everything else is kept off that chain: the columns of R come in
+// panels of CP columns through LDS (two buffers), each panel's global loads issued
+// two panels before its steps run (two register sets), the panel's LDS reads
+// issued together before its steps, and 1 / R_rr formed per panel in parallel.
+RR_DEV double tri_readlane(double x, int l) {
+    const uint64_t b = (uint64_t)__double_as_longlong(x);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, l);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), l);
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+template <int U, int CP>
+__global__ __launch_bounds__(64) void k_tri_inv_upper_wave(const double* __restrict__ R, int64_t l,
+                                                           int64_t ldr, double* __restrict__ X,
+                                                           int64_t ldx) {
+    static_assert(64 % (2 * CP) == 0, "a slot holds an even number of panels");
+    constexpr int LR = 64 * U;       // LDS rows per staged column
+    extern __shared__ double rs[];   // 2 buffers x CP columns x LR rows
+    const int lane = threadIdx.x;
+    const int j = (int)blockIdx.x;
+    const int uj = j >> 6;
+    double v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = (64 * u + lane == j) ? 1.0 : 0.0;
+    // panel p = columns p CP + c (c < CP), entries at rows <= the column; columns
+    // past j (and panels p < 0) load as zeros and their steps are skipped
+    double ga[CP][U], gb[CP][U];
+    // The loads are unconditional (clamped addresses, masked values): no branches
+    // around them, so the wait before staging a panel covers only that panel's
+    // loads and not the ones just issued for the panel after it.
+    auto gload = [&](int p, double (&g)[CP][U]) {
+#pragma unroll
+        for (int c = 0; c < CP; ++c) {
+            const int r = p * CP + c;
+            const int rc = r < 0 ? 0 : (r > j ? j : r);
+#pragma unroll
+            for (int w = 0; w < U; ++w) {
+                const int i = 64 * w + lane;
+                const double x = R[(i < rc ? i : rc) + (int64_t)rc * ldr];
+                g[c][w] = (r >= 0 && r <= j && i <= r) ? x : 0.0;
+            }
+        }
+    };
+    auto lstore = [&](int p, const double (&g)[CP][U]) {
+        double* dst = rs + (p & 1) * CP * LR;
+#pragma unroll
+        for (int c = 0; c < CP; ++c)
+#pragma unroll
+            for (int w = 0; w < U; ++w) dst[c * LR + 64 * w + lane] = g[c][w];
+    };
+    // the steps of panel p (rows of slot u), its columns read from LDS
+    auto steps = [&](int p, auto uc) {
+        constexpr int u = decltype(uc)::value;
+        const double* Rb = rs + (p & 1) * CP * LR;
+        const int rlo = p * CP;
+        double col[CP][u + 1];
+#pragma unroll
+        for (int c = 0; c < CP; ++c)
+#pragma unroll
+            for (int w = 0; w <= u; ++w) col[c][w] = Rb[c * LR + 64 * w + lane];
+        const double dinv = lane < CP ? 1.0 / Rb[lane * LR + rlo + lane] : 0.0;
+#pragma unroll
+        for (int c = CP - 1; c >= 0; --c) {
+            const int r = rlo + c;
+            if (r > j) continue;   // uniform over the wave
+            const int rr = r - 64 * u;
+            const double xr = tri_readlane(v[u], rr) * tri_readlane(dinv, c);
+            if (lane == rr) v[u] = xr;
+#pragma unroll
+            for (int w = 0; w < u; ++w) v[w] = fma(-col[c][w], xr, v[w]);
+            if (lane < rr) v[u] = fma(-col[c][u], xr, v[u]);
+        }
+    };
+    // panel p's steps with panel p - 1 in flight in `hold`: load p - 2 into `free`,
+    // run p, then stage p - 1 (its buffer was last read before the previous barrier)
+    auto panel = [&](int p, auto uc, double (&hold)[CP][U], double (&free)[CP][U]) {
+        gload(p - 2, free);
+        steps(p, uc);
+        lstore(p - 1, hold);
+        __syncthreads();
+    };
+    // slot uj starts at an even panel count from its bottom (a leading panel past j
+    // is empty), so every slot runs whole pairs and the register roles line up
+    const int ppb = 64 / CP;                          // panels per slot
+    int p0 = uj * ppb + ((j - 64 * uj) / CP | 1);     // odd offset within the slot
+    gload(p0, ga);
+    lstore(p0, ga);
+    gload(p0 - 1, ga);
+    __syncthreads();
+    auto slot = [&](auto uc) {
+        constexpr int u = decltype(uc)::value;
+        if (u > uj) return;
+        const int ptop = (u == uj) ? p0 : u * ppb + ppb - 1;
+        for (int p = ptop; p >= u * ppb; p -= 2) {
+            panel(p, uc, ga, gb);
+            panel(p - 1, uc, gb, ga);
+        }
+    };
+    [&] {
+        auto down = [&](auto self, auto uc) -> void {
+            constexpr int u = decltype(uc)::value;
+            slot(uc);
+            if constexpr (u > 0) self(self, std::integral_constant<int, u - 1>{});
+        };
+        down(down, std::integral_constant<int, U - 1>{});
+    }();
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int i = 64 * u + lane;
+        if (i < l) X[i + (int64_t)j * ldx] = (i <= j) ? v[u] : 0.0;
+    }
+}
+
+template <int U, int CP>
+static void tri_inv_wave(const double* R, int64_t l, int64_t ldr, double* X, int64_t ldx, hipStream_t st) {
+    const size_t shm = (size_t)2 * CP * 64 * U * sizeof(double);
+    k_tri_inv_upper_wave<U, CP><<<(unsigned)l, 64, shm, st>>>(R, l, ldr, X, ldx);
+}
+
 void launch_tri_inv_upper(const double* R, int64_t l, int64_t ldr, double* X, int64_t ldx,
                           hipStream_t st) {
-    k_tri_inv_upper<<<(unsigned)l, 256, (size_t)l * sizeof(double), st>>>(R, l, ldr, X, ldx);
+    if (l <= 0) return;
+    const int64_t slots = (l + 63) / 64;
+    if (slots <= 1) tri_inv_wave<1, 4>(R, l, ldr, X, ldx, st);
+    else if (slots <= 2) tri_inv_wave<2, 4>(R, l, ldr, X, ldx, st);
+    else if (slots <= 4) tri_inv_wave<4, 4>(R, l, ldr, X, ldx, st);
+    else if (slots <= 8) tri_inv_wave<8, 4>(R, l, ldr, X, ldx, st);
+    else k_tri_inv_upper<<<(unsigned)l, 256, (size_t)l * sizeof(double), st>>>(R, l, ldr, X, ldx);
 }
 
 }  // namespace rr
