@@ -279,41 +279,64 @@ __global__ __launch_bounds__(KM_THREADS) __attribute__((amdgpu_waves_per_eu(NR *
 }
 
 // y_q = scale * (sum of row i's slots) + mu u_q, with block partials of u_q^T y_q.
-__global__ __launch_bounds__(256) void k_ksym_mma_finish(int64_t n, int rb, int nb, int m, int S, int nr,
-                                                         const double* __restrict__ part,
-                                                         double scale, double mu,
-                                                         const double* __restrict__ u,
-                                                         double* __restrict__ y,
-                                                         double* __restrict__ dot_part,
-                                                         const int32_t* __restrict__ stop) {
+// Block: the 256 rows of one row block b (so the slot list is uniform over the
+// block) and 1024 threads: four groups of 256 split the list
+//   column slots p S (p < b), the run slots b S .. z1 - 1, the diagonal slot nb S
+// into four contiguous quarters, each summed with four running sums, and group 0
+// adds the quarters in a fixed order (bitwise reproducible, the same for one or
+// two columns).
+constexpr int KF_GROUPS = 4;
+__global__ __launch_bounds__(256 * KF_GROUPS) void k_ksym_mma_finish(int64_t n, int rb, int nb, int m, int S,
+                                                                     int nr,
+                                                                     const double* __restrict__ part,
+                                                                     double scale, double mu,
+                                                                     const double* __restrict__ u,
+                                                                     double* __restrict__ y,
+                                                                     double* __restrict__ dot_part,
+                                                                     const int32_t* __restrict__ stop) {
+    __shared__ double quart[KF_GROUPS - 1][256];
     __shared__ double sc[4];
     if (stop && *stop) return;
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const int b = (int)(i / rb);
+    const int t = threadIdx.x & 255, g = threadIdx.x >> 8;
+    const int64_t i = (int64_t)blockIdx.x * 256 + t;
+    const int b = (int)(((int64_t)blockIdx.x * 256) / rb);
+    const int64_t z1 = (int64_t)(b + (nb - b + m - 1) / m) * S;
+    const int64_t nrun = z1 - (int64_t)b * S;
+    const int64_t T = b + nrun + 1;
+    const int64_t k0 = T * g / KF_GROUPS, k1 = T * (g + 1) / KF_GROUPS;
+    auto slot = [&](int64_t k) -> int64_t {
+        return k < b ? k * S : (k < b + nrun ? (int64_t)b * S + (k - b) : (int64_t)nb * S);
+    };
     for (int q = 0; q < nr; ++q) {
-        double dot = 0.0;
+        double s = 0.0;
         if (i < n) {
-            // slots in a fixed order, four running sums so that loads stay in flight
             double s4[4] = {0.0, 0.0, 0.0, 0.0};
-            int p = 0;
-            for (; p + 4 <= b; p += 4)
+            int64_t k = k0;
+            for (; k + 4 <= k1; k += 4)
 #pragma unroll
-                for (int w = 0; w < 4; ++w) s4[w] += part[((int64_t)(p + w) * S * nr + q) * n + i];
-            for (; p < b; ++p) s4[0] += part[((int64_t)p * S * nr + q) * n + i];
-            const int64_t z1 = (int64_t)(b + (nb - b + m - 1) / m) * S;
-            int64_t z = (int64_t)b * S;
-            for (; z + 4 <= z1; z += 4)
-#pragma unroll
-                for (int w = 0; w < 4; ++w) s4[w] += part[((z + w) * nr + q) * n + i];
-            for (; z < z1; ++z) s4[0] += part[(z * nr + q) * n + i];
-            const double s = ((s4[0] + s4[1]) + (s4[2] + s4[3])) + part[((int64_t)nb * S * nr + q) * n + i];
+                for (int w = 0; w < 4; ++w) s4[w] += part[(slot(k + w) * nr + q) * n + i];
+            for (; k < k1; ++k) s4[0] += part[(slot(k) * nr + q) * n + i];
+            s = (s4[0] + s4[1]) + (s4[2] + s4[3]);
+        }
+        // quart and sc are reused for the next column only after the barrier below
+        if (g > 0) quart[g - 1][t] = s;
+        __syncthreads();
+        double dot = 0.0;
+        if (g == 0 && i < n) {
+            const double tot = (s + quart[0][t]) + (quart[1][t] + quart[2][t]);
             const double ui = u[(int64_t)q * n + i];
-            const double yi = fma(scale, s, mu * ui);
+            const double yi = fma(scale, tot, mu * ui);
             y[(int64_t)q * n + i] = yi;
             dot = ui * yi;
         }
-        dot = block_sum(dot, sc);
-        if (threadIdx.x == 0) dot_part[(int64_t)q * gridDim.x + blockIdx.x] = dot;
+        if (g == 0) {
+            dot = wave_sum(dot);
+            if ((t & 63) == 0) sc[t >> 6] = dot;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0)
+            dot_part[(int64_t)q * gridDim.x + blockIdx.x] = (sc[0] + sc[1]) + (sc[2] + sc[3]);
+        __syncthreads();
     }
 }
 
@@ -364,7 +387,7 @@ void launch_kernel_matvec_mma(const KernelOp& op, const double* u, int nr, doubl
         if (op.kind == 1) { KMD(1) } else { KMD(2) }
 #undef KMD
     }
-    k_ksym_mma_finish<<<(unsigned)((op.n + 255) / 256), 256, 0, st>>>(op.n, KM_RB, p.nb, p.m, p.S, nr, ws,
+    k_ksym_mma_finish<<<(unsigned)((op.n + 255) / 256), 256 * KF_GROUPS, 0, st>>>(op.n, KM_RB, p.nb, p.m, p.S, nr, ws,
                                                                       op.scale, mu, u, y, dot_part,
                                                                       stop);
 }
