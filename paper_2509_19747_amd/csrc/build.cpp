@@ -53,6 +53,13 @@ struct Builder {
         launch_gemm(dta, ta, dtb, tb, M, N, K, A, lda, B, ldb, C, ldc, alpha, beta, gws.as<double>(),
                     gwsd, st);
     }
+    // C = op(A) B (float64) with B upper triangular and zero below the diagonal (an
+    // inverse from launch_tri_inv_upper): the MFMA kernel skips the zero blocks
+    void gemm_upper_b(bool ta, int64_t M, int64_t N, int64_t K, const double* A, int64_t lda,
+                      const double* B, int64_t ldb, double* C, int64_t ldc) {
+        if (!launch_gemm_upper_b(ta, M, N, K, A, lda, B, ldb, C, ldc, gws.as<double>(), gwsd, st))
+            gemm(DT_F64, ta, DT_F64, false, M, N, K, A, lda, B, ldb, C, ldc);
+    }
     // C = A^T A (A: K x M float64): symmetric MFMA product, else the general GEMM
     void gram(int64_t M, int64_t K, const double* A, int64_t lda, double* C, int64_t ldc) {
         if (!launch_gemm_ata(M, K, A, lda, C, ldc, gws.as<double>(), gwsd, st)) {
@@ -239,13 +246,13 @@ struct Builder {
             DBuf Rskinv = mat(k, k);
             launch_tri_inv_upper(Rsk.as<double>(), k, k, Rskinv.as<double>(), k, st);
             DBuf W = mat(n, k);
-            gemm(DT_F64, true, DT_F64, false, n, k, k, yt, k, Rskinv.ptr(), k, W.as<double>(), n);
+            gemm_upper_b(true, n, k, k, yt, k, Rskinv.as<double>(), k, W.as<double>(), n);
             DBuf GW = mat(k, k);
             gram(k, n, W.as<double>(), n, GW.as<double>(), k);
             chol_ladder(GW.as<double>(), k);            // GW <- R_chol
             DBuf Rcinv = mat(k, k);
             launch_tri_inv_upper(GW.as<double>(), k, k, Rcinv.as<double>(), k, st);
-            gemm(DT_F64, false, DT_F64, false, n, k, k, W.ptr(), n, Rcinv.ptr(), k, Q, n);
+            gemm_upper_b(false, n, k, k, W.as<double>(), n, Rcinv.as<double>(), k, Q, n);
             gemm(DT_F64, false, DT_F64, false, k, k, k, GW.ptr(), k, Rsk.ptr(), k, R, k);  // R = R_chol R_sk
             launch_zero_lower(R, k, k, st);
         } else {
@@ -254,7 +261,7 @@ struct Builder {
             chol_ladder(R, k);
             DBuf Rinv = mat(k, k);
             launch_tri_inv_upper(R, k, k, Rinv.as<double>(), k, st);
-            gemm(DT_F64, true, DT_F64, false, n, k, k, yt, k, Rinv.ptr(), k, Q, n);
+            gemm_upper_b(true, n, k, k, yt, k, Rinv.as<double>(), k, Q, n);
         }
         check_launch();
         if (yt_out) *yt_out = std::move(Yt);

@@ -64,15 +64,21 @@ void launch_gemm(int dta, bool trA, int dtb, bool trB, int64_t M, int64_t N, int
 
 // The same on float64 MFMA for float64/float32 operands with M, N >= 32 (returns
 // false, doing nothing, otherwise); launch_gemm tries it first.
+bool launch_gemm_mfma(int dta, bool trA, int dtb, bool trB, int64_t M, int64_t N, int64_t K,
+                      const void* A, int64_t lda, const void* B, int64_t ldb, double* C,
+                      int64_t ldc, double alpha, double beta, double* ws, size_t wsd,
+                      hipStream_t st);
 // C (M x M) = A^T A for float64 A (K x M, column-major): only the tiles on and
 // above the diagonal are multiplied, then mirrored, so C is exactly symmetric.
 // Returns false (nothing launched) when the MFMA path does not apply (M < 32 or K < 16).
 bool launch_gemm_ata(int64_t M, int64_t K, const double* A, int64_t lda, double* C, int64_t ldc,
                      double* ws, size_t wsd, hipStream_t st);
-bool launch_gemm_mfma(int dta, bool trA, int dtb, bool trB, int64_t M, int64_t N, int64_t K,
-                      const void* A, int64_t lda, const void* B, int64_t ldb, double* C,
-                      int64_t ldc, double alpha, double beta, double* ws, size_t wsd,
-                      hipStream_t st);
+// C = op(A) B (float64) for B upper triangular with zeros stored below its diagonal
+// (column block j reads only rows k < its last column); false when the sizes are
+// too small for the MFMA kernel.
+bool launch_gemm_upper_b(bool trA, int64_t M, int64_t N, int64_t K, const double* A, int64_t lda,
+                         const double* B, int64_t ldb, double* C, int64_t ldc, double* ws, size_t wsd,
+                         hipStream_t st);
 
 // ------------------------------------------------------ small dense helpers
 void launch_symmetrize(double* A, int64_t l, int64_t lda, hipStream_t st);

@@ -56,7 +56,8 @@ __global__ __launch_bounds__(GM_THREADS) void k_gemm_mfma(int64_t M, int64_t N, 
                                                           double* __restrict__ C, int64_t ldc,
                                                           double alpha, double beta, int64_t kchunk,
                                                           double* __restrict__ part, int64_t gn,
-                                                          int64_t ntiles, int64_t nwork, int64_t per_xcd) {
+                                                          int64_t ntiles, int64_t nwork, int64_t per_xcd,
+                                                          bool b_upper) {
     __shared__ double As[GM_BK][GM_BM + GM_PAD];
     __shared__ double Bs[GM_BK][GM_BN + GM_PAD];
     // XCD-aware order: workgroups go to the 8 XCDs round robin, so block b runs on
@@ -83,7 +84,10 @@ __global__ __launch_bounds__(GM_THREADS) void k_gemm_mfma(int64_t M, int64_t N, 
     const int64_t i0 = bx * GM_BM;
     const int64_t j0 = by * GM_BN;
     const int64_t kb = bz * kchunk;
-    const int64_t ke = std::min<int64_t>(kb + kchunk, K);
+    int64_t ke = std::min<int64_t>(kb + kchunk, K);
+    // op(B) upper triangular (zeros stored below the diagonal): column block j0 needs
+    // only k < j0 + GM_BN
+    if (b_upper) ke = std::min<int64_t>(ke, j0 + GM_BN);
 
     f64x4_t acc[2][2];
 #pragma unroll
@@ -169,7 +173,7 @@ __global__ void k_gemm_mfma_reduce(int64_t M, int64_t N, int splits, const doubl
 template <typename TA, typename TB, bool TRA, bool TRB, bool SYM = false>
 static void gm_run(int64_t M, int64_t N, int64_t K, const void* A, int64_t lda, const void* B,
                    int64_t ldb, double* C, int64_t ldc, double alpha, double beta, double* ws,
-                   size_t wsd, hipStream_t st) {
+                   size_t wsd, hipStream_t st, bool b_upper = false) {
     const int64_t gm = (M + GM_BM - 1) / GM_BM, gn = (N + GM_BN - 1) / GM_BN;
     const int64_t kblocks = (K + GM_BK - 1) / GM_BK;
     const int64_t tiles = SYM ? gm * (gm + 1) / 2 : gm * gn;   // tiles that do work
@@ -191,7 +195,7 @@ static void gm_run(int64_t M, int64_t N, int64_t K, const void* A, int64_t lda, 
     k_gemm_mfma<TA, TB, TRA, TRB, SYM><<<grid, GM_THREADS, 0, st>>>(M, N, K, (const TA*)A, lda,
                                                                (const TB*)B, ldb, C, ldc, alpha,
                                                                beta, kchunk, part, gn, tiles, work,
-                                                               per_xcd);
+                                                               per_xcd, b_upper);
     if (part) {
         const int64_t g = std::min<int64_t>((M * N + 255) / 256, 16384);
         k_gemm_mfma_reduce<<<(unsigned)g, 256, 0, st>>>(M, N, (int)splits, part, C, ldc, alpha, beta);
@@ -225,6 +229,15 @@ bool launch_gemm_ata(int64_t M, int64_t K, const double* A, int64_t lda, double*
     gm_run<double, double, true, false, true>(M, M, K, A, lda, A, lda, C, ldc, 1.0, 0.0, ws, wsd, st);
     const int64_t g = std::min<int64_t>((M * M + 255) / 256, 16384);
     k_mirror_upper<<<(unsigned)g, 256, 0, st>>>(M, C, ldc);
+    return true;
+}
+
+bool launch_gemm_upper_b(bool trA, int64_t M, int64_t N, int64_t K, const double* A, int64_t lda,
+                         const double* B, int64_t ldb, double* C, int64_t ldc, double* ws, size_t wsd,
+                         hipStream_t st) {
+    if (M < 32 || N < 32 || K < 16) return false;
+    if (trA) gm_run<double, double, true, false>(M, N, K, A, lda, B, ldb, C, ldc, 1.0, 0.0, ws, wsd, st, true);
+    else gm_run<double, double, false, false>(M, N, K, A, lda, B, ldb, C, ldc, 1.0, 0.0, ws, wsd, st, true);
     return true;
 }
 
