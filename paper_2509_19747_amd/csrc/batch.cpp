@@ -38,6 +38,7 @@ struct Batch {
     DBuf cpart, dcols, rzp;   // projection through the basis, groups of up to 8 columns
     int pmax = 0, gch = 1;
     DBuf rrp;                 // block partials of ||r_j||^2 from the x, r update
+    DBuf cnt;                 // per-column block counters of the fused updates (2 m int32)
     bool single = false;      // every column under one shift mu1
     double mu1 = 0.0;
     size_t gwsd = 0;
@@ -71,7 +72,9 @@ struct Batch {
             kdot.reset(al, (size_t)kernel_matvec_blocks(n) * m * sizeof(double));
         }
         rrp.reset(al, (size_t)bxr_blocks(n) * m * sizeof(double));
+        cnt.reset(al, (size_t)2 * m * sizeof(int32_t));
         RR_HIP(hipMemsetAsync(state.ptr(), 0, (size_t)m * sizeof(BState), st));
+        RR_HIP(hipMemsetAsync(cnt.ptr(), 0, (size_t)2 * m * sizeof(int32_t), st));
     }
 
     // Few columns under one shift: the projection is a streaming pass over Qb per
@@ -172,16 +175,13 @@ struct Batch {
         double* z = Z.as<double>();
         double* pp = parts.as<double>();
         const ColParts own{pp, nch, m, 1};
+        int32_t* c = cnt.as<int32_t>();
         ColParts pw = matmat(p, n, w, false);
         if (!pw.p) { launch_coldot(n, m, p, n, w, n, pp, st); pw = own; }
-        launch_bscal_alpha(pw, m, s, st);
-        const int gx = bxr_blocks(n);
-        launch_bxr(n, m, X, ldx, r, p, w, s, rrp.as<double>(), st);
-        launch_bscal_rr(ColParts{rrp.as<double>(), gx, 1, gx}, m, s, st);
+        launch_bxr_fused(n, m, X, ldx, r, p, w, s, pw, rrp.as<double>(), c, st);
         ColParts rz = precond(r, z);
         if (!rz.p) { launch_coldot(n, m, r, n, z, n, pp, st); rz = own; }
-        launch_bscal_beta(rz, m, s, st);
-        launch_bp(n, m, z, p, s, st);
+        launch_bp_fused(n, m, z, p, s, rz, c + m, st);
     }
 };
 

@@ -213,17 +213,20 @@ struct ColParts {
     int nch;
     int64_t cs, js;
 };
-void launch_bscal_alpha(ColParts part, int64_t m, BState* st, hipStream_t s);
-void launch_bscal_rr(ColParts part, int64_t m, BState* st, hipStream_t s);
-void launch_bscal_beta(ColParts part, int64_t m, BState* st, hipStream_t s);
 void launch_bstate_start(ColParts part, int64_t m, BState* st, const int32_t* start,
                          const double* target2, int32_t maxit, hipStream_t s);
-// x_j += alpha_j p_j, r_j -= alpha_j w_j for running columns; rr_part (optional)
-// receives block partials of the new ||r_j||^2 at rr_part[j * bxr_blocks(n) + block].
+// Blocks per column of the fused x/r and p updates (rr_part of the x/r update holds
+// bxr_blocks(n) partials per column, at rr_part[j * bxr_blocks(n) + block]).
 int bxr_blocks(int64_t n);
-void launch_bxr(int64_t n, int64_t m, double* X, int64_t ldx, double* R, const double* P,
-                const double* W, const BState* st, double* rr_part, hipStream_t s);
-void launch_bp(int64_t n, int64_t m, const double* Z, double* P, const BState* st, hipStream_t s);
+// The x/r update with alpha folded in (alpha_j = rho_j / sum of pw's partials, formed
+// by every block) and the p update with beta folded in (beta_j = sum of rz's partials
+// / rho_j); the last block of each column records the scalars and stop tests (what
+// launch_bscal_alpha / _rr / _beta do) and resets its counter: cnt holds m int32
+// that are zero between launches.
+void launch_bxr_fused(int64_t n, int64_t m, double* X, int64_t ldx, double* R, const double* P,
+                      const double* W, BState* st, ColParts pw, double* rr_part, int32_t* cnt, hipStream_t s);
+void launch_bp_fused(int64_t n, int64_t m, const double* Z, double* P, BState* st, ColParts rz, int32_t* cnt,
+                     hipStream_t s);
 void launch_copy_flagged(int64_t n, int64_t m, const double* src, int64_t lds, double* dst,
                          int64_t ldd, const int32_t* flag, hipStream_t s);
 void launch_bresid(int64_t n, int64_t m, const double* B, int64_t ldb, const double* T, double* Rt,

@@ -201,37 +201,6 @@ RR_DEV double colsum(const ColParts& pt, int64_t j) {
     return s;
 }
 
-__global__ void k_bscal_alpha(ColParts part, int64_t m, BState* st) {
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= m || !st[j].run) return;
-    const double pw = colsum(part, j);
-    st[j].pw = pw;
-    if (!(pw > 0.0) || !isfinite(pw)) {
-        st[j].run = 0;
-        st[j].code = STOP_BREAKDOWN;
-    } else {
-        st[j].alpha = st[j].rho / pw;
-    }
-}
-__global__ void k_bscal_rr(ColParts part, int64_t m, BState* st) {
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= m || !st[j].run) return;
-    const double rr = colsum(part, j);
-    st[j].rr = rr;
-    const int it = st[j].iters + 1;
-    st[j].iters = it;
-    if (!isfinite(rr)) { st[j].run = 0; st[j].code = STOP_BREAKDOWN; }
-    else if (rr <= st[j].target2) { st[j].run = 0; st[j].code = STOP_TARGET; }
-    else if (it >= st[j].maxit) { st[j].run = 0; st[j].code = STOP_MAXIT; }
-}
-__global__ void k_bscal_beta(ColParts part, int64_t m, BState* st) {
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= m || !st[j].run) return;
-    const double rz = colsum(part, j);
-    if (!(rz > 0.0) || !isfinite(rz)) { st[j].run = 0; st[j].code = STOP_BREAKDOWN; return; }
-    st[j].beta = rz / st[j].rho;
-    st[j].rho = rz;
-}
 // start a cycle for the columns flagged in `start`: rho = r^T z, run = 1
 __global__ void k_bstate_start(ColParts part, int64_t m, BState* st,
                                const int32_t* __restrict__ start, const double* __restrict__ target2,
@@ -248,59 +217,109 @@ __global__ void k_bstate_start(ColParts part, int64_t m, BState* st,
     if (!(rz > 0.0) || !isfinite(rz)) { st[j].run = 0; st[j].code = STOP_BREAKDOWN; }
 }
 static int cgrid(int64_t m) { return (int)((m + 255) / 256); }
-void launch_bscal_alpha(ColParts part, int64_t m, BState* st, hipStream_t s) { k_bscal_alpha<<<cgrid(m), 256, 0, s>>>(part, m, st); }
-void launch_bscal_rr(ColParts part, int64_t m, BState* st, hipStream_t s) { k_bscal_rr<<<cgrid(m), 256, 0, s>>>(part, m, st); }
-void launch_bscal_beta(ColParts part, int64_t m, BState* st, hipStream_t s) { k_bscal_beta<<<cgrid(m), 256, 0, s>>>(part, m, st); }
 void launch_bstate_start(ColParts part, int64_t m, BState* st, const int32_t* start,
                          const double* target2, int32_t maxit, hipStream_t s) {
     k_bstate_start<<<cgrid(m), 256, 0, s>>>(part, m, st, start, target2, maxit);
 }
 
 // column blocks: grid (row chunks, m); the column's run flag is uniform per block
-// rr_part (optional): block partials of the new ||r_j||^2 at rr_part[j * gridDim.x + block]
-__global__ __launch_bounds__(BC_THREADS) void k_bxr(int64_t n, double* __restrict__ X, int64_t ldx,
-                                                   double* __restrict__ R, const double* __restrict__ P,
-                                                   const double* __restrict__ W, const BState* st,
-                                                   double* __restrict__ rr_part) {
-    __shared__ double sc[BC_THREADS / WAVE];
-    const int64_t j = blockIdx.y;
-    if (!st[j].run) return;
-    const double a = st[j].alpha;
-    double acc = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * BC_THREADS + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * BC_THREADS) {
-        X[i + j * ldx] = fma(a, P[i + j * n], X[i + j * ldx]);
-        const double ri = fma(-a, W[i + j * n], R[i + j * n]);
-        R[i + j * n] = ri;
-        acc = fma(ri, ri, acc);
-    }
-    if (rr_part) {
-        acc = block_sum(acc, sc);
-        if (threadIdx.x == 0) rr_part[j * gridDim.x + blockIdx.x] = acc;
-    }
-}
-__global__ __launch_bounds__(BC_THREADS) void k_bp(int64_t n, const double* __restrict__ Z,
-                                                  double* __restrict__ P, const BState* st) {
-    const int64_t j = blockIdx.y;
-    if (!st[j].run) return;
-    const double b = st[j].beta;
-    for (int64_t i = (int64_t)blockIdx.x * BC_THREADS + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * BC_THREADS)
-        P[i + j * n] = fma(b, P[i + j * n], Z[i + j * n]);
-}
 static dim3 vgrid(int64_t n, int64_t m) {
     int64_t gx = (n + BC_THREADS * 8 - 1) / (BC_THREADS * 8);
     if (gx < 1) gx = 1;
     return dim3((unsigned)gx, (unsigned)m);
 }
 int bxr_blocks(int64_t n) { return (int)vgrid(n, 1).x; }
-void launch_bxr(int64_t n, int64_t m, double* X, int64_t ldx, double* R, const double* P,
-                const double* W, const BState* st, double* rr_part, hipStream_t s) {
-    k_bxr<<<vgrid(n, m), BC_THREADS, 0, s>>>(n, X, ldx, R, P, W, st, rr_part);
+// Fused per-column steps.  Every block of column j recomputes the column's scalar
+// from the block partials (one block-wide sum in a fixed order, so all blocks get
+// the same value), applies its share of the vector update, and the last block of
+// the column to finish (a per-column counter; that block resets it to zero)
+// records the scalars and the stop tests in the column state.  A column that is
+// not running at launch is left alone by every block.
+RR_DEV double colsum_block(const ColParts& pt, int64_t j, double* sc) {
+    double v = 0.0;
+    for (int c = threadIdx.x; c < pt.nch; c += blockDim.x) v += pt.p[(int64_t)c * pt.cs + j * pt.js];
+    return block_sum(v, sc);
 }
-void launch_bp(int64_t n, int64_t m, const double* Z, double* P, const BState* st, hipStream_t s) {
-    k_bp<<<vgrid(n, m), BC_THREADS, 0, s>>>(n, Z, P, st);
+RR_DEV bool last_block_of_column(int32_t* cnt, int64_t j, int* flag) {
+    __threadfence();   // this block's partials and vector updates are visible device-wide
+    if (threadIdx.x == 0) *flag = atomicAdd(&cnt[j], 1) == (int)gridDim.x - 1;
+    __syncthreads();
+    if (!*flag) return false;
+    __threadfence();   // the other blocks' partials are read after this point
+    return true;
 }
+
+// alpha_j = rho_j / p_j^T w_j; x_j += alpha_j p_j, r_j -= alpha_j w_j, partials of
+// ||r_j||^2; last block: pw, alpha, ||r||^2, the iteration count and the stop tests
+__global__ __launch_bounds__(BC_THREADS) void k_bxr_fused(int64_t n, double* __restrict__ X, int64_t ldx,
+                                                         double* __restrict__ R, const double* __restrict__ P,
+                                                         const double* __restrict__ W, BState* st, ColParts pw,
+                                                         double* __restrict__ rr_part, int32_t* cnt) {
+    __shared__ double sc[BC_THREADS / WAVE];
+    __shared__ int last;
+    const int64_t j = blockIdx.y;
+    if (!st[j].run) return;
+    const double pwj = colsum_block(pw, j, sc);
+    const bool ok = pwj > 0.0 && isfinite(pwj);
+    const double a = ok ? st[j].rho / pwj : 0.0;
+    double acc = 0.0;
+    if (ok)
+        for (int64_t i = (int64_t)blockIdx.x * BC_THREADS + threadIdx.x; i < n;
+             i += (int64_t)gridDim.x * BC_THREADS) {
+            X[i + j * ldx] = fma(a, P[i + j * n], X[i + j * ldx]);
+            const double ri = fma(-a, W[i + j * n], R[i + j * n]);
+            R[i + j * n] = ri;
+            acc = fma(ri, ri, acc);
+        }
+    acc = block_sum(acc, sc);
+    if (threadIdx.x == 0) rr_part[j * gridDim.x + blockIdx.x] = acc;
+    if (!last_block_of_column(cnt, j, &last)) return;
+    const double rr = colsum_block(ColParts{rr_part, (int)gridDim.x, 1, (int64_t)gridDim.x}, j, sc);
+    if (threadIdx.x != 0) return;
+    cnt[j] = 0;
+    st[j].pw = pwj;
+    if (!ok) { st[j].run = 0; st[j].code = STOP_BREAKDOWN; return; }
+    st[j].alpha = a;
+    st[j].rr = rr;
+    const int it = st[j].iters + 1;
+    st[j].iters = it;
+    if (!isfinite(rr)) { st[j].run = 0; st[j].code = STOP_BREAKDOWN; }
+    else if (rr <= st[j].target2) { st[j].run = 0; st[j].code = STOP_TARGET; }
+    else if (it >= st[j].maxit) { st[j].run = 0; st[j].code = STOP_MAXIT; }
+}
+
+// beta_j = r_j^T z_j / rho_j; p_j = z_j + beta_j p_j; last block: beta, rho
+__global__ __launch_bounds__(BC_THREADS) void k_bp_fused(int64_t n, const double* __restrict__ Z,
+                                                        double* __restrict__ P, BState* st, ColParts rz,
+                                                        int32_t* cnt) {
+    __shared__ double sc[BC_THREADS / WAVE];
+    __shared__ int last;
+    const int64_t j = blockIdx.y;
+    if (!st[j].run) return;
+    const double rzj = colsum_block(rz, j, sc);
+    const bool ok = rzj > 0.0 && isfinite(rzj);
+    const double b = ok ? rzj / st[j].rho : 0.0;
+    if (ok)
+        for (int64_t i = (int64_t)blockIdx.x * BC_THREADS + threadIdx.x; i < n;
+             i += (int64_t)gridDim.x * BC_THREADS)
+            P[i + j * n] = fma(b, P[i + j * n], Z[i + j * n]);
+    if (!last_block_of_column(cnt, j, &last)) return;
+    if (threadIdx.x != 0) return;
+    cnt[j] = 0;
+    if (!ok) { st[j].run = 0; st[j].code = STOP_BREAKDOWN; return; }
+    st[j].beta = b;
+    st[j].rho = rzj;
+}
+
+void launch_bxr_fused(int64_t n, int64_t m, double* X, int64_t ldx, double* R, const double* P,
+                      const double* W, BState* st, ColParts pw, double* rr_part, int32_t* cnt, hipStream_t s) {
+    k_bxr_fused<<<vgrid(n, m), BC_THREADS, 0, s>>>(n, X, ldx, R, P, W, st, pw, rr_part, cnt);
+}
+void launch_bp_fused(int64_t n, int64_t m, const double* Z, double* P, BState* st, ColParts rz, int32_t* cnt,
+                     hipStream_t s) {
+    k_bp_fused<<<vgrid(n, m), BC_THREADS, 0, s>>>(n, Z, P, st, rz, cnt);
+}
+
 
 // For flagged columns: dst[:, j] = src[:, j]
 __global__ __launch_bounds__(BC_THREADS) void k_copy_flagged(int64_t n, const double* __restrict__ src,
