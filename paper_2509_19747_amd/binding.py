@@ -456,4 +456,7 @@ def serve(requests, hbm_budget: int = 96 << 30, max_slots: int = 8, graph_iters:
     for i, (pts, Bc, Xc) in enumerate(keep):
         if results[i] is not None:
             results[i]["X"] = Xc.T.copy()
-    return results, stats.as_dict()
+    out = stats.as_dict()
+    if any(r is not None and r["info"]["status"] != RR_OK for r in results):
+        out["first_error"] = lib().rr_last_error().decode()
+    return results, out

@@ -77,6 +77,14 @@ size_t round_block(size_t bytes) {
 
 void flush_all_caches() {   // caller holds g_cache_mu
     for (auto& c : g_caches) {
+        // a stream that is being captured into a graph (by another thread) keeps its
+        // blocks: a free queued on it would become part of, or break, that capture
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(c.st, &cs) != hipSuccess) {
+            (void)hipGetLastError();
+            continue;
+        }
+        if (cs != hipStreamCaptureStatusNone) continue;
         for (auto& b : c.blocks) (void)hipFreeAsync(b.p, c.st);
         c.blocks.clear();
         c.total = 0;
@@ -121,6 +129,19 @@ void* Alloc::get(size_t bytes) const {
     }
     g_live.push_back(CachedBlock{p, want});
     return p;
+}
+
+void release_stream_blocks(hipStream_t st) {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    for (size_t i = 0; i < g_caches.size(); ++i) {
+        StreamCache& c = g_caches[i];
+        if (c.dev != dev || c.st != st) continue;
+        for (auto& b : c.blocks) (void)hipFreeAsync(b.p, st);
+        g_caches.erase(g_caches.begin() + (std::ptrdiff_t)i);
+        return;
+    }
 }
 
 void Alloc::put(void* p) const {

@@ -52,6 +52,10 @@ rr_status guarded(F&& body) {
 }
 
 // Device allocator: the caller's rr_allocator if given, else hipMalloc/hipFree.
+// Frees the blocks the allocator cache holds for stream st (on this device) and
+// forgets the stream: called before the library destroys a stream it created.
+void release_stream_blocks(hipStream_t st);
+
 struct Alloc {
     rr_allocator a{};
     bool custom = false;

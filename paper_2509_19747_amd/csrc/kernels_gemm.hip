@@ -180,7 +180,9 @@ static void gm_run(int64_t M, int64_t N, int64_t K, const void* A, int64_t lda, 
     int64_t splits = 1;
     const int64_t target = 1024;   // four blocks per compute unit
     if (tiles < target && kblocks >= 16) {
-        splits = std::min<int64_t>((target + tiles - 1) / tiles, kblocks / 8);
+        // round down: one more slice than fits would leave a second, nearly empty
+        // round of blocks as long as the first
+        splits = std::min<int64_t>(std::max<int64_t>(target / tiles, 1), kblocks / 8);
         splits = std::min<int64_t>(splits, 64);
         while (splits > 1 && (size_t)(splits * M * N) > wsd) --splits;
         splits = std::max<int64_t>(splits, 1);

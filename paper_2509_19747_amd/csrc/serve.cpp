@@ -64,6 +64,7 @@ struct Shared {
     int64_t served = 0, rejected = 0;
     std::mutex deliver_mu;
     rr_status first_err = RR_OK;
+    std::string first_err_msg;   // the library's message for the first failed request
 };
 
 void run_job(const rr_serve_config& cfg, Job& job, hipStream_t st, double t0, rr_deliver_fn deliver,
@@ -76,7 +77,11 @@ void run_job(const rr_serve_config& cfg, Job& job, hipStream_t st, double t0, rr
     double *b = nullptr, *x = nullptr;
     const int64_t n = r.n;
     const int64_t nr = std::max<int32_t>(r.nrhs, 1);
-    auto fail = [&](rr_status s) { info.status = s; };
+    std::string err_msg;
+    auto fail = [&](rr_status s) {
+        info.status = s;
+        if (err_msg.empty()) err_msg = rr_last_error();   // this worker thread's message
+    };
     do {
         if (hipMallocAsync((void**)&pts, (size_t)r.d * n * sizeof(float), st) != hipSuccess ||
             hipMallocAsync((void**)&b, (size_t)n * nr * sizeof(double), st) != hipSuccess ||
@@ -154,7 +159,10 @@ void run_job(const rr_serve_config& cfg, Job& job, hipStream_t st, double t0, rr
     sh.active -= 1;
     sh.served += 1;
     sh.lat_ms.push_back(1e3 * (t_done - r.t_arrival));
-    if (info.status != RR_OK && sh.first_err == RR_OK) sh.first_err = (rr_status)info.status;
+    if (info.status != RR_OK && sh.first_err == RR_OK) {
+        sh.first_err = (rr_status)info.status;
+        sh.first_err_msg = err_msg;
+    }
     sh.cv_done.notify_all();
 }
 
@@ -191,7 +199,12 @@ extern "C" rr_status rr_serve(const rr_serve_config* cfg, rr_next_fn next, rr_de
                     }
                     run_job(*cfg, job, st, t0, deliver, user, sh);
                 }
-                if (st) (void)hipStreamDestroy(st);
+                if (st) {
+                    (void)hipStreamSynchronize(st);
+                    release_stream_blocks(st);
+                    (void)hipStreamSynchronize(st);
+                    (void)hipStreamDestroy(st);
+                }
             });
         }
         std::deque<Job> pending;
@@ -268,7 +281,8 @@ extern "C" rr_status rr_serve(const rr_serve_config* cfg, rr_next_fn next, rr_de
             stats->max_active = sh.max_active;
         }
         (void)loop_err;
-        if (sh.first_err != RR_OK) set_error("at least one request failed (see its deliver status)");
+        if (sh.first_err != RR_OK)
+            set_error("at least one request failed (see its deliver status); first: " + sh.first_err_msg);
         return RR_OK;
     });
 }

@@ -235,7 +235,9 @@ extern "C" rr_status rr_solve(const rr_precond* Pc, int32_t mu_index, const doub
                     S.sync();
                     if (!gexec) {
                         Solver C{P, W, W.cap, S.mu, S.Kc};
-                        RR_HIP(hipStreamBeginCapture(W.cap, hipStreamCaptureModeThreadLocal));
+                        // relaxed: the capture holds kernel launches only, and allocation or copy calls
+                        // of other threads (a server's other requests) must not invalidate it
+                        RR_HIP(hipStreamBeginCapture(W.cap, hipStreamCaptureModeRelaxed));
                         for (int k = 0; k < o.check_every; ++k) C.iteration(x);
                         RR_HIP(hipStreamEndCapture(W.cap, &graph));
                         RR_HIP(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));

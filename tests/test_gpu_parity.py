@@ -635,7 +635,8 @@ def test_serving_alone_equals_mixed_and_oracle():
     assert 0 < stats["p50_ms"] <= stats["p99_ms"]
     for i, r in enumerate(reqs):
         alone, _ = rb.serve([dict(r, t_arrival=0.0)], max_slots=1, graph_iters=8, **kw)
-        assert mixed[i]["info"]["status"] == rr.RR_OK
+        assert mixed[i]["info"]["status"] == rr.RR_OK, stats.get("first_error")
+        assert alone[0]["info"]["status"] == rr.RR_OK
         assert np.array_equal(alone[0]["X"], mixed[i]["X"])      # bitwise: batch-invariant
         op = Operator(kind=rr.OP_RBF, pts=r["pts"], kconst=r["kconst"], scale=r["scale"])
         for j in range(r["B"].shape[1]):
