@@ -225,17 +225,20 @@ rr_status rr_solve_batch_fused(const rr_precond* Pc, const int32_t* mu_index_per
         RR_HIP(hipMemcpyAsync(Bt.muidx.ptr(), mu_index_per_col, m * sizeof(int32_t), hipMemcpyHostToDevice, st));
 
         // NaN / Inf scan
+        // (and whether X0 is zero: then the first residuals are the columns of B)
+        bool x0_zero = false;
         {
             DBuf flag(Bt.al, 16);
-            RR_HIP(hipMemsetAsync(flag.ptr(), 0, sizeof(int32_t), st));
+            RR_HIP(hipMemsetAsync(flag.ptr(), 0, 2 * sizeof(int32_t), st));
             for (int64_t j = 0; j < m; ++j) {
                 launch_nonfinite(n, B + j * ldb, flag.as<int32_t>(), st);
-                launch_nonfinite(n, X + j * ldx, flag.as<int32_t>(), st);
+                launch_nonfinite(n, X + j * ldx, flag.as<int32_t>(), st, flag.as<int32_t>() + 1);
             }
-            int32_t bad = 0;
-            RR_HIP(hipMemcpyAsync(&bad, flag.ptr(), sizeof(int32_t), hipMemcpyDeviceToHost, st));
+            int32_t flags[2] = {0, 0};
+            RR_HIP(hipMemcpyAsync(flags, flag.ptr(), 2 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
             RR_HIP(hipStreamSynchronize(st));
-            RR_REQUIRE(bad == 0, "B or X0 contains NaN or Inf");
+            RR_REQUIRE(flags[0] == 0, "B or X0 contains NaN or Inf");
+            x0_zero = flags[1] == 0;
         }
         const bool ir = (o->fp64_ir == 1) || (o->fp64_ir == -1 && P.opts.prec == RR_PREC_MIXED);
         const std::vector<double> bb = Bt.coldots(B, ldb, B, ldb);
@@ -250,11 +253,19 @@ rr_status rr_solve_batch_fused(const rr_precond* Pc, const int32_t* mu_index_per
         std::vector<int> pending(m, 1);   // needs a true-residual check
         double* Xd = X;
 
+        bool first_pass = true;
         auto restart_pass = [&]() {
-            // T = B - A_mu X for every column; decide per pending column
-            Bt.matmat(Xd, ldx, Bt.T.as<double>(), ir);
-            launch_bresid(n, m, B, ldb, Bt.T.as<double>(), Bt.T.as<double>(), st);
-            const std::vector<double> rr = Bt.coldots(Bt.T.as<double>(), n, Bt.T.as<double>(), n);
+            // T = B - A_mu X for every column (T = B for a zero X0); decide per pending column
+            std::vector<double> rr;
+            if (first_pass && x0_zero) {
+                launch_copy_mat(DT_F64, B, ldb, DT_F64, Bt.T.as<double>(), n, n, m, st);
+                rr = bb;
+            } else {
+                Bt.matmat(Xd, ldx, Bt.T.as<double>(), ir);
+                launch_bresid(n, m, B, ldb, Bt.T.as<double>(), Bt.T.as<double>(), st);
+                rr = Bt.coldots(Bt.T.as<double>(), n, Bt.T.as<double>(), n);
+            }
+            first_pass = false;
             bool any = false;
             for (int64_t j = 0; j < m; ++j) {
                 hstart[j] = 0;

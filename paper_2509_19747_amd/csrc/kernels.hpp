@@ -293,6 +293,7 @@ void launch_state_init(CgState* s, const double* rz_part, int rz_count, double t
                        int32_t maxit, int32_t iters, double* hist, int32_t hist_cap,
                        hipStream_t st);
 // Finite check of a vector: *flag = 1 if any entry is NaN/Inf.
-void launch_nonfinite(int64_t n, const double* v, int32_t* flag, hipStream_t st);
+// *flag = 1 if v holds a NaN or Inf; *nonzero = 1 (when given) if any entry is not 0.
+void launch_nonfinite(int64_t n, const double* v, int32_t* flag, hipStream_t st, int32_t* nonzero = nullptr);
 
 }  // namespace rr

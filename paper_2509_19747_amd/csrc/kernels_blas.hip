@@ -879,13 +879,16 @@ void launch_state_init(CgState* s, const double* rz_part, int rz_count, double t
     k_state_init<<<1, 1024, 0, st>>>(s, rz_part, rz_count, target2, maxit, iters, hist, hist_cap);
 }
 
-__global__ void k_nonfinite(int64_t n, const double* __restrict__ v, int32_t* flag) {
+__global__ void k_nonfinite(int64_t n, const double* __restrict__ v, int32_t* flag, int32_t* nonzero) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x)
-        if (!isfinite(v[i])) *flag = 1;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const double x = v[i];
+        if (!isfinite(x)) *flag = 1;
+        if (nonzero && x != 0.0) *nonzero = 1;
+    }
 }
-void launch_nonfinite(int64_t n, const double* v, int32_t* flag, hipStream_t st) {
-    k_nonfinite<<<vec_blocks(n), 256, 0, st>>>(n, v, flag);
+void launch_nonfinite(int64_t n, const double* v, int32_t* flag, hipStream_t st, int32_t* nonzero) {
+    k_nonfinite<<<vec_blocks(n), 256, 0, st>>>(n, v, flag, nonzero);
 }
 
 }  // namespace rr

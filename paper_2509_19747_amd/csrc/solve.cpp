@@ -174,13 +174,15 @@ extern "C" rr_status rr_solve(const rr_precond* Pc, int32_t mu_index, const doub
         const bool ir = (o.fp64_ir == 1) || (o.fp64_ir == -1 && P.opts.prec == RR_PREC_MIXED);
 
         // NaN/Inf scan of b (and x0) before any arithmetic
-        RR_HIP(hipMemsetAsync(W.flag.ptr(), 0, sizeof(int32_t), st));
+        // (and whether x0 is zero: then the first residual is b itself, no operator product)
+        RR_HIP(hipMemsetAsync(W.flag.ptr(), 0, 2 * sizeof(int32_t), st));
         launch_nonfinite(n, b, W.flag.as<int32_t>(), st);
-        launch_nonfinite(n, x, W.flag.as<int32_t>(), st);
-        int32_t bad = 0;
-        RR_HIP(hipMemcpyAsync(&bad, W.flag.ptr(), sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        launch_nonfinite(n, x, W.flag.as<int32_t>(), st, W.flag.as<int32_t>() + 1);
+        int32_t flags[2] = {0, 0};
+        RR_HIP(hipMemcpyAsync(flags, W.flag.ptr(), 2 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
         S.sync();
-        RR_REQUIRE(bad == 0, "b or x0 contains NaN or Inf");
+        RR_REQUIRE(flags[0] == 0, "b or x0 contains NaN or Inf");
+        const bool x0_zero = flags[1] == 0;
 
         const double t0 = now_ms();
         launch_dot_part(n, b, b, W.rr_part.as<double>(), st);
@@ -213,7 +215,9 @@ extern "C" rr_status rr_solve(const rr_precond* Pc, int32_t mu_index, const doub
         rr_status result = RR_ENOCONV;
         double relres = 1.0;
         while (true) {
-            const double rn = std::sqrt(S.true_residual(b, x, ir));
+            double rn = nb;
+            if (x0_zero && cycles == 0) launch_copy_vec(n, b, W.r.as<double>(), st);   // r0 = b - A 0
+            else rn = std::sqrt(S.true_residual(b, x, ir));
             relres = rn / nb;
             if (its < o.history_cap) o.relres_history[its] = relres;
             if (!std::isfinite(rn)) { result = RR_EBREAKDOWN; break; }
