@@ -313,8 +313,9 @@ rr_status rr_solve_batch_fused(const rr_precond* Pc, const int32_t* mu_index_per
                 if (*s) (void)hipStreamDestroy(*s);
             }
         } gguard{&cap, &graph, &gexec};
+        bool eager = !o->use_graph;
         auto run_batch = [&]() {
-            if (!o->use_graph) {
+            if (eager) {
                 for (int k = 0; k < o->check_every; ++k) Bt.iteration(X, ldx);
                 return;
             }
@@ -330,10 +331,17 @@ rr_status rr_solve_batch_fused(const rr_precond* Pc, const int32_t* mu_index_per
                 Bt.capturing = false;
                 const hipError_t ce = hipStreamEndCapture(cap, &graph);
                 Bt.st = st;
-                if (ce != hipSuccess)
-                    throw RrError{RR_EDEVICE, std::string("graph capture of the PCG batch failed (") +
-                                                  hipGetErrorString(ce) + "); capture lost after: " +
-                                                  (Bt.capture_lost_at ? Bt.capture_lost_at : "-")};
+                if (ce != hipSuccess) {
+                    // The runtime invalidated the capture (seen under concurrent requests in
+                    // one process, after the preconditioner's launches): nothing captured
+                    // has run, so the batch runs eagerly, now and for the rest of the solve,
+                    // with the same kernels and results.
+                    (void)hipGetLastError();
+                    if (graph) { (void)hipGraphDestroy(graph); graph = nullptr; }
+                    eager = true;
+                    for (int k = 0; k < o->check_every; ++k) Bt.iteration(X, ldx);
+                    return;
+                }
                 RR_HIP(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
             }
             RR_HIP(hipGraphLaunch(gexec, cap));

@@ -211,6 +211,7 @@ extern "C" rr_status rr_solve(const rr_precond* Pc, int32_t mu_index, const doub
             ~GraphGuard() { if (*e) (void)hipGraphExecDestroy(*e); if (*g) (void)hipGraphDestroy(*g); }
         } gg{&gexec, &graph};
 
+        bool graph_failed = false;
         int its = 0, cycles = 0;
         rr_status result = RR_ENOCONV;
         double relres = 1.0;
@@ -232,7 +233,7 @@ extern "C" rr_status rr_solve(const rr_precond* Pc, int32_t mu_index, const doub
             RR_HIP(hipGetLastError());
             CgState hs{};
             while (true) {
-                if (o.use_graph) {
+                if (o.use_graph && !graph_failed) {
                     // capture on a private non-default stream; the caller's stream
                     // has been synchronised, so ordering is preserved
                     if (!W.cap) RR_HIP(hipStreamCreateWithFlags(&W.cap, hipStreamNonBlocking));
@@ -243,7 +244,13 @@ extern "C" rr_status rr_solve(const rr_precond* Pc, int32_t mu_index, const doub
                         // of other threads (a server's other requests) must not invalidate it
                         RR_HIP(hipStreamBeginCapture(W.cap, hipStreamCaptureModeRelaxed));
                         for (int k = 0; k < o.check_every; ++k) C.iteration(x);
-                        RR_HIP(hipStreamEndCapture(W.cap, &graph));
+                        if (hipStreamEndCapture(W.cap, &graph) != hipSuccess) {
+                            // an invalidated capture ran nothing: continue eagerly
+                            (void)hipGetLastError();
+                            if (graph) { (void)hipGraphDestroy(graph); graph = nullptr; }
+                            graph_failed = true;
+                            continue;
+                        }
                         RR_HIP(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
                     }
                     RR_HIP(hipGraphLaunch(gexec, W.cap));
