@@ -259,6 +259,27 @@ def test_build_fp64_wide_basis_matches_oracle():
     assert abs(g["tau"] - o.tau) < 1e-8 * o.tau
 
 
+@pytest.mark.parametrize("n,l", [(300, 64), (320, 65), (600, 200), (800, 300)])
+def test_build_fp64_triangular_inverse_widths(n, l):
+    """Basis widths at and across the row-slot sizes of the wave-per-column
+    triangular inverse (64 rows per register slot: one, two, four and eight slots),
+    each against the oracle."""
+    prob = workloads.cfg_small_dense(n=n, d=8, l=l)
+    op = Operator.from_problem(prob)
+    kop = rr.kernel_operator(rr.OP_RBF, _cuda(prob.pts), prob.kconst, prob.scale)
+    A = rr.kernel_to_dense(kop, "fp64")
+    mu = prob.mus[0]
+    P = rr.build_precond(rr.dense_operator(A), [mu], l=prob.l, sketch="gaussian", seed=prob.omega_seed)
+    g = P.export(0)
+    o = orr.build(op, [mu], prob.l, "gaussian", prob.omega_seed)[0]
+    rel = lambda a, b_: np.linalg.norm(a - b_) / np.linalg.norm(b_)
+    assert rel(g["Q"], o.Q) < 1e-9
+    assert rel(g["R"], o.R) < 1e-9
+    assert rel(g["G"], o.G) < 1e-8
+    assert abs(g["tau"] - o.tau) < 1e-8 * o.tau
+    assert np.abs(g["Q"].T @ g["Q"] - np.eye(l)).max() < 1e-12
+
+
 @pytest.mark.parametrize("l", [0, 45])
 @pytest.mark.parametrize("use_graph", [False, True])
 def test_solve_fp64_matches_oracle(dense_small, l, use_graph):
