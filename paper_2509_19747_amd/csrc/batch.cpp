@@ -167,17 +167,6 @@ struct Batch {
         return out;
     }
 
-    // while the iterations are captured into a graph: the first step after which the
-    // capture stopped being active (reported if the capture fails)
-    bool capturing = false;
-    const char* capture_lost_at = nullptr;
-    void capture_check(const char* step) {
-        if (!capturing || capture_lost_at) return;
-        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-        const hipError_t e = hipStreamIsCapturing(st, &cs);
-        if (e != hipSuccess || cs != hipStreamCaptureStatusActive) capture_lost_at = step;
-    }
-
     void iteration(double* X, int64_t ldx) {
         BState* s = state.as<BState>();
         double* r = R.as<double>();
@@ -187,17 +176,12 @@ struct Batch {
         double* pp = parts.as<double>();
         const ColParts own{pp, nch, m, 1};
         int32_t* c = cnt.as<int32_t>();
-        capture_check("before the iteration");
         ColParts pw = matmat(p, n, w, false);
-        capture_check("operator product");
         if (!pw.p) { launch_coldot(n, m, p, n, w, n, pp, st); pw = own; }
         launch_bxr_fused(n, m, X, ldx, r, p, w, s, pw, rrp.as<double>(), c, st);
-        capture_check("x/r update");
         ColParts rz = precond(r, z);
-        capture_check("preconditioner");
         if (!rz.p) { launch_coldot(n, m, r, n, z, n, pp, st); rz = own; }
         launch_bp_fused(n, m, z, p, s, rz, c + m, st);
-        capture_check("p update");
     }
 };
 
@@ -326,9 +310,7 @@ rr_status rr_solve_batch_fused(const rr_precond* Pc, const int32_t* mu_index_per
                 // relaxed: the capture holds kernel launches only, and allocation or copy calls
                 // of other threads (a server's other requests) must not invalidate it
                 RR_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeRelaxed));
-                Bt.capturing = true;
                 for (int k = 0; k < o->check_every; ++k) Bt.iteration(X, ldx);
-                Bt.capturing = false;
                 const hipError_t ce = hipStreamEndCapture(cap, &graph);
                 Bt.st = st;
                 if (ce != hipSuccess) {
