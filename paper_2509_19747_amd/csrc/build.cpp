@@ -342,7 +342,7 @@ struct Builder {
         DBuf cpart(al, (size_t)2 * nch * kb * sizeof(double)), d(al, 3 * kb * sizeof(double));
         DBuf rz(al, (size_t)2 * qd_blocks(n) * sizeof(double));
         DBuf op_part(al, (size_t)2 * operator_part_count(P) * sizeof(double));
-        DBuf c1(al, kb * sizeof(double)), qf(al, (size_t)vec_blocks(kb) * sizeof(double));
+        DBuf c1(al, kb * sizeof(double));
         // merged cores: KE = T M T - 2T (with r added back: I - Qb (2T - TMT) Qb^T),
         // KL = TGT M T, B1 = T M T
         DBuf MT = mat(kb, kb), B1 = mat(kb, kb), KE = mat(kb, kb), KL = mat(kb, kb);
@@ -379,9 +379,8 @@ struct Builder {
             launch_core_apply_triple(kb, KE.as<double>(), KL.as<double>(), B1.as<double>(), kb, cp, nch, dd,
                                      c1.as<double>(), st);
             launch_qd_multi(2, n, kb, P.Qb.as<double>(), n, dd, y0, n, 1.0, 0.0, w0, rzp, nullptr, st);
-            launch_dot_part(kb, c1.as<double>(), dd + 2 * kb, qf.as<double>(), st);
-            launch_normalize(n, u0, w0, rzp, qd_blocks(n), lam_dev + 0, st);
-            launch_normalize(n, u1, w1, qf.as<double>(), vec_blocks(kb), lam_dev + 1, st);
+            launch_normalize_pair(n, u0, w0, rzp, qd_blocks(n), lam_dev + 0, u1, w1, c1.as<double>(),
+                                  dd + 2 * kb, kb, lam_dev + 1, st);
         }
         check_launch();
         double lams[2] = {0.0, 0.0};

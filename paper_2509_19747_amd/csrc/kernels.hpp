@@ -269,6 +269,11 @@ void launch_qd_multi(int nr, int64_t n, int64_t k, const double* Q, int64_t ldq,
                      const double* R, int64_t ldr, double rc0, double rc1, double* Z, double* rz_part,
                      const int32_t* stop, hipStream_t st);
 // v = v / sqrt(sum(part)); lam_out[0] = sqrt(sum(part))  (power-iteration step)
+// v0 = src0 / ||src0|| (||src0||^2 from count0 partials) and v1 = src1 / sqrt(a^T b) (k
+// entries) in one launch; the norms go to lam0 and lam1.
+void launch_normalize_pair(int64_t n, double* v0, const double* src0, const double* part0, int count0,
+                           double* lam0, double* v1, const double* src1, const double* a, const double* b,
+                           int64_t k, double* lam1, hipStream_t st);
 void launch_normalize(int64_t n, double* v, const double* src, const double* part, int count,
                       double* lam_out, hipStream_t st);
 

@@ -912,4 +912,39 @@ void launch_normalize(int64_t n, double* v, const double* src, const double* par
                       double* lam_out, hipStream_t st) {
     k_normalize<<<vec_blocks(n), 256, 0, st>>>(n, v, src, part, count, lam_out);
 }
+
+// Two normalisations in one launch (blockIdx.y = column): column 0 as k_normalize;
+// column 1 with ||src1||^2 = a^T b over k entries, summed in every block in a fixed order.
+__global__ __launch_bounds__(256) void k_normalize_pair(int64_t n, double* __restrict__ v0,
+                                                        const double* __restrict__ src0,
+                                                        const double* __restrict__ part0, int count0,
+                                                        double* lam0, double* __restrict__ v1,
+                                                        const double* __restrict__ src1,
+                                                        const double* __restrict__ a,
+                                                        const double* __restrict__ b, int64_t k,
+                                                        double* lam1) {
+    __shared__ double sc[4];
+    const bool second = blockIdx.y == 1;
+    double s;
+    if (!second) {
+        s = block_sum_array(part0, count0, sc);
+    } else {
+        double t = 0.0;
+        for (int64_t j = threadIdx.x; j < k; j += 256) t = fma(a[j], b[j], t);
+        s = block_sum(t, sc);
+    }
+    const double nrm = sqrt(s > 0.0 ? s : 0.0);
+    const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
+    double* v = second ? v1 : v0;
+    const double* src = second ? src1 : src0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) *(second ? lam1 : lam0) = nrm;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        v[i] = src[i] * inv;
+}
+void launch_normalize_pair(int64_t n, double* v0, const double* src0, const double* part0, int count0,
+                           double* lam0, double* v1, const double* src1, const double* a, const double* b,
+                           int64_t k, double* lam1, hipStream_t st) {
+    k_normalize_pair<<<dim3((unsigned)vec_blocks(n), 2), 256, 0, st>>>(n, v0, src0, part0, count0, lam0, v1,
+                                                                        src1, a, b, k, lam1);
+}
 }  // namespace rr
