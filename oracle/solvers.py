@@ -32,7 +32,11 @@ class SolveResult:
     restarts: int
     relres: float
     status: int
+    # history[k]: relative residual after k iterations (the recurrence residual
+    # inside a cycle, the true residual where a cycle starts and at the end)
     history: List[float] = field(default_factory=list)
+    # the true relative residual at the start of every cycle and at the end
+    cycle_history: List[float] = field(default_factory=list)
 
 
 def pcg(Amu: Callable, P: Callable, b: np.ndarray, tol: float, x0: Optional[np.ndarray] = None,
@@ -51,37 +55,51 @@ def pcg(Amu: Callable, P: Callable, b: np.ndarray, tol: float, x0: Optional[np.n
     its = 0
     cycles = 0
     hist: List[float] = []
+    cyc: List[float] = []
+
+    def record(k: int, value: float):
+        # index k = iterations done; a true residual replaces the recurrence value
+        if len(hist) == k + 1:
+            hist[k] = value
+        else:
+            hist.append(value)
+
+    def result(status, relres):
+        return SolveResult(x, its, max(cycles - 1, 0), relres, status, hist, cyc)
+
     while True:
         r = b - Atrue(x)
         rn = float(np.linalg.norm(r))
-        hist.append(rn / nb)
+        record(its, rn / nb)
+        cyc.append(rn / nb)
         if rn <= tol * nb:
-            return SolveResult(x, its, max(cycles - 1, 0), rn / nb, OK, hist)
+            return result(OK, rn / nb)
         if its >= maxit:
-            return SolveResult(x, its, max(cycles - 1, 0), rn / nb, NOCONV, hist)
+            return result(NOCONV, rn / nb)
         cycles += 1
         target = max(eta * rn, tol * nb)
         z = P(r)
         p = z.copy()
         rho = float(r @ z)
         if not rho > 0:
-            return SolveResult(x, its, cycles - 1, rn / nb, BREAKDOWN, hist)
+            return result(BREAKDOWN, rn / nb)
         while its < maxit:
             w = Amu(p)
             pw = float(p @ w)
             if not pw > 0:
-                return SolveResult(x, its, cycles - 1, rn / nb, BREAKDOWN, hist)
+                return result(BREAKDOWN, rn / nb)
             alpha = rho / pw
             x = x + alpha * p
             r = r - alpha * w
             its += 1
             rn = float(np.linalg.norm(r))
+            record(its, rn / nb)
             if rn <= target:
                 break
             z = P(r)
             rho_new = float(r @ z)
             if not rho_new > 0:
-                return SolveResult(x, its, cycles - 1, rn / nb, BREAKDOWN, hist)
+                return result(BREAKDOWN, rn / nb)
             beta = rho_new / rho
             p = z + beta * p
             rho = rho_new

@@ -132,6 +132,56 @@ def test_closed_form_diagonal():
     assert np.allclose(spec, expect, rtol=1e-10)
 
 
+@pytest.mark.parametrize("rule,rho", [(rr.NYS, 1.0), (rr.RHO, 0.7), (rr.RHO, 2.5)])
+def test_closed_form_diagonal_tau_rules(rule, rho):
+    # A = diag(lambda) (decreasing), Omega = [e_1 .. e_l]: Q = Omega, R = diag(lambda_i + mu)
+    # and G = diag(1 / (lambda_i + mu)), so
+    #   eq. nys_tau:         tau = 1 / lambda_max(G) = lambda_l + mu,
+    #   eq. c_randrand_tau:  tau = rho ||E|| / lam = rho (lambda_{l+1} + mu)   (lam = 1).
+    n, l, mu = 60, 8, 0.05
+    lam = np.linspace(40.0, 0.5, n)
+    op = Operator(dense=np.diag(lam))
+    Om = np.eye(n)[:, :l]
+    P = rr.build(op, [mu], l, seed=2, Omega=Om, orth=rr.CHOLQR, tau_rule=rule, rho=rho,
+                 power_iters=400)[0]
+    assert np.allclose(np.diag(P.G), 1.0 / (lam[:l] + mu), rtol=1e-13)
+    if rule == rr.NYS:
+        assert abs(P.tau - (lam[l - 1] + mu)) <= 1e-12 * (lam[l - 1] + mu)
+    else:
+        expect = rho * (lam[l] + mu)
+        assert abs(P.tau - expect) <= 1e-6 * expect
+
+
+def test_cholesky_ladder_alpha_diagonal():
+    # W = diag(1, 1, -5e-13): plain Cholesky fails; the ladder adds
+    # alpha = 10^e max_i W_ii for e = -14, -13, ...; e = -12 is the first with
+    # -5e-13 + alpha > 0, so alpha = 1e-12 and R^T R = W + 1e-12 I.
+    W = np.diag([1.0, 1.0, -5e-13])
+    R, alpha = rr.chol_upper_ladder(W)
+    assert alpha == 1e-12
+    assert np.allclose(R.T @ R, W + alpha * np.eye(3), rtol=0, atol=1e-15)
+
+
+def test_cholesky_ladder_alpha_from_spectrum():
+    # A symmetric matrix with a known negative eigenvalue: the first ladder shift
+    # that makes it positive definite is determined by lambda_min and max_i W_ii
+    # (computed independently here from eigvalsh), and no shift for an spd matrix.
+    rg = np.random.default_rng(5)
+    U, _ = np.linalg.qr(rg.standard_normal((40, 40)))
+    ev = np.logspace(0, -6, 40)
+    ev[-1] = -3.7e-9
+    W = (U * ev) @ U.T
+    W = 0.5 * (W + W.T)
+    wn = np.max(np.abs(np.diag(W)))
+    lmin = np.min(np.linalg.eigvalsh(W))
+    e = next(e for e in range(-14, 0) if lmin + 10.0 ** e * wn > 1e-12 * wn)
+    R, alpha = rr.chol_upper_ladder(W)
+    assert alpha == 10.0 ** e * wn
+    assert np.allclose(R.T @ R, W + alpha * np.eye(40), atol=1e-13)
+    R0, a0 = rr.chol_upper_ladder(W + 1e-3 * np.eye(40))
+    assert a0 == 0.0
+
+
 def test_full_rank_sketch_gives_scaled_inverse():
     # l = n: Pi = I and P = tau A_mu^{-1}
     n, mu = 50, 0.1

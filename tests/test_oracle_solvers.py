@@ -66,9 +66,36 @@ def test_restart_history_monotone_cycles():
     P = rr.build(op, [mu], p.l, p.sketch, p.omega_seed)[0]
     res = solvers.pcg(op.shifted(mu), P.apply, p.b, 1e-10, eta=1e-2)
     # one true-residual evaluation per cycle, each at least a factor ~eta lower
-    h = np.array(res.history)
+    h = np.array(res.cycle_history)
     assert len(h) == res.restarts + 2
     assert np.all(h[1:-1] <= 1.5e-2 * h[:-2])
+    # the per-iteration history has one entry per iteration plus the start, and
+    # its last entry is the final true residual
+    assert len(res.history) == res.iters + 1
+    assert res.history[0] == 1.0 and res.history[-1] == res.relres
+
+
+@pytest.mark.parametrize("precond", [False, True])
+def test_history_first_step_closed_form(precond):
+    # One (P)CG step from x0 = 0 minimises over span{Pb}: x1 = a P b with
+    # a = b^T P b / ((P b)^T A (P b)), so r1 = b - a A P b.  The oracle's history[1]
+    # must equal ||r1|| / ||b|| computed directly from that formula.
+    p, op = _kernel_problem(300)
+    mu = p.mus[0]
+    A = op.dense + mu * np.eye(p.n)
+    if precond:
+        Pc = rr.build(op, [mu], p.l, p.sketch, p.omega_seed)[0]
+        Pm = Pc.dense()
+        apply = Pc.apply
+    else:
+        Pm = np.eye(p.n)
+        apply = lambda r: r.copy()
+    b = p.b
+    z = Pm @ b
+    a = (b @ z) / (z @ (A @ z))
+    r1 = b - a * (A @ z)
+    res = solvers.pcg(lambda u: A @ u, apply, b, 1e-10, maxit=3)
+    assert abs(res.history[1] - np.linalg.norm(r1) / np.linalg.norm(b)) <= 1e-12
 
 
 def test_breakdown_on_indefinite():
