@@ -136,6 +136,9 @@ typedef struct {
     double ms_build;      /* wall time of rr_build_precond                                */
     double ms_solve;      /* wall time of the solve                                       */
     int32_t status;       /* rr_status of this solve / column                             */
+    int32_t graph_fallbacks;  /* 1 if use_graph was asked for but the runtime invalidated
+                                 the capture, so the iterations ran as eager launches of the
+                                 same kernels (same results); 0 otherwise                 */
 } rr_solve_info;
 
 /* Optional device allocator (e.g. backed by PyTorch's caching allocator). */
@@ -224,14 +227,20 @@ typedef struct {
     int32_t graph_iters;  /* PCG iterations per replayed batch                          */
     rr_build_opts build;  /* l and seed are taken per request                           */
     rr_solve_opts solve;
+    const rr_allocator* alloc;  /* device allocator for every request buffer and handle
+                                   (NULL: the library's stream-ordered pool); its alloc and
+                                   free are called from the server's worker threads       */
 } rr_serve_config;
 
 typedef struct {
-    double p50_ms, p99_ms, mean_ms;  /* arrival -> delivered latency                     */
-    double solves_per_s;             /* delivered requests / wall time                   */
-    int64_t served, rejected;
+    double p50_ms, p99_ms, mean_ms;  /* arrival -> delivered latency of OK requests        */
+    double solves_per_s;             /* OK requests / wall time                          */
+    int64_t served;                  /* requests delivered after running (ok + failed)   */
+    int64_t rejected;                /* requests refused at admission (budget, invalid)  */
     size_t hbm_peak;
     int32_t max_active;
+    int64_t ok, failed;              /* delivered with status RR_OK / with an error       */
+    int64_t graph_fallbacks;         /* requests whose PCG graph capture was invalidated  */
 } rr_serve_stats;
 
 /*
@@ -242,7 +251,9 @@ typedef struct {
  * batches on separate streams so their work overlaps, and delivers each result
  * as soon as it converges.  Per-request arithmetic does not depend on what else
  * is resident.  Returns when next() has returned -1 and every admitted request is
- * delivered.  Errors: RR_EINVAL, RR_EDEVICE.
+ * delivered.  Returns RR_OK only if every admitted request succeeded; otherwise
+ * the first failed request's status (stats->failed counts them, rr_last_error()
+ * names the first).  Errors: RR_EINVAL, RR_EDEVICE, or a request's status.
  */
 rr_status rr_serve(const rr_serve_config* cfg, rr_next_fn next, rr_deliver_fn deliver,
                    void* user, rr_serve_stats* stats);
@@ -318,6 +329,29 @@ rr_status rr_random_matrix(int32_t kind, uint64_t seed, int64_t rows, int64_t co
  */
 rr_status rr_theta_apply(uint64_t seed, int64_t n, int64_t k, const double* Y, double* S,
                          void* hip_stream);
+
+/*
+ * The build's Cholesky step on a caller matrix (inspection of the factorisation
+ * that Algorithms chol_qr / prec_chol_qr and the core R_Omega use): R (device,
+ * k x k float64, column-major, ld k) = upper factor of sym(W) + alpha I with
+ * R^T R = sym(W) + alpha I, where alpha = 0 if sym(W) factors, else the first of
+ * 10^e max_i |W_ii| (e = -14 .. -1) that does.  W (device, k x k) is borrowed and
+ * not modified.  alpha_host (may be NULL) receives alpha.  Errors: RR_EINVAL,
+ * RR_ENOTSPD (the whole ladder failed), RR_EDEVICE.  Returns after the work.
+ */
+rr_status rr_cholesky_ladder(const double* W, int64_t k, double* R, double* alpha_host,
+                             void* hip_stream);
+
+/*
+ * lambda_max of a symmetric positive semidefinite k x k float64 matrix G (device,
+ * column-major, ld k, borrowed), exactly as the NYS tau rule computes
+ * 1 / tau = lambda_max(G) (eq. nys_tau): Lanczos with full reorthogonalisation
+ * from the Gaussian start vector of stream `seed`, stopped when the Ritz residual
+ * bound is below 1e-14 lambda or after k steps.  out_host[3] = {lambda_max,
+ * residual bound (|theta - lambda| <= it), Lanczos steps}.  1 <= k <= 1536.
+ * Errors: RR_EINVAL, RR_EDEVICE.  Returns after the work.
+ */
+rr_status rr_lambda_max(const double* G, int64_t k, uint64_t seed, double* out_host, void* hip_stream);
 
 /*
  * Kernel timing for measurement (off by default).  rr_profile_enable(1) clears the

@@ -57,7 +57,7 @@ class rr_solve_info(C.Structure):
     _fields_ = [("iters", C.c_int32), ("restarts", C.c_int32), ("relres_work", C.c_double),
                 ("relres_fp64", C.c_double), ("tau", C.c_double), ("normE", C.c_double),
                 ("lamhat", C.c_double), ("orth_err", C.c_double), ("ms_build", C.c_double),
-                ("ms_solve", C.c_double), ("status", C.c_int32)]
+                ("ms_solve", C.c_double), ("status", C.c_int32), ("graph_fallbacks", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -83,13 +83,15 @@ DELIVER_FN = C.CFUNCTYPE(None, C.c_void_p, C.POINTER(rr_request), C.POINTER(rr_s
 
 class rr_serve_config(C.Structure):
     _fields_ = [("hbm_budget", C.c_size_t), ("max_slots", C.c_int32), ("graph_iters", C.c_int32),
-                ("build", rr_build_opts), ("solve", rr_solve_opts)]
+                ("build", rr_build_opts), ("solve", rr_solve_opts),
+                ("alloc", C.POINTER(rr_allocator))]
 
 
 class rr_serve_stats(C.Structure):
     _fields_ = [("p50_ms", C.c_double), ("p99_ms", C.c_double), ("mean_ms", C.c_double),
                 ("solves_per_s", C.c_double), ("served", C.c_int64), ("rejected", C.c_int64),
-                ("hbm_peak", C.c_size_t), ("max_active", C.c_int32)]
+                ("hbm_peak", C.c_size_t), ("max_active", C.c_int32), ("ok", C.c_int64),
+                ("failed", C.c_int64), ("graph_fallbacks", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -130,6 +132,8 @@ def lib():
         L.rr_theta_apply.argtypes = [C.c_uint64, C.c_int64, C.c_int64, P, P, P]
         L.rr_sketch_apply.argtypes = [C.POINTER(rr_operator), C.c_double, C.POINTER(rr_build_opts),
                                       P, P]
+        L.rr_cholesky_ladder.argtypes = [P, C.c_int64, P, C.POINTER(C.c_double), P]
+        L.rr_lambda_max.argtypes = [P, C.c_int64, C.c_uint64, P, P]
         L.rr_profile_enable.argtypes = [C.c_int32]
         L.rr_profile_enable.restype = None
         L.rr_profile_read.argtypes = [C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_double)]
@@ -143,7 +147,7 @@ def lib():
         for name in ("rr_build_precond", "rr_solve", "rr_solve_batch", "rr_serve",
                      "rr_precond_export", "rr_precond_export_omega", "rr_precond_shape",
                      "rr_kernel_to_dense", "rr_apply_operator", "rr_apply_operator_block", "rr_random_matrix", "rr_sketch_apply",
-                     "rr_theta_apply"):
+                     "rr_theta_apply", "rr_cholesky_ladder", "rr_lambda_max"):
             getattr(L, name).restype = C.c_int32
         _lib = L
     return _lib
@@ -234,6 +238,32 @@ def solve_opts(tol=1e-6, restart_eta=1e-2, maxit=5000, check_every=8, fp64_ir=-1
     return o
 
 
+class TorchAllocator:
+    """An rr_allocator backed by PyTorch's caching allocator (device memory of the
+    current device, ordered on the stream the library passes)."""
+
+    def __init__(self):
+        import torch
+        self.live = {}
+
+        def _alloc(ctx, nbytes, stream):
+            try:
+                p = torch.cuda.caching_allocator_alloc(int(nbytes), None, stream or 0)
+            except Exception:
+                return None
+            self.live[p] = stream
+            return p
+
+        def _free(ctx, ptr, stream):
+            if ptr:
+                self.live.pop(ptr, None)
+                torch.cuda.caching_allocator_delete(ptr)
+
+        self._a = rr_allocator._fields_[1][1](_alloc)
+        self._f = rr_allocator._fields_[2][1](_free)
+        self.struct = rr_allocator(ctx=None, alloc=self._a, free=self._f)
+
+
 class Precond:
     """Owning wrapper of an rr_precond handle."""
 
@@ -308,15 +338,18 @@ class Precond:
         return O.T.copy()
 
 
-def build_precond(op: Operator, mus, l=0, stream=None, **kw) -> Precond:
+def build_precond(op: Operator, mus, l=0, stream=None, allocator=None, **kw) -> Precond:
     mus = [float(m) for m in (mus if isinstance(mus, (list, tuple)) else [mus])]
     arr = (C.c_double * len(mus))(*mus)
     o = build_opts(l=l, **kw)
     h = C.c_void_p()
-    st = lib().rr_build_precond(C.byref(op.struct), arr, len(mus), C.byref(o), None,
+    ap = C.byref(allocator.struct) if allocator is not None else None
+    st = lib().rr_build_precond(C.byref(op.struct), arr, len(mus), C.byref(o), ap,
                                 _stream(stream), C.byref(h))
     _check(st, "rr_build_precond")
-    return Precond(h, op, mus)
+    P = Precond(h, op, mus)
+    P.allocator = allocator   # the handle frees through it: keep it alive as long
+    return P
 
 
 def kernel_to_dense(op: Operator, dtype: str = "fp64", stream=None):
@@ -370,6 +403,28 @@ def theta_apply(seed: int, Y, stream=None):
     return S.t()
 
 
+def cholesky_ladder(W, stream=None):
+    """(R, alpha): the build's Cholesky with its shift ladder; W: CUDA float64 (k, k) symmetric."""
+    import torch
+    k = W.shape[0]
+    Wc = W.t().contiguous()
+    R = torch.empty_like(Wc)
+    a = C.c_double()
+    _check(lib().rr_cholesky_ladder(_ptr(Wc), k, _ptr(R), C.byref(a), _stream(stream)),
+           "rr_cholesky_ladder")
+    return R.t(), a.value
+
+
+def lambda_max(G, seed: int = 0, stream=None):
+    """(lambda_max, residual bound, steps) of a symmetric psd CUDA float64 (k, k) G."""
+    k = G.shape[0]
+    Gc = G.t().contiguous()
+    out = np.zeros(3)
+    _check(lib().rr_lambda_max(_ptr(Gc), k, int(seed), out.ctypes.data_as(C.c_void_p),
+                               _stream(stream)), "rr_lambda_max")
+    return float(out[0]), float(out[1]), int(out[2])
+
+
 (PROF_KERNEL_MATVEC, PROF_KERNEL_SKETCH, PROF_DENSE_MATVEC, PROF_DENSE_SKETCH, PROF_PROJECT,
  PROF_KERNEL_MATMAT) = range(6)
 
@@ -396,7 +451,7 @@ def sketch(op: Operator, mu: float, l: int, stream=None, **kw):
 
 
 def serve(requests, hbm_budget: int = 96 << 30, max_slots: int = 8, graph_iters: int = 8,
-          build: Optional[dict] = None, solve: Optional[dict] = None):
+          build: Optional[dict] = None, solve: Optional[dict] = None, allocator=None):
     """Run the continuous-batching server over `requests` (arrival-ordered).
 
     Each request is a dict with keys: kind, pts (float32 (d, n) host array), kconst,
@@ -452,11 +507,16 @@ def serve(requests, hbm_budget: int = 96 << 30, max_slots: int = 8, graph_iters:
 
     nf, df = NEXT_FN(_next), DELIVER_FN(_deliver)
     stats = rr_serve_stats()
-    _check(lib().rr_serve(C.byref(cfg), nf, df, None, C.byref(stats)), "rr_serve")
+    if allocator is not None:
+        cfg.alloc = C.pointer(allocator.struct)
+    st = lib().rr_serve(C.byref(cfg), nf, df, None, C.byref(stats))
+    if st == RR_EINVAL or (st != RR_OK and stats.served + stats.rejected == 0):
+        _check(st, "rr_serve")
     for i, (pts, Bc, Xc) in enumerate(keep):
         if results[i] is not None:
             results[i]["X"] = Xc.T.copy()
     out = stats.as_dict()
-    if any(r is not None and r["info"]["status"] != RR_OK for r in results):
+    out["status"] = st
+    if st != RR_OK:
         out["first_error"] = lib().rr_last_error().decode()
     return results, out

@@ -144,6 +144,36 @@ void release_stream_blocks(hipStream_t st) {
     }
 }
 
+namespace {
+std::mutex g_stream_mu;
+std::vector<SideStream> g_free_streams;
+}  // namespace
+
+SideStream acquire_side_stream() {
+    int dev = 0;
+    RR_HIP(hipGetDevice(&dev));
+    {
+        std::lock_guard<std::mutex> lk(g_stream_mu);
+        for (size_t i = g_free_streams.size(); i-- > 0;)
+            if (g_free_streams[i].dev == dev) {
+                SideStream s = g_free_streams[i];
+                g_free_streams.erase(g_free_streams.begin() + (std::ptrdiff_t)i);
+                return s;
+            }
+    }
+    SideStream s;
+    s.dev = dev;
+    RR_HIP(hipStreamCreateWithFlags(&s.st, hipStreamNonBlocking));
+    RR_HIP(hipEventCreateWithFlags(&s.a, hipEventDisableTiming));
+    RR_HIP(hipEventCreateWithFlags(&s.b, hipEventDisableTiming));
+    return s;
+}
+
+void release_side_stream(const SideStream& s) {
+    std::lock_guard<std::mutex> lk(g_stream_mu);
+    g_free_streams.push_back(s);
+}
+
 void Alloc::put(void* p) const {
     if (!p) return;
     if (custom) {
@@ -289,7 +319,19 @@ void require_device() {
 }  // namespace rr
 
 rr_precond::~rr_precond() {
-    if (ws) rr_free_workspace(ws);
+    for (rr::Workspace* w : ws_pool) rr_free_workspace(w);
+}
+
+void rr_precond_release(rr_precond* P, bool keep_stream) {
+    if (!P) return;
+    try {
+        if (!P->alloc.custom && !keep_stream) {
+            P->alloc.st = nullptr;
+            for (rr::Workspace* w : P->ws_pool) rr_workspace_null_stream(w);
+        }
+        delete P;
+    } catch (...) {
+    }
 }
 
 using namespace rr;
@@ -342,19 +384,12 @@ const char* rr_last_error(void) { return g_last_error.c_str(); }
 const char* rr_version(void) { return "randrand-gfx950 0.1"; }
 
 void rr_precond_destroy(rr_precond* P) {
-    if (!P) return;
-    try {
-        if (!P->alloc.custom) {
-            // the handle's buffers were ordered on the build (and solve) streams, which
-            // the caller may have destroyed since: finish all work, then free on the
-            // null stream
-            (void)hipDeviceSynchronize();
-            P->alloc.st = nullptr;
-            rr_workspace_null_stream(P->ws);
-        }
-        delete P;
-    } catch (...) {
-    }
+    // Every entry point returns only after its device work has completed, so the
+    // handle's buffers have no work pending: no device-wide wait here (one would
+    // also stall, or break the graph captures of, other threads' streams).  The
+    // build and solve streams may be gone by now, so the blocks go to the null
+    // stream's cache.
+    rr_precond_release(P, false);
 }
 
 rr_status rr_precond_shape(const rr_precond* P, int64_t* n, int64_t* l, int32_t* n_mu) {

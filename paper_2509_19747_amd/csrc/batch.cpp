@@ -286,17 +286,18 @@ rr_status rr_solve_batch_fused(const rr_precond* Pc, const int32_t* mu_index_per
         RR_HIP(hipMemcpyAsync(Bt.state.ptr(), hs.data(), m * sizeof(BState), hipMemcpyHostToDevice, st));
         // optional hipGraph of one batch of check_every iterations, captured on a
         // private stream the first time and replayed after every host check
+        PooledStream capture;
         hipStream_t cap = nullptr;
         hipGraph_t graph = nullptr;
         hipGraphExec_t gexec = nullptr;
         struct GraphGuard {
-            hipStream_t* s; hipGraph_t* g; hipGraphExec_t* e;
+            hipGraph_t* g; hipGraphExec_t* e;
             ~GraphGuard() {
                 if (*e) (void)hipGraphExecDestroy(*e);
                 if (*g) (void)hipGraphDestroy(*g);
-                if (*s) (void)hipStreamDestroy(*s);
             }
-        } gguard{&cap, &graph, &gexec};
+        } gguard{&graph, &gexec};
+        int graph_fallbacks = 0;
         bool eager = !o->use_graph;
         auto run_batch = [&]() {
             if (eager) {
@@ -305,7 +306,7 @@ rr_status rr_solve_batch_fused(const rr_precond* Pc, const int32_t* mu_index_per
             }
             RR_HIP(hipStreamSynchronize(st));   // everything queued on st precedes the replay
             if (!gexec) {
-                RR_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+                cap = capture.get();
                 Bt.st = cap;
                 // relaxed: the capture holds kernel launches only, and allocation or copy calls
                 // of other threads (a server's other requests) must not invalidate it
@@ -314,13 +315,13 @@ rr_status rr_solve_batch_fused(const rr_precond* Pc, const int32_t* mu_index_per
                 const hipError_t ce = hipStreamEndCapture(cap, &graph);
                 Bt.st = st;
                 if (ce != hipSuccess) {
-                    // The runtime invalidated the capture (seen under concurrent requests in
-                    // one process, after the preconditioner's launches): nothing captured
-                    // has run, so the batch runs eagerly, now and for the rest of the solve,
-                    // with the same kernels and results.
+                    // An invalidated capture has run nothing: the batch runs eagerly, now
+                    // and for the rest of the solve, with the same kernels and results,
+                    // and every column's info.graph_fallbacks reports it.
                     (void)hipGetLastError();
                     if (graph) { (void)hipGraphDestroy(graph); graph = nullptr; }
                     eager = true;
+                    graph_fallbacks = 1;
                     for (int k = 0; k < o->check_every; ++k) Bt.iteration(X, ldx);
                     return;
                 }
@@ -366,6 +367,7 @@ rr_status rr_solve_batch_fused(const rr_precond* Pc, const int32_t* mu_index_per
                 rr_solve_info& inf = infos[j];
                 const PerMu& pm = P.per[mu_index_per_col[j]];
                 inf.iters = iters[j];
+                inf.graph_fallbacks = graph_fallbacks;
                 inf.restarts = std::max(cycles[j] - 1, 0);
                 inf.relres_work = relres[j];
                 inf.relres_fp64 = rel64[j];

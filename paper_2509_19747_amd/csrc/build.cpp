@@ -84,12 +84,13 @@ struct Builder {
         launch_cholesky_upper(A, l, l, stat, ws, wsd, s);
         check_launch();
     }
-    void chol_finish(double* A, int64_t l, const double* copy, hipStream_t s, int32_t* stat, double* ws,
-                     size_t wsd) {
+    // returns the shift alpha that the factored matrix carries (0: none)
+    double chol_finish(double* A, int64_t l, const double* copy, hipStream_t s, int32_t* stat, double* ws,
+                       size_t wsd) {
         int32_t h = 0;
         RR_HIP(hipMemcpyAsync(&h, stat, sizeof(int32_t), hipMemcpyDeviceToHost, s));
         RR_HIP(hipStreamSynchronize(s));
-        if (h == 0) return;
+        if (h == 0) return 0.0;
         std::vector<double> hc((size_t)l * l);
         RR_HIP(hipMemcpyAsync(hc.data(), copy, hc.size() * sizeof(double), hipMemcpyDeviceToHost, s));
         RR_HIP(hipStreamSynchronize(s));
@@ -105,44 +106,34 @@ struct Builder {
             check_launch();
             RR_HIP(hipMemcpyAsync(&h, stat, sizeof(int32_t), hipMemcpyDeviceToHost, s));
             RR_HIP(hipStreamSynchronize(s));
-            if (h == 0) return;
+            if (h == 0) return alpha;
         }
         throw RrError{RR_ENOTSPD, "Cholesky failed after the whole shift ladder"};
     }
-    void chol_ladder(double* A, int64_t l) {
+    double chol_ladder(double* A, int64_t l) {
         DBuf copy = mat(l, l);
         chol_start(A, l, copy.as<double>(), st, status.as<int32_t>(), gws.as<double>(), gwsd);
-        chol_finish(A, l, copy.as<double>(), st, status.as<int32_t>(), gws.as<double>(), gwsd);
+        return chol_finish(A, l, copy.as<double>(), st, status.as<int32_t>(), gws.as<double>(), gwsd);
     }
 
     // A second stream for work that does not depend on the main chain (its own
     // status word and GEMM workspace); side_begin orders it after everything queued
     // on the main stream so far, side_join makes the main stream wait for it.
+    PooledStream side;
     hipStream_t st2 = nullptr;
-    hipEvent_t ev_a = nullptr, ev_b = nullptr;
     DBuf gws2, status2;
     void side_begin() {
         if (!st2) {
-            RR_HIP(hipStreamCreateWithFlags(&st2, hipStreamNonBlocking));
-            RR_HIP(hipEventCreateWithFlags(&ev_a, hipEventDisableTiming));
-            RR_HIP(hipEventCreateWithFlags(&ev_b, hipEventDisableTiming));
+            st2 = side.get();
             gws2.reset(al, gwsd * sizeof(double));
             status2.reset(al, 64);
         }
-        RR_HIP(hipEventRecord(ev_a, st));
-        RR_HIP(hipStreamWaitEvent(st2, ev_a, 0));
+        RR_HIP(hipEventRecord(side.ev_a(), st));
+        RR_HIP(hipStreamWaitEvent(st2, side.ev_a(), 0));
     }
     void side_join() {
-        RR_HIP(hipEventRecord(ev_b, st2));
-        RR_HIP(hipStreamWaitEvent(st, ev_b, 0));
-    }
-    ~Builder() {
-        if (st2) {
-            (void)hipStreamSynchronize(st2);
-            (void)hipStreamDestroy(st2);
-        }
-        if (ev_a) (void)hipEventDestroy(ev_a);
-        if (ev_b) (void)hipEventDestroy(ev_b);
+        RR_HIP(hipEventRecord(side.ev_b(), st2));
+        RR_HIP(hipStreamWaitEvent(st, side.ev_b(), 0));
     }
 
     // Omega (n x l) into P.Omega.  In float32 mode for kernels and in mixed mode for
@@ -291,8 +282,20 @@ struct Builder {
         return lam;
     }
 
-    // lambda_max of a small spd k x k matrix by power iteration on the device.
+    // lambda_max of a small spd k x k matrix on the device: Lanczos with full
+    // reorthogonalisation run until its Ritz residual bound is below 1e-14 lambda
+    // (k <= lanczos_max_dim()), else 200 power-iteration steps.
     double small_lambda_max(const double* G, int64_t k, uint64_t seed) {
+        if (k <= lanczos_max_dim()) {
+            DBuf ws(al, lanczos_ws_doubles(k) * sizeof(double));
+            double* o3 = scal.as<double>() + 8;
+            launch_lanczos_lmax(G, k, k, seed, ws.as<double>(), o3, st);
+            check_launch();
+            double h[3] = {0.0, 0.0, 0.0};
+            RR_HIP(hipMemcpyAsync(h, o3, sizeof(h), hipMemcpyDeviceToHost, st));
+            sync();
+            return h[0];
+        }
         DBuf v(al, k * sizeof(double)), w(al, k * sizeof(double));
         launch_gauss_fill(v.ptr(), DT_F64, k, 1, k, seed, st);
         launch_dot_part(k, v.as<double>(), v.as<double>(), vparts.as<double>(), st);
@@ -682,6 +685,49 @@ extern "C" rr_status rr_sketch_apply(const rr_operator* A, double mu, const rr_b
         B.sketch(P.Omega.ptr(), P.omega_dt, mu, Y.ptr(), ydt, A16.ptr());
         launch_copy_mat(ydt, Y.ptr(), n, DT_F64, Y_out, n, n, l, st);
         RR_HIP(hipGetLastError());
+        RR_HIP(hipStreamSynchronize(st));
+        return RR_OK;
+    });
+}
+
+// Inspection: the build's Cholesky with its shift ladder on a caller matrix.
+extern "C" rr_status rr_cholesky_ladder(const double* W, int64_t k, double* R, double* alpha_host,
+                                        void* hip_stream) {
+    return guarded([&]() -> rr_status {
+        RR_REQUIRE(W != nullptr && R != nullptr, "W or R is null");
+        RR_REQUIRE(k >= 1 && k <= 16384, "k must be in [1, 16384]");
+        require_device();
+        hipStream_t st = (hipStream_t)hip_stream;
+        rr_precond P;
+        P.op.kind = RR_OP_DENSE;
+        P.n = k;
+        P.l = k;
+        P.kb = k;
+        P.alloc.st = st;
+        Builder B(P, st);
+        RR_HIP(hipMemcpyAsync(R, W, (size_t)k * k * sizeof(double), hipMemcpyDeviceToDevice, st));
+        launch_symmetrize(R, k, k, st);
+        const double a = B.chol_ladder(R, k);
+        if (alpha_host) *alpha_host = a;
+        RR_HIP(hipStreamSynchronize(st));
+        return RR_OK;
+    });
+}
+
+// Inspection: lambda_max of a symmetric psd matrix exactly as the NYS tau rule takes it.
+extern "C" rr_status rr_lambda_max(const double* G, int64_t k, uint64_t seed, double* out_host,
+                                   void* hip_stream) {
+    return guarded([&]() -> rr_status {
+        RR_REQUIRE(G != nullptr && out_host != nullptr, "G or out is null");
+        RR_REQUIRE(k >= 1 && k <= lanczos_max_dim(), "k must be in [1, 1536]");
+        require_device();
+        hipStream_t st = (hipStream_t)hip_stream;
+        Alloc al;
+        al.st = st;
+        DBuf ws(&al, lanczos_ws_doubles(k) * sizeof(double)), o3(&al, 4 * sizeof(double));
+        launch_lanczos_lmax(G, k, k, seed, ws.as<double>(), o3.as<double>(), st);
+        RR_HIP(hipGetLastError());
+        RR_HIP(hipMemcpyAsync(out_host, o3.ptr(), 3 * sizeof(double), hipMemcpyDeviceToHost, st));
         RR_HIP(hipStreamSynchronize(st));
         return RR_OK;
     });

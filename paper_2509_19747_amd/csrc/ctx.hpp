@@ -64,6 +64,43 @@ struct Alloc {
     void put(void* p) const;
 };
 
+// Non-blocking streams (each with two timing-free events) kept in a process-wide
+// pool per device and reused: the library never creates or destroys a stream
+// inside a build or a solve, so concurrent requests do not churn streams while
+// other threads capture graphs.
+struct SideStream {
+    hipStream_t st = nullptr;
+    hipEvent_t a = nullptr, b = nullptr;
+    int dev = 0;
+};
+SideStream acquire_side_stream();
+void release_side_stream(const SideStream& s);
+class PooledStream {
+  public:
+    PooledStream() = default;
+    ~PooledStream() { reset(); }
+    PooledStream(const PooledStream&) = delete;
+    PooledStream& operator=(const PooledStream&) = delete;
+    hipStream_t get() {
+        if (!s_.st) s_ = acquire_side_stream();
+        return s_.st;
+    }
+    hipEvent_t ev_a() { get(); return s_.a; }
+    hipEvent_t ev_b() { get(); return s_.b; }
+    bool active() const { return s_.st != nullptr; }
+    hipStream_t raw() const { return s_.st; }
+    void reset() {
+        if (s_.st) {
+            (void)hipStreamSynchronize(s_.st);
+            release_side_stream(s_);
+            s_ = SideStream{};
+        }
+    }
+
+  private:
+    SideStream s_;
+};
+
 // Owning device buffer.
 class DBuf {
   public:
@@ -123,6 +160,11 @@ struct Workspace;
 
 void rr_free_workspace(rr::Workspace* w);
 void rr_workspace_null_stream(rr::Workspace* w);   // free on the null stream from now on
+// Release a handle whose work has completed.  keep_stream: its blocks stay in the
+// allocator cache of the stream it was built on (the caller guarantees that stream
+// is alive, as the server's worker streams are); otherwise they go to the null
+// stream's cache.
+void rr_precond_release(rr_precond* P, bool keep_stream);
 
 struct rr_precond {
     rr_operator op{};
@@ -142,9 +184,11 @@ struct rr_precond {
     double orth_err = 0.0;
     double ms_build = 0.0;
     int device = 0;
-    // cached solve workspace (guarded by ws_mu)
+    // solve workspaces: each rr_solve takes one from this pool (or makes one) and
+    // returns it, so concurrent solves on one handle run with their own
+    // workspaces; the pool is guarded by ws_mu
     std::mutex ws_mu;
-    rr::Workspace* ws = nullptr;
+    std::vector<rr::Workspace*> ws_pool;
     ~rr_precond();
 };
 

@@ -119,6 +119,14 @@ void launch_householder_r_blocked(double* S, int64_t m, int64_t k, int64_t lds, 
 void launch_householder_qr_blocked(double* S, int64_t m, int64_t k, int64_t lds, double* Q,
                                    int64_t ldq, double* R, int64_t ldr, double* ws, size_t wsd,
                                    hipStream_t st);
+// lambda_max of a symmetric psd k x k matrix G (k <= lanczos_max_dim()) by Lanczos
+// with full reorthogonalisation in one workgroup; start vector from Gaussian stream
+// `seed`.  out3 (device): {lambda_max, Ritz residual bound, steps}.  ws:
+// lanczos_ws_doubles(k) doubles.
+int lanczos_max_dim();
+size_t lanczos_ws_doubles(int64_t k);
+void launch_lanczos_lmax(const double* G, int64_t ldg, int64_t k, uint64_t seed, double* ws, double* out3,
+                         hipStream_t st);
 // X = R^{-1} for an upper-triangular l x l R.
 void launch_tri_inv_upper(const double* R, int64_t l, int64_t ldr, double* X, int64_t ldx,
                           hipStream_t st);

@@ -60,8 +60,8 @@ struct Shared {
     bool stop = false;
     size_t used = 0, peak = 0;
     int active = 0, max_active = 0;
-    std::vector<double> lat_ms;
-    int64_t served = 0, rejected = 0;
+    std::vector<double> lat_ms;          // OK requests only
+    int64_t served = 0, rejected = 0, ok = 0, failed = 0, graph_fallbacks = 0;
     std::mutex deliver_mu;
     rr_status first_err = RR_OK;
     std::string first_err_msg;   // the library's message for the first failed request
@@ -82,11 +82,28 @@ void run_job(const rr_serve_config& cfg, Job& job, hipStream_t st, double t0, rr
         info.status = s;
         if (err_msg.empty()) err_msg = rr_last_error();   // this worker thread's message
     };
-    do {
-        if (hipMallocAsync((void**)&pts, (size_t)r.d * n * sizeof(float), st) != hipSuccess ||
-            hipMallocAsync((void**)&b, (size_t)n * nr * sizeof(double), st) != hipSuccess ||
-            hipMallocAsync((void**)&x, (size_t)n * nr * sizeof(double), st) != hipSuccess) {
+    // request buffers: the caller's allocator when the config has one, else the
+    // device's stream-ordered pool on this worker's stream
+    const rr_allocator* ua = cfg.alloc;
+    auto dalloc = [&](size_t bytes) -> void* {
+        if (ua) return ua->alloc(ua->ctx, bytes, (void*)st);
+        void* q = nullptr;
+        if (hipMallocAsync(&q, bytes, st) != hipSuccess) {
             (void)hipGetLastError();
+            return nullptr;
+        }
+        return q;
+    };
+    auto dfree = [&](void* q) {
+        if (!q) return;
+        if (ua) ua->free(ua->ctx, q, (void*)st);
+        else (void)hipFreeAsync(q, st);
+    };
+    do {
+        pts = (float*)dalloc((size_t)r.d * n * sizeof(float));
+        b = (double*)dalloc((size_t)n * nr * sizeof(double));
+        x = (double*)dalloc((size_t)n * nr * sizeof(double));
+        if (!pts || !b || !x) {
             fail(RR_ENOMEM);
             break;
         }
@@ -109,7 +126,7 @@ void run_job(const rr_serve_config& cfg, Job& job, hipStream_t st, double t0, rr
         const double mu = r.mu;
         // the library's own allocation path: the worker's stream keeps its freed
         // blocks, so the next request on this slot reuses them without pool calls
-        rr_status s = rr_build_precond(&op, &mu, 1, &bo, nullptr, st, &P);
+        rr_status s = rr_build_precond(&op, &mu, 1, &bo, ua, st, &P);
         if (s != RR_OK) { fail(s); break; }
         // every right-hand side of the request in one fused batched PCG, its
         // iteration batches replayed as a hipGraph
@@ -133,6 +150,7 @@ void run_job(const rr_serve_config& cfg, Job& job, hipStream_t st, double t0, rr
             info.ms_build = si.ms_build;
             info.ms_solve = si.ms_solve;
             info.restarts = std::max(info.restarts, si.restarts);
+            info.graph_fallbacks = std::max(info.graph_fallbacks, si.graph_fallbacks);
         }
         if (hipMemcpyAsync(r.X, x, (size_t)n * nr * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
             hipStreamSynchronize(st) != hipSuccess) {
@@ -144,10 +162,13 @@ void run_job(const rr_serve_config& cfg, Job& job, hipStream_t st, double t0, rr
         if (s != RR_OK) fail(s);
     } while (false);
     (void)hipStreamSynchronize(st);
-    if (P) rr_precond_destroy(P);
-    if (pts) (void)hipFreeAsync(pts, st);
-    if (b) (void)hipFreeAsync(b, st);
-    if (x) (void)hipFreeAsync(x, st);
+    // the handle's work is complete (every call returned after it); its blocks stay
+    // in this worker stream's cache for the next request on the slot.  No device-wide
+    // synchronisation anywhere on this path: other workers may be capturing graphs.
+    if (P) rr_precond_release(P, true);
+    dfree(pts);
+    dfree(b);
+    dfree(x);
     (void)hipStreamSynchronize(st);
     const double t_done = wall_s() - t0;
     {
@@ -158,7 +179,13 @@ void run_job(const rr_serve_config& cfg, Job& job, hipStream_t st, double t0, rr
     sh.used -= job.bytes;
     sh.active -= 1;
     sh.served += 1;
-    sh.lat_ms.push_back(1e3 * (t_done - r.t_arrival));
+    if (info.status == RR_OK) {
+        sh.ok += 1;
+        sh.lat_ms.push_back(1e3 * (t_done - r.t_arrival));
+    } else {
+        sh.failed += 1;
+    }
+    sh.graph_fallbacks += info.graph_fallbacks ? 1 : 0;
     if (info.status != RR_OK && sh.first_err == RR_OK) {
         sh.first_err = (rr_status)info.status;
         sh.first_err_msg = err_msg;
@@ -176,6 +203,7 @@ extern "C" rr_status rr_serve(const rr_serve_config* cfg, rr_next_fn next, rr_de
         RR_REQUIRE(cfg->max_slots >= 1 && cfg->max_slots <= 64, "max_slots must be in [1, 64]");
         RR_REQUIRE(cfg->hbm_budget > 0, "hbm_budget must be > 0");
         RR_REQUIRE(cfg->graph_iters >= 0 && cfg->graph_iters <= 4096, "graph_iters must be in [0, 4096]");
+        if (cfg->alloc) RR_REQUIRE(cfg->alloc->alloc && cfg->alloc->free, "allocator callbacks are null");
         require_device();
         int dev = 0;
         RR_HIP(hipGetDevice(&dev));
@@ -276,13 +304,18 @@ extern "C" rr_status rr_serve(const rr_serve_config* cfg, rr_next_fn next, rr_de
             stats->mean_ms = v.empty() ? 0.0 : s / v.size();
             stats->served = sh.served;
             stats->rejected = sh.rejected;
-            stats->solves_per_s = wall > 0 ? sh.served / wall : 0.0;
+            stats->ok = sh.ok;
+            stats->failed = sh.failed;
+            stats->graph_fallbacks = sh.graph_fallbacks;
+            stats->solves_per_s = wall > 0 ? sh.ok / wall : 0.0;
             stats->hbm_peak = sh.peak;
             stats->max_active = sh.max_active;
         }
         (void)loop_err;
-        if (sh.first_err != RR_OK)
+        if (sh.first_err != RR_OK) {
             set_error("at least one request failed (see its deliver status); first: " + sh.first_err_msg);
+            return sh.first_err;
+        }
         return RR_OK;
     });
 }

@@ -33,8 +33,7 @@ struct Workspace {
     DBuf op_part, rr_part, rz_part, c_part, d, kws, state, flag, scal, hist;
     int32_t hist_cap = 0;
     int op_parts = 0, nch = 0;
-    hipStream_t cap = nullptr;   // private stream used for graph capture/replay
-    ~Workspace() { if (cap) (void)hipStreamDestroy(cap); }
+    PooledStream cap;            // private stream used for graph capture/replay
 };
 
 static Workspace* make_workspace(const rr_precond& P, int32_t maxit, hipStream_t st) {
@@ -161,13 +160,28 @@ extern "C" rr_status rr_solve(const rr_precond* Pc, int32_t mu_index, const doub
         require_device();
         rr_precond& P = const_cast<rr_precond&>(*Pc);
         hipStream_t st = (hipStream_t)hip_stream;
-        std::lock_guard<std::mutex> lock(P.ws_mu);
-        if (!P.ws || P.ws->hist_cap < o.maxit + 2) {
-            if (P.ws) rr_free_workspace(P.ws);
-            P.ws = nullptr;
-            P.ws = make_workspace(P, o.maxit, st);
+        // a workspace of this handle's pool (a new one if every pooled one is busy
+        // or too small); returned to the pool when the solve ends
+        Workspace* wsp = nullptr;
+        {
+            std::lock_guard<std::mutex> lock(P.ws_mu);
+            for (size_t i = P.ws_pool.size(); i-- > 0;)
+                if (P.ws_pool[i]->hist_cap >= o.maxit + 2) {
+                    wsp = P.ws_pool[i];
+                    P.ws_pool.erase(P.ws_pool.begin() + (std::ptrdiff_t)i);
+                    break;
+                }
         }
-        Workspace& W = *P.ws;
+        if (!wsp) wsp = make_workspace(P, o.maxit, st);
+        struct WsReturn {
+            rr_precond& P;
+            Workspace* w;
+            ~WsReturn() {
+                std::lock_guard<std::mutex> lock(P.ws_mu);
+                P.ws_pool.push_back(w);
+            }
+        } ws_return{P, wsp};
+        Workspace& W = *wsp;
         const PerMu& pm = P.per[mu_index];
         Solver S{P, W, st, pm.mu, P.l > 0 ? pm.Kc.as<double>() : nullptr};
         const int64_t n = P.n;
@@ -236,16 +250,18 @@ extern "C" rr_status rr_solve(const rr_precond* Pc, int32_t mu_index, const doub
                 if (o.use_graph && !graph_failed) {
                     // capture on a private non-default stream; the caller's stream
                     // has been synchronised, so ordering is preserved
-                    if (!W.cap) RR_HIP(hipStreamCreateWithFlags(&W.cap, hipStreamNonBlocking));
+                    hipStream_t cst = W.cap.get();
                     S.sync();
                     if (!gexec) {
-                        Solver C{P, W, W.cap, S.mu, S.Kc};
+                        Solver C{P, W, cst, S.mu, S.Kc};
                         // relaxed: the capture holds kernel launches only, and allocation or copy calls
                         // of other threads (a server's other requests) must not invalidate it
-                        RR_HIP(hipStreamBeginCapture(W.cap, hipStreamCaptureModeRelaxed));
+                        RR_HIP(hipStreamBeginCapture(cst, hipStreamCaptureModeRelaxed));
                         for (int k = 0; k < o.check_every; ++k) C.iteration(x);
-                        if (hipStreamEndCapture(W.cap, &graph) != hipSuccess) {
-                            // an invalidated capture ran nothing: continue eagerly
+                        if (hipStreamEndCapture(cst, &graph) != hipSuccess) {
+                            // an invalidated capture ran nothing: the solve continues with
+                            // eager launches of the same kernels, and info.graph_fallbacks
+                            // reports it
                             (void)hipGetLastError();
                             if (graph) { (void)hipGraphDestroy(graph); graph = nullptr; }
                             graph_failed = true;
@@ -253,8 +269,8 @@ extern "C" rr_status rr_solve(const rr_precond* Pc, int32_t mu_index, const doub
                         }
                         RR_HIP(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
                     }
-                    RR_HIP(hipGraphLaunch(gexec, W.cap));
-                    RR_HIP(hipStreamSynchronize(W.cap));
+                    RR_HIP(hipGraphLaunch(gexec, cst));
+                    RR_HIP(hipStreamSynchronize(cst));
                 } else {
                     for (int k = 0; k < o.check_every; ++k) S.iteration(x);
                 }
@@ -278,6 +294,7 @@ extern "C" rr_status rr_solve(const rr_precond* Pc, int32_t mu_index, const doub
             // STOP_TARGET or STOP_MAXIT: recompute the true residual (restart)
         }
         inf.iters = its;
+        inf.graph_fallbacks = graph_failed ? 1 : 0;
         inf.restarts = std::max(cycles - 1, 0);
         inf.relres_work = relres;
         inf.ms_solve = now_ms() - t0;

@@ -233,8 +233,8 @@ def test_build_fp64_matches_oracle(dense_small, orth, tau_rule):
     assert rel(g["G"], o.G) < 1e-9
     assert rel(g["T"], o.T) < 1e-12
     if tau_rule == "nys":
-        # device power iteration on G versus the exact eigenvalue in the oracle
-        assert abs(g["tau"] - o.tau) < 1e-4 * o.tau
+        # device Lanczos on the device G versus the exact eigenvalue of the oracle's G
+        assert abs(g["tau"] - o.tau) < 1e-9 * o.tau
     else:
         assert abs(g["normE"] - o.normE) < 1e-9 * o.normE
         assert abs(g["lam"] - o.lam) < 1e-9 * o.lam
@@ -257,6 +257,55 @@ def test_build_fp64_wide_basis_matches_oracle():
     assert rel(g["R"], o.R) < 1e-9
     assert rel(g["G"], o.G) < 1e-8
     assert abs(g["tau"] - o.tau) < 1e-8 * o.tau
+
+
+@pytest.mark.parametrize("k,spectrum", [(1, "flat"), (45, "decay"), (300, "cluster"),
+                                        (1024, "decay"), (1536, "lowrank")])
+def test_lambda_max_matches_eigvalsh(k, spectrum):
+    """The NYS rule's lambda_max(G) (eq. nys_tau) against LAPACK's eigvalsh, to rounding:
+    decaying, top-clustered (gap 1e-6) and rank-deficient spectra."""
+    g = np.random.default_rng(k)
+    U, _ = np.linalg.qr(g.standard_normal((k, k)))
+    if spectrum == "flat":
+        ev = np.full(k, 2.5)
+    elif spectrum == "decay":
+        ev = np.logspace(2, -8, k)
+    elif spectrum == "cluster":
+        ev = np.concatenate([[1.0, 1.0 - 1e-6, 1.0 - 2e-6], np.linspace(0.9, 1e-3, k - 3)])
+    else:
+        ev = np.concatenate([np.logspace(1, -3, 40), np.zeros(k - 40)])
+    G = (U * ev) @ U.T
+    G = 0.5 * (G + G.T)
+    lam, res, steps = rr.binding.lambda_max(_cuda(G), seed=7)
+    ref = np.max(np.linalg.eigvalsh(G))
+    assert abs(lam - ref) <= 1e-12 * ref, (lam, ref, res, steps)
+    assert res <= 1e-13 * ref or steps == k
+
+
+def test_cholesky_ladder_matches_oracle():
+    """The device Cholesky and its shift ladder against the oracle's: same alpha, and
+    R^T R = W + alpha I to rounding (no shift for an spd W, one step for a failing pivot)."""
+    g = np.random.default_rng(5)
+    U, _ = np.linalg.qr(g.standard_normal((40, 40)))
+    for ev_min, shift in ((1e-3, 0.0), (-3.7e-9, None)):
+        ev = np.logspace(0, -6, 40)
+        ev[-1] = ev_min
+        W = (U * ev) @ U.T
+        W = 0.5 * (W + W.T)
+        R, alpha = rr.binding.cholesky_ladder(_cuda(W))
+        R = R.cpu().numpy()
+        Ro, ao = orr.chol_upper_ladder(W)
+        assert alpha == ao
+        if shift is not None:
+            assert alpha == shift
+        assert np.allclose(np.tril(R, -1), 0.0)
+        assert np.linalg.norm(R.T @ R - (W + alpha * np.eye(40))) < 1e-13
+    W = np.diag([1.0, 1.0, -5e-13])
+    R, alpha = rr.binding.cholesky_ladder(_cuda(W))
+    assert alpha == 1e-12
+    W = -np.eye(4)
+    with pytest.raises(rr.RRError):
+        rr.binding.cholesky_ladder(_cuda(W))
 
 
 @pytest.mark.parametrize("n,l", [(300, 64), (320, 65), (600, 200), (800, 300)])
@@ -655,13 +704,19 @@ def test_serving_alone_equals_mixed_and_oracle():
     reqs = _serving_requests(10, 3)
     kw = dict(build=dict(prec="fp32", sketch="gaussian"), solve=dict(tol=1e-6, certify=True))
     mixed, stats = rb.serve(reqs, max_slots=4, graph_iters=8, **kw)
+    assert stats["status"] == rr.RR_OK, stats.get("first_error")
     assert stats["served"] == len(reqs) and stats["rejected"] == 0
+    assert stats["ok"] == len(reqs) and stats["failed"] == 0
+    # every request's PCG batches ran as replayed graphs (no invalidated capture)
+    assert stats["graph_fallbacks"] == 0
     assert stats["max_active"] >= 2
     assert 0 < stats["p50_ms"] <= stats["p99_ms"]
     for i, r in enumerate(reqs):
-        alone, _ = rb.serve([dict(r, t_arrival=0.0)], max_slots=1, graph_iters=8, **kw)
+        alone, st1 = rb.serve([dict(r, t_arrival=0.0)], max_slots=1, graph_iters=8, **kw)
         assert mixed[i]["info"]["status"] == rr.RR_OK, stats.get("first_error")
+        assert mixed[i]["info"]["graph_fallbacks"] == 0
         assert alone[0]["info"]["status"] == rr.RR_OK
+        assert st1["graph_fallbacks"] == 0
         assert np.array_equal(alone[0]["X"], mixed[i]["X"])      # bitwise: batch-invariant
         op = Operator(kind=rr.OP_RBF, pts=r["pts"], kconst=r["kconst"], scale=r["scale"])
         for j in range(r["B"].shape[1]):
@@ -675,5 +730,49 @@ def test_serving_rejects_over_budget():
     from paper_2509_19747_amd import binding as rb
     reqs = _serving_requests(3, 5)
     res, stats = rb.serve(reqs, hbm_budget=1 << 20, max_slots=2)
-    assert stats["rejected"] == 3 and stats["served"] == 0
+    assert stats["rejected"] == 3 and stats["served"] == 0 and stats["ok"] == 0
     assert all(r["info"]["status"] == rr.RR_ENOMEM for r in res)
+
+
+def test_serving_with_torch_allocator():
+    """rr_serve_config.alloc: every request buffer and handle allocation goes through
+    the caller's allocator (PyTorch's caching allocator here); results equal the
+    library-pool run bitwise."""
+    from paper_2509_19747_amd import binding as rb
+    reqs = _serving_requests(4, 9)
+    kw = dict(build=dict(prec="fp32", sketch="gaussian"), solve=dict(tol=1e-6, certify=False))
+    ta = rb.TorchAllocator()
+    a, sa = rb.serve(reqs, max_slots=2, graph_iters=8, allocator=ta, **kw)
+    p, sp = rb.serve(reqs, max_slots=2, graph_iters=8, **kw)
+    assert sa["status"] == rr.RR_OK and sa["ok"] == len(reqs) and sa["graph_fallbacks"] == 0
+    assert not ta.live   # every block handed out was given back
+    for x, y in zip(a, p):
+        assert np.array_equal(x["X"], y["X"])
+
+
+def test_concurrent_solves_on_one_handle():
+    """Solves on one handle from several threads and streams at once use their own
+    workspaces and give the same result as a solve alone."""
+    import threading
+    prob = workloads.cfg_small_dense(n=900, d=8, l=40)
+    kop = rr.kernel_operator(rr.OP_RBF, _cuda(prob.pts), prob.kconst, prob.scale)
+    P = rr.build_precond(rr.dense_operator(rr.kernel_to_dense(kop, "fp64")), prob.mus, l=prob.l,
+                         seed=prob.omega_seed)
+    b = _cuda(prob.b)
+    x0, i0 = P.solve(b, tol=1e-10)
+    torch.cuda.synchronize()
+    out = [None] * 4
+    def run(k):
+        s = torch.cuda.Stream()
+        with torch.cuda.stream(s):
+            x, info = P.solve(b, tol=1e-10, stream=s, use_graph=(k % 2 == 1))
+            s.synchronize()
+            out[k] = (x, info)
+    ts = [threading.Thread(target=run, args=(k,)) for k in range(4)]
+    for t in ts:
+        t.start()
+    for t in ts:
+        t.join()
+    for x, info in out:
+        assert info["rc"] == rr.RR_OK and info["iters"] == i0["iters"]
+        assert torch.equal(x, x0)
