@@ -52,24 +52,43 @@ def _traffic(kernel: str, src_hash: str):
     return t.get("bytes_per_launch")
 
 
-def cpu_baseline(prob, iters_hint: int, restarts_hint: int, power_iters: int):
-    """Time the float64 oracle on a bounded sample of the same workload and scale to solves/s.
+def cpu_baseline(prob, iters_hint: int, restarts_hint: int, power_iters: int, full: bool = False):
+    """Time the float64 oracle on the host cores and express it in solves/s.
 
-    Sample: one full float64 kernel matvec (row-blocked, all host cores), the
-    oracle sketch on the first 2,000 of the n rows (scaled by n/2000), and the
-    oracle's sketched Cholesky QR on an n x l matrix.  The full-solve estimate is
-    T_sketch + T_orth + (2*N_pow + iters + restarts + 2) * T_matvec, with the
-    iteration count of the same algorithm measured on the GPU in this run.
+    full=False (default, about 20 s): a bounded sample of the same solve.  One full
+    float64 kernel matvec (row-blocked, all host cores), the oracle sketch on the
+    first 2,000 of the n rows (scaled by n/2000), and the oracle's sketched Cholesky
+    QR on an n x l matrix; the solve is then T_sketch + T_orth +
+    (2 N_pow + iters + restarts + 2) T_matvec with the iteration count of the same
+    algorithm measured on the GPU in this run.
+    full=True: the oracle's whole C-RandRAND build and PCG solve with restarts,
+    timed end to end (about 1.5 minutes on 16 cores).
     """
     import numpy as np
 
     from oracle import randrand as orr
     from oracle import rng as orng
+    from oracle import solvers as osol
     from oracle.operators import Operator, kernel_block
 
     cores = os.cpu_count() or 1
     op = Operator.from_problem(prob, threads=cores)
-    n, l = prob.n, prob.l
+    n, l, mu = prob.n, prob.l, prob.mus[0]
+    if full:
+        t0 = time.perf_counter()
+        Pr = orr.build(op, [mu], l, "srht", prob.omega_seed, omega_bf16=True,
+                       power_iters=power_iters)[0]
+        t_build = time.perf_counter() - t0
+        res = osol.pcg(op.shifted(mu), Pr.apply, prob.b, prob.tol)
+        t_all = time.perf_counter() - t0
+        return {
+            "value": 1.0 / t_all, "unit": "solves/s", "cores": cores, "kind": "oracle",
+            "sample": (f"the whole float64 oracle solve, timed: build {t_build:.1f} s (sketch, "
+                       f"sketched Cholesky QR, core, {power_iters}+{power_iters} power steps), PCG "
+                       f"{t_all - t_build:.1f} s ({res.iters} iterations, {res.restarts} restarts, "
+                       f"relres {res.relres:.2e})"),
+            "s_per_solve": t_all,
+        }
     u = np.random.default_rng(0).standard_normal(n)
     t0 = time.perf_counter()
     op.matmat(u)
@@ -78,7 +97,7 @@ def cpu_baseline(prob, iters_hint: int, restarts_hint: int, power_iters: int):
     rows = 2000
     t0 = time.perf_counter()
     Kb = kernel_block(op.kind, op.kconst, op.X[:rows], op.X)
-    Yb = op.scale * (Kb @ Om) + prob.mus[0] * Om[:rows]
+    Yb = op.scale * (Kb @ Om) + mu * Om[:rows]
     t_sk = (time.perf_counter() - t0) * (n / rows)
     del Kb, Yb
     Y = np.random.default_rng(1).standard_normal((n, l))
@@ -105,6 +124,8 @@ def main():
     ap.add_argument("--n", type=int, default=50_000)
     ap.add_argument("--l", type=int, default=500)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-full", action="store_true",
+                    help="time the whole float64 oracle solve instead of the bounded sample")
     ap.add_argument("--no-cg", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="kernel-ridge: first copy 1 GiB device to device (a plain copy of known "
@@ -176,13 +197,27 @@ def main():
     t_total = time.perf_counter() - t0
     kmv_n, kmv_ms = rb.profile_read(rb.PROF_KERNEL_MATVEC)
     sk_n, sk_ms = rb.profile_read(rb.PROF_KERNEL_SKETCH)
+    k64_n, k64_ms = rb.profile_read(rb.PROF_KERNEL_MATVEC64)
     rb.profile_enable(False)
     ms_step = 1e3 * t_total / args.steps
     last = infos[-1]
 
     # accuracy of the last result against the float64 operator (outside the timed region)
     r64 = b - rr.apply_operator(kop, mu, "fp64", x)
-    relres_fp64 = float(torch.linalg.norm(r64) / torch.linalg.norm(b))
+    nb = float(torch.linalg.norm(b))
+    relres_fp64 = float(torch.linalg.norm(r64)) / nb
+    # per-result error bound for the float32-class working operator: ||dA|| by power
+    # iteration on A_fp32 - A (once, outside the timed region)
+    dA = rb.operator_delta_norm(kop, "fp32", iters=20)
+
+    def bounds(xv, relres64):
+        # relres64: the final float64 residual (refinement takes it with the float64
+        # operator).  Forward error <= ||r|| / lambda_min(A_mu) with lambda_min >= mu;
+        # without refinement the float64 residual would only be bounded by
+        # tol + ||dA|| ||x|| / ||b|| (both reported).
+        nx = float(torch.linalg.norm(xv))
+        return {"fwd_err_bound": relres64 * nb / mu / nx,
+                "relres_fp64_bound_without_refinement": prob.tol + dA * nx / nb}
 
     cg = None
     if not args.no_cg:
@@ -200,29 +235,35 @@ def main():
         r0 = b - rr.apply_operator(kop, mu, "fp64", x0)
         cg = {"ms": 1e3 * t_cg, "iters": i0["iters"], "restarts": i0["restarts"],
               "relres_work": i0["relres_work"],
-              "relres_fp64": float(torch.linalg.norm(r0) / torch.linalg.norm(b))}
+              "relres_fp64": float(torch.linalg.norm(r0) / torch.linalg.norm(b)),
+              **bounds(x0, i0["relres_fp64"])}
 
     # roofline of the dominant kernel (by device time inside the timed steps).  The
-    # symmetric kernel matvec evaluates the n(n+1)/2 distinct entries once each.  The
-    # pair terms (the exponents) come from bf16 MFMA (7 v_mfma_f32_32x32x16_bf16 per
-    # 32 x 32 tile at d = 16, 224 flops per pair), which runs beside the vector ALU;
-    # the vector ALU then needs at least 5 issue slots per pair: exp2 (half rate, 2
-    # slots), the float64 widening and two float64 FMAs (row and column sums).  The
-    # roofline is the vector-ALU lane-op rate / 5 pairs per second (the MFMA side
-    # would allow about 11 Tpair/s, so the vector ALU binds).
+    # symmetric kernel matvec evaluates the n(n+1)/2 distinct pairs once each; the
+    # algorithmic work per pair is 2d flops for the distance, one for the scale and
+    # two for the row and column accumulations (2d + 3 = 35 at d = 16, plus one
+    # exponential), so a launch does (2d + 3) n(n+1)/2 flops, priced against the
+    # float32 vector rate (157.3 TFLOP/s): bound "alu".  The kernel's own issue-slot
+    # model (5 vector-ALU slots per pair once the exponents come from bf16 MFMA) is
+    # reported beside it.
     pairs = n * (n + 1) / 2.0
     kmv_avg = kmv_ms / max(kmv_n, 1)
     sk_avg = sk_ms / max(sk_n, 1)
     h = _src_hash("kernels_ksym_mma.hip", "kmma.hpp", "kentry.hpp", "common.hpp")
+    flops_per_launch = (2 * d + 3) * pairs
     if kmv_ms >= sk_ms:
-        peak = PEAK_LANE_OPS / 5 / 1e9
-        ach = pairs / (kmv_avg * 1e-3) / 1e9
+        ach = flops_per_launch / (kmv_avg * 1e-3) / 1e12
+        slot_ach = pairs / (kmv_avg * 1e-3) / 1e9
+        slot_peak = PEAK_LANE_OPS / 5 / 1e9
         roof = {"kernel": "k_ksym_mma (symmetric kernel matvec, bf16-MFMA pair terms)",
-                "bound": "alu", "achieved": ach, "peak": peak, "unit": "Gpair/s",
-                "frac": ach / peak, "traffic": _traffic("k_ksym_mma", h), "avg_ms": kmv_avg,
-                "launches": kmv_n,
-                "per_unit": "5 VALU slots per distinct pair (exp2 at half rate, float64 widening, "
-                            "two float64 FMAs), n(n+1)/2 pairs per launch"}
+                "bound": "alu", "achieved": ach, "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
+                "frac": ach / PEAK_FP32_MFMA_TFLOPS, "traffic": _traffic("k_ksym_mma", h),
+                "avg_ms": kmv_avg, "launches": kmv_n,
+                "per_unit": f"(2d+3) = {2 * d + 3} flops per distinct pair, n(n+1)/2 pairs per launch",
+                "slot_model": {"achieved": slot_ach, "peak": slot_peak, "unit": "Gpair/s",
+                               "frac": slot_ach / slot_peak,
+                               "per_unit": "5 vector-ALU issue slots per pair (exp2 at half rate, "
+                                           "float64 widening, two float64 FMAs)"}}
     else:
         flops = 2.0 * n * n * l
         ach = flops / (sk_avg * 1e-3) / 1e12
@@ -230,6 +271,7 @@ def main():
                 "peak": PEAK_BF16_TFLOPS / 2, "unit": "TFLOP/s", "frac": ach / (PEAK_BF16_TFLOPS / 2),
                 "traffic": None, "avg_ms": sk_avg, "launches": sk_n,
                 "per_unit": "2 n^2 l flops, run as two bf16 passes (hi, lo)"}
+    k64_avg = k64_ms / max(k64_n, 1) if k64_n else None
     sketch_tflops = (2.0 * n * n * l) / (sk_avg * 1e-3) / 1e12 if sk_n else None
     kmv_gpairs = pairs / (kmv_avg * 1e-3) / 1e9 if kmv_n else None
 
@@ -264,7 +306,7 @@ def main():
 
     cpu = None
     if not args.no_cpu:
-        cpu = cpu_baseline(prob, last["iters"], last["restarts"], 10)
+        cpu = cpu_baseline(prob, last["iters"], last["restarts"], 10, full=args.cpu_full)
 
     out = {
         "metric": "time-to-rel-residual 1e-6 and solves/s vs plain CG, same GPU; HBM GB/s",
@@ -278,7 +320,7 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32-class kernel entries (bf16x3 MFMA pair terms), f64 accumulation/dots/"
-                 "projections; bf16 (hi+lo) MFMA sketch",
+                 "projections; bf16 (hi+lo) MFMA sketch; f64 kernel at restarts (refinement)",
         "data": "synthetic",
         "config": {"workload": "kernel-ridge RBF, n=50000, d=16, 10-component mixture, "
                                "median bandwidth, A=K/n, mu=1e-4, SRHT l=500, tol 1e-6",
@@ -288,6 +330,9 @@ def main():
         "build_ms": last["ms_build"], "solve_ms": last["ms_solve"],
         "pcg_iters": last["iters"], "pcg_restarts": last["restarts"],
         "relres_work": last["relres_work"], "relres_fp64": relres_fp64,
+        "relres_fp64_library": last["relres_fp64"], **bounds(x, last["relres_fp64"]),
+        "delta_A_norm": dA, "fp64_refinement": True,
+        "kernel_matvec_fp64_avg_ms": k64_avg, "kernel_matvec_fp64_launches": k64_n,
         "tau": last["tau"], "normE": last["normE"], "lamhat": last["lamhat"],
         "orth_err": last["orth_err"],
         "plain_cg": cg,

@@ -82,12 +82,16 @@ typedef enum { RR_ORTH_SKETCHED_CHOLQR = 0, RR_ORTH_CHOLQR = 1 } rr_orth;
 /*
  * Working precision.
  *  FP64:  everything float64.
- *  FP32:  matvec in float32 (float32 copy of a dense A, or float32 kernel
- *         entries) with float64 accumulation; float32 MFMA sketch; Q, Gram,
- *         Cholesky, dots and vectors float64.
- *  MIXED: as FP32 but a dense sketch runs bf16 x bf16 -> float32 on MFMA, and the
- *         residual at every restart is taken with the float64 operator
- *         (outer float64 iterative refinement).
+ *  FP32:  matvec with float32-class entries and float64 accumulation (a float32
+ *         copy of a dense A; kernel entries whose exponents are float32-accurate
+ *         record products on bf16 MFMA, each term split into three bf16 pieces);
+ *         sketch: kernel operators on bf16 MFMA with each kernel entry split into
+ *         bf16 hi + lo (about 16 significant bits) and Omega drawn in bf16, dense
+ *         operators on float64 MFMA from the float32 copy; Q, Gram, Cholesky, dots
+ *         and vectors float64.
+ *  MIXED: as FP32 but a dense sketch runs bf16 x bf16 -> float32 on MFMA.
+ *  In FP32 and MIXED the residual at every restart is taken with the float64
+ *  operator by default (outer float64 iterative refinement, rr_solve_opts.fp64_ir).
  */
 typedef enum { RR_PREC_FP64 = 0, RR_PREC_FP32 = 1, RR_PREC_MIXED = 2 } rr_precision;
 /*
@@ -117,13 +121,16 @@ typedef struct {
     double restart_eta;   /* restart after each residual drop by this factor (1e-2)      */
     int32_t maxit;        /* maximum PCG iterations (default 5000)                       */
     int32_t check_every;  /* iterations per device launch batch between host checks (8)  */
-    int32_t fp64_ir;      /* 1: residual at restarts with the float64 operator; -1: by
-                             precision (on for MIXED); 0: off                            */
+    int32_t fp64_ir;      /* 1: residual at restarts with the float64 operator (outer
+                             float64 refinement); -1: by precision (on unless the handle
+                             works in FP64); 0: off                                      */
     double* relres_history;  /* optional host array: relative residual per iteration     */
     int32_t history_cap;     /* its length                                               */
     int32_t use_graph;    /* 1: replay each batch of iterations as a captured hipGraph   */
-    int32_t certify;      /* 1: after convergence, one float64-operator residual fills
-                             info.relres_fp64 (not counted in ms_solve); 0: skip        */
+    int32_t certify;      /* 1: when refinement is off, one float64-operator residual
+                             after convergence fills info.relres_fp64 (not counted in
+                             ms_solve); with refinement on, or in FP64, the final true
+                             residual is already the float64 one; 0: skip             */
 } rr_solve_opts;
 
 typedef struct {
@@ -298,6 +305,19 @@ rr_status rr_apply_operator(const rr_operator* A, double mu, int32_t prec, const
                             double* y, void* hip_stream);
 
 /*
+ * Estimate of ||A_work - A||_2, the distance between the working operator of
+ * precision prec (float32 entries / the float32 copy of a dense A) and the float64
+ * operator: `iters` power-iteration steps on the difference (each step one product
+ * with each operator), start vector from Gaussian stream `seed`.  It enters the
+ * per-result error bound for the non-float64 modes: if ||b - A_work x|| <= tol ||b||
+ * then ||b - A_mu x|| <= tol ||b|| + ||dA|| ||x|| and
+ * ||x - x*|| <= (tol ||b|| + ||dA|| ||x||) / lambda_min(A_mu), lambda_min(A_mu) >= mu.
+ * *out_host = 0 for prec = FP64.  Errors: RR_EINVAL, RR_ENOMEM, RR_EDEVICE.
+ */
+rr_status rr_operator_delta_norm(const rr_operator* A, int32_t prec, int32_t iters, uint64_t seed,
+                                 double* out_host, void* hip_stream);
+
+/*
  * Y = (A + mu I) U for nr columns at once (U, Y: device float64, n x nr,
  * column-major, leading dimension n; 1 <= nr <= 4096).  Kernel operators form each
  * entry once per group of up to 8 (FP32) or 2 (FP64) columns; in FP32 the entry
@@ -362,7 +382,8 @@ rr_status rr_lambda_max(const double* G, int64_t k, uint64_t seed, double* out_h
  * which the device-side stop flag turns into no-ops).  Slots:
  * 0 = float32 kernel matvec (first stage), 1 = float32 kernel-GEMM sketch,
  * 2 = float32 dense matvec, 3 = bf16 dense sketch, 4 = projections,
- * 5 = float64 kernel matrix-matrix product of the batched solve.
+ * 5 = float64 kernel matrix-matrix product of the batched solve, 6 = float64 kernel
+ * matvec (first stage; restart residuals of the float64 refinement).
  */
 void rr_profile_enable(int32_t on);
 rr_status rr_profile_read(int32_t slot, int64_t* count, double* total_ms);

@@ -132,6 +132,8 @@ def lib():
         L.rr_theta_apply.argtypes = [C.c_uint64, C.c_int64, C.c_int64, P, P, P]
         L.rr_sketch_apply.argtypes = [C.POINTER(rr_operator), C.c_double, C.POINTER(rr_build_opts),
                                       P, P]
+        L.rr_operator_delta_norm.argtypes = [C.POINTER(rr_operator), C.c_int32, C.c_int32, C.c_uint64,
+                                             C.POINTER(C.c_double), P]
         L.rr_cholesky_ladder.argtypes = [P, C.c_int64, P, C.POINTER(C.c_double), P]
         L.rr_lambda_max.argtypes = [P, C.c_int64, C.c_uint64, P, P]
         L.rr_profile_enable.argtypes = [C.c_int32]
@@ -147,7 +149,7 @@ def lib():
         for name in ("rr_build_precond", "rr_solve", "rr_solve_batch", "rr_serve",
                      "rr_precond_export", "rr_precond_export_omega", "rr_precond_shape",
                      "rr_kernel_to_dense", "rr_apply_operator", "rr_apply_operator_block", "rr_random_matrix", "rr_sketch_apply",
-                     "rr_theta_apply", "rr_cholesky_ladder", "rr_lambda_max"):
+                     "rr_theta_apply", "rr_cholesky_ladder", "rr_lambda_max", "rr_operator_delta_norm"):
             getattr(L, name).restype = C.c_int32
         _lib = L
     return _lib
@@ -371,6 +373,14 @@ def apply_operator(op: Operator, mu: float, prec: str, u, stream=None):
     return y
 
 
+def operator_delta_norm(op: Operator, prec: str = "fp32", iters: int = 20, seed: int = 99, stream=None):
+    """||A_work - A||_2 estimate for the working precision `prec` (power iteration)."""
+    out = C.c_double()
+    _check(lib().rr_operator_delta_norm(C.byref(op.struct), _PREC[prec], int(iters), int(seed),
+                                        C.byref(out), _stream(stream)), "rr_operator_delta_norm")
+    return out.value
+
+
 def apply_operator_block(op: Operator, mu: float, prec: str, U, stream=None):
     """Y = (A + mu I) U for a CUDA float64 tensor U (n, nr)."""
     import torch
@@ -426,7 +436,7 @@ def lambda_max(G, seed: int = 0, stream=None):
 
 
 (PROF_KERNEL_MATVEC, PROF_KERNEL_SKETCH, PROF_DENSE_MATVEC, PROF_DENSE_SKETCH, PROF_PROJECT,
- PROF_KERNEL_MATMAT) = range(6)
+ PROF_KERNEL_MATMAT, PROF_KERNEL_MATVEC64) = range(7)
 
 
 def profile_enable(on: bool = True):

@@ -216,6 +216,8 @@ KernelOp kernel_op_of(const rr_precond& P) {
     k.dm = kernel_record_len(P.op.d);
     k.kconst = P.op.kconst;
     k.scale = P.op.scale;
+    k.xd = P.xd.as<double>();
+    k.hd = P.hd.as<double>();
     return k;
 }
 
@@ -228,6 +230,10 @@ void setup_operator(rr_precond& P, hipStream_t st) {
         launch_sqnorms(A.pts, n, A.d, P.sqn.as<float>(), st);
         P.xa.reset(&P.alloc, (size_t)n * dm * sizeof(float));
         launch_point_records(A.pts, n, A.d, dm, P.xa.as<float>(), st);
+        P.xd.reset(&P.alloc, (size_t)n * dm * sizeof(double));
+        P.hd.reset(&P.alloc, (size_t)n * sizeof(double));
+        launch_point_records64(A.pts, n, A.d, dm, kernel_g64(A.kind, A.kconst), P.xd.as<double>(),
+                               P.hd.as<double>(), st);
     } else if (P.opts.prec != RR_PREC_FP64) {
         P.A32.reset(&P.alloc, (size_t)n * n * sizeof(float));
         launch_copy_mat(DT_F64, A.A, A.lda, DT_F32, P.A32.ptr(), n, n, n, st);
@@ -497,6 +503,50 @@ rr_status rr_apply_operator_block(const rr_operator* A, double mu, int32_t prec,
         apply_operator_multi(P, U, nr, mu, Y, part.as<double>(), kws.as<double>(),
                              prec == RR_PREC_FP64, st);
         RR_HIP(hipGetLastError());
+        RR_HIP(hipStreamSynchronize(st));
+        return RR_OK;
+    });
+}
+
+rr_status rr_operator_delta_norm(const rr_operator* A, int32_t prec, int32_t iters, uint64_t seed,
+                                 double* out_host, void* hip_stream) {
+    return guarded([&]() -> rr_status {
+        validate_operator(A);
+        RR_REQUIRE(out_host != nullptr, "out is null");
+        RR_REQUIRE(prec >= 0 && prec <= 2, "unknown precision");
+        RR_REQUIRE(iters >= 1 && iters <= 1000, "iters must be in [1, 1000]");
+        require_device();
+        hipStream_t st = (hipStream_t)hip_stream;
+        rr_precond P;
+        P.op = *A;
+        P.n = A->n;
+        P.opts.prec = prec;
+        P.alloc.st = st;
+        const int64_t n = A->n;
+        if (prec == RR_PREC_FP64) {
+            *out_host = 0.0;   // the working operator is the float64 one
+            return RR_OK;
+        }
+        const size_t ws = is_kernel(*A) ? kernel_matvec_ws_doubles(n, A->d, 1) : 0;
+        DBuf part(&P.alloc, ((size_t)operator_part_count(P) + 1) * sizeof(double));
+        DBuf kws(&P.alloc, (ws + 1) * sizeof(double));
+        DBuf v(&P.alloc, n * sizeof(double)), y1(&P.alloc, n * sizeof(double)), y2(&P.alloc, n * sizeof(double));
+        DBuf vp(&P.alloc, ((size_t)vec_blocks(n) + 1) * sizeof(double)), sc(&P.alloc, 4 * sizeof(double));
+        setup_operator(P, st);
+        launch_gauss_fill(v.ptr(), DT_F64, n, 1, n, seed, st);
+        launch_dot_part(n, v.as<double>(), v.as<double>(), vp.as<double>(), st);
+        launch_normalize(n, v.as<double>(), v.as<double>(), vp.as<double>(), vec_blocks(n), sc.as<double>() + 1, st);
+        for (int it = 0; it < iters; ++it) {
+            apply_operator(P, v.as<double>(), 0.0, y1.as<double>(), part.as<double>(), kws.as<double>(), false,
+                           nullptr, st);
+            apply_operator(P, v.as<double>(), 0.0, y2.as<double>(), part.as<double>(), kws.as<double>(), true,
+                           nullptr, st);
+            launch_axpby_mat(1.0, y1.as<double>(), n, -1.0, y2.as<double>(), n, y1.as<double>(), n, n, 1, st);
+            launch_dot_part(n, y1.as<double>(), y1.as<double>(), vp.as<double>(), st);
+            launch_normalize(n, v.as<double>(), y1.as<double>(), vp.as<double>(), vec_blocks(n), sc.as<double>(), st);
+        }
+        RR_HIP(hipGetLastError());
+        RR_HIP(hipMemcpyAsync(out_host, sc.ptr(), sizeof(double), hipMemcpyDeviceToHost, st));
         RR_HIP(hipStreamSynchronize(st));
         return RR_OK;
     });

@@ -106,6 +106,15 @@ struct Batch {
     // Wout = A_mu Pin for every column (fp64: float64 operator).  Returns the block
     // partials of Pin_j^T Wout_j when the product produced them (nch = 0 otherwise).
     ColParts matmat(const double* Pin, int64_t ldp, double* Wout, bool fp64) {
+        if (kmulti && fp64 && ldp == n) {
+            // a few columns under the float64 operator: the pair-once float64 matvec,
+            // two columns per pass
+            const KernelOp k = kernel_op_of(P);
+            launch_kernel_matvec_multi(k, true, Pin, (int)m, 0.0, Wout, kdot.as<double>(), kws.as<double>(),
+                                       nullptr, st);
+            launch_add_shift_cols(n, m, mucol.as<double>(), Pin, ldp, Wout, n, st);
+            return ColParts{nullptr, 0, 0, 0};
+        }
         if (kmulti && !fp64 && ldp == n) {
             const KernelOp k = kernel_op_of(P);
             const int nblk = kernel_matvec_blocks(n);
@@ -224,7 +233,7 @@ rr_status rr_solve_batch_fused(const rr_precond* Pc, const int32_t* mu_index_per
             RR_REQUIRE(flags[0] == 0, "B or X0 contains NaN or Inf");
             x0_zero = flags[1] == 0;
         }
-        const bool ir = (o->fp64_ir == 1) || (o->fp64_ir == -1 && P.opts.prec == RR_PREC_MIXED);
+        const bool ir = (o->fp64_ir == 1) || (o->fp64_ir == -1 && P.opts.prec != RR_PREC_FP64);
         const std::vector<double> bb = Bt.coldots(B, ldb, B, ldb);
         std::vector<double> nb(m);
         for (int64_t j = 0; j < m; ++j) nb[j] = std::sqrt(bb[j]);
@@ -353,7 +362,10 @@ rr_status rr_solve_batch_fused(const rr_precond* Pc, const int32_t* mu_index_per
         }
         const double t_solve = now_ms() - t0;
         std::vector<double> rel64(m, std::nan(""));
-        if (o->certify) {
+        if (ir || P.opts.prec == RR_PREC_FP64) {
+            // every column's last true residual came from the float64 operator
+            rel64 = relres;
+        } else if (o->certify) {
             Bt.matmat(X, ldx, Bt.T.as<double>(), true);
             launch_bresid(n, m, B, ldb, Bt.T.as<double>(), Bt.T.as<double>(), st);
             const std::vector<double> rr = Bt.coldots(Bt.T.as<double>(), n, Bt.T.as<double>(), n);

@@ -176,6 +176,7 @@ struct rr_precond {
     rr::DBuf A32;         // float32 copy of a dense A (FP32 / MIXED)
     rr::DBuf sqn;         // |x_i|^2 (kernel operators)
     rr::DBuf xa;          // padded point records (kernel operators)
+    rr::DBuf xd, hd;      // float64 point records and -g |x_i|^2 / 2 (kernel operators)
     // basis
     rr::DBuf Omega;       // n x l, dtype omega_dt
     int omega_dt = rr::DT_F64;

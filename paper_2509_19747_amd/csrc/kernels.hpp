@@ -150,7 +150,20 @@ struct KernelOp {
     const float* xa;     // point records: n x dm floats, coordinates then zero padding
     int dm;              // record length kernel_record_len(d) in {4, 8, 16, 32}
     double kconst, scale;
+    const double* xd = nullptr;   // float64 point records: n x dm doubles (coordinates, zeros)
+    const double* hd = nullptr;   // -g |x_i|^2 / 2 in float64 (g of kernel_g64)
 };
+// float64 exponent scale g: an RBF entry is exp2(-g r^2 / 2) with g = 2 kconst log2(e);
+// a Matern-3/2 entry uses g = 1 (the record product is then -r^2 / 2).
+double kernel_g64(int kind, double kconst);
+// xd[i*dm + k] = (double) pts[k*n + i] (k < d, zeros after), hd[i] = -g |x_i|^2 / 2.
+void launch_point_records64(const float* pts, int64_t n, int d, int dm, double g, double* xd, double* hd,
+                            hipStream_t st);
+// Symmetric float64 kernel matvec (entries in float64: record products on the vector
+// ALU, table-driven exp2), nr in {1, 2}; needs op.xd and op.hd.
+size_t kernel_sym64_ws_doubles(int64_t n, int d, int nr);
+void launch_kernel_matvec_sym64(const KernelOp& op, const double* u, int nr, double mu, double* y,
+                                double* dot_part, double* ws, const int32_t* stop, hipStream_t st);
 // Record length (floats) of a d-dimensional point: the next of 4, 8, 16, 32.
 int kernel_record_len(int d);
 // xa[i*dm + k] = pts[k*n + i] for k < d, 0 for d <= k < dm.

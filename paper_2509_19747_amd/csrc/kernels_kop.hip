@@ -49,6 +49,31 @@ __global__ void k_point_records(const float* __restrict__ pts, int64_t n, int d,
         xa[e] = k < d ? pts[(int64_t)k * n + i] : 0.0f;
     }
 }
+__global__ void k_point_records64(const float* __restrict__ pts, int64_t n, int d, int dm, double g,
+                                  double* __restrict__ xd, double* __restrict__ hd) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        double s = 0.0;
+        for (int k = 0; k < dm; ++k) {
+            const double v = k < d ? (double)pts[(int64_t)k * n + i] : 0.0;
+            xd[i * dm + k] = v;
+            s = fma(v, v, s);
+        }
+        hd[i] = -0.5 * g * s;
+    }
+}
+
+double kernel_g64(int kind, double kconst) {
+    return kind == 1 ? 2.0 * kconst * 1.4426950408889634074 : 1.0;
+}
+
+void launch_point_records64(const float* pts, int64_t n, int d, int dm, double g, double* xd, double* hd,
+                            hipStream_t st) {
+    int64_t gr = (n + 255) / 256;
+    if (gr > 65536) gr = 65536;
+    k_point_records64<<<(int)gr, 256, 0, st>>>(pts, n, d, dm, g, xd, hd);
+}
+
 void launch_point_records(const float* pts, int64_t n, int d, int dm, float* xa, hipStream_t st) {
     int64_t g = (n * dm + 255) / 256;
     if (g > 8192) g = 8192;
@@ -184,6 +209,7 @@ size_t kernel_matvec_ws_doubles(int64_t n, int d, int nr) {
     for (int c = 1; c <= 8; c *= 2)
         if (c == 1 || c <= nr) w = std::max(w, kernel_sym_ws_doubles(n, d, c));
     if (kernel_mma_ok(n, d)) w = std::max(w, kernel_mma_ws_doubles(n, std::min(nr, 2)));
+    w = std::max(w, kernel_sym64_ws_doubles(n, d, std::min(nr, 2)));
     return w;
 }
 
@@ -196,7 +222,12 @@ void launch_kernel_matvec_multi(const KernelOp& op, bool fp64, const double* u, 
         const double* uq = u + (int64_t)q0 * op.n;
         double* yq = y + (int64_t)q0 * op.n;
         double* dq = dot_part + (int64_t)q0 * nblk;
-        if (fp64) {
+        if (fp64 && op.xd) {
+            // each unordered pair once, float64 entries
+            const int c = left >= 2 ? 2 : 1;
+            launch_kernel_matvec_sym64(op, uq, c, mu, yq, dq, ws, stop, st);
+            q0 += c;
+        } else if (fp64) {
             const int c = left >= 2 ? 2 : 1;
             const int slices = kmv_stage1_f64(op, uq, c, ws, stop, st);
             k_kmv_finish<<<(unsigned)nblk, 256, 0, st>>>(op.n, slices, c, ws, op.scale, mu, uq, yq, dq,

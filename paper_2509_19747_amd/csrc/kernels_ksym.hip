@@ -335,4 +335,237 @@ void launch_kernel_matvec_sym(const KernelOp& op, const double* u, int nr, doubl
                                                                   op.scale, mu, u, y, dot_part, stop);
 }
 
+// ===================================================================== float64
+// The same pair-once scheme with float64 entries, for the float64 operator (the
+// residual at restarts of the outer float64 refinement, certification, and the
+// float64 working precision).  Points come as float64 records (coordinates, zero
+// padding) and h_i = -g |x_i|^2 / 2; the thread's rows hold g x_i in registers and
+// a column point streams through scalar loads, so an entry's exponent
+//   t_ij = h_i + h_j + sum_k (g x_ik) x_jk = -g r_ij^2 / 2
+// costs dm fused multiply-adds.  The RBF entry is 2^t; the Matern-3/2 entry
+// (g = 1) is (1 + kconst r) 2^(-kconst r log2 e) with r = sqrt(-2 t).
+//
+// 2^t for t <= 0 is table-driven (Tang, ACM TOMS 15(2), 1989): t = m + j/32 + f
+// with |f| <= 1/64, 2^t = 2^m 2^(j/32) exp(f ln 2); the last factor is its Taylor
+// polynomial of degree 6 (truncation below 4e-18 for |f ln 2| <= ln 2 / 64) and
+// 2^(j/32) comes from a 32-entry LDS table.  About 3 ulp in all.
+constexpr double LN2_D = 0.69314718055994530942;
+constexpr double LOG2E_D = 1.44269504088896340736;
+
+RR_DEV double exp2_nonpos(double t, const double* __restrict__ tab) {
+    t = fmax(t, -1100.0);
+    const double kf = rint(t * 32.0);
+    const double f = fma(kf, -0.03125, t);
+    const int k = (int)kf;
+    const int j = k & 31;
+    const int m = k >> 5;   // floor(k / 32)
+    const double z = f * LN2_D;
+    double p = fma(z, 1.0 / 720.0, 1.0 / 120.0);
+    p = fma(z, p, 1.0 / 24.0);
+    p = fma(z, p, 1.0 / 6.0);
+    p = fma(z, p, 0.5);
+    p = fma(z, p, 1.0);
+    p = fma(z, p, 1.0);
+    return ldexp(tab[j] * p, m);
+}
+
+template <int KIND>
+RR_DEV double kentry64(double t, double kconst, const double* __restrict__ tab) {
+    if (KIND == 1) return exp2_nonpos(t, tab);
+    const double kr = kconst * sqrt(fmax(-2.0 * t, 0.0));
+    return (1.0 + kr) * exp2_nonpos(-kr * LOG2E_D, tab);
+}
+
+// Rows per thread and the work split do not depend on the number of columns, so a
+// column goes through the same arithmetic alone and inside a two-column product.
+constexpr int ks64_rows(int DM, int NR) { return (void)NR, DM <= 16 ? 4 : 2; }
+constexpr int ks64_jb(int DM) { return DM <= 4 ? 4 : DM <= 8 ? 2 : 1; }
+constexpr int KS64_CH = 256;
+
+static KsymPlan ksym64_plan(int64_t n, int d, int nr) {
+    KsymPlan p;
+    p.R = ks64_rows(kernel_record_len(d), nr);
+    p.RB = KS_THREADS * p.R;
+    p.nb = (int)((n + p.RB - 1) / p.RB);
+    const int64_t tiles = (int64_t)p.nb * (p.nb + 1) / 2;
+    const int64_t target = 2048;
+    int64_t S = (target + tiles - 1) / tiles;
+    S = std::min<int64_t>(S, std::max(1, p.RB / 64));
+    S = std::max<int64_t>(S, 1);
+    p.S = (int)S;
+    p.CL = (p.RB + p.S - 1) / p.S;
+    p.items = tiles * p.S;
+    return p;
+}
+
+size_t kernel_sym64_ws_doubles(int64_t n, int d, int nr) {
+    const KsymPlan p = ksym64_plan(n, d, nr);
+    return (size_t)p.nb * p.S * nr * (size_t)n;
+}
+
+template <int KIND, int DM, int NR, int R, int JB, bool OFFD>
+RR_DEV void ks64_step(int64_t n, const double* __restrict__ xd, const double* __restrict__ hd, double kconst,
+                      const double* __restrict__ u, int64_t j, int64_t c0, const double (&ai)[R][DM],
+                      const double (&hi)[R], const double (&ui)[R][NR], double (&acc)[R][NR], double* colw,
+                      int lane, const double* __restrict__ tab) {
+    double cp[JB * NR];
+#pragma unroll
+    for (int jb = 0; jb < JB; ++jb) {
+        const int64_t jj = j + jb;
+        const double hj = hd[jj];
+        double uj[NR];
+#pragma unroll
+        for (int q = 0; q < NR; ++q) uj[q] = u[(int64_t)q * n + jj];
+        double t[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) t[r] = hi[r] + hj;
+        const double* xj = xd + jj * DM;
+#pragma unroll
+        for (int k = 0; k < DM; ++k) {
+            const double xjk = xj[k];
+#pragma unroll
+            for (int r = 0; r < R; ++r) t[r] = fma(ai[r][k], xjk, t[r]);
+        }
+        double kv[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) kv[r] = kentry64<KIND>(t[r], kconst, tab);
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int q = 0; q < NR; ++q) acc[r][q] = fma(kv[r], uj[q], acc[r][q]);
+        if (OFFD) {
+#pragma unroll
+            for (int q = 0; q < NR; ++q) {
+                double c = 0.0;
+#pragma unroll
+                for (int r = 0; r < R; ++r) c = fma(kv[r], ui[r][q], c);
+                cp[jb * NR + q] = c;
+            }
+        }
+    }
+    if (OFFD) {
+        wave_sum_to63(cp);
+        if (lane == 63) {
+            const int base = (int)(j - c0) * NR;
+#pragma unroll
+            for (int m = 0; m < JB * NR; ++m) colw[base + m] = cp[m];
+        }
+    }
+}
+
+template <int KIND, int DM, int NR, bool OFFD>
+RR_DEV void ks64_columns(int64_t n, const double* __restrict__ xd, const double* __restrict__ hd, double kconst,
+                         const double* __restrict__ u, double* __restrict__ part, int64_t cb, int64_t ce,
+                         int64_t colslot, const double (&ai)[ks64_rows(DM, NR)][DM], const double (&hi)[ks64_rows(DM, NR)],
+                         const double (&ui)[ks64_rows(DM, NR)][NR], double (&acc)[ks64_rows(DM, NR)][NR],
+                         double (*colw)[KS64_CH * NR], const double* __restrict__ tab) {
+    constexpr int R = ks64_rows(DM, NR);
+    constexpr int JB = ks64_jb(DM);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int64_t c0 = cb; c0 < ce; c0 += KS64_CH) {
+        const int64_t c1 = (c0 + KS64_CH < ce) ? c0 + KS64_CH : ce;
+        int64_t j = c0;
+        for (; j + JB <= c1; j += JB)
+            ks64_step<KIND, DM, NR, R, JB, OFFD>(n, xd, hd, kconst, u, j, c0, ai, hi, ui, acc, colw[wave], lane,
+                                                  tab);
+        for (; j < c1; ++j)
+            ks64_step<KIND, DM, NR, R, 1, OFFD>(n, xd, hd, kconst, u, j, c0, ai, hi, ui, acc, colw[wave], lane,
+                                                 tab);
+        if (OFFD) {
+            __syncthreads();
+            const int64_t jj = c0 + threadIdx.x;
+            if (threadIdx.x < KS64_CH && jj < c1) {
+#pragma unroll
+                for (int q = 0; q < NR; ++q) {
+                    const int e = threadIdx.x * NR + q;
+                    const double v = (colw[0][e] + colw[1][e]) + (colw[2][e] + colw[3][e]);
+                    part[(colslot * NR + q) * n + jj] = v;
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+template <int KIND, int DM, int NR>
+__global__ __launch_bounds__(KS_THREADS) void k_ksym_f64(int64_t n, const double* __restrict__ xd,
+                                                         const double* __restrict__ hd, double g,
+                                                         double kconst, const double* __restrict__ u,
+                                                         double* __restrict__ part, int nb, int S, int CL,
+                                                         const int32_t* __restrict__ stop) {
+    if (stop && *stop) return;
+    constexpr int R = ks64_rows(DM, NR);
+    constexpr int RB = KS_THREADS * R;
+    __shared__ double colw[4][KS64_CH * NR];
+    __shared__ double tab[32];
+    if (threadIdx.x < 32) tab[threadIdx.x] = exp2((double)threadIdx.x / 32.0);
+
+    int64_t t = blockIdx.x / S;
+    const int s = (int)(blockIdx.x - t * S);
+    int bi = 0;
+    while (t >= nb - bi) { t -= nb - bi; ++bi; }
+    const int bj = bi + (int)t;
+    const int64_t row0 = (int64_t)bi * RB;
+    const int64_t cb = (int64_t)bj * RB + (int64_t)s * CL;
+    int64_t ce = cb + CL;
+    if (ce > (int64_t)(bj + 1) * RB) ce = (int64_t)(bj + 1) * RB;
+    if (ce > n) ce = n;
+
+    double ai[R][DM], hi[R], ui[R][NR], acc[R][NR];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t i = row0 + (int64_t)r * KS_THREADS + threadIdx.x;
+        const int64_t ic = i < n ? i : n - 1;
+#pragma unroll
+        for (int k = 0; k < DM; ++k) ai[r][k] = g * xd[ic * DM + k];
+        hi[r] = hd[ic];
+#pragma unroll
+        for (int q = 0; q < NR; ++q) {
+            ui[r][q] = i < n ? u[(int64_t)q * n + i] : 0.0;
+            acc[r][q] = 0.0;
+        }
+    }
+    __syncthreads();   // the exp2 table
+    if (bj != bi)
+        ks64_columns<KIND, DM, NR, true>(n, xd, hd, kconst, u, part, cb, ce, (int64_t)bi * S, ai, hi, ui, acc,
+                                         colw, tab);
+    else
+        ks64_columns<KIND, DM, NR, false>(n, xd, hd, kconst, u, part, cb, ce, 0, ai, hi, ui, acc, colw, tab);
+    const int64_t rslot = (int64_t)bj * S + s;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t i = row0 + (int64_t)r * KS_THREADS + threadIdx.x;
+        if (i < n)
+#pragma unroll
+            for (int q = 0; q < NR; ++q) part[(rslot * NR + q) * n + i] = acc[r][q];
+    }
+}
+
+void launch_kernel_matvec_sym64(const KernelOp& op, const double* u, int nr, double mu, double* y,
+                                double* dot_part, double* ws, const int32_t* stop, hipStream_t st) {
+    const KsymPlan p = ksym64_plan(op.n, op.d, nr);
+    const double g = kernel_g64(op.kind, op.kconst);
+    const unsigned grid = (unsigned)p.items;
+#define K64(K, DD, Q) k_ksym_f64<K, DD, Q><<<grid, KS_THREADS, 0, st>>>(op.n, op.xd, op.hd, g, op.kconst, u, ws, p.nb, p.S, p.CL, stop)
+#define K64D(K, Q)                      \
+    switch (op.dm) {                    \
+        case 4: K64(K, 4, Q); break;    \
+        case 8: K64(K, 8, Q); break;    \
+        case 16: K64(K, 16, Q); break;  \
+        default: K64(K, 32, Q); break;  \
+    }
+    {
+        ProfScope prof(nr == 1 ? PROF_KERNEL_MATVEC64 : -1, st);
+        if (op.kind == 1) {
+            if (nr == 1) { K64D(1, 1) } else { K64D(1, 2) }
+        } else {
+            if (nr == 1) { K64D(2, 1) } else { K64D(2, 2) }
+        }
+    }
+#undef K64D
+#undef K64
+    k_ksym_finish<<<(unsigned)((op.n + 255) / 256), 256, 0, st>>>(op.n, p.RB, p.nb, p.S, nr, ws, op.scale, mu,
+                                                                  u, y, dot_part, stop);
+}
+
 }  // namespace rr

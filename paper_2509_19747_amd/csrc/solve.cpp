@@ -185,7 +185,9 @@ extern "C" rr_status rr_solve(const rr_precond* Pc, int32_t mu_index, const doub
         const PerMu& pm = P.per[mu_index];
         Solver S{P, W, st, pm.mu, P.l > 0 ? pm.Kc.as<double>() : nullptr};
         const int64_t n = P.n;
-        const bool ir = (o.fp64_ir == 1) || (o.fp64_ir == -1 && P.opts.prec == RR_PREC_MIXED);
+        // outer float64 refinement: by default whenever the working operator is not the
+        // float64 one (the residual at every restart then uses the float64 operator)
+        const bool ir = (o.fp64_ir == 1) || (o.fp64_ir == -1 && P.opts.prec != RR_PREC_FP64);
 
         // NaN/Inf scan of b (and x0) before any arithmetic
         // (and whether x0 is zero: then the first residual is b itself, no operator product)
@@ -299,7 +301,10 @@ extern "C" rr_status rr_solve(const rr_precond* Pc, int32_t mu_index, const doub
         inf.relres_work = relres;
         inf.ms_solve = now_ms() - t0;
         inf.relres_fp64 = std::nan("");
-        if (o.certify) {
+        if (ir || P.opts.prec == RR_PREC_FP64) {
+            // the last true residual already came from the float64 operator
+            inf.relres_fp64 = relres;
+        } else if (o.certify) {
             const double rf = std::sqrt(S.true_residual(b, x, true));
             inf.relres_fp64 = rf / nb;
         }
