@@ -318,6 +318,26 @@ rr_status rr_operator_delta_norm(const rr_operator* A, int32_t prec, int32_t ite
                                  double* out_host, void* hip_stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): y = (A + mu I) u exactly as
+ * rr_apply_operator computes it (same kernels, bitwise the same result), with every
+ * buffer beyond u and y (kernel point records, the float32 copy of a dense A in
+ * FP32/MIXED, partial sums) taken from a static device scratch array of
+ * rr_noalloc_scratch_bytes() = 64 MiB that each GPU holds until the process ends.
+ * It calls no allocator and does not synchronise: the work is enqueued on
+ * hip_stream and the caller synchronises.  All calls on one GPU share that array and
+ * it keeps the last call's contents, so calls that overlap on one GPU (on different
+ * streams or threads) race.  Limit: the layout must fit the scratch (kernel
+ * operators up to about n = 32,768 at d <= 16; dense FP32/MIXED up to n of about
+ * 4,000; dense FP64 any n).  Errors: RR_EINVAL (as rr_apply_operator, and for an
+ * operator too large for the scratch, before any device work), RR_EDEVICE.
+ */
+rr_status rr_apply_operator_noalloc(const rr_operator* A, double mu, int32_t prec, const double* u,
+                                    double* y, void* hip_stream);
+/* Size in bytes of the per-GPU scratch array behind rr_apply_operator_noalloc. */
+size_t rr_noalloc_scratch_bytes(void);
+
+/*
  * Y = (A + mu I) U for nr columns at once (U, Y: device float64, n x nr,
  * column-major, leading dimension n; 1 <= nr <= 4096).  Kernel operators form each
  * entry once per group of up to 8 (FP32) or 2 (FP64) columns; in FP32 the entry

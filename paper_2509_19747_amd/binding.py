@@ -132,6 +132,9 @@ def lib():
         L.rr_theta_apply.argtypes = [C.c_uint64, C.c_int64, C.c_int64, P, P, P]
         L.rr_sketch_apply.argtypes = [C.POINTER(rr_operator), C.c_double, C.POINTER(rr_build_opts),
                                       P, P]
+        L.rr_apply_operator_noalloc.argtypes = [C.POINTER(rr_operator), C.c_double, C.c_int32, P, P, P]
+        L.rr_noalloc_scratch_bytes.argtypes = []
+        L.rr_noalloc_scratch_bytes.restype = C.c_size_t
         L.rr_operator_delta_norm.argtypes = [C.POINTER(rr_operator), C.c_int32, C.c_int32, C.c_uint64,
                                              C.POINTER(C.c_double), P]
         L.rr_cholesky_ladder.argtypes = [P, C.c_int64, P, C.POINTER(C.c_double), P]
@@ -149,7 +152,8 @@ def lib():
         for name in ("rr_build_precond", "rr_solve", "rr_solve_batch", "rr_serve",
                      "rr_precond_export", "rr_precond_export_omega", "rr_precond_shape",
                      "rr_kernel_to_dense", "rr_apply_operator", "rr_apply_operator_block", "rr_random_matrix", "rr_sketch_apply",
-                     "rr_theta_apply", "rr_cholesky_ladder", "rr_lambda_max", "rr_operator_delta_norm"):
+                     "rr_theta_apply", "rr_cholesky_ladder", "rr_lambda_max", "rr_operator_delta_norm",
+                     "rr_apply_operator_noalloc"):
             getattr(L, name).restype = C.c_int32
         _lib = L
     return _lib
@@ -370,6 +374,17 @@ def apply_operator(op: Operator, mu: float, prec: str, u, stream=None):
     y = torch.empty_like(u)
     _check(lib().rr_apply_operator(C.byref(op.struct), float(mu), _PREC[prec], _ptr(u), _ptr(y),
                                    _stream(stream)), "rr_apply_operator")
+    return y
+
+
+def apply_operator_noalloc(op: Operator, mu: float, prec: str, u, y=None, stream=None):
+    """y = (A + mu I) u through the no-allocation entry point (asynchronous on the
+    stream; y may be given to keep the call free of any allocation)."""
+    import torch
+    if y is None:
+        y = torch.empty_like(u)
+    _check(lib().rr_apply_operator_noalloc(C.byref(op.struct), float(mu), _PREC[prec], _ptr(u), _ptr(y),
+                                           _stream(stream)), "rr_apply_operator_noalloc")
     return y
 
 

@@ -171,6 +171,9 @@ void launch_point_records(const float* pts, int64_t n, int d, int dm, float* xa,
 int kernel_matvec_blocks(int64_t n);
 // Workspace (doubles) of launch_kernel_matvec(_multi) for up to nr columns.
 size_t kernel_matvec_ws_doubles(int64_t n, int d, int nr);
+// The same for one precision only (fp64: the float64 operator on point records;
+// otherwise the float32-class operator): what launch_kernel_matvec_multi uses then.
+size_t kernel_matvec_ws_doubles_for(int64_t n, int d, int nr, bool fp64);
 void launch_kernel_matvec(const KernelOp& op, bool fp64, const double* u, double mu, double* y,
                           double* dot_part, double* ws, const int32_t* stop, hipStream_t st);
 // nr >= 1 right-hand sides at once: u, y are n x nr (leading dimension n);

@@ -213,6 +213,15 @@ size_t kernel_matvec_ws_doubles(int64_t n, int d, int nr) {
     return w;
 }
 
+size_t kernel_matvec_ws_doubles_for(int64_t n, int d, int nr, bool fp64) {
+    if (fp64) return kernel_sym64_ws_doubles(n, d, std::min(nr, 2));
+    if (kernel_mma_ok(n, d)) return kernel_mma_ws_doubles(n, std::min(nr, 2));
+    size_t w = 0;
+    for (int c = 1; c <= 8; c *= 2)
+        if (c == 1 || c <= nr) w = std::max(w, kernel_sym_ws_doubles(n, d, c));
+    return w;
+}
+
 void launch_kernel_matvec_multi(const KernelOp& op, bool fp64, const double* u, int nr, double mu,
                                 double* y, double* dot_part, double* ws, const int32_t* stop,
                                 hipStream_t st, bool estimate) {
