@@ -105,6 +105,24 @@ typedef enum { RR_PREC_FP64 = 0, RR_PREC_FP32 = 1, RR_PREC_MIXED = 2 } rr_precis
  */
 typedef enum { RR_TAU_OPT = 0, RR_TAU_RHO = 1, RR_TAU_NYS = 2 } rr_tau_rule;
 
+/*
+ * How rr_solve uses the handle (Section 6).
+ *  C:        C-RandRAND preconditioner P = I - Pi + tau Pi A_mu^{-1} Pi inside the
+ *            Krylov method (Algorithm RandRAND_PCG).
+ *  R:        R-RandRAND (Algorithm RandRAND_CG): the Krylov method runs on
+ *            B = (I-Pi) A_mu (I-Pi) + ||E|| Pi (eq. APdef2 with tau = ||E||, eq. cnd_bound,
+ *            rho = 1) and each cycle recovers x with eq. APdef3.
+ *  SPLIT_R:  split R-RandRAND (Algorithm RandRAND_CG_split): the Krylov method runs on
+ *            E y = (I-Pi)(I-Pi) b, E = (I-Pi) A_mu, then x = A_mu^{-1} Pi (b - A_mu y) + y.
+ * Pi = Q T Q^T is the refined projector (eq. accurate_proj) and A_mu^{-1} Pi u =
+ * Omega R^{-1} T Q^T u.  R and SPLIT_R need a single-shift handle with l >= 1 (R also
+ * the ||E|| estimate of the OPT or RHO tau rule).
+ */
+typedef enum { RR_METHOD_C = 0, RR_METHOD_R = 1, RR_METHOD_SPLIT_R = 2 } rr_method;
+/* Krylov method: CG (Hestenes-Stiefel) or MINRES (Paige-Saunders, preconditioned for
+ * method C), both restarted after each residual drop by restart_eta. */
+typedef enum { RR_KRYLOV_CG = 0, RR_KRYLOV_MINRES = 1 } rr_krylov;
+
 typedef struct {
     int64_t l;            /* columns of Omega (sketch size); 0 = plain CG (P = I)       */
     int32_t sketch;       /* rr_sketch                                                   */
@@ -131,10 +149,12 @@ typedef struct {
                              after convergence fills info.relres_fp64 (not counted in
                              ms_solve); with refinement on, or in FP64, the final true
                              residual is already the float64 one; 0: skip             */
+    int32_t method;       /* rr_method (default C); rr_solve_batch runs C only           */
+    int32_t krylov;       /* rr_krylov (default CG); rr_solve_batch runs CG only         */
 } rr_solve_opts;
 
 typedef struct {
-    int32_t iters;        /* PCG iterations                                               */
+    int32_t iters;        /* Krylov iterations (operator products inside the cycles)      */
     int32_t restarts;     /* restarts after the first cycle                               */
     double relres_work;   /* final relative residual with the working operator            */
     double relres_fp64;   /* final relative residual with the float64 operator            */

@@ -31,6 +31,14 @@ struct BState {
     int32_t maxit;
 };
 
+// Device scalar state of one preconditioned MINRES recurrence (kernels_krylov.hip).
+struct MrState {
+    double beta, oldb, alfa, dbar, epsln, phibar, cs, sn, phi, gamma, delta, oldeps, rr, target2;
+    int32_t stop, iters, maxit, k;   // k: steps in the current cycle
+    int32_t hist_cap;
+    double* hist;                    // ||res||^2 per iteration (may be null)
+};
+
 // ----------------------------------------------------------- random matrices
 void launch_gauss_fill(void* out, int dtype, int64_t rows, int64_t cols, int64_t ld,
                        uint64_t seed, hipStream_t st);
@@ -324,5 +332,26 @@ void launch_state_init(CgState* s, const double* rz_part, int rz_count, double t
 // Finite check of a vector: *flag = 1 if any entry is NaN/Inf.
 // *flag = 1 if v holds a NaN or Inf; *nonzero = 1 (when given) if any entry is not 0.
 void launch_nonfinite(int64_t n, const double* v, int32_t* flag, hipStream_t st, int32_t* nonzero = nullptr);
+
+// ------------------------------------------------ general Krylov engine
+void launch_mr_init(const double* part, int count, MrState* s, double target2, int32_t maxit, int32_t iters,
+                    double* hist, int32_t hist_cap, hipStream_t st);
+void launch_mr_v(int64_t n, const double* z, double* v, const MrState* s, hipStream_t st);
+void launch_mr_t(int64_t n, const double* av, const double* r1, const double* v, double* t, const MrState* s,
+                 double* part, hipStream_t st);
+void launch_mr_alfa(const double* part, int count, MrState* s, hipStream_t st);
+void launch_mr_shift(int64_t n, const double* t, double* r1, double* r2, const MrState* s, hipStream_t st);
+void launch_mr_rot(const double* part, int count, MrState* s, hipStream_t st);
+void launch_mr_update(int64_t n, const double* v, const double* av, double* w, double* w2, double* aw,
+                      double* aw2, double* y, double* res, const MrState* s, double* part, hipStream_t st);
+void launch_mr_rr(const double* part, int count, MrState* s, hipStream_t st);
+// dst = src with vec_blocks(n) partials of ||src||^2
+void launch_copy_dot(int64_t n, const double* src, double* dst, double* part, const int32_t* stop, hipStream_t st);
+// vec_blocks(n) partials of a^T b (no-op once *stop is set)
+void launch_dot_part_stop(int64_t n, const double* a, const double* b, double* part, const int32_t* stop,
+                          hipStream_t st);
+// d = K1 c1 + K2 c2 (symmetric k x k cores, c's as chunk partials; k <= 4096)
+void launch_core_apply2(int64_t k, const double* K1, const double* K2, int64_t ldk, const double* c1_part,
+                        const double* c2_part, int nchunks, double* d, const int32_t* stop, hipStream_t st);
 
 }  // namespace rr

@@ -142,8 +142,13 @@ static rr_status validate_solve(const rr_precond* P, const rr_solve_opts& o) {
     RR_REQUIRE(o.check_every >= 1 && o.check_every <= 4096, "check_every must be in [1, 4096]");
     RR_REQUIRE(o.history_cap >= 0, "history_cap must be >= 0");
     RR_REQUIRE(o.history_cap == 0 || o.relres_history != nullptr, "relres_history is null");
+    RR_REQUIRE(o.method >= RR_METHOD_C && o.method <= RR_METHOD_SPLIT_R, "unknown method");
+    RR_REQUIRE(o.krylov == RR_KRYLOV_CG || o.krylov == RR_KRYLOV_MINRES, "unknown Krylov method");
     return RR_OK;
 }
+
+rr_status rr_solve_general(const rr_precond* Pc, int32_t mu_index, const double* b, double* x,
+                           const rr_solve_opts& o, rr_solve_info* info, hipStream_t st);
 
 extern "C" rr_status rr_solve(const rr_precond* Pc, int32_t mu_index, const double* b, double* x,
                               const rr_solve_opts* opts_in, rr_solve_info* info, void* hip_stream) {
@@ -160,6 +165,8 @@ extern "C" rr_status rr_solve(const rr_precond* Pc, int32_t mu_index, const doub
         require_device();
         rr_precond& P = const_cast<rr_precond&>(*Pc);
         hipStream_t st = (hipStream_t)hip_stream;
+        if (o.method != RR_METHOD_C || o.krylov != RR_KRYLOV_CG)
+            return rr_solve_general(Pc, mu_index, b, x, o, info, st);
         // a workspace of this handle's pool (a new one if every pooled one is busy
         // or too small); returned to the pool when the solve ends
         Workspace* wsp = nullptr;
@@ -337,6 +344,8 @@ extern "C" rr_status rr_solve_batch(const rr_precond* P, const int32_t* mu_index
             RR_REQUIRE(mu_index_per_col[j] >= 0 && mu_index_per_col[j] < (int32_t)P->per.size(),
                        "mu index out of range");
         RR_REQUIRE(o.history_cap == 0, "relres_history is not supported for batched solves");
+        RR_REQUIRE(o.method == RR_METHOD_C && o.krylov == RR_KRYLOV_CG,
+                   "batched solves run C-RandRAND PCG (method C, krylov CG)");
         return RR_OK;
     });
     if (v != RR_OK) return v;

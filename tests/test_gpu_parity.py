@@ -842,3 +842,88 @@ def test_concurrent_solves_on_one_handle():
     for x, info in out:
         assert info["rc"] == rr.RR_OK and info["iters"] == i0["iters"]
         assert torch.equal(x, x0)
+
+
+# ------------------------------------------------- R-RandRAND, split, MINRES
+from oracle import variants as ovar  # noqa: E402
+
+
+def _oracle_variant(op, prob, mu, method, krylov, tol, P_or=None, Omega=None, omega_bf16=False,
+                    sketch="gaussian"):
+    Pr = P_or or orr.build(op, [mu], prob.l, sketch, prob.omega_seed, omega_bf16=omega_bf16)[0]
+    amu = op.shifted(mu)
+    if method == "c":
+        return ovar.c_randrand_minres(amu, Pr.apply, prob.b, tol), Pr
+    Om = Omega if Omega is not None else orng.omega(sketch, prob.omega_seed, prob.n, prob.l, bf16=omega_bf16)
+    proj = ovar.Projections(Pr.Q, Pr.T, Pr.R, Om)
+    if method == "r":
+        return ovar.r_randrand(amu, proj, Pr.normE, prob.b, tol, krylov=krylov), Pr
+    return ovar.split_r_randrand(amu, proj, prob.b, tol, krylov=krylov), Pr
+
+
+@pytest.mark.parametrize("method,krylov", [("c", "minres"), ("r", "cg"), ("r", "minres"),
+                                           ("split", "cg"), ("split", "minres")])
+def test_variant_solvers_fp64_match_oracle(dense_small, method, krylov):
+    """Algorithms RandRAND_CG, RandRAND_CG_split and the MINRES branch of RandRAND_PCG
+    in float64 against the oracle: relres within 1e-8 of the oracle's (both <= tol),
+    iteration counts within max(2, 3 %), the first 20 per-iteration residuals entry by
+    entry, and the forward error against the direct solve."""
+    prob, op, kop, A = dense_small
+    mu, tol = prob.mus[0], 1e-10
+    P = rr.build_precond(rr.dense_operator(A), [mu], l=prob.l, seed=prob.omega_seed)
+    h = np.full(600, np.nan)
+    x, info = P.solve(_cuda(prob.b), tol=tol, method=method, krylov=krylov, history=h)
+    x = x.cpu().numpy()
+    ref, _ = _oracle_variant(op, prob, mu, method, krylov, tol)
+    assert ref.status == osol.OK
+    rel = osol.relres(op.shifted(mu), x, prob.b)
+    assert info["rc"] == rr.RR_OK and rel <= tol * 1.0001 and rel <= ref.relres + 1e-8
+    assert abs(info["iters"] - ref.iters) <= max(2, int(0.03 * ref.iters)), (info["iters"], ref.iters)
+    k = min(info["iters"], ref.iters, 20)
+    np.testing.assert_allclose(h[: k + 1], np.array(ref.history)[: k + 1], rtol=1e-6, atol=0)
+    xs = osol.direct(op.dense, mu, prob.b)
+    cond = np.linalg.cond(op.dense + mu * np.eye(prob.n))
+    assert np.linalg.norm(x - xs) / np.linalg.norm(xs) <= 10 * tol * cond
+
+
+def test_variant_solver_graph_equals_eager(dense_small):
+    prob, op, kop, A = dense_small
+    P = rr.build_precond(rr.dense_operator(A), prob.mus, l=prob.l, seed=prob.omega_seed)
+    b = _cuda(prob.b)
+    for method, krylov in (("r", "minres"), ("split", "cg"), ("c", "minres")):
+        x1, i1 = P.solve(b, tol=1e-9, method=method, krylov=krylov, use_graph=False, check_every=4)
+        x2, i2 = P.solve(b, tol=1e-9, method=method, krylov=krylov, use_graph=True, check_every=4)
+        assert torch.equal(x1, x2) and i1["iters"] == i2["iters"] and i2["graph_fallbacks"] == 0
+
+
+@pytest.mark.parametrize("method,krylov", [("c", "minres"), ("r", "cg"), ("split", "minres")])
+def test_variant_solvers_kernel_fp32_with_refinement(method, krylov):
+    """Float32-class kernel operator with float64 refinement: every variant reaches
+    float64 relres <= tol against the oracle operator; iteration counts near the
+    oracle's float64 run of the same algorithm (the R recovery uses the bf16-sketch
+    basis, so its counts may exceed the float64 ones by a few cycles)."""
+    prob = workloads.cfg_kernel_ridge(n=4000, d=16, l=120)
+    mu = prob.mus[0]
+    op = Operator.from_problem(prob)
+    kop = rr.kernel_operator(rr.OP_RBF, _cuda(prob.pts), prob.kconst, prob.scale)
+    P = rr.build_precond(kop, [mu], l=prob.l, sketch="srht", seed=prob.omega_seed, prec="fp32")
+    x, info = P.solve(_cuda(prob.b), tol=prob.tol, method=method, krylov=krylov, maxit=5000)
+    x = x.cpu().numpy()
+    rel = osol.relres(op.shifted(mu), x, prob.b)
+    assert info["rc"] == rr.RR_OK and rel <= prob.tol * 1.0001
+    assert abs(info["relres_fp64"] - rel) <= 1e-6 * rel + 1e-14
+    ref, _ = _oracle_variant(op, prob, mu, method, krylov, prob.tol, omega_bf16=True, sketch="srht")
+    assert ref.status == osol.OK
+    assert info["iters"] <= 1.5 * ref.iters + 5 and info["iters"] >= 0.5 * ref.iters, (info["iters"], ref.iters)
+
+
+def test_variant_solver_rejects_joint_basis_and_nys(dense_small):
+    prob, op, kop, A = dense_small
+    Pj = rr.build_precond(rr.dense_operator(A), [1e-2, 1e-3], l=20, seed=1)
+    with pytest.raises(rr.RRError):
+        Pj.solve(_cuda(prob.b), method="r")
+    Pn = rr.build_precond(rr.dense_operator(A), [1e-3], l=20, seed=1, tau_rule="nys")
+    with pytest.raises(rr.RRError):
+        Pn.solve(_cuda(prob.b), method="r")
+    x, info = Pn.solve(_cuda(prob.b), method="split", tol=1e-8)
+    assert info["rc"] == rr.RR_OK
