@@ -197,22 +197,53 @@ def _tau(rule, mu, rho, Amu, Q, T, G, seed, n, power_iters):
     return tau, normE, lam
 
 
+def _finish(mu, Amu, Q, R, C, T, tau_rule, rho, seed, n, power_iters, Qb=None, Qred=None):
+    """G, tau and the apply core from the basis of one shift (shared tail of build)."""
+    R_om, _ = chol_upper_ladder(0.5 * (C + C.T))
+    H = R_om @ tri_inv_upper(R)
+    G = H.T @ H
+    tau, normE, lam = _tau(tau_rule, mu, rho, Amu, Q, T, G, seed, n, power_iters)
+    K = tau * (T @ G @ T) - T
+    if Qb is None:
+        return Precond(mu, Q, R, G, T, K, tau, normE, lam, Qb=Q, Kc=K)
+    return Precond(mu, Q, R, G, T, K, tau, normE, lam, Qb=Qb, Kc=Qred @ K @ Qred.T,
+                   extras={"Qred": Qred})
+
+
+def test_matrix(op, sketch: str, seed: int, l: int, q: int = 0, omega_bf16: bool = False,
+                Omega: Optional[np.ndarray] = None) -> np.ndarray:
+    """Omega = A^q X (eq. testmatrix; the sketch is then A_mu Omega = A_mu A^q X).
+
+    X is the generator's Gaussian or SRHT matrix (drawn in bf16 when omega_bf16);
+    with q = 1 the product A X is rounded to bf16 as well in that mode, so the bf16
+    MFMA sketch sees Omega exactly."""
+    X = _rng.omega(sketch, seed, op.n, l, bf16=omega_bf16) if Omega is None else Omega
+    if q == 0:
+        return X
+    if q != 1:
+        raise ValueError("q must be 0 or 1")
+    AX = op.matmat(X)
+    return _rng.round_bf16(AX) if omega_bf16 else AX
+
+
 def build(op, mus: List[float], l: int, sketch: str = "gaussian", seed: int = 0,
           orth: int = SKETCHED_CHOLQR, tau_rule: int = OPT, rho: float = 1.0,
           power_iters: int = 10, Omega: Optional[np.ndarray] = None,
-          omega_bf16: bool = False) -> List[Precond]:
+          omega_bf16: bool = False, q: int = 0, multi: str = "joint") -> List[Precond]:
     """Build one C-RandRAND preconditioner per shift (Algorithm RandRAND_PCG steps 1-4).
 
     omega_bf16: the test matrix is drawn in bfloat16 (as the float32-precision
     kernel path and the mixed-precision dense path do); SRHT entries are unchanged.
+    q: power of eq. testmatrix (Omega = A^q X, q in {0, 1}).
+    multi (several shifts): "joint" = the joint basis orth([Omega, A Omega]) with a
+    reduced QR per shift (Section 5.1); "shifted_chol" = the shifted Cholesky
+    technique of Section 5.1 (see build_shifted_cholesky).
     """
     n = op.n
     if l == 0:
         return [Precond(mu, None, None, None, None, None, 1.0, float("nan"), float("nan"))
                 for mu in mus]
-    if Omega is None:
-        Omega = _rng.omega(sketch, seed, n, l, bf16=omega_bf16)
-    out = []
+    Omega = test_matrix(op, sketch, seed, l, q, omega_bf16, Omega)
     if len(mus) == 1:
         mu = mus[0]
         Amu = op.shifted(mu)
@@ -221,12 +252,12 @@ def build(op, mus: List[float], l: int, sketch: str = "gaussian", seed: int = 0,
             Q, R = sketched_cholqr(Y, _rng.theta(seed, n, l))
         else:
             Q, R = cholqr(Y)
-        G = _core(Omega, Y, R)
         T = 2.0 * np.eye(l) - Q.T @ Q
-        tau, normE, lam = _tau(tau_rule, mu, rho, Amu, Q, T, G, seed, n, power_iters)
-        K = tau * (T @ G @ T) - T
-        out.append(Precond(mu, Q, R, G, T, K, tau, normE, lam, Qb=Q, Kc=K))
-        return out
+        return [_finish(mu, Amu, Q, R, Omega.T @ Y, T, tau_rule, rho, seed, n, power_iters)]
+    if multi == "shifted_chol":
+        return build_shifted_cholesky(op, mus, l, Omega, seed, orth, tau_rule, rho, power_iters)
+    if multi != "joint":
+        raise ValueError(multi)
     # several shifts sharing one joint basis (Section 5.1)
     AO = op.matmat(Omega)
     Z = np.concatenate([Omega, AO], axis=1)
@@ -239,17 +270,84 @@ def build(op, mus: List[float], l: int, sketch: str = "gaussian", seed: int = 0,
     OAO = Omega.T @ AO
     OO = Omega.T @ Omega
     QjtQj = Qj.T @ Qj
+    out = []
     for mu in mus:
         Amu = op.shifted(mu)
         Qred, R = householder_qr(Zj + mu * Oj)
         Q = Qj @ Qred
-        C = OAO + mu * OO
-        R_om, _ = chol_upper_ladder(0.5 * (C + C.T))
-        H = R_om @ tri_inv_upper(R)
-        G = H.T @ H
         T = 2.0 * np.eye(l) - Qred.T @ QjtQj @ Qred
-        tau, normE, lam = _tau(tau_rule, mu, rho, Amu, Q, T, G, seed, n, power_iters)
-        K = tau * (T @ G @ T) - T
-        out.append(Precond(mu, Q, R, G, T, K, tau, normE, lam, Qb=Qj,
-                           Kc=Qred @ K @ Qred.T, extras={"Qred": Qred}))
+        out.append(_finish(mu, Amu, Q, R, OAO + mu * OO, T, tau_rule, rho, seed, n, power_iters,
+                           Qb=Qj, Qred=Qred))
     return out
+
+
+def build_shifted_cholesky(op, mus: List[float], l: int, Omega: np.ndarray, seed: int = 0,
+                           orth: int = SKETCHED_CHOLQR, tau_rule: int = OPT, rho: float = 1.0,
+                           power_iters: int = 10, alpha: Optional[float] = None) -> List[Precond]:
+    """Several shifts from one orthogonalisation at a fixed shift alpha (Section 5.1,
+    shifted Cholesky preconditioning).
+
+    A_alpha Omega = Q_alpha R_alpha (Algorithm prec_chol_qr).  With Om_a = Omega R_alpha^{-1},
+    every mu gets R = R_chol R_alpha where R_chol = chol of the preconditioned Gram
+        Om_a^T A_alpha^T A_alpha Om_a + 2 (mu - alpha) Om_a^T A_alpha Om_a + (mu - alpha)^2 Om_a^T Om_a
+    (A_mu = A_alpha + (mu - alpha) I; the last coefficient is (mu - alpha)^2), whose three
+    parts are precomputed once, and the basis Q_mu = A_mu Omega R^{-1}
+    = (Q_alpha + (mu - alpha) Om_a) R_chol^{-1}.  The apply basis is Qb = [Q_alpha, Om_a]
+    (n x 2l) with the per-shift map M_mu = [I; (mu - alpha) I] R_chol^{-1} (2l x l).
+    alpha defaults to the largest shift, so every mu <= alpha as the technique asks.
+    """
+    n = op.n
+    a = max(mus) if alpha is None else float(alpha)
+    AO = op.matmat(Omega)
+    Ya = AO + a * Omega
+    if orth == SKETCHED_CHOLQR:
+        Qa, Ra = sketched_cholqr(Ya, _rng.theta(seed, n, l))
+    else:
+        Qa, Ra = cholqr(Ya)
+    Rai = tri_inv_upper(Ra)
+    Oma = Omega @ Rai
+    W2 = Qa.T @ Qa                       # Om_a^T A_alpha^2 Om_a
+    W1 = Rai.T @ (Omega.T @ Ya) @ Rai    # Om_a^T A_alpha Om_a
+    W0 = Oma.T @ Oma                     # Om_a^T Om_a
+    Qb = np.concatenate([Qa, Oma], axis=1)
+    QbtQb = Qb.T @ Qb
+    OAO = Omega.T @ AO
+    OO = Omega.T @ Omega
+    out = []
+    for mu in mus:
+        s = mu - a
+        Rc, _ = chol_upper_ladder(W2 + 2.0 * s * W1 + s * s * W0)
+        Rci = tri_inv_upper(Rc)
+        M = np.concatenate([Rci, s * Rci], axis=0)
+        R = Rc @ Ra
+        Q = Qb @ M
+        T = 2.0 * np.eye(l) - M.T @ QbtQb @ M
+        out.append(_finish(mu, op.shifted(mu), Q, R, OAO + mu * OO, T, tau_rule, rho, seed, n,
+                           power_iters, Qb=Qb, Qred=M))
+    return out
+
+
+def ad_threshold(n: int, l_max: int, q: int, mu: float, f: float) -> float:
+    """Right-hand side of eq. ad_criterion: f (n / l_max)^(1/(2q+2)) |mu|."""
+    return f * (n / l_max) ** (1.0 / (2 * q + 2)) * abs(mu)
+
+
+def build_adaptive(op, mu: float, l0: int, l_max: int, f: float = 100.0, sketch: str = "gaussian",
+                   seed: int = 0, q: int = 0, growth: int = 2, stagnation: float = 0.9, **kw):
+    """Adaptive sketch size (Section 5.3, eq. ad_criterion): build with l, and while
+    ||E|| = ||(I-Pi) A_mu (I-Pi)|| (the footnote's refinement of ||(I-Pi) A_mu||, the
+    build's power-iteration estimate) is above f (n/l_max)^(1/(2q+2)) |mu|, l < l_max and
+    the last growth cut ||E|| below `stagnation` times its previous value, grow
+    l <- min(growth l, l_max) and build again.  Returns (preconditioner, l, trail of
+    (l, ||E||))."""
+    thr = ad_threshold(op.n, l_max, q, mu, f)
+    l = l0
+    trail = []
+    prev = None
+    while True:
+        P = build(op, [mu], l, sketch, seed, q=q, **kw)[0]
+        trail.append((l, P.normE))
+        if P.normE <= thr or l >= l_max or (prev is not None and P.normE > stagnation * prev):
+            return P, l, trail
+        prev = P.normE
+        l = min(growth * l, l_max)
