@@ -123,6 +123,18 @@ typedef enum { RR_METHOD_C = 0, RR_METHOD_R = 1, RR_METHOD_SPLIT_R = 2 } rr_meth
  * method C), both restarted after each residual drop by restart_eta. */
 typedef enum { RR_KRYLOV_CG = 0, RR_KRYLOV_MINRES = 1 } rr_krylov;
 
+/*
+ * Several shifts in one handle (Section 5.1).
+ *  JOINT:         one joint basis orth([Omega, A Omega]) and a 2l x l Householder QR per
+ *                 shift.
+ *  SHIFTED_CHOL:  one orthogonalisation of A_alpha Omega at alpha = the largest shift,
+ *                 then per shift R = R_chol R_alpha with R_chol = chol of the Gram
+ *                 W2 + 2 (mu - alpha) W1 + (mu - alpha)^2 W0 of A_mu Omega R_alpha^{-1}
+ *                 (shifted Cholesky preconditioning), the basis
+ *                 Q_mu = [Q_alpha, Omega R_alpha^{-1}] [I; (mu - alpha) I] R_chol^{-1}.
+ */
+typedef enum { RR_MULTI_JOINT = 0, RR_MULTI_SHIFTED_CHOL = 1 } rr_multi_shift;
+
 typedef struct {
     int64_t l;            /* columns of Omega (sketch size); 0 = plain CG (P = I)       */
     int32_t sketch;       /* rr_sketch                                                   */
@@ -132,6 +144,14 @@ typedef struct {
     int32_t tau_rule;     /* rr_tau_rule                                                 */
     double rho;           /* RHO rule factor (default 1.0)                               */
     int32_t power_iters;  /* power iterations per estimate (default 10)                  */
+    int32_t power_q;      /* q of eq. testmatrix: Omega = A^q X, q in {0, 1} (default 0) */
+    int32_t multi_shift;  /* rr_multi_shift for n_mu > 1 (default JOINT)                 */
+    int64_t l_max;        /* > l: adaptive sketch size (Section 5.3, eq. ad_criterion):
+                             build with l, l <- min(2 l, l_max) while the ||E|| estimate
+                             exceeds ad_factor (n / l_max)^(1/(2q+2)) mu and the last
+                             doubling cut it below 0.9 of its previous value; single
+                             shift, tau rule OPT or RHO.  0: off (default)               */
+    double ad_factor;     /* f of eq. ad_criterion (default 100)                         */
 } rr_build_opts;
 
 typedef struct {

@@ -47,7 +47,8 @@ class rr_operator(C.Structure):
 class rr_build_opts(C.Structure):
     _fields_ = [("l", C.c_int64), ("sketch", C.c_int32), ("seed", C.c_uint64),
                 ("orth", C.c_int32), ("prec", C.c_int32), ("tau_rule", C.c_int32),
-                ("rho", C.c_double), ("power_iters", C.c_int32)]
+                ("rho", C.c_double), ("power_iters", C.c_int32), ("power_q", C.c_int32),
+                ("multi_shift", C.c_int32), ("l_max", C.c_int64), ("ad_factor", C.c_double)]
 
 
 class rr_solve_opts(C.Structure):
@@ -218,7 +219,7 @@ def kernel_operator(kind: int, pts, kconst: float, scale: float) -> Operator:
 
 
 def build_opts(l=0, sketch="gaussian", seed=0, orth="sketched", prec="fp64", tau_rule="opt",
-               rho=1.0, power_iters=10) -> rr_build_opts:
+               rho=1.0, power_iters=10, q=0, multi="joint", l_max=0, ad_factor=100.0) -> rr_build_opts:
     o = rr_build_opts()
     lib().rr_build_opts_default(C.byref(o))
     o.l = int(l)
@@ -229,6 +230,10 @@ def build_opts(l=0, sketch="gaussian", seed=0, orth="sketched", prec="fp64", tau
     o.tau_rule = _TAU[tau_rule] if isinstance(tau_rule, str) else int(tau_rule)
     o.rho = float(rho)
     o.power_iters = int(power_iters)
+    o.power_q = int(q)
+    o.multi_shift = {"joint": 0, "shifted_chol": 1}[multi] if isinstance(multi, str) else int(multi)
+    o.l_max = int(l_max)
+    o.ad_factor = float(ad_factor)
     return o
 
 

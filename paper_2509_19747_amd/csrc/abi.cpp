@@ -355,6 +355,10 @@ void rr_build_opts_default(rr_build_opts* o) {
     o->tau_rule = RR_TAU_OPT;
     o->rho = 1.0;
     o->power_iters = 10;
+    o->power_q = 0;
+    o->multi_shift = RR_MULTI_JOINT;
+    o->l_max = 0;
+    o->ad_factor = 100.0;
 }
 
 void rr_solve_opts_default(rr_solve_opts* o) {

@@ -179,6 +179,26 @@ struct Builder {
         check_launch();
     }
 
+    // q = 1 (eq. testmatrix): Omega <- A X for the X just drawn, stored the way
+    // make_omega stores a test matrix (bf16-rounded where the sketch reads bf16).
+    void apply_power(const void* A16) {
+        if (P.opts.power_q != 1) return;
+        const int64_t n = P.n, l = P.l;
+        const bool bf16_omega = ob_buf.ptr() != nullptr;
+        const int ydt = bf16_omega ? DT_F32 : DT_F64;
+        DBuf Y0 = mat(n, l, ydt == DT_F32 ? sizeof(float) : sizeof(double));
+        sketch(P.Omega.ptr(), P.omega_dt, 0.0, Y0.ptr(), ydt, A16);
+        srht_dbits.release();   // Omega is no longer the SRHT: the sketch reads it
+        srht_rows.release();
+        if (bf16_omega) {
+            launch_copy_mat(DT_F32, Y0.ptr(), n, DT_BF16, ob_buf.ptr(), ldo, n, l, st);
+            launch_copy_mat(DT_BF16, ob_buf.ptr(), ldo, P.omega_dt, P.Omega.ptr(), n, n, l, st);
+        } else {
+            launch_copy_mat(DT_F64, Y0.ptr(), n, P.omega_dt, P.Omega.ptr(), n, n, l, st);
+        }
+        check_launch();
+    }
+
     // Y = A Omega + mu Omega (the sketch, q = 0).
     void sketch(const void* Om, int odt, double mu, void* Y, int ydt, const void* A16) {
         const int64_t n = P.n, l = P.l;
@@ -450,9 +470,42 @@ extern "C" rr_status rr_build_precond(const rr_operator* A, const double* mus, i
         RR_REQUIRE(o.tau_rule >= RR_TAU_OPT && o.tau_rule <= RR_TAU_NYS, "unknown tau rule");
         RR_REQUIRE(std::isfinite(o.rho) && o.rho > 0.0, "rho must be finite and > 0");
         RR_REQUIRE(o.power_iters >= 1 && o.power_iters <= 10000, "power_iters must be in [1, 10000]");
+        RR_REQUIRE(o.power_q == 0 || o.power_q == 1, "power_q must be 0 or 1");
+        RR_REQUIRE(o.multi_shift == RR_MULTI_JOINT || o.multi_shift == RR_MULTI_SHIFTED_CHOL, "unknown multi_shift");
+        RR_REQUIRE(o.l_max >= 0 && o.l_max <= n, "l_max must be in [0, n]");
+        if (o.l_max > o.l) {
+            RR_REQUIRE(o.l >= 1 && n_mu == 1, "adaptive l needs l >= 1 and a single shift");
+            RR_REQUIRE(o.tau_rule != RR_TAU_NYS, "adaptive l needs the ||E|| estimate (tau rule OPT or RHO)");
+            RR_REQUIRE(std::isfinite(o.ad_factor) && o.ad_factor > 0.0, "ad_factor must be > 0");
+        }
         if (n_mu > 1 && o.l > 0) RR_REQUIRE(2 * o.l <= n, "several shifts need 2l <= n (joint basis)");
         if (alloc) RR_REQUIRE(alloc->alloc && alloc->free, "allocator callbacks are null");
         require_device();
+        if (o.l_max > o.l) {
+            // adaptive sketch size (eq. ad_criterion, with ||E|| for ||(I-Pi) A_mu||)
+            const double t_all = now_ms();
+            const double thr = o.ad_factor * std::pow((double)n / (double)o.l_max, 1.0 / (2.0 * o.power_q + 2.0)) *
+                               std::fabs(mus[0]);
+            rr_build_opts oi = o;
+            oi.l_max = 0;
+            double prev = -1.0;
+            while (true) {
+                rr_precond* h = nullptr;
+                const rr_status s1 = rr_build_precond(A, mus, 1, &oi, alloc, hip_stream, &h);
+                if (s1 != RR_OK) return s1;
+                const double nE = h->per[0].normE;
+                const bool done = nE <= thr || oi.l >= o.l_max || (prev >= 0.0 && nE > 0.9 * prev);
+                if (done) {
+                    h->ms_build = now_ms() - t_all;
+                    h->opts.l_max = o.l_max;
+                    *out = h;
+                    return RR_OK;
+                }
+                prev = nE;
+                rr_precond_destroy(h);
+                oi.l = std::min<int64_t>(2 * oi.l, o.l_max);
+            }
+        }
 
         const double t0 = now_ms();
         hipStream_t st = (hipStream_t)hip_stream;
@@ -494,6 +547,7 @@ extern "C" rr_status rr_build_precond(const rr_operator* A, const double* mus, i
             A16.reset(al, (size_t)n * n * 2);
             launch_copy_mat(DT_F64, A->A, A->lda, DT_BF16, A16.ptr(), n, n, n, st);
         }
+        B.apply_power(A16.ptr());
         const int ydt = ((kernel && f32path) || (!kernel && o.prec == RR_PREC_MIXED)) ? DT_F32 : DT_F64;
         const size_t yes = ydt == DT_F32 ? sizeof(float) : sizeof(double);
         P.Qb.reset(al, (size_t)n * P.kb * sizeof(double));
@@ -571,54 +625,102 @@ extern "C" rr_status rr_build_precond(const rr_operator* A, const double* mus, i
             launch_axpby_mat(pm.tau, TGT.as<double>(), l, -1.0, pm.T.as<double>(), l, pm.Kc.as<double>(), l, l, l, st);
             B.check_launch();
         } else {
-            // joint basis for several shifts (Section 5.1)
-            DBuf Y0 = B.mat(n, l, yes);
-            B.sketch(P.Omega.ptr(), P.omega_dt, 0.0, Y0.ptr(), ydt, A16.ptr());
-            A16.release();
+            // several shifts (Section 5.1): the apply basis Qb (n x 2l) and, per shift,
+            // Qred (2l x l) with Q_mu = Qb Qred and R with A_mu Omega = Q_mu R.
+            // JOINT: Qb = orth([Omega, A Omega]); Qred, R = qr(Qb^T A Omega + mu Qb^T Omega).
+            // SHIFTED_CHOL: A_alpha Omega = Q_a R_a at alpha = max mu, Qb = [Q_a, Omega R_a^{-1}],
+            // R_chol = chol(W2 + 2 (mu - alpha) W1 + (mu - alpha)^2 W0), Qred = [I; (mu - alpha) I]
+            // R_chol^{-1}, R = R_chol R_a.
             const int64_t k2 = 2 * l;
-            DBuf Z = B.mat(n, k2);
-            launch_copy_mat(P.omega_dt, P.Omega.ptr(), n, DT_F64, Z.ptr(), n, n, l, st);
-            launch_copy_mat(ydt, Y0.ptr(), n, DT_F64, Z.as<double>() + (size_t)n * l, n, n, l, st);
-            DBuf Rj = B.mat(k2, k2);
-            B.orth(Z.ptr(), DT_F64, k2, o.seed + 1, P.Qb.as<double>(), Rj.as<double>());
-            Z.release();
-            const double* Qj = P.Qb.as<double>();
-            DBuf Zj = B.mat(k2, l), Oj = B.mat(k2, l), OAO = B.mat(l, l), OO = B.mat(l, l), QQ = B.mat(k2, k2);
-            B.gemm(DT_F64, true, ydt, false, k2, l, n, Qj, n, Y0.ptr(), n, Zj.as<double>(), k2);
-            B.gemm(DT_F64, true, P.omega_dt, false, k2, l, n, Qj, n, P.Omega.ptr(), n, Oj.as<double>(), k2);
+            const bool shifted = o.multi_shift == RR_MULTI_SHIFTED_CHOL;
+            double alpha = 0.0;
+            for (int im = 0; im < n_mu; ++im) alpha = std::max(alpha, P.per[im].mu);
+            DBuf Y0 = B.mat(n, l, yes);
+            B.sketch(P.Omega.ptr(), P.omega_dt, shifted ? alpha : 0.0, Y0.ptr(), ydt, A16.ptr());
+            A16.release();
+            double* Qj = P.Qb.as<double>();
+            DBuf Zj, Oj, OAO = B.mat(l, l), OO = B.mat(l, l), QQ = B.mat(k2, k2);
+            DBuf Ra, W2, W1, W0;
             B.gemm(P.omega_dt, true, ydt, false, l, l, n, P.Omega.ptr(), n, Y0.ptr(), n, OAO.as<double>(), l);
             B.gemm(P.omega_dt, true, P.omega_dt, false, l, l, n, P.Omega.ptr(), n, P.Omega.ptr(), n, OO.as<double>(), l);
-            B.gram(k2, n, Qj, n, QQ.as<double>(), k2);
+            if (!shifted) {
+                DBuf Z = B.mat(n, k2);
+                launch_copy_mat(P.omega_dt, P.Omega.ptr(), n, DT_F64, Z.ptr(), n, n, l, st);
+                launch_copy_mat(ydt, Y0.ptr(), n, DT_F64, Z.as<double>() + (size_t)n * l, n, n, l, st);
+                DBuf Rj = B.mat(k2, k2);
+                B.orth(Z.ptr(), DT_F64, k2, o.seed + 1, Qj, Rj.as<double>());
+                Z.release();
+                Zj = B.mat(k2, l);
+                Oj = B.mat(k2, l);
+                B.gemm(DT_F64, true, ydt, false, k2, l, n, Qj, n, Y0.ptr(), n, Zj.as<double>(), k2);
+                B.gemm(DT_F64, true, P.omega_dt, false, k2, l, n, Qj, n, P.Omega.ptr(), n, Oj.as<double>(), k2);
+                B.gram(k2, n, Qj, n, QQ.as<double>(), k2);
+                B.orth_error(QQ.as<double>(), k2);
+            } else {
+                Ra = B.mat(l, l);
+                B.orth(Y0.ptr(), ydt, l, o.seed + 1, Qj, Ra.as<double>());
+                DBuf Rai = B.mat(l, l), tmp = B.mat(l, l);
+                launch_tri_inv_upper(Ra.as<double>(), l, l, Rai.as<double>(), l, st);
+                double* Oma = Qj + (size_t)n * l;
+                B.gemm(P.omega_dt, false, DT_F64, false, n, l, l, P.Omega.ptr(), n, Rai.ptr(), l, Oma, n);
+                B.gram(k2, n, Qj, n, QQ.as<double>(), k2);
+                W2 = B.mat(l, l);
+                W0 = B.mat(l, l);
+                W1 = B.mat(l, l);
+                launch_copy_mat(DT_F64, QQ.ptr(), k2, DT_F64, W2.ptr(), l, l, l, st);
+                launch_copy_mat(DT_F64, QQ.as<double>() + (size_t)l * k2 + l, k2, DT_F64, W0.ptr(), l, l, l, st);
+                // W1 = R_a^{-T} (Omega^T A_alpha Omega) R_a^{-1}; OAO holds Omega^T A_alpha Omega here
+                B.gemm(DT_F64, true, DT_F64, false, l, l, l, Rai.ptr(), l, OAO.ptr(), l, tmp.as<double>(), l);
+                B.gemm(DT_F64, false, DT_F64, false, l, l, l, tmp.ptr(), l, Rai.ptr(), l, W1.as<double>(), l);
+                launch_symmetrize(W1.as<double>(), l, l, st);
+                // OAO <- Omega^T A Omega = Omega^T A_alpha Omega - alpha Omega^T Omega
+                launch_axpby_mat(1.0, OAO.as<double>(), l, -alpha, OO.as<double>(), l, OAO.as<double>(), l, l, l, st);
+            }
             Y0.release();
-            B.orth_error(QQ.as<double>(), k2);
             const size_t hwd = std::max<size_t>((size_t)k2 * l + l + 16, householder_ws_doubles(k2, l));
             DBuf hws(al, hwd * sizeof(double));
             for (int im = 0; im < n_mu; ++im) {
                 PerMu& pm = P.per[im];
                 const double mu = pm.mu;
-                DBuf Mred = B.mat(k2, l);
-                launch_axpby_mat(1.0, Zj.as<double>(), k2, mu, Oj.as<double>(), k2, Mred.as<double>(), k2, k2, l, st);
                 pm.Qred.reset(al, (size_t)k2 * l * sizeof(double));
                 pm.R.reset(al, (size_t)l * l * sizeof(double));
-                launch_householder_qr(Mred.as<double>(), k2, l, k2, pm.Qred.as<double>(), k2, pm.R.as<double>(), l,
-                                      hws.as<double>(), hwd, st);
+                if (!shifted) {
+                    DBuf Mred = B.mat(k2, l);
+                    launch_axpby_mat(1.0, Zj.as<double>(), k2, mu, Oj.as<double>(), k2, Mred.as<double>(), k2, k2, l, st);
+                    launch_householder_qr(Mred.as<double>(), k2, l, k2, pm.Qred.as<double>(), k2, pm.R.as<double>(), l,
+                                          hws.as<double>(), hwd, st);
+                } else {
+                    const double sft = mu - alpha;
+                    DBuf Wm = B.mat(l, l), Rci = B.mat(l, l);
+                    launch_axpby_mat(1.0, W2.as<double>(), l, 2.0 * sft, W1.as<double>(), l, Wm.as<double>(), l, l, l, st);
+                    launch_axpby_mat(1.0, Wm.as<double>(), l, sft * sft, W0.as<double>(), l, Wm.as<double>(), l, l, l, st);
+                    launch_symmetrize(Wm.as<double>(), l, l, st);
+                    B.chol_ladder(Wm.as<double>(), l);   // Wm <- R_chol
+                    launch_tri_inv_upper(Wm.as<double>(), l, l, Rci.as<double>(), l, st);
+                    launch_copy_mat(DT_F64, Rci.ptr(), l, DT_F64, pm.Qred.ptr(), k2, l, l, st);
+                    launch_axpby_mat(sft, Rci.as<double>(), l, 0.0, Rci.as<double>(), l, pm.Qred.as<double>() + l, k2,
+                                     l, l, st);
+                    B.gemm(DT_F64, false, DT_F64, false, l, l, l, Wm.ptr(), l, Ra.ptr(), l, pm.R.as<double>(), l);
+                    launch_zero_lower(pm.R.as<double>(), l, l, st);
+                }
                 B.check_launch();
                 DBuf C = B.mat(l, l);
                 launch_axpby_mat(1.0, OAO.as<double>(), l, mu, OO.as<double>(), l, C.as<double>(), l, l, l, st);
                 pm.G.reset(al, (size_t)l * l * sizeof(double));
                 B.core_G(C.as<double>(), pm.R.as<double>(), pm.G.as<double>(), l);
-                // T = 2I - Qred^T (Qj^T Qj) Qred
+                // T = 2I - Qred^T (Qb^T Qb) Qred
                 DBuf tmp = B.mat(k2, l);
                 B.gemm(DT_F64, false, DT_F64, false, k2, l, k2, QQ.ptr(), k2, pm.Qred.ptr(), k2, tmp.as<double>(), k2);
                 pm.T.reset(al, (size_t)l * l * sizeof(double));
                 B.gemm(DT_F64, true, DT_F64, false, l, l, k2, pm.Qred.ptr(), k2, tmp.ptr(), k2, pm.T.as<double>(), l);
                 launch_symmetrize(pm.T.as<double>(), l, l, st);
+                if (shifted) B.orth_error(pm.T.as<double>(), l);   // Q_mu^T Q_mu against I
                 launch_two_minus(pm.T.as<double>(), l, l, st);
                 DBuf TG = B.mat(l, l), TGT = B.mat(l, l);
                 B.gemm(DT_F64, false, DT_F64, false, l, l, l, pm.T.ptr(), l, pm.G.ptr(), l, TG.as<double>(), l);
                 B.gemm(DT_F64, false, DT_F64, false, l, l, l, TG.ptr(), l, pm.T.ptr(), l, TGT.as<double>(), l);
                 launch_symmetrize(TGT.as<double>(), l, l, st);
-                // lift l x l cores to the 2l-dimensional joint coordinates: X -> Qred X Qred^T
+                // lift l x l cores to the 2l-dimensional basis coordinates: X -> Qred X Qred^T
                 auto lift = [&](const double* X, double* outm) {
                     DBuf t1 = B.mat(k2, l);
                     B.gemm(DT_F64, false, DT_F64, false, k2, l, l, pm.Qred.ptr(), k2, X, l, t1.as<double>(), k2);
@@ -679,6 +781,7 @@ extern "C" rr_status rr_sketch_apply(const rr_operator* A, double mu, const rr_b
             A16.reset(&P.alloc, (size_t)n * n * 2);
             launch_copy_mat(DT_F64, A->A, A->lda, DT_BF16, A16.ptr(), n, n, n, st);
         }
+        B.apply_power(A16.ptr());
         const int ydt = ((kernel && opts->prec != RR_PREC_FP64) || (!kernel && opts->prec == RR_PREC_MIXED))
                             ? DT_F32 : DT_F64;
         DBuf Y = B.mat(n, l, ydt == DT_F32 ? sizeof(float) : sizeof(double));

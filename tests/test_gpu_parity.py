@@ -927,3 +927,69 @@ def test_variant_solver_rejects_joint_basis_and_nys(dense_small):
         Pn.solve(_cuda(prob.b), method="r")
     x, info = Pn.solve(_cuda(prob.b), method="split", tol=1e-8)
     assert info["rc"] == rr.RR_OK
+
+
+# ---------------------------------------------- q = 1, shift sweeps, adaptive l
+def test_q1_build_fp64_matches_oracle(dense_small):
+    """Omega = A X (eq. testmatrix, q = 1) in float64 against the oracle: Q, R, G, tau."""
+    prob, op, kop, A = dense_small
+    mu, l = prob.mus[0], prob.l
+    P = rr.build_precond(rr.dense_operator(A), [mu], l=l, sketch="gaussian", seed=prob.omega_seed, q=1)
+    g = P.export(0)
+    o = orr.build(op, [mu], l, "gaussian", prob.omega_seed, q=1)[0]
+    rel = lambda a, b_: np.linalg.norm(a - b_) / np.linalg.norm(b_)
+    # A X entries are sums with cancellation: compare normwise (float64 product rounding)
+    assert rel(P.omega(), orr.test_matrix(op, "gaussian", prob.omega_seed, l, q=1)) < 1e-13
+    assert rel(g["Q"], o.Q) < 1e-9 and rel(g["R"], o.R) < 1e-9 and rel(g["G"], o.G) < 1e-8
+    assert abs(g["tau"] - o.tau) < 1e-8 * o.tau
+    x, info = P.solve(_cuda(prob.b), tol=1e-10)
+    ref = osol.pcg(op.shifted(mu), o.apply, prob.b, 1e-10)
+    assert info["rc"] == rr.RR_OK and abs(info["iters"] - ref.iters) <= max(2, int(0.03 * ref.iters))
+
+
+def test_q1_kernel_fp32_solve():
+    prob = workloads.cfg_kernel_ridge(n=4000, d=16, l=120)
+    mu = prob.mus[0]
+    op = Operator.from_problem(prob)
+    kop = rr.kernel_operator(rr.OP_RBF, _cuda(prob.pts), prob.kconst, prob.scale)
+    P0 = rr.build_precond(kop, [mu], l=prob.l, sketch="srht", seed=prob.omega_seed, prec="fp32")
+    P1 = rr.build_precond(kop, [mu], l=prob.l, sketch="srht", seed=prob.omega_seed, prec="fp32", q=1)
+    x, info = P1.solve(_cuda(prob.b), tol=prob.tol)
+    rel = osol.relres(op.shifted(mu), x.cpu().numpy(), prob.b)
+    assert info["rc"] == rr.RR_OK and rel <= prob.tol
+    # the power iteration captures the dominant range at least as well here
+    assert P1.export(0, with_q=False)["normE"] <= 1.05 * P0.export(0, with_q=False)["normE"]
+
+
+def test_shifted_cholesky_sweep_matches_oracle():
+    """Several shifts from one orthogonalisation at alpha = max mu (Section 5.1, shifted
+    Cholesky) against the oracle: Q_mu, R, G, tau per shift; batched solves reach tol."""
+    prob = workloads.cfg_small_dense(n=900, d=8, l=40)
+    op = Operator.from_problem(prob)
+    kop = rr.kernel_operator(rr.OP_RBF, _cuda(prob.pts), prob.kconst, prob.scale)
+    A = rr.kernel_to_dense(kop, "fp64")
+    mus = [1e-2, 1e-3, 1e-4]
+    P = rr.build_precond(rr.dense_operator(A), mus, l=prob.l, seed=prob.omega_seed, multi="shifted_chol")
+    o = orr.build(op, mus, prob.l, "gaussian", prob.omega_seed, multi="shifted_chol")
+    rel = lambda a, b_: np.linalg.norm(a - b_) / np.linalg.norm(b_)
+    for j in range(len(mus)):
+        g = P.export(j)
+        assert rel(g["Q"], o[j].Q) < 1e-8 and rel(g["R"], o[j].R) < 1e-8 and rel(g["G"], o[j].G) < 1e-7
+        assert abs(g["tau"] - o[j].tau) < 1e-7 * o[j].tau
+    B = np.stack([prob.b] * 3, axis=1)
+    X, infos, st = P.solve_batch(_cuda(B), [0, 1, 2], tol=1e-9)
+    for j, mu in enumerate(mus):
+        r = osol.relres(op.shifted(mu), X[:, j].cpu().numpy(), prob.b)
+        assert infos[j]["status"] == rr.RR_OK and r <= 1e-9 * 1.0001
+
+
+def test_adaptive_sketch_size_matches_oracle(dense_small):
+    """eq. ad_criterion: the device's doubling loop picks the oracle's l and ||E||."""
+    prob, op, kop, A = dense_small
+    mu = prob.mus[0]
+    kw = dict(l=8, sketch="gaussian", seed=prob.omega_seed, l_max=256, ad_factor=3.0)
+    P = rr.build_precond(rr.dense_operator(A), [mu], **kw)
+    n, l, _ = P.shape
+    Po, lo, trail = orr.build_adaptive(op, mu, 8, 256, f=3.0, seed=prob.omega_seed)
+    assert l == lo and len(trail) >= 2
+    assert abs(P.export(0, with_q=False)["normE"] - Po.normE) <= 1e-8 * Po.normE
