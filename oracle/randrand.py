@@ -197,13 +197,27 @@ def _tau(rule, mu, rho, Amu, Q, T, G, seed, n, power_iters):
     return tau, normE, lam
 
 
-def _finish(mu, Amu, Q, R, C, T, tau_rule, rho, seed, n, power_iters, Qb=None, Qred=None):
+def apply_core(tau, T, G, reorth: bool = False):
+    """Core K of P = I + Q K Q^T.
+
+    Default: P = I - Pi + tau Pi~ with the refined Pi = Q T Q^T, Pi~ = Q T G T Q^T
+    (eq. g_randrand_explicit with eq. accurate_proj): K = tau T G T - T.
+    reorth: the re-orthogonalised C-RandRAND of eq. c_randrand_reorth,
+    P = (I-Pi)(I-Pi) + tau (I - (I-Pi)(I-Pi)) A_mu^{-1} Pi with Pi = Q Q^T and
+    A_mu^{-1} Pi = Omega R^{-1} Q^T.  Since (I-Pi)(I-Pi) = I - Q T Q^T and
+    Q^T Omega R^{-1} = G for Q = A_mu Omega R^{-1}, this is K = tau T G - T (not
+    symmetric when Q is not exactly orthonormal)."""
+    return tau * (T @ G) - T if reorth else tau * (T @ G @ T) - T
+
+
+def _finish(mu, Amu, Q, R, C, T, tau_rule, rho, seed, n, power_iters, Qb=None, Qred=None,
+            reorth: bool = False):
     """G, tau and the apply core from the basis of one shift (shared tail of build)."""
     R_om, _ = chol_upper_ladder(0.5 * (C + C.T))
     H = R_om @ tri_inv_upper(R)
     G = H.T @ H
     tau, normE, lam = _tau(tau_rule, mu, rho, Amu, Q, T, G, seed, n, power_iters)
-    K = tau * (T @ G @ T) - T
+    K = apply_core(tau, T, G, reorth)
     if Qb is None:
         return Precond(mu, Q, R, G, T, K, tau, normE, lam, Qb=Q, Kc=K)
     return Precond(mu, Q, R, G, T, K, tau, normE, lam, Qb=Qb, Kc=Qred @ K @ Qred.T,
@@ -229,7 +243,8 @@ def test_matrix(op, sketch: str, seed: int, l: int, q: int = 0, omega_bf16: bool
 def build(op, mus: List[float], l: int, sketch: str = "gaussian", seed: int = 0,
           orth: int = SKETCHED_CHOLQR, tau_rule: int = OPT, rho: float = 1.0,
           power_iters: int = 10, Omega: Optional[np.ndarray] = None,
-          omega_bf16: bool = False, q: int = 0, multi: str = "joint") -> List[Precond]:
+          omega_bf16: bool = False, q: int = 0, multi: str = "joint",
+          reorth: bool = False) -> List[Precond]:
     """Build one C-RandRAND preconditioner per shift (Algorithm RandRAND_PCG steps 1-4).
 
     omega_bf16: the test matrix is drawn in bfloat16 (as the float32-precision
@@ -253,7 +268,8 @@ def build(op, mus: List[float], l: int, sketch: str = "gaussian", seed: int = 0,
         else:
             Q, R = cholqr(Y)
         T = 2.0 * np.eye(l) - Q.T @ Q
-        return [_finish(mu, Amu, Q, R, Omega.T @ Y, T, tau_rule, rho, seed, n, power_iters)]
+        return [_finish(mu, Amu, Q, R, Omega.T @ Y, T, tau_rule, rho, seed, n, power_iters,
+                        reorth=reorth)]
     if multi == "shifted_chol":
         return build_shifted_cholesky(op, mus, l, Omega, seed, orth, tau_rule, rho, power_iters)
     if multi != "joint":
@@ -279,6 +295,62 @@ def build(op, mus: List[float], l: int, sketch: str = "gaussian", seed: int = 0,
         out.append(_finish(mu, Amu, Q, R, OAO + mu * OO, T, tau_rule, rho, seed, n, power_iters,
                            Qb=Qj, Qred=Qred))
     return out
+
+
+@dataclass
+class BasislessPrecond:
+    """Basis-less C-RandRAND (Section 4.2, Algorithm BL_RandRAND_PCG): Q is never
+    formed; Q^T u = R^{-T} (A_mu Omega)^T u and Q d = (A_mu Omega) R^{-1} d, so
+    P = I + Y Kr Y^T with Y = A_mu Omega and Kr = R^{-1} K R^{-T}."""
+    mu: float
+    Y: np.ndarray
+    R: np.ndarray
+    G: np.ndarray
+    T: np.ndarray
+    K: np.ndarray
+    Kr: np.ndarray
+    tau: float
+    normE: float
+    lam: float
+
+    def apply(self, r: np.ndarray) -> np.ndarray:
+        return r + self.Y @ (self.Kr @ (self.Y.T @ r))
+
+    def dense(self) -> np.ndarray:
+        return np.eye(self.Y.shape[0]) + self.Y @ self.Kr @ self.Y.T
+
+    @property
+    def Q(self) -> np.ndarray:
+        return self.Y @ tri_inv_upper(self.R)
+
+
+def build_basisless(op, mu: float, l: int, sketch: str = "colsample", seed: int = 0,
+                    tau_rule: int = OPT, rho: float = 1.0, power_iters: int = 10,
+                    reorth: bool = False) -> BasislessPrecond:
+    """Algorithm BL_RandRAND_PCG steps 1-3 with the fast Q-less preconditioned Cholesky
+    QR (Algorithm prec_chol_qr): S = Theta Y, R_sk = qr(S), the preconditioned Gram
+    R_sk^{-T} Y^T Y R_sk^{-1}, R = R_chol R_sk; Q^T Q = R^{-T} Y^T Y R^{-1} gives
+    T = 2I - Q^T Q; Omega^T A_mu Omega = Omega^T Y gives G; tau from the same power
+    iterations as the explicit build, with Q applied through Y and R."""
+    n = op.n
+    Omega = _rng.omega(sketch, seed, n, l)
+    Y = op.matmat(Omega) + mu * Omega
+    S = np.asarray(_rng.theta(seed, n, l) @ Y)
+    R_sk = householder_r(S)
+    Rski = tri_inv_upper(R_sk)
+    GY = Y.T @ Y
+    R_c, _ = chol_upper_ladder(Rski.T @ GY @ Rski)
+    R = R_c @ R_sk
+    Ri = tri_inv_upper(R)
+    T = 2.0 * np.eye(l) - Ri.T @ GY @ Ri
+    C = Omega.T @ Y
+    R_om, _ = chol_upper_ladder(0.5 * (C + C.T))
+    H = R_om @ Ri
+    G = H.T @ H
+    Q = Y @ Ri        # only inside the tau estimates, as the operator Y R^{-1}
+    tau, normE, lam = _tau(tau_rule, mu, rho, op.shifted(mu), Q, T, G, seed, n, power_iters)
+    K = apply_core(tau, T, G, reorth)
+    return BasislessPrecond(mu, Y, R, G, T, K, Ri @ K @ Ri.T, tau, normE, lam)
 
 
 def build_shifted_cholesky(op, mus: List[float], l: int, Omega: np.ndarray, seed: int = 0,

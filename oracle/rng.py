@@ -111,6 +111,35 @@ def round_bf16(x) -> np.ndarray:
     return r.view(np.float32).astype(np.float64)
 
 
+def colsample_descriptor(seed: int, n: int, l: int):
+    """Signed uniform column sampling (Section 7.2.2 and the limited-memory kernel
+    ridge experiments: Omega = X^T a uniform sampling matrix, so A_mu Omega is a set of
+    columns of A_mu).  Column c of Omega is D_{i_c} e_{i_c}: the l distinct indices
+    i_c come from a partial Fisher-Yates shuffle of [0, n) (step c swaps position c
+    with c + floor(hi32(w) (n - c) / 2^32), w = word n + c of stream `seed`) and the
+    signs D_i from the top bit of word i -- the SRHT descriptor's draws with the
+    padded size replaced by n.  Returns (signs of the sampled columns, indices)."""
+    if l > n:
+        raise ValueError("l exceeds n")
+    wsign = splitmix64_words(seed, np.arange(n, dtype=np.uint64))
+    D = np.where((wsign >> np.uint64(63)) == 0, 1.0, -1.0)
+    perm = np.arange(n, dtype=np.int64)
+    wsamp = splitmix64_words(seed, np.arange(n, n + l, dtype=np.uint64))
+    for c in range(l):
+        span = n - c
+        j = c + int(((int(wsamp[c]) >> 32) * span) >> 32)
+        perm[c], perm[j] = perm[j], perm[c]
+    idx = perm[:l].copy()
+    return D[idx], idx
+
+
+def colsample_omega(seed: int, n: int, l: int) -> np.ndarray:
+    sgn, idx = colsample_descriptor(seed, n, l)
+    Om = np.zeros((n, l))
+    Om[idx, np.arange(l)] = sgn
+    return Om
+
+
 def omega(kind: str, seed: int, n: int, l: int, bf16: bool = False) -> np.ndarray:
     """The test matrix; `bf16` draws it in bfloat16 (Gaussian entries rounded once)."""
     if kind == "gaussian":
@@ -118,6 +147,8 @@ def omega(kind: str, seed: int, n: int, l: int, bf16: bool = False) -> np.ndarra
         return round_bf16(g) if bf16 else g
     if kind == "srht":
         return srht_omega(seed, n, l)
+    if kind == "colsample":
+        return colsample_omega(seed, n, l)
     raise ValueError(kind)
 
 
