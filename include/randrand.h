@@ -75,8 +75,16 @@ typedef struct {
     double scale;
 } rr_operator;
 
-/* Test matrix Omega (Section 1.1 eq. testmatrix with q = 0; Section 2). */
-typedef enum { RR_SK_GAUSSIAN = 0, RR_SK_SRHT = 1 } rr_sketch;
+/* Test matrix Omega (Section 1.1 eq. testmatrix; Section 2).  COLSAMPLE: signed
+ * uniform column sampling (column c = sgn_c e_idx_c, l distinct indices), the
+ * paper's test matrix for kernel systems (Section 7.2.2, limited-memory KRR). */
+typedef enum { RR_SK_GAUSSIAN = 0, RR_SK_SRHT = 1, RR_SK_COLSAMPLE = 2 } rr_sketch;
+/* Representation of the deflation basis (Section 4).  EXPLICIT: Q (n x l) stored.
+ * LESS: basis-less (Section 4.2, Algorithm BL_RandRAND_PCG): only R, the l x l
+ * factors and the sampled indices are kept; Q^T u = R^{-T} (A_mu Omega)^T u and
+ * Q d = (A_mu Omega) R^{-1} d are formed from kernel entries on every use (kernel
+ * operators, COLSAMPLE test matrix, one shift; O(n + l^2) memory). */
+typedef enum { RR_BASIS_EXPLICIT = 0, RR_BASIS_LESS = 1 } rr_basis;
 /* Orthogonalisation of A_mu Omega: Algorithm prec_chol_qr (sketched, default) or chol_qr. */
 typedef enum { RR_ORTH_SKETCHED_CHOLQR = 0, RR_ORTH_CHOLQR = 1 } rr_orth;
 /*
@@ -152,6 +160,9 @@ typedef struct {
                              doubling cut it below 0.9 of its previous value; single
                              shift, tau rule OPT or RHO.  0: off (default)               */
     double ad_factor;     /* f of eq. ad_criterion (default 100)                         */
+    int32_t basis;        /* rr_basis (default EXPLICIT)                                 */
+    int32_t reorth;       /* 1: re-orthogonalised C-RandRAND, eq. c_randrand_reorth: core
+                             tau T G - T in place of tau T G T - T (default 0)           */
 } rr_build_opts;
 
 typedef struct {

@@ -28,7 +28,7 @@ ORTH_SKETCHED_CHOLQR, ORTH_CHOLQR = 0, 1
 PREC_FP64, PREC_FP32, PREC_MIXED = 0, 1, 2
 TAU_OPT, TAU_RHO, TAU_NYS = 0, 1, 2
 
-_SKETCH = {"gaussian": SK_GAUSSIAN, "srht": SK_SRHT}
+_SKETCH = {"gaussian": SK_GAUSSIAN, "srht": SK_SRHT, "colsample": 2}
 _PREC = {"fp64": PREC_FP64, "fp32": PREC_FP32, "mixed": PREC_MIXED}
 _TAU = {"opt": TAU_OPT, "rho": TAU_RHO, "nys": TAU_NYS}
 _ORTH = {"sketched": ORTH_SKETCHED_CHOLQR, "cholqr": ORTH_CHOLQR}
@@ -48,7 +48,8 @@ class rr_build_opts(C.Structure):
     _fields_ = [("l", C.c_int64), ("sketch", C.c_int32), ("seed", C.c_uint64),
                 ("orth", C.c_int32), ("prec", C.c_int32), ("tau_rule", C.c_int32),
                 ("rho", C.c_double), ("power_iters", C.c_int32), ("power_q", C.c_int32),
-                ("multi_shift", C.c_int32), ("l_max", C.c_int64), ("ad_factor", C.c_double)]
+                ("multi_shift", C.c_int32), ("l_max", C.c_int64), ("ad_factor", C.c_double),
+                ("basis", C.c_int32), ("reorth", C.c_int32)]
 
 
 class rr_solve_opts(C.Structure):
@@ -219,7 +220,8 @@ def kernel_operator(kind: int, pts, kconst: float, scale: float) -> Operator:
 
 
 def build_opts(l=0, sketch="gaussian", seed=0, orth="sketched", prec="fp64", tau_rule="opt",
-               rho=1.0, power_iters=10, q=0, multi="joint", l_max=0, ad_factor=100.0) -> rr_build_opts:
+               rho=1.0, power_iters=10, q=0, multi="joint", l_max=0, ad_factor=100.0,
+               basis="explicit", reorth=False) -> rr_build_opts:
     o = rr_build_opts()
     lib().rr_build_opts_default(C.byref(o))
     o.l = int(l)
@@ -234,6 +236,8 @@ def build_opts(l=0, sketch="gaussian", seed=0, orth="sketched", prec="fp64", tau
     o.multi_shift = {"joint": 0, "shifted_chol": 1}[multi] if isinstance(multi, str) else int(multi)
     o.l_max = int(l_max)
     o.ad_factor = float(ad_factor)
+    o.basis = {"explicit": 0, "less": 1}[basis] if isinstance(basis, str) else int(basis)
+    o.reorth = 1 if reorth else 0
     return o
 
 

@@ -279,6 +279,17 @@ void apply_operator_multi(const rr_precond& P, const double* U, int nr, double m
 
 int apply_projected(const rr_precond& P, const double* Kc, const double* r, double rcoef, double* z,
                     double* c_part, double* d, double* rz_part, const int32_t* stop, hipStream_t st) {
+    if (P.basisless) {
+        // z = rcoef r + Y Kr Y^T r with Y = A_mu Omega (Kc holds Kr^T)
+        const KernelOp k = kernel_op_of(P);
+        const bool f64 = P.opts.prec == RR_PREC_FP64;
+        const double mu = P.per[0].mu;
+        launch_kblock_rows(k, f64, P.bl_idx.as<int32_t>(), P.bl_sgn.as<double>(), P.l, r, mu, c_part, stop, st);
+        launch_core_apply(P.l, Kc, P.l, c_part, 1, d, stop, st);
+        launch_kblock_cols(k, f64, P.bl_idx.as<int32_t>(), P.bl_sgn.as<double>(), P.bl_pos.as<int32_t>(), P.l, d, mu,
+                           r, rcoef, z, rz_part, stop, st);
+        return kblock_cols_blocks(P.n);
+    }
     const int nch = gemv_t_chunks(P.n, P.kb);
     launch_gemv_t(P.n, P.kb, P.Qb.as<double>(), P.n, r, c_part, nch, stop, st);
     launch_core_apply(P.kb, Kc, P.kb, c_part, nch, d, stop, st);
@@ -359,6 +370,8 @@ void rr_build_opts_default(rr_build_opts* o) {
     o->multi_shift = RR_MULTI_JOINT;
     o->l_max = 0;
     o->ad_factor = 100.0;
+    o->basis = RR_BASIS_EXPLICIT;
+    o->reorth = 0;
 }
 
 void rr_solve_opts_default(rr_solve_opts* o) {
@@ -429,7 +442,22 @@ rr_status rr_precond_export(const rr_precond* P, int32_t mu_index, double* Q_hos
         RR_HIP(hipSetDevice(P->device));
         RR_HIP(hipDeviceSynchronize());
         if (Q_host) {
-            if (!P->joint) {
+            if (P->basisless) {
+                // Q = Y R^{-1} formed on demand (a basis-less handle never stores it)
+                Alloc al;
+                DBuf Yr(&al, (size_t)n * l * sizeof(double)), Q(&al, (size_t)n * l * sizeof(double));
+                DBuf Ri(&al, (size_t)l * l * sizeof(double));
+                DBuf ws(&al, ((size_t)4 * l * l + 4 * n) * sizeof(double));
+                const KernelOp k = kernel_op_of(*P);
+                launch_kblock_y(k, P->opts.prec == RR_PREC_FP64, P->bl_idx.as<int32_t>(), P->bl_sgn.as<double>(), l,
+                                pm.mu, 0, n, nullptr, nullptr, Yr.as<double>(), l, nullptr);
+                launch_tri_inv_upper(pm.R.as<double>(), l, l, Ri.as<double>(), l, nullptr);
+                // Yr (row-major n x l) is the column-major l x n matrix Y^T
+                launch_gemm(DT_F64, true, DT_F64, false, n, l, l, Yr.ptr(), l, Ri.ptr(), l, Q.as<double>(), n, 1.0,
+                            0.0, ws.as<double>(), (size_t)4 * l * l + 4 * n, nullptr);
+                RR_HIP(hipDeviceSynchronize());
+                RR_HIP(hipMemcpy(Q_host, Q.ptr(), (size_t)n * l * sizeof(double), hipMemcpyDeviceToHost));
+            } else if (!P->joint) {
                 RR_HIP(hipMemcpy(Q_host, P->Qb.ptr(), (size_t)n * l * sizeof(double), hipMemcpyDeviceToHost));
             } else {
                 Alloc al;
@@ -457,7 +485,11 @@ rr_status rr_precond_export_omega(const rr_precond* P, double* Omega_host) {
         RR_HIP(hipSetDevice(P->device));
         Alloc al;
         DBuf O(&al, (size_t)P->n * P->l * sizeof(double));
-        launch_copy_mat(P->omega_dt, P->Omega.ptr(), P->n, DT_F64, O.ptr(), P->n, P->n, P->l, nullptr);
+        if (P->basisless)
+            launch_colsample_fill(DT_F64, P->n, P->l, P->n, P->bl_idx.as<int32_t>(), P->bl_sgn.as<double>(), O.ptr(),
+                                  nullptr);
+        else
+            launch_copy_mat(P->omega_dt, P->Omega.ptr(), P->n, DT_F64, O.ptr(), P->n, P->n, P->l, nullptr);
         RR_HIP(hipDeviceSynchronize());
         RR_HIP(hipMemcpy(Omega_host, O.ptr(), (size_t)P->n * P->l * sizeof(double), hipMemcpyDeviceToHost));
         return RR_OK;

@@ -142,6 +142,20 @@ struct Builder {
     // exactly; P.Omega then holds the same values in float32.
     DBuf ob_buf;
     DBuf srht_rows, srht_dbits;   // SRHT descriptor (sampled rows, sign bits of D)
+    // Signed column sampling: idx, sgn and pos into the handle (the SRHT descriptor's
+    // sampler and signs over [0, n)).
+    void make_colsample() {
+        const int64_t n = P.n, l = P.l;
+        DBuf perm(al, (size_t)n * sizeof(int32_t)), D(al, (size_t)n * sizeof(float));
+        P.bl_idx.reset(al, (size_t)l * sizeof(int32_t));
+        P.bl_sgn.reset(al, (size_t)l * sizeof(double));
+        P.bl_pos.reset(al, (size_t)n * sizeof(int32_t));
+        launch_srht_prepare(n, l, P.opts.seed, n, perm.as<int32_t>(), P.bl_idx.as<int32_t>(), D.as<float>(), st);
+        launch_colsample_prep(n, l, D.as<float>(), P.bl_idx.as<int32_t>(), P.bl_sgn.as<double>(),
+                              P.bl_pos.as<int32_t>(), st);
+        check_launch();
+    }
+
     void make_omega() {
         const int64_t n = P.n, l = P.l;
         const rr_build_opts& o = P.opts;
@@ -162,6 +176,9 @@ struct Builder {
         const int64_t gld = bf16_omega ? ldo : n;
         if (o.sketch == RR_SK_GAUSSIAN) {
             launch_gauss_fill(gen, gdt, n, l, gld, o.seed, st);
+        } else if (o.sketch == RR_SK_COLSAMPLE) {
+            make_colsample();
+            launch_colsample_fill(gdt, n, l, gld, P.bl_idx.as<int32_t>(), P.bl_sgn.as<double>(), gen, st);
         } else {
             int64_t s = 1;
             while (s < n) s *= 2;
@@ -332,6 +349,129 @@ struct Builder {
         return lam;
     }
 
+    // Basis-less C-RandRAND (Algorithm BL_RandRAND_PCG steps 1-3) for a kernel
+    // operator and a signed column-sampling Omega: Y = A_mu Omega streams through
+    // row blocks (never stored whole) to form S = Theta Y and Y^T Y; R from the Q-less
+    // preconditioned Cholesky QR (Algorithm prec_chol_qr) or Cholesky QR; Q^T Q =
+    // R^{-T} Y^T Y R^{-1} gives T, Omega^T A_mu Omega gives G, and the power iterations
+    // apply Q through Y and R.  The apply core is Kr = R^{-1} K R^{-T} over Y.
+    void build_basisless(PerMu& pm) {
+        const int64_t n = P.n, l = P.l;
+        const KernelOp k = kernel_op_of(P);
+        const bool f64 = P.opts.prec == RR_PREC_FP64;
+        const double mu = pm.mu;
+        const int32_t* idx = P.bl_idx.as<int32_t>();
+        const double* sgn = P.bl_sgn.as<double>();
+        const int32_t* pos = P.bl_pos.as<int32_t>();
+        const int64_t rb = std::max<int64_t>(256, std::min<int64_t>(n, ((int64_t)1 << 22) / l));
+        DBuf Yb = mat(rb, l), GY = mat(l, l), S = mat(2 * l, l);
+        const bool sketched = P.opts.orth == RR_ORTH_SKETCHED_CHOLQR;
+        for (int64_t r0 = 0; r0 < n; r0 += rb) {
+            const int64_t rows = std::min(rb, n - r0);
+            launch_kblock_y(k, f64, idx, sgn, l, mu, r0, rows, nullptr, nullptr, Yb.as<double>(), l, st);
+            if (sketched)
+                launch_theta_apply_rows(rows, r0, l, P.opts.seed + 1, Yb.as<double>(), l, S.as<double>(), 2 * l,
+                                        r0 > 0, st);
+            // Yb (row-major rows x l) is the column-major l x rows matrix Y_b^T
+            gemm(DT_F64, false, DT_F64, true, l, l, rows, Yb.ptr(), l, Yb.ptr(), l, GY.as<double>(), l, 1.0,
+                 r0 > 0 ? 1.0 : 0.0);
+        }
+        Yb.release();
+        launch_symmetrize(GY.as<double>(), l, l, st);
+        pm.R.reset(al, (size_t)l * l * sizeof(double));
+        if (sketched) {
+            DBuf Rsk = mat(l, l), Rski = mat(l, l), tmp = mat(l, l), W = mat(l, l);
+            const size_t hwd = householder_ws_doubles(2 * l, l);
+            DBuf hws(al, hwd * sizeof(double));
+            launch_householder_r(S.as<double>(), 2 * l, l, 2 * l, Rsk.as<double>(), l, hws.as<double>(), hwd, st);
+            launch_tri_inv_upper(Rsk.as<double>(), l, l, Rski.as<double>(), l, st);
+            gemm(DT_F64, true, DT_F64, false, l, l, l, Rski.ptr(), l, GY.ptr(), l, tmp.as<double>(), l);
+            gemm(DT_F64, false, DT_F64, false, l, l, l, tmp.ptr(), l, Rski.ptr(), l, W.as<double>(), l);
+            launch_symmetrize(W.as<double>(), l, l, st);
+            chol_ladder(W.as<double>(), l);   // W <- R_chol
+            gemm(DT_F64, false, DT_F64, false, l, l, l, W.ptr(), l, Rsk.ptr(), l, pm.R.as<double>(), l);
+            launch_zero_lower(pm.R.as<double>(), l, l, st);
+        } else {
+            launch_copy_mat(DT_F64, GY.ptr(), l, DT_F64, pm.R.ptr(), l, l, l, st);
+            chol_ladder(pm.R.as<double>(), l);
+        }
+        S.release();
+        DBuf Rinv = mat(l, l), tmp = mat(l, l);
+        launch_tri_inv_upper(pm.R.as<double>(), l, l, Rinv.as<double>(), l, st);
+        // T = 2I - R^{-T} Y^T Y R^{-1}
+        pm.T.reset(al, (size_t)l * l * sizeof(double));
+        gemm(DT_F64, true, DT_F64, false, l, l, l, Rinv.ptr(), l, GY.ptr(), l, tmp.as<double>(), l);
+        gemm(DT_F64, false, DT_F64, false, l, l, l, tmp.ptr(), l, Rinv.ptr(), l, pm.T.as<double>(), l);
+        launch_symmetrize(pm.T.as<double>(), l, l, st);
+        orth_error(pm.T.as<double>(), l);
+        launch_two_minus(pm.T.as<double>(), l, l, st);
+        // G from C = Omega^T A_mu Omega (sampled rows and columns of A_mu, signed)
+        DBuf C = mat(l, l);
+        launch_kblock_y(k, f64, idx, sgn, l, mu, 0, l, idx, sgn, C.as<double>(), l, st);
+        pm.G.reset(al, (size_t)l * l * sizeof(double));
+        core_G(C.as<double>(), pm.R.as<double>(), pm.G.as<double>(), l);
+        DBuf TG = mat(l, l), TGT = mat(l, l);
+        gemm(DT_F64, false, DT_F64, false, l, l, l, pm.T.ptr(), l, pm.G.ptr(), l, TG.as<double>(), l);
+        gemm(DT_F64, false, DT_F64, false, l, l, l, TG.ptr(), l, pm.T.ptr(), l, TGT.as<double>(), l);
+        launch_symmetrize(TGT.as<double>(), l, l, st);
+        // cores over Y: X -> R^{-1} X R^{-T}
+        auto over_y = [&](const double* X, double* outm, bool sym) {
+            gemm(DT_F64, false, DT_F64, false, l, l, l, Rinv.ptr(), l, X, l, tmp.as<double>(), l);
+            gemm(DT_F64, false, DT_F64, true, l, l, l, tmp.ptr(), l, Rinv.ptr(), l, outm, l);
+            if (sym) launch_symmetrize(outm, l, l, st);
+        };
+        DBuf KPi = mat(l, l), KnegPi = mat(l, l), KPt = mat(l, l);
+        over_y(pm.T.as<double>(), KPi.as<double>(), true);
+        launch_axpby_mat(-1.0, KPi.as<double>(), l, 0.0, KPi.as<double>(), l, KnegPi.as<double>(), l, l, l, st);
+        over_y(TGT.as<double>(), KPt.as<double>(), true);
+        DBuf cv(al, (size_t)l * sizeof(double)), dv(al, (size_t)l * sizeof(double));
+        DBuf t1(al, (size_t)n * sizeof(double)), t2(al, (size_t)n * sizeof(double));
+        DBuf opp(al, ((size_t)operator_part_count(P) + 1) * sizeof(double));
+        // out = rcoef v + Y Kcore Y^T v (Kcore symmetric)
+        auto proj = [&](const double* Kcore, const double* v, double rcoef, double* out) {
+            launch_kblock_rows(k, f64, idx, sgn, l, v, mu, cv.as<double>(), nullptr, st);
+            launch_core_apply(l, Kcore, l, cv.as<double>(), 1, dv.as<double>(), nullptr, st);
+            launch_kblock_cols(k, f64, idx, sgn, pos, l, dv.as<double>(), mu, v, rcoef, out, nullptr, nullptr, st);
+        };
+        auto amu = [&](const double* v, double* out) {
+            apply_operator(P, v, mu, out, opp.as<double>(), kws.as<double>(), false, nullptr, st);
+        };
+        if (P.opts.tau_rule == RR_TAU_NYS) {
+            pm.tau = 1.0 / small_lambda_max(pm.G.as<double>(), l, P.opts.seed + 3);
+            pm.normE = pm.lam = std::nan("");
+        } else {
+            // ||E||: v -> (I-Pi) A_mu (I-Pi) v;  lam: v -> Pi A_mu Pi~ v
+            pm.normE = power_norm([&](const double* v, double* w) {
+                proj(KnegPi.as<double>(), v, 1.0, t1.as<double>());
+                amu(t1.as<double>(), t2.as<double>());
+                proj(KnegPi.as<double>(), t2.as<double>(), 1.0, w);
+            }, P.opts.seed + 2, P.opts.power_iters);
+            pm.lam = power_norm([&](const double* v, double* w) {
+                proj(KPt.as<double>(), v, 0.0, t1.as<double>());
+                amu(t1.as<double>(), t2.as<double>());
+                proj(KPi.as<double>(), t2.as<double>(), 0.0, w);
+            }, P.opts.seed + 3, P.opts.power_iters);
+            if (!std::isfinite(pm.normE) || !(pm.lam > 0.0) || !std::isfinite(pm.lam))
+                throw RrError{RR_ENOTSPD, "power-iteration estimates of ||E|| or lam are not positive"};
+            if (!(pm.normE > 0.0)) pm.tau = 1.0 / small_lambda_max(pm.G.as<double>(), l, P.opts.seed + 3);
+            else if (P.opts.tau_rule == RR_TAU_OPT && mu > 0.0) pm.tau = std::sqrt(mu * pm.normE / pm.lam);
+            else pm.tau = P.opts.rho * pm.normE / pm.lam;
+        }
+        // K = tau T G T - T (or the re-orthogonalised tau T G - T); the solve's core apply
+        // computes Kc^T c, so Kc = (R^{-1} K R^{-T})^T = R^{-1} K^T R^{-T}
+        DBuf Kt = mat(l, l);
+        if (P.opts.reorth) {
+            DBuf GT = mat(l, l);
+            gemm(DT_F64, false, DT_F64, false, l, l, l, pm.G.ptr(), l, pm.T.ptr(), l, GT.as<double>(), l);
+            launch_axpby_mat(pm.tau, GT.as<double>(), l, -1.0, pm.T.as<double>(), l, Kt.as<double>(), l, l, l, st);
+        } else {
+            launch_axpby_mat(pm.tau, TGT.as<double>(), l, -1.0, pm.T.as<double>(), l, Kt.as<double>(), l, l, l, st);
+        }
+        pm.Kc.reset(al, (size_t)l * l * sizeof(double));
+        over_y(Kt.as<double>(), pm.Kc.as<double>(), !P.opts.reorth);
+        check_launch();
+    }
+
     // tau and its estimates for one shift; cores are kb x kb over the basis Qb.
     // M: Qb^T Qb (kb x kb), for the merged projections below.
     void tau_for(PerMu& pm, const double* negT, const double* TGT, const double* T, const double* G,
@@ -464,8 +604,18 @@ extern "C" rr_status rr_build_precond(const rr_operator* A, const double* mus, i
         if (opts_in) o = *opts_in; else rr_build_opts_default(&o);
         const int64_t n = A->n;
         RR_REQUIRE(o.l >= 0 && o.l <= n, "l must be in [0, n]");
-        RR_REQUIRE(o.sketch == RR_SK_GAUSSIAN || o.sketch == RR_SK_SRHT, "unknown sketch");
+        RR_REQUIRE(o.sketch == RR_SK_GAUSSIAN || o.sketch == RR_SK_SRHT || o.sketch == RR_SK_COLSAMPLE,
+                   "unknown sketch");
         RR_REQUIRE(o.orth == RR_ORTH_SKETCHED_CHOLQR || o.orth == RR_ORTH_CHOLQR, "unknown orth");
+        RR_REQUIRE(o.basis == RR_BASIS_EXPLICIT || o.basis == RR_BASIS_LESS, "unknown basis");
+        RR_REQUIRE(o.reorth == 0 || o.reorth == 1, "reorth must be 0 or 1");
+        if (o.basis == RR_BASIS_LESS && o.l > 0) {
+            RR_REQUIRE(is_kernel(*A), "a basis-less handle needs a kernel operator");
+            RR_REQUIRE(o.sketch == RR_SK_COLSAMPLE, "a basis-less handle needs the COLSAMPLE test matrix");
+            RR_REQUIRE(n_mu == 1, "a basis-less handle holds one shift");
+            RR_REQUIRE(o.power_q == 0, "a basis-less handle uses q = 0");
+        }
+        if (o.reorth) RR_REQUIRE(n_mu == 1, "the re-orthogonalised core is built for one shift");
         RR_REQUIRE(o.prec >= RR_PREC_FP64 && o.prec <= RR_PREC_MIXED, "unknown precision");
         RR_REQUIRE(o.tau_rule >= RR_TAU_OPT && o.tau_rule <= RR_TAU_NYS, "unknown tau rule");
         RR_REQUIRE(std::isfinite(o.rho) && o.rho > 0.0, "rho must be finite and > 0");
@@ -536,6 +686,18 @@ extern "C" rr_status rr_build_precond(const rr_operator* A, const double* mus, i
 
         Builder B(P, st);
         const int64_t l = o.l;
+        if (o.basis == RR_BASIS_LESS) {
+            P.basisless = true;
+            B.make_colsample();
+            B.build_basisless(P.per[0]);
+            RR_HIP(hipGetLastError());
+            if (B.oerr.ptr())
+                RR_HIP(hipMemcpyAsync(&P.orth_err, B.oerr.ptr(), sizeof(double), hipMemcpyDeviceToHost, st));
+            RR_HIP(hipStreamSynchronize(st));
+            P.ms_build = now_ms() - t0;
+            *out = H.release();
+            return RR_OK;
+        }
         // A1: Omega
         B.make_omega();
         const bool kernel = is_kernel(*A);
@@ -622,7 +784,16 @@ extern "C" rr_status rr_build_precond(const rr_operator* A, const double* mus, i
                           M.as<double>());
             }
             pm.Kc.reset(al, (size_t)l * l * sizeof(double));
-            launch_axpby_mat(pm.tau, TGT.as<double>(), l, -1.0, pm.T.as<double>(), l, pm.Kc.as<double>(), l, l, l, st);
+            if (o.reorth) {
+                // eq. c_randrand_reorth: K = tau T G - T; the core apply computes Kc^T c,
+                // so Kc = K^T = tau G T - T
+                DBuf GT = B.mat(l, l);
+                B.gemm(DT_F64, false, DT_F64, false, l, l, l, pm.G.ptr(), l, pm.T.ptr(), l, GT.as<double>(), l);
+                launch_axpby_mat(pm.tau, GT.as<double>(), l, -1.0, pm.T.as<double>(), l, pm.Kc.as<double>(), l, l, l, st);
+            } else {
+                launch_axpby_mat(pm.tau, TGT.as<double>(), l, -1.0, pm.T.as<double>(), l, pm.Kc.as<double>(), l, l, l,
+                                 st);
+            }
             B.check_launch();
         } else {
             // several shifts (Section 5.1): the apply basis Qb (n x 2l) and, per shift,

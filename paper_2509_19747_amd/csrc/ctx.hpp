@@ -180,7 +180,11 @@ struct rr_precond {
     // basis
     rr::DBuf Omega;       // n x l, dtype omega_dt
     int omega_dt = rr::DT_F64;
-    rr::DBuf Qb;          // n x kb float64
+    rr::DBuf Qb;          // n x kb float64 (not stored by a basis-less handle)
+    // basis-less handle (signed column sampling): Omega's columns sgn_c e_idx_c,
+    // pos[i] = c for i = idx_c (else -1); Q = A_mu Omega R^{-1} is never formed
+    bool basisless = false;
+    rr::DBuf bl_idx, bl_sgn, bl_pos;
     std::vector<rr::PerMu> per;
     double orth_err = 0.0;
     double ms_build = 0.0;

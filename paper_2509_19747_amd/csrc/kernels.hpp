@@ -55,6 +55,10 @@ constexpr int THETA_NNZ = 8;
 int theta_nnz(int64_t k);
 void launch_theta_apply(int64_t n, int64_t k, uint64_t seed, const double* Yt, int64_t ldy, double* S,
                         int64_t lds, hipStream_t st);
+// The same over rows [row0, row0 + rows) of Y (Yt holds those rows), adding into S
+// when accumulate: S = Theta Y is then summed over row blocks.
+void launch_theta_apply_rows(int64_t rows, int64_t row0, int64_t k, uint64_t seed, const double* Yt, int64_t ldy,
+                             double* S, int64_t lds, bool accumulate, hipStream_t st);
 // out[c + i * ldo] = (double) in[i + c * ldi] (i < rows, c < cols): a column-major
 // matrix of dtype float64 / float32 written row-major in float64.
 void launch_transpose_f64(int dtype, int64_t rows, int64_t cols, const void* in, int64_t ldi, double* out,
@@ -332,6 +336,28 @@ void launch_state_init(CgState* s, const double* rz_part, int rz_count, double t
 // Finite check of a vector: *flag = 1 if any entry is NaN/Inf.
 // *flag = 1 if v holds a NaN or Inf; *nonzero = 1 (when given) if any entry is not 0.
 void launch_nonfinite(int64_t n, const double* v, int32_t* flag, hipStream_t st, int32_t* nonzero = nullptr);
+
+// ------------------------------------------- basis-less kernel blocks
+// Signed column sampling: sgn[c] = D[idx[c]], pos[i] = c if i = idx[c] else -1.
+void launch_colsample_prep(int64_t n, int64_t l, const float* D, const int32_t* idx, double* sgn, int32_t* pos,
+                           hipStream_t st);
+// dense Omega (ld x l, dtype) with Omega[idx[c], c] = sgn[c]
+void launch_colsample_fill(int dtype, int64_t n, int64_t l, int64_t ld, const int32_t* idx, const double* sgn,
+                           void* out, hipStream_t st);
+// out[c] = sgn_c (scale K(x_idx_c, :) v + mu v_idx_c)  (= (A_mu Omega)^T v)
+void launch_kblock_rows(const KernelOp& op, bool f64, const int32_t* idx, const double* sgn, int64_t l,
+                        const double* v, double mu, double* out, const int32_t* stop, hipStream_t st);
+// z = rcoef r + (A_mu Omega) d, with kblock_cols_blocks(n) partials of r^T z (rz_part may be null;
+// r may be null for z = (A_mu Omega) d)
+int kblock_cols_blocks(int64_t n);
+void launch_kblock_cols(const KernelOp& op, bool f64, const int32_t* idx, const double* sgn, const int32_t* pos,
+                        int64_t l, const double* d, double mu, const double* r, double rcoef, double* z,
+                        double* rz_part, const int32_t* stop, hipStream_t st);
+// rows of A_mu Omega, row-major (out[i * ldo + c]): rows r0 .. r0 + rows - 1, or the rows
+// rowidx[i] scaled by rowsgn[i] (Omega^T A_mu Omega for rowidx = idx, rowsgn = sgn)
+void launch_kblock_y(const KernelOp& op, bool f64, const int32_t* idx, const double* sgn, int64_t l, double mu,
+                     int64_t r0, int64_t rows, const int32_t* rowidx, const double* rowsgn, double* out,
+                     int64_t ldo, hipStream_t st);
 
 // ------------------------------------------------ general Krylov engine
 void launch_mr_init(const double* part, int count, MrState* s, double target2, int32_t maxit, int32_t iters,

@@ -98,7 +98,8 @@ constexpr int TH_THREADS = 256, TH_SLOTS = 8, TH_WAVES = TH_THREADS / WAVE;
 
 __global__ __launch_bounds__(TH_THREADS) void k_theta_apply(int64_t n, int64_t k, int64_t lsk, int zeta,
                                                             uint64_t seed, const double* __restrict__ Yt,
-                                                            int64_t ldy, double* __restrict__ S, int64_t lds) {
+                                                            int64_t ldy, double* __restrict__ S, int64_t lds,
+                                                            int64_t row0, int accumulate) {
     __shared__ uint64_t bal[TH_SLOTS][TH_WAVES];
     __shared__ int32_t list[TH_SLOTS * TH_THREADS];
     const int64_t r = blockIdx.x;
@@ -118,7 +119,7 @@ __global__ __launch_bounds__(TH_THREADS) void k_theta_apply(int64_t n, int64_t k
             hit[s] = false;
             neg[s] = false;
             if (i < n) {
-                const uint64_t wd = splitmix64(seed, (uint64_t)i * (uint64_t)zeta + (uint64_t)blk);
+                const uint64_t wd = splitmix64(seed, (uint64_t)(row0 + i) * (uint64_t)zeta + (uint64_t)blk);
                 hit[s] = b0 + (int64_t)(((wd >> 32) * bs) >> 32) == r;
                 neg[s] = (wd & 1ull) != 0;
             }
@@ -160,7 +161,7 @@ __global__ __launch_bounds__(TH_THREADS) void k_theta_apply(int64_t n, int64_t k
         }
         __syncthreads();
     }
-    if (c < k) S[r + c * lds] = acc;
+    if (c < k) S[r + c * lds] = accumulate ? S[r + c * lds] + acc : acc;
 }
 
 __global__ void k_srht_dbits(int64_t n, const float* __restrict__ D, uint32_t* __restrict__ dbits) {
@@ -220,7 +221,15 @@ void launch_theta_apply(int64_t n, int64_t k, uint64_t seed, const double* Yt, i
                         int64_t lds, hipStream_t st) {
     const int64_t lsk = 2 * k;
     dim3 grid((unsigned)lsk, (unsigned)((k + TH_THREADS - 1) / TH_THREADS));
-    k_theta_apply<<<grid, TH_THREADS, 0, st>>>(n, k, lsk, theta_nnz(k), seed, Yt, ldy, S, lds);
+    k_theta_apply<<<grid, TH_THREADS, 0, st>>>(n, k, lsk, theta_nnz(k), seed, Yt, ldy, S, lds, 0, 0);
+}
+
+void launch_theta_apply_rows(int64_t rows, int64_t row0, int64_t k, uint64_t seed, const double* Yt, int64_t ldy,
+                             double* S, int64_t lds, bool accumulate, hipStream_t st) {
+    const int64_t lsk = 2 * k;
+    dim3 grid((unsigned)lsk, (unsigned)((k + TH_THREADS - 1) / TH_THREADS));
+    k_theta_apply<<<grid, TH_THREADS, 0, st>>>(rows, k, lsk, theta_nnz(k), seed, Yt, ldy, S, lds, row0,
+                                                accumulate ? 1 : 0);
 }
 
 void launch_srht_dbits(int64_t n, const float* D, uint32_t* dbits, hipStream_t st) {

@@ -239,6 +239,7 @@ rr_status rr_solve_general(const rr_precond* Pc, int32_t mu_index, const double*
     if (o.method != RR_METHOD_C) {
         RR_REQUIRE(P.l > 0, "R-RandRAND methods need a sketch (l > 0)");
         RR_REQUIRE(!P.joint, "R-RandRAND methods need a single-shift handle");
+        RR_REQUIRE(!P.basisless, "R-RandRAND methods need an explicit basis");
         RR_REQUIRE(P.l <= 4096, "R-RandRAND methods support l <= 4096");
         if (o.method == RR_METHOD_R)
             RR_REQUIRE(std::isfinite(pm.normE) && pm.normE > 0.0,

@@ -346,6 +346,7 @@ extern "C" rr_status rr_solve_batch(const rr_precond* P, const int32_t* mu_index
         RR_REQUIRE(o.history_cap == 0, "relres_history is not supported for batched solves");
         RR_REQUIRE(o.method == RR_METHOD_C && o.krylov == RR_KRYLOV_CG,
                    "batched solves run C-RandRAND PCG (method C, krylov CG)");
+        RR_REQUIRE(!P->basisless, "batched solves need an explicit basis");
         return RR_OK;
     });
     if (v != RR_OK) return v;

@@ -993,3 +993,71 @@ def test_adaptive_sketch_size_matches_oracle(dense_small):
     Po, lo, trail = orr.build_adaptive(op, mu, 8, 256, f=3.0, seed=prob.omega_seed)
     assert l == lo and len(trail) >= 2
     assert abs(P.export(0, with_q=False)["normE"] - Po.normE) <= 1e-8 * Po.normE
+
+
+# ---------------------------------------------------------------- basis-less
+def test_colsample_omega_bit_exact():
+    n, l = 1000, 37
+    prob = workloads.cfg_small_dense(n=n, d=8, l=l)
+    kop = rr.kernel_operator(rr.OP_RBF, _cuda(prob.pts), prob.kconst, prob.scale)
+    P = rr.build_precond(kop, [1e-3], l=l, sketch="colsample", seed=99)
+    assert np.array_equal(P.omega(), orng.colsample_omega(99, n, l))
+    Pb = rr.build_precond(kop, [1e-3], l=l, sketch="colsample", seed=99, basis="less")
+    assert np.array_equal(Pb.omega(), orng.colsample_omega(99, n, l))
+
+
+@pytest.mark.parametrize("reorth", [False, True])
+@pytest.mark.parametrize("orth", ["sketched", "cholqr"])
+def test_basisless_fp64_matches_oracle(orth, reorth):
+    """Algorithm BL_RandRAND_PCG in float64 against the oracle: R, T, G, tau and the
+    implicit Q (formed on export), with Y streamed over several row blocks (n = 12,000,
+    l = 200); PCG iterations and relres against the oracle's run."""
+    prob = workloads.cfg_kernel_ridge(n=12_000, d=8, l=200)
+    mu = prob.mus[0]
+    op = Operator.from_problem(prob)
+    kop = rr.kernel_operator(rr.OP_RBF, _cuda(prob.pts), prob.kconst, prob.scale)
+    P = rr.build_precond(kop, [mu], l=prob.l, sketch="colsample", seed=prob.omega_seed, basis="less",
+                         orth=orth, reorth=reorth, prec="fp64")
+    g = P.export(0)
+    o = orr.build_basisless(op, mu, prob.l, "colsample", prob.omega_seed, reorth=reorth)
+    if orth == "cholqr":
+        ex = orr.build(op, [mu], prob.l, "colsample", prob.omega_seed, orth=orr.CHOLQR, reorth=reorth)[0]
+        o_R, o_G, o_T, o_tau, o_Q = ex.R, ex.G, ex.T, ex.tau, ex.Q
+    else:
+        o_R, o_G, o_T, o_tau, o_Q = o.R, o.G, o.T, o.tau, o.Q
+    rel = lambda a, b_: np.linalg.norm(a - b_) / np.linalg.norm(b_)
+    assert rel(g["R"], o_R) < 1e-9 and rel(g["G"], o_G) < 1e-8 and rel(g["Q"], o_Q) < 1e-9
+    assert np.abs(g["T"] - o_T).max() < 1e-10
+    assert abs(g["tau"] - o_tau) < 1e-8 * o_tau
+    x, info = P.solve(_cuda(prob.b), tol=1e-9)
+    Pref = o if orth == "sketched" else ex
+    ref = osol.pcg(op.shifted(mu), Pref.apply, prob.b, 1e-9)
+    rel64 = osol.relres(op.shifted(mu), x.cpu().numpy(), prob.b)
+    assert info["rc"] == rr.RR_OK and rel64 <= 1e-9 * 1.0001 and rel64 <= ref.relres + 1e-8
+    assert abs(info["iters"] - ref.iters) <= max(2, int(0.03 * ref.iters)), (info["iters"], ref.iters)
+
+
+def test_basisless_fp32_kernel_ridge_solve():
+    """Basis-less float32-class handle at n = 20,000, l = 500 (no n x l basis stored):
+    float64 relres <= tol with refinement; C-RandRAND MINRES on it as well; iteration
+    counts near the explicit-basis handle on the same column sample."""
+    prob = workloads.cfg_kernel_ridge(n=20_000, d=16, l=500)
+    mu = prob.mus[0]
+    op = Operator.from_problem(prob)
+    kop = rr.kernel_operator(rr.OP_RBF, _cuda(prob.pts), prob.kconst, prob.scale)
+    kw = dict(l=prob.l, sketch="colsample", seed=prob.omega_seed, prec="fp32")
+    Pb = rr.build_precond(kop, [mu], basis="less", **kw)
+    Pe = rr.build_precond(kop, [mu], **kw)
+    b = _cuda(prob.b)
+    xb, ib = Pb.solve(b, tol=prob.tol)
+    xe, ie = Pe.solve(b, tol=prob.tol)
+    for x, info in ((xb, ib), (xe, ie)):
+        assert info["rc"] == rr.RR_OK
+        assert osol.relres(op.shifted(mu), x.cpu().numpy(), prob.b) <= prob.tol
+    assert abs(ib["iters"] - ie["iters"]) <= max(3, int(0.15 * ie["iters"]))
+    xm, im = Pb.solve(b, tol=prob.tol, krylov="minres")
+    assert im["rc"] == rr.RR_OK and osol.relres(op.shifted(mu), xm.cpu().numpy(), prob.b) <= prob.tol
+    with pytest.raises(rr.RRError):
+        Pb.solve(b, method="r")
+    with pytest.raises(rr.RRError):
+        Pb.solve_batch(torch.stack([b, b], 1), [0, 0])
