@@ -128,8 +128,24 @@ typedef enum { RR_TAU_OPT = 0, RR_TAU_RHO = 1, RR_TAU_NYS = 2 } rr_tau_rule;
  */
 typedef enum { RR_METHOD_C = 0, RR_METHOD_R = 1, RR_METHOD_SPLIT_R = 2 } rr_method;
 /* Krylov method: CG (Hestenes-Stiefel) or MINRES (Paige-Saunders, preconditioned for
- * method C), both restarted after each residual drop by restart_eta. */
-typedef enum { RR_KRYLOV_CG = 0, RR_KRYLOV_MINRES = 1 } rr_krylov;
+ * method C), both restarted after each residual drop by restart_eta.
+ * BLOCK_MINRES / BLOCK_CG (rr_solve_batch with method C only): the columns under one
+ * shift are solved together, in groups of at most RR_BLOCK_MAX columns (in column
+ * order), over the block Krylov space of the preconditioned operator, with every
+ * stored Krylov block reorthogonalised twice per step (Section 7.2.2: block
+ * preconditioned MINRES with Krylov basis reorthogonalisation).  BLOCK_MINRES
+ * minimises each column's residual in the norm of P (block Lanczos in that inner
+ * product, block QR of the band matrix); BLOCK_CG takes the Galerkin step with
+ * A_mu-orthonormal direction blocks.  A group converges when
+ * max_i ||b_i - A_mu x_i|| / ||b_i|| <= tol; a restart keeps only the columns not yet
+ * at tol; a cycle also ends after block_kmax steps (its stored blocks).  iters counts
+ * block steps (one operator product per group block).  A group whose residual block
+ * is not numerically full rank at a cycle start (a Cholesky pivot c_jj^2 <= 1e-20 S_jj
+ * of its Gram matrix, e.g. equal or dependent right-hand sides) stops with
+ * RR_EBREAKDOWN for its unconverged columns. */
+#define RR_BLOCK_MAX 32
+typedef enum { RR_KRYLOV_CG = 0, RR_KRYLOV_MINRES = 1, RR_KRYLOV_BLOCK_MINRES = 2,
+               RR_KRYLOV_BLOCK_CG = 3 } rr_krylov;
 
 /*
  * Several shifts in one handle (Section 5.1).
@@ -181,7 +197,11 @@ typedef struct {
                              ms_solve); with refinement on, or in FP64, the final true
                              residual is already the float64 one; 0: skip             */
     int32_t method;       /* rr_method (default C); rr_solve_batch runs C only           */
-    int32_t krylov;       /* rr_krylov (default CG); rr_solve_batch runs CG only         */
+    int32_t krylov;       /* rr_krylov (default CG); rr_solve takes CG or MINRES,
+                             rr_solve_batch CG, BLOCK_MINRES or BLOCK_CG               */
+    int32_t block_kmax;   /* block solvers: steps per cycle, i.e. Krylov blocks kept for
+                             reorthogonalisation (2 x (block_kmax + 1) n x s float64
+                             blocks per group); default 128                           */
 } rr_solve_opts;
 
 typedef struct {

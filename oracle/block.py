@@ -27,7 +27,8 @@ preconditioned operator (P spd, C-RandRAND) and reorthogonalise in full.
 * solve_block   restarted driver (Algorithm RandRAND_PCG step 10 with eta): each
       cycle starts from the true residual block, keeps only the columns not yet at
       tol, and runs until every kept column i has ||r_i|| <= max(eta ||r_i^0||,
-      tol ||b_i||).  Columns are solved in groups of at most `group` (in order).
+      tol ||b_i||), or after kmax steps.  Columns are solved in groups of at most
+      `group` (in order).
 
 A cycle stops with BREAKDOWN when the block it has to normalise is not
 numerically full rank: a Cholesky pivot c_jj with c_jj^2 <= 1e-20 S_jj (the new
@@ -178,7 +179,7 @@ def block_cg_cycle(op: Callable, prec: Callable, R0: np.ndarray, targets: np.nda
 CYCLES = {"minres": block_minres_cycle, "cg": block_cg_cycle}
 
 
-def _solve_group(Amu, Atrue, prec, B, tol, cycle, eta, maxit, reorth):
+def _solve_group(Amu, Atrue, prec, B, tol, cycle, eta, maxit, reorth, kmax):
     n, m = B.shape
     X = np.zeros_like(B)
     nb = _cols(B)
@@ -201,7 +202,7 @@ def _solve_group(Amu, Atrue, prec, B, tol, cycle, eta, maxit, reorth):
         rn = rel * safe
         targets = np.maximum(eta * rn[act], tol * nb[act])
         cycles += 1
-        c = cycle(Amu, prec, Rt[:, act], targets, maxit - its, reorth)
+        c = cycle(Amu, prec, Rt[:, act], targets, min(maxit - its, kmax or maxit), reorth)
         X[:, act] += c.Y
         its += c.its
         done = rel.copy()
@@ -217,12 +218,13 @@ def _solve_group(Amu, Atrue, prec, B, tol, cycle, eta, maxit, reorth):
 
 def solve_block(Amu: Callable, prec: Callable, B: np.ndarray, tol: float, method: str = "minres",
                 eta: float = 1e-2, maxit: int = 5000, group: int = 32, reorth: bool = True,
-                Amu_true: Optional[Callable] = None) -> BlockResult:
+                Amu_true: Optional[Callable] = None, kmax: Optional[int] = None) -> BlockResult:
     """Block MINRES or block CG on A_mu X = B (columns in groups of `group`).
 
     Amu and prec act on n x s blocks; Amu_true (default Amu) gives the residual
     at every restart.  iters counts block iterations (one product with A_mu per
-    block of columns)."""
+    block of columns).  kmax: steps per cycle (a cycle that reaches it restarts
+    from the true residual); None: no limit."""
     cycle = CYCLES[method]
     n, m = B.shape
     X = np.zeros_like(B)
@@ -234,7 +236,7 @@ def solve_block(Amu: Callable, prec: Callable, B: np.ndarray, tol: float, method
     for g0 in range(0, m, group):
         g1 = min(g0 + group, m)
         Xg, its, rs, rel, st, h = _solve_group(Amu, Amu_true or Amu, prec, B[:, g0:g1], tol, cycle,
-                                              eta, maxit, reorth)
+                                              eta, maxit, reorth, kmax)
         X[:, g0:g1] = Xg
         iters[g0:g1] = its
         restarts[g0:g1] = rs

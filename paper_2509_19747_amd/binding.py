@@ -33,9 +33,11 @@ _PREC = {"fp64": PREC_FP64, "fp32": PREC_FP32, "mixed": PREC_MIXED}
 _TAU = {"opt": TAU_OPT, "rho": TAU_RHO, "nys": TAU_NYS}
 _ORTH = {"sketched": ORTH_SKETCHED_CHOLQR, "cholqr": ORTH_CHOLQR}
 METHOD_C, METHOD_R, METHOD_SPLIT_R = 0, 1, 2
-KRYLOV_CG, KRYLOV_MINRES = 0, 1
+KRYLOV_CG, KRYLOV_MINRES, KRYLOV_BLOCK_MINRES, KRYLOV_BLOCK_CG = 0, 1, 2, 3
 _METHOD = {"c": METHOD_C, "r": METHOD_R, "split": METHOD_SPLIT_R}
-_KRYLOV = {"cg": KRYLOV_CG, "minres": KRYLOV_MINRES}
+_KRYLOV = {"cg": KRYLOV_CG, "minres": KRYLOV_MINRES, "block_minres": KRYLOV_BLOCK_MINRES,
+           "block_cg": KRYLOV_BLOCK_CG}
+BLOCK_MAX = 32
 
 
 class rr_operator(C.Structure):
@@ -57,7 +59,7 @@ class rr_solve_opts(C.Structure):
                 ("check_every", C.c_int32), ("fp64_ir", C.c_int32),
                 ("relres_history", C.POINTER(C.c_double)), ("history_cap", C.c_int32),
                 ("use_graph", C.c_int32), ("certify", C.c_int32), ("method", C.c_int32),
-                ("krylov", C.c_int32)]
+                ("krylov", C.c_int32), ("block_kmax", C.c_int32)]
 
 
 class rr_solve_info(C.Structure):
@@ -242,7 +244,8 @@ def build_opts(l=0, sketch="gaussian", seed=0, orth="sketched", prec="fp64", tau
 
 
 def solve_opts(tol=1e-6, restart_eta=1e-2, maxit=5000, check_every=8, fp64_ir=-1,
-               use_graph=False, certify=True, history=None, method="c", krylov="cg") -> rr_solve_opts:
+               use_graph=False, certify=True, history=None, method="c", krylov="cg",
+               block_kmax=128) -> rr_solve_opts:
     o = rr_solve_opts()
     lib().rr_solve_opts_default(C.byref(o))
     o.tol = float(tol)
@@ -254,6 +257,7 @@ def solve_opts(tol=1e-6, restart_eta=1e-2, maxit=5000, check_every=8, fp64_ir=-1
     o.certify = 1 if certify else 0
     o.method = _METHOD[method] if isinstance(method, str) else int(method)
     o.krylov = _KRYLOV[krylov] if isinstance(krylov, str) else int(krylov)
+    o.block_kmax = int(block_kmax)
     if history is not None:
         o.relres_history = history.ctypes.data_as(C.POINTER(C.c_double))
         o.history_cap = len(history)

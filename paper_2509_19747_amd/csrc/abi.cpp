@@ -386,6 +386,7 @@ void rr_solve_opts_default(rr_solve_opts* o) {
     o->history_cap = 0;
     o->use_graph = 0;
     o->certify = 1;
+    o->block_kmax = 128;
 }
 
 const char* rr_status_string(rr_status s) {

@@ -1,0 +1,188 @@
+// Column-block products shared by the batched and block solvers: the operator
+// product A_mu P for every column (each column under its own shift), the
+// C-RandRAND preconditioner P R for every column, GEMMs on the solve stream and
+// fixed-order column dots.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "ctx.hpp"
+
+namespace rr {
+
+constexpr int64_t KMULTI_MAX = 32;
+
+struct Batch {
+    const rr_precond& P;
+    hipStream_t st;
+    int64_t n, m, kb;
+    Alloc alloc;          // the handle's allocator, ordered on the solve stream
+    const Alloc* al;
+    DBuf R, Pm, Z, W, T, parts, C, Dall, D, state, start, target2, mucol, muidx, gws;
+    DBuf kws, kdot;       // symmetric multi-column kernel matvec (few columns)
+    bool kmulti = false;
+    DBuf cpart, dcols, rzp;   // projection through the basis, groups of up to 8 columns
+    int pmax = 0, gch = 1;
+    DBuf rrp;                 // block partials of ||r_j||^2 from the x, r update
+    DBuf cnt;                 // per-column block counters of the fused updates (2 m int32)
+    bool single = false;      // every column under one shift mu1
+    double mu1 = 0.0;
+    size_t gwsd = 0;
+    std::vector<int> mus_used;
+    int nch = 1;
+
+    Batch(const rr_precond& p, hipStream_t s, int64_t mcols)
+        : P(p), st(s), n(p.n), m(mcols), kb(p.kb), alloc(p.alloc), al(&alloc) {
+        alloc.st = s;
+        const size_t nm = (size_t)n * m * sizeof(double);
+        R.reset(al, nm); Pm.reset(al, nm); Z.reset(al, nm); W.reset(al, nm); T.reset(al, nm);
+        nch = coldot_chunks(n);
+        parts.reset(al, (size_t)nch * m * sizeof(double));
+        if (kb > 0) {
+            C.reset(al, (size_t)kb * m * sizeof(double));
+            D.reset(al, (size_t)kb * m * sizeof(double));
+            Dall.reset(al, (size_t)p.per.size() * kb * m * sizeof(double));
+        }
+        state.reset(al, (size_t)m * sizeof(BState));
+        start.reset(al, (size_t)m * sizeof(int32_t));
+        target2.reset(al, (size_t)m * sizeof(double));
+        mucol.reset(al, (size_t)m * sizeof(double));
+        muidx.reset(al, (size_t)m * sizeof(int32_t));
+        gwsd = std::max<size_t>((size_t)8 * std::max<int64_t>(kb, 1) * m, (size_t)1 << 20);
+        gws.reset(al, gwsd * sizeof(double));
+        // a few columns: the symmetric matvec kernel (each entry formed once per
+        // group of up to 8 columns, float64 sums) beats a 128-column MFMA tile
+        kmulti = is_kernel(p.op) && p.opts.prec != RR_PREC_FP64 && m <= KMULTI_MAX;
+        if (kmulti) {
+            kws.reset(al, (kernel_matvec_ws_doubles(n, p.op.d, (int)std::min<int64_t>(m, 8)) + 1) * sizeof(double));
+            kdot.reset(al, (size_t)kernel_matvec_blocks(n) * m * sizeof(double));
+        }
+        rrp.reset(al, (size_t)bxr_blocks(n) * m * sizeof(double));
+        cnt.reset(al, (size_t)2 * m * sizeof(int32_t));
+        RR_HIP(hipMemsetAsync(state.ptr(), 0, (size_t)m * sizeof(BState), st));
+        RR_HIP(hipMemsetAsync(cnt.ptr(), 0, (size_t)2 * m * sizeof(int32_t), st));
+    }
+
+    // Few columns under one shift: the projection is a streaming pass over Qb per
+    // group of columns (Qb^T R, the core, R + Qb D) rather than GEMMs, which cuts
+    // the launches per iteration.  Group width limited by the qd kernel's LDS
+    // (D of the group plus its partial sums within 64 KiB).
+    // A single shift also folds mu into the kernel product, whose block partials
+    // of p_j^T w_j then serve alpha, and the projection's partials of r_j^T z_j
+    // serve beta (no separate column dots).
+    void setup_single_shift() {
+        if (mus_used.size() != 1) return;
+        single = true;
+        mu1 = P.per[mus_used[0]].mu;
+        if (kb == 0 || m > KMULTI_MAX) return;
+        pmax = kb <= 768 ? 8 : kb <= 1792 ? 4 : 0;
+        if (pmax == 0) return;
+        gch = gemv_t_chunks(n, kb);
+        cpart.reset(al, (size_t)pmax * gch * kb * sizeof(double));
+        dcols.reset(al, (size_t)pmax * kb * sizeof(double));
+        rzp.reset(al, (size_t)m * qd_blocks(n) * sizeof(double));
+    }
+
+    void gemm(bool ta, bool tb, int64_t M, int64_t N, int64_t K, const void* A, int64_t lda,
+              const void* B, int64_t ldb, double* Cm, int64_t ldc, double alpha, double beta,
+              int dta = DT_F64) {
+        launch_gemm(dta, ta, DT_F64, tb, M, N, K, A, lda, B, ldb, Cm, ldc, alpha, beta, gws.as<double>(), gwsd, st);
+    }
+
+    // Wout = A_mu Pin for every column (fp64: float64 operator).  Returns the block
+    // partials of Pin_j^T Wout_j when the product produced them (nch = 0 otherwise).
+    ColParts matmat(const double* Pin, int64_t ldp, double* Wout, bool fp64) {
+        if (kmulti && fp64 && ldp == n) {
+            // a few columns under the float64 operator: the pair-once float64 matvec,
+            // two columns per pass
+            const KernelOp k = kernel_op_of(P);
+            launch_kernel_matvec_multi(k, true, Pin, (int)m, 0.0, Wout, kdot.as<double>(), kws.as<double>(),
+                                       nullptr, st);
+            launch_add_shift_cols(n, m, mucol.as<double>(), Pin, ldp, Wout, n, st);
+            return ColParts{nullptr, 0, 0, 0};
+        }
+        if (kmulti && !fp64 && ldp == n) {
+            const KernelOp k = kernel_op_of(P);
+            const int nblk = kernel_matvec_blocks(n);
+            launch_kernel_matvec_multi(k, false, Pin, (int)m, single ? mu1 : 0.0, Wout, kdot.as<double>(),
+                                       kws.as<double>(), nullptr, st);
+            if (single) return ColParts{kdot.as<double>(), nblk, 1, nblk};
+            launch_add_shift_cols(n, m, mucol.as<double>(), Pin, ldp, Wout, n, st);
+            return ColParts{nullptr, 0, 0, 0};
+        }
+        if (is_kernel(P.op)) {
+            const KernelOp k = kernel_op_of(P);
+            launch_kernel_matmat_f64(k, fp64 || P.opts.prec == RR_PREC_FP64, mucol.as<double>(), Pin, ldp, m,
+                                     Wout, n, st);
+        } else {
+            if (!fp64 && P.A32.ptr()) gemm(false, false, n, m, n, P.A32.ptr(), n, Pin, ldp, Wout, n, 1.0, 0.0, DT_F32);
+            else gemm(false, false, n, m, n, P.op.A, P.op.lda, Pin, ldp, Wout, n, 1.0, 0.0);
+            launch_add_shift_cols(n, m, mucol.as<double>(), Pin, ldp, Wout, n, st);
+        }
+        return ColParts{nullptr, 0, 0, 0};
+    }
+
+    // Zout = P_{mu(j)} Rin for every column.  Returns the block partials of
+    // Rin_j^T Zout_j when the projection produced them (nch = 0 otherwise).
+    ColParts precond(const double* Rin, double* Zout) {
+        const double* Qb = P.Qb.as<double>();
+        if (pmax > 0) {
+            const double* Kc = P.per[mus_used[0]].Kc.as<double>();
+            const int nb = qd_blocks(n);
+            for (int64_t c0 = 0; c0 < m;) {
+                const int64_t left = m - c0;
+                const int nr = left >= pmax ? pmax : left >= 4 ? 4 : left >= 2 ? 2 : 1;
+                launch_gemv_t_multi(nr, n, kb, Qb, n, Rin + c0 * n, n, cpart.as<double>(), gch, nullptr, st);
+                launch_core_apply_cols(kb, Kc, kb, cpart.as<double>(), gch, nr, dcols.as<double>(), st);
+                launch_qd_multi(nr, n, kb, Qb, n, dcols.as<double>(), Rin + c0 * n, n, 1.0, 1.0, Zout + c0 * n,
+                                rzp.as<double>() + c0 * nb, nullptr, st);
+                c0 += nr;
+            }
+            return ColParts{rzp.as<double>(), nb, 1, nb};
+        }
+        launch_copy_mat(DT_F64, Rin, n, DT_F64, Zout, n, n, m, st);
+        if (kb == 0) return ColParts{nullptr, 0, 0, 0};
+        gemm(true, false, kb, m, n, Qb, n, Rin, n, C.as<double>(), kb, 1.0, 0.0);
+        for (int g : mus_used)
+            gemm(false, false, kb, m, kb, P.per[g].Kc.ptr(), kb, C.ptr(), kb,
+                 Dall.as<double>() + (size_t)g * kb * m, kb, 1.0, 0.0);
+        launch_select_cols(kb, m, Dall.as<double>(), muidx.as<int32_t>(), D.as<double>(), st);
+        gemm(false, false, n, m, kb, Qb, n, D.ptr(), kb, Zout, n, 1.0, 1.0);
+        return ColParts{nullptr, 0, 0, 0};
+    }
+
+    // per-column sums of A_j^T B_j on the host (fixed order)
+    std::vector<double> coldots(const double* A, int64_t lda, const double* B, int64_t ldb) {
+        launch_coldot(n, m, A, lda, B, ldb, parts.as<double>(), st);
+        std::vector<double> h((size_t)nch * m), out((size_t)m, 0.0);
+        RR_HIP(hipMemcpyAsync(h.data(), parts.ptr(), h.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+        RR_HIP(hipStreamSynchronize(st));
+        for (int64_t j = 0; j < m; ++j)
+            for (int c = 0; c < nch; ++c) out[j] += h[(size_t)c * m + j];
+        return out;
+    }
+
+    void iteration(double* X, int64_t ldx) {
+        BState* s = state.as<BState>();
+        double* r = R.as<double>();
+        double* p = Pm.as<double>();
+        double* w = W.as<double>();
+        double* z = Z.as<double>();
+        double* pp = parts.as<double>();
+        const ColParts own{pp, nch, m, 1};
+        int32_t* c = cnt.as<int32_t>();
+        ColParts pw = matmat(p, n, w, false);
+        if (!pw.p) { launch_coldot(n, m, p, n, w, n, pp, st); pw = own; }
+        launch_bxr_fused(n, m, X, ldx, r, p, w, s, pw, rrp.as<double>(), c, st);
+        ColParts rz = precond(r, z);
+        if (!rz.p) { launch_coldot(n, m, r, n, z, n, pp, st); rz = own; }
+        launch_bp_fused(n, m, z, p, s, rz, c + m, st);
+    }
+};
+
+
+}  // namespace rr

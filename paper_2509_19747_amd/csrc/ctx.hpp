@@ -239,3 +239,6 @@ void require_device();
 rr_status rr_solve_batch_fused(const rr_precond* P, const int32_t* mu_index_per_col,
                                const double* B, int64_t ldb, int32_t nrhs, double* X, int64_t ldx,
                                const rr_solve_opts* o, rr_solve_info* infos, void* hip_stream);
+rr_status rr_solve_block(const rr_precond* P, const int32_t* mu_index_per_col, const double* B, int64_t ldb,
+                         int32_t nrhs, double* X, int64_t ldx, const rr_solve_opts* o, rr_solve_info* infos,
+                         void* hip_stream);

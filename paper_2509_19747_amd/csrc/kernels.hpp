@@ -108,6 +108,29 @@ void launch_scale_mat(double* A, int64_t lda, int64_t rows, int64_t cols, double
 // max |A^T A - I| style check: out = max_ij |M_ij - delta_ij| (one double on device)
 void launch_max_abs_minus_identity(const double* M, int64_t l, int64_t ldm, double* out, hipStream_t st);
 
+// ------------------------------------------------- block Krylov solvers
+// Right-hand sides per block of block MINRES / block CG (small matrices s x s,
+// column-major, leading dimension s).
+constexpr int BLOCK_MAX_S = 32;
+// S = C^T C (S symmetrised first), C upper and C^{-1}; *flag = 1 (C, C^{-1} zero)
+// when a pivot fails c_jj^2 > 1e-20 S_jj.
+void launch_blk_chol(int s, const double* S, double* C, double* Ci, int32_t* flag, hipStream_t st);
+// One block-QR step of block MINRES (see kernels_block.hip); G slots 2s x 2s.
+void launch_bmr_qr(int s, int k, const double* M, const double* Cprev, const double* Cnew, const int32_t* brk,
+                   const double* Gm2, const double* Gm1, double* Gk, double* phibar, double* R2, double* R1,
+                   double* Rinv, double* phi, hipStream_t st);
+// D_k = (Z - D1 R1 - D2 R2) Rinv, ADk likewise from U, Y += D_k phi, Rres -= ADk phi
+// (D1/AD1, D2/AD2 may be null: zero blocks).  n x s blocks, leading dimension n.
+void launch_bmr_rows(int64_t n, int s, const double* Z, const double* U, const double* D1, const double* D2,
+                     const double* AD1, const double* AD2, const double* R1, const double* R2,
+                     const double* Rinv, const double* phi, double* Dk, double* ADk, double* Y, double* Rres,
+                     hipStream_t st);
+// dst(:, j) = src(:, idx[j]);  dst(:, idx[j]) (+)= src(:, j)
+void launch_blk_gather(int64_t n, int s, const double* src, int64_t lds, const int32_t* idx, double* dst,
+                       hipStream_t st);
+void launch_blk_scatter(int64_t n, int s, const double* src, const int32_t* idx, double* dst, int64_t ldd,
+                        bool add, hipStream_t st);
+
 // ------------------------------------------------------- factorizations
 // In-place upper Cholesky of an l x l spd matrix (A = R^T R, R stored in the upper
 // triangle, lower part zeroed).  *status (device int) is set non-zero on failure.

@@ -143,7 +143,8 @@ static rr_status validate_solve(const rr_precond* P, const rr_solve_opts& o) {
     RR_REQUIRE(o.history_cap >= 0, "history_cap must be >= 0");
     RR_REQUIRE(o.history_cap == 0 || o.relres_history != nullptr, "relres_history is null");
     RR_REQUIRE(o.method >= RR_METHOD_C && o.method <= RR_METHOD_SPLIT_R, "unknown method");
-    RR_REQUIRE(o.krylov == RR_KRYLOV_CG || o.krylov == RR_KRYLOV_MINRES, "unknown Krylov method");
+    RR_REQUIRE(o.krylov >= RR_KRYLOV_CG && o.krylov <= RR_KRYLOV_BLOCK_CG, "unknown Krylov method");
+    RR_REQUIRE(o.block_kmax >= 1 && o.block_kmax <= 4096, "block_kmax must be in [1, 4096]");
     return RR_OK;
 }
 
@@ -162,6 +163,8 @@ extern "C" rr_status rr_solve(const rr_precond* Pc, int32_t mu_index, const doub
         validate_solve(Pc, o);
         RR_REQUIRE(mu_index >= 0 && mu_index < (int32_t)Pc->per.size(), "mu_index out of range");
         RR_REQUIRE(b != nullptr && x != nullptr, "b or x is null");
+        RR_REQUIRE(o.krylov == RR_KRYLOV_CG || o.krylov == RR_KRYLOV_MINRES,
+                   "rr_solve runs CG or MINRES (block methods: rr_solve_batch)");
         require_device();
         rr_precond& P = const_cast<rr_precond&>(*Pc);
         hipStream_t st = (hipStream_t)hip_stream;
@@ -344,11 +347,13 @@ extern "C" rr_status rr_solve_batch(const rr_precond* P, const int32_t* mu_index
             RR_REQUIRE(mu_index_per_col[j] >= 0 && mu_index_per_col[j] < (int32_t)P->per.size(),
                        "mu index out of range");
         RR_REQUIRE(o.history_cap == 0, "relres_history is not supported for batched solves");
-        RR_REQUIRE(o.method == RR_METHOD_C && o.krylov == RR_KRYLOV_CG,
-                   "batched solves run C-RandRAND PCG (method C, krylov CG)");
+        RR_REQUIRE(o.method == RR_METHOD_C && o.krylov != RR_KRYLOV_MINRES,
+                   "batched solves run C-RandRAND with CG, BLOCK_MINRES or BLOCK_CG");
         RR_REQUIRE(!P->basisless, "batched solves need an explicit basis");
         return RR_OK;
     });
     if (v != RR_OK) return v;
+    if (o.krylov == RR_KRYLOV_BLOCK_MINRES || o.krylov == RR_KRYLOV_BLOCK_CG)
+        return rr_solve_block(P, mu_index_per_col, B, ldb, nrhs, X, ldx, &o, infos, hip_stream);
     return rr_solve_batch_fused(P, mu_index_per_col, B, ldb, nrhs, X, ldx, &o, infos, hip_stream);
 }

@@ -16,6 +16,7 @@ import pytest
 import workloads
 from oracle import randrand as orr
 from oracle import rng as orng
+from oracle import block as oblk
 from oracle import solvers as osol
 from oracle.operators import Operator
 
@@ -1061,3 +1062,126 @@ def test_basisless_fp32_kernel_ridge_solve():
         Pb.solve(b, method="r")
     with pytest.raises(rr.RRError):
         Pb.solve_batch(torch.stack([b, b], 1), [0, 0])
+
+
+# ------------------------------------------------------------ block solvers
+@pytest.mark.parametrize("method", ["minres", "cg"])
+def test_block_solvers_match_oracle(method):
+    """Block preconditioned MINRES / block CG in float64 against the oracle: six
+    right-hand sides (one zero) under one shift, then eleven under two shifts of a
+    joint-basis handle (groups per shift); solutions, block iterations and the
+    per-column residuals."""
+    prob = workloads.cfg_batched(n=2500, d=16, l=60, nrhs=11)
+    op = Operator.from_problem(prob)
+    kop = rr.kernel_operator(rr.OP_RBF, _cuda(prob.pts), prob.kconst, prob.scale)
+    mus = prob.mus[1:3]
+    P = rr.build_precond(kop, mus, l=prob.l, sketch="srht", seed=prob.omega_seed, prec="fp64")
+    tol = 1e-9
+    B = prob.B[:, :6].copy()
+    B[:, 3] = 0.0
+    X, infos, st = P.solve_batch(_cuda(B), [0] * 6, tol=tol, krylov="block_" + method)
+    X = X.cpu().numpy()
+    assert st == rr.RR_OK
+    Po = orr.build(op, mus, prob.l, "srht", prob.omega_seed)
+    ref = oblk.solve_block(op.shifted(mus[0]), Po[0].apply, B, tol, method=method)
+    assert ref.status == osol.OK
+    assert np.all(X[:, 3] == 0.0)
+    for c in range(6):
+        assert infos[c]["status"] == rr.RR_OK
+        if c == 3:
+            assert infos[c]["relres_work"] == 0.0
+            continue
+        rel64 = osol.relres(op.shifted(mus[0]), X[:, c], B[:, c])
+        assert rel64 <= tol * 1.0001
+        # two float64 evaluations of b - A x in different summation orders differ by
+        # about n u (||A|| ||x|| / ||b|| + 1), ~1e-12 here
+        assert abs(infos[c]["relres_fp64"] - rel64) <= 1e-12
+        assert abs(infos[c]["iters"] - ref.iters[c]) <= 1, (infos[c]["iters"], ref.iters[c])
+    xs = np.linalg.solve(op.to_dense() + mus[0] * np.eye(prob.n), B)
+    assert np.linalg.norm(X - xs) <= 1e-6 * np.linalg.norm(xs)
+    # two shifts, columns interleaved: each shift's columns form their own group
+    idx = [j % 2 for j in range(11)]
+    X2, inf2, st = P.solve_batch(_cuda(prob.B), idx, tol=tol, krylov="block_" + method)
+    X2 = X2.cpu().numpy()
+    assert st == rr.RR_OK
+    for g in (0, 1):
+        cols = [c for c in range(11) if idx[c] == g]
+        rg = oblk.solve_block(op.shifted(mus[g]), Po[g].apply, prob.B[:, cols], tol, method=method)
+        for k, c in enumerate(cols):
+            assert inf2[c]["status"] == rr.RR_OK
+            assert osol.relres(op.shifted(mus[g]), X2[:, c], prob.B[:, c]) <= tol * 1.0001
+            assert abs(inf2[c]["iters"] - rg.iters[k]) <= 1
+        assert len({inf2[c]["iters"] for c in cols}) == 1
+
+
+def test_block_minres_groups_and_cycle_cap():
+    """40 columns under one shift: groups of 32 and 8 (each group's columns share a
+    count, the 8 alone give the same result), and a cycle cap of 3 block steps
+    (restarts, still converging)."""
+    prob = workloads.cfg_batched(n=3000, d=16, l=60, nrhs=40)
+    op = Operator.from_problem(prob)
+    mu = prob.mus[1]
+    kop = rr.kernel_operator(rr.OP_RBF, _cuda(prob.pts), prob.kconst, prob.scale)
+    P = rr.build_precond(kop, [mu], l=prob.l, sketch="srht", seed=prob.omega_seed, prec="fp64")
+    tol = 1e-8
+    X, infos, st = P.solve_batch(_cuda(prob.B), [0] * 40, tol=tol, krylov="block_minres")
+    X = X.cpu().numpy()
+    assert st == rr.RR_OK
+    assert rr.BLOCK_MAX == 32
+    assert len({i["iters"] for i in infos[:32]}) == 1 and len({i["iters"] for i in infos[32:]}) == 1
+    X8, i8, _ = P.solve_batch(_cuda(prob.B[:, 32:]), [0] * 8, tol=tol, krylov="block_minres")
+    assert np.array_equal(X8.cpu().numpy(), X[:, 32:])
+    assert i8[0]["iters"] == infos[32]["iters"]
+    for c in range(40):
+        assert osol.relres(op.shifted(mu), X[:, c], prob.B[:, c]) <= tol * 1.0001
+    Po = orr.build(op, [mu], prob.l, "srht", prob.omega_seed)[0]
+    Xc, ic, st = P.solve_batch(_cuda(prob.B[:, :5]), [0] * 5, tol=tol, krylov="block_minres", block_kmax=3)
+    assert st == rr.RR_OK and ic[0]["restarts"] >= 2
+    ref = oblk.solve_block(op.shifted(mu), Po.apply, prob.B[:, :5], tol, kmax=3)
+    assert ic[0]["iters"] == ref.iters[0] and ic[0]["restarts"] == ref.restarts[0]
+
+
+def test_block_minres_fp32_ten_rhs():
+    """Ten right-hand sides (the paper's block size for its 10-class problem) on a
+    float32-class handle at n = 20,000: every column at tol in float64 (refinement),
+    fewer block steps than the largest single-column PCG count."""
+    prob = workloads.cfg_kernel_ridge(n=20_000, d=16, l=500)
+    mu = prob.mus[0]
+    op = Operator.from_problem(prob)
+    kop = rr.kernel_operator(rr.OP_RBF, _cuda(prob.pts), prob.kconst, prob.scale)
+    P = rr.build_precond(kop, [mu], l=prob.l, sketch="srht", seed=prob.omega_seed, prec="fp32")
+    rng = np.random.default_rng(5)
+    B = np.sign(rng.standard_normal((prob.n, 10)))
+    for method in ("block_minres", "block_cg"):
+        X, infos, st = P.solve_batch(_cuda(B), [0] * 10, tol=prob.tol, krylov=method)
+        X = X.cpu().numpy()
+        assert st == rr.RR_OK
+        rows = np.random.default_rng(1).choice(prob.n, 64, replace=False)
+        for c in range(10):
+            assert infos[c]["relres_fp64"] <= prob.tol
+        Xp, ip, _ = P.solve_batch(_cuda(B), [0] * 10, tol=prob.tol)
+        assert infos[0]["iters"] <= max(i["iters"] for i in ip)
+        # sampled rows of the float64 residual against the oracle's rows
+        Kr = op.scale * orr_kernel_rows(op, rows)
+        R = B[rows] - (Kr @ X + mu * X[rows])
+        assert np.abs(R).max() <= 10 * prob.tol * np.abs(B).max() * np.sqrt(prob.n)
+
+
+def orr_kernel_rows(op, rows):
+    from oracle.operators import kernel_block
+    return kernel_block(op.kind, op.kconst, op.X[rows], op.X)
+
+
+def test_block_dependent_columns_and_guards():
+    prob = workloads.cfg_batched(n=1500, d=8, l=40, nrhs=3)
+    kop = rr.kernel_operator(rr.OP_RBF, _cuda(prob.pts), prob.kconst, prob.scale)
+    P = rr.build_precond(kop, [prob.mus[1]], l=prob.l, sketch="srht", seed=prob.omega_seed, prec="fp64")
+    B = prob.B.copy()
+    B[:, 2] = 2.0 * B[:, 0]
+    X, infos, st = P.solve_batch(_cuda(B), [0] * 3, tol=1e-8, krylov="block_minres",
+                                 ok=(rr.RR_OK, rr.RR_EBREAKDOWN))
+    assert st == rr.RR_EBREAKDOWN and all(i["status"] == rr.RR_EBREAKDOWN for i in infos)
+    with pytest.raises(rr.RRError):
+        P.solve(_cuda(B[:, 0]), krylov="block_minres")
+    with pytest.raises(rr.RRError):
+        P.solve_batch(_cuda(B), [0] * 3, krylov="block_cg", block_kmax=0)
