@@ -12,7 +12,9 @@
               residual inside a restart cycle and the true residual at each
               restart and at the end.
 * cg          the same loop with P = I (plain CG, Section 1).
-* direct      x* = (A + mu I)^{-1} b by a dense Cholesky solve (LAPACK).
+* direct      x* = (A + mu I)^{-1} b by a dense Cholesky solve (LAPACK);
+              direct_blocked the same factorisation by column panels in the
+              caller's array, for n^2 beyond LP64 LAPACK's 32-bit offsets.
 """
 from __future__ import annotations
 
@@ -115,6 +117,47 @@ def direct(A_dense: np.ndarray, mu: float, b: np.ndarray) -> np.ndarray:
     n = A_dense.shape[0]
     c = sla.cho_factor(A_dense + mu * np.eye(n), lower=False)
     return sla.cho_solve(c, b)
+
+
+def direct_blocked(A_dense: np.ndarray, mu: float, b: np.ndarray, nb: int = 2048,
+                   log: Optional[Callable[[str], None]] = None) -> np.ndarray:
+    """direct() for a matrix too large for one LAPACK call (an n x n array with
+    n^2 >= 2^31 overflows the 32-bit element offsets of LP64 LAPACK): the same
+    Cholesky factorisation A + mu I = L L^T, right-looking by column panels of nb
+    (LAPACK on each nb x nb diagonal block, triangular solves for the panel below
+    it, the trailing lower triangle updated by GEMMs in row chunks), then the two
+    triangular solves by the same panels.  Works in the caller's row-major array,
+    whose lower triangle holds L afterwards."""
+    n = A_dense.shape[0]
+    A = A_dense
+    A[np.diag_indices_from(A)] += mu
+    for k0 in range(0, n, nb):
+        k1 = min(k0 + nb, n)
+        L11 = np.linalg.cholesky(A[k0:k1, k0:k1])
+        A[k0:k1, k0:k1] = L11
+        if k1 < n:
+            # L21 = A21 L11^{-T}
+            A[k1:, k0:k1] = sla.solve_triangular(L11, A[k1:, k0:k1].T, lower=True).T
+            L21 = A[k1:, k0:k1]
+            for r0 in range(k1, n, nb):
+                r1 = min(r0 + nb, n)
+                # rows r0..r1 of the trailing block, columns k1..r1 (lower part)
+                A[r0:r1, k1:r1] -= L21[r0 - k1:r1 - k1] @ L21[:r1 - k1].T
+        if log:
+            log(f"panel {k0 // nb + 1} of {(n + nb - 1) // nb}")
+    y = np.array(b, dtype=np.float64)
+    for k0 in range(0, n, nb):
+        k1 = min(k0 + nb, n)
+        if k0:
+            y[k0:k1] -= A[k0:k1, :k0] @ y[:k0]
+        y[k0:k1] = sla.solve_triangular(A[k0:k1, k0:k1], y[k0:k1], lower=True)
+    x = y
+    for k1 in range(n, 0, -nb):
+        k0 = max(k1 - nb, 0)
+        if k1 < n:
+            x[k0:k1] -= A[k1:, k0:k1].T @ x[k1:]
+        x[k0:k1] = sla.solve_triangular(A[k0:k1, k0:k1], x[k0:k1], lower=True, trans="T")
+    return x
 
 
 def relres(Amu_true: Callable, x: np.ndarray, b: np.ndarray) -> float:

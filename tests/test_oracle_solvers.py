@@ -126,3 +126,17 @@ def test_multi_shift_pcg_all_columns():
             assert res.status == solvers.OK
             xs = solvers.direct(A, mu, p.B[:, j])
             assert np.linalg.norm(res.x - xs) / np.linalg.norm(xs) < 1e-8 / mu * 10
+
+
+def test_direct_blocked_equals_direct():
+    rng = np.random.default_rng(0)
+    M = rng.standard_normal((300, 300))
+    A = M @ M.T / 300
+    b = rng.standard_normal(300)
+    x = solvers.direct(A, 1e-3, b)
+    for nb in (64, 100, 300, 512):
+        work = np.ascontiguousarray(A.copy())
+        xb = solvers.direct_blocked(work, 1e-3, b, nb=nb)
+        assert np.abs(xb - x).max() <= 1e-10 * np.abs(x).max()
+        L = np.tril(work)
+        assert np.abs(L @ L.T - (A + 1e-3 * np.eye(300))).max() <= 1e-13
