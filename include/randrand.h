@@ -167,7 +167,7 @@ typedef struct {
     int32_t prec;         /* rr_precision                                                */
     int32_t tau_rule;     /* rr_tau_rule                                                 */
     double rho;           /* RHO rule factor (default 1.0)                               */
-    int32_t power_iters;  /* power iterations per estimate (default 10)                  */
+    int32_t power_iters;  /* power iterations per estimate (default 4)                   */
     int32_t power_q;      /* q of eq. testmatrix: Omega = A^q X, q in {0, 1} (default 0) */
     int32_t multi_shift;  /* rr_multi_shift for n_mu > 1 (default JOINT)                 */
     int64_t l_max;        /* > l: adaptive sketch size (Section 5.3, eq. ad_criterion):
@@ -474,7 +474,8 @@ rr_status rr_lambda_max(const double* G, int64_t k, uint64_t seed, double* out_h
  * 0 = float32 kernel matvec (first stage), 1 = float32 kernel-GEMM sketch,
  * 2 = float32 dense matvec, 3 = bf16 dense sketch, 4 = projections,
  * 5 = float64 kernel matrix-matrix product of the batched solve, 6 = float64 kernel
- * matvec (first stage; restart residuals of the float64 refinement).
+ * matvec (first stage; restart residuals of the float64 refinement), 7 = float64 dense
+ * matvec.
  */
 void rr_profile_enable(int32_t on);
 rr_status rr_profile_read(int32_t slot, int64_t* count, double* total_ms);

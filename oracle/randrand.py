@@ -242,7 +242,7 @@ def test_matrix(op, sketch: str, seed: int, l: int, q: int = 0, omega_bf16: bool
 
 def build(op, mus: List[float], l: int, sketch: str = "gaussian", seed: int = 0,
           orth: int = SKETCHED_CHOLQR, tau_rule: int = OPT, rho: float = 1.0,
-          power_iters: int = 10, Omega: Optional[np.ndarray] = None,
+          power_iters: int = 4, Omega: Optional[np.ndarray] = None,
           omega_bf16: bool = False, q: int = 0, multi: str = "joint",
           reorth: bool = False) -> List[Precond]:
     """Build one C-RandRAND preconditioner per shift (Algorithm RandRAND_PCG steps 1-4).
@@ -325,7 +325,7 @@ class BasislessPrecond:
 
 
 def build_basisless(op, mu: float, l: int, sketch: str = "colsample", seed: int = 0,
-                    tau_rule: int = OPT, rho: float = 1.0, power_iters: int = 10,
+                    tau_rule: int = OPT, rho: float = 1.0, power_iters: int = 4,
                     reorth: bool = False) -> BasislessPrecond:
     """Algorithm BL_RandRAND_PCG steps 1-3 with the fast Q-less preconditioned Cholesky
     QR (Algorithm prec_chol_qr): S = Theta Y, R_sk = qr(S), the preconditioned Gram
@@ -355,7 +355,7 @@ def build_basisless(op, mu: float, l: int, sketch: str = "colsample", seed: int 
 
 def build_shifted_cholesky(op, mus: List[float], l: int, Omega: np.ndarray, seed: int = 0,
                            orth: int = SKETCHED_CHOLQR, tau_rule: int = OPT, rho: float = 1.0,
-                           power_iters: int = 10, alpha: Optional[float] = None) -> List[Precond]:
+                           power_iters: int = 4, alpha: Optional[float] = None) -> List[Precond]:
     """Several shifts from one orthogonalisation at a fixed shift alpha (Section 5.1,
     shifted Cholesky preconditioning).
 

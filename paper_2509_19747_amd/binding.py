@@ -222,7 +222,7 @@ def kernel_operator(kind: int, pts, kconst: float, scale: float) -> Operator:
 
 
 def build_opts(l=0, sketch="gaussian", seed=0, orth="sketched", prec="fp64", tau_rule="opt",
-               rho=1.0, power_iters=10, q=0, multi="joint", l_max=0, ad_factor=100.0,
+               rho=1.0, power_iters=4, q=0, multi="joint", l_max=0, ad_factor=100.0,
                basis="explicit", reorth=False) -> rr_build_opts:
     o = rr_build_opts()
     lib().rr_build_opts_default(C.byref(o))
@@ -471,7 +471,7 @@ def lambda_max(G, seed: int = 0, stream=None):
 
 
 (PROF_KERNEL_MATVEC, PROF_KERNEL_SKETCH, PROF_DENSE_MATVEC, PROF_DENSE_SKETCH, PROF_PROJECT,
- PROF_KERNEL_MATMAT, PROF_KERNEL_MATVEC64) = range(7)
+ PROF_KERNEL_MATMAT, PROF_KERNEL_MATVEC64, PROF_DENSE_MATVEC64) = range(8)
 
 
 def profile_enable(on: bool = True):

@@ -365,7 +365,7 @@ void rr_build_opts_default(rr_build_opts* o) {
     o->prec = RR_PREC_FP64;
     o->tau_rule = RR_TAU_OPT;
     o->rho = 1.0;
-    o->power_iters = 10;
+    o->power_iters = 4;
     o->power_q = 0;
     o->multi_shift = RR_MULTI_JOINT;
     o->l_max = 0;

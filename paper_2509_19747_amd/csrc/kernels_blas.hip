@@ -427,7 +427,7 @@ void launch_dense_matvec(int dta, int64_t n, const void* A, int64_t lda, const d
                          double mu, double* y, double* dot_part, const int32_t* stop,
                          hipStream_t st) {
     const int g = dense_matvec_blocks(n);
-    ProfScope prof(dta == DT_F32 ? PROF_DENSE_MATVEC : -1, st);
+    ProfScope prof(dta == DT_F32 ? PROF_DENSE_MATVEC : PROF_DENSE_MATVEC64, st);
     if (dta == DT_F32)
         k_dense_matvec<float><<<g, DM_THREADS, 0, st>>>(n, (const float*)A, lda, u, mu, y, dot_part, stop);
     else

@@ -35,7 +35,7 @@ def test_library_exports_every_declared_symbol():
 def test_defaults():
     o = b.rr_build_opts()
     b.lib().rr_build_opts_default(C.byref(o))
-    assert o.l == 0 and o.power_iters == 10 and o.rho == 1.0 and o.tau_rule == b.TAU_OPT
+    assert o.l == 0 and o.power_iters == 4 and o.rho == 1.0 and o.tau_rule == b.TAU_OPT
     s = b.rr_solve_opts()
     b.lib().rr_solve_opts_default(C.byref(s))
     assert s.tol == 1e-6 and s.restart_eta == 1e-2 and s.maxit == 5000 and s.check_every == 8

@@ -10,6 +10,8 @@ Sizes span several kernel tiles with ragged tails (n not a multiple of 64 or
   * float32-entry operators: the float32 rounding of each kernel entry bounds
     the matvec error by ~n * 2^-23 * max|A| per row sum (checked at 2e-6 relative).
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -1185,3 +1187,45 @@ def test_block_dependent_columns_and_guards():
         P.solve(_cuda(B[:, 0]), krylov="block_minres")
     with pytest.raises(rr.RRError):
         P.solve_batch(_cuda(B), [0] * 3, krylov="block_cg", block_kmax=0)
+
+
+XSTAR_PRECISION = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                               "precision_matern32_n65536_xstar.npy")
+
+
+def test_precision_full_size_against_direct_solution():
+    """The precision workload at its full size (stored dense Matern-3/2, n = 65,536,
+    l = 1024, mu = 1e-5, tol 1e-10, mixed precision with float64 refinement):
+    float64 relres <= tol over the whole residual, 64 sampled residual rows against
+    the oracle's kernel formula, and the forward error against the stored direct
+    solution x* (the oracle's float64 Cholesky solve) within ||A_mu (x - x*)|| / mu."""
+    prob = workloads.cfg_precision()
+    n, mu, tol = prob.n, prob.mus[0], prob.tol
+    xs = np.load(XSTAR_PRECISION)
+    kop = rr.kernel_operator(rr.OP_MATERN32, _cuda(prob.pts), prob.kconst, 1.0)
+    A = rr.kernel_to_dense(kop, "fp64")
+    dop = rr.dense_operator(A)
+    P = rr.build_precond(dop, [mu], l=prob.l, sketch="gaussian", seed=prob.omega_seed, prec="mixed")
+    b = _cuda(prob.b)
+    x, info = P.solve(b, tol=tol, certify=False, maxit=20000)
+    assert info["rc"] == rr.RR_OK
+    r = (b - rr.apply_operator(dop, mu, "fp64", x)).cpu().numpy()
+    # ||x - x*|| <= ||A_mu^{-1}|| ||A_mu (x - x*)|| <= ||A_mu (x - x*)|| / mu (A psd)
+    dx = x - _cuda(xs)
+    adx = float(torch.linalg.norm(rr.apply_operator(dop, mu, "fp64", dx)))
+    del A, dop, P
+    relres = np.linalg.norm(r) / np.linalg.norm(prob.b)
+    assert relres <= tol * 1.0001
+    xh = x.cpu().numpy()
+    rows = np.random.default_rng(0).choice(n, 64, replace=False)
+    from oracle.operators import kernel_block
+    Xp = prob.pts.T.astype(np.float64)
+    r_or = prob.b[rows] - kernel_block(prob.kind, prob.kconst, Xp[rows], Xp) @ xh - mu * xh[rows]
+    # both are float64 residuals of the same x: they differ by the rounding of the sums
+    scale = np.abs(kernel_block(prob.kind, prob.kconst, Xp[rows], Xp)) @ np.abs(xh)
+    assert np.all(np.abs(r_or - r[rows]) <= 1e-13 * (scale + np.abs(prob.b[rows])))
+    fwd = np.linalg.norm(xh - xs) / np.linalg.norm(xs)
+    bound = adx / mu / np.linalg.norm(xs)
+    assert fwd <= bound * 1.01, (fwd, bound)
+    # both solutions have residuals near 1e-10 ||b||: the bound is about 1e-8 here
+    assert bound <= 1e-7, bound
