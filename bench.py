@@ -439,7 +439,8 @@ def bench_precision(args):
 
 def bench_small(args):
     """Plain float64 method at small size: stored dense RBF, n = 2,000, d = 8, mu = 1e-3,
-    Gaussian l = 100, tol 1e-8; RandRAND PCG against plain CG, both float64."""
+    Gaussian l = 100, tol 1e-8; RandRAND PCG against plain CG, both float64, iteration
+    batches of 16 replayed as hipGraphs."""
     import numpy as np
     import torch
 
@@ -454,9 +455,11 @@ def bench_small(args):
     dop = rr.dense_operator(A)
     b = torch.from_numpy(prob.b).cuda()
 
+    # at this size an iteration is a few microseconds of work: both solves replay their
+    # iteration batches as hipGraphs, which removes most of the per-kernel launch cost
     def run(ll):
         P = rr.build_precond(dop, [mu], l=ll, sketch="gaussian", seed=prob.omega_seed, prec="fp64")
-        x, info = P.solve(b, tol=tol)
+        x, info = P.solve(b, tol=tol, use_graph=True, check_every=16)
         return x, info
 
     def timed(ll, steps):

@@ -345,10 +345,9 @@ void launch_max_abs_minus_identity(const double* M, int64_t l, int64_t ldm, doub
 // 256 threads owns DM_COLS consecutive columns: every column is read as one
 // contiguous, coalesced stream, the u values a thread loads are reused across
 // the block's columns, and the products are accumulated in float64.
-constexpr int DM_COLS = 8;
 constexpr int DM_THREADS = 256;
 
-template <typename TA>
+template <typename TA, int DM_COLS>
 __global__ __launch_bounds__(DM_THREADS) void k_dense_matvec(int64_t n, const TA* __restrict__ A,
                                                              int64_t lda,
                                                              const double* __restrict__ u,
@@ -421,17 +420,27 @@ __global__ __launch_bounds__(DM_THREADS) void k_dense_matvec(int64_t n, const TA
     }
 }
 
-int dense_matvec_blocks(int64_t n) { return (int)((n + DM_COLS - 1) / DM_COLS); }
+// Columns per block: 8 for large n; 2 below 8,192, so a small matrix still spreads
+// over every compute unit.  A column's sum is formed the same way either way (each
+// thread's strided terms, then the block reduction in a fixed order).
+static int dense_matvec_cols(int64_t n) { return n <= 8192 ? 2 : 8; }
+int dense_matvec_blocks(int64_t n) {
+    const int c = dense_matvec_cols(n);
+    return (int)((n + c - 1) / c);
+}
 
 void launch_dense_matvec(int dta, int64_t n, const void* A, int64_t lda, const double* u,
                          double mu, double* y, double* dot_part, const int32_t* stop,
                          hipStream_t st) {
     const int g = dense_matvec_blocks(n);
     ProfScope prof(dta == DT_F32 ? PROF_DENSE_MATVEC : PROF_DENSE_MATVEC64, st);
-    if (dta == DT_F32)
-        k_dense_matvec<float><<<g, DM_THREADS, 0, st>>>(n, (const float*)A, lda, u, mu, y, dot_part, stop);
-    else
-        k_dense_matvec<double><<<g, DM_THREADS, 0, st>>>(n, (const double*)A, lda, u, mu, y, dot_part, stop);
+#define KDM(T, C) k_dense_matvec<T, C><<<g, DM_THREADS, 0, st>>>(n, (const T*)A, lda, u, mu, y, dot_part, stop)
+    if (dense_matvec_cols(n) == 2) {
+        if (dta == DT_F32) KDM(float, 2); else KDM(double, 2);
+    } else {
+        if (dta == DT_F32) KDM(float, 8); else KDM(double, 8);
+    }
+#undef KDM
 }
 
 // ============================================== projections
