@@ -41,4 +41,40 @@ inline float kernel_c32(int kind, double kconst) {
     return kind == 1 ? (float)(2.0 * kconst * 1.4426950408889634074) : (float)kconst;
 }
 
+// 2^t for t <= 0 is table-driven (Tang, ACM TOMS 15(2), 1989): t = m + j/256 + f
+// with |f| <= 1/512, 2^t = 2^m 2^(j/256) exp(f ln 2); the last factor is its Taylor
+// polynomial of degree 4 (truncation below 4e-17 for |f ln 2| <= ln 2 / 512) and
+// 2^(j/256) comes from a 256-entry LDS table (EXP2_TAB entries, filled by
+// exp2_table_fill).  About 2 ulp in all.
+constexpr double LN2_D = 0.69314718055994530942;
+constexpr double LOG2E_D = 1.44269504088896340736;
+constexpr int EXP2_TAB = 256;
+
+// Fills tab[0..EXP2_TAB) with 2^(j/256); the caller synchronises before use.
+RR_DEV void exp2_table_fill(double* tab) {
+    for (int j = threadIdx.x; j < EXP2_TAB; j += blockDim.x) tab[j] = exp2((double)j / EXP2_TAB);
+}
+
+RR_DEV double exp2_nonpos(double t, const double* __restrict__ tab) {
+    t = fmax(t, -1100.0);
+    const double kf = rint(t * EXP2_TAB);
+    const double f = fma(kf, -1.0 / EXP2_TAB, t);
+    const int k = (int)kf;
+    const int j = k & (EXP2_TAB - 1);
+    const int m = k >> 8;   // floor(k / 256)
+    const double z = f * LN2_D;
+    double p = fma(z, 1.0 / 24.0, 1.0 / 6.0);
+    p = fma(z, p, 0.5);
+    p = fma(z, p, 1.0);
+    p = fma(z, p, 1.0);
+    return ldexp(tab[j] * p, m);
+}
+
+template <int KIND>
+RR_DEV double kentry64(double t, double kconst, const double* __restrict__ tab) {
+    if (KIND == 1) return exp2_nonpos(t, tab);
+    const double kr = kconst * sqrt(fmax(-2.0 * t, 0.0));
+    return (1.0 + kr) * exp2_nonpos(-kr * LOG2E_D, tab);
+}
+
 }  // namespace rr

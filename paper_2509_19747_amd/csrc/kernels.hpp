@@ -197,6 +197,10 @@ void launch_point_records64(const float* pts, int64_t n, int d, int dm, double g
 // Symmetric float64 kernel matvec (entries in float64: record products on the vector
 // ALU, table-driven exp2), nr in {1, 2}; needs op.xd and op.hd.
 size_t kernel_sym64_ws_doubles(int64_t n, int d, int nr);
+// Float64 symmetric kernel matvec with the exponents' Gram products on float64 MFMA
+// (the MFMA kernel's items and slots: kernel_mma_ok, kernel_mma_ws_doubles).
+void launch_kernel_matvec_mma64(const KernelOp& op, const double* u, int nr, double mu, double* y,
+                                double* dot_part, double* ws, const int32_t* stop, hipStream_t st);
 void launch_kernel_matvec_sym64(const KernelOp& op, const double* u, int nr, double mu, double* y,
                                 double* dot_part, double* ws, const int32_t* stop, hipStream_t st);
 // Record length (floats) of a d-dimensional point: the next of 4, 8, 16, 32.

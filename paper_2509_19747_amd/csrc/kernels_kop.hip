@@ -214,7 +214,8 @@ size_t kernel_matvec_ws_doubles(int64_t n, int d, int nr) {
 }
 
 size_t kernel_matvec_ws_doubles_for(int64_t n, int d, int nr, bool fp64) {
-    if (fp64) return kernel_sym64_ws_doubles(n, d, std::min(nr, 2));
+    if (fp64) return kernel_mma_ok(n, d) ? kernel_mma_ws_doubles(n, std::min(nr, 2))
+                                         : kernel_sym64_ws_doubles(n, d, std::min(nr, 2));
     if (kernel_mma_ok(n, d)) return kernel_mma_ws_doubles(n, std::min(nr, 2));
     size_t w = 0;
     for (int c = 1; c <= 8; c *= 2)
@@ -232,9 +233,11 @@ void launch_kernel_matvec_multi(const KernelOp& op, bool fp64, const double* u, 
         double* yq = y + (int64_t)q0 * op.n;
         double* dq = dot_part + (int64_t)q0 * nblk;
         if (fp64 && op.xd) {
-            // each unordered pair once, float64 entries
+            // each unordered pair once, float64 entries (Gram products on float64 MFMA
+            // within the MFMA kernel's slot bound, else on the vector ALU)
             const int c = left >= 2 ? 2 : 1;
-            launch_kernel_matvec_sym64(op, uq, c, mu, yq, dq, ws, stop, st);
+            if (kernel_mma_ok(op.n, op.d)) launch_kernel_matvec_mma64(op, uq, c, mu, yq, dq, ws, stop, st);
+            else launch_kernel_matvec_sym64(op, uq, c, mu, yq, dq, ws, stop, st);
             q0 += c;
         } else if (fp64) {
             const int c = left >= 2 ? 2 : 1;

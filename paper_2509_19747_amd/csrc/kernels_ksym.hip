@@ -345,36 +345,7 @@ void launch_kernel_matvec_sym(const KernelOp& op, const double* u, int nr, doubl
 // costs dm fused multiply-adds.  The RBF entry is 2^t; the Matern-3/2 entry
 // (g = 1) is (1 + kconst r) 2^(-kconst r log2 e) with r = sqrt(-2 t).
 //
-// 2^t for t <= 0 is table-driven (Tang, ACM TOMS 15(2), 1989): t = m + j/32 + f
-// with |f| <= 1/64, 2^t = 2^m 2^(j/32) exp(f ln 2); the last factor is its Taylor
-// polynomial of degree 6 (truncation below 4e-18 for |f ln 2| <= ln 2 / 64) and
-// 2^(j/32) comes from a 32-entry LDS table.  About 3 ulp in all.
-constexpr double LN2_D = 0.69314718055994530942;
-constexpr double LOG2E_D = 1.44269504088896340736;
-
-RR_DEV double exp2_nonpos(double t, const double* __restrict__ tab) {
-    t = fmax(t, -1100.0);
-    const double kf = rint(t * 32.0);
-    const double f = fma(kf, -0.03125, t);
-    const int k = (int)kf;
-    const int j = k & 31;
-    const int m = k >> 5;   // floor(k / 32)
-    const double z = f * LN2_D;
-    double p = fma(z, 1.0 / 720.0, 1.0 / 120.0);
-    p = fma(z, p, 1.0 / 24.0);
-    p = fma(z, p, 1.0 / 6.0);
-    p = fma(z, p, 0.5);
-    p = fma(z, p, 1.0);
-    p = fma(z, p, 1.0);
-    return ldexp(tab[j] * p, m);
-}
-
-template <int KIND>
-RR_DEV double kentry64(double t, double kconst, const double* __restrict__ tab) {
-    if (KIND == 1) return exp2_nonpos(t, tab);
-    const double kr = kconst * sqrt(fmax(-2.0 * t, 0.0));
-    return (1.0 + kr) * exp2_nonpos(-kr * LOG2E_D, tab);
-}
+// 2^t is the table-driven exp2_nonpos of kentry.hpp.
 
 // Rows per thread and the work split do not depend on the number of columns, so a
 // column goes through the same arithmetic alone and inside a two-column product.
@@ -497,8 +468,8 @@ __global__ __launch_bounds__(KS_THREADS) void k_ksym_f64(int64_t n, const double
     constexpr int R = ks64_rows(DM, NR);
     constexpr int RB = KS_THREADS * R;
     __shared__ double colw[4][KS64_CH * NR];
-    __shared__ double tab[32];
-    if (threadIdx.x < 32) tab[threadIdx.x] = exp2((double)threadIdx.x / 32.0);
+    __shared__ double tab[EXP2_TAB];
+    exp2_table_fill(tab);
 
     int64_t t = blockIdx.x / S;
     const int s = (int)(blockIdx.x - t * S);

@@ -340,6 +340,219 @@ __global__ __launch_bounds__(256 * KF_GROUPS) void k_ksym_mma_finish(int64_t n, 
     }
 }
 
+// ------------------------------------------------------------------ float64
+// The same work items, partial slots and finish as k_ksym_mma, with float64 entries
+// (the restart residuals of the float64 refinement and the float64 working
+// precision).  The Gram part of the exponent
+//   t_ij = h_i + h_j + sum_k (g x_ik) x_jk = -g r_ij^2 / 2,   h_i = -g |x_i|^2 / 2,
+// runs on v_mfma_f64_16x16x4_f64 with h_i as the accumulator's initial value; h_j,
+// the table exp2 (kentry64) and the float64 row and column sums run on the vector
+// ALU.  A wave's 32 x 32 tile is four 16 x 16 MFMA tiles (a, b): lane l supplies
+// A[row 16 a + l%16][k 4 s + l/16] and B[k 4 s + l/16][column 16 b + l%16] of step s
+// and holds element e of the product at row 16 a + 4 e + l/16, column 16 b + l%16, so
+// a lane owns 8 rows and 2 columns of the tile.  Column sums: the lane's 8 rows, then
+// the four lanes of a column (l/16 = 0..3), then the eight waves in a fixed order;
+// row sums: the lane's columns over the item, then the 16 lanes of a row.  Each pair
+// is evaluated once, also inside the diagonal blocks (wave w forms the column tiles
+// >= w, and in its own tile only row <= column for the row sums and row < column for
+// the column sums), so the operator is exactly symmetric.
+typedef double f64x4_t __attribute__((ext_vector_type(4)));
+
+template <int KIND, int DM, int NR>
+__global__ __launch_bounds__(KM_THREADS) __attribute__((amdgpu_waves_per_eu(NR == 1 ? 4 : 2))) void k_ksym_mma64(
+    int64_t n, const double* __restrict__ xd, const double* __restrict__ hd, double g, double kconst,
+    const double* __restrict__ u, double* __restrict__ part, int nb, int m, int S,
+    const int32_t* __restrict__ stop) {
+    constexpr int KS = DM / 4;   // MFMA steps of 4 coordinates
+    __shared__ double bsd[DM][KM_RB];                 // column records, coordinate-major
+    __shared__ double hs[KM_RB];                      // h_j
+    __shared__ double hr[KM_RB];                      // h_i of the item's rows
+    __shared__ double us[NR][KM_RB];                  // u_j
+    __shared__ double colw[KM_WAVES][NR][KM_RB];      // column partials per wave
+    __shared__ double tab[EXP2_TAB];
+    if (stop && *stop) return;
+    exp2_table_fill(tab);
+
+    int64_t t = blockIdx.x / S;
+    const int sr = (int)(blockIdx.x % S);
+    int bi = 0;
+    while (t >= (nb - bi + m - 1) / m) { t -= (nb - bi + m - 1) / m; ++bi; }
+    const int run = (int)t;
+    const int bj0 = bi + run * m, bj1 = std::min(bj0 + m, nb);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lr = lane >> 4, lc = lane & 15;
+    const int64_t r0 = (int64_t)bi * KM_RB + 32 * wave;   // the wave's 32 rows
+    const int cpr = KM_CT / S;
+    const int ct0 = sr * cpr, ct1 = ct0 + cpr;
+
+    // A operands (g x_i of rows 16 a + lc) and u_i at the lane's output rows; h_i of
+    // the block's rows in LDS (read as the accumulators' initial values per tile)
+    double areg[2][KS];
+    double ui[8][NR], acc[8][NR];
+    for (int e = tid; e < KM_RB; e += KM_THREADS) {
+        const int64_t i = (int64_t)bi * KM_RB + e;
+        hr[e] = hd[i < n ? i : n - 1];
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+        const int64_t i = r0 + 16 * a + lc;
+        const int64_t ic = i < n ? i : n - 1;
+#pragma unroll
+        for (int s = 0; s < KS; ++s) areg[a][s] = g * xd[ic * DM + 4 * s + lr];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int64_t ir = r0 + 16 * a + 4 * e + lr;
+#pragma unroll
+            for (int q = 0; q < NR; ++q) {
+                ui[4 * a + e][q] = ir < n ? u[(int64_t)q * n + ir] : 0.0;
+                acc[4 * a + e][q] = 0.0;
+            }
+        }
+    }
+
+    const int64_t cslot = (int64_t)bi * S;
+    const int64_t dslot = (int64_t)nb * S;
+#pragma unroll 1
+    for (int bj = bj0; bj < bj1; ++bj) {
+        const int64_t cbase = (int64_t)bj * KM_RB;
+        __syncthreads();   // the previous block's records and partials are consumed (and the table is in)
+        for (int e = tid; e < 32 * cpr; e += KM_THREADS) {
+            const int jl = 32 * ct0 + e;
+            const int64_t j = cbase + jl;
+            const int64_t jc = j < n ? j : n - 1;
+#pragma unroll
+            for (int k = 0; k < DM; ++k) bsd[k][jl] = xd[jc * DM + k];
+            hs[jl] = hd[jc];
+#pragma unroll
+            for (int q = 0; q < NR; ++q) us[q][jl] = j < n ? u[(int64_t)q * n + j] : 0.0;
+        }
+        __syncthreads();
+        const int wlo = bj == bi ? wave : -1;
+#pragma unroll 1
+        for (int ct = ct0; ct < ct1; ++ct) {
+            if (ct < wlo) {
+                if (lr == 0)
+#pragma unroll
+                    for (int b = 0; b < 2; ++b)
+#pragma unroll
+                        for (int q = 0; q < NR; ++q) colw[wave][q][32 * ct + 16 * b + lc] = 0.0;
+                continue;
+            }
+            auto tile = [&](auto dgc) {
+                constexpr bool DG = decltype(dgc)::value;
+                f64x4_t d[2][2];
+#pragma unroll
+                for (int a = 0; a < 2; ++a) {
+                    f64x4_t h;
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) h[e] = hr[32 * wave + 16 * a + 4 * e + lr];
+                    d[a][0] = h;
+                    d[a][1] = h;
+                }
+#pragma unroll
+                for (int s = 0; s < KS; ++s) {
+                    const double b0 = bsd[4 * s + lr][32 * ct + lc];
+                    const double b1 = bsd[4 * s + lr][32 * ct + 16 + lc];
+#pragma unroll
+                    for (int a = 0; a < 2; ++a) {
+                        d[a][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(areg[a][s], b0, d[a][0], 0, 0, 0);
+                        d[a][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(areg[a][s], b1, d[a][1], 0, 0, 0);
+                    }
+                }
+#pragma unroll
+                for (int b = 0; b < 2; ++b) {
+                    const int jl = 32 * ct + 16 * b + lc;
+                    const double hj = hs[jl];
+                    double uj[NR], cs[NR];
+#pragma unroll
+                    for (int q = 0; q < NR; ++q) { uj[q] = us[q][jl]; cs[q] = 0.0; }
+#pragma unroll
+                    for (int a = 0; a < 2; ++a)
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) {
+                            const double kv = kentry64<KIND>(d[a][b][e] + hj, kconst, tab);
+                            double kr = kv, kc = kv;
+                            if constexpr (DG) {
+                                const int rrow = 16 * a + 4 * e + lr, rcol = 16 * b + lc;
+                                kr = rrow <= rcol ? kv : 0.0;
+                                kc = rrow < rcol ? kv : 0.0;
+                            }
+#pragma unroll
+                            for (int q = 0; q < NR; ++q) {
+                                acc[4 * a + e][q] = fma(kr, uj[q], acc[4 * a + e][q]);
+                                cs[q] = fma(kc, ui[4 * a + e][q], cs[q]);
+                            }
+                        }
+                    // the four lanes of the column add in a fixed pattern (equal results)
+#pragma unroll
+                    for (int q = 0; q < NR; ++q) {
+                        double v = cs[q];
+                        v = v + __shfl_xor(v, 16, 64);
+                        v = v + __shfl_xor(v, 32, 64);
+                        if (lr == 0) colw[wave][q][jl] = v;
+                    }
+                }
+            };
+            if (ct == wlo) tile(std::true_type{});
+            else tile(std::false_type{});
+        }
+        __syncthreads();
+        const int64_t slot = bj != bi ? cslot : dslot;
+        for (int e = tid; e < NR * 32 * cpr; e += KM_THREADS) {
+            const int q = e / (32 * cpr), jl = 32 * ct0 + e % (32 * cpr);
+            const int64_t j = cbase + jl;
+            if (j < n) {
+                double v = 0.0;
+#pragma unroll
+                for (int w = 0; w < KM_WAVES; ++w) v += colw[w][q][jl];
+                part[(slot * NR + q) * n + j] = v;
+            }
+        }
+    }
+    // row sums of the run: the 16 lanes of a row add in a fixed butterfly
+    const int64_t rslot = (int64_t)(bi + run) * S + sr;
+#pragma unroll
+    for (int r = 0; r < 8; ++r)
+#pragma unroll
+        for (int q = 0; q < NR; ++q) {
+            double v = acc[r][q];
+            v = v + __shfl_xor(v, 1, 64);
+            v = v + __shfl_xor(v, 2, 64);
+            v = v + __shfl_xor(v, 4, 64);
+            v = v + __shfl_xor(v, 8, 64);
+            const int64_t i = r0 + 16 * (r >> 2) + 4 * (r & 3) + lr;
+            if (lc == 0 && i < n) part[(rslot * NR + q) * n + i] = v;
+        }
+}
+
+void launch_kernel_matvec_mma64(const KernelOp& op, const double* u, int nr, double mu, double* y,
+                                double* dot_part, double* ws, const int32_t* stop, hipStream_t st) {
+    const KmmaPlan p = kmma_plan(op.n);
+    const double g = kernel_g64(op.kind, op.kconst);
+    const unsigned grid = (unsigned)p.items;
+    {
+        ProfScope prof(nr == 1 ? PROF_KERNEL_MATVEC64 : -1, st);
+#define KM64(K, DD, Q) k_ksym_mma64<K, DD, Q><<<grid, KM_THREADS, 0, st>>>(op.n, op.xd, op.hd, g, op.kconst, u, ws, p.nb, p.m, p.S, stop)
+#define KM64D(K, Q)                      \
+    switch (op.dm) {                     \
+        case 4: KM64(K, 4, Q); break;    \
+        case 8: KM64(K, 8, Q); break;    \
+        case 16: KM64(K, 16, Q); break;  \
+        default: KM64(K, 32, Q); break;  \
+    }
+        if (op.kind == 1) {
+            if (nr == 1) { KM64D(1, 1) } else { KM64D(1, 2) }
+        } else {
+            if (nr == 1) { KM64D(2, 1) } else { KM64D(2, 2) }
+        }
+#undef KM64D
+#undef KM64
+    }
+    k_ksym_mma_finish<<<(unsigned)((op.n + 255) / 256), 256 * KF_GROUPS, 0, st>>>(op.n, KM_RB, p.nb, p.m, p.S, nr, ws,
+                                                                      op.scale, mu, u, y, dot_part,
+                                                                      stop);
+}
+
 template <int KIND, int NR, typename T>
 static void kmma_dispatch(const KernelOp& op, float c, const double* u, double* ws,
                           const KmmaPlan& p, const int32_t* stop, hipStream_t st) {
