@@ -158,8 +158,16 @@ def test_kernel_fp32_operator_symmetric_multi_tile():
     K = rr.apply_operator_block(kop, 0.0, "fp32", E).cpu().numpy()
     assert np.array_equal(K, K.T)
     ref = Operator(kind=rr.OP_RBF, pts=pts, kconst=0.05, scale=1.0).to_dense()
-    # |s| error <= (d+1) 2^-24 (|x_i|^2 + |x_j|^2 + |x_i.x_j|) ~ 3e-5, times the exponent's c ln 2
-    assert np.max(np.abs(K - ref)) <= 1e-5
+    # elementwise bound from the arithmetic: the exponent t = -kconst |x_i - x_j|^2 is the
+    # float32-class record product (terms g |x_i|^2 / 2, g |x_j|^2 / 2, g x_i.x_j, each
+    # split into bf16 pieces to 24 bits, summed over 6 d + 6 products in float32), so
+    # |dt| <= (6 d + 6) 2^-24 kconst (|x_i|^2 + |x_j|^2 + 2 |x_i.x_j|); the entry
+    # exp(t) then has relative error |dt| plus the exp2's own 2^-22
+    X = pts.T.astype(np.float64)
+    sq = np.sum(X * X, axis=1)
+    mag = sq[:, None] + sq[None, :] + 2.0 * np.abs(X @ X.T)
+    bound = ref * ((6 * d + 6) * 2.0 ** -24 * 0.05 * mag + 2.0 ** -22)
+    assert np.all(np.abs(K - ref) <= bound), np.max(np.abs(K - ref) / bound)
 
 
 def test_kernel_fp32_operator_symmetric():
@@ -1229,3 +1237,68 @@ def test_precision_full_size_against_direct_solution():
     assert fwd <= bound * 1.01, (fwd, bound)
     # both solutions have residuals near 1e-10 ||b||: the bound is about 1e-8 here
     assert bound <= 1e-7, bound
+
+
+def test_small_dense_config_at_stated_size():
+    """Config 1 as stated: stored dense RBF on n = 2,000 points ~ N(0, I_8), bandwidth 1,
+    mu = 1e-3, Gaussian l = 100, float64, tol 1e-8: tau, the iteration count and the
+    solution against the oracle's Algorithm RandRAND_PCG and the direct solve; plain CG
+    (l = 0) against the oracle's CG."""
+    prob = workloads.cfg_small_dense()
+    mu, tol = prob.mus[0], prob.tol
+    op = Operator.from_problem(prob)
+    kop = rr.kernel_operator(rr.OP_RBF, _cuda(prob.pts), prob.kconst, prob.scale)
+    A = rr.kernel_to_dense(kop, "fp64")
+    dop = rr.dense_operator(A)
+    P = rr.build_precond(dop, [mu], l=prob.l, sketch="gaussian", seed=prob.omega_seed, prec="fp64")
+    x, info = P.solve(_cuda(prob.b), tol=tol, use_graph=True, check_every=16)
+    Po = orr.build(op, [mu], prob.l, "gaussian", prob.omega_seed)[0]
+    ref = osol.pcg(op.shifted(mu), Po.apply, prob.b, tol)
+    assert info["rc"] == rr.RR_OK and ref.status == osol.OK
+    assert abs(info["tau"] - Po.tau) <= 1e-9 * Po.tau
+    assert abs(info["iters"] - ref.iters) <= max(2, int(0.03 * ref.iters)), (info["iters"], ref.iters)
+    x = x.cpu().numpy()
+    rel = osol.relres(op.shifted(mu), x, prob.b)
+    assert rel <= tol * 1.0001 and rel <= ref.relres + 1e-8
+    xs = osol.direct(op.to_dense(), mu, prob.b)
+    cond = np.linalg.cond(op.to_dense() + mu * np.eye(prob.n))
+    assert np.linalg.norm(x - xs) <= 2 * tol * cond * np.linalg.norm(xs)
+    P0 = rr.build_precond(dop, [mu], l=0, prec="fp64")
+    x0, i0 = P0.solve(_cuda(prob.b), tol=tol)
+    r0 = osol.cg(op.shifted(mu), prob.b, tol)
+    assert i0["rc"] == rr.RR_OK and abs(i0["iters"] - r0.iters) <= max(2, int(0.03 * r0.iters))
+    assert info["iters"] < i0["iters"]
+
+
+def test_kernel_ridge_headline_full_size():
+    """The headline workload at full size (RBF n = 50,000, d = 16, mu = 1e-4, SRHT
+    l = 500, tol 1e-6, float32-class entries with float64 refinement): the library's
+    float64 relres <= tol; the device float64 residual agrees on 64 sampled rows with
+    the oracle's kernel formula; the float32-class product agrees with the oracle's on
+    the same rows within its arithmetic bound; RandRAND needs fewer iterations than
+    plain CG."""
+    prob = workloads.cfg_kernel_ridge()
+    mu, tol = prob.mus[0], prob.tol
+    kop = rr.kernel_operator(rr.OP_RBF, _cuda(prob.pts), prob.kconst, prob.scale)
+    P = rr.build_precond(kop, [mu], l=prob.l, sketch="srht", seed=prob.omega_seed, prec="fp32")
+    b = _cuda(prob.b)
+    x, info = P.solve(b, tol=tol)
+    assert info["rc"] == rr.RR_OK and info["relres_fp64"] <= tol
+    r = (b - rr.apply_operator(kop, mu, "fp64", x)).cpu().numpy()
+    y32 = rr.apply_operator(kop, mu, "fp32", x).cpu().numpy()
+    assert abs(np.linalg.norm(r) / np.linalg.norm(prob.b) - info["relres_fp64"]) <= 1e-9 * info["relres_fp64"]
+    xh = x.cpu().numpy()
+    from oracle.operators import kernel_block
+    Xp = prob.pts.T.astype(np.float64)
+    rows = np.random.default_rng(3).choice(prob.n, 64, replace=False)
+    Kr = prob.scale * kernel_block(prob.kind, prob.kconst, Xp[rows], Xp)
+    r_or = prob.b[rows] - Kr @ xh - mu * xh[rows]
+    scale = np.abs(Kr) @ np.abs(xh) + mu * np.abs(xh[rows]) + np.abs(prob.b[rows])
+    assert np.all(np.abs(r_or - r[rows]) <= 1e-13 * scale), np.max(np.abs(r_or - r[rows]) / scale)
+    # float32-class product on the same rows: within 2e-6 of sum |K_ij x_j| (reading of
+    # the float32 operator; the same bound as the smaller parity tests)
+    y_or = Kr @ xh + mu * xh[rows]
+    assert np.all(np.abs(y32[rows] - y_or) <= 2e-6 * scale)
+    P0 = rr.build_precond(kop, [mu], l=0, prec="fp32")
+    x0, i0 = P0.solve(b, tol=tol)
+    assert i0["rc"] == rr.RR_OK and info["iters"] < i0["iters"]
