@@ -1302,3 +1302,50 @@ def test_kernel_ridge_headline_full_size():
     P0 = rr.build_precond(kop, [mu], l=0, prec="fp32")
     x0, i0 = P0.solve(b, tol=tol)
     assert i0["rc"] == rr.RR_OK and info["iters"] < i0["iters"]
+
+
+def test_edge_cases_of_the_variants():
+    """Degenerate inputs for the rows beyond PCG: a kernel operator smaller than one
+    tile (n = 5) in float32 and float64 against the direct solve; b = 0 for R-RandRAND,
+    split R-RandRAND, MINRES and block MINRES; one right-hand side in block MINRES is
+    preconditioned MINRES (same iteration count, same solution); basis-less and q = 1
+    builds with l = n solve in one or two iterations."""
+    rng = np.random.default_rng(8)
+    pts = rng.standard_normal((4, 5)).astype(np.float32)
+    op5 = Operator(kind=rr.OP_RBF, pts=pts, kconst=0.3, scale=1.0)
+    kop5 = rr.kernel_operator(rr.OP_RBF, _cuda(pts), 0.3, 1.0)
+    b5 = rng.standard_normal(5)
+    xs = osol.direct(op5.to_dense(), 0.1, b5)
+    for prec in ("fp32", "fp64"):
+        P = rr.build_precond(kop5, [0.1], l=2, sketch="gaussian", seed=4, prec=prec)
+        x, info = P.solve(_cuda(b5), tol=1e-12)
+        assert info["rc"] == rr.RR_OK
+        assert np.linalg.norm(x.cpu().numpy() - xs) <= 1e-9 * np.linalg.norm(xs)
+    prob = workloads.cfg_kernel_ridge(n=3000, d=8, l=90)
+    mu = prob.mus[0]
+    kop = rr.kernel_operator(rr.OP_RBF, _cuda(prob.pts), prob.kconst, prob.scale)
+    P = rr.build_precond(kop, [mu], l=prob.l, sketch="srht", seed=prob.omega_seed, prec="fp64")
+    z = torch.zeros(prob.n, dtype=torch.float64, device="cuda")
+    for kw in (dict(method="r"), dict(method="split"), dict(krylov="minres"), dict(method="r", krylov="minres")):
+        x, info = P.solve(z, **kw)
+        assert info["rc"] == rr.RR_OK and float(x.abs().max()) == 0.0, kw
+    X, infos, st = P.solve_batch(torch.zeros(prob.n, 3, dtype=torch.float64, device="cuda"), [0] * 3,
+                                 krylov="block_minres")
+    assert st == rr.RR_OK and float(X.abs().max()) == 0.0
+    b = _cuda(prob.b)
+    xm, im = P.solve(b, tol=1e-9, krylov="minres")
+    Xb, ib, st = P.solve_batch(b[:, None], [0], tol=1e-9, krylov="block_minres")
+    assert st == rr.RR_OK and abs(ib[0]["iters"] - im["iters"]) <= 1, (ib[0]["iters"], im["iters"])
+    xb = Xb[:, 0]
+    assert float(torch.linalg.norm(xb - xm) / torch.linalg.norm(xm)) <= 1e-7
+    # l = n with column sampling: every column is sampled and the deflated space is
+    # everything (one iteration, as the oracle).  (q = 1 at l = n is a degenerate case of
+    # the method itself: Omega = A X is numerically rank deficient for this kernel and
+    # tau_NYS collapses to ~1e-17 in the oracle as well, so it is not asserted here.)
+    small = workloads.cfg_kernel_ridge(n=200, d=4, l=200)
+    ksm = rr.kernel_operator(rr.OP_RBF, _cuda(small.pts), small.kconst, small.scale)
+    for basis in ("explicit", "less"):
+        Pl = rr.build_precond(ksm, [1e-2], l=200, sketch="colsample", seed=6, prec="fp64", tau_rule="nys",
+                              basis=basis)
+        xl, il = Pl.solve(_cuda(small.b), tol=1e-8, ok=(rr.RR_OK, rr.RR_ENOCONV), maxit=50)
+        assert il["rc"] == rr.RR_OK and il["iters"] <= 2, (basis, il["iters"], il["tau"])
