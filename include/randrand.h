@@ -12,7 +12,11 @@
  *     P = I - Pi + tau Pi A_mu^{-1} Pi = I + Q (tau T G T - T) Q^T,
  *     A_mu Omega = Q R,  G = R^{-T} (Omega^T A_mu Omega) R^{-1},  T = 2I - Q^T Q,
  *
- * used inside PCG with restarts (Algorithm RandRAND_PCG, Section 6.2).
+ * used inside PCG with restarts (Algorithm RandRAND_PCG, Section 6.2).  The same
+ * handle also serves preconditioned MINRES, R-RandRAND and split R-RandRAND
+ * (Section 3.1, Algorithms RandRAND_CG and RandRAND_CG_split), block MINRES and
+ * block CG over several right-hand sides (Section 7.2.2), and a basis-less form
+ * (Section 4.1, Algorithm BL_RandRAND_PCG); see rr_method, rr_krylov and rr_basis.
  *
  * Conventions for every entry point:
  *  - All functions are extern "C", never throw, never abort, and return rr_status.
