@@ -312,6 +312,11 @@ typedef struct {
     const rr_allocator* alloc;  /* device allocator for every request buffer and handle
                                    (NULL: the library's stream-ordered pool); its alloc and
                                    free are called from the server's worker threads       */
+    int32_t grouped;      /* 1: the PCG batches of all resident requests run together, one
+                             replay of grouped persistent kernels over a device work list
+                             per batch (requests of one shift whose kernel product runs on
+                             MFMA; others replay their own graph); 0: every request
+                             replays its own graph.  Needs graph_iters > 0.            */
 } rr_serve_config;
 
 typedef struct {
@@ -323,16 +328,24 @@ typedef struct {
     int32_t max_active;
     int64_t ok, failed;              /* delivered with status RR_OK / with an error       */
     int64_t graph_fallbacks;         /* requests whose PCG graph capture was invalidated  */
+    int64_t group_replays;           /* grouped replays run (grouped = 1)                 */
+    double group_mean;               /* request batches per grouped replay                */
+    int32_t group_max;               /* largest number of requests in one replay          */
+    double group_busy_s;             /* time the grouped engine spent on replays          */
+    double group_wait_s;             /* summed over request batches: queued to completed  */
 } rr_serve_stats;
 
 /*
  * Continuous-batching server: a persistent loop polls next(), admits requests while
  * slots and the HBM budget allow (a request larger than the whole budget is
  * rejected with status RR_ENOMEM in its deliver()), builds each request's
- * preconditioner on the device, advances all resident requests' PCG iterations in
- * batches on separate streams so their work overlaps, and delivers each result
- * as soon as it converges.  Per-request arithmetic does not depend on what else
- * is resident.  Returns when next() has returned -1 and every admitted request is
+ * preconditioner on the device (worker threads, one stream each, builds
+ * overlapping), advances the resident requests' PCG iterations in batches of
+ * graph_iters (grouped = 1: the batches of every request waiting at that moment in
+ * one replay of grouped kernels; grouped = 0: a graph per request) and delivers
+ * each result as soon as it converges.  Per-request arithmetic does not depend on
+ * what else is resident (each request keeps its own work items and reduction
+ * orders in the grouped kernels), so a result is the same alone and in the mix.  Returns when next() has returned -1 and every admitted request is
  * delivered.  Returns RR_OK only if every admitted request succeeded; otherwise
  * the first failed request's status (stats->failed counts them, rr_last_error()
  * names the first).  Errors: RR_EINVAL, RR_EDEVICE, or a request's status.
@@ -479,7 +492,9 @@ rr_status rr_lambda_max(const double* G, int64_t k, uint64_t seed, double* out_h
  * 2 = float32 dense matvec, 3 = bf16 dense sketch, 4 = projections,
  * 5 = float64 kernel matrix-matrix product of the batched solve, 6 = float64 kernel
  * matvec (first stage; restart residuals of the float64 refinement), 7 = float64 dense
- * matvec.
+ * matvec; the serving loop's grouped iterations (run as plain launches while timing
+ * is on): 8 = kernel products, 9 = their finish, 10 = projections, 11 = x, r and p
+ * updates (one timed span per iteration and class).
  */
 void rr_profile_enable(int32_t on);
 rr_status rr_profile_read(int32_t slot, int64_t* count, double* total_ms);

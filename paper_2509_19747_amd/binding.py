@@ -93,14 +93,16 @@ DELIVER_FN = C.CFUNCTYPE(None, C.c_void_p, C.POINTER(rr_request), C.POINTER(rr_s
 class rr_serve_config(C.Structure):
     _fields_ = [("hbm_budget", C.c_size_t), ("max_slots", C.c_int32), ("graph_iters", C.c_int32),
                 ("build", rr_build_opts), ("solve", rr_solve_opts),
-                ("alloc", C.POINTER(rr_allocator))]
+                ("alloc", C.POINTER(rr_allocator)), ("grouped", C.c_int32)]
 
 
 class rr_serve_stats(C.Structure):
     _fields_ = [("p50_ms", C.c_double), ("p99_ms", C.c_double), ("mean_ms", C.c_double),
                 ("solves_per_s", C.c_double), ("served", C.c_int64), ("rejected", C.c_int64),
                 ("hbm_peak", C.c_size_t), ("max_active", C.c_int32), ("ok", C.c_int64),
-                ("failed", C.c_int64), ("graph_fallbacks", C.c_int64)]
+                ("failed", C.c_int64), ("graph_fallbacks", C.c_int64),
+                ("group_replays", C.c_int64), ("group_mean", C.c_double), ("group_max", C.c_int32),
+                ("group_busy_s", C.c_double), ("group_wait_s", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -471,7 +473,8 @@ def lambda_max(G, seed: int = 0, stream=None):
 
 
 (PROF_KERNEL_MATVEC, PROF_KERNEL_SKETCH, PROF_DENSE_MATVEC, PROF_DENSE_SKETCH, PROF_PROJECT,
- PROF_KERNEL_MATMAT, PROF_KERNEL_MATVEC64, PROF_DENSE_MATVEC64) = range(8)
+ PROF_KERNEL_MATMAT, PROF_KERNEL_MATVEC64, PROF_DENSE_MATVEC64, PROF_GROUP_PRODUCT, PROF_GROUP_FINISH,
+ PROF_GROUP_PROJECT, PROF_GROUP_UPDATE) = range(12)
 
 
 def profile_enable(on: bool = True):
@@ -496,8 +499,12 @@ def sketch(op: Operator, mu: float, l: int, stream=None, **kw):
 
 
 def serve(requests, hbm_budget: int = 96 << 30, max_slots: int = 8, graph_iters: int = 8,
-          build: Optional[dict] = None, solve: Optional[dict] = None, allocator=None):
+          build: Optional[dict] = None, solve: Optional[dict] = None, allocator=None,
+          grouped: bool = True):
     """Run the continuous-batching server over `requests` (arrival-ordered).
+
+    grouped: the PCG batches of all resident requests run as one replay of grouped
+    kernels (False: each request replays its own graph).
 
     Each request is a dict with keys: kind, pts (float32 (d, n) host array), kconst,
     scale, mu, l, seed, B (float64 (n, m) host array), t_arrival (seconds after the
@@ -507,7 +514,7 @@ def serve(requests, hbm_budget: int = 96 << 30, max_slots: int = 8, graph_iters:
     bo = build_opts(**(build or {}))
     so = solve_opts(**(solve or {}))
     cfg = rr_serve_config(hbm_budget=int(hbm_budget), max_slots=int(max_slots),
-                          graph_iters=int(graph_iters), build=bo, solve=so)
+                          graph_iters=int(graph_iters), build=bo, solve=so, grouped=int(bool(grouped)))
     keep = []
     for i, r in enumerate(requests):
         pts = np.ascontiguousarray(r["pts"], dtype=np.float32)

@@ -25,7 +25,8 @@ using namespace rr;
 
 rr_status rr_solve_batch_fused(const rr_precond* Pc, const int32_t* mu_index_per_col,
                                const double* B, int64_t ldb, int32_t nrhs, double* X, int64_t ldx,
-                               const rr_solve_opts* o, rr_solve_info* infos, void* hip_stream) {
+                               const rr_solve_opts* o, rr_solve_info* infos, void* hip_stream,
+                               rr::BatchRunner* runner) {
     if (infos)
         for (int j = 0; j < nrhs; ++j) { std::memset(&infos[j], 0, sizeof(rr_solve_info)); infos[j].status = RR_EINVAL; }
     return guarded([&]() -> rr_status {
@@ -34,13 +35,16 @@ rr_status rr_solve_batch_fused(const rr_precond* Pc, const int32_t* mu_index_per
         hipStream_t st = (hipStream_t)hip_stream;
         const int64_t n = P.n, m = nrhs;
         const double t0 = now_ms();
-        Batch Bt(P, st, m);
+        Batch Bt(P, st, m, runner != nullptr);
         // per-column shifts and the set of shifts in use
         std::vector<double> hmu(m);
         std::vector<int> used(P.per.size(), 0);
         for (int64_t j = 0; j < m; ++j) { hmu[j] = P.per[mu_index_per_col[j]].mu; used[mu_index_per_col[j]] = 1; }
         for (size_t g = 0; g < used.size(); ++g) if (used[g]) Bt.mus_used.push_back((int)g);
         Bt.setup_single_shift();
+        // iteration batches in the serving loop's grouped replays when the column block
+        // has their shape (one shift, the MFMA kernel product, streaming projection)
+        const bool grouped = runner != nullptr && Bt.group_ok();
         RR_HIP(hipMemcpyAsync(Bt.mucol.ptr(), hmu.data(), m * sizeof(double), hipMemcpyHostToDevice, st));
         RR_HIP(hipMemcpyAsync(Bt.muidx.ptr(), mu_index_per_col, m * sizeof(int32_t), hipMemcpyHostToDevice, st));
 
@@ -136,6 +140,11 @@ rr_status rr_solve_batch_fused(const rr_precond* Pc, const int32_t* mu_index_per
         int graph_fallbacks = 0;
         bool eager = !o->use_graph;
         auto run_batch = [&]() {
+            if (grouped) {
+                const rr_status rs = runner->run(Bt, X, ldx);
+                if (rs != RR_OK) throw RrError{rs, "grouped PCG replay failed on the device"};
+                return;
+            }
             if (eager) {
                 for (int k = 0; k < o->check_every; ++k) Bt.iteration(X, ldx);
                 return;

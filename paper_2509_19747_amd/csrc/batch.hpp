@@ -16,10 +16,19 @@ namespace rr {
 
 constexpr int64_t KMULTI_MAX = 32;
 
+struct Batch;
+// Runs one batch of PCG iterations of a column block elsewhere (the serving loop's
+// grouped replays); returns once they have completed on the device.
+struct BatchRunner {
+    virtual ~BatchRunner() = default;
+    virtual rr_status run(Batch& bt, double* X, int64_t ldx) = 0;
+};
+
 struct Batch {
     const rr_precond& P;
     hipStream_t st;
     int64_t n, m, kb;
+    int64_t mp;           // columns of P, W and their product partials (m, or padded to whole column blocks)
     Alloc alloc;          // the handle's allocator, ordered on the solve stream
     const Alloc* al;
     DBuf R, Pm, Z, W, T, parts, C, Dall, D, state, start, target2, mucol, muidx, gws;
@@ -34,12 +43,39 @@ struct Batch {
     size_t gwsd = 0;
     std::vector<int> mus_used;
     int nch = 1;
+    // grouped layout (serving): every column pair and projection group has its own
+    // partials, so that all of them can run in one launch
+    bool grouped = false;
+    DBuf gpart;               // slot partials, gpart_doubles per column (a block at its first column)
+    size_t gpart_doubles = 0;
+    DBuf gcpart, gdcols;      // Q^T R partials (m x gch x kb) and D (m x kb) per column
 
-    Batch(const rr_precond& p, hipStream_t s, int64_t mcols)
-        : P(p), st(s), n(p.n), m(mcols), kb(p.kb), alloc(p.alloc), al(&alloc) {
+    // Width of the grouped kernel product's column block starting at column c0: four
+    // columns (the last ones zero padding) while at least three are left and the
+    // records allow it, else two or one.
+    static int mat_width(int64_t m, int64_t c0, int dm) {
+        const int64_t left = m - c0;
+        if (left >= 3 && kernel_mma_max_cols(dm) >= 4) return 4;
+        return left >= 2 ? 2 : 1;
+    }
+    static int64_t padded_cols(int64_t m, int dm) {
+        int64_t c = 0;
+        while (c < m) c += mat_width(m, c, dm);
+        return c;
+    }
+
+    Batch(const rr_precond& p, hipStream_t s, int64_t mcols, bool grouped_layout = false)
+        : P(p), st(s), n(p.n), m(mcols), kb(p.kb),
+          mp(grouped_layout && is_kernel(p.op) ? padded_cols(mcols, kernel_record_len(p.op.d)) : mcols),
+          alloc(p.alloc), al(&alloc), grouped(grouped_layout) {
         alloc.st = s;
-        const size_t nm = (size_t)n * m * sizeof(double);
-        R.reset(al, nm); Pm.reset(al, nm); Z.reset(al, nm); W.reset(al, nm); T.reset(al, nm);
+        const size_t nm = (size_t)n * m * sizeof(double), nmp = (size_t)n * mp * sizeof(double);
+        R.reset(al, nm); Pm.reset(al, nmp); Z.reset(al, nm); W.reset(al, nmp); T.reset(al, nm);
+        if (mp > m) {
+            // the padding column of the last pair is zero (and stays so: nothing updates it)
+            RR_HIP(hipMemsetAsync(Pm.ptr(), 0, nmp, st));
+            RR_HIP(hipMemsetAsync(W.ptr(), 0, nmp, st));
+        }
         nch = coldot_chunks(n);
         parts.reset(al, (size_t)nch * m * sizeof(double));
         if (kb > 0) {
@@ -59,7 +95,7 @@ struct Batch {
         kmulti = is_kernel(p.op) && p.opts.prec != RR_PREC_FP64 && m <= KMULTI_MAX;
         if (kmulti) {
             kws.reset(al, (kernel_matvec_ws_doubles(n, p.op.d, (int)std::min<int64_t>(m, 8)) + 1) * sizeof(double));
-            kdot.reset(al, (size_t)kernel_matvec_blocks(n) * m * sizeof(double));
+            kdot.reset(al, (size_t)kernel_matvec_blocks(n) * mp * sizeof(double));
         }
         rrp.reset(al, (size_t)bxr_blocks(n) * m * sizeof(double));
         cnt.reset(al, (size_t)2 * m * sizeof(int32_t));
@@ -85,6 +121,24 @@ struct Batch {
         cpart.reset(al, (size_t)pmax * gch * kb * sizeof(double));
         dcols.reset(al, (size_t)pmax * kb * sizeof(double));
         rzp.reset(al, (size_t)m * qd_blocks(n) * sizeof(double));
+        if (group_ok()) {
+            gpart_doubles = kernel_mma_ws_doubles(n, 1);
+            gpart.reset(al, (size_t)mp * gpart_doubles * sizeof(double));
+            gcpart.reset(al, (size_t)m * gch * kb * sizeof(double));
+            gdcols.reset(al, (size_t)m * kb * sizeof(double));
+        }
+    }
+
+    // The grouped iterations cover one shift, the float32-class kernel product on bf16
+    // MFMA and the streaming projection (the serving loop's requests); other column
+    // blocks run their own iterations.
+    bool group_ok() const {
+        return grouped && kmulti && single && pmax > 0 && kb > 0 && kernel_mma_ok(n, P.op.d);
+    }
+    // Width of the projection group starting at column c0 (the same grouping as precond).
+    int group_width(int64_t c0) const {
+        const int64_t left = m - c0;
+        return left >= pmax ? pmax : left >= 4 ? 4 : left >= 2 ? 2 : 1;
     }
 
     void gemm(bool ta, bool tb, int64_t M, int64_t N, int64_t K, const void* A, int64_t lda,
@@ -134,8 +188,7 @@ struct Batch {
             const double* Kc = P.per[mus_used[0]].Kc.as<double>();
             const int nb = qd_blocks(n);
             for (int64_t c0 = 0; c0 < m;) {
-                const int64_t left = m - c0;
-                const int nr = left >= pmax ? pmax : left >= 4 ? 4 : left >= 2 ? 2 : 1;
+                const int nr = group_width(c0);
                 launch_gemv_t_multi(nr, n, kb, Qb, n, Rin + c0 * n, n, cpart.as<double>(), gch, nullptr, st);
                 launch_core_apply_cols(kb, Kc, kb, cpart.as<double>(), gch, nr, dcols.as<double>(), st);
                 launch_qd_multi(nr, n, kb, Qb, n, dcols.as<double>(), Rin + c0 * n, n, 1.0, 1.0, Zout + c0 * n,

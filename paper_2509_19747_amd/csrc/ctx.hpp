@@ -234,11 +234,20 @@ void apply_projected_pair(const rr_precond& P, const double* K0, const double* K
 rr_status validate_operator(const rr_operator* A);
 void require_device();
 
+struct BatchRunner;
+// rr_solve_batch (argument checks included) with a runner for its iteration batches.
+rr_status solve_batch_with(const rr_precond* P, const int32_t* mu_index_per_col, const double* B,
+                           int64_t ldb, int32_t nrhs, double* X, int64_t ldx, const rr_solve_opts* opts,
+                           rr_solve_info* infos, void* hip_stream, BatchRunner* runner);
+
 }  // namespace rr
 
+// runner: where the column block's PCG iteration batches run (the serving loop's
+// grouped replays), nullptr for the solve's own launches or hipGraph.
 rr_status rr_solve_batch_fused(const rr_precond* P, const int32_t* mu_index_per_col,
                                const double* B, int64_t ldb, int32_t nrhs, double* X, int64_t ldx,
-                               const rr_solve_opts* o, rr_solve_info* infos, void* hip_stream);
+                               const rr_solve_opts* o, rr_solve_info* infos, void* hip_stream,
+                               rr::BatchRunner* runner = nullptr);
 rr_status rr_solve_block(const rr_precond* P, const int32_t* mu_index_per_col, const double* B, int64_t ldb,
                          int32_t nrhs, double* X, int64_t ldx, const rr_solve_opts* o, rr_solve_info* infos,
                          void* hip_stream);

@@ -227,6 +227,16 @@ void launch_kernel_matvec_multi(const KernelOp& op, bool fp64, const double* u, 
 // float32-class entries, float64 sums), nr in {1, 2} (kernels_ksym_mma.hip).
 bool kernel_mma_ok(int64_t n, int d);
 size_t kernel_mma_ws_doubles(int64_t n, int nr);
+// Work-item plan of the MFMA kernel product (row blocks nb, column blocks per run m,
+// column ranges S, items per column block of the launch).
+struct KmmaPlanInfo {
+    int nb, m, S;
+    int64_t items;
+};
+KmmaPlanInfo kernel_mma_plan_info(int64_t n);
+// Columns one MFMA kernel product may carry with float64 sums (4 for records of up to
+// 16 terms, else 2); each column's arithmetic is the same whatever the width.
+int kernel_mma_max_cols(int dm);
 // a32: float32 products and partial sums (estimate grade, power iterations).
 void launch_kernel_matvec_mma(const KernelOp& op, const double* u, int nr, double mu, double* y,
                               double* dot_part, double* ws, const int32_t* stop, hipStream_t st,
@@ -300,6 +310,7 @@ void launch_select_cols(int64_t k, int64_t m, const double* Dall, const int32_t*
 // ------------------------------------------------------ projections
 // c_part[chunk * k + j] = sum_{i in chunk} Q[i, j] r[i]; returns number of chunks.
 int gemv_t_chunks(int64_t n, int64_t k);
+int64_t gemv_t_rows_per_chunk_of(int64_t n, int64_t k);   // rows of each of those chunks
 void launch_gemv_t(int64_t n, int64_t k, const double* Q, int64_t ldq, const double* r,
                    double* c_part, int nchunks, const int32_t* stop, hipStream_t st);
 // nr = 1 or 2 vectors (R: n x nr, leading dimension ldr); vector q's partials at

@@ -9,6 +9,7 @@
 //  * per-column dot partials, scalar steps and vector updates with a per-column
 //      run flag: converged or restarting columns are left untouched.
 #include "common.hpp"
+#include "group.hpp"
 #include "kentry.hpp"
 #include "kernels.hpp"
 #include "prof.hpp"
@@ -240,9 +241,9 @@ RR_DEV double colsum_block(const ColParts& pt, int64_t j, double* sc) {
     for (int c = threadIdx.x; c < pt.nch; c += blockDim.x) v += pt.p[(int64_t)c * pt.cs + j * pt.js];
     return block_sum(v, sc);
 }
-RR_DEV bool last_block_of_column(int32_t* cnt, int64_t j, int* flag) {
+RR_DEV bool last_block_of_column(int32_t* cnt, int64_t j, int nbx, int* flag) {
     __threadfence();   // this block's partials and vector updates are visible device-wide
-    if (threadIdx.x == 0) *flag = atomicAdd(&cnt[j], 1) == (int)gridDim.x - 1;
+    if (threadIdx.x == 0) *flag = atomicAdd(&cnt[j], 1) == nbx - 1;
     __syncthreads();
     if (!*flag) return false;
     __threadfence();   // the other blocks' partials are read after this point
@@ -250,31 +251,29 @@ RR_DEV bool last_block_of_column(int32_t* cnt, int64_t j, int* flag) {
 }
 
 // alpha_j = rho_j / p_j^T w_j; x_j += alpha_j p_j, r_j -= alpha_j w_j, partials of
-// ||r_j||^2; last block: pw, alpha, ||r||^2, the iteration count and the stop tests
-__global__ __launch_bounds__(BC_THREADS) void k_bxr_fused(int64_t n, double* __restrict__ X, int64_t ldx,
-                                                         double* __restrict__ R, const double* __restrict__ P,
-                                                         const double* __restrict__ W, BState* st, ColParts pw,
-                                                         double* __restrict__ rr_part, int32_t* cnt) {
+// ||r_j||^2; last block: pw, alpha, ||r||^2, the iteration count and the stop tests.
+// Block bx of the nbx blocks of column j (shared with the grouped serving kernel).
+RR_DEV void bxr_block(int bx, int nbx, int64_t j, int64_t n, double* __restrict__ X, int64_t ldx,
+                      double* __restrict__ R, const double* __restrict__ P, const double* __restrict__ W,
+                      BState* st, const ColParts& pw, double* __restrict__ rr_part, int32_t* cnt) {
     __shared__ double sc[BC_THREADS / WAVE];
     __shared__ int last;
-    const int64_t j = blockIdx.y;
     if (!st[j].run) return;
     const double pwj = colsum_block(pw, j, sc);
     const bool ok = pwj > 0.0 && isfinite(pwj);
     const double a = ok ? st[j].rho / pwj : 0.0;
     double acc = 0.0;
     if (ok)
-        for (int64_t i = (int64_t)blockIdx.x * BC_THREADS + threadIdx.x; i < n;
-             i += (int64_t)gridDim.x * BC_THREADS) {
+        for (int64_t i = (int64_t)bx * BC_THREADS + threadIdx.x; i < n; i += (int64_t)nbx * BC_THREADS) {
             X[i + j * ldx] = fma(a, P[i + j * n], X[i + j * ldx]);
             const double ri = fma(-a, W[i + j * n], R[i + j * n]);
             R[i + j * n] = ri;
             acc = fma(ri, ri, acc);
         }
     acc = block_sum(acc, sc);
-    if (threadIdx.x == 0) rr_part[j * gridDim.x + blockIdx.x] = acc;
-    if (!last_block_of_column(cnt, j, &last)) return;
-    const double rr = colsum_block(ColParts{rr_part, (int)gridDim.x, 1, (int64_t)gridDim.x}, j, sc);
+    if (threadIdx.x == 0) rr_part[j * nbx + bx] = acc;
+    if (!last_block_of_column(cnt, j, nbx, &last)) return;
+    const double rr = colsum_block(ColParts{rr_part, nbx, 1, (int64_t)nbx}, j, sc);
     if (threadIdx.x != 0) return;
     cnt[j] = 0;
     st[j].pw = pwj;
@@ -287,28 +286,36 @@ __global__ __launch_bounds__(BC_THREADS) void k_bxr_fused(int64_t n, double* __r
     else if (rr <= st[j].target2) { st[j].run = 0; st[j].code = STOP_TARGET; }
     else if (it >= st[j].maxit) { st[j].run = 0; st[j].code = STOP_MAXIT; }
 }
+__global__ __launch_bounds__(BC_THREADS) void k_bxr_fused(int64_t n, double* __restrict__ X, int64_t ldx,
+                                                         double* __restrict__ R, const double* __restrict__ P,
+                                                         const double* __restrict__ W, BState* st, ColParts pw,
+                                                         double* __restrict__ rr_part, int32_t* cnt) {
+    bxr_block(blockIdx.x, gridDim.x, blockIdx.y, n, X, ldx, R, P, W, st, pw, rr_part, cnt);
+}
 
 // beta_j = r_j^T z_j / rho_j; p_j = z_j + beta_j p_j; last block: beta, rho
-__global__ __launch_bounds__(BC_THREADS) void k_bp_fused(int64_t n, const double* __restrict__ Z,
-                                                        double* __restrict__ P, BState* st, ColParts rz,
-                                                        int32_t* cnt) {
+RR_DEV void bp_block(int bx, int nbx, int64_t j, int64_t n, const double* __restrict__ Z,
+                     double* __restrict__ P, BState* st, const ColParts& rz, int32_t* cnt) {
     __shared__ double sc[BC_THREADS / WAVE];
     __shared__ int last;
-    const int64_t j = blockIdx.y;
     if (!st[j].run) return;
     const double rzj = colsum_block(rz, j, sc);
     const bool ok = rzj > 0.0 && isfinite(rzj);
     const double b = ok ? rzj / st[j].rho : 0.0;
     if (ok)
-        for (int64_t i = (int64_t)blockIdx.x * BC_THREADS + threadIdx.x; i < n;
-             i += (int64_t)gridDim.x * BC_THREADS)
+        for (int64_t i = (int64_t)bx * BC_THREADS + threadIdx.x; i < n; i += (int64_t)nbx * BC_THREADS)
             P[i + j * n] = fma(b, P[i + j * n], Z[i + j * n]);
-    if (!last_block_of_column(cnt, j, &last)) return;
+    if (!last_block_of_column(cnt, j, nbx, &last)) return;
     if (threadIdx.x != 0) return;
     cnt[j] = 0;
     if (!ok) { st[j].run = 0; st[j].code = STOP_BREAKDOWN; return; }
     st[j].beta = b;
     st[j].rho = rzj;
+}
+__global__ __launch_bounds__(BC_THREADS) void k_bp_fused(int64_t n, const double* __restrict__ Z,
+                                                        double* __restrict__ P, BState* st, ColParts rz,
+                                                        int32_t* cnt) {
+    bp_block(blockIdx.x, gridDim.x, blockIdx.y, n, Z, P, st, rz, cnt);
 }
 
 void launch_bxr_fused(int64_t n, int64_t m, double* X, int64_t ldx, double* R, const double* P,
@@ -365,6 +372,47 @@ void launch_select_cols(int64_t k, int64_t m, const double* Dall, const int32_t*
     int64_t g = (k * m + 255) / 256;
     if (g > 65536) g = 65536;
     k_select_cols<<<(int)g, 256, 0, s>>>(k, m, Dall, mu_idx, D);
+}
+
+// ------------------------------------------------------------------ grouped
+// The x, r and p updates of many requests in one persistent launch each: work item
+// w of the list belongs to the request whose first item is the largest <= w; its
+// offset w - w0 is block (w - w0) % nbx of column (w - w0) / nbx, the block that
+// k_bxr_fused / k_bp_fused would run.
+template <bool BP>
+__global__ __launch_bounds__(BC_THREADS) void k_group_vec(const GTable* __restrict__ tab,
+                                                          const GVec* __restrict__ units, int32_t* ctr) {
+    __shared__ int32_t wsh;
+    constexpr int L = BP ? GL_BP : GL_BXR;
+    const int32_t off = gu(tab->list[L].off), cnt = gu(tab->list[L].count), total = gu(tab->list[L].total);
+    GroupCursor cur(ctr, &wsh);
+    while (true) {
+        const int32_t w = cur.next();
+        if (w >= total) return;
+        const int32_t ui = group_find(units, off, off + cnt, w, [](const GVec& g) { return g.w0; });
+        const GVec& g = units[ui];
+        const int32_t nbx = gu(g.nbx), loc = w - gu(g.w0);
+        const int64_t j = loc / nbx;
+        const ColParts pt{gu(g.pw.p), gu(g.pw.nch), gu(g.pw.cs), gu(g.pw.js)};
+        const ColParts rz{gu(g.rz.p), gu(g.rz.nch), gu(g.rz.cs), gu(g.rz.js)};
+        if (BP)
+            bp_block(loc % nbx, nbx, j, gu(g.n), gu(g.Z), gu(g.P), gu(g.st), rz, gu(g.cnt) + gu(g.m));
+        else
+            bxr_block(loc % nbx, nbx, j, gu(g.n), gu(g.X), gu(g.ldx), gu(g.R), gu(g.P), gu(g.W), gu(g.st), pt,
+                      gu(g.rr_part), gu(g.cnt));
+    }
+}
+
+void launch_group_vec(bool bp, int blocks, const GTable* tab, const GVec* vecs, int32_t* ctr, hipStream_t st) {
+    if (bp) k_group_vec<true><<<blocks, BC_THREADS, 0, st>>>(tab, vecs, ctr);
+    else k_group_vec<false><<<blocks, BC_THREADS, 0, st>>>(tab, vecs, ctr);
+}
+
+__global__ void k_group_reset(int32_t* ctr, int ncount) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < ncount; i += gridDim.x * blockDim.x) ctr[i] = 0;
+}
+void launch_group_reset(int32_t* ctr, int ncount, hipStream_t st) {
+    k_group_reset<<<(ncount + 255) / 256, 256, 0, st>>>(ctr, ncount);
 }
 
 }  // namespace rr

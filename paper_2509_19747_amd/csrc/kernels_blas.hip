@@ -5,6 +5,7 @@
 // vector/scalar steps (Algorithm RandRAND_PCG).  Every reduction runs in a
 // fixed order, so results are bitwise reproducible run to run.
 #include "common.hpp"
+#include "group.hpp"
 #include "kernels.hpp"
 #include "prof.hpp"
 
@@ -451,17 +452,14 @@ void launch_dense_matvec(int dta, int64_t n, const void* A, int64_t lda, const d
 constexpr int GT_COLS = 4;
 constexpr int GT_THREADS = 256;
 
+// Block (bx, ch): columns GT_COLS bx .. of Q over row chunk ch (shared with the
+// grouped serving kernel).
 template <int NR>
-__global__ __launch_bounds__(GT_THREADS) void k_gemv_t(int64_t n, int64_t k,
-                                                       const double* __restrict__ Q, int64_t ldq,
-                                                       const double* __restrict__ R, int64_t ldr,
-                                                       double* __restrict__ c_part, int nchunks,
-                                                       int64_t rows_per_chunk,
-                                                       const int32_t* __restrict__ stop) {
+RR_DEV void gemv_t_block(int bx, int ch, int64_t n, int64_t k, const double* __restrict__ Q, int64_t ldq,
+                         const double* __restrict__ R, int64_t ldr, double* __restrict__ c_part, int nchunks,
+                         int64_t rows_per_chunk) {
     __shared__ double red[GT_COLS * NR][GT_THREADS / WAVE];
-    if (stop && *stop) return;
-    const int64_t j0 = (int64_t)blockIdx.x * GT_COLS;
-    const int64_t ch = blockIdx.y;
+    const int64_t j0 = (int64_t)bx * GT_COLS;
     const int64_t ib = ch * rows_per_chunk;
     const int64_t ie = (ib + rows_per_chunk < n) ? ib + rows_per_chunk : n;
     double acc[GT_COLS][NR];
@@ -516,9 +514,19 @@ __global__ __launch_bounds__(GT_THREADS) void k_gemv_t(int64_t n, int64_t k,
         if (j < k) {
             double s = 0.0;
             for (int w2 = 0; w2 < GT_THREADS / WAVE; ++w2) s += red[threadIdx.x][w2];
-            c_part[(int64_t)q * nchunks * k + ch * k + j] = s;
+            c_part[(int64_t)q * nchunks * k + (int64_t)ch * k + j] = s;
         }
     }
+}
+template <int NR>
+__global__ __launch_bounds__(GT_THREADS) void k_gemv_t(int64_t n, int64_t k,
+                                                       const double* __restrict__ Q, int64_t ldq,
+                                                       const double* __restrict__ R, int64_t ldr,
+                                                       double* __restrict__ c_part, int nchunks,
+                                                       int64_t rows_per_chunk,
+                                                       const int32_t* __restrict__ stop) {
+    if (stop && *stop) return;
+    gemv_t_block<NR>(blockIdx.x, blockIdx.y, n, k, Q, ldq, R, ldr, c_part, nchunks, rows_per_chunk);
 }
 
 static int64_t gemv_t_rows_per_chunk(int64_t n, int64_t k) {
@@ -530,6 +538,8 @@ static int64_t gemv_t_rows_per_chunk(int64_t n, int64_t k) {
     if (chunks > 64) chunks = 64;
     return (n + chunks - 1) / chunks;
 }
+
+int64_t gemv_t_rows_per_chunk_of(int64_t n, int64_t k) { return gemv_t_rows_per_chunk(n, k); }
 
 int gemv_t_chunks(int64_t n, int64_t k) {
     const int64_t rpc = gemv_t_rows_per_chunk(n, k);
@@ -559,23 +569,19 @@ void launch_gemv_t(int64_t n, int64_t k, const double* Q, int64_t ldq, const dou
 constexpr int CA_ROWS = 4;
 // blockIdx.y = 2 (launch_core_apply_triple): core K2 on column 1's c, into d[2k:3k);
 // c_out, when given, receives column 1's c.
-__global__ __launch_bounds__(256) void k_core_apply(int64_t k, const double* __restrict__ K0,
-                                                    const double* __restrict__ K1, int64_t ldk,
-                                                    const double* __restrict__ c_part, int nchunks,
-                                                    double* __restrict__ d,
-                                                    const int32_t* __restrict__ stop,
-                                                    const double* __restrict__ K2 = nullptr,
-                                                    double* __restrict__ c_out = nullptr,
-                                                    bool shared_core = false) {
+// Block (bx, q): rows CA_ROWS bx .. of d for column q (shared with the grouped
+// serving kernel).
+RR_DEV void core_apply_block(int bx, int q, int64_t k, const double* __restrict__ K0,
+                             const double* __restrict__ K1, int64_t ldk, const double* __restrict__ c_part,
+                             int nchunks, double* __restrict__ d, const double* __restrict__ K2,
+                             double* __restrict__ c_out, bool shared_core) {
     __shared__ double red[CA_ROWS][256 / WAVE];
-    if (stop && *stop) return;
-    const int q = blockIdx.y;
     // shared_core: column q of c_part with core K0 (any number of columns);
     // otherwise the pair / triple layout above
     const double* __restrict__ Kc = shared_core ? K0 : q == 0 ? K0 : q == 1 ? K1 : K2;
     const double* __restrict__ cp = c_part + (int64_t)(shared_core ? q : (q ? 1 : 0)) * nchunks * k;
-    const bool write_c = c_out && q == 1 && blockIdx.x == 0;
-    const int64_t i0 = (int64_t)blockIdx.x * CA_ROWS;
+    const bool write_c = c_out && q == 1 && bx == 0;
+    const int64_t i0 = (int64_t)bx * CA_ROWS;
     double acc[CA_ROWS];
 #pragma unroll
     for (int r = 0; r < CA_ROWS; ++r) acc[r] = 0.0;
@@ -610,6 +616,17 @@ __global__ __launch_bounds__(256) void k_core_apply(int64_t k, const double* __r
         d[(int64_t)q * k + i0 + threadIdx.x] = s;
     }
 }
+__global__ __launch_bounds__(256) void k_core_apply(int64_t k, const double* __restrict__ K0,
+                                                    const double* __restrict__ K1, int64_t ldk,
+                                                    const double* __restrict__ c_part, int nchunks,
+                                                    double* __restrict__ d,
+                                                    const int32_t* __restrict__ stop,
+                                                    const double* __restrict__ K2 = nullptr,
+                                                    double* __restrict__ c_out = nullptr,
+                                                    bool shared_core = false) {
+    if (stop && *stop) return;
+    core_apply_block(blockIdx.x, blockIdx.y, k, K0, K1, ldk, c_part, nchunks, d, K2, c_out, shared_core);
+}
 
 void launch_core_apply(int64_t k, const double* Kc, int64_t ldk, const double* c_part,
                        int nchunks, double* d, const int32_t* stop, hipStream_t st) {
@@ -640,22 +657,17 @@ void launch_core_apply_triple(int64_t k, const double* K0, const double* K1, con
 // their partial row sums in a fixed order.
 constexpr int QD_ROWS = 64;
 constexpr int QD_THREADS = 256;
+// Block bx of the nblk row blocks; d_sh: LDS for NR * k doubles (shared with the
+// grouped serving kernel).
 template <int NR>
-__global__ __launch_bounds__(QD_THREADS) void k_qd(int64_t n, int64_t k,
-                                                   const double* __restrict__ Q, int64_t ldq,
-                                                   const double* __restrict__ D,
-                                                   const double* __restrict__ R, int64_t ldr,
-                                                   double rc0, double rc1,
-                                                   double* __restrict__ Z,
-                                                   double* __restrict__ rz_part,
-                                                   const int32_t* __restrict__ stop) {
-    extern __shared__ double d_sh[];   // NR * k
+RR_DEV void qd_block(int bx, int nblk, int64_t n, int64_t k, const double* __restrict__ Q, int64_t ldq,
+                     const double* __restrict__ D, const double* __restrict__ R, int64_t ldr, double rc0,
+                     double rc1, double* __restrict__ Z, double* __restrict__ rz_part, double* d_sh) {
     __shared__ double part[QD_THREADS / WAVE][NR][QD_ROWS];
-    if (stop && *stop) return;
     for (int64_t e = threadIdx.x; e < (int64_t)NR * k; e += QD_THREADS) d_sh[e] = D[e];
     __syncthreads();
     const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
-    const int64_t i = (int64_t)blockIdx.x * QD_ROWS + lane;
+    const int64_t i = (int64_t)bx * QD_ROWS + lane;
     const int64_t per = (k + 3) / 4;
     const int64_t jb = w * per, je = (jb + per < k) ? jb + per : k;
     double acc[NR][2];
@@ -694,9 +706,22 @@ __global__ __launch_bounds__(QD_THREADS) void k_qd(int64_t n, int64_t k,
                 rz = ri * zi;
             }
             rz = wave_sum(rz);
-            if (lane == 0) rz_part[(int64_t)q * gridDim.x + blockIdx.x] = rz;
+            if (lane == 0) rz_part[(int64_t)q * nblk + bx] = rz;
         }
     }
+}
+template <int NR>
+__global__ __launch_bounds__(QD_THREADS) void k_qd(int64_t n, int64_t k,
+                                                   const double* __restrict__ Q, int64_t ldq,
+                                                   const double* __restrict__ D,
+                                                   const double* __restrict__ R, int64_t ldr,
+                                                   double rc0, double rc1,
+                                                   double* __restrict__ Z,
+                                                   double* __restrict__ rz_part,
+                                                   const int32_t* __restrict__ stop) {
+    extern __shared__ double d_sh[];   // NR * k
+    if (stop && *stop) return;
+    qd_block<NR>(blockIdx.x, gridDim.x, n, k, Q, ldq, D, R, ldr, rc0, rc1, Z, rz_part, d_sh);
 }
 
 int qd_blocks(int64_t n) { return (int)((n + QD_ROWS - 1) / QD_ROWS); }
@@ -955,5 +980,98 @@ void launch_normalize_pair(int64_t n, double* v0, const double* src0, const doub
                            int64_t k, double* lam1, hipStream_t st) {
     k_normalize_pair<<<dim3((unsigned)vec_blocks(n), 2), 256, 0, st>>>(n, v0, src0, part0, count0, lam0, v1,
                                                                         src1, a, b, k, lam1);
+}
+
+// ------------------------------------------------------------------ grouped
+// The projection of many column groups (of many requests) in one persistent launch
+// per kernel and width: a group's items are the blocks k_gemv_t, k_core_apply and
+// k_qd would run for it.  Groups whose columns have all stopped are skipped.
+RR_DEV bool group_proj_runs(const GProj& g) {
+    const BState* st = gu(g.st);
+    const int32_t nr = gu(g.nr);
+    for (int32_t q = 0; q < nr; ++q)
+        if (gu(st[q].run)) return true;
+    return false;
+}
+
+template <int NR>
+__global__ __launch_bounds__(GT_THREADS) void k_group_gemv(const GTable* __restrict__ tab, int list,
+                                                           const GProj* __restrict__ units, int32_t* ctr) {
+    __shared__ int32_t wsh;
+    const int32_t off = gu(tab->list[list].off), cnt = gu(tab->list[list].count);
+    const int32_t total = gu(tab->list[list].total);
+    GroupCursor cur(ctr, &wsh);
+    while (true) {
+        const int32_t w = cur.next();
+        if (w >= total) return;
+        const int32_t ui = group_find(units, off, off + cnt, w, [](const GProj& g) { return g.w_gemv; });
+        const GProj& g = units[ui];
+        if (!group_proj_runs(g)) continue;
+        const int32_t cblk = gu(g.cblk), loc = w - gu(g.w_gemv);
+        const int64_t n = gu(g.n);
+        gemv_t_block<NR>(loc % cblk, loc / cblk, n, gu(g.k), gu(g.Q), n, gu(g.R), n, gu(g.cpart), gu(g.nch),
+                         gu(g.rpc));
+    }
+}
+
+__global__ __launch_bounds__(256) void k_group_core(const GTable* __restrict__ tab,
+                                                    const GProj* __restrict__ units, int32_t* ctr) {
+    __shared__ int32_t wsh;
+    const int32_t off = gu(tab->list[GL_CORE].off), cnt = gu(tab->list[GL_CORE].count);
+    const int32_t total = gu(tab->list[GL_CORE].total);
+    GroupCursor cur(ctr, &wsh);
+    while (true) {
+        const int32_t w = cur.next();
+        if (w >= total) return;
+        const int32_t ui = group_find(units, off, off + cnt, w, [](const GProj& g) { return g.w_core; });
+        const GProj& g = units[ui];
+        if (!group_proj_runs(g)) continue;
+        const int64_t k = gu(g.k);
+        const int32_t rb = (int32_t)((k + CA_ROWS - 1) / CA_ROWS), loc = w - gu(g.w_core);
+        const double* Kc = gu(g.Kc);
+        core_apply_block(loc % rb, loc / rb, k, Kc, Kc, k, gu(g.cpart), gu(g.nch), gu(g.D), Kc, nullptr, true);
+    }
+}
+
+template <int NR>
+__global__ __launch_bounds__(QD_THREADS) void k_group_qd(const GTable* __restrict__ tab, int list,
+                                                         const GProj* __restrict__ units, int32_t* ctr) {
+    extern __shared__ double d_sh[];   // NR * group_qd_kmax(NR)
+    __shared__ int32_t wsh;
+    const int32_t off = gu(tab->list[list].off), cnt = gu(tab->list[list].count);
+    const int32_t total = gu(tab->list[list].total);
+    GroupCursor cur(ctr, &wsh);
+    while (true) {
+        const int32_t w = cur.next();
+        if (w >= total) return;
+        const int32_t ui = group_find(units, off, off + cnt, w, [](const GProj& g) { return g.w_qd; });
+        const GProj& g = units[ui];
+        if (!group_proj_runs(g)) continue;
+        const int64_t n = gu(g.n);
+        qd_block<NR>(w - gu(g.w_qd), gu(g.nbq), n, gu(g.k), gu(g.Q), n, gu(g.D), gu(g.R), n, 1.0, 1.0, gu(g.Z),
+                     gu(g.rz), d_sh);
+    }
+}
+
+void launch_group_proj(int list, int blocks, const GTable* tab, const GProj* projs, int32_t* ctr, hipStream_t st) {
+    if (list == GL_CORE) {
+        k_group_core<<<blocks, 256, 0, st>>>(tab, projs, ctr);
+    } else if (list >= GL_GEMV && list < GL_GEMV + 4) {
+        switch (list - GL_GEMV) {
+            case 3: k_group_gemv<8><<<blocks, GT_THREADS, 0, st>>>(tab, list, projs, ctr); break;
+            case 2: k_group_gemv<4><<<blocks, GT_THREADS, 0, st>>>(tab, list, projs, ctr); break;
+            case 1: k_group_gemv<2><<<blocks, GT_THREADS, 0, st>>>(tab, list, projs, ctr); break;
+            default: k_group_gemv<1><<<blocks, GT_THREADS, 0, st>>>(tab, list, projs, ctr); break;
+        }
+    } else {
+#define KGQ(R) k_group_qd<R><<<blocks, QD_THREADS, (size_t)R * group_qd_kmax(R) * sizeof(double), st>>>(tab, list, projs, ctr)
+        switch (list - GL_QD) {
+            case 3: KGQ(8); break;
+            case 2: KGQ(4); break;
+            case 1: KGQ(2); break;
+            default: KGQ(1); break;
+        }
+#undef KGQ
+    }
 }
 }  // namespace rr

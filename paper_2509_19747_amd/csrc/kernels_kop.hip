@@ -208,7 +208,8 @@ size_t kernel_matvec_ws_doubles(int64_t n, int d, int nr) {
     size_t w = (size_t)2 * (size_t)kmv64_slices(n) * (size_t)n;
     for (int c = 1; c <= 8; c *= 2)
         if (c == 1 || c <= nr) w = std::max(w, kernel_sym_ws_doubles(n, d, c));
-    if (kernel_mma_ok(n, d)) w = std::max(w, kernel_mma_ws_doubles(n, std::min(nr, 2)));
+    if (kernel_mma_ok(n, d))
+        w = std::max(w, kernel_mma_ws_doubles(n, std::min(nr, kernel_mma_max_cols(kernel_record_len(d)))));
     w = std::max(w, kernel_sym64_ws_doubles(n, d, std::min(nr, 2)));
     return w;
 }
@@ -216,7 +217,8 @@ size_t kernel_matvec_ws_doubles(int64_t n, int d, int nr) {
 size_t kernel_matvec_ws_doubles_for(int64_t n, int d, int nr, bool fp64) {
     if (fp64) return kernel_mma_ok(n, d) ? kernel_mma_ws_doubles(n, std::min(nr, 2))
                                          : kernel_sym64_ws_doubles(n, d, std::min(nr, 2));
-    if (kernel_mma_ok(n, d)) return kernel_mma_ws_doubles(n, std::min(nr, 2));
+    if (kernel_mma_ok(n, d))
+        return kernel_mma_ws_doubles(n, std::min(nr, kernel_mma_max_cols(kernel_record_len(d))));
     size_t w = 0;
     for (int c = 1; c <= 8; c *= 2)
         if (c == 1 || c <= nr) w = std::max(w, kernel_sym_ws_doubles(n, d, c));
@@ -246,11 +248,13 @@ void launch_kernel_matvec_multi(const KernelOp& op, bool fp64, const double* u, 
                                                          stop);
             q0 += c;
         } else if (kernel_mma_ok(op.n, op.d)) {
-            // pair terms on bf16 MFMA, two columns at a time: every column goes through
-            // the same arithmetic whatever the block width, so a column solved alone
-            // and inside a block gives bitwise the same products (this path also
-            // serves the power iterations)
-            const int c = left >= 2 ? 2 : 1;
+            // pair terms on bf16 MFMA, up to four columns at a time (two for the
+            // estimate grade and the longest records): every column goes through the
+            // same arithmetic whatever the block width, so a column solved alone and
+            // inside a block gives bitwise the same products (this path also serves
+            // the power iterations)
+            const int cmax = estimate ? 2 : kernel_mma_max_cols(op.dm);
+            const int c = left >= 4 && cmax >= 4 ? 4 : left >= 2 ? 2 : 1;
             launch_kernel_matvec_mma(op, uq, c, mu, yq, dq, ws, stop, st, estimate);
             q0 += c;
         } else {

@@ -25,6 +25,7 @@
 // reproducible).
 //
 #include "common.hpp"
+#include "group.hpp"
 #include "kentry.hpp"
 #include "kernels.hpp"
 #include "kmma.hpp"
@@ -98,24 +99,24 @@ RR_DEV T kmma_rowsum16(T (&v)[16], int l32) {
     return w1 + __shfl_xor(w1, 1, 64);
 }
 
-// T: the type of the products and partial sums (double; float for the estimate
-// grade of the power iterations, whose per-item partials are still stored as double).
+// One work item of the block (see above).  T: the type of the products and partial
+// sums (double; float for the estimate grade of the power iterations, whose per-item
+// partials are still stored as double).  Shared by k_ksym_mma (item = block index)
+// and the grouped serving kernel (items of many operators in one launch).
 template <int KIND, int DM, int NR, typename T>
-__global__ __launch_bounds__(KM_THREADS) __attribute__((amdgpu_waves_per_eu(NR * sizeof(T) <= 8 ? 4 : 2))) void k_ksym_mma(
-    int64_t n, const float* __restrict__ xa, const float* __restrict__ sqn, float c,
-    const double* __restrict__ u, double* __restrict__ part, int nb, int m, int S,
-    const int32_t* __restrict__ stop) {
+RR_DEV void ksym_mma_item(unsigned item, int64_t n, const float* __restrict__ xa, const float* __restrict__ sqn,
+                          float c, const double* __restrict__ u, double* __restrict__ part, int nb, int m,
+                          int S) {
     using Sh = KmmaShape<DM>;
     constexpr int KB = Sh::KB, BSTR = Sh::BSTR;
     __shared__ __attribute__((aligned(16))) __bf16 bs[KM_RB * BSTR];   // column records (B layout)
     __shared__ T us[NR][KM_RB];                                         // column u_j
     __shared__ __attribute__((aligned(16))) T ur[NR][KM_RB];            // row u_i
     __shared__ T colw[KM_WAVES][NR][KM_RB];                             // column partials per wave
-    if (stop && *stop) return;
 
     // item -> (bi, r, s)
-    int64_t t = blockIdx.x / S;
-    const int sr = (int)(blockIdx.x % S);
+    int64_t t = item / S;
+    const int sr = (int)(item % S);
     int bi = 0;
     while (t >= (nb - bi + m - 1) / m) { t -= (nb - bi + m - 1) / m; ++bi; }
     const int run = (int)t;
@@ -278,6 +279,15 @@ __global__ __launch_bounds__(KM_THREADS) __attribute__((amdgpu_waves_per_eu(NR *
     }
 }
 
+template <int KIND, int DM, int NR, typename T>
+__global__ __launch_bounds__(KM_THREADS) __attribute__((amdgpu_waves_per_eu(NR * sizeof(T) <= 8 ? 4 : 2))) void k_ksym_mma(
+    int64_t n, const float* __restrict__ xa, const float* __restrict__ sqn, float c,
+    const double* __restrict__ u, double* __restrict__ part, int nb, int m, int S,
+    const int32_t* __restrict__ stop) {
+    if (stop && *stop) return;
+    ksym_mma_item<KIND, DM, NR, T>(blockIdx.x, n, xa, sqn, c, u, part, nb, m, S);
+}
+
 // y_q = scale * (sum of row i's slots) + mu u_q, with block partials of u_q^T y_q.
 // Block: the 256 rows of one row block b (so the slot list is uniform over the
 // block) and 1024 threads: four groups of 256 split the list
@@ -285,21 +295,18 @@ __global__ __launch_bounds__(KM_THREADS) __attribute__((amdgpu_waves_per_eu(NR *
 // into four contiguous quarters, each summed with four running sums, and group 0
 // adds the quarters in a fixed order (bitwise reproducible, the same for one or
 // two columns).
+// Block bx of the nblk = ceil(n / 256) blocks of one finish (shared with the grouped
+// serving kernel).
 constexpr int KF_GROUPS = 4;
-__global__ __launch_bounds__(256 * KF_GROUPS) void k_ksym_mma_finish(int64_t n, int rb, int nb, int m, int S,
-                                                                     int nr,
-                                                                     const double* __restrict__ part,
-                                                                     double scale, double mu,
-                                                                     const double* __restrict__ u,
-                                                                     double* __restrict__ y,
-                                                                     double* __restrict__ dot_part,
-                                                                     const int32_t* __restrict__ stop) {
+RR_DEV void ksym_mma_finish_block(unsigned bx, unsigned nblk, int64_t n, int rb, int nb, int m, int S, int nr,
+                                  const double* __restrict__ part, double scale, double mu,
+                                  const double* __restrict__ u, double* __restrict__ y,
+                                  double* __restrict__ dot_part) {
     __shared__ double quart[KF_GROUPS - 1][256];
     __shared__ double sc[4];
-    if (stop && *stop) return;
     const int t = threadIdx.x & 255, g = threadIdx.x >> 8;
-    const int64_t i = (int64_t)blockIdx.x * 256 + t;
-    const int b = (int)(((int64_t)blockIdx.x * 256) / rb);
+    const int64_t i = (int64_t)bx * 256 + t;
+    const int b = (int)(((int64_t)bx * 256) / rb);
     const int64_t z1 = (int64_t)(b + (nb - b + m - 1) / m) * S;
     const int64_t nrun = z1 - (int64_t)b * S;
     const int64_t T = b + nrun + 1;
@@ -335,9 +342,21 @@ __global__ __launch_bounds__(256 * KF_GROUPS) void k_ksym_mma_finish(int64_t n, 
         }
         __syncthreads();
         if (threadIdx.x == 0)
-            dot_part[(int64_t)q * gridDim.x + blockIdx.x] = (sc[0] + sc[1]) + (sc[2] + sc[3]);
+            dot_part[(int64_t)q * nblk + bx] = (sc[0] + sc[1]) + (sc[2] + sc[3]);
         __syncthreads();
     }
+}
+
+__global__ __launch_bounds__(256 * KF_GROUPS) void k_ksym_mma_finish(int64_t n, int rb, int nb, int m, int S,
+                                                                     int nr,
+                                                                     const double* __restrict__ part,
+                                                                     double scale, double mu,
+                                                                     const double* __restrict__ u,
+                                                                     double* __restrict__ y,
+                                                                     double* __restrict__ dot_part,
+                                                                     const int32_t* __restrict__ stop) {
+    if (stop && *stop) return;
+    ksym_mma_finish_block(blockIdx.x, gridDim.x, n, rb, nb, m, S, nr, part, scale, mu, u, y, dot_part);
 }
 
 // ------------------------------------------------------------------ float64
@@ -564,14 +583,24 @@ static void kmma_dispatch(const KernelOp& op, float c, const double* u, double* 
         case 4: KML(4); break;
         case 8: KML(8); break;
         case 16: KML(16); break;
-        default: KML(32); break;
+        default:
+            // four columns of 32-term records exceed the LDS (callers use at most two)
+            if constexpr (NR <= 2) KML(32);
+            break;
     }
 #undef KML
 }
 
+int kernel_mma_max_cols(int dm) { return dm <= 16 ? 4 : 2; }
+
 bool kernel_mma_ok(int64_t n, int d) {
     const KmmaPlan p = kmma_plan(n);
     return d <= 32 && (int64_t)p.nb * p.S + 1 <= KM_MAX_SLOTS;
+}
+
+KmmaPlanInfo kernel_mma_plan_info(int64_t n) {
+    const KmmaPlan p = kmma_plan(n);
+    return KmmaPlanInfo{p.nb, p.m, p.S, p.items};
 }
 
 size_t kernel_mma_ws_doubles(int64_t n, int nr) {
@@ -579,9 +608,9 @@ size_t kernel_mma_ws_doubles(int64_t n, int nr) {
     return ((size_t)p.nb * p.S + 1) * nr * (size_t)n;
 }
 
-// nr in {1, 2}; u, y column-major with leading dimension n; ws holds
-// kernel_mma_ws_doubles(n, nr) doubles.  a32: float32 products and partial sums
-// (estimate grade).
+// nr in {1, 2} (also 4 with float64 sums when kernel_mma_max_cols(dm) allows); u, y
+// column-major with leading dimension n; ws holds kernel_mma_ws_doubles(n, nr) doubles.
+// a32: float32 products and partial sums (estimate grade, nr <= 2).
 void launch_kernel_matvec_mma(const KernelOp& op, const double* u, int nr, double mu, double* y,
                               double* dot_part, double* ws, const int32_t* stop, hipStream_t st,
                               bool a32) {
@@ -595,7 +624,8 @@ void launch_kernel_matvec_mma(const KernelOp& op, const double* u, int nr, doubl
         else kmma_dispatch<K, 2, float>(op, c, u, ws, p, stop, st);              \
     } else {                                                                     \
         if (nr == 1) kmma_dispatch<K, 1, double>(op, c, u, ws, p, stop, st);     \
-        else kmma_dispatch<K, 2, double>(op, c, u, ws, p, stop, st);             \
+        else if (nr == 2) kmma_dispatch<K, 2, double>(op, c, u, ws, p, stop, st); \
+        else kmma_dispatch<K, 4, double>(op, c, u, ws, p, stop, st);             \
     }
         if (op.kind == 1) { KMD(1) } else { KMD(2) }
 #undef KMD
@@ -603,6 +633,85 @@ void launch_kernel_matvec_mma(const KernelOp& op, const double* u, int nr, doubl
     k_ksym_mma_finish<<<(unsigned)((op.n + 255) / 256), 256 * KF_GROUPS, 0, st>>>(op.n, KM_RB, p.nb, p.m, p.S, nr, ws,
                                                                       op.scale, mu, u, y, dot_part,
                                                                       stop);
+}
+
+// ------------------------------------------------------------------ grouped
+// The product and finish of many column blocks (of many requests) in one persistent
+// launch each: work item w of the list belongs to the block whose first item is the
+// largest <= w, and runs that block's item w - w_mat (the same block of threads
+// k_ksym_mma would run for it).  Column blocks whose columns have all stopped are
+// skipped.
+RR_DEV bool group_pair_runs(const GPair& g) {
+    const BState* st = gu(g.st);
+    const int32_t nc = gu(g.ncols);
+    for (int32_t q = 0; q < nc; ++q)
+        if (gu(st[q].run)) return true;
+    return false;
+}
+
+template <int KIND, int DM, int NR>
+__global__ __launch_bounds__(KM_THREADS) __attribute__((amdgpu_waves_per_eu(NR == 1 ? 4 : 2))) void k_group_mat(
+    const GTable* __restrict__ tab, int list, const GPair* __restrict__ units, int32_t* ctr) {
+    __shared__ int32_t wsh;
+    const int32_t off = gu(tab->list[list].off), cnt = gu(tab->list[list].count);
+    const int32_t total = gu(tab->list[list].total);
+    GroupCursor cur(ctr, &wsh);
+    while (true) {
+        const int32_t w = cur.next();
+        if (w >= total) return;
+        const int32_t ui = group_find(units, off, off + cnt, w, [](const GPair& g) { return g.w_mat; });
+        const GPair& g = units[ui];
+        if (!group_pair_runs(g)) continue;
+        ksym_mma_item<KIND, DM, NR, double>((unsigned)(w - gu(g.w_mat)), gu(g.n), gu(g.xa), gu(g.sqn), gu(g.c),
+                                            gu(g.u), gu(g.part), gu(g.nb), gu(g.m), gu(g.S));
+    }
+}
+
+__global__ __launch_bounds__(256 * KF_GROUPS) void k_group_fin(const GTable* __restrict__ tab,
+                                                               const GPair* __restrict__ units, int32_t* ctr) {
+    __shared__ int32_t wsh;
+    const int32_t off = gu(tab->list[GL_FIN].off), cnt = gu(tab->list[GL_FIN].count);
+    const int32_t total = gu(tab->list[GL_FIN].total);
+    GroupCursor cur(ctr, &wsh);
+    while (true) {
+        const int32_t w = cur.next();
+        if (w >= total) return;
+        const int32_t ui = group_find(units, off, off + cnt, w, [](const GPair& g) { return g.w_fin; });
+        const GPair& g = units[ui];
+        if (!group_pair_runs(g)) continue;
+        ksym_mma_finish_block((unsigned)(w - gu(g.w_fin)), (unsigned)gu(g.nfb), gu(g.n), KM_RB, gu(g.nb),
+                              gu(g.m), gu(g.S), gu(g.nr), gu(g.part), gu(g.scale), gu(g.mu), gu(g.u), gu(g.y),
+                              gu(g.dot));
+    }
+}
+
+int group_mat_list(int kind, int dm, int nr) {
+    return GL_MAT + 12 * (kind - 1) + 3 * group_rec_class(dm) + (nr >= 4 ? 2 : nr >= 2 ? 1 : 0);
+}
+
+template <int KIND, int DM>
+static void group_mat_width(int wc, int list, int blocks, const GTable* tab, const GPair* pairs, int32_t* ctr,
+                            hipStream_t st) {
+    if (wc == 0) k_group_mat<KIND, DM, 1><<<blocks, KM_THREADS, 0, st>>>(tab, list, pairs, ctr);
+    else if (wc == 1) k_group_mat<KIND, DM, 2><<<blocks, KM_THREADS, 0, st>>>(tab, list, pairs, ctr);
+    else if constexpr (DM <= 16) k_group_mat<KIND, DM, 4><<<blocks, KM_THREADS, 0, st>>>(tab, list, pairs, ctr);
+}
+
+void launch_group_mat(int list, int blocks, const GTable* tab, const GPair* pairs, int32_t* ctr, hipStream_t st) {
+    const int kind = (list - GL_MAT) / 12 + 1, rc = ((list - GL_MAT) % 12) / 3, wc = (list - GL_MAT) % 3;
+#define KGMD(K)                                                              \
+    switch (rc) {                                                            \
+        case 0: group_mat_width<K, 4>(wc, list, blocks, tab, pairs, ctr, st); break;   \
+        case 1: group_mat_width<K, 8>(wc, list, blocks, tab, pairs, ctr, st); break;   \
+        case 2: group_mat_width<K, 16>(wc, list, blocks, tab, pairs, ctr, st); break;  \
+        default: group_mat_width<K, 32>(wc, list, blocks, tab, pairs, ctr, st); break; \
+    }
+    if (kind == 1) { KGMD(1) } else { KGMD(2) }
+#undef KGMD
+}
+
+void launch_group_fin(int blocks, const GTable* tab, const GPair* pairs, int32_t* ctr, hipStream_t st) {
+    k_group_fin<<<blocks, 256 * KF_GROUPS, 0, st>>>(tab, pairs, ctr);
 }
 
 }  // namespace rr

@@ -7,7 +7,8 @@
 namespace rr {
 
 enum ProfSlot { PROF_KERNEL_MATVEC = 0, PROF_KERNEL_SKETCH, PROF_DENSE_MATVEC, PROF_DENSE_SKETCH,
-                PROF_PROJECT, PROF_KERNEL_MATMAT, PROF_KERNEL_MATVEC64, PROF_DENSE_MATVEC64, PROF_NSLOTS };
+                PROF_PROJECT, PROF_KERNEL_MATMAT, PROF_KERNEL_MATVEC64, PROF_DENSE_MATVEC64,
+                PROF_GROUP_PRODUCT, PROF_GROUP_FINISH, PROF_GROUP_PROJECT, PROF_GROUP_UPDATE, PROF_NSLOTS };
 
 bool prof_enabled();
 void prof_record(int slot, hipEvent_t start, hipEvent_t stop);

@@ -5,11 +5,14 @@
 // fits in the remaining HBM budget (a request larger than the whole budget is
 // rejected).  Each slot is a worker thread with its own HIP stream: it uploads
 // the request, builds the request's C-RandRAND preconditioner, keeps it resident
-// while it solves each right-hand side (PCG batches replayed as captured
-// hipGraphs), copies X back to the host, frees everything and calls deliver().
-// Requests admitted while others run execute concurrently on their own streams.
-// A request's arithmetic depends only on the request (own handle, own stream,
-// fixed-order reductions), so its result is the same alone and in the mix.
+// while it solves all its right-hand sides, copies X back to the host, frees
+// everything and calls deliver().  Builds of different requests overlap on their
+// streams.  The PCG iteration batches run in the grouped engine (group.cpp): every
+// request waiting for its next batch joins one replay of grouped persistent
+// kernels, so the iterations of all resident requests share each launch; with
+// grouping off each request replays its own captured hipGraph.  A request's
+// arithmetic depends only on the request (own handle, own work items, fixed-order
+// reductions), so its result is the same alone and in the mix.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -19,11 +22,14 @@
 #include <condition_variable>
 #include <cstring>
 #include <deque>
+#include <memory>
 #include <mutex>
 #include <thread>
 #include <vector>
 
+#include "batch.hpp"
 #include "ctx.hpp"
+#include "group.hpp"
 
 using namespace rr;
 
@@ -35,7 +41,7 @@ double wall_s() {
 }
 
 // Device bytes one request holds at its peak (build temporaries included).
-size_t request_bytes(const rr_request& r) {
+size_t request_bytes(const rr_request& r, bool grouped) {
     const double n = (double)r.n, l = (double)r.l, d = (double)r.d, m = (double)std::max(r.nrhs, 1);
     double b = n * l * (4 + 2 + 8 + 4 + 8 + 16);        // Omega f32/bf16, Q, Y, W, Theta
     b += n * d * 4 + n * 4;                              // points, |x|^2
@@ -44,6 +50,12 @@ size_t request_bytes(const rr_request& r) {
     b += 8.0 * (double)std::max(rr::kernel_matvec_ws_doubles(r.n, r.d, nr),   // matvec slot partials
                                 rr::kernel_matvec_ws_doubles(r.n, r.d, 2));
     b += n * 8 * (8 + 8 * m);                            // CG vectors, batched PCG blocks, B and X
+    if (grouped) {
+        // slot partials per (padded) column, Q^T R partials and D per column
+        const int64_t cols = std::max<int64_t>(r.nrhs, 1) + 3;
+        b += 8.0 * (double)cols * (double)rr::kernel_mma_ws_doubles(r.n, 1);
+        b += 8.0 * m * l * (rr::gemv_t_chunks(r.n, std::max<int64_t>(r.l, 1)) + 1);
+    }
     b += 64.0 * 1024 * 1024;                             // fixed slack
     return (size_t)b;
 }
@@ -62,6 +74,7 @@ struct Shared {
     int active = 0, max_active = 0;
     std::vector<double> lat_ms;          // OK requests only
     int64_t served = 0, rejected = 0, ok = 0, failed = 0, graph_fallbacks = 0;
+    GroupEngine* engine = nullptr;   // grouped PCG batches (nullptr: a graph per request)
     std::mutex deliver_mu;
     rr_status first_err = RR_OK;
     std::string first_err_msg;   // the library's message for the first failed request
@@ -139,7 +152,13 @@ void run_job(const rr_serve_config& cfg, Job& job, hipStream_t st, double t0, rr
         so.history_cap = 0;
         std::vector<int32_t> mu_idx((size_t)nr, 0);
         std::vector<rr_solve_info> infos((size_t)nr);
-        s = rr_solve_batch(P, mu_idx.data(), b, n, (int32_t)nr, x, n, &so, infos.data(), st);
+        struct EngineRunner final : BatchRunner {
+            GroupEngine* e;
+            explicit EngineRunner(GroupEngine* eng) : e(eng) {}
+            rr_status run(Batch& bt, double* X, int64_t ldx) override { return e->run(bt, X, ldx); }
+        } runner(sh.engine);
+        s = solve_batch_with(P, mu_idx.data(), b, n, (int32_t)nr, x, n, &so, infos.data(), st,
+                             sh.engine ? &runner : nullptr);
         int iters = 0;
         double worst = 0.0, worst64 = 0.0;
         for (const rr_solve_info& si : infos) {
@@ -204,10 +223,19 @@ extern "C" rr_status rr_serve(const rr_serve_config* cfg, rr_next_fn next, rr_de
         RR_REQUIRE(cfg->hbm_budget > 0, "hbm_budget must be > 0");
         RR_REQUIRE(cfg->graph_iters >= 0 && cfg->graph_iters <= 4096, "graph_iters must be in [0, 4096]");
         if (cfg->alloc) RR_REQUIRE(cfg->alloc->alloc && cfg->alloc->free, "allocator callbacks are null");
+        RR_REQUIRE(cfg->grouped == 0 || cfg->grouped == 1, "grouped must be 0 or 1");
+        RR_REQUIRE(cfg->grouped == 0 || (cfg->graph_iters > 0 && cfg->graph_iters <= 256),
+                   "grouped batches need graph_iters in [1, 256]");
         require_device();
         int dev = 0;
         RR_HIP(hipGetDevice(&dev));
         Shared sh;
+        std::unique_ptr<GroupEngine> engine;
+        if (cfg->grouped) {
+            engine.reset(new GroupEngine(cfg->graph_iters, cfg->max_slots));
+            engine->init();
+            sh.engine = engine.get();
+        }
         const double t0 = wall_s();
         std::vector<std::thread> workers;
         for (int w = 0; w < cfg->max_slots; ++w) {
@@ -249,7 +277,7 @@ extern "C" rr_status rr_serve(const rr_serve_config* cfg, rr_next_fn next, rr_de
                     const bool valid = r.n >= 1 && r.d >= 1 && r.d <= 32 && r.pts && r.B && r.X &&
                                        r.nrhs >= 1 && r.l >= 0 && r.l <= r.n && std::isfinite(r.mu) &&
                                        r.mu >= 0.0 && (r.kind == RR_OP_RBF || r.kind == RR_OP_MATERN32);
-                    Job j{r, request_bytes(r)};
+                    Job j{r, request_bytes(r, cfg->grouped != 0)};
                     if (!valid || j.bytes > cfg->hbm_budget) {
                         rr_solve_info inf{};
                         inf.status = valid ? RR_ENOMEM : RR_EINVAL;
@@ -288,6 +316,11 @@ extern "C" rr_status rr_serve(const rr_serve_config* cfg, rr_next_fn next, rr_de
         sh.cv_work.notify_all();
         for (auto& t : workers) t.join();
         const double wall = wall_s() - t0;
+        GroupStats gst{};
+        if (engine) {
+            gst = engine->stats();
+            engine.reset();
+        }
         if (stats) {
             std::memset(stats, 0, sizeof(*stats));
             std::vector<double> v = sh.lat_ms;
@@ -310,6 +343,11 @@ extern "C" rr_status rr_serve(const rr_serve_config* cfg, rr_next_fn next, rr_de
             stats->solves_per_s = wall > 0 ? sh.ok / wall : 0.0;
             stats->hbm_peak = sh.peak;
             stats->max_active = sh.max_active;
+            stats->group_replays = gst.replays;
+            stats->group_mean = gst.replays > 0 ? (double)gst.jobs / (double)gst.replays : 0.0;
+            stats->group_max = (int32_t)gst.max_jobs;
+            stats->group_busy_s = gst.busy_s;
+            stats->group_wait_s = gst.wait_s;
         }
         (void)loop_err;
         if (sh.first_err != RR_OK) {

@@ -335,6 +335,12 @@ extern "C" rr_status rr_solve_batch(const rr_precond* P, const int32_t* mu_index
                                     const double* B, int64_t ldb, int32_t nrhs, double* X,
                                     int64_t ldx, const rr_solve_opts* opts, rr_solve_info* infos,
                                     void* hip_stream) {
+    return rr::solve_batch_with(P, mu_index_per_col, B, ldb, nrhs, X, ldx, opts, infos, hip_stream, nullptr);
+}
+
+rr_status rr::solve_batch_with(const rr_precond* P, const int32_t* mu_index_per_col, const double* B,
+                               int64_t ldb, int32_t nrhs, double* X, int64_t ldx, const rr_solve_opts* opts,
+                               rr_solve_info* infos, void* hip_stream, BatchRunner* runner) {
     rr_solve_opts o;
     if (opts) o = *opts; else rr_solve_opts_default(&o);
     rr_status v = guarded([&]() -> rr_status {
@@ -355,5 +361,5 @@ extern "C" rr_status rr_solve_batch(const rr_precond* P, const int32_t* mu_index
     if (v != RR_OK) return v;
     if (o.krylov == RR_KRYLOV_BLOCK_MINRES || o.krylov == RR_KRYLOV_BLOCK_CG)
         return rr_solve_block(P, mu_index_per_col, B, ldb, nrhs, X, ldx, &o, infos, hip_stream);
-    return rr_solve_batch_fused(P, mu_index_per_col, B, ldb, nrhs, X, ldx, &o, infos, hip_stream);
+    return rr_solve_batch_fused(P, mu_index_per_col, B, ldb, nrhs, X, ldx, &o, infos, hip_stream, runner);
 }

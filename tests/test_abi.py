@@ -135,3 +135,33 @@ def test_serve_rejects_null_config():
     nf = b.NEXT_FN(lambda u, t, r: -1)
     df = b.DELIVER_FN(lambda u, r, i, t: None)
     assert L.rr_serve(None, nf, df, None, C.byref(stats)) == b.RR_EINVAL
+
+
+def test_ctypes_structures_match_the_header_layout(tmp_path):
+    """Every structure the binding mirrors has the header's size and field offsets
+    (a C program built with gcc from include/randrand.h prints them)."""
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("gcc not available")
+    structs = [b.rr_operator, b.rr_build_opts, b.rr_solve_opts, b.rr_solve_info, b.rr_allocator,
+               b.rr_request, b.rr_serve_config, b.rr_serve_stats]
+    lines = ["#include <stddef.h>", "#include <stdio.h>", f'#include "{HEADER}"', "int main(void) {"]
+    for s in structs:
+        name = s.__name__
+        lines.append(f'printf("{name} size %zu\\n", sizeof({name}));')
+        for f, _ in s._fields_:
+            lines.append(f'printf("{name} {f} %zu\\n", offsetof({name}, {f}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([gcc, "-std=c11", str(src), "-o", str(exe)], check=True, capture_output=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(line.split()[:2]): int(line.split()[2]) for line in out if line.strip()}
+    for s in structs:
+        name = s.__name__
+        assert got[(name, "size")] == C.sizeof(s), name
+        for f, _ in s._fields_:
+            assert got[(name, f)] == getattr(s, f).offset, (name, f)

@@ -95,10 +95,11 @@ def test_kernel_matvec_block_multi_tile(kind, n, d, nr):
         assert np.linalg.norm(Y32[:, q] - ref[:, q]) <= 2e-6 * np.linalg.norm(ref[:, q]), q
     Y64 = rr.apply_operator_block(kop, mu, "fp64", _cuda(U)).cpu().numpy()
     assert np.linalg.norm(Y64 - ref) <= 1e-12 * np.linalg.norm(ref)
-    # a block product equals the column-by-column products bitwise
-    y0 = rr.apply_operator(kop, mu, "fp32", _cuda(U[:, 0].copy())).cpu().numpy()
-    if nr == 1:
-        assert np.array_equal(y0, Y32[:, 0])
+    # a block product (column blocks of four, two and one) equals the column-by-column
+    # products bitwise
+    for q in range(nr):
+        yq = rr.apply_operator(kop, mu, "fp32", _cuda(U[:, q].copy())).cpu().numpy()
+        assert np.array_equal(yq, Y32[:, q]), q
 
 
 def test_kernel_fp32_matvec_beyond_mfma_slot_bound():
@@ -801,6 +802,54 @@ def test_serving_alone_equals_mixed_and_oracle():
             n = r["pts"].shape[1]
             dA = n * 2.0 ** -23 * r["scale"]
             assert rel <= 1e-6 + dA * np.linalg.norm(mixed[i]["X"][:, j]) / np.linalg.norm(r["B"][:, j])
+
+
+def test_serving_grouped_equals_per_request_graphs():
+    """Grouped serving (the PCG batches of all waiting requests in one replay of
+    persistent kernels over the device work list) gives bitwise the results of
+    per-request graphs, alone and in the mix, and meets tol against the oracle.  The
+    mix covers both kernels, record lengths 4/8/16, an odd and a wide right-hand-side
+    block (padded pair, projection groups of width 4, 2 and 1) and a product with
+    several column blocks per work item."""
+    from paper_2509_19747_amd import binding as rb
+    reqs = _serving_requests(6, 21, n_range=(700, 2600))
+    rng = np.random.default_rng(77)
+    reqs[1]["kind"] = rr.OP_MATERN32
+    reqs[1]["kconst"] = float(np.float32(np.sqrt(3.0) / workloads.median_pairwise_distance(reqs[1]["pts"], 500)))
+    reqs[2]["B"] = rng.standard_normal((reqs[2]["pts"].shape[1], 7))
+    n = 9000
+    pts = rng.standard_normal((8, n)).astype(np.float32)
+    bw = workloads.median_pairwise_distance(pts, 500)
+    reqs.append(dict(kind=rr.OP_RBF, pts=pts, kconst=float(np.float32(1 / (2 * bw * bw))), scale=1.0 / n,
+                     mu=1e-4, l=int(np.ceil(n / 32)), seed=901, B=rng.standard_normal((n, 5)),
+                     t_arrival=reqs[-1]["t_arrival"] + 0.004))
+    kw = dict(build=dict(prec="fp32", sketch="gaussian"), solve=dict(tol=1e-6, certify=True))
+    grouped, sg = rb.serve(reqs, max_slots=4, graph_iters=8, grouped=True, **kw)
+    assert sg["status"] == rr.RR_OK, sg.get("first_error")
+    assert sg["ok"] == len(reqs) and sg["group_replays"] > 0 and sg["group_max"] >= 2
+    single, ss = rb.serve(reqs, max_slots=4, graph_iters=8, grouped=False, **kw)
+    assert ss["status"] == rr.RR_OK and ss["group_replays"] == 0
+    for i, r in enumerate(reqs):
+        g, p = grouped[i], single[i]
+        assert g["info"]["status"] == rr.RR_OK and p["info"]["status"] == rr.RR_OK
+        assert g["info"]["iters"] == p["info"]["iters"]
+        assert np.array_equal(g["X"], p["X"]), i
+        alone, sa = rb.serve([dict(r, t_arrival=0.0)], max_slots=1, graph_iters=8, grouped=True, **kw)
+        assert sa["group_max"] == 1
+        assert np.array_equal(alone[0]["X"], g["X"]), i
+        op = Operator(kind=r["kind"], pts=r["pts"], kconst=r["kconst"], scale=r["scale"])
+        n = r["pts"].shape[1]
+        for j in range(r["B"].shape[1]):
+            rel = osol.relres(op.shifted(r["mu"]), g["X"][:, j], r["B"][:, j])
+            dA = n * 2.0 ** -23 * r["scale"]
+            assert rel <= 1e-6 + dA * np.linalg.norm(g["X"][:, j]) / np.linalg.norm(r["B"][:, j])
+
+
+def test_serving_grouped_rejects_bad_config():
+    from paper_2509_19747_amd import binding as rb
+    reqs = _serving_requests(1, 3)
+    with pytest.raises(rb.RRError):
+        rb.serve(reqs, graph_iters=0, grouped=True)
 
 
 def test_serving_rejects_over_budget():
