@@ -144,6 +144,8 @@ def main():
     ap.add_argument("--graph-iters", type=int, default=8,
                     help="serving: PCG iterations per replayed hipGraph batch (0: plain launches)")
     ap.add_argument("--budget-gb", type=float, default=96.0, help="serving: HBM budget")
+    ap.add_argument("--lanes", type=int, default=0,
+                    help="serving: grouped replay lanes (0: each request replays its own graph)")
     ap.add_argument("--dump", default="", help="serving: write per-request records (JSON lines)")
     ap.add_argument("--nrhs", type=int, default=256, help="batched: right-hand sides per shift")
     args = ap.parse_args()
@@ -576,7 +578,7 @@ def bench_serving(args):
     kw = dict(build=dict(prec="fp32", sketch="gaussian"), solve=dict(tol=1e-6, certify=False))
     _log(f"serving: {len(reqs)} requests generated")
     res, stats = rb.serve(reqs, hbm_budget=int(args.budget_gb * (1 << 30)), max_slots=args.slots,
-                          graph_iters=args.graph_iters, **kw)
+                          graph_iters=args.graph_iters, grouped=args.lanes, **kw)
     lat = np.array([r["t_done"] - q["t_arrival"] for r, q in zip(res, reqs) if r is not None])
     warm = 200 if len(lat) > 400 else 0
     ok = sum(1 for r in res if r is not None and r["info"]["status"] == 0)
@@ -587,7 +589,7 @@ def bench_serving(args):
         "p50_ms": float(np.percentile(lat[warm:], 50) * 1e3),
         "p99_ms": float(np.percentile(lat[warm:], 99) * 1e3), "server_stats": stats,
         "requests": len(reqs), "ok": ok, "rate": args.rate, "slots": args.slots,
-        "graph_iters": args.graph_iters,
+        "graph_iters": args.graph_iters, "lanes": args.lanes,
         "mean_build_ms": float(np.mean([i["ms_build"] for i in infos])),
         "mean_solve_ms": float(np.mean([i["ms_solve"] for i in infos])),
         "mean_iters": float(np.mean([i["iters"] for i in infos])),

@@ -312,11 +312,13 @@ typedef struct {
     const rr_allocator* alloc;  /* device allocator for every request buffer and handle
                                    (NULL: the library's stream-ordered pool); its alloc and
                                    free are called from the server's worker threads       */
-    int32_t grouped;      /* 1: the PCG batches of all resident requests run together, one
-                             replay of grouped persistent kernels over a device work list
-                             per batch (requests of one shift whose kernel product runs on
-                             MFMA; others replay their own graph); 0: every request
-                             replays its own graph.  Needs graph_iters > 0.            */
+    int32_t grouped;      /* k in [1, 8]: the PCG batches of the resident requests run
+                             together, each batch of every request waiting at that moment
+                             in one replay of grouped persistent kernels over a device
+                             work list, on k replay lanes (streams) at once (requests of
+                             one shift whose kernel product runs on MFMA; others replay
+                             their own graph); 0: every request replays its own graph.
+                             Needs graph_iters in [1, 256].                            */
 } rr_serve_config;
 
 typedef struct {
@@ -331,7 +333,7 @@ typedef struct {
     int64_t group_replays;           /* grouped replays run (grouped = 1)                 */
     double group_mean;               /* request batches per grouped replay                */
     int32_t group_max;               /* largest number of requests in one replay          */
-    double group_busy_s;             /* time the grouped engine spent on replays          */
+    double group_busy_s;             /* replay time of the grouped engine (summed over lanes) */
     double group_wait_s;             /* summed over request batches: queued to completed  */
 } rr_serve_stats;
 

@@ -500,11 +500,11 @@ def sketch(op: Operator, mu: float, l: int, stream=None, **kw):
 
 def serve(requests, hbm_budget: int = 96 << 30, max_slots: int = 8, graph_iters: int = 8,
           build: Optional[dict] = None, solve: Optional[dict] = None, allocator=None,
-          grouped: bool = True):
+          grouped: int = 0):
     """Run the continuous-batching server over `requests` (arrival-ordered).
 
-    grouped: the PCG batches of all resident requests run as one replay of grouped
-    kernels (False: each request replays its own graph).
+    grouped: the PCG batches of the waiting requests run as replays of grouped kernels
+    on this many lanes (0: each request replays its own graph).
 
     Each request is a dict with keys: kind, pts (float32 (d, n) host array), kconst,
     scale, mu, l, seed, B (float64 (n, m) host array), t_arrival (seconds after the
@@ -514,7 +514,7 @@ def serve(requests, hbm_budget: int = 96 << 30, max_slots: int = 8, graph_iters:
     bo = build_opts(**(build or {}))
     so = solve_opts(**(solve or {}))
     cfg = rr_serve_config(hbm_budget=int(hbm_budget), max_slots=int(max_slots),
-                          graph_iters=int(graph_iters), build=bo, solve=so, grouped=int(bool(grouped)))
+                          graph_iters=int(graph_iters), build=bo, solve=so, grouped=int(grouped))
     keep = []
     for i, r in enumerate(requests):
         pts = np.ascontiguousarray(r["pts"], dtype=np.float32)

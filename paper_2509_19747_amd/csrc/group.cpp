@@ -3,12 +3,13 @@
 // Worker threads own their requests (build, restarts with the true residual,
 // stopping rules and delivery, exactly as rr_solve_batch).  When a request needs
 // its next batch of iterations, its worker calls GroupEngine::run, which queues it
-// and waits.  The engine thread takes every queued request, writes their work units
-// and the list headers to the device, and replays one hipGraph of `iters` grouped
-// iterations (persistent kernels over the unit lists, work counters zeroed by the
-// graph's first node) for all of them at once, then wakes their workers.  One graph
-// is captured per set of non-empty lists and kept for the engine's lifetime; the
-// unit arrays change between replays, the graph does not.
+// and waits.  An idle lane of the engine takes every queued request, writes their
+// work units and the list headers to the device, and replays one hipGraph of `iters`
+// grouped iterations (persistent kernels over the unit lists, work counters zeroed by
+// the graph's first node) for all of them at once, then wakes their workers.  Lanes
+// run on their own streams, so replays of different groups overlap on the device.
+// Each lane captures one graph per set of non-empty lists and keeps it for the
+// engine's lifetime; the unit arrays change between replays, the graph does not.
 #include "group.hpp"
 
 #include <hip/hip_runtime.h>
@@ -73,32 +74,40 @@ struct GroupEngine::Impl {
         rr_status status = RR_OK;
         bool done = false;
     };
+    // One replay lane: its own stream, device and pinned host images of the unit lists,
+    // work counters, graphs and thread.  Lanes take queued batches independently, so
+    // a batch that arrives while one replay runs starts on an idle lane at once.
+    struct Lane {
+        hipStream_t gs = nullptr;
+        void* dtab = nullptr;       // device image
+        char* htab = nullptr;       // pinned host image
+        int32_t* ctr = nullptr;     // iters x GL_COUNT work counters
+        std::map<uint64_t, hipGraphExec_t> graphs;
+        std::thread th;
+    };
     int iters, max_jobs, cap_pairs, cap_vecs, cap_projs;
     Layout lay;
     int dev = 0;
-    hipStream_t gs = nullptr;
-    void* dtab = nullptr;       // device image
-    char* htab = nullptr;       // pinned host image
-    int32_t* ctr = nullptr;     // iters x GL_COUNT work counters
-    std::map<uint64_t, hipGraphExec_t> graphs;
+    std::vector<Lane> lanes;
     std::mutex mu;
     std::condition_variable cv_in, cv_out;
     std::deque<Job*> queue;
     bool stop = false;
-    std::thread th;
     GroupStats stats{};
 
-    Impl(int it, int jobs)
+    Impl(int it, int jobs, int nlanes)
         : iters(it), max_jobs(jobs), cap_pairs(jobs * (int)KMULTI_MAX), cap_vecs(jobs),
-          cap_projs(jobs * (int)KMULTI_MAX), lay(cap_pairs, cap_vecs, cap_projs) {}
+          cap_projs(jobs * (int)KMULTI_MAX), lay(cap_pairs, cap_vecs, cap_projs), lanes(nlanes) {}
 
     rr_status init() {
         RR_HIP(hipGetDevice(&dev));
-        RR_HIP(hipStreamCreateWithFlags(&gs, hipStreamNonBlocking));
-        RR_HIP(hipMalloc(&dtab, lay.bytes));
-        RR_HIP(hipHostMalloc((void**)&htab, lay.bytes, hipHostMallocDefault));
-        RR_HIP(hipMalloc((void**)&ctr, (size_t)iters * GL_COUNT * sizeof(int32_t)));
-        th = std::thread([this]() { loop(); });
+        for (Lane& ln : lanes) {
+            RR_HIP(hipStreamCreateWithFlags(&ln.gs, hipStreamNonBlocking));
+            RR_HIP(hipMalloc(&ln.dtab, lay.bytes));
+            RR_HIP(hipHostMalloc((void**)&ln.htab, lay.bytes, hipHostMallocDefault));
+            RR_HIP(hipMalloc((void**)&ln.ctr, (size_t)iters * GL_COUNT * sizeof(int32_t)));
+        }
+        for (Lane& ln : lanes) ln.th = std::thread([this, &ln]() { loop(ln); });
         return RR_OK;
     }
 
@@ -108,13 +117,16 @@ struct GroupEngine::Impl {
             stop = true;
         }
         cv_in.notify_all();
-        if (th.joinable()) th.join();
-        for (auto& g : graphs) (void)hipGraphExecDestroy(g.second);
-        if (gs) (void)hipStreamSynchronize(gs);
-        if (ctr) (void)hipFree(ctr);
-        if (dtab) (void)hipFree(dtab);
-        if (htab) (void)hipHostFree(htab);
-        if (gs) (void)hipStreamDestroy(gs);
+        for (Lane& ln : lanes)
+            if (ln.th.joinable()) ln.th.join();
+        for (Lane& ln : lanes) {
+            for (auto& g : ln.graphs) (void)hipGraphExecDestroy(g.second);
+            if (ln.gs) (void)hipStreamSynchronize(ln.gs);
+            if (ln.ctr) (void)hipFree(ln.ctr);
+            if (ln.dtab) (void)hipFree(ln.dtab);
+            if (ln.htab) (void)hipHostFree(ln.htab);
+            if (ln.gs) (void)hipStreamDestroy(ln.gs);
+        }
     }
 
     rr_status run(Batch& bt, double* X, int64_t ldx) {
@@ -133,7 +145,7 @@ struct GroupEngine::Impl {
 
     // Work units of the taken jobs, written into the host image; returns the mask of
     // non-empty lists.
-    uint64_t describe(const std::vector<Job*>& jobs) {
+    uint64_t describe(const std::vector<Job*>& jobs, char* htab) {
         GTable& tab = *reinterpret_cast<GTable*>(htab);
         std::memset(&tab, 0, sizeof(tab));
         GPair* pairs = reinterpret_cast<GPair*>(htab + lay.pairs);
@@ -268,12 +280,14 @@ struct GroupEngine::Impl {
     // The launches of one replay on the engine stream: counter reset, then per
     // iteration the products (widest blocks first), their finish, the x and r update,
     // the projection and the p update.  timed: one event span per iteration and class.
-    void launch_lists(uint64_t mask, bool timed, bool sized) {
-        const GTable& htb = *reinterpret_cast<const GTable*>(htab);
-        const GTable* tab = reinterpret_cast<const GTable*>(dtab);
-        const GPair* pairs = reinterpret_cast<const GPair*>((char*)dtab + lay.pairs);
-        const GVec* vecs = reinterpret_cast<const GVec*>((char*)dtab + lay.vecs);
-        const GProj* projs = reinterpret_cast<const GProj*>((char*)dtab + lay.projs);
+    void launch_lists(Lane& ln, uint64_t mask, bool timed, bool sized) {
+        const GTable& htb = *reinterpret_cast<const GTable*>(ln.htab);
+        const GTable* tab = reinterpret_cast<const GTable*>(ln.dtab);
+        const GPair* pairs = reinterpret_cast<const GPair*>((char*)ln.dtab + lay.pairs);
+        const GVec* vecs = reinterpret_cast<const GVec*>((char*)ln.dtab + lay.vecs);
+        const GProj* projs = reinterpret_cast<const GProj*>((char*)ln.dtab + lay.projs);
+        hipStream_t gs = ln.gs;
+        int32_t* ctr = ln.ctr;
         launch_group_reset(ctr, iters * GL_COUNT, gs);
         for (int k = 0; k < iters; ++k) {
             int L = 0;
@@ -294,15 +308,15 @@ struct GroupEngine::Impl {
     }
 
     // The replay graph for the lists in mask (captured on first use).
-    hipGraphExec_t graph_for(uint64_t mask) {
-        auto it = graphs.find(mask);
-        if (it != graphs.end()) return it->second;
+    hipGraphExec_t graph_for(Lane& ln, uint64_t mask) {
+        auto it = ln.graphs.find(mask);
+        if (it != ln.graphs.end()) return it->second;
         hipGraph_t g = nullptr;
         hipGraphExec_t e = nullptr;
         // relaxed: other threads allocate and launch while the engine captures
-        if (hipStreamBeginCapture(gs, hipStreamCaptureModeRelaxed) != hipSuccess) return nullptr;
-        launch_lists(mask, false, false);
-        const hipError_t ce = hipStreamEndCapture(gs, &g);
+        if (hipStreamBeginCapture(ln.gs, hipStreamCaptureModeRelaxed) != hipSuccess) return nullptr;
+        launch_lists(ln, mask, false, false);
+        const hipError_t ce = hipStreamEndCapture(ln.gs, &g);
         if (ce != hipSuccess || !g) {
             (void)hipGetLastError();
             if (g) (void)hipGraphDestroy(g);
@@ -314,11 +328,11 @@ struct GroupEngine::Impl {
             (void)hipGetLastError();
             return nullptr;
         }
-        graphs[mask] = e;
+        ln.graphs[mask] = e;
         return e;
     }
 
-    void loop() {
+    void loop(Lane& ln) {
         (void)hipSetDevice(dev);
         while (true) {
             std::vector<Job*> jobs;
@@ -333,18 +347,18 @@ struct GroupEngine::Impl {
             }
             rr_status s = RR_OK;
             const double t0 = now_ms();
-            const uint64_t mask = describe(jobs);
+            const uint64_t mask = describe(jobs, ln.htab);
             hipGraphExec_t e = nullptr;
-            bool ok = hipMemcpyAsync(dtab, htab, lay.bytes, hipMemcpyHostToDevice, gs) == hipSuccess;
+            bool ok = hipMemcpyAsync(ln.dtab, ln.htab, lay.bytes, hipMemcpyHostToDevice, ln.gs) == hipSuccess;
             if (ok && prof_enabled()) {
                 // kernel timing: the same kernels as plain launches, grids sized to the
                 // work, one timed span per iteration and class
-                launch_lists(mask, true, true);
+                launch_lists(ln, mask, true, true);
                 ok = hipGetLastError() == hipSuccess;
             } else if (ok) {
-                ok = (e = graph_for(mask)) != nullptr && hipGraphLaunch(e, gs) == hipSuccess;
+                ok = (e = graph_for(ln, mask)) != nullptr && hipGraphLaunch(e, ln.gs) == hipSuccess;
             }
-            if (!ok || hipStreamSynchronize(gs) != hipSuccess) {
+            if (!ok || hipStreamSynchronize(ln.gs) != hipSuccess) {
                 (void)hipGetLastError();
                 s = RR_EDEVICE;
             }
@@ -363,7 +377,7 @@ struct GroupEngine::Impl {
     }
 };
 
-GroupEngine::GroupEngine(int iters, int max_jobs) : impl_(new Impl(iters, max_jobs)) {}
+GroupEngine::GroupEngine(int iters, int max_jobs, int lanes) : impl_(new Impl(iters, max_jobs, lanes)) {}
 GroupEngine::~GroupEngine() { delete impl_; }
 rr_status GroupEngine::init() { return impl_->init(); }
 rr_status GroupEngine::run(Batch& bt, double* X, int64_t ldx) { return impl_->run(bt, X, ldx); }

@@ -132,15 +132,16 @@ constexpr int GROUP_MAT_BLOCKS = 512, GROUP_FIN_BLOCKS = 256, GROUP_VEC_BLOCKS =
 struct Batch;
 struct GroupStats {
     int64_t replays, jobs, max_jobs;   // replays, request batches they carried, largest group
-    double busy_s;                     // wall time from each replay's upload to its completion
+    double busy_s;                     // wall time from each replay's upload to its completion (summed over lanes)
     double wait_s;                     // summed over request batches: queued until completed
 };
 // One engine per serving loop: iters grouped iterations per replay, at most max_jobs
-// requests per replay.  run() blocks the calling worker until a replay that included
-// its column block has completed.
+// requests per replay, `lanes` replays in flight at once (each on its own stream).
+// run() blocks the calling worker until a replay that included its column block has
+// completed.
 class GroupEngine {
   public:
-    GroupEngine(int iters, int max_jobs);
+    GroupEngine(int iters, int max_jobs, int lanes);
     ~GroupEngine();
     GroupEngine(const GroupEngine&) = delete;
     GroupEngine& operator=(const GroupEngine&) = delete;

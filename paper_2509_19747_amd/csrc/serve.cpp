@@ -223,7 +223,7 @@ extern "C" rr_status rr_serve(const rr_serve_config* cfg, rr_next_fn next, rr_de
         RR_REQUIRE(cfg->hbm_budget > 0, "hbm_budget must be > 0");
         RR_REQUIRE(cfg->graph_iters >= 0 && cfg->graph_iters <= 4096, "graph_iters must be in [0, 4096]");
         if (cfg->alloc) RR_REQUIRE(cfg->alloc->alloc && cfg->alloc->free, "allocator callbacks are null");
-        RR_REQUIRE(cfg->grouped == 0 || cfg->grouped == 1, "grouped must be 0 or 1");
+        RR_REQUIRE(cfg->grouped >= 0 && cfg->grouped <= 8, "grouped must be in [0, 8]");
         RR_REQUIRE(cfg->grouped == 0 || (cfg->graph_iters > 0 && cfg->graph_iters <= 256),
                    "grouped batches need graph_iters in [1, 256]");
         require_device();
@@ -232,7 +232,7 @@ extern "C" rr_status rr_serve(const rr_serve_config* cfg, rr_next_fn next, rr_de
         Shared sh;
         std::unique_ptr<GroupEngine> engine;
         if (cfg->grouped) {
-            engine.reset(new GroupEngine(cfg->graph_iters, cfg->max_slots));
+            engine.reset(new GroupEngine(cfg->graph_iters, cfg->max_slots, cfg->grouped));
             engine->init();
             sh.engine = engine.get();
         }

@@ -824,17 +824,20 @@ def test_serving_grouped_equals_per_request_graphs():
                      mu=1e-4, l=int(np.ceil(n / 32)), seed=901, B=rng.standard_normal((n, 5)),
                      t_arrival=reqs[-1]["t_arrival"] + 0.004))
     kw = dict(build=dict(prec="fp32", sketch="gaussian"), solve=dict(tol=1e-6, certify=True))
-    grouped, sg = rb.serve(reqs, max_slots=4, graph_iters=8, grouped=True, **kw)
+    grouped, sg = rb.serve(reqs, max_slots=4, graph_iters=8, grouped=1, **kw)
     assert sg["status"] == rr.RR_OK, sg.get("first_error")
     assert sg["ok"] == len(reqs) and sg["group_replays"] > 0 and sg["group_max"] >= 2
-    single, ss = rb.serve(reqs, max_slots=4, graph_iters=8, grouped=False, **kw)
+    lanes2, s2 = rb.serve(reqs, max_slots=4, graph_iters=8, grouped=2, **kw)
+    assert s2["status"] == rr.RR_OK and s2["group_replays"] > 0
+    single, ss = rb.serve(reqs, max_slots=4, graph_iters=8, grouped=0, **kw)
     assert ss["status"] == rr.RR_OK and ss["group_replays"] == 0
     for i, r in enumerate(reqs):
         g, p = grouped[i], single[i]
         assert g["info"]["status"] == rr.RR_OK and p["info"]["status"] == rr.RR_OK
         assert g["info"]["iters"] == p["info"]["iters"]
         assert np.array_equal(g["X"], p["X"]), i
-        alone, sa = rb.serve([dict(r, t_arrival=0.0)], max_slots=1, graph_iters=8, grouped=True, **kw)
+        assert np.array_equal(lanes2[i]["X"], p["X"]), i
+        alone, sa = rb.serve([dict(r, t_arrival=0.0)], max_slots=1, graph_iters=8, grouped=1, **kw)
         assert sa["group_max"] == 1
         assert np.array_equal(alone[0]["X"], g["X"]), i
         op = Operator(kind=r["kind"], pts=r["pts"], kconst=r["kconst"], scale=r["scale"])
@@ -849,7 +852,9 @@ def test_serving_grouped_rejects_bad_config():
     from paper_2509_19747_amd import binding as rb
     reqs = _serving_requests(1, 3)
     with pytest.raises(rb.RRError):
-        rb.serve(reqs, graph_iters=0, grouped=True)
+        rb.serve(reqs, graph_iters=0, grouped=1)
+    with pytest.raises(rb.RRError):
+        rb.serve(reqs, graph_iters=8, grouped=9)
 
 
 def test_serving_rejects_over_budget():
