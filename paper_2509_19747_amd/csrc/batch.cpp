@@ -85,7 +85,12 @@ rr_status rr_solve_batch_fused(const rr_precond* Pc, const int32_t* mu_index_per
                 launch_copy_mat(DT_F64, B, ldb, DT_F64, Bt.T.as<double>(), n, n, m, st);
                 rr = bb;
             } else {
-                Bt.matmat(Xd, ldx, Bt.T.as<double>(), ir);
+                // the true residuals of the columns checked now (those still running
+                // or finished keep their state; their columns of T are not used)
+                std::vector<int32_t> cols;
+                for (int64_t j = 0; j < m; ++j)
+                    if (pending[j] && !done[j]) cols.push_back((int32_t)j);
+                Bt.product_cols(Xd, ldx, Bt.T.as<double>(), ir, cols, hmu);
                 launch_bresid(n, m, B, ldb, Bt.T.as<double>(), Bt.T.as<double>(), st);
                 rr = Bt.coldots(Bt.T.as<double>(), n, Bt.T.as<double>(), n);
             }

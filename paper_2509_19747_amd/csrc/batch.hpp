@@ -32,6 +32,7 @@ struct Batch {
     Alloc alloc;          // the handle's allocator, ordered on the solve stream
     const Alloc* al;
     DBuf R, Pm, Z, W, T, parts, C, Dall, D, state, start, target2, mucol, muidx, gws;
+    DBuf cidx, mucomp;    // column list and shifts of a compact restart product
     DBuf kws, kdot;       // symmetric multi-column kernel matvec (few columns)
     bool kmulti = false;
     DBuf cpart, dcols, rzp;   // projection through the basis, groups of up to 8 columns
@@ -88,6 +89,8 @@ struct Batch {
         target2.reset(al, (size_t)m * sizeof(double));
         mucol.reset(al, (size_t)m * sizeof(double));
         muidx.reset(al, (size_t)m * sizeof(int32_t));
+        cidx.reset(al, (size_t)m * sizeof(int32_t));
+        mucomp.reset(al, (size_t)m * sizeof(double));
         gwsd = std::max<size_t>((size_t)8 * std::max<int64_t>(kb, 1) * m, (size_t)1 << 20);
         gws.reset(al, gwsd * sizeof(double));
         // a few columns: the symmetric matvec kernel (each entry formed once per
@@ -149,35 +152,61 @@ struct Batch {
 
     // Wout = A_mu Pin for every column (fp64: float64 operator).  Returns the block
     // partials of Pin_j^T Wout_j when the product produced them (nch = 0 otherwise).
-    ColParts matmat(const double* Pin, int64_t ldp, double* Wout, bool fp64) {
+    // mc columns (default all m) under the shifts mu_c (default the columns' own).
+    ColParts matmat(const double* Pin, int64_t ldp, double* Wout, bool fp64, int64_t mc = -1,
+                    const double* mu_c = nullptr) {
+        if (mc < 0) mc = m;
+        const double* muc = mu_c ? mu_c : mucol.as<double>();
         if (kmulti && fp64 && ldp == n) {
             // a few columns under the float64 operator: the pair-once float64 matvec,
             // two columns per pass
             const KernelOp k = kernel_op_of(P);
-            launch_kernel_matvec_multi(k, true, Pin, (int)m, 0.0, Wout, kdot.as<double>(), kws.as<double>(),
+            launch_kernel_matvec_multi(k, true, Pin, (int)mc, 0.0, Wout, kdot.as<double>(), kws.as<double>(),
                                        nullptr, st);
-            launch_add_shift_cols(n, m, mucol.as<double>(), Pin, ldp, Wout, n, st);
+            launch_add_shift_cols(n, mc, muc, Pin, ldp, Wout, n, st);
             return ColParts{nullptr, 0, 0, 0};
         }
         if (kmulti && !fp64 && ldp == n) {
             const KernelOp k = kernel_op_of(P);
             const int nblk = kernel_matvec_blocks(n);
-            launch_kernel_matvec_multi(k, false, Pin, (int)m, single ? mu1 : 0.0, Wout, kdot.as<double>(),
+            launch_kernel_matvec_multi(k, false, Pin, (int)mc, single ? mu1 : 0.0, Wout, kdot.as<double>(),
                                        kws.as<double>(), nullptr, st);
             if (single) return ColParts{kdot.as<double>(), nblk, 1, nblk};
-            launch_add_shift_cols(n, m, mucol.as<double>(), Pin, ldp, Wout, n, st);
+            launch_add_shift_cols(n, mc, muc, Pin, ldp, Wout, n, st);
             return ColParts{nullptr, 0, 0, 0};
         }
         if (is_kernel(P.op)) {
             const KernelOp k = kernel_op_of(P);
-            launch_kernel_matmat_f64(k, fp64 || P.opts.prec == RR_PREC_FP64, mucol.as<double>(), Pin, ldp, m,
-                                     Wout, n, st);
+            launch_kernel_matmat_f64(k, fp64 || P.opts.prec == RR_PREC_FP64, muc, Pin, ldp, mc, Wout, n, st);
         } else {
-            if (!fp64 && P.A32.ptr()) gemm(false, false, n, m, n, P.A32.ptr(), n, Pin, ldp, Wout, n, 1.0, 0.0, DT_F32);
-            else gemm(false, false, n, m, n, P.op.A, P.op.lda, Pin, ldp, Wout, n, 1.0, 0.0);
-            launch_add_shift_cols(n, m, mucol.as<double>(), Pin, ldp, Wout, n, st);
+            if (!fp64 && P.A32.ptr()) gemm(false, false, n, mc, n, P.A32.ptr(), n, Pin, ldp, Wout, n, 1.0, 0.0, DT_F32);
+            else gemm(false, false, n, mc, n, P.op.A, P.op.lda, Pin, ldp, Wout, n, 1.0, 0.0);
+            launch_add_shift_cols(n, mc, muc, Pin, ldp, Wout, n, st);
         }
         return ColParts{nullptr, 0, 0, 0};
+    }
+
+    // Tout[:, j] = A_mu(j) X[:, j] for the columns j in cols (a restart's true
+    // residuals).  A strict subset goes through the product as a compact block: its
+    // columns are gathered into Z, multiplied into W (both are recomputed by the next
+    // iteration before use) and scattered into Tout.  hmu: every column's shift.
+    void product_cols(const double* X, int64_t ldx, double* Tout, bool fp64, const std::vector<int32_t>& cols,
+                      const std::vector<double>& hmu) {
+        const int64_t c = (int64_t)cols.size();
+        if (c == 0) return;
+        if (c == m) {
+            matmat(X, ldx, Tout, fp64);
+            return;
+        }
+        std::vector<double> muc((size_t)c);
+        for (int64_t q = 0; q < c; ++q) muc[q] = hmu[cols[q]];
+        RR_HIP(hipMemcpyAsync(cidx.ptr(), cols.data(), c * sizeof(int32_t), hipMemcpyHostToDevice, st));
+        RR_HIP(hipMemcpyAsync(mucomp.ptr(), muc.data(), c * sizeof(double), hipMemcpyHostToDevice, st));
+        launch_copy_cols(n, c, cidx.as<int32_t>(), X, ldx, nullptr, Z.as<double>(), n, st);
+        matmat(Z.as<double>(), n, W.as<double>(), fp64, c, mucomp.as<double>());
+        launch_copy_cols(n, c, nullptr, W.as<double>(), n, cidx.as<int32_t>(), Tout, n, st);
+        // the copies read host vectors staged by the runtime; keep them until the work ran
+        RR_HIP(hipStreamSynchronize(st));
     }
 
     // Zout = P_{mu(j)} Rin for every column.  Returns the block partials of

@@ -300,6 +300,9 @@ void launch_bxr_fused(int64_t n, int64_t m, double* X, int64_t ldx, double* R, c
                       const double* W, BState* st, ColParts pw, double* rr_part, int32_t* cnt, hipStream_t s);
 void launch_bp_fused(int64_t n, int64_t m, const double* Z, double* P, BState* st, ColParts rz, int32_t* cnt,
                      hipStream_t s);
+// dst[:, di[c]] = src[:, si[c]] for c < ncols (a null index list is the identity).
+void launch_copy_cols(int64_t n, int64_t ncols, const int32_t* si, const double* src, int64_t lds,
+                      const int32_t* di, double* dst, int64_t ldd, hipStream_t s);
 void launch_copy_flagged(int64_t n, int64_t m, const double* src, int64_t lds, double* dst,
                          int64_t ldd, const int32_t* flag, hipStream_t s);
 void launch_bresid(int64_t n, int64_t m, const double* B, int64_t ldb, const double* T, double* Rt,

@@ -1,11 +1,13 @@
 // Kernels of the batched solve: many independent PCG recurrences (one per
 // column, each with its own shift mu_j) advanced by fused launches.
 //
-//  * k_kgemm_f64_mfma : W = scale * K P + diag(mu_col) P for m columns at once.
-//      The kernel entries are the same float32 values as the single-vector
-//      matvec (bitwise: same formula over the same padded point records),
-//      widened to float64 and multiplied on v_mfma_f64_16x16x4_f64 with float64
-//      accumulation, so every column sees the same operator to float64 rounding.
+//  * k_kgemm_f32_mfma : W = scale * K P + diag(mu_col) P for m columns at once in
+//      the working precision: float32 entries (the formula of the vector-ALU
+//      symmetric matvec over the padded point records) times P in float32 on
+//      v_mfma_f32_32x32x2_f32, float32 sums over runs of 64 points added in float64.
+//  * k_kgemm_f64_mfma : the same product with float64 entries (the table exp2 of
+//      the float64 symmetric matvec) on v_mfma_f64_16x16x4_f64 (float64 mode and
+//      the refinement residuals).
 //  * per-column dot partials, scalar steps and vector updates with a per-column
 //      run flag: converged or restarting columns are left untouched.
 #include "common.hpp"
@@ -23,15 +25,18 @@ constexpr int KD_BM = 256, KD_BN = 128, KD_BK = 16, KD_THREADS = 1024;
 // MFMA tiles, 32 float64 accumulators per lane), four waves per SIMD: the float64
 // MFMA pipe needs several resident waves to stay busy.  Per step of 16 points the
 // block forms the 256 x 16 kernel tile (thread: one row, 4 points whose records
-// arrive through scalar loads) into LDS (k-major) and stages the 16 x 128 slice of P.
-// F64E: entries in float64 (difference form, float64 exp) instead of float32.
-template <int KIND, int DM, bool F64E>
+// arrive through scalar loads; float64 entries: difference form, float64 exp) into
+// LDS (k-major) and stages the 16 x 128 slice of P.
+template <int KIND, int DM>
 __global__ __launch_bounds__(KD_THREADS) void k_kgemm_f64_mfma(
-    int64_t n, const float* __restrict__ xa, const float* __restrict__ sqn, float c,
-    double kconst, double scale, const double* __restrict__ mucol, const double* __restrict__ P,
-    int64_t ldp, int64_t m, double* __restrict__ W, int64_t ldw) {
+    int64_t n, const float* __restrict__ xa, double g, double kconst, double scale,
+    const double* __restrict__ mucol, const double* __restrict__ P, int64_t ldp, int64_t m,
+    double* __restrict__ W, int64_t ldw) {
     __shared__ double As[KD_BK][KD_BM + 2];
     __shared__ double Bs[KD_BK][KD_BN + 2];
+    __shared__ double tab[EXP2_TAB];
+    exp2_table_fill(tab);
+    __syncthreads();
     const int t = threadIdx.x;
     const int lane = t & 63, wave = t >> 6;
     const int wm = wave & 3, wn = wave >> 2;
@@ -45,8 +50,6 @@ __global__ __launch_bounds__(KD_THREADS) void k_kgemm_f64_mfma(
     float xi[DM];
 #pragma unroll
     for (int k = 0; k < DM; ++k) xi[k] = xa[gic * DM + k];
-    const float mhn = -0.5f * sqn[gic];
-
     f64x4 acc[4][2];
 #pragma unroll
     for (int u = 0; u < 4; ++u)
@@ -60,22 +63,14 @@ __global__ __launch_bounds__(KD_THREADS) void k_kgemm_f64_mfma(
             const int64_t gj = j0 + p;
             const int64_t gjc = gj < n ? gj : n - 1;
             const float* xj = xa + gjc * DM;
-            double kv;
-            if (F64E) {
-                double r2 = 0.0;
+            double r2 = 0.0;
 #pragma unroll
-                for (int k = 0; k < DM; ++k) {
-                    const double df = (double)xi[k] - (double)xj[k];
-                    r2 = fma(df, df, r2);
-                }
-                kv = kval64<KIND>(r2, kconst);
-            } else {
-                float sv = kpair_init(mhn, sqn[gjc]);
-#pragma unroll
-                for (int k = 0; k < DM; ++k) sv = fmaf(xi[k], xj[k], sv);
-                kv = (double)kval32<KIND>(sv, c);
+            for (int k = 0; k < DM; ++k) {
+                const double df = (double)xi[k] - (double)xj[k];
+                r2 = fma(df, df, r2);
             }
-            As[p][trow] = (gj < n) ? kv : 0.0;
+            // 2^t with t = -g r^2 / 2 (the float64 entry of the symmetric matvec)
+            As[p][trow] = (gj < n) ? kentry64<KIND>(-0.5 * g * r2, kconst, tab) : 0.0;
         }
 #pragma unroll
         for (int s = 0; s < 2; ++s) {
@@ -118,11 +113,100 @@ __global__ __launch_bounds__(KD_THREADS) void k_kgemm_f64_mfma(
     }
 }
 
-template <int KIND, bool F64E>
+// The working-precision product (float32 and mixed modes): the same float32 entries
+// times P rounded to float32 on v_mfma_f32_32x32x2_f32 (twice the float64 MFMA rate),
+// with the float32 accumulators added into float64 sums every KF_FLUSH slices of 16
+// points, so the sums stay float64 beyond 64-term runs (the float32 working operator
+// of the multi-RHS block).  Block: 16 waves in a 4 x 4 grid of 32 x 32 wave tiles
+// (one MFMA tile each: 16 float32 and 16 float64 accumulators per lane), a 128 x 16
+// kernel tile formed per slice (thread: one row, two points) and a 16 x 128 slice of P.
+constexpr int KF32_BM = 128, KF32_BN = 128, KF32_BK = 16, KF32_FLUSH = 4, KF32_THREADS = 1024;
+typedef float f32x16_mm __attribute__((ext_vector_type(16)));
+
+template <int KIND, int DM>
+__global__ __launch_bounds__(KF32_THREADS) void k_kgemm_f32_mfma(
+    int64_t n, const float* __restrict__ xa, const float* __restrict__ sqn, float c, double scale,
+    const double* __restrict__ mucol, const double* __restrict__ P, int64_t ldp, int64_t m,
+    double* __restrict__ W, int64_t ldw) {
+    __shared__ float As[KF32_BK][KF32_BM + 4];
+    __shared__ float Bs[KF32_BK][KF32_BN + 4];
+    const int t = threadIdx.x;
+    const int lane = t & 63, wave = t >> 6;
+    const int wm = wave & 3, wn = wave >> 2;
+    const int64_t i0 = (int64_t)blockIdx.x * KF32_BM;
+    const int64_t c0 = (int64_t)blockIdx.y * KF32_BN;
+
+    const int trow = t & (KF32_BM - 1);
+    const int pg = __builtin_amdgcn_readfirstlane(t >> 7);   // 0..7: points 2 pg, 2 pg + 1 of a slice
+    const int64_t gi = i0 + trow;
+    const int64_t gic = gi < n ? gi : n - 1;
+    float xi[DM];
+#pragma unroll
+    for (int k = 0; k < DM; ++k) xi[k] = xa[gic * DM + k];
+    const float mhn = -0.5f * sqn[gic];
+
+    f32x16_mm acc;
+    double acc64[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+        acc[e] = 0.0f;
+        acc64[e] = 0.0;
+    }
+    int slices = 0;
+    for (int64_t j0 = 0; j0 < n; j0 += KF32_BK) {
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            const int p = 2 * pg + e;
+            const int64_t gj = j0 + p;
+            const int64_t gjc = gj < n ? gj : n - 1;
+            const float* xj = xa + gjc * DM;
+            float sv = kpair_init(mhn, sqn[gjc]);
+#pragma unroll
+            for (int k = 0; k < DM; ++k) sv = fmaf(xi[k], xj[k], sv);
+            As[p][trow] = gj < n ? kval32<KIND>(sv, c) : 0.0f;
+        }
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            const int k = t & 15;
+            const int col = (t >> 4) + 64 * s;
+            const int64_t gj = j0 + k, gc = c0 + col;
+            Bs[k][col] = (gj < n && gc < m) ? (float)P[gj + gc * ldp] : 0.0f;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kc = 0; kc < KF32_BK; kc += 2) {
+            const float a = As[kc + (lane >> 5)][wm * 32 + (lane & 31)];
+            const float b = Bs[kc + (lane >> 5)][wn * 32 + (lane & 31)];
+            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc, 0, 0, 0);
+        }
+        __syncthreads();
+        if (++slices == KF32_FLUSH) {
+            slices = 0;
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                acc64[e] += (double)acc[e];
+                acc[e] = 0.0f;
+            }
+        }
+    }
+    // accumulator element e of lane l: row 8 (e / 4) + 4 (l / 32) + e % 4, column l % 32
+    const int64_t gc = c0 + wn * 32 + (lane & 31);
+    if (gc >= m) return;
+    const double mu = mucol[gc];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+        const double v = acc64[e] + (double)acc[e];
+        const int64_t gr = i0 + wm * 32 + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
+        if (gr < n) W[gr + gc * ldw] = fma(scale, v, mu * P[gr + gc * ldp]);
+    }
+}
+
+template <int KIND>
 static void kd_dispatch(const KernelOp& op, float c, const double* mucol, const double* P,
                         int64_t ldp, int64_t m, double* W, int64_t ldw, hipStream_t st) {
     dim3 grid((unsigned)((op.n + KD_BM - 1) / KD_BM), (unsigned)((m + KD_BN - 1) / KD_BN));
-#define KDL(DD) k_kgemm_f64_mfma<KIND, DD, F64E><<<grid, KD_THREADS, 0, st>>>(op.n, op.xa, op.sqn, c, op.kconst, op.scale, mucol, P, ldp, m, W, ldw)
+    const double g = kernel_g64(op.kind, op.kconst);
+#define KDL(DD) k_kgemm_f64_mfma<KIND, DD><<<grid, KD_THREADS, 0, st>>>(op.n, op.xa, g, op.kconst, op.scale, mucol, P, ldp, m, W, ldw)
     switch (op.dm) {
         case 4: KDL(4); break;
         case 8: KDL(8); break;
@@ -132,17 +216,31 @@ static void kd_dispatch(const KernelOp& op, float c, const double* mucol, const 
 #undef KDL
 }
 
+template <int KIND>
+static void kf32_dispatch(const KernelOp& op, float c, const double* mucol, const double* P, int64_t ldp,
+                          int64_t m, double* W, int64_t ldw, hipStream_t st) {
+    dim3 grid((unsigned)((op.n + KF32_BM - 1) / KF32_BM), (unsigned)((m + KF32_BN - 1) / KF32_BN));
+#define KFL(DD) k_kgemm_f32_mfma<KIND, DD><<<grid, KF32_THREADS, 0, st>>>(op.n, op.xa, op.sqn, c, op.scale, mucol, P, ldp, m, W, ldw)
+    switch (op.dm) {
+        case 4: KFL(4); break;
+        case 8: KFL(8); break;
+        case 16: KFL(16); break;
+        default: KFL(32); break;
+    }
+#undef KFL
+}
+
 void launch_kernel_matmat_f64(const KernelOp& op, bool f64_entries, const double* mucol,
                               const double* P, int64_t ldp, int64_t m, double* W, int64_t ldw,
                               hipStream_t st) {
     const float c = kernel_c32(op.kind, op.kconst);
     ProfScope prof(f64_entries ? -1 : PROF_KERNEL_MATMAT, st);
     if (op.kind == 1) {
-        if (f64_entries) kd_dispatch<1, true>(op, c, mucol, P, ldp, m, W, ldw, st);
-        else kd_dispatch<1, false>(op, c, mucol, P, ldp, m, W, ldw, st);
+        if (f64_entries) kd_dispatch<1>(op, c, mucol, P, ldp, m, W, ldw, st);
+        else kf32_dispatch<1>(op, c, mucol, P, ldp, m, W, ldw, st);
     } else {
-        if (f64_entries) kd_dispatch<2, true>(op, c, mucol, P, ldp, m, W, ldw, st);
-        else kd_dispatch<2, false>(op, c, mucol, P, ldp, m, W, ldw, st);
+        if (f64_entries) kd_dispatch<2>(op, c, mucol, P, ldp, m, W, ldw, st);
+        else kf32_dispatch<2>(op, c, mucol, P, ldp, m, W, ldw, st);
     }
 }
 
@@ -327,6 +425,22 @@ void launch_bp_fused(int64_t n, int64_t m, const double* Z, double* P, BState* s
     k_bp_fused<<<vgrid(n, m), BC_THREADS, 0, s>>>(n, Z, P, st, rz, cnt);
 }
 
+
+// dst[:, di(c)] = src[:, si(c)] for c < ncols, si / di = the index lists or the identity
+__global__ __launch_bounds__(BC_THREADS) void k_copy_cols(int64_t n, const int32_t* __restrict__ si,
+                                                         const double* __restrict__ src, int64_t lds,
+                                                         const int32_t* __restrict__ di, double* __restrict__ dst,
+                                                         int64_t ldd) {
+    const int64_t c = blockIdx.y;
+    const int64_t sc = si ? si[c] : c, dc = di ? di[c] : c;
+    for (int64_t i = (int64_t)blockIdx.x * BC_THREADS + threadIdx.x; i < n; i += (int64_t)gridDim.x * BC_THREADS)
+        dst[i + dc * ldd] = src[i + sc * lds];
+}
+void launch_copy_cols(int64_t n, int64_t ncols, const int32_t* si, const double* src, int64_t lds,
+                      const int32_t* di, double* dst, int64_t ldd, hipStream_t s) {
+    if (ncols <= 0) return;
+    k_copy_cols<<<vgrid(n, ncols), BC_THREADS, 0, s>>>(n, si, src, lds, di, dst, ldd);
+}
 
 // For flagged columns: dst[:, j] = src[:, j]
 __global__ __launch_bounds__(BC_THREADS) void k_copy_flagged(int64_t n, const double* __restrict__ src,
