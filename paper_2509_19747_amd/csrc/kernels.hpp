@@ -293,9 +293,10 @@ void launch_bstate_start(ColParts part, int64_t m, BState* st, const int32_t* st
 int bxr_blocks(int64_t n);
 // The x/r update with alpha folded in (alpha_j = rho_j / sum of pw's partials, formed
 // by every block) and the p update with beta folded in (beta_j = sum of rz's partials
-// / rho_j); the last block of each column records the scalars and stop tests (what
-// launch_bscal_alpha / _rr / _beta do) and resets its counter: cnt holds m int32
-// that are zero between launches.
+// / rho_j); the last block of each column records the scalars and stop tests and
+// resets its counter: cnt holds m int32 that are zero between launches.  More than 32
+// columns: the updates write their partials and a second launch (one block per column)
+// records the scalars from the same sums (no per-block device-scope fence).
 void launch_bxr_fused(int64_t n, int64_t m, double* X, int64_t ldx, double* R, const double* P,
                       const double* W, BState* st, ColParts pw, double* rr_part, int32_t* cnt, hipStream_t s);
 void launch_bp_fused(int64_t n, int64_t m, const double* Z, double* P, BState* st, ColParts rz, int32_t* cnt,

@@ -56,29 +56,41 @@ __global__ __launch_bounds__(KD_THREADS) void k_kgemm_f64_mfma(
 #pragma unroll
         for (int v = 0; v < 2; ++v) acc[u][v] = f64x4{0.0, 0.0, 0.0, 0.0};
 
+    // the next step's point records (wave-uniform) and P values are loaded while the
+    // current step's MFMAs run
+    float xj[4][DM];
+    double pv[2];
+    auto load = [&](int64_t j0) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int64_t gj = j0 + pg * 4 + e;
+            const int64_t gjc = gj < n ? gj : n - 1;
+#pragma unroll
+            for (int k = 0; k < DM; ++k) xj[e][k] = xa[gjc * DM + k];
+        }
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            const int64_t gj = j0 + (t & 15), gc = c0 + (t >> 4) + 64 * s;
+            pv[s] = (gj < n && gc < m) ? P[gj + gc * ldp] : 0.0;
+        }
+    };
+    load(0);
     for (int64_t j0 = 0; j0 < n; j0 += KD_BK) {
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
             const int p = pg * 4 + e;
-            const int64_t gj = j0 + p;
-            const int64_t gjc = gj < n ? gj : n - 1;
-            const float* xj = xa + gjc * DM;
             double r2 = 0.0;
 #pragma unroll
             for (int k = 0; k < DM; ++k) {
-                const double df = (double)xi[k] - (double)xj[k];
+                const double df = (double)xi[k] - (double)xj[e][k];
                 r2 = fma(df, df, r2);
             }
             // 2^t with t = -g r^2 / 2 (the float64 entry of the symmetric matvec)
-            As[p][trow] = (gj < n) ? kentry64<KIND>(-0.5 * g * r2, kconst, tab) : 0.0;
+            As[p][trow] = (j0 + p < n) ? kentry64<KIND>(-0.5 * g * r2, kconst, tab) : 0.0;
         }
 #pragma unroll
-        for (int s = 0; s < 2; ++s) {
-            const int k = t & 15;
-            const int col = (t >> 4) + 64 * s;
-            const int64_t gj = j0 + k, gc = c0 + col;
-            Bs[k][col] = (gj < n && gc < m) ? P[gj + gc * ldp] : 0.0;
-        }
+        for (int s = 0; s < 2; ++s) Bs[t & 15][(t >> 4) + 64 * s] = pv[s];
+        if (j0 + KD_BK < n) load(j0 + KD_BK);
         __syncthreads();
 #pragma unroll
         for (int kc = 0; kc < KD_BK; kc += 4) {
@@ -152,26 +164,39 @@ __global__ __launch_bounds__(KF32_THREADS) void k_kgemm_f32_mfma(
         acc[e] = 0.0f;
         acc64[e] = 0.0;
     }
+    // the next slice's point records (wave-uniform) and P values are loaded while the
+    // current slice's MFMAs run
+    float xj[2][DM], sqj[2];
+    double pv[2];
+    auto load = [&](int64_t j0) {
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            const int64_t gj = j0 + 2 * pg + e;
+            const int64_t gjc = gj < n ? gj : n - 1;
+#pragma unroll
+            for (int k = 0; k < DM; ++k) xj[e][k] = xa[gjc * DM + k];
+            sqj[e] = sqn[gjc];
+        }
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            const int64_t gj = j0 + (t & 15), gc = c0 + (t >> 4) + 64 * s;
+            pv[s] = (gj < n && gc < m) ? P[gj + gc * ldp] : 0.0;
+        }
+    };
+    load(0);
     int slices = 0;
     for (int64_t j0 = 0; j0 < n; j0 += KF32_BK) {
 #pragma unroll
         for (int e = 0; e < 2; ++e) {
             const int p = 2 * pg + e;
-            const int64_t gj = j0 + p;
-            const int64_t gjc = gj < n ? gj : n - 1;
-            const float* xj = xa + gjc * DM;
-            float sv = kpair_init(mhn, sqn[gjc]);
+            float sv = kpair_init(mhn, sqj[e]);
 #pragma unroll
-            for (int k = 0; k < DM; ++k) sv = fmaf(xi[k], xj[k], sv);
-            As[p][trow] = gj < n ? kval32<KIND>(sv, c) : 0.0f;
+            for (int k = 0; k < DM; ++k) sv = fmaf(xi[k], xj[e][k], sv);
+            As[p][trow] = j0 + p < n ? kval32<KIND>(sv, c) : 0.0f;
         }
 #pragma unroll
-        for (int s = 0; s < 2; ++s) {
-            const int k = t & 15;
-            const int col = (t >> 4) + 64 * s;
-            const int64_t gj = j0 + k, gc = c0 + col;
-            Bs[k][col] = (gj < n && gc < m) ? (float)P[gj + gc * ldp] : 0.0f;
-        }
+        for (int s = 0; s < 2; ++s) Bs[t & 15][(t >> 4) + 64 * s] = (float)pv[s];
+        if (j0 + KF32_BK < n) load(j0 + KF32_BK);
         __syncthreads();
 #pragma unroll
         for (int kc = 0; kc < KF32_BK; kc += 2) {
@@ -351,29 +376,9 @@ RR_DEV bool last_block_of_column(int32_t* cnt, int64_t j, int nbx, int* flag) {
 // alpha_j = rho_j / p_j^T w_j; x_j += alpha_j p_j, r_j -= alpha_j w_j, partials of
 // ||r_j||^2; last block: pw, alpha, ||r||^2, the iteration count and the stop tests.
 // Block bx of the nbx blocks of column j (shared with the grouped serving kernel).
-RR_DEV void bxr_block(int bx, int nbx, int64_t j, int64_t n, double* __restrict__ X, int64_t ldx,
-                      double* __restrict__ R, const double* __restrict__ P, const double* __restrict__ W,
-                      BState* st, const ColParts& pw, double* __restrict__ rr_part, int32_t* cnt) {
-    __shared__ double sc[BC_THREADS / WAVE];
-    __shared__ int last;
-    if (!st[j].run) return;
-    const double pwj = colsum_block(pw, j, sc);
-    const bool ok = pwj > 0.0 && isfinite(pwj);
-    const double a = ok ? st[j].rho / pwj : 0.0;
-    double acc = 0.0;
-    if (ok)
-        for (int64_t i = (int64_t)bx * BC_THREADS + threadIdx.x; i < n; i += (int64_t)nbx * BC_THREADS) {
-            X[i + j * ldx] = fma(a, P[i + j * n], X[i + j * ldx]);
-            const double ri = fma(-a, W[i + j * n], R[i + j * n]);
-            R[i + j * n] = ri;
-            acc = fma(ri, ri, acc);
-        }
-    acc = block_sum(acc, sc);
-    if (threadIdx.x == 0) rr_part[j * nbx + bx] = acc;
-    if (!last_block_of_column(cnt, j, nbx, &last)) return;
-    const double rr = colsum_block(ColParts{rr_part, nbx, 1, (int64_t)nbx}, j, sc);
-    if (threadIdx.x != 0) return;
-    cnt[j] = 0;
+// The column's scalars after its x and r update: pw, alpha, ||r||^2, the iteration
+// count and the stop tests (thread 0 of the block that records them).
+RR_DEV void bxr_record(int64_t j, BState* st, double pwj, bool ok, double a, double rr) {
     st[j].pw = pwj;
     if (!ok) { st[j].run = 0; st[j].code = STOP_BREAKDOWN; return; }
     st[j].alpha = a;
@@ -384,6 +389,45 @@ RR_DEV void bxr_block(int bx, int nbx, int64_t j, int64_t n, double* __restrict_
     else if (rr <= st[j].target2) { st[j].run = 0; st[j].code = STOP_TARGET; }
     else if (it >= st[j].maxit) { st[j].run = 0; st[j].code = STOP_MAXIT; }
 }
+
+// alpha_j and block bx's share of x_j += alpha_j p_j, r_j -= alpha_j w_j; writes the
+// block's partial of ||r_j||^2.  Returns false when the column is not running.
+RR_DEV bool bxr_apply(int bx, int nbx, int64_t j, int64_t n, double* __restrict__ X, int64_t ldx,
+                      double* __restrict__ R, const double* __restrict__ P, const double* __restrict__ W,
+                      const BState* st, const ColParts& pw, double* __restrict__ rr_part, double* sc,
+                      double& pwj, bool& ok, double& a) {
+    if (!st[j].run) return false;
+    pwj = colsum_block(pw, j, sc);
+    ok = pwj > 0.0 && isfinite(pwj);
+    a = ok ? st[j].rho / pwj : 0.0;
+    double acc = 0.0;
+    if (ok)
+        for (int64_t i = (int64_t)bx * BC_THREADS + threadIdx.x; i < n; i += (int64_t)nbx * BC_THREADS) {
+            X[i + j * ldx] = fma(a, P[i + j * n], X[i + j * ldx]);
+            const double ri = fma(-a, W[i + j * n], R[i + j * n]);
+            R[i + j * n] = ri;
+            acc = fma(ri, ri, acc);
+        }
+    acc = block_sum(acc, sc);
+    if (threadIdx.x == 0) rr_part[j * nbx + bx] = acc;
+    return true;
+}
+
+// Fused: the last block of the column to finish records the scalars.
+RR_DEV void bxr_block(int bx, int nbx, int64_t j, int64_t n, double* __restrict__ X, int64_t ldx,
+                      double* __restrict__ R, const double* __restrict__ P, const double* __restrict__ W,
+                      BState* st, const ColParts& pw, double* __restrict__ rr_part, int32_t* cnt) {
+    __shared__ double sc[BC_THREADS / WAVE];
+    __shared__ int last;
+    double pwj, a;
+    bool ok;
+    if (!bxr_apply(bx, nbx, j, n, X, ldx, R, P, W, st, pw, rr_part, sc, pwj, ok, a)) return;
+    if (!last_block_of_column(cnt, j, nbx, &last)) return;
+    const double rr = colsum_block(ColParts{rr_part, nbx, 1, (int64_t)nbx}, j, sc);
+    if (threadIdx.x != 0) return;
+    cnt[j] = 0;
+    bxr_record(j, st, pwj, ok, a, rr);
+}
 __global__ __launch_bounds__(BC_THREADS) void k_bxr_fused(int64_t n, double* __restrict__ X, int64_t ldx,
                                                          double* __restrict__ R, const double* __restrict__ P,
                                                          const double* __restrict__ W, BState* st, ColParts pw,
@@ -391,37 +435,105 @@ __global__ __launch_bounds__(BC_THREADS) void k_bxr_fused(int64_t n, double* __r
     bxr_block(blockIdx.x, gridDim.x, blockIdx.y, n, X, ldx, R, P, W, st, pw, rr_part, cnt);
 }
 
-// beta_j = r_j^T z_j / rho_j; p_j = z_j + beta_j p_j; last block: beta, rho
+// Split (wide column blocks): the update without the election of a column's last
+// block, whose device-scope fence writes back the L2 on every block; one block per
+// column then records the scalars from the same fixed-order sums.
+__global__ __launch_bounds__(BC_THREADS) void k_bxr_part(int64_t n, double* __restrict__ X, int64_t ldx,
+                                                        double* __restrict__ R, const double* __restrict__ P,
+                                                        const double* __restrict__ W, const BState* st,
+                                                        ColParts pw, double* __restrict__ rr_part) {
+    __shared__ double sc[BC_THREADS / WAVE];
+    double pwj, a;
+    bool ok;
+    (void)bxr_apply(blockIdx.x, gridDim.x, blockIdx.y, n, X, ldx, R, P, W, st, pw, rr_part, sc, pwj, ok, a);
+}
+__global__ __launch_bounds__(BC_THREADS) void k_bxr_tail(int nbx, BState* st, ColParts pw,
+                                                        const double* __restrict__ rr_part) {
+    __shared__ double sc[BC_THREADS / WAVE];
+    const int64_t j = blockIdx.x;
+    if (!st[j].run) return;
+    const double pwj = colsum_block(pw, j, sc);
+    const bool ok = pwj > 0.0 && isfinite(pwj);
+    const double a = ok ? st[j].rho / pwj : 0.0;
+    const double rr = colsum_block(ColParts{rr_part, nbx, 1, (int64_t)nbx}, j, sc);
+    if (threadIdx.x == 0) bxr_record(j, st, pwj, ok, a, rr);
+}
+
+// beta_j = r_j^T z_j / rho_j and block bx's share of p_j = z_j + beta_j p_j.
+// Returns false when the column is not running.
+RR_DEV bool bp_apply(int bx, int nbx, int64_t j, int64_t n, const double* __restrict__ Z,
+                     double* __restrict__ P, const BState* st, const ColParts& rz, double* sc, double& rzj,
+                     bool& ok, double& b) {
+    if (!st[j].run) return false;
+    rzj = colsum_block(rz, j, sc);
+    ok = rzj > 0.0 && isfinite(rzj);
+    b = ok ? rzj / st[j].rho : 0.0;
+    if (ok)
+        for (int64_t i = (int64_t)bx * BC_THREADS + threadIdx.x; i < n; i += (int64_t)nbx * BC_THREADS)
+            P[i + j * n] = fma(b, P[i + j * n], Z[i + j * n]);
+    return true;
+}
+RR_DEV void bp_record(int64_t j, BState* st, double rzj, bool ok, double b) {
+    if (!ok) { st[j].run = 0; st[j].code = STOP_BREAKDOWN; return; }
+    st[j].beta = b;
+    st[j].rho = rzj;
+}
+
+// Fused: the last block of the column records beta and rho.
 RR_DEV void bp_block(int bx, int nbx, int64_t j, int64_t n, const double* __restrict__ Z,
                      double* __restrict__ P, BState* st, const ColParts& rz, int32_t* cnt) {
     __shared__ double sc[BC_THREADS / WAVE];
     __shared__ int last;
-    if (!st[j].run) return;
-    const double rzj = colsum_block(rz, j, sc);
-    const bool ok = rzj > 0.0 && isfinite(rzj);
-    const double b = ok ? rzj / st[j].rho : 0.0;
-    if (ok)
-        for (int64_t i = (int64_t)bx * BC_THREADS + threadIdx.x; i < n; i += (int64_t)nbx * BC_THREADS)
-            P[i + j * n] = fma(b, P[i + j * n], Z[i + j * n]);
+    double rzj, b;
+    bool ok;
+    if (!bp_apply(bx, nbx, j, n, Z, P, st, rz, sc, rzj, ok, b)) return;
     if (!last_block_of_column(cnt, j, nbx, &last)) return;
     if (threadIdx.x != 0) return;
     cnt[j] = 0;
-    if (!ok) { st[j].run = 0; st[j].code = STOP_BREAKDOWN; return; }
-    st[j].beta = b;
-    st[j].rho = rzj;
+    bp_record(j, st, rzj, ok, b);
 }
 __global__ __launch_bounds__(BC_THREADS) void k_bp_fused(int64_t n, const double* __restrict__ Z,
                                                         double* __restrict__ P, BState* st, ColParts rz,
                                                         int32_t* cnt) {
     bp_block(blockIdx.x, gridDim.x, blockIdx.y, n, Z, P, st, rz, cnt);
 }
+__global__ __launch_bounds__(BC_THREADS) void k_bp_part(int64_t n, const double* __restrict__ Z,
+                                                       double* __restrict__ P, const BState* st, ColParts rz) {
+    __shared__ double sc[BC_THREADS / WAVE];
+    double rzj, b;
+    bool ok;
+    (void)bp_apply(blockIdx.x, gridDim.x, blockIdx.y, n, Z, P, st, rz, sc, rzj, ok, b);
+}
+__global__ __launch_bounds__(BC_THREADS) void k_bp_tail(BState* st, ColParts rz) {
+    __shared__ double sc[BC_THREADS / WAVE];
+    const int64_t j = blockIdx.x;
+    if (!st[j].run) return;
+    const double rzj = colsum_block(rz, j, sc);
+    const bool ok = rzj > 0.0 && isfinite(rzj);
+    const double b = ok ? rzj / st[j].rho : 0.0;
+    if (threadIdx.x == 0) bp_record(j, st, rzj, ok, b);
+}
+
+// Column blocks wider than this take the split updates.
+constexpr int64_t BUPDATE_FUSED_MAX = 32;
 
 void launch_bxr_fused(int64_t n, int64_t m, double* X, int64_t ldx, double* R, const double* P,
                       const double* W, BState* st, ColParts pw, double* rr_part, int32_t* cnt, hipStream_t s) {
+    if (m > BUPDATE_FUSED_MAX) {
+        const dim3 g = vgrid(n, m);
+        k_bxr_part<<<g, BC_THREADS, 0, s>>>(n, X, ldx, R, P, W, st, pw, rr_part);
+        k_bxr_tail<<<(unsigned)m, BC_THREADS, 0, s>>>((int)g.x, st, pw, rr_part);
+        return;
+    }
     k_bxr_fused<<<vgrid(n, m), BC_THREADS, 0, s>>>(n, X, ldx, R, P, W, st, pw, rr_part, cnt);
 }
 void launch_bp_fused(int64_t n, int64_t m, const double* Z, double* P, BState* st, ColParts rz, int32_t* cnt,
                      hipStream_t s) {
+    if (m > BUPDATE_FUSED_MAX) {
+        k_bp_part<<<vgrid(n, m), BC_THREADS, 0, s>>>(n, Z, P, st, rz);
+        k_bp_tail<<<(unsigned)m, BC_THREADS, 0, s>>>(st, rz);
+        return;
+    }
     k_bp_fused<<<vgrid(n, m), BC_THREADS, 0, s>>>(n, Z, P, st, rz, cnt);
 }
 
