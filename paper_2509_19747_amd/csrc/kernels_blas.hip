@@ -374,17 +374,23 @@ __global__ __launch_bounds__(DM_THREADS) void k_dense_matvec(int64_t n, const TA
             for (int c = 0; c < DM_COLS; ++c) {
                 const int64_t j = j0 + c;
                 if (j < n) {
+                    // large n: A streams through once, so non-temporal loads keep u in the
+                    // caches (a small matrix stays cache-resident across iterations instead)
                     const TA* col = A + j * lda + v * VW;
                     if constexpr (sizeof(TA) == 4) {
-                        const float4 a = *(const float4*)col;
-                        acc[c] = fma((double)a.x, uu[0], acc[c]);
-                        acc[c] = fma((double)a.y, uu[1], acc[c]);
-                        acc[c] = fma((double)a.z, uu[2], acc[c]);
-                        acc[c] = fma((double)a.w, uu[3], acc[c]);
+                        typedef float f4v __attribute__((ext_vector_type(4)));
+                        const f4v a = DM_COLS >= 16 ? __builtin_nontemporal_load(reinterpret_cast<const f4v*>(col))
+                                                    : *reinterpret_cast<const f4v*>(col);
+                        acc[c] = fma((double)a[0], uu[0], acc[c]);
+                        acc[c] = fma((double)a[1], uu[1], acc[c]);
+                        acc[c] = fma((double)a[2], uu[2], acc[c]);
+                        acc[c] = fma((double)a[3], uu[3], acc[c]);
                     } else {
-                        const double2 a = *(const double2*)col;
-                        acc[c] = fma(a.x, uu[0], acc[c]);
-                        acc[c] = fma(a.y, uu[1], acc[c]);
+                        typedef double d2v __attribute__((ext_vector_type(2)));
+                        const d2v a = DM_COLS >= 16 ? __builtin_nontemporal_load(reinterpret_cast<const d2v*>(col))
+                                                    : *reinterpret_cast<const d2v*>(col);
+                        acc[c] = fma(a[0], uu[0], acc[c]);
+                        acc[c] = fma(a[1], uu[1], acc[c]);
                     }
                 }
             }
@@ -421,10 +427,11 @@ __global__ __launch_bounds__(DM_THREADS) void k_dense_matvec(int64_t n, const TA
     }
 }
 
-// Columns per block: 8 for large n; 2 below 8,192, so a small matrix still spreads
-// over every compute unit.  A column's sum is formed the same way either way (each
-// thread's strided terms, then the block reduction in a fixed order).
-static int dense_matvec_cols(int64_t n) { return n <= 8192 ? 2 : 8; }
+// Columns per block: 16 for large n (each u chunk read from cache serves 16 columns);
+// 2 below 8,192, so a small matrix still spreads over every compute unit.  A column's
+// sum is formed the same way either way (each thread's strided terms, then the block
+// reduction in a fixed order).
+static int dense_matvec_cols(int64_t n) { return n <= 8192 ? 2 : 16; }
 int dense_matvec_blocks(int64_t n) {
     const int c = dense_matvec_cols(n);
     return (int)((n + c - 1) / c);
@@ -439,7 +446,7 @@ void launch_dense_matvec(int dta, int64_t n, const void* A, int64_t lda, const d
     if (dense_matvec_cols(n) == 2) {
         if (dta == DT_F32) KDM(float, 2); else KDM(double, 2);
     } else {
-        if (dta == DT_F32) KDM(float, 8); else KDM(double, 8);
+        if (dta == DT_F32) KDM(float, 16); else KDM(double, 16);
     }
 #undef KDM
 }
