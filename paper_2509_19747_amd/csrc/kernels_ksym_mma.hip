@@ -239,18 +239,45 @@ RR_DEV void ksym_mma_item(unsigned item, int64_t n, const float* __restrict__ xa
         // in the diagonal block wave w forms only the column tiles >= w, so each pair
         // is evaluated once and the operator stays exactly symmetric
         const int wlo = bj == bi ? wave : -1;
-#pragma unroll 1
-        for (int ct = ct0; ct < ct1; ++ct) {
-            if (ct <= wlo) {
-                if (ct == wlo) {
-                    entries(ct, dots(ct), std::true_type{});
-                } else {
+        if constexpr (NR == 2 && sizeof(T) == 8) {
+            // Two columns with float64 sums: the next tile's exponent MFMAs are issued
+            // before this tile's entries, so the matrix cores run while the vector ALU
+            // works (the second accumulator fits this variant's registers; the others
+            // would spill and run each tile's MFMAs and entries in turn, below).
+            int ct = ct0;
+            // in a diagonal block the tiles below the wave's own hold no pairs
+            for (; ct < ct1 && ct < wlo; ++ct)
 #pragma unroll
-                    for (int q = 0; q < NR; ++q) colw[wave][q][32 * ct + l32] = T(0);
-                }
-                continue;
+                for (int q = 0; q < NR; ++q) colw[wave][q][32 * ct + l32] = T(0);
+            if (ct < ct1 && ct == wlo) {
+                entries(ct, dots(ct), std::true_type{});
+                ++ct;
             }
-            entries(ct, dots(ct), std::false_type{});
+            if (ct < ct1) {
+                f32x16_t dcur = dots(ct);
+#pragma unroll 1
+                for (; ct + 1 < ct1; ++ct) {
+                    const f32x16_t dnext = dots(ct + 1);
+                    __builtin_amdgcn_sched_barrier(0);
+                    entries(ct, dcur, std::false_type{});
+                    dcur = dnext;
+                }
+                entries(ct, dcur, std::false_type{});
+            }
+        } else {
+#pragma unroll 1
+            for (int ct = ct0; ct < ct1; ++ct) {
+                if (ct <= wlo) {
+                    if (ct == wlo) {
+                        entries(ct, dots(ct), std::true_type{});
+                    } else {
+#pragma unroll
+                        for (int q = 0; q < NR; ++q) colw[wave][q][32 * ct + l32] = T(0);
+                    }
+                    continue;
+                }
+                entries(ct, dots(ct), std::false_type{});
+            }
         }
         __syncthreads();
         const int64_t slot = bj != bi ? cslot : dslot;
