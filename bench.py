@@ -52,6 +52,75 @@ def _traffic(kernel: str, src_hash: str):
     return t.get("bytes_per_launch")
 
 
+TRAFFIC_SOURCES = ("kernels_ksym_mma.hip", "kmma.hpp", "kentry.hpp", "common.hpp")
+TRAFFIC_KERNEL = "k_ksym_mma<1, 16, 1, double>"
+
+
+def traffic_from_counters(d: str) -> dict:
+    """Write profiles/traffic.json from two rocprofv3 --pmc csv runs under d.
+
+    d/FETCH_SIZE and d/WRITE_SIZE hold one run each of the headline step with
+    --copy-calibration.  Each counter is scaled by what it reads for the 1 GiB
+    device-to-device copy (bytes moved / counter KiB), and the headline matvec's
+    bytes per launch are the scaled medians over its launches.
+    """
+    import csv
+
+    med, cal = {}, {}
+    for c in ("FETCH_SIZE", "WRITE_SIZE"):
+        with open(os.path.join(d, c, f"{c}_counter_collection.csv")) as f:
+            rows = list(csv.DictReader(f))
+        copy = [float(r["Counter_Value"]) for r in rows if "copy" in r["Kernel_Name"].lower()]
+        km = sorted(float(r["Counter_Value"]) for r in rows if TRAFFIC_KERNEL in r["Kernel_Name"])
+        if not copy or not km:
+            raise SystemExit(f"{c}: no calibration copy or no {TRAFFIC_KERNEL} launch in {d}")
+        cal[c], med[c] = max(copy), km[len(km) // 2]
+    fs, ws = (1 << 20) / cal["FETCH_SIZE"], (1 << 20) / cal["WRITE_SIZE"]
+    fb, wb = med["FETCH_SIZE"] * fs * 1024, med["WRITE_SIZE"] * ws * 1024
+    t = {"k_ksym_mma": {
+        "src_hash": _src_hash(*TRAFFIC_SOURCES), "bytes_per_launch": fb + wb,
+        "fetch_bytes": fb, "write_bytes": wb, "fetch_scale": fs, "write_scale": ws,
+        "fetch_kib": med["FETCH_SIZE"], "write_kib": med["WRITE_SIZE"],
+        "workload": "kernel ridge RBF n=50000 d=16, one float64-sum launch (1 column)",
+        "calibration": "1 GiB device-to-device copy: FETCH_SIZE %d KiB, WRITE_SIZE %d KiB"
+                       % (cal["FETCH_SIZE"], cal["WRITE_SIZE"])}}
+    with open(os.path.join(ROOT, "profiles", "traffic.json"), "w") as f:
+        json.dump(t, f, indent=1)
+        f.write("\n")
+    return t
+
+
+def trace_summary(db: str, top: int = 25) -> str:
+    """Markdown table of the kernels in a rocprofv3 --kernel-trace results database.
+
+    Per kernel: launches, total and mean duration, and the mean over the launches
+    longer than a tenth of the kernel's median ("work": PCG iterations past a
+    column's convergence, which the device-side stop flags turn into near-empty
+    launches, are left out of it).
+    """
+    import sqlite3
+    import statistics
+
+    c = sqlite3.connect(db)
+    rows = c.execute("select S.display_name, K.end - K.start from rocpd_kernel_dispatch K "
+                     "join rocpd_info_kernel_symbol S on S.id = K.kernel_id and S.guid = K.guid"
+                     ).fetchall()
+    by = {}
+    for name, dur in rows:
+        by.setdefault(name, []).append(dur / 1000.0)
+    total = sum(sum(v) for v in by.values())
+    out = [f"Total kernel time {total / 1000:.1f} ms over {len(rows)} launches.", "",
+           "| kernel | calls | total ms | avg us | avg us (work) | work calls | min us | max us | % |",
+           "|---|---|---|---|---|---|---|---|---|"]
+    for name, v in sorted(by.items(), key=lambda kv: -sum(kv[1]))[:top]:
+        med = statistics.median(v)
+        w = [x for x in v if x >= 0.1 * med]
+        out.append(f"| `{name}` | {len(v)} | {sum(v) / 1000:.2f} | {sum(v) / len(v):.2f} | "
+                   f"{sum(w) / len(w):.2f} | {len(w)} | {min(v):.2f} | {max(v):.2f} | "
+                   f"{100 * sum(v) / total:.1f} |")
+    return "\n".join(out)
+
+
 def cpu_baseline(prob, iters_hint: int, restarts_hint: int, power_iters: int, full: bool = False):
     """Time the float64 oracle on the host cores and express it in solves/s.
 
@@ -148,7 +217,20 @@ def main():
                     help="serving: grouped replay lanes (0: each request replays its own graph)")
     ap.add_argument("--dump", default="", help="serving: write per-request records (JSON lines)")
     ap.add_argument("--nrhs", type=int, default=256, help="batched: right-hand sides per shift")
+    ap.add_argument("--traffic-from", default="",
+                    help="no GPU work: derive profiles/traffic.json from the FETCH_SIZE and "
+                         "WRITE_SIZE counter runs under this directory, then exit")
+    ap.add_argument("--trace-summary", default="",
+                    help="no GPU work: print a markdown table of the kernels in this rocprofv3 "
+                         "--kernel-trace results database, then exit")
+    ap.add_argument("--top", type=int, default=25, help="trace summary: kernels listed")
     args = ap.parse_args()
+    if args.trace_summary:
+        print(trace_summary(args.trace_summary, args.top))
+        return
+    if args.traffic_from:
+        print(json.dumps(traffic_from_counters(args.traffic_from)))
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
               "sharding is a design, not a build", file=sys.stderr)
@@ -251,7 +333,7 @@ def main():
     pairs = n * (n + 1) / 2.0
     kmv_avg = kmv_ms / max(kmv_n, 1)
     sk_avg = sk_ms / max(sk_n, 1)
-    h = _src_hash("kernels_ksym_mma.hip", "kmma.hpp", "kentry.hpp", "common.hpp")
+    h = _src_hash(*TRAFFIC_SOURCES)
     flops_per_launch = (2 * d + 3) * pairs
     if kmv_ms >= sk_ms:
         ach = flops_per_launch / (kmv_avg * 1e-3) / 1e12
