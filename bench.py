@@ -204,9 +204,10 @@ def main():
                          "smaller shifts (reported under 'context', outside the timed steps)")
     ap.add_argument("--graph", action="store_true", help="replay PCG batches as hipGraphs")
     ap.add_argument("--workload", default="kernel-ridge",
-                    choices=["kernel-ridge", "small", "precision", "batched", "serving"],
+                    choices=["kernel-ridge", "small", "precision", "batched", "serving", "variants"],
                     help="kernel-ridge is the headline step; the others measure the remaining "
-                         "paths (dense mixed precision, batched multi-shift, serving)")
+                         "paths (dense mixed precision, batched multi-shift, serving) and "
+                         "the solver and preconditioner variants")
     ap.add_argument("--requests", type=int, default=2200, help="serving: number of requests")
     ap.add_argument("--rate", type=float, default=200.0, help="serving: arrivals per second")
     ap.add_argument("--slots", type=int, default=16, help="serving: concurrent requests")
@@ -237,7 +238,7 @@ def main():
         sys.exit(2)
     if args.workload != "kernel-ridge":
         {"small": bench_small, "precision": bench_precision, "batched": bench_batched,
-         "serving": bench_serving}[args.workload](args)
+         "serving": bench_serving, "variants": bench_variants}[args.workload](args)
         return
 
     import numpy as np
@@ -592,6 +593,133 @@ def bench_small(args):
         out["cpu_baseline"] = {"value": 1.0 / t_all, "unit": "solves/s", "cores": _host_threads(),
                                "kind": "oracle", "sample": f"the whole float64 oracle build and PCG solve "
                                                            f"({res.iters} iterations), timed once"}
+    print(json.dumps(out), flush=True)
+
+
+def bench_variants(args):
+    """The paper's other solvers and preconditioner forms on the headline problem (kernel
+    ridge, RBF, n = 50,000, d = 16, mu = 1e-4, tol 1e-6, float32-class entries with float64
+    refinement), each timed on one GPU and checked against the float64 operator:
+      * C-RandRAND with CG and with MINRES, R-RandRAND (Algorithm RandRAND_CG) with CG and
+        MINRES and split R-RandRAND (Algorithm RandRAND_CG_split), all on one SRHT handle
+        (l = 500; its build timed once);
+      * block MINRES and block CG over 8 right-hand sides (Section 7.2.2), beside the
+        per-column batched PCG on the same block;
+      * the basis-less handle (Algorithm BL_RandRAND_PCG, column sampling, l = 500);
+      * q = 1 (eq. testmatrix), adaptive l from 64 (eq. ad_criterion, l_max = 1,024), and
+        the shifted-Cholesky sweep over the shifts 1e-3 .. 1e-6 (Section 5.1).
+    Times are medians over `steps` runs after `warmup` runs."""
+    import statistics
+
+    import numpy as np
+    import torch
+
+    import paper_2509_19747_amd as rr
+    from paper_2509_19747_amd import binding as rb
+    import workloads
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    prob = workloads.cfg_kernel_ridge()
+    n, l, mu, tol = prob.n, prob.l, prob.mus[0], prob.tol
+    kop = rr.kernel_operator(rr.OP_RBF, torch.from_numpy(prob.pts).cuda(), prob.kconst, prob.scale)
+    b = torch.from_numpy(prob.b).cuda()
+    nb = float(torch.linalg.norm(b))
+    steps, warm = max(args.steps, 1), args.warmup
+
+    def timed(fn):
+        for _ in range(warm):
+            fn()
+        torch.cuda.synchronize()
+        ts, out = [], None
+        for _ in range(steps):
+            t0 = time.perf_counter()
+            out = fn()
+            torch.cuda.synchronize()
+            ts.append(1e3 * (time.perf_counter() - t0))
+        return statistics.median(ts), out
+
+    def relres64(x, m=mu, rhs=b, nrm=nb):
+        return float(torch.linalg.norm(rhs - rr.apply_operator(kop, m, "fp64", x))) / nrm
+
+    def line(info, x, **extra):
+        return {"iters": info["iters"], "restarts": info["restarts"], "status": info["rc"],
+                "relres_fp64": relres64(x), **extra}
+
+    rows = {}
+    rb.profile_enable(True)
+    srht = dict(l=l, sketch="srht", seed=prob.omega_seed, prec="fp32")
+    build_ms, P = timed(lambda: rr.build_precond(kop, [mu], **srht))
+    rows["build (SRHT l=500, shared by the next six)"] = {"ms": build_ms}
+    for method, krylov in (("c", "cg"), ("c", "minres"), ("r", "cg"), ("r", "minres"),
+                           ("split", "cg"), ("split", "minres")):
+        ms, (x, info) = timed(lambda: P.solve(b, tol=tol, method=method, krylov=krylov, certify=False,
+                                              check_every=8, maxit=5000))
+        label = {"c": "C", "r": "R", "split": "split R"}[method]
+        rows[f"{label}-RandRAND {krylov.upper()}"] = line(info, x, ms=ms, total_ms=build_ms + ms)
+        _log(f"variants: {method}/{krylov} {ms:.1f} ms, {info['iters']} iterations")
+
+    bp = workloads.cfg_batched(nrhs=8, mus=(mu,))
+    B = torch.from_numpy(np.ascontiguousarray(bp.B)).cuda()
+    Pb = rr.build_precond(kop, [mu], l=l, sketch="srht", seed=bp.omega_seed, prec="fp32")
+    nB = torch.linalg.norm(B, dim=0)
+    for krylov in ("block_minres", "block_cg", "cg"):
+        ms, (X, infos, st) = timed(lambda: Pb.solve_batch(B, [0] * 8, tol=tol, krylov=krylov, check_every=8))
+        R = B - rr.apply_operator_block(kop, mu, "fp64", X.contiguous())
+        rel = (torch.linalg.norm(R, dim=0) / nB).max().item()
+        name = {"block_minres": "block MINRES", "block_cg": "block CG", "cg": "batched PCG (per column)"}[krylov]
+        rows[f"{name}, 8 right-hand sides"] = {"ms": ms, "columns_per_s": 8e3 / ms, "status": st,
+                                              "max_iters": max(i["iters"] for i in infos),
+                                              "max_relres_fp64": rel}
+        _log(f"variants: {krylov} x 8 {ms:.1f} ms")
+
+    def build_solve(mus_, idx=0, **kw):
+        def fn():
+            Q = rr.build_precond(kop, mus_, **kw)
+            x_, i_ = Q.solve(b, mu_index=idx, tol=tol, certify=False, check_every=8, maxit=5000)
+            return Q, x_, i_
+        return fn
+
+    cs = dict(l=l, sketch="colsample", seed=prob.omega_seed, prec="fp32")
+    ms, (Q, x, info) = timed(build_solve([mu], basis="less", **cs))
+    rows["basis-less C-RandRAND (column sampling l=500), build + solve"] = line(info, x, ms=ms, total_ms=ms)
+    ms, (Q, x, info) = timed(build_solve([mu], **cs))
+    rows["explicit basis, same column sample, build + solve"] = line(info, x, ms=ms, total_ms=ms)
+    ms, (Q, x, info) = timed(build_solve([mu], q=1, **srht))
+    rows["q = 1 (Omega = A X), build + solve"] = line(info, x, ms=ms, total_ms=ms)
+    ad = dict(srht, l=64, l_max=1024)
+    ms, (Q, x, info) = timed(build_solve([mu], **ad))
+    rows["adaptive l from 64 (l_max 1024), build + solve"] = line(info, x, ms=ms, total_ms=ms,
+                                                                  l_chosen=Q.shape[1])
+    mus4 = [1e-3, 1e-4, 1e-5, 1e-6]
+    ms, Q = timed(lambda: rr.build_precond(kop, mus4, multi="shifted_chol", **srht))
+    sweep = {"build_ms": ms}
+    for k, m in enumerate(mus4):
+        ms_k, (x, info) = timed(lambda: Q.solve(b, mu_index=k, tol=tol, certify=False, check_every=8,
+                                                maxit=5000))
+        sweep[f"mu={m:g}"] = {"ms": ms_k, "iters": info["iters"], "status": info["rc"],
+                              "relres_fp64": relres64(x, m)}
+    rows["shifted-Cholesky sweep, 4 shifts (one orthogonalisation)"] = sweep
+    kmv_n, kmv_ms = rb.profile_read(rb.PROF_KERNEL_MATVEC)
+    rb.profile_enable(False)
+
+    kmv_avg = kmv_ms / max(kmv_n, 1)
+    pairs = n * (n + 1) / 2
+    ach = (2 * prob.d + 3) * pairs / (kmv_avg * 1e-3) / 1e12
+    # the fastest single right-hand-side variant, build included (total_ms)
+    best = min((v["total_ms"], k) for k, v in rows.items() if "total_ms" in v)
+    out = {
+        "metric": "time-to-rel-residual 1e-6 (build + solve) by solver and preconditioner variant",
+        "value": 1e3 / best[0], "unit": "solves/s", "best": best[1], "n_gpus": 1, "steps": steps,
+        "warmup": warm, "higher_is_better": True, "dtype": "f32-class kernel entries, f64 sums",
+        "data": "synthetic",
+        "config": {"workload": "kernel ridge RBF n=50000 d=16 mu=1e-4 tol 1e-6, float64 refinement; "
+                               "solver and preconditioner variants", "n": n, "l": l},
+        "variants": rows,
+        "roofline": {"kernel": "k_ksym_mma (symmetric kernel matvec)", "bound": "alu", "achieved": ach,
+                     "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s", "frac": ach / PEAK_FP32_MFMA_TFLOPS,
+                     "avg_ms": kmv_avg, "launches": kmv_n, "traffic": None,
+                     "per_unit": "(2d+3) = 35 flops per distinct pair, n(n+1)/2 pairs per launch"},
+    }
     print(json.dumps(out), flush=True)
 
 
