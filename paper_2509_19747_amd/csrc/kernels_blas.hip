@@ -151,6 +151,22 @@ static void gemm_tr(bool trA, bool trB, int64_t M, int64_t N, int64_t K, const v
     else gemm_t<TA, TB, true, true>(M, N, K, A, lda, B, ldb, C, ldc, alpha, beta, ws, wsd, st);
 }
 
+// C = alpha sum_ch part[q nch M + ch M + j] + beta C: the chunk partials of a streamed
+// A^T B added in chunk order.
+__global__ void k_gemv_t_reduce(int64_t M, int64_t N, int nch, const double* __restrict__ part,
+                                double* __restrict__ C, int64_t ldc, double alpha, double beta) {
+    const int64_t total = M * N;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t j = e % M, q = e / M;
+        double s = 0.0;
+        for (int ch = 0; ch < nch; ++ch) s += part[(q * nch + ch) * M + j];
+        double o = alpha * s;
+        if (beta != 0.0) o += beta * C[j + q * ldc];
+        C[j + q * ldc] = o;
+    }
+}
+
 void launch_gemm(int dta, bool trA, int dtb, bool trB, int64_t M, int64_t N, int64_t K,
                  const void* A, int64_t lda, const void* B, int64_t ldb, double* C, int64_t ldc,
                  double alpha, double beta, double* ws, size_t wsd, hipStream_t st) {
@@ -161,6 +177,22 @@ void launch_gemm(int dta, bool trA, int dtb, bool trB, int64_t M, int64_t N, int
     }
     if (launch_gemm_mfma(dta, trA, dtb, trB, M, N, K, A, lda, B, ldb, C, ldc, alpha, beta, ws, wsd, st))
         return;
+    // A^T B with at most 8 columns of B and a long K (the Gram products of the block
+    // solvers): A is streamed once per group of up to 8 columns by the projection
+    // kernel's blocks (row chunks x 4 columns of A), then the partials are added.
+    if (dta == DT_F64 && dtb == DT_F64 && trA && !trB && N <= 8 && K >= 1024 && ws &&
+        (size_t)N * (size_t)gemv_t_chunks(K, M) * (size_t)M <= wsd) {
+        const int nch = gemv_t_chunks(K, M);
+        for (int64_t c0 = 0; c0 < N;) {
+            const int64_t left = N - c0;
+            const int nr = left >= 8 ? 8 : left >= 4 ? 4 : left >= 2 ? 2 : 1;
+            launch_gemv_t_multi(nr, K, M, (const double*)A, lda, (const double*)B + c0 * ldb, ldb,
+                                ws + c0 * nch * M, nch, nullptr, st);
+            c0 += nr;
+        }
+        k_gemv_t_reduce<<<clamp_grid((M * N + 255) / 256), 256, 0, st>>>(M, N, nch, ws, C, ldc, alpha, beta);
+        return;
+    }
     if (dtb == DT_F64) {
         if (dta == DT_F64) gemm_tr<double, double>(trA, trB, M, N, K, A, lda, B, ldb, C, ldc, alpha, beta, ws, wsd, st);
         else if (dta == DT_F32) gemm_tr<float, double>(trA, trB, M, N, K, A, lda, B, ldb, C, ldc, alpha, beta, ws, wsd, st);

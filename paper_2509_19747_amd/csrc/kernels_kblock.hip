@@ -13,6 +13,7 @@
 #include "kernels.hpp"
 
 #include <algorithm>
+#include <type_traits>
 
 namespace rr {
 
@@ -62,31 +63,106 @@ RR_DEV void kb_table(double* tab) {
     __syncthreads();
 }
 
-// out[c] = sgn_c (scale sum_j K(x_{idx_c}, x_j) v_j + mu v_{idx_c}): one block per c.
-template <int KIND, bool F64>
+// The records of a kernel entry held by one side: the float32 path keeps x and
+// -|x|^2 / 2, the float64 path g x and h = -g |x|^2 / 2 (the operands kb_entry uses).
+// An entry between a held side a (the "i" of kb_entry) and a streamed side b is
+// computed in kb_entry's order, so both forms give the same value.
+template <bool F64, int DM>
+struct KbSide {
+    using T = std::conditional_t<F64, double, float>;
+    T x[DM];
+    T h;   // F32: -0.5 |x|^2 (the i side) or |x|^2 (the j side); F64: h
+};
+template <bool F64, int DM>
+RR_DEV void kb_load(const KernelOp& op, int64_t i, double g, bool as_i, KbSide<F64, DM>& o) {
+    if constexpr (F64) {
+        const double* xi = op.xd + i * DM;
+#pragma unroll
+        for (int k = 0; k < DM; ++k) o.x[k] = as_i ? g * xi[k] : xi[k];
+        o.h = op.hd[i];
+    } else {
+        const float* xi = op.xa + i * DM;
+#pragma unroll
+        for (int k = 0; k < DM; ++k) o.x[k] = xi[k];
+        o.h = as_i ? -0.5f * op.sqn[i] : op.sqn[i];
+    }
+}
+// entry (without scale) between i-side a and j-side b (kb_entry<KIND, F64>(op, i, j))
+template <int KIND, bool F64, int DM, typename A, typename B>
+RR_DEV double kb_entry_r(const A& ax, double ah, const B& bx, double bh, float c32, double kconst,
+                         const double* tab) {
+    if constexpr (F64) {
+        double t = ah + bh;
+#pragma unroll
+        for (int k = 0; k < DM; ++k) t = fma((double)ax[k], (double)bx[k], t);
+        if (KIND == 1) return kb_exp2(t, tab);
+        const double kr = kconst * sqrt(fmax(-2.0 * t, 0.0));
+        return (1.0 + kr) * kb_exp2(-kr * KB_LOG2E, tab);
+    } else {
+        float s = kpair_init((float)ah, (float)bh);
+#pragma unroll
+        for (int k = 0; k < DM; ++k) s = fmaf((float)ax[k], (float)bx[k], s);
+        return (double)kval32<KIND>(s, c32);
+    }
+}
+
+// out[c] = sgn_c (scale sum_j K(x_{idx_c}, x_j) v_j + mu v_{idx_c}).  Block: KB_RB
+// sampled rows (their records in LDS, read as broadcasts) against every point j,
+// one point per thread and pass, so a point's record is loaded once per KB_RB
+// entries; the per-thread sums are added by a block reduction in a fixed order.
+constexpr int KB_RB = 4;
+template <int KIND, bool F64, int DM>
 __global__ __launch_bounds__(KB_THREADS) void k_kblock_rows(KernelOp op, const int32_t* __restrict__ idx,
                                                             const double* __restrict__ sgn, int64_t l, float c32,
                                                             double g, const double* __restrict__ v, double mu,
                                                             double* __restrict__ out,
                                                             const int32_t* __restrict__ stop) {
+    using T = typename KbSide<F64, DM>::T;
     __shared__ double tab[32];
     __shared__ double sc[KB_THREADS / WAVE];
+    __shared__ T rx[KB_RB][DM];
+    __shared__ T rh[KB_RB];
     if (stop && *stop) return;
     kb_table(tab);
-    const int64_t c = blockIdx.x;
-    const int64_t ic = idx[c];
-    double acc = 0.0;
-    for (int64_t j = threadIdx.x; j < op.n; j += KB_THREADS)
-        acc = fma(kb_entry<KIND, F64>(op, ic, j, c32, g, tab), v[j], acc);
-    acc = block_sum(acc, sc);
-    if (threadIdx.x == 0) out[c] = sgn[c] * fma(op.scale, acc, mu * v[ic]);
+    const int64_t c0 = (int64_t)blockIdx.x * KB_RB;
+    if (threadIdx.x < KB_RB) {
+        const int64_t c = c0 + threadIdx.x < l ? c0 + threadIdx.x : l - 1;
+        KbSide<F64, DM> a;
+        kb_load<F64, DM>(op, idx[c], g, true, a);
+#pragma unroll
+        for (int k = 0; k < DM; ++k) rx[threadIdx.x][k] = a.x[k];
+        rh[threadIdx.x] = a.h;
+    }
+    __syncthreads();
+    double acc[KB_RB];
+#pragma unroll
+    for (int r = 0; r < KB_RB; ++r) acc[r] = 0.0;
+    for (int64_t j = threadIdx.x; j < op.n; j += KB_THREADS) {
+        KbSide<F64, DM> b;
+        kb_load<F64, DM>(op, j, g, false, b);
+        const double vj = v[j];
+#pragma unroll
+        for (int r = 0; r < KB_RB; ++r)
+            acc[r] = fma(kb_entry_r<KIND, F64, DM>(rx[r], (double)rh[r], b.x, (double)b.h, c32, op.kconst, tab), vj,
+                         acc[r]);
+    }
+#pragma unroll
+    for (int r = 0; r < KB_RB; ++r) {
+        const double tot = block_sum(acc[r], sc);
+        const int64_t c = c0 + r;
+        if (threadIdx.x == 0 && c < l) {
+            const int64_t ic = idx[c];
+            out[c] = sgn[c] * fma(op.scale, tot, mu * v[ic]);
+        }
+    }
 }
 
 // z_i = rcoef r_i + scale sum_c K(x_i, x_{idx_c}) sgn_c d_c + mu sgn_{pos_i} d_{pos_i},
-// with block partials of r^T z (rz_part may be null): thread per row, the sampled
-// columns' indices and sgn d staged in LDS in chunks.
-constexpr int KB_CHUNK = 1024;
-template <int KIND, bool F64>
+// with block partials of r^T z (rz_part may be null): thread per row (its record in
+// registers), the sampled columns' records and sgn d staged in LDS in chunks and
+// read as broadcasts.
+constexpr int KB_CHUNK = 128;
+template <int KIND, bool F64, int DM>
 __global__ __launch_bounds__(KB_THREADS) void k_kblock_cols(KernelOp op, const int32_t* __restrict__ idx,
                                                             const double* __restrict__ sgn,
                                                             const int32_t* __restrict__ pos, int64_t l, float c32,
@@ -94,24 +170,34 @@ __global__ __launch_bounds__(KB_THREADS) void k_kblock_cols(KernelOp op, const i
                                                             const double* __restrict__ r, double rcoef,
                                                             double* __restrict__ z, double* __restrict__ rz_part,
                                                             const int32_t* __restrict__ stop) {
+    using T = typename KbSide<F64, DM>::T;
     __shared__ double tab[32];
+    __shared__ T cx[KB_CHUNK][DM];
+    __shared__ T ch[KB_CHUNK];
     __shared__ double sd[KB_CHUNK];
-    __shared__ int32_t si[KB_CHUNK];
     __shared__ double sc[KB_THREADS / WAVE];
     if (stop && *stop) return;
     kb_table(tab);
     const int64_t i = (int64_t)blockIdx.x * KB_THREADS + threadIdx.x;
     const int64_t ic = i < op.n ? i : op.n - 1;
+    KbSide<F64, DM> a;
+    kb_load<F64, DM>(op, ic, g, true, a);
     double acc = 0.0;
     for (int64_t c0 = 0; c0 < l; c0 += KB_CHUNK) {
         const int cn = (int)std::min<int64_t>(KB_CHUNK, l - c0);
         __syncthreads();
         for (int q = threadIdx.x; q < cn; q += KB_THREADS) {
-            si[q] = idx[c0 + q];
+            KbSide<F64, DM> b;
+            kb_load<F64, DM>(op, idx[c0 + q], g, false, b);
+#pragma unroll
+            for (int k = 0; k < DM; ++k) cx[q][k] = b.x[k];
+            ch[q] = b.h;
             sd[q] = sgn[c0 + q] * d[c0 + q];
         }
         __syncthreads();
-        for (int q = 0; q < cn; ++q) acc = fma(kb_entry<KIND, F64>(op, ic, si[q], c32, g, tab), sd[q], acc);
+        for (int q = 0; q < cn; ++q)
+            acc = fma(kb_entry_r<KIND, F64, DM>(a.x, (double)a.h, cx[q], (double)ch[q], c32, op.kconst, tab), sd[q],
+                      acc);
     }
     double dot = 0.0;
     if (i < op.n) {
@@ -181,13 +267,33 @@ struct KbArgs {
 };
 static KbArgs kb_args(const KernelOp& op) { return KbArgs{kernel_c32(op.kind, op.kconst), kernel_g64(op.kind, op.kconst)}; }
 
+// f(integral_constant K, bool F64, int DM): the kernel template of this operator
+template <typename F>
+static void kb_dispatch(const KernelOp& op, bool f64, F&& f) {
+    auto dm = [&](auto kk, auto ff) {
+        switch (op.dm) {
+            case 4: f(kk, ff, std::integral_constant<int, 4>{}); break;
+            case 8: f(kk, ff, std::integral_constant<int, 8>{}); break;
+            case 16: f(kk, ff, std::integral_constant<int, 16>{}); break;
+            default: f(kk, ff, std::integral_constant<int, 32>{}); break;
+        }
+    };
+    auto fl = [&](auto kk) {
+        if (f64) dm(kk, std::true_type{});
+        else dm(kk, std::false_type{});
+    };
+    if (op.kind == 1) fl(std::integral_constant<int, 1>{});
+    else fl(std::integral_constant<int, 2>{});
+}
+
 void launch_kblock_rows(const KernelOp& op, bool f64, const int32_t* idx, const double* sgn, int64_t l,
                         const double* v, double mu, double* out, const int32_t* stop, hipStream_t st) {
     const KbArgs a = kb_args(op);
-#define KBR(K, F) k_kblock_rows<K, F><<<(unsigned)l, KB_THREADS, 0, st>>>(op, idx, sgn, l, a.c32, a.g, v, mu, out, stop)
-    if (op.kind == 1) { if (f64) KBR(1, true); else KBR(1, false); }
-    else { if (f64) KBR(2, true); else KBR(2, false); }
-#undef KBR
+    const unsigned grid = (unsigned)((l + KB_RB - 1) / KB_RB);
+    kb_dispatch(op, f64, [&](auto kk, auto ff, auto dd) {
+        k_kblock_rows<decltype(kk)::value, decltype(ff)::value, decltype(dd)::value>
+            <<<grid, KB_THREADS, 0, st>>>(op, idx, sgn, l, a.c32, a.g, v, mu, out, stop);
+    });
 }
 
 int kblock_cols_blocks(int64_t n) { return (int)((n + KB_THREADS - 1) / KB_THREADS); }
@@ -197,10 +303,10 @@ void launch_kblock_cols(const KernelOp& op, bool f64, const int32_t* idx, const 
                         double* rz_part, const int32_t* stop, hipStream_t st) {
     const KbArgs a = kb_args(op);
     const unsigned grid = (unsigned)kblock_cols_blocks(op.n);
-#define KBC(K, F) k_kblock_cols<K, F><<<grid, KB_THREADS, 0, st>>>(op, idx, sgn, pos, l, a.c32, a.g, d, mu, r, rcoef, z, rz_part, stop)
-    if (op.kind == 1) { if (f64) KBC(1, true); else KBC(1, false); }
-    else { if (f64) KBC(2, true); else KBC(2, false); }
-#undef KBC
+    kb_dispatch(op, f64, [&](auto kk, auto ff, auto dd) {
+        k_kblock_cols<decltype(kk)::value, decltype(ff)::value, decltype(dd)::value>
+            <<<grid, KB_THREADS, 0, st>>>(op, idx, sgn, pos, l, a.c32, a.g, d, mu, r, rcoef, z, rz_part, stop);
+    });
 }
 
 void launch_kblock_y(const KernelOp& op, bool f64, const int32_t* idx, const double* sgn, int64_t l, double mu,
