@@ -41,6 +41,35 @@ RR_DEV float wave_sum(float v) {
     return v;
 }
 
+// v[l] + v[l ^ 32] (XOR = 32) or v[l] + v[l ^ 16] (XOR = 16) in every lane, the same value
+// as v + __shfl_xor(v, XOR) (addition is commutative), with gfx950's lane-swap moves
+// instead of an LDS permute.  A swap of a register with itself leaves the two
+// partners of a lane in the two results, so their sum is the pair's sum.
+template <int XOR>
+RR_DEV uint2 lane_swap_pair(uint32_t u) {
+    static_assert(XOR == 16 || XOR == 32, "lane_swap_pair: XOR must be 16 or 32");
+    if constexpr (XOR == 32) {
+        const auto r = __builtin_amdgcn_permlane32_swap(u, u, false, false);
+        return make_uint2(r[0], r[1]);
+    } else {
+        const auto r = __builtin_amdgcn_permlane16_swap(u, u, false, false);
+        return make_uint2(r[0], r[1]);
+    }
+}
+template <int XOR>
+RR_DEV double xor_pair_sum(double v) {
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const uint2 lo = lane_swap_pair<XOR>((uint32_t)b), hi = lane_swap_pair<XOR>((uint32_t)(b >> 32));
+    const double x = __builtin_bit_cast(double, ((uint64_t)hi.x << 32) | lo.x);
+    const double y = __builtin_bit_cast(double, ((uint64_t)hi.y << 32) | lo.y);
+    return x + y;
+}
+template <int XOR>
+RR_DEV float xor_pair_sum(float v) {
+    const uint2 r = lane_swap_pair<XOR>(__builtin_bit_cast(uint32_t, v));
+    return __builtin_bit_cast(float, r.x) + __builtin_bit_cast(float, r.y);
+}
+
 // DPP wave reduction towards lane 63.  One step on a float64 value (the same
 // DPP move on both halves; rows outside row_mask read 0 and keep their value).
 template <int CTRL, int ROWMASK>

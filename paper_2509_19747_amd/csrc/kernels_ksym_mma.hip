@@ -210,7 +210,10 @@ RR_DEV void ksym_mma_item(unsigned item, int64_t n, const float* __restrict__ xa
 #pragma unroll
         for (int q = 0; q < NR; ++q) {
             const T v = cs[0][q] + cs[1][q];
-            colw[wave][q][jl] = v + __shfl_xor(v, 32, 64);
+            // (the lane swap for float64 sums; the float estimate-grade variant keeps the
+            // permute, which spares it the swap's register copy at its register limit)
+            if constexpr (sizeof(T) == 8) colw[wave][q][jl] = xor_pair_sum<32>(v);
+            else colw[wave][q][jl] = v + __shfl_xor(v, 32, 64);
         }
     };
 
@@ -533,8 +536,8 @@ __global__ __launch_bounds__(KM_THREADS) __attribute__((amdgpu_waves_per_eu(NR =
 #pragma unroll
                     for (int q = 0; q < NR; ++q) {
                         double v = cs[q];
-                        v = v + __shfl_xor(v, 16, 64);
-                        v = v + __shfl_xor(v, 32, 64);
+                        v = xor_pair_sum<16>(v);
+                        v = xor_pair_sum<32>(v);
                         if (lr == 0) colw[wave][q][jl] = v;
                     }
                 }
