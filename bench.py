@@ -56,8 +56,9 @@ TRAFFIC_SOURCES = ("kernels_ksym_mma.hip", "kmma.hpp", "kentry.hpp", "common.hpp
 TRAFFIC_KERNEL = "k_ksym_mma<1, 16, 1, double>"
 
 
-def traffic_from_counters(d: str) -> dict:
-    """Write profiles/traffic.json from two rocprofv3 --pmc csv runs under d.
+def traffic_from_counters(d: str, out_path: str | None = None) -> dict:
+    """HBM bytes of the headline matvec from two rocprofv3 --pmc csv runs under d
+    (written to out_path as JSON when given; the command line writes profiles/traffic.json).
 
     d/FETCH_SIZE and d/WRITE_SIZE hold one run each of the headline step with
     --copy-calibration.  Each counter is scaled by what it reads for the 1 GiB
@@ -84,9 +85,10 @@ def traffic_from_counters(d: str) -> dict:
         "workload": "kernel ridge RBF n=50000 d=16, one float64-sum launch (1 column)",
         "calibration": "1 GiB device-to-device copy: FETCH_SIZE %d KiB, WRITE_SIZE %d KiB"
                        % (cal["FETCH_SIZE"], cal["WRITE_SIZE"])}}
-    with open(os.path.join(ROOT, "profiles", "traffic.json"), "w") as f:
-        json.dump(t, f, indent=1)
-        f.write("\n")
+    if out_path:
+        with open(out_path, "w") as f:
+            json.dump(t, f, indent=1)
+            f.write("\n")
     return t
 
 
@@ -230,7 +232,8 @@ def main():
         print(trace_summary(args.trace_summary, args.top))
         return
     if args.traffic_from:
-        print(json.dumps(traffic_from_counters(args.traffic_from)))
+        print(json.dumps(traffic_from_counters(args.traffic_from,
+                                               os.path.join(ROOT, "profiles", "traffic.json"))))
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
