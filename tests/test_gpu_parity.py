@@ -1102,6 +1102,38 @@ def test_basisless_fp64_matches_oracle(orth, reorth):
     assert abs(info["iters"] - ref.iters) <= max(2, int(0.03 * ref.iters)), (info["iters"], ref.iters)
 
 
+@pytest.mark.parametrize("kind,d,prec", [(rr.OP_MATERN32, 20, "fp64"), (rr.OP_RBF, 3, "fp64"),
+                                         (rr.OP_RBF, 3, "fp32"), (rr.OP_MATERN32, 7, "fp32")])
+def test_basisless_record_lengths_and_kinds(kind, d, prec):
+    """The basis-less kernel blocks at the record lengths 4, 8 and 32 and for both kernels
+    (n = 3,000, l = 100): in float64 the implicit Q, R and tau against the oracle's
+    Algorithm BL_RandRAND_PCG; in both precisions the PCG result against the oracle
+    operator and the explicit handle on the same column sample."""
+    n, l, mu = 3000, 100, 1e-3
+    rng = np.random.default_rng(50 + d)
+    pts = rng.standard_normal((d, n)).astype(np.float32)
+    kconst, scale = (0.3 if kind == rr.OP_MATERN32 else 0.5 / d), 1.0 / n
+    op = Operator(kind=kind, pts=pts, kconst=kconst, scale=scale)
+    b = rng.standard_normal(n)
+    kop = rr.kernel_operator(kind, _cuda(pts), kconst, scale)
+    kw = dict(l=l, sketch="colsample", seed=7, prec=prec)
+    Pb = rr.build_precond(kop, [mu], basis="less", **kw)
+    Pe = rr.build_precond(kop, [mu], **kw)
+    if prec == "fp64":
+        g = Pb.export(0)
+        o = orr.build_basisless(op, mu, l, "colsample", 7)
+        rel = lambda a, b_: np.linalg.norm(a - b_) / np.linalg.norm(b_)
+        assert rel(g["R"], o.R) < 1e-9 and rel(g["Q"], o.Q) < 1e-9
+        assert abs(g["tau"] - o.tau) < 1e-8 * o.tau
+    tol = 1e-8 if prec == "fp64" else 1e-6
+    xb, ib = Pb.solve(_cuda(b), tol=tol)
+    xe, ie = Pe.solve(_cuda(b), tol=tol)
+    for x, info in ((xb, ib), (xe, ie)):
+        assert info["rc"] == rr.RR_OK
+        assert osol.relres(op.shifted(mu), x.cpu().numpy(), b) <= tol * 1.0001
+    assert abs(ib["iters"] - ie["iters"]) <= max(3, int(0.15 * ie["iters"])), (ib["iters"], ie["iters"])
+
+
 def test_basisless_fp32_kernel_ridge_solve():
     """Basis-less float32-class handle at n = 20,000, l = 500 (no n x l basis stored):
     float64 relres <= tol with refinement; C-RandRAND MINRES on it as well; iteration
