@@ -730,7 +730,14 @@ extern "C" rr_status rr_build_precond(const rr_operator* A, const double* mus, i
             // it is ordered after the main stream, and freed only after the join (or,
             // on an error, after the guard below has waited for the second stream).
             DBuf Yt, C = B.mat(l, l), Ccopy = B.mat(l, l), Od;
-            if (P.omega_dt != DT_F64) Od = B.mat(n, l);
+            // An SRHT Omega (still the SRHT: q = 0) gives C^T = Y^T Omega by chunked
+            // Walsh-Hadamard transforms of the columns of Y instead of a GEMM against a
+            // float64 copy of Omega: far fewer flops and bytes beside the orthogonalisation.
+            int64_t hs = 1;
+            while (hs < n) hs *= 2;
+            const bool fwht = B.srht_dbits.ptr() && B.srht_rows.ptr();
+            if (fwht) Od = B.mat(srht_yt_omega_ws_doubles(n, l, hs), 1);
+            else if (P.omega_dt != DT_F64) Od = B.mat(n, l);
             struct SideGuard {
                 Builder& b;
                 ~SideGuard() {
@@ -739,6 +746,14 @@ extern "C" rr_status rr_build_precond(const rr_operator* A, const double* mus, i
             } side_guard{B};
             auto side = [&](const double* yt) {
                 B.side_begin();
+                if (fwht) {
+                    launch_srht_yt_omega(ydt, n, l, hs, Y.ptr(), n, B.srht_dbits.as<uint32_t>(),
+                                         B.srht_rows.as<int32_t>(), Od.as<double>(), C.as<double>(), l, B.st2);
+                    launch_symmetrize(C.as<double>(), l, l, B.st2);
+                    B.chol_start(C.as<double>(), l, Ccopy.as<double>(), B.st2, B.status2.as<int32_t>(),
+                                 B.gws2.as<double>(), B.gwsd);
+                    return;
+                }
                 const void* om = P.Omega.ptr();
                 if (P.omega_dt != DT_F64) {
                     launch_copy_mat(P.omega_dt, P.Omega.ptr(), n, DT_F64, Od.ptr(), n, n, l, B.st2);

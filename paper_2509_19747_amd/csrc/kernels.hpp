@@ -48,6 +48,13 @@ void launch_srht_fill(void* out, int dtype, int64_t n, int64_t l, int64_t ld, co
                       const int32_t* rows, hipStream_t st);
 // dbits[w] bit b = 1 when D[32 w + b] < 0 (i < n), words ceil(n / 32).
 void launch_srht_dbits(int64_t n, const float* D, uint32_t* dbits, hipStream_t st);
+// C (l x l, ldc) = Y^T Omega for the SRHT Omega of Hadamard size s (sampled rows, sign
+// bits of D), Y n x l (float32 or float64, leading dimension ldy), by chunked
+// Walsh-Hadamard transforms of the columns of D o Y; ws: srht_yt_omega_ws_doubles.
+int64_t srht_yt_omega_ws_doubles(int64_t n, int64_t l, int64_t s);
+void launch_srht_yt_omega(int ydt, int64_t n, int64_t l, int64_t s, const void* Y, int64_t ldy,
+                          const uint32_t* dbits, const int32_t* rows, double* ws, double* C, int64_t ldc,
+                          hipStream_t st);
 // S (2k x k, column-major, lds) = Theta Y for the sparse sign embedding of stream
 // `seed` (THETA_NNZ nonzeros per column, one per row block); Yt: Y row-major in
 // float64 (Yt[i * ldy + c], i < n, c < k).

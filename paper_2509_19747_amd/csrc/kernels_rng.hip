@@ -237,4 +237,81 @@ void launch_srht_dbits(int64_t n, const float* D, uint32_t* dbits, hipStream_t s
     k_srht_dbits<<<grid_for(words), 256, 0, st>>>(n, D, dbits);
 }
 
+// ------------------------------------------------ Y^T Omega for an SRHT Omega
+// (Y^T Omega)[c, c'] = sum_i Y[i, c] D_i (-1)^popcount(i & s_c') is entry s_c' of the
+// Walsh-Hadamard transform of D o Y[:, c] (length s, the power of two of the SRHT,
+// zero past n).  With s = nch * ch and i = j ch + e, the transform factors into one
+// of length ch per chunk j and a sum over the chunks with signs (-1)^popcount(j & s_hi):
+// one pass transforms every nonzero chunk of every column in LDS, a second forms the
+// l x l entries from the chunk transforms (16 chunk values each at n = 50,000).
+constexpr int FW_THREADS = 256, FW_MAX = 4096;
+
+template <typename T>
+__global__ __launch_bounds__(FW_THREADS) void k_srht_fwht_chunks(int64_t n, int64_t ch, int nch,
+                                                                 const T* __restrict__ Y, int64_t ldy,
+                                                                 const uint32_t* __restrict__ dbits,
+                                                                 double* __restrict__ W) {
+    __shared__ double buf[FW_MAX];
+    const int64_t c = blockIdx.y, j = blockIdx.x, base = j * ch;
+    const int t = threadIdx.x;
+    for (int64_t e = t; e < ch; e += FW_THREADS) {
+        const int64_t i = base + e;
+        double v = 0.0;
+        if (i < n) {
+            v = (double)Y[i + c * ldy];
+            if ((dbits[i >> 5] >> (i & 31)) & 1u) v = -v;
+        }
+        buf[e] = v;
+    }
+    __syncthreads();
+    for (int64_t h = 1; h < ch; h <<= 1) {
+        for (int64_t q = t; q < ch / 2; q += FW_THREADS) {
+            const int64_t i0 = (q / h) * 2 * h + (q % h);
+            const double a = buf[i0], b = buf[i0 + h];
+            buf[i0] = a + b;
+            buf[i0 + h] = a - b;
+        }
+        __syncthreads();
+    }
+    double* out = W + (c * nch + j) * ch;
+    for (int64_t e = t; e < ch; e += FW_THREADS) out[e] = buf[e];
+}
+
+// C[c + c' ldc] = sum_j (-1)^popcount(j & (s_c' / ch)) W[c, j, s_c' mod ch], chunks in order.
+__global__ void k_srht_fwht_sample(int64_t l, int64_t ch, int nch, const double* __restrict__ W,
+                                   const int32_t* __restrict__ rows, double* __restrict__ C, int64_t ldc) {
+    const int64_t total = l * l;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t c = e % l, cp = e / l;
+        const int64_t sr = rows[cp];
+        const int64_t hi = sr / ch, lo = sr % ch;
+        const double* w = W + c * nch * ch + lo;
+        double acc = 0.0;
+        for (int j = 0; j < nch; ++j) {
+            const double v = w[(int64_t)j * ch];
+            acc += (__popcll((unsigned long long)(j & hi)) & 1) ? -v : v;
+        }
+        C[c + cp * ldc] = acc;
+    }
+}
+
+int64_t srht_yt_omega_ws_doubles(int64_t n, int64_t l, int64_t s) {
+    const int64_t ch = s < FW_MAX ? s : FW_MAX;
+    return l * ((n + ch - 1) / ch) * ch;
+}
+
+void launch_srht_yt_omega(int ydt, int64_t n, int64_t l, int64_t s, const void* Y, int64_t ldy,
+                          const uint32_t* dbits, const int32_t* rows, double* ws, double* C, int64_t ldc,
+                          hipStream_t st) {
+    const int64_t ch = s < FW_MAX ? s : FW_MAX;
+    const int nch = (int)((n + ch - 1) / ch);   // chunks past n are zero
+    const dim3 grid((unsigned)nch, (unsigned)l);
+    if (ydt == DT_F32)
+        k_srht_fwht_chunks<float><<<grid, FW_THREADS, 0, st>>>(n, ch, nch, (const float*)Y, ldy, dbits, ws);
+    else
+        k_srht_fwht_chunks<double><<<grid, FW_THREADS, 0, st>>>(n, ch, nch, (const double*)Y, ldy, dbits, ws);
+    k_srht_fwht_sample<<<grid_for(l * l), 256, 0, st>>>(l, ch, nch, ws, rows, C, ldc);
+}
+
 }  // namespace rr
