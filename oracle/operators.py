@@ -37,6 +37,18 @@ def kernel_block(kind: int, kconst: float, Xr: np.ndarray, Xc: np.ndarray) -> np
     raise ValueError(kind)
 
 
+def _default_threads() -> int:
+    """ORACLE_THREADS if set, else the CPU count capped by OMP_NUM_THREADS (the host share
+    a shared machine grants this process)."""
+    if os.environ.get("ORACLE_THREADS"):
+        return max(1, int(os.environ["ORACLE_THREADS"]))
+    n = os.cpu_count() or 1
+    try:
+        return max(1, min(n, int(os.environ.get("OMP_NUM_THREADS", n))))
+    except ValueError:
+        return n
+
+
 class Operator:
     """A = scale * K(X, X) (kernel) or a stored dense symmetric A, both float64."""
 
@@ -48,7 +60,7 @@ class Operator:
         self.kconst = float(kconst)
         self.scale = float(scale)
         self.block = block
-        self.threads = threads or int(os.environ.get("ORACLE_THREADS", os.cpu_count() or 1))
+        self.threads = threads or _default_threads()
         if self.dense is not None:
             self.n = self.dense.shape[0]
             self.X = None

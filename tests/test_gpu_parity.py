@@ -1363,8 +1363,9 @@ def test_kernel_ridge_headline_full_size():
     l = 500, tol 1e-6, float32-class entries with float64 refinement): the library's
     float64 relres <= tol; the device float64 residual agrees on 64 sampled rows with
     the oracle's kernel formula; the float32-class product agrees with the oracle's on
-    the same rows within its arithmetic bound; RandRAND needs fewer iterations than
-    plain CG."""
+    the same rows within its arithmetic bound; the oracle operator's whole residual
+    agrees with the library's; the float32 operator is exactly symmetric at this size;
+    RandRAND needs fewer iterations than plain CG."""
     prob = workloads.cfg_kernel_ridge()
     mu, tol = prob.mus[0], prob.tol
     kop = rr.kernel_operator(rr.OP_RBF, _cuda(prob.pts), prob.kconst, prob.scale)
@@ -1387,6 +1388,15 @@ def test_kernel_ridge_headline_full_size():
     # the float32 operator; the same bound as the smaller parity tests)
     y_or = Kr @ xh + mu * xh[rows]
     assert np.all(np.abs(y32[rows] - y_or) <= 2e-6 * scale)
+    # the whole residual from the oracle operator
+    rel64 = osol.relres(Operator.from_problem(prob).shifted(mu), xh, prob.b)
+    assert rel64 <= tol and abs(info["relres_fp64"] - rel64) <= 1e-6 * rel64, (rel64, info["relres_fp64"])
+    # the float32 operator at this size is exactly symmetric through its float64 sums
+    U = np.random.default_rng(77).standard_normal((prob.n, 2))
+    Y = rr.apply_operator_block(kop, mu, "fp32", _cuda(U)).cpu().numpy()
+    uKv = U[:, 0] @ (Y[:, 1] - mu * U[:, 1])
+    vKu = U[:, 1] @ (Y[:, 0] - mu * U[:, 0])
+    assert abs(uKv - vKu) <= 1e-11 * (np.abs(U[:, 0]) @ np.abs(Y[:, 1] - mu * U[:, 1]))
     P0 = rr.build_precond(kop, [mu], l=0, prec="fp32")
     x0, i0 = P0.solve(b, tol=tol)
     assert i0["rc"] == rr.RR_OK and info["iters"] < i0["iters"]
