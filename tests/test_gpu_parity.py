@@ -704,6 +704,39 @@ def test_batched_graph_replay_and_wide_block():
         assert rel64 <= tol + dA * np.linalg.norm(X13[:, c]) / np.linalg.norm(B[:, 7 + c])
 
 
+def test_batched_full_size_in_the_bench_configuration():
+    """The batched workload at its full size (kernel ridge n = 50,000, 256 right-hand
+    sides x 4 shifts on one joint SRHT basis, tol 1e-6, the bench's call): every column
+    converges with float64 relres <= tol; on 12 sampled columns the device float64
+    residual agrees on 32 sampled rows with the oracle's kernel formula, and its norm
+    over the whole column with the library's relres."""
+    from oracle.operators import kernel_block
+    prob = workloads.cfg_batched()
+    n, k = prob.n, prob.B.shape[1]
+    kop = rr.kernel_operator(rr.OP_RBF, _cuda(prob.pts), prob.kconst, prob.scale)
+    mus_idx = [j for j in range(len(prob.mus)) for _ in range(k)]
+    Bh = np.concatenate([prob.B] * len(prob.mus), axis=1)
+    P = rr.build_precond(kop, prob.mus, l=prob.l, sketch="srht", seed=prob.omega_seed, prec="fp32")
+    X, infos, st = P.solve_batch(_cuda(Bh), mus_idx, tol=prob.tol, certify=False, check_every=4)
+    assert st == rr.RR_OK
+    assert all(i["status"] == rr.RR_OK and i["relres_fp64"] <= prob.tol for i in infos)
+    rng = np.random.default_rng(21)
+    cols = np.sort(rng.choice(Bh.shape[1], 12, replace=False))
+    rows = np.sort(rng.choice(n, 32, replace=False))
+    Xp = prob.pts.T.astype(np.float64)
+    Kr = prob.scale * kernel_block(rr.OP_RBF, prob.kconst, Xp[rows], Xp)
+    Xc = X[:, cols.tolist()].contiguous()
+    Xh = Xc.cpu().numpy()
+    for q, c in enumerate(cols):
+        mu = prob.mus[mus_idx[c]]
+        r = (_cuda(Bh[:, c].copy()) - rr.apply_operator(kop, mu, "fp64", Xc[:, q].contiguous())).cpu().numpy()
+        r_or = Bh[rows, c] - Kr @ Xh[:, q] - mu * Xh[rows, q]
+        scale = np.abs(Kr) @ np.abs(Xh[:, q]) + mu * np.abs(Xh[rows, q]) + np.abs(Bh[rows, c])
+        assert np.all(np.abs(r_or - r[rows]) <= 1e-13 * scale), (c, np.max(np.abs(r_or - r[rows]) / scale))
+        rel = np.linalg.norm(r) / np.linalg.norm(Bh[:, c])
+        assert abs(rel - infos[c]["relres_fp64"]) <= 1e-6 * rel + 1e-14, (c, rel, infos[c]["relres_fp64"])
+
+
 def test_batched_dense_operator():
     prob = workloads.cfg_small_dense(n=900, d=8, l=30)
     kop = rr.kernel_operator(rr.OP_RBF, _cuda(prob.pts), prob.kconst, 1.0)
