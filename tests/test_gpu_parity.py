@@ -837,6 +837,42 @@ def test_serving_alone_equals_mixed_and_oracle():
             assert rel <= 1e-6 + dA * np.linalg.norm(mixed[i]["X"][:, j]) / np.linalg.norm(r["B"][:, j])
 
 
+def test_serving_stream_at_the_workload_sizes():
+    """The first 24 requests of the serving workload's own stream (n log-uniform up to
+    32,768, l = n/32, 1-8 right-hand sides, the bench's server settings): every request
+    OK with no graph fallback, each column's float64 relres <= tol, and for the three
+    largest requests the residual on 24 sampled rows of every column against the
+    oracle's kernel formula."""
+    from oracle.operators import kernel_block
+    from paper_2509_19747_amd import binding as rb
+    stream = workloads.serving_stream(num=24, rate=200.0)
+    reqs = []
+    for r in stream:
+        p = r.problem
+        reqs.append(dict(kind=p.kind, pts=p.pts, kconst=p.kconst, scale=p.scale, mu=p.mus[0], l=p.l,
+                         seed=p.omega_seed, B=p.B, t_arrival=r.t_arrival))
+    kw = dict(build=dict(prec="fp32", sketch="gaussian"), solve=dict(tol=1e-6, certify=False))
+    res, stats = rb.serve(reqs, hbm_budget=96 << 30, max_slots=16, graph_iters=8, **kw)
+    assert stats["status"] == rr.RR_OK, stats.get("first_error")
+    assert stats["ok"] == len(reqs) and stats["failed"] == 0 and stats["graph_fallbacks"] == 0
+    for q, r in zip(res, reqs):
+        assert q["info"]["status"] == rr.RR_OK and q["info"]["relres_fp64"] <= 1e-6
+    rng = np.random.default_rng(9)
+    for i in np.argsort([r["pts"].shape[1] for r in reqs])[-3:]:
+        r, X = reqs[i], res[i]["X"]
+        n = r["pts"].shape[1]
+        Xp = r["pts"].T.astype(np.float64)
+        rows = np.sort(rng.choice(n, 24, replace=False))
+        Kr = r["scale"] * kernel_block(rr.OP_RBF, r["kconst"], Xp[rows], Xp)
+        op = Operator(kind=rr.OP_RBF, pts=r["pts"], kconst=r["kconst"], scale=r["scale"])
+        for j in range(r["B"].shape[1]):
+            x = X[:, j]
+            r_or = r["B"][rows, j] - Kr @ x - r["mu"] * x[rows]
+            assert np.linalg.norm(r_or) <= 1e-6 * np.linalg.norm(r["B"][:, j]) * 1.01
+        rel = osol.relres(op.shifted(r["mu"]), X[:, 0], r["B"][:, 0])
+        assert rel <= 1e-6 * 1.0001, (i, n, rel)
+
+
 def test_serving_grouped_equals_per_request_graphs():
     """Grouped serving (the PCG batches of all waiting requests in one replay of
     persistent kernels over the device work list) gives bitwise the results of
