@@ -1171,14 +1171,19 @@ def test_basisless_fp64_matches_oracle(orth, reorth):
     assert abs(info["iters"] - ref.iters) <= max(2, int(0.03 * ref.iters)), (info["iters"], ref.iters)
 
 
-@pytest.mark.parametrize("kind,d,prec", [(rr.OP_MATERN32, 20, "fp64"), (rr.OP_RBF, 3, "fp64"),
-                                         (rr.OP_RBF, 3, "fp32"), (rr.OP_MATERN32, 7, "fp32")])
-def test_basisless_record_lengths_and_kinds(kind, d, prec):
-    """The basis-less kernel blocks at the record lengths 4, 8 and 32 and for both kernels
-    (n = 3,000, l = 100): in float64 the implicit Q, R and tau against the oracle's
-    Algorithm BL_RandRAND_PCG; in both precisions the PCG result against the oracle
-    operator and the explicit handle on the same column sample."""
-    n, l, mu = 3000, 100, 1e-3
+@pytest.mark.parametrize("kind,d,prec,n,l", [(rr.OP_MATERN32, 20, "fp64", 3000, 100),
+                                             (rr.OP_RBF, 3, "fp64", 3000, 100),
+                                             (rr.OP_RBF, 3, "fp32", 3000, 100),
+                                             (rr.OP_MATERN32, 7, "fp32", 3000, 100),
+                                             (rr.OP_RBF, 16, "fp64", 1001, 37)])
+def test_basisless_record_lengths_and_kinds(kind, d, prec, n, l):
+    """The basis-less kernel blocks at the record lengths 4, 8, 16 and 32 and for both
+    kernels (n = 3,000, l = 100; and a ragged n = 1,001, l = 37, not a multiple of the
+    four sampled rows per block nor of the 128-column chunks): in float64 the implicit
+    Q, R and tau against the oracle's Algorithm BL_RandRAND_PCG; in both precisions the
+    PCG result against the oracle operator and the explicit handle on the same column
+    sample."""
+    mu = 1e-3
     rng = np.random.default_rng(50 + d)
     pts = rng.standard_normal((d, n)).astype(np.float32)
     kconst, scale = (0.3 if kind == rr.OP_MATERN32 else 0.5 / d), 1.0 / n
