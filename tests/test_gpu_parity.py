@@ -457,6 +457,23 @@ def test_kernel_fp32_solve_fp64_refinement_matches_oracle(kind):
     assert r0 <= i0["relres_work"] + 1.5 * dA * np.linalg.norm(x0) / np.linalg.norm(prob.b)
 
 
+@pytest.mark.parametrize("n,l", [(1500, 50), (4000, 120), (9000, 150)])
+def test_kernel_fp32_srht_factors_against_oracle(n, l):
+    """The float32-mode build with an SRHT test matrix, whose C = Omega^T Y comes from
+    Walsh-Hadamard transforms of chunks of Y (one chunk shorter than 4,096 points, one
+    full chunk, three chunks with a ragged last one): R, G and tau against the oracle's
+    float64 build on the same bf16 Omega, within the float32-class sketch's error (measured
+    at 1e-6 for R and 5e-5 for G; a wrong C would put G off by O(1))."""
+    prob = workloads.cfg_kernel_ridge(n=n, d=16, l=l)
+    mu = prob.mus[0]
+    kop = rr.kernel_operator(rr.OP_RBF, _cuda(prob.pts), prob.kconst, prob.scale)
+    P = rr.build_precond(kop, [mu], l=l, sketch="srht", seed=prob.omega_seed, prec="fp32")
+    g = P.export(0, with_q=False)
+    o = orr.build(Operator.from_problem(prob), [mu], l, "srht", prob.omega_seed, omega_bf16=True)[0]
+    rel = lambda a, b_: np.linalg.norm(a - b_) / np.linalg.norm(b_)
+    assert rel(g["R"], o.R) < 1e-5 and rel(g["G"], o.G) < 1e-3 and abs(g["tau"] - o.tau) < 1e-3 * o.tau
+
+
 def test_kernel_fp32_solve_with_srht():
     prob = workloads.cfg_kernel_ridge(n=4000, d=16, l=120)
     mu = prob.mus[0]
